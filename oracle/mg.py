@@ -22,7 +22,8 @@ remaining choices are this project's readings, stated here once:
 * prolongation: multilinear interpolation (the transpose of full weighting
   up to the factor 2^dim), zero boundary values.
 * coarsest level: exact when it has a single point, otherwise
-  ``coarse_sweeps`` red-black sweeps from zero.
+  ``coarse_sweeps`` red-black sweeps from the incoming iterate (zero on every
+  level below the finest).
 * V(nu1, nu2) cycle; the solve stops when ||b - M x||_2 <= tol ||b||_2.
 """
 from __future__ import annotations
@@ -160,11 +161,12 @@ class Hierarchy:
         return self.sizes[level][::-1]
 
 
-def coarse_solve(b: np.ndarray, hier: Hierarchy, level: int) -> np.ndarray:
+def coarse_solve(x: np.ndarray, b: np.ndarray, hier: Hierarchy, level: int) -> np.ndarray:
+    """Coarsest level: exact for a single point, otherwise ``coarse_sweeps``
+    red-black sweeps from the incoming iterate (zero below the finest level)."""
     h = hier.h[level]
     if b.size == 1:
         return b / diag_M(b.shape, h, hier.order, hier.a)
-    x = np.zeros_like(b)
     for _ in range(hier.coarse_sweeps):
         x = rb_sweep(x, b, h, hier.order, hier.a)
     return x
@@ -174,7 +176,7 @@ def vcycle(x: np.ndarray, b: np.ndarray, hier: Hierarchy, level: int = 0) -> np.
     """One V(nu1, nu2) cycle on ``level``; returns the new x."""
     h = hier.h[level]
     if level == len(hier.sizes) - 1:
-        return coarse_solve(b, hier, level)
+        return coarse_solve(x, b, hier, level)
     for _ in range(hier.nu1):
         x = rb_sweep(x, b, h, hier.order, hier.a)
     r = residual(x, b, h, hier.order, hier.a)
