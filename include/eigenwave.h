@@ -1,0 +1,227 @@
+/*
+ * eigenwave.h -- C ABI of the MI355X (gfx950) WaveHoltz-filter eigensolver.
+ *
+ * The library computes eigenpairs of the Dirichlet Laplacian on boxes near a
+ * target frequency omega with the EigenWave method: the WaveHoltz operator S
+ * (one wave-solve over N_p periods plus a trapezoidal time filter) is applied
+ * once per Arnoldi step, and the eigenvalues of L_h are recovered from the
+ * eigenvectors of S by a Rayleigh quotient stage.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns ew_status: 0 on success, a negative code otherwise;
+ *     ew_last_error() returns a thread-local message for the last failure.
+ *     No C++ exception crosses the ABI.  On error the contents of output
+ *     buffers are unspecified.
+ *   - Vectors hold the active (interior) grid points only, as FP64,
+ *     lexicographic with x fastest (the paper's matrix-vector routine,
+ *     Alg. "WaveHoltz matrix-vector product"; boundary points are constraint
+ *     equations and never enter the vectors).  A grid with n[d] interior
+ *     points per dimension has n_active = prod n[d] entries.
+ *   - "_dev" pointers are device (HBM) addresses on the device that was
+ *     current when the object was created; "_host" pointers are host memory.
+ *     The caller owns every buffer it passes; the library owns its workspace,
+ *     allocated by *_create and released by *_destroy.
+ *   - Device work is ordered on the hip stream given at creation (a
+ *     hipStream_t passed as void*; NULL = the null stream).  Calls marked
+ *     "stream-ordered" return before the device work finishes; calls marked
+ *     "host-blocking" synchronise the stream before returning.
+ *   - Objects are not thread-safe: one host thread at a time per object.
+ */
+#ifndef EIGENWAVE_H
+#define EIGENWAVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EW_OK = 0,
+    EW_ERR_INVALID_ARG = -1,       /* an argument violates the documented range */
+    EW_ERR_OOM = -2,               /* device or host allocation failed */
+    EW_ERR_HIP = -3,               /* a HIP runtime call failed */
+    EW_ERR_MG_NOT_CONVERGED = -4,  /* multigrid hit mg_max_cycles before mg_tol */
+    EW_ERR_NONFINITE = -5,         /* a NaN or Inf appeared in a norm */
+    EW_ERR_NOT_CONVERGED = -6,     /* eigensolver hit max_wave_solves */
+    EW_ERR_UNSUPPORTED = -7        /* valid but not implemented combination */
+} ew_status;
+
+enum { EW_TS_EXPLICIT = 0, EW_TS_IMPLICIT = 1 };
+enum { EW_FILTER_ALPHA_D = 0, EW_FILTER_QUARTER = 1 };
+enum { EW_PREC_FP64 = 0, EW_PREC_MIXED = 1 };
+enum { EW_PRED_ZERO = 0, EW_PRED_SCALED = 1, EW_PRED_CNN = 2 };
+
+typedef struct ew_op_s* ew_op;
+
+/* Grid: a box [0,len_0] x [0,len_1] (x [0,len_2]) with n[d] interior points per
+ * dimension, spacing h_d = len_d / (n_d + 1), homogeneous Dirichlet walls.
+ * dim in {2,3}; 1 <= n[d] <= 65535 for d < dim (entries beyond dim are ignored);
+ * order in {2,4}: the 2nd-order (5/7-point) or 4th-order (width-5 cross)
+ * Laplacian L_h of eq. eigBVPdiscrete.  Order 4 closes the stencil at a wall by
+ * odd reflection (u_{-1} = -u_{1}), the form the paper's compatibility
+ * conditions take for a flat Dirichlet wall (Sec. "Discrete approximations"). */
+typedef struct {
+    int dim;
+    int64_t n[3];
+    double len[3];
+    int order;
+} ew_grid_desc;
+
+/* Operator: one wave-solve plus time filter, S v (eqs. explicitScheme or
+ * implicitScheme, and filterQuadrature).
+ *   omega > 0          target frequency; T_f = n_p * 2 pi / omega.
+ *   ts                 EW_TS_EXPLICIT: leapfrog, dt from cfl (0 < cfl <= 1) with
+ *                      dt_max = 2/sqrt(rho), rho = sum_d c/h_d^2 (c = 4 for order
+ *                      2, 16/3 for order 4), N_t = ceil(T_f/(cfl dt_max));
+ *                      EW_TS_IMPLICIT: trapezoidal, N_t = n_p * n_its (n_its >= 5,
+ *                      Sec. "Discrete time-stepping analysis").
+ *   n_p >= 1           number of periods.
+ *   adjust_omega       nonzero: use the adjusted frequency of eq. adjustedOmega
+ *                      (implicit only).
+ *   filter_const       EW_FILTER_ALPHA_D: cos(omega t) - alpha_d/2 (eq. alphad);
+ *                      EW_FILTER_QUARTER: cos(omega t) - 1/4.
+ *   precision          EW_PREC_FP64, or EW_PREC_MIXED: FP32 state, stencils,
+ *                      smoother and filter accumulation, FP64 multigrid defect
+ *                      correction (implicit) and FP64 vectors at the boundary.
+ *   mg_tol, mg_nu1, mg_nu2, mg_max_cycles, mg_coarse_sweeps
+ *                      implicit only: V(nu1,nu2) cycles of red-black
+ *                      Gauss-Seidel multigrid on M = I - (dt^2/2) L_h (eq.
+ *                      impMatrix) until ||b - M x||_2 <= mg_tol ||b||_2.
+ *   predictor          initial guess of each implicit solve: EW_PRED_ZERO, or
+ *                      EW_PRED_SCALED (x0 = b / (1 + a omega^2), exact for
+ *                      every mode with lambda = omega since M phi = (1 + a mu) phi), or
+ *                      EW_PRED_CNN (needs ew_op_set_cnn). */
+typedef struct {
+    double omega;
+    int ts;
+    double cfl;
+    int n_its;
+    int n_p;
+    int adjust_omega;
+    int filter_const;
+    int precision;
+    double mg_tol;
+    int mg_nu1;
+    int mg_nu2;
+    int mg_max_cycles;
+    int mg_coarse_sweeps;
+    int predictor;
+} ew_op_desc;
+
+/* Read-only facts about an operator. */
+typedef struct {
+    int64_t n_active;     /* length of every vector */
+    int n_t;              /* time steps per wave-solve */
+    double dt;            /* time step */
+    double omega_used;    /* frequency used in the filter (adjusted or not) */
+    double t_final;       /* T_f */
+    double alpha_d;       /* eq. alphad at omega_used * dt */
+    int mg_levels;        /* multigrid levels (implicit), else 0 */
+} ew_op_info;
+
+/* Cumulative counters of an operator (reset by ew_op_reset_stats). */
+typedef struct {
+    int64_t wave_solves;      /* applications of S */
+    int64_t time_steps;       /* time levels advanced */
+    int64_t pt_updates;       /* active points x time levels advanced */
+    int64_t mg_solves;        /* implicit solves */
+    int64_t mg_cycles;        /* V-cycles over all implicit solves */
+    int64_t laplacian_applies;
+} ew_op_stats;
+
+/* Create an operator on the current device.  The filter weights c_n, dt and
+ * N_t are computed once here in FP64.  Errors: EW_ERR_INVALID_ARG for any
+ * violated range above, EW_ERR_OOM, EW_ERR_HIP. */
+ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* hip_stream, ew_op* out);
+void ew_op_destroy(ew_op op);
+ew_status ew_op_get_info(ew_op op, ew_op_info* out);
+ew_status ew_op_get_stats(ew_op op, ew_op_stats* out);
+ew_status ew_op_reset_stats(ew_op op);
+
+/* out_dev = S v_dev (both n_active FP64, device; may not alias).  This is the
+ * paper's matVec (Alg. "WaveHoltz matrix-vector product"): the vector is the
+ * initial condition W^0 with zero velocity, W is advanced N_t steps, and
+ * out = sum_n c_n W^n with trapezoidal c_n (eq. filterQuadrature).
+ * Stream-ordered for explicit; implicit blocks the host once per multigrid
+ * cycle to test convergence.  EW_ERR_MG_NOT_CONVERGED if a solve fails. */
+ew_status ew_op_apply_filter(ew_op op, const double* v_dev, double* out_dev);
+
+/* out_dev = L_h v_dev (FP64, device; may not alias), the operator of eq.
+ * eigBVPdiscrete with the order's closure.  Stream-ordered. */
+ew_status ew_op_apply_laplacian(ew_op op, const double* v_dev, double* out_dev);
+
+/* Solve M x = b with M = I - (dt^2/2) L_h of the operator (implicit only) by
+ * multigrid from the initial guess in x_dev, to the operator's mg_tol.
+ * b_dev, x_dev: n_active FP64 device vectors (may not alias).  cycles_host and
+ * rel_res_host (may be NULL) receive the V-cycle count and the final
+ * ||b - M x||_2 / ||b||_2.  Host-blocking. */
+ew_status ew_op_mg_solve(ew_op op, const double* b_dev, double* x_dev, int* cycles_host, double* rel_res_host);
+
+/* One V-cycle x <- V(x, b) on the finest level (FP64 operators only; for
+ * component parity tests).  Stream-ordered. */
+ew_status ew_op_mg_vcycle(ew_op op, const double* b_dev, double* x_dev);
+
+/* One red-black half-sweep on the finest level: every point whose 0-based
+ * index sum has parity `colour` gets x_i += (b - M x)_i / M_ii, all from the
+ * values before the half-sweep (FP64 operators only).  Stream-ordered. */
+ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* x_dev, int colour);
+
+/* Eigensolver (Alg. "Krylov-Schur" interface of the paper):
+ *   k >= 1 wanted pairs (largest |beta|, the paper's "largestAbs"), Krylov
+ *   dimension m with k < m <= n_active and m <= 256, Ritz tolerance tol_ritz
+ *   (relative |S y - theta y| / |theta|) and L_h residual tolerance tol_res
+ *   (||L y + mu y||_2 / (mu ||y||_2)), wave-solve cap max_wave_solves.
+ *   The start vector is v0_dev if non-NULL, else SplitMix64 uniform[-1,1) of
+ *   stream `seed`; deflation probes (fresh starts that find further copies of
+ *   repeated eigenvalues) use streams seed+1, seed+2, ...  n_keep (0 = default
+ *   max(k, (m+k)/2)) Ritz vectors are kept at each restart. */
+typedef struct {
+    int k;
+    int m;
+    double tol_ritz;
+    double tol_res;
+    int64_t max_wave_solves;
+    uint64_t seed;
+    const double* v0_dev;
+    int n_keep;
+    int max_probes;
+} ew_eigs_desc;
+
+typedef struct {
+    int n_conv;               /* converged pairs found (may exceed k) */
+    int n_returned;           /* pairs written (min(n_conv, k_cap)) */
+    int64_t wave_solves;
+    int64_t restarts;
+    int64_t probes;
+    int64_t time_steps;
+    int64_t pt_updates;
+    int64_t mg_cycles;
+    double seconds;           /* wall time of the call */
+    double max_res;           /* largest L_h residual among returned pairs */
+} ew_eigs_stats;
+
+/* Run the eigensolver.  Outputs (k_cap entries each, first n_returned valid,
+ * ordered by |beta| descending): mu_host = lambda_h^2, beta_host = eigenvalue
+ * of S, res_host = L_h residual, Y_dev = eigenvectors (n_active x k_cap FP64
+ * column-major on the device, unit 2-norm; may be NULL).  Host-blocking.
+ * EW_ERR_NOT_CONVERGED if max_wave_solves is reached first. */
+ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host, double* beta_host,
+                  double* res_host, double* Y_dev, ew_eigs_stats* stats);
+
+/* Fill x_dev (n FP64, device) with SplitMix64 uniform[-1,1) values of stream
+ * `seed`: element i is 2*((z_i >> 11) * 2^-53) - 1 with z_i the SplitMix64
+ * output for counter i+1.  Stream-ordered on `hip_stream`. */
+ew_status ew_fill_uniform(double* x_dev, int64_t n, uint64_t seed, void* hip_stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* ew_last_error(void);
+
+/* Library version string. */
+const char* ew_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIGENWAVE_H */

@@ -1,0 +1,191 @@
+"""MI355X-native WaveHoltz-filter eigensolver (EigenWave): Python binding.
+
+Every step of the computation runs in the HIP library libeigenwave.so
+(include/eigenwave.h); this module only marshals arguments.  PyTorch supplies
+device memory (tensors) and the stream.  There is no CPU fallback: without the
+built library, or without a GPU, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import EigenwaveError, check, load
+
+__all__ = ["Operator", "EigsResult", "fill_uniform", "EigenwaveError", "load", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_ptr(t, n: int) -> int:
+    torch = _torch()
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
+        raise ValueError("expected a contiguous float64 CUDA tensor with at least n_active elements")
+    return int(t.data_ptr())
+
+
+def version() -> str:
+    return load().ew_version().decode()
+
+
+@dataclass
+class EigsResult:
+    mu: list            # lambda_h^2 per returned pair, |beta| descending
+    beta: list          # eigenvalues of S
+    res: list           # ||L y + mu y|| / (mu ||y||)
+    Y: object           # torch tensor (n_active, n_returned) on the device, or None
+    n_conv: int
+    wave_solves: int
+    restarts: int
+    probes: int
+    time_steps: int
+    pt_updates: int
+    mg_cycles: int
+    seconds: float
+    status: int
+
+
+class Operator:
+    """The WaveHoltz operator S on one Dirichlet box (see ew_op_create)."""
+
+    def __init__(self, n: Sequence[int], length: Sequence[float], order: int, omega: float, ts: str,
+                 cfl: float = 0.5, n_its: int = 10, n_p: int = 1, adjust_omega: bool = False,
+                 filter_const: str = "alpha_d", precision: str = "fp64", mg_tol: float = 1e-10,
+                 mg_nu1: int = 2, mg_nu2: int = 1, mg_max_cycles: int = 100, mg_coarse_sweeps: int = 8,
+                 predictor: str = "zero", stream=None):
+        lib = load()
+        self._lib = lib
+        g = _lib.GridDesc()
+        g.dim = len(n)
+        for d in range(3):
+            g.n[d] = int(n[d]) if d < len(n) else 1
+            g.len[d] = float(length[d]) if d < len(n) else 1.0
+        g.order = int(order)
+        d = _lib.OpDesc()
+        d.omega = float(omega)
+        d.ts = _lib.TS[ts]
+        d.cfl = float(cfl)
+        d.n_its = int(n_its)
+        d.n_p = int(n_p)
+        d.adjust_omega = int(bool(adjust_omega))
+        d.filter_const = _lib.FILTER[filter_const]
+        d.precision = _lib.PRECISION[precision]
+        d.mg_tol = float(mg_tol)
+        d.mg_nu1 = int(mg_nu1)
+        d.mg_nu2 = int(mg_nu2)
+        d.mg_max_cycles = int(mg_max_cycles)
+        d.mg_coarse_sweeps = int(mg_coarse_sweeps)
+        d.predictor = _lib.PREDICTOR[predictor]
+        self._stream = stream
+        self._h = ctypes.c_void_p()
+        check(lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)),
+                               ctypes.byref(self._h)))
+        self.n = tuple(int(x) for x in n)
+        info = _lib.OpInfo()
+        check(lib.ew_op_get_info(self._h, ctypes.byref(info)))
+        self.n_active = int(info.n_active)
+        self.n_t = int(info.n_t)
+        self.dt = float(info.dt)
+        self.omega_used = float(info.omega_used)
+        self.t_final = float(info.t_final)
+        self.alpha_d = float(info.alpha_d)
+        self.mg_levels = int(info.mg_levels)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ew_op_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self):
+        torch = _torch()
+        return torch.empty(self.n_active, dtype=torch.float64, device="cuda")
+
+    def stats(self) -> dict:
+        s = _lib.OpStats()
+        check(self._lib.ew_op_get_stats(self._h, ctypes.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in _lib.OpStats._fields_}
+
+    def reset_stats(self) -> None:
+        check(self._lib.ew_op_reset_stats(self._h))
+
+    def apply_filter(self, v, out=None):
+        out = self._new() if out is None else out
+        check(self._lib.ew_op_apply_filter(self._h, _dev_ptr(v, self.n_active), _dev_ptr(out, self.n_active)))
+        return out
+
+    def apply_laplacian(self, v, out=None):
+        out = self._new() if out is None else out
+        check(self._lib.ew_op_apply_laplacian(self._h, _dev_ptr(v, self.n_active), _dev_ptr(out, self.n_active)))
+        return out
+
+    def mg_solve(self, b, x):
+        cyc = ctypes.c_int()
+        rel = ctypes.c_double()
+        check(self._lib.ew_op_mg_solve(self._h, _dev_ptr(b, self.n_active), _dev_ptr(x, self.n_active),
+                                       ctypes.byref(cyc), ctypes.byref(rel)))
+        return x, int(cyc.value), float(rel.value)
+
+    def mg_vcycle(self, b, x):
+        check(self._lib.ew_op_mg_vcycle(self._h, _dev_ptr(b, self.n_active), _dev_ptr(x, self.n_active)))
+        return x
+
+    def mg_half_sweep(self, b, x, colour: int):
+        check(self._lib.ew_op_mg_half_sweep(self._h, _dev_ptr(b, self.n_active), _dev_ptr(x, self.n_active),
+                                            int(colour)))
+        return x
+
+    def eigs(self, k: int, m: int, tol_ritz: float = 1e-12, tol_res: float = 1e-8,
+             max_wave_solves: int = 100000, seed: int = 1, v0=None, n_keep: int = 0, max_probes: int = 16,
+             k_cap: Optional[int] = None, want_vectors: bool = True, raise_on_error: bool = True) -> EigsResult:
+        torch = _torch()
+        d = _lib.EigsDesc()
+        d.k, d.m = int(k), int(m)
+        d.tol_ritz, d.tol_res = float(tol_ritz), float(tol_res)
+        d.max_wave_solves = int(max_wave_solves)
+        d.seed = int(seed)
+        d.v0_dev = _dev_ptr(v0, self.n_active) if v0 is not None else None
+        d.n_keep = int(n_keep)
+        d.max_probes = int(max_probes)
+        cap = int(k_cap) if k_cap is not None else 3 * m + k
+        mu = (ctypes.c_double * cap)()
+        beta = (ctypes.c_double * cap)()
+        res = (ctypes.c_double * cap)()
+        Y = torch.zeros((cap, self.n_active), dtype=torch.float64, device="cuda") if want_vectors else None
+        st = _lib.EigsStats()
+        status = self._lib.ew_eigs(self._h, ctypes.byref(d), cap, mu, beta, res,
+                                   ctypes.c_void_p(int(Y.data_ptr())) if Y is not None else None,
+                                   ctypes.byref(st))
+        if status != _lib.EW_OK and raise_on_error:
+            check(status)
+        nret = int(st.n_returned)
+        return EigsResult(mu=list(mu[:nret]), beta=list(beta[:nret]), res=list(res[:nret]),
+                          Y=(Y[:nret].T if Y is not None else None), n_conv=int(st.n_conv),
+                          wave_solves=int(st.wave_solves), restarts=int(st.restarts), probes=int(st.probes),
+                          time_steps=int(st.time_steps), pt_updates=int(st.pt_updates),
+                          mg_cycles=int(st.mg_cycles), seconds=float(st.seconds), status=int(status))
+
+
+def fill_uniform(n: int, seed: int, stream=None):
+    """SplitMix64 uniform[-1,1) vector of stream ``seed`` generated on the device."""
+    torch = _torch()
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    check(load().ew_fill_uniform(ctypes.c_void_p(int(x.data_ptr())), int(n), int(seed),
+                                 ctypes.c_void_p(_stream_handle(stream))))
+    return x

@@ -1,0 +1,109 @@
+"""ctypes declarations of the C ABI in include/eigenwave.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int64, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeigenwave.so")
+
+EW_OK = 0
+STATUS_NAMES = {
+    0: "EW_OK", -1: "EW_ERR_INVALID_ARG", -2: "EW_ERR_OOM", -3: "EW_ERR_HIP",
+    -4: "EW_ERR_MG_NOT_CONVERGED", -5: "EW_ERR_NONFINITE", -6: "EW_ERR_NOT_CONVERGED",
+    -7: "EW_ERR_UNSUPPORTED",
+}
+TS = {"explicit": 0, "implicit": 1}
+FILTER = {"alpha_d": 0, "quarter": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+PREDICTOR = {"zero": 0, "scaled": 1, "cnn": 2}
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("n", c_int64 * 3), ("len", c_double * 3), ("order", c_int)]
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("omega", c_double), ("ts", c_int), ("cfl", c_double), ("n_its", c_int), ("n_p", c_int),
+                ("adjust_omega", c_int), ("filter_const", c_int), ("precision", c_int), ("mg_tol", c_double),
+                ("mg_nu1", c_int), ("mg_nu2", c_int), ("mg_max_cycles", c_int), ("mg_coarse_sweeps", c_int),
+                ("predictor", c_int)]
+
+
+class OpInfo(ctypes.Structure):
+    _fields_ = [("n_active", c_int64), ("n_t", c_int), ("dt", c_double), ("omega_used", c_double),
+                ("t_final", c_double), ("alpha_d", c_double), ("mg_levels", c_int)]
+
+
+class OpStats(ctypes.Structure):
+    _fields_ = [("wave_solves", c_int64), ("time_steps", c_int64), ("pt_updates", c_int64),
+                ("mg_solves", c_int64), ("mg_cycles", c_int64), ("laplacian_applies", c_int64)]
+
+
+class EigsDesc(ctypes.Structure):
+    _fields_ = [("k", c_int), ("m", c_int), ("tol_ritz", c_double), ("tol_res", c_double),
+                ("max_wave_solves", c_int64), ("seed", c_uint64), ("v0_dev", c_void_p), ("n_keep", c_int),
+                ("max_probes", c_int)]
+
+
+class EigsStats(ctypes.Structure):
+    _fields_ = [("n_conv", c_int), ("n_returned", c_int), ("wave_solves", c_int64), ("restarts", c_int64),
+                ("probes", c_int64), ("time_steps", c_int64), ("pt_updates", c_int64), ("mg_cycles", c_int64),
+                ("seconds", c_double), ("max_res", c_double)]
+
+
+# name -> (restype, argtypes); every symbol include/eigenwave.h declares.
+SIGNATURES = {
+    "ew_op_create": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
+    "ew_op_destroy": (None, [c_void_p]),
+    "ew_op_get_info": (c_int, [c_void_p, POINTER(OpInfo)]),
+    "ew_op_get_stats": (c_int, [c_void_p, POINTER(OpStats)]),
+    "ew_op_reset_stats": (c_int, [c_void_p]),
+    "ew_op_apply_filter": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ew_op_apply_laplacian": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ew_op_mg_solve": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int), POINTER(c_double)]),
+    "ew_op_mg_vcycle": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ew_op_mg_half_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    "ew_eigs": (c_int, [c_void_p, POINTER(EigsDesc), c_int, POINTER(c_double), POINTER(c_double),
+                        POINTER(c_double), c_void_p, POINTER(EigsStats)]),
+    "ew_fill_uniform": (c_int, [c_void_p, c_int64, c_uint64, c_void_p]),
+    "ew_last_error": (c_char_p, []),
+    "ew_version": (c_char_p, []),
+}
+
+_lib = None
+
+
+class EigenwaveError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def load() -> ctypes.CDLL:
+    """Load libeigenwave.so from the package directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Importing
+    # it first makes the library's dependency on that soname resolve to the
+    # same copy, so one HIP runtime serves both (two runtimes in one process
+    # do not share devices, streams or memory).
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2507_18282_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != EW_OK:
+        msg = load().ew_last_error()
+        raise EigenwaveError(status, msg.decode() if msg else "")

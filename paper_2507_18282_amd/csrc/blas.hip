@@ -1,0 +1,206 @@
+// FP64 vector kernels of the Arnoldi process: deterministic reductions, the
+// chained modified Gram-Schmidt links, tall-skinny basis rotations and Gram
+// blocks, and the SplitMix64 start-vector generator.
+//
+// These are HBM-bound GEMV/GEMM shapes (arithmetic intensity <= k/8 flop/B for
+// k <= 64 columns, far below the FP64 ridge), so they use vector FMA; every
+// reduction runs over a fixed grid of kRedBlocks blocks with a fixed order of
+// additions, so repeated runs are bitwise identical.
+#include "stencil_dev.h"
+
+namespace ew {
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x, const double* __restrict__ y,
+                                                     int64_t n, double* __restrict__ partial) {
+    double acc = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)kRedBlocks * 256)
+        acc += x[c] * y[c];
+    const double s = block_sum_256(acc, threadIdx.x);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* partial, hipStream_t s) {
+    k_dot_partial<<<kRedBlocks, 256, 0, s>>>(x, y, n, partial);
+    return hipGetLastError();
+}
+
+// One link of the modified Gram-Schmidt chain (Alg. "Arnoldi"): the previous
+// kernel left the partial sums of h = (w, v_prev); finish that sum, subtract
+// h v_prev from w, and start the next inner product (w, v_next) in the same
+// pass.  Each link reads w, v_prev, v_next and writes w.
+// With vnext == w the new inner product is the squared norm of the updated w.
+__global__ __launch_bounds__(256) void k_mgs_link(double* w, const double* __restrict__ vprev, const double* vnext,
+                                                  int64_t n, const double* __restrict__ partial_in,
+                                                  double* __restrict__ partial_out, double* __restrict__ h_out) {
+    const double h = sum_partials(partial_in);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && h_out) *h_out = h;
+    const bool self = (vnext == w);
+    double acc = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)kRedBlocks * 256) {
+        const double wi = w[c] - h * vprev[c];
+        w[c] = wi;
+        acc += wi * (self ? wi : vnext[c]);
+    }
+    const double s = block_sum_256(acc, threadIdx.x);
+    if (threadIdx.x == 0) partial_out[blockIdx.x] = s;
+}
+
+hipError_t launch_mgs_link(double* w, const double* vprev, const double* vnext, int64_t n, const double* partial_in,
+                           double* partial_out, double* h_out, hipStream_t s) {
+    k_mgs_link<<<kRedBlocks, 256, 0, s>>>(w, vprev, vnext, n, partial_in, partial_out, h_out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_normalize(const double* __restrict__ w, double* __restrict__ v, int64_t n,
+                                                   const double* __restrict__ partial_in, double* __restrict__ nrm_out) {
+    const double nrm = sqrt(sum_partials(partial_in));
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nrm_out) *nrm_out = nrm;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)kRedBlocks * 256)
+        v[c] = w[c] / nrm;
+}
+
+hipError_t launch_normalize_from_partial(const double* w, double* v, int64_t n, const double* partial_in,
+                                         double* nrm_out, hipStream_t s) {
+    k_normalize<<<kRedBlocks, 256, 0, s>>>(w, v, n, partial_in, nrm_out);
+    return hipGetLastError();
+}
+
+// Y[:, c] = V[:, 0:nv] Q[0:nv, c] for a chunk of up to 16 output columns per
+// launch pass; each thread owns one row, Q sits in LDS.
+constexpr int kGemmCols = 16;
+constexpr int kMaxGemmRows = 320;  // nv bound: Krylov dimension + locked vectors
+
+__global__ __launch_bounds__(256) void k_tall_gemm(const double* __restrict__ V, int64_t n, int nv,
+                                                   const double* __restrict__ Q, int ldq, int c0, int nc,
+                                                   double* __restrict__ Y) {
+    __shared__ double q[kMaxGemmRows * kGemmCols];
+    for (int t = threadIdx.x; t < nv * nc; t += 256) {
+        const int i = t % nv, c = t / nv;
+        q[i * kGemmCols + c] = Q[i + (int64_t)(c0 + c) * ldq];
+    }
+    __syncthreads();
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
+        double acc[kGemmCols];
+#pragma unroll
+        for (int c = 0; c < kGemmCols; ++c) acc[c] = 0.0;
+        for (int i = 0; i < nv; ++i) {
+            const double vi = V[(int64_t)i * n + r];
+#pragma unroll
+            for (int c = 0; c < kGemmCols; ++c) acc[c] += vi * q[i * kGemmCols + c];
+        }
+#pragma unroll
+        for (int c = 0; c < kGemmCols; ++c)
+            if (c < nc) Y[(int64_t)(c0 + c) * n + r] = acc[c];
+    }
+}
+
+hipError_t launch_tall_gemm(const double* V, int64_t n, int nv, const double* Q_dev, int ldq, int ncols, double* Y,
+                            hipStream_t s) {
+    if (nv > kMaxGemmRows) return hipErrorInvalidValue;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    for (int c0 = 0; c0 < ncols; c0 += kGemmCols) {
+        const int nc = (ncols - c0) < kGemmCols ? (ncols - c0) : kGemmCols;
+        k_tall_gemm<<<(unsigned)blocks, 256, 0, s>>>(V, n, nv, Q_dev, ldq, c0, nc, Y);
+    }
+    return hipGetLastError();
+}
+
+// Gram block partials: block b accumulates sum_r A[r, i] B[r, j] over its
+// contiguous range of rows for i < na, j < nb (na, nb <= 32), staging 32 rows
+// of both blocks through LDS at a time.
+constexpr int kGramMax = 32;
+__global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ A, int na, const double* __restrict__ B,
+                                                      int nb, int64_t n, double* __restrict__ partial) {
+    __shared__ double ta[32][kGramMax + 1];
+    __shared__ double tb[32][kGramMax + 1];
+    const int np = na * nb;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // pairs tid, tid+256, tid+512, tid+768
+    const int64_t rows_per_block = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_block;
+    int64_t r_end = r_begin + rows_per_block;
+    if (r_end > n) r_end = n;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 32) {
+        for (int t = threadIdx.x; t < 32 * na; t += 256) {
+            const int rr = t % 32, c = t / 32;
+            const int64_t r = r0 + rr;
+            ta[rr][c] = (r < r_end) ? A[(int64_t)c * n + r] : 0.0;
+        }
+        for (int t = threadIdx.x; t < 32 * nb; t += 256) {
+            const int rr = t % 32, c = t / 32;
+            const int64_t r = r0 + rr;
+            tb[rr][c] = (r < r_end) ? B[(int64_t)c * n + r] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = threadIdx.x + 256 * q;
+            if (p < np) {
+                const int i = p / nb, j = p % nb;
+                double s = 0.0;
+                for (int rr = 0; rr < 32; ++rr) s += ta[rr][i] * tb[rr][j];
+                acc[q] += s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int p = threadIdx.x + 256 * q;
+        if (p < np) partial[(int64_t)blockIdx.x * np + p] = acc[q];
+    }
+}
+
+hipError_t launch_gram_partial(const double* A, int na, const double* B, int nb, int64_t n, double* partial,
+                               int nblocks, hipStream_t s) {
+    if (na > kGramMax || nb > kGramMax || na < 1 || nb < 1) return hipErrorInvalidValue;
+    k_gram_partial<<<nblocks, 256, 0, s>>>(A, na, B, nb, n, partial);
+    return hipGetLastError();
+}
+
+// Partials of ||lz + mu z||^2 (first kRedBlocks entries) and ||z||^2 (next kRedBlocks).
+__global__ __launch_bounds__(256) void k_eig_residual(const double* __restrict__ lz, const double* __restrict__ z,
+                                                      double mu, int64_t n, double* __restrict__ partial) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)kRedBlocks * 256) {
+        const double r = lz[c] + mu * z[c];
+        a0 += r * r;
+        a1 += z[c] * z[c];
+    }
+    const double s0 = block_sum_256(a0, threadIdx.x);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+    const double s1 = block_sum_256(a1, threadIdx.x);
+    if (threadIdx.x == 0) partial[kRedBlocks + blockIdx.x] = s1;
+}
+
+hipError_t launch_eig_residual(const double* lz, const double* z, double mu, int64_t n, double* partial,
+                               hipStream_t s) {
+    k_eig_residual<<<kRedBlocks, 256, 0, s>>>(lz, z, mu, n, partial);
+    return hipGetLastError();
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014; Vigna's finaliser constants), counter
+// form: z_i = mix(seed + (i+1) * golden); value = 2 * (z_i >> 11) * 2^-53 - 1.
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_splitmix_uniform(double* __restrict__ x, int64_t n, uint64_t seed) {
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+        const uint64_t z = splitmix_at(seed, (uint64_t)c);
+        x[c] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+    }
+}
+
+hipError_t launch_splitmix_uniform(double* x, int64_t n, uint64_t seed, hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_splitmix_uniform<<<(unsigned)blocks, 256, 0, s>>>(x, n, seed);
+    return hipGetLastError();
+}
+
+}  // namespace ew

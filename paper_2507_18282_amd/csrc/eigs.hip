@@ -1,0 +1,402 @@
+// ew_eigs: restarted Arnoldi with modified Gram-Schmidt over the WaveHoltz
+// operator S, Krylov-Schur restarting, deflation probes for repeated
+// eigenvalues, and the Rayleigh-Ritz stage with L_h.
+//
+// Vectors live on the device; the host holds only the small projected
+// matrices.  Each Arnoldi step crosses the host/device boundary once (the
+// column of Gram-Schmidt coefficients, j+2 doubles).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "dense.h"
+#include "op.h"
+
+namespace ew {
+
+namespace {
+
+struct Workspace {
+    Op* op = nullptr;
+    int64_t N = 0;
+    int m = 0, cap_lock = 0;
+    double* V = nullptr;      // N x (m+1)
+    double* Vt = nullptr;     // N x (m+1), rotation target
+    double* Y = nullptr;      // N x cap_lock, locked vectors
+    double* LY = nullptr;     // N x cap_lock, L_h applied to them / scratch
+    double* Z = nullptr;      // N x cap_lock, Rayleigh-Ritz vectors
+    double* P = nullptr;      // 2 x kRedBlocks partial sums (ping-pong)
+    double* h_dev = nullptr;  // Gram-Schmidt coefficients of one step
+    double* q_dev = nullptr;  // small matrices for basis rotations
+    double* gram_dev = nullptr;
+    double* h_host = nullptr;
+    std::vector<void*> owned;
+    ~Workspace() {
+        for (void* p : owned) hipFree(p);
+        if (h_host) hipHostFree(h_host);
+    }
+    ew_status alloc(double** p, size_t count) {
+        hipError_t e = hipMalloc((void**)p, count * sizeof(double) + 256);
+        if (e != hipSuccess) return fail(EW_ERR_OOM, std::string("eigensolver workspace: ") + hipGetErrorString(e));
+        owned.push_back(*p);
+        return EW_OK;
+    }
+    double* col(double* base, int j) const { return base + (int64_t)j * N; }
+};
+
+constexpr int kGramBlocks = 256;
+
+// w <- w - sum_i (w, u_i) u_i over the vector list by chained MGS links, then
+// w <- w / ||w||.  coeff receives the n_u coefficients and the norm (n_u + 1).
+ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const double*>& u, std::vector<double>& coeff) {
+    Op* op = ws.op;
+    hipStream_t s = op->stream;
+    const int nu = (int)u.size();
+    double* P0 = ws.P;
+    double* P1 = ws.P + kRedBlocks;
+    if (nu == 0) {
+        EW_HIP_TRY(launch_dot_partial(w, w, ws.N, P0, s));
+        EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, P0, ws.h_dev, s));
+    } else {
+        EW_HIP_TRY(launch_dot_partial(w, u[0], ws.N, P0, s));
+        for (int i = 1; i <= nu; ++i) {
+            const double* pin = (i % 2 == 1) ? P0 : P1;
+            double* pout = (i % 2 == 1) ? P1 : P0;
+            const double* vnext = (i < nu) ? u[i] : w;
+            EW_HIP_TRY(launch_mgs_link(w, u[i - 1], vnext, ws.N, pin, pout, ws.h_dev + (i - 1), s));
+        }
+        const double* plast = (nu % 2 == 1) ? P1 : P0;
+        EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, plast, ws.h_dev + nu, s));
+    }
+    EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    EW_HIP_TRY(hipStreamSynchronize(s));
+    coeff.assign(ws.h_host, ws.h_host + nu + 1);
+    for (double v : coeff)
+        if (!std::isfinite(v)) return fail(EW_ERR_NONFINITE, "non-finite value in Gram-Schmidt");
+    return EW_OK;
+}
+
+// Y[:, 0:ncols] = X[:, 0:nx] Qm[0:nx, 0:ncols] (Qm row-major nx x qcols).
+ew_status rotate(Workspace& ws, const double* X, int nx, const Mat& Qm, int ncols, double* Y) {
+    std::vector<double> qc((size_t)nx * ncols);
+    for (int c = 0; c < ncols; ++c)
+        for (int i = 0; i < nx; ++i) qc[(size_t)c * nx + i] = Qm(i, c);
+    EW_HIP_TRY(hipMemcpyAsync(ws.q_dev, qc.data(), qc.size() * sizeof(double), hipMemcpyHostToDevice, ws.op->stream));
+    EW_HIP_TRY(launch_tall_gemm(X, ws.N, nx, ws.q_dev, nx, ncols, Y, ws.op->stream));
+    // qc must outlive the copy: the stream is synchronised before it goes out of scope.
+    EW_HIP_TRY(hipStreamSynchronize(ws.op->stream));
+    return EW_OK;
+}
+
+int leading_converged(const std::vector<char>& conv) {
+    int n = 0;
+    while (n < (int)conv.size() && conv[n]) ++n;
+    return n;
+}
+
+struct RunResult {
+    std::vector<double> theta;
+    Mat Q;                    // m x m, columns ordered by |theta| descending
+    std::vector<char> conv;
+};
+
+// One Krylov-Schur run on S deflated by the nl locked vectors, started from
+// column 0 of ws.V (already filled, not yet orthonormalised).
+ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, int k, double floor_abs,
+                 int64_t ws_budget, uint64_t seed_base, int64_t& wave_solves, int64_t& restarts, RunResult& out) {
+    Op* op = ws.op;
+    const int m = ws.m;
+    Mat T(m + 1, m);
+    std::vector<double> coeff;
+    std::vector<const double*> u;
+    // normalise the start vector against the locked set
+    {
+        u.clear();
+        for (int i = 0; i < nl; ++i) u.push_back(ws.col(ws.Y, i));
+        EW_TRY(mgs_orthonormalize(ws, ws.col(ws.V, 0), u, coeff));
+        if (!(coeff.back() > 0.0)) return fail(EW_ERR_NONFINITE, "start vector lies in the locked space");
+    }
+    int p = 0;
+    for (;;) {
+        for (int j = p; j < m; ++j) {
+            double* w = ws.col(ws.V, j + 1);
+            EW_TRY(op->apply_filter(ws.col(ws.V, j), w));
+            ++wave_solves;
+            u.clear();
+            for (int i = 0; i < nl; ++i) u.push_back(ws.col(ws.Y, i));
+            for (int i = 0; i <= j; ++i) u.push_back(ws.col(ws.V, i));
+            EW_TRY(mgs_orthonormalize(ws, w, u, coeff));
+            double hsq = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                T(i, j) = coeff[nl + i];
+                hsq += coeff[nl + i] * coeff[nl + i];
+            }
+            double nrm = coeff.back();
+            if (!(nrm > 1e-12 * std::sqrt(hsq + nrm * nrm))) {
+                // Breakdown: the Krylov space is invariant.  Continue from a
+                // fresh random direction orthogonal to everything so far.
+                EW_HIP_TRY(launch_splitmix_uniform(w, ws.N, seed_base + 0x100000ULL + (uint64_t)wave_solves, op->stream));
+                EW_TRY(mgs_orthonormalize(ws, w, u, coeff));
+                nrm = 0.0;
+            }
+            T(j + 1, j) = nrm;
+        }
+        // Projected matrix (symmetric up to rounding) and its eigenpairs.
+        Mat A(m, m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) A(i, j) = 0.5 * (T(i, j) + T(j, i));
+        std::vector<double> w0;
+        Mat Q0;
+        jacobi_eigh(A, w0, Q0);
+        std::vector<int> idx = order_by_abs_desc(w0);
+        out.theta.assign(m, 0.0);
+        out.Q = Mat(m, m);
+        for (int c = 0; c < m; ++c) {
+            out.theta[c] = w0[idx[c]];
+            for (int i = 0; i < m; ++i) out.Q(i, c) = Q0(i, idx[c]);
+        }
+        const double beta_m = T(m, m - 1);
+        out.conv.assign(m, 0);
+        for (int c = 0; c < m; ++c)
+            out.conv[c] = std::fabs(beta_m * out.Q(m - 1, c)) <= tol_ritz * std::fabs(out.theta[c]);
+        // stopping rule
+        bool stop = false;
+        const int nlead = leading_converged(out.conv);
+        if (probe == 0) {
+            stop = nlead >= k;
+        } else if (out.conv[0]) {
+            if (std::fabs(out.theta[0]) < floor_abs) stop = true;
+            else {
+                int n_band = 0;
+                for (int c = 0; c < m; ++c) n_band += std::fabs(out.theta[c]) >= floor_abs;
+                stop = nlead >= n_band;
+            }
+        }
+        if (stop || wave_solves >= ws_budget) return EW_OK;
+        // Thick restart: keep the leading n_keep Ritz vectors and the residual vector.
+        EW_TRY(rotate(ws, ws.V, m, out.Q, n_keep, ws.Vt));
+        EW_HIP_TRY(hipMemcpyAsync(ws.col(ws.Vt, n_keep), ws.col(ws.V, m), ws.N * sizeof(double),
+                                  hipMemcpyDeviceToDevice, op->stream));
+        std::swap(ws.V, ws.Vt);
+        T = Mat(m + 1, m);
+        for (int c = 0; c < n_keep; ++c) {
+            T(c, c) = out.theta[c];
+            T(n_keep, c) = beta_m * out.Q(m - 1, c);
+        }
+        p = n_keep;
+        ++restarts;
+    }
+}
+
+// Sum nblocks partial Gram blocks on the host, in block order.
+ew_status gram(Workspace& ws, const double* A, int na, const double* B, int nb, Mat& G, int r0, int c0) {
+    Op* op = ws.op;
+    EW_HIP_TRY(launch_gram_partial(A, na, B, nb, ws.N, ws.gram_dev, kGramBlocks, op->stream));
+    std::vector<double> hbuf((size_t)kGramBlocks * na * nb);
+    EW_HIP_TRY(hipMemcpyAsync(hbuf.data(), ws.gram_dev, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              op->stream));
+    EW_HIP_TRY(hipStreamSynchronize(op->stream));
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+            double s = 0.0;
+            for (int b = 0; b < kGramBlocks; ++b) s += hbuf[(size_t)b * na * nb + i * nb + j];
+            G(r0 + i, c0 + j) = s;
+        }
+    return EW_OK;
+}
+
+ew_status full_gram(Workspace& ws, const double* A, const double* B, int n, Mat& G) {
+    G = Mat(n, n);
+    for (int i0 = 0; i0 < n; i0 += 32)
+        for (int j0 = 0; j0 < n; j0 += 32)
+            EW_TRY(gram(ws, ws.col(const_cast<double*>(A), i0), std::min(32, n - i0),
+                        ws.col(const_cast<double*>(B), j0), std::min(32, n - j0), G, i0, j0));
+    return EW_OK;
+}
+
+}  // namespace
+
+}  // namespace ew
+
+using namespace ew;
+
+extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host, double* beta_host,
+                             double* res_host, double* Y_dev, ew_eigs_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!op || !desc) return fail(EW_ERR_INVALID_ARG, "null argument");
+    const int k = desc->k, m = desc->m;
+    const int64_t N = op->N;
+    if (k < 1 || m <= k || m > 256 || (int64_t)m > N) return fail(EW_ERR_INVALID_ARG, "need 1 <= k < m <= min(256, n_active)");
+    if (!(desc->tol_ritz > 0.0) || !(desc->tol_res > 0.0)) return fail(EW_ERR_INVALID_ARG, "tolerances must be > 0");
+    if (desc->max_wave_solves < m) return fail(EW_ERR_INVALID_ARG, "max_wave_solves must be >= m");
+    if (k_cap < 0 || (k_cap > 0 && (!mu_host || !beta_host || !res_host)))
+        return fail(EW_ERR_INVALID_ARG, "k_cap > 0 needs mu_host, beta_host and res_host");
+    int n_keep = desc->n_keep > 0 ? desc->n_keep : std::max(k, (m + k) / 2);
+    n_keep = std::min(n_keep, m - 1);
+    if (n_keep < k) return fail(EW_ERR_INVALID_ARG, "n_keep must be >= k");
+    const int max_probes = desc->max_probes > 0 ? desc->max_probes : 16;
+
+    Workspace ws;
+    ws.op = op;
+    ws.N = N;
+    ws.m = m;
+    ws.cap_lock = (int)std::min<int64_t>(std::min<int64_t>(N, 3 * m + k), 320);
+    EW_TRY(ws.alloc(&ws.V, (size_t)N * (m + 1)));
+    EW_TRY(ws.alloc(&ws.Vt, (size_t)N * (m + 1)));
+    EW_TRY(ws.alloc(&ws.Y, (size_t)N * ws.cap_lock));
+    EW_TRY(ws.alloc(&ws.LY, (size_t)N * ws.cap_lock));
+    EW_TRY(ws.alloc(&ws.Z, (size_t)N * ws.cap_lock));
+    EW_TRY(ws.alloc(&ws.P, 2 * kRedBlocks));
+    EW_TRY(ws.alloc(&ws.h_dev, 4 * 256 + 64));
+    EW_TRY(ws.alloc(&ws.q_dev, (size_t)(4 * 256) * 256));
+    EW_TRY(ws.alloc(&ws.gram_dev, (size_t)kGramBlocks * 32 * 32));
+    EW_HIP_TRY(hipHostMalloc((void**)&ws.h_host, (4 * 256 + 64) * sizeof(double), hipHostMallocDefault));
+
+    const ew_op_stats s0 = op->stats;
+    int64_t wave_solves = 0, restarts = 0;
+    int nl = 0;
+    std::vector<double> th_locked;
+    int probe = 0, runs = 0;
+    bool budget_hit = false;
+    for (; probe < max_probes; ++probe) {
+        // start vector
+        if (probe == 0 && desc->v0_dev) {
+            EW_HIP_TRY(hipMemcpyAsync(ws.V, desc->v0_dev, N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));
+        } else {
+            EW_HIP_TRY(launch_splitmix_uniform(ws.V, N, desc->seed + (uint64_t)probe, op->stream));
+        }
+        double floor_abs = 0.0;
+        if (probe > 0) {
+            std::vector<double> a(th_locked.size());
+            for (size_t i = 0; i < a.size(); ++i) a[i] = std::fabs(th_locked[i]);
+            std::sort(a.begin(), a.end(), std::greater<double>());
+            floor_abs = (1.0 - 1e-10) * a[k - 1];
+        }
+        RunResult rr;
+        EW_TRY(ks_run(ws, nl, n_keep, desc->tol_ritz, probe, k, floor_abs, desc->max_wave_solves, desc->seed,
+                      wave_solves, restarts, rr));
+        ++runs;
+        int nlead = leading_converged(rr.conv);
+        if (wave_solves >= desc->max_wave_solves) budget_hit = true;
+        if (probe == 0 && nlead < k) break;  // budget exhausted before the first k converged
+        if (probe > 0) {
+            if (!rr.conv[0] || std::fabs(rr.theta[0]) < floor_abs) {
+                if (rr.conv[0]) budget_hit = false;  // search complete
+                break;
+            }
+            int n_band = 0;
+            for (int c = 0; c < m; ++c) n_band += std::fabs(rr.theta[c]) >= floor_abs;
+            nlead = std::min(nlead, n_band);
+        }
+        nlead = std::min(nlead, ws.cap_lock - nl);
+        if (nlead <= 0) break;
+        EW_TRY(rotate(ws, ws.V, m, rr.Q, nlead, ws.col(ws.Y, nl)));
+        for (int c = 0; c < nlead; ++c) th_locked.push_back(rr.theta[c]);
+        nl += nlead;
+        if (budget_hit || nl >= ws.cap_lock) break;
+    }
+
+    if (nl < k) {
+        return fail(EW_ERR_NOT_CONVERGED, "eigensolver reached max_wave_solves with " + std::to_string(nl) +
+                                              " converged pairs");
+    }
+
+    // Stage 2: Rayleigh-Ritz of L_h on the locked vectors, G q = mu B q with
+    // G = -Y^T L Y and B = Y^T Y.
+    for (int i = 0; i < nl; ++i) EW_TRY((ew_status)ew_op_apply_laplacian(op, ws.col(ws.Y, i), ws.col(ws.LY, i)));
+    Mat G, B;
+    EW_TRY(full_gram(ws, ws.Y, ws.LY, nl, G));
+    EW_TRY(full_gram(ws, ws.Y, ws.Y, nl, B));
+    Mat Gs(nl, nl), Bs(nl, nl);
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+            Gs(i, j) = -0.5 * (G(i, j) + G(j, i));
+            Bs(i, j) = 0.5 * (B(i, j) + B(j, i));
+        }
+    Mat Lc;
+    if (!cholesky(Bs, Lc)) return fail(EW_ERR_NONFINITE, "locked vectors are not linearly independent");
+    Mat Li = lower_inverse(Lc);
+    Mat C(nl, nl);
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+            double s = 0.0;
+            for (int a = 0; a <= i; ++a)
+                for (int b = 0; b <= j; ++b) s += Li(i, a) * Gs(a, b) * Li(j, b);
+            C(i, j) = s;
+        }
+    std::vector<double> mu;
+    Mat Zc;
+    jacobi_eigh(C, mu, Zc);
+    Mat Qr(nl, nl);  // Q = Li^T Zc
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+            double s = 0.0;
+            for (int a = i; a < nl; ++a) s += Li(a, i) * Zc(a, j);
+            Qr(i, j) = s;
+        }
+    // beta of each Rayleigh-Ritz vector: theta averaged with weights Q^2
+    std::vector<double> beta(nl);
+    for (int j = 0; j < nl; ++j) {
+        double num = 0.0, den = 0.0;
+        for (int i = 0; i < nl; ++i) {
+            num += th_locked[i] * Qr(i, j) * Qr(i, j);
+            den += Qr(i, j) * Qr(i, j);
+        }
+        beta[j] = num / den;
+    }
+    EW_TRY(rotate(ws, ws.Y, nl, Qr, nl, ws.Z));
+    std::vector<double> res(nl), znorm(nl);
+    for (int j = 0; j < nl; ++j) {
+        // L z_j into the (no longer needed) L Y buffer, then ||L z + mu z||.
+        EW_TRY((ew_status)ew_op_apply_laplacian(op, ws.col(ws.Z, j), ws.col(ws.LY, j)));
+        EW_HIP_TRY(launch_eig_residual(ws.col(ws.LY, j), ws.col(ws.Z, j), mu[j], N, ws.P, op->stream));
+        EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.P, 2 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, op->stream));
+        EW_HIP_TRY(hipStreamSynchronize(op->stream));
+        double r2 = 0.0, z2 = 0.0;
+        for (int b = 0; b < kRedBlocks; ++b) r2 += ws.h_host[b];
+        for (int b = 0; b < kRedBlocks; ++b) z2 += ws.h_host[kRedBlocks + b];
+        znorm[j] = std::sqrt(z2);
+        res[j] = std::sqrt(r2) / (std::fabs(mu[j]) * znorm[j]);
+    }
+    std::vector<int> order = order_by_abs_desc(beta);
+    int n_conv = 0;
+    for (int j = 0; j < nl; ++j) n_conv += res[j] <= desc->tol_res;
+    const int n_ret = std::min(nl, k_cap);
+    double max_res = 0.0;
+    for (int r = 0; r < n_ret; ++r) {
+        const int j = order[r];
+        mu_host[r] = mu[j];
+        beta_host[r] = beta[j];
+        res_host[r] = res[j];
+        max_res = std::max(max_res, res[j]);
+        if (Y_dev) {
+            EW_HIP_TRY(launch_scale_copy<double>(Y_dev + (int64_t)r * N, ws.col(ws.Z, j), N, 1.0 / znorm[j], op->stream));
+        }
+    }
+    EW_HIP_TRY(hipStreamSynchronize(op->stream));
+    if (stats) {
+        stats->n_conv = n_conv;
+        stats->n_returned = n_ret;
+        stats->wave_solves = wave_solves;
+        stats->restarts = restarts;
+        stats->probes = runs;
+        stats->time_steps = op->stats.time_steps - s0.time_steps;
+        stats->pt_updates = op->stats.pt_updates - s0.pt_updates;
+        stats->mg_cycles = op->stats.mg_cycles - s0.mg_cycles;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->max_res = max_res;
+    }
+    if (budget_hit) return fail(EW_ERR_NOT_CONVERGED, "eigensolver reached max_wave_solves");
+    return EW_OK;
+}
+
+extern "C" ew_status ew_fill_uniform(double* x_dev, int64_t n, uint64_t seed, void* hip_stream) {
+    if (!x_dev || n < 0) return fail(EW_ERR_INVALID_ARG, "bad argument");
+    if (n == 0) return EW_OK;
+    EW_HIP_TRY(launch_splitmix_uniform(x_dev, n, seed, (hipStream_t)hip_stream));
+    return EW_OK;
+}
+
+extern "C" const char* ew_last_error(void) { return ew::last_error_cstr(); }
+
+extern "C" const char* ew_version(void) { return "eigenwave-mi355x 0.1 (gfx950)"; }

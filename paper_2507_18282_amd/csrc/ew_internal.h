@@ -1,0 +1,119 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/eigenwave.h"
+
+namespace ew {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* last_error_cstr();
+ew_status fail(ew_status code, const std::string& msg);
+
+#define EW_HIP_TRY(expr)                                                        \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess)                                                   \
+            return ::ew::fail(EW_ERR_HIP, std::string(#expr) + ": " +           \
+                                              hipGetErrorString(e_));           \
+    } while (0)
+
+#define EW_TRY(expr)                         \
+    do {                                     \
+        ew_status s_ = (expr);               \
+        if (s_ != EW_OK) return s_;          \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Grid geometry passed by value to kernels.  Interior points only, x fastest.
+// ---------------------------------------------------------------------------
+struct Geo {
+    int dim;
+    int nx, ny, nz;        // nz = 1 in 2D
+    double ihx2, ihy2, ihz2;  // 1/h^2 per dimension (ihz2 = 0 in 2D)
+    __host__ __device__ int64_t size() const { return (int64_t)nx * ny * nz; }
+};
+
+Geo make_geo(int dim, const int64_t* n, const double* h);
+
+// Number of partial sums written by the reduction kernels (one per block).
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (templated on the storage type T = double or float).
+// All lengths are element counts; every launcher returns hipGetLastError().
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_laplacian(const T* u, T* out, const Geo& g, int order, hipStream_t s);
+
+// Explicit leapfrog step fused with the filter accumulation.
+//   first != 0: wnext = wcur + (dt2/2) L wcur;  acc = ccur*wcur + cnext*wnext
+//   first == 0: wnext = 2 wcur - wprev + dt2 L wcur;  acc += cnext*wnext
+// wnext may alias wprev.
+template <typename T>
+hipError_t launch_leapfrog(const T* wcur, const T* wprev, T* wnext, T* acc, const Geo& g, int order,
+                           double dt2, double ccur, double cnext, int first, hipStream_t s);
+
+// Implicit step update: wnext = sol - wprev; acc += cnext*wnext (wnext may alias wprev).
+// With first != 0: wnext = sol; acc = ccur*wprev + cnext*wnext.
+template <typename T, typename TA>
+hipError_t launch_implicit_update(const T* sol, const T* wprev, T* wnext, TA* acc, int64_t n,
+                                  double ccur, double cnext, int first, hipStream_t s);
+
+// Multigrid pieces for M = I - a L.
+// Out of place: xout = xin with the points of one colour relaxed.
+template <typename T>
+hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, const Geo& g, int order, double a,
+                          int colour, hipStream_t s);
+template <typename T>
+hipError_t launch_residual_restrict(const T* x, const T* b, double bscale, const Geo& gf, int order, double a,
+                                    T* bc, const Geo& gc, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& gc, hipStream_t s);
+// Partial sums of r^2, r = bscale*b - (x - a L x), one per block (kRedBlocks).
+// With r_out != nullptr the residual is also stored (converted to TR).
+template <typename T, typename TR>
+hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo& g, int order, double a,
+                                double* partial, TR* r_out, hipStream_t s);
+
+// Elementwise helpers.
+template <typename TD, typename TS>
+hipError_t launch_convert(TD* dst, const TS* src, int64_t n, double scale, hipStream_t s);
+template <typename T, typename TE>
+hipError_t launch_add_inplace(T* x, const TE* e, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* x, int64_t n, T value, hipStream_t s);
+template <typename T>
+hipError_t launch_scale_copy(T* dst, const T* src, int64_t n, double scale, hipStream_t s);
+
+// FP64 vector kernels for the Arnoldi process (deterministic block reductions).
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* partial, hipStream_t s);
+// MGS link: h = sum(partial_in); if (store_h) *h_out = h;
+// w -= h * vprev; partial_out = partial dot(w, vnext) (vnext may be w itself).
+hipError_t launch_mgs_link(double* w, const double* vprev, const double* vnext, int64_t n,
+                           const double* partial_in, double* partial_out, double* h_out, hipStream_t s);
+// v = w / sqrt(sum(partial_in)); *nrm_out = sqrt(sum(partial_in)).
+hipError_t launch_normalize_from_partial(const double* w, double* v, int64_t n, const double* partial_in,
+                                         double* nrm_out, hipStream_t s);
+// Y[:, c] = sum_i V[:, i] * Q[i + c*ldq], c < ncols, i < nv (column-major, leading dim n).
+hipError_t launch_tall_gemm(const double* V, int64_t n, int nv, const double* Q_dev, int ldq, int ncols, double* Y,
+                            hipStream_t s);
+// Partial Gram blocks: block b writes P_b[i*nb + j] = sum over its rows of A[:,i]*B[:,j]
+// (na, nb <= 32; partial holds nblocks*na*nb doubles).
+hipError_t launch_gram_partial(const double* A, int na, const double* B, int nb, int64_t n, double* partial,
+                               int nblocks, hipStream_t s);
+// Partials of ||lz + mu z||^2 (partial[0:kRedBlocks]) and ||z||^2 (partial[kRedBlocks:2 kRedBlocks]).
+hipError_t launch_eig_residual(const double* lz, const double* z, double mu, int64_t n, double* partial,
+                               hipStream_t s);
+hipError_t launch_splitmix_uniform(double* x, int64_t n, uint64_t seed, hipStream_t s);
+
+}  // namespace ew

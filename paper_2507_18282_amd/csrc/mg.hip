@@ -1,0 +1,221 @@
+// Geometric multigrid kernels for the implicit step matrix M = I - a L_h,
+// a = dt^2/2 (eq. impMatrix), used with red-black Gauss-Seidel smoothing on
+// Cartesian grids.  Levels coarsen by two (n_c = (n-1)/2) and rediscretise the
+// same operator; restriction is full weighting and prolongation multilinear.
+#include "stencil_dev.h"
+
+namespace ew {
+
+// --------------------------------------------------------------------------
+// One red-black half-sweep, out of place: the points whose 0-based index sum
+// has parity `colour` get x + (b - M x)/M_ii from the input values, the others
+// are copied.  Out of place because for order 4 the +-2 neighbours share the
+// colour and must be read before any of them is overwritten.
+// --------------------------------------------------------------------------
+template <typename T, int ORDER, int DIM>
+__global__ __launch_bounds__(256) void k_rb_half(const T* __restrict__ xin, T* __restrict__ xout,
+                                                 const T* __restrict__ b, T bscale, Geo g, T a, int colour) {
+    int i, j, k;
+    if (!tile_coords(g, i, j, k)) return;
+    const int64_t c = lin(g, i, j, k);
+    const T xc = xin[c];
+    if (((i + j + k) & 1) != colour) {
+        xout[c] = xc;
+        return;
+    }
+    const T lap = lap_at<T, ORDER, DIM>(xin, c, i, j, k, g, xc);
+    const T r = bscale * b[c] - (xc - a * lap);
+    xout[c] = xc + r / mdiag_at<T, ORDER, DIM>(i, j, k, g, a);
+}
+
+template <typename T>
+hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, const Geo& g, int order, double a,
+                          int colour, hipStream_t s) {
+    dim3 grid = tile_grid(g), block(kTileX, kTileY, 1);
+    const T bs = (T)bscale, aa = (T)a;
+    if (g.dim == 2) {
+        if (order == 2) k_rb_half<T, 2, 2><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
+        else k_rb_half<T, 4, 2><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
+    } else {
+        if (order == 2) k_rb_half<T, 2, 3><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
+        else k_rb_half<T, 4, 3><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Residual fused with full-weighting restriction: one thread per coarse point
+// I, fine centre 2I+1, weights prod_d w(o_d) with w(0) = 1/2, w(+-1) = 1/4.
+// --------------------------------------------------------------------------
+template <typename T, int ORDER, int DIM>
+__device__ __forceinline__ T fine_residual(const T* __restrict__ x, const T* __restrict__ b, T bscale, const Geo& g,
+                                           T a, int i, int j, int k) {
+    const int64_t c = lin(g, i, j, k);
+    const T xc = x[c];
+    return bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM>(x, c, i, j, k, g, xc));
+}
+
+template <typename T, int ORDER, int DIM>
+__global__ __launch_bounds__(256) void k_residual_restrict(const T* __restrict__ x, const T* __restrict__ b,
+                                                           T bscale, Geo gf, T a, T* __restrict__ bc, Geo gc) {
+    int ic, jc, kc;
+    if (!tile_coords(gc, ic, jc, kc)) return;
+    const int fi = 2 * ic + 1, fj = 2 * jc + 1, fk = (DIM == 3) ? 2 * kc + 1 : 0;
+    T sum = T(0);
+    if (DIM == 2) {
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+            T row = T(0);
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                const T w = ox == 0 ? T(0.5) : T(0.25);
+                row += w * fine_residual<T, ORDER, DIM>(x, b, bscale, gf, a, fi + ox, fj + oy, 0);
+            }
+            sum += (oy == 0 ? T(0.5) : T(0.25)) * row;
+        }
+    } else {
+#pragma unroll
+        for (int oz = -1; oz <= 1; ++oz) {
+            T plane = T(0);
+#pragma unroll
+            for (int oy = -1; oy <= 1; ++oy) {
+                T row = T(0);
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const T w = ox == 0 ? T(0.5) : T(0.25);
+                    row += w * fine_residual<T, ORDER, DIM>(x, b, bscale, gf, a, fi + ox, fj + oy, fk + oz);
+                }
+                plane += (oy == 0 ? T(0.5) : T(0.25)) * row;
+            }
+            sum += (oz == 0 ? T(0.5) : T(0.25)) * plane;
+        }
+    }
+    bc[lin(gc, ic, jc, kc)] = sum;
+}
+
+template <typename T>
+hipError_t launch_residual_restrict(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
+                                    const Geo& gc, hipStream_t s) {
+    dim3 grid = tile_grid(gc), block(kTileX, kTileY, 1);
+    const T bs = (T)bscale, aa = (T)a;
+    if (gf.dim == 2) {
+        if (order == 2) k_residual_restrict<T, 2, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+        else k_residual_restrict<T, 4, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+    } else {
+        if (order == 2) k_residual_restrict<T, 2, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+        else k_residual_restrict<T, 4, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Prolongation (multilinear) fused with the correction x += P xc.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void interp_1d(int f, int nc, int& c0, int& c1, float& w0, float& w1) {
+    if (f & 1) {  // coincides with coarse point (f-1)/2
+        c0 = (f - 1) >> 1;
+        c1 = -1;
+        w0 = 1.0f;
+        w1 = 0.0f;
+    } else {      // midway between coarse f/2-1 and f/2
+        c0 = (f >> 1) - 1;
+        c1 = f >> 1;
+        w0 = 0.5f;
+        w1 = 0.5f;
+        if (c1 >= nc) c1 = -1;
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_prolong_correct(T* __restrict__ x, const T* __restrict__ xc, Geo gf, Geo gc) {
+    int i, j, k;
+    if (!tile_coords(gf, i, j, k)) return;
+    int xi[2], yj[2], zk[2];
+    float wx[2], wy[2], wz[2];
+    interp_1d(i, gc.nx, xi[0], xi[1], wx[0], wx[1]);
+    interp_1d(j, gc.ny, yj[0], yj[1], wy[0], wy[1]);
+    if (DIM == 3) interp_1d(k, gc.nz, zk[0], zk[1], wz[0], wz[1]);
+    else { zk[0] = 0; zk[1] = -1; wz[0] = 1.0f; wz[1] = 0.0f; }
+    T v = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (zk[c] < 0) continue;
+        T plane = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+            if (yj[bb] < 0) continue;
+            T row = T(0);
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa) {
+                if (xi[aa] < 0) continue;
+                row += (T)wx[aa] * xc[lin(gc, xi[aa], yj[bb], zk[c])];
+            }
+            plane += (T)wy[bb] * row;
+        }
+        v += (T)wz[c] * plane;
+    }
+    const int64_t cf = lin(gf, i, j, k);
+    x[cf] = x[cf] + v;
+}
+
+template <typename T>
+hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& gc, hipStream_t s) {
+    dim3 grid = tile_grid(gf), block(kTileX, kTileY, 1);
+    if (gf.dim == 2) k_prolong_correct<T, 2><<<grid, block, 0, s>>>(x, xc, gf, gc);
+    else k_prolong_correct<T, 3><<<grid, block, 0, s>>>(x, xc, gf, gc);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Residual norm partials (and optionally the residual itself, converted).
+// --------------------------------------------------------------------------
+template <typename T, typename TR, int ORDER, int DIM>
+__global__ __launch_bounds__(256) void k_residual_norm(const T* __restrict__ x, const T* __restrict__ b, T bscale,
+                                                       Geo g, T a, double* __restrict__ partial, TR* __restrict__ r_out) {
+    const int64_t n = g.size();
+    double acc = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)kRedBlocks * 256) {
+        const int i = (int)(c % g.nx);
+        const int64_t q = c / g.nx;
+        const int j = (int)(q % g.ny);
+        const int k = (int)(q / g.ny);
+        const T xc = x[c];
+        const T r = bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM>(x, c, i, j, k, g, xc));
+        if (r_out) r_out[c] = (TR)r;
+        acc += (double)r * (double)r;
+    }
+    const double s = block_sum_256(acc, threadIdx.x);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T, typename TR>
+hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo& g, int order, double a,
+                                double* partial, TR* r_out, hipStream_t s) {
+    const T bs = (T)bscale, aa = (T)a;
+    if (g.dim == 2) {
+        if (order == 2) k_residual_norm<T, TR, 2, 2><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
+        else k_residual_norm<T, TR, 4, 2><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
+    } else {
+        if (order == 2) k_residual_norm<T, TR, 2, 3><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
+        else k_residual_norm<T, TR, 4, 3><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
+    }
+    return hipGetLastError();
+}
+
+#define EW_INST_MG(T)                                                                                          \
+    template hipError_t launch_rb_half<T>(const T*, T*, const T*, double, const Geo&, int, double, int,         \
+                                          hipStream_t);                                                        \
+    template hipError_t launch_residual_restrict<T>(const T*, const T*, double, const Geo&, int, double, T*,    \
+                                                    const Geo&, hipStream_t);                                  \
+    template hipError_t launch_prolong_correct<T>(T*, const T*, const Geo&, const Geo&, hipStream_t);
+EW_INST_MG(double)
+EW_INST_MG(float)
+#undef EW_INST_MG
+template hipError_t launch_residual_norm<double, double>(const double*, const double*, double, const Geo&, int,
+                                                         double, double*, double*, hipStream_t);
+template hipError_t launch_residual_norm<double, float>(const double*, const double*, double, const Geo&, int,
+                                                        double, double*, float*, hipStream_t);
+template hipError_t launch_residual_norm<float, float>(const float*, const float*, double, const Geo&, int, double,
+                                                       double*, float*, hipStream_t);
+
+}  // namespace ew

@@ -1,0 +1,70 @@
+// The operator object behind ew_op.
+#pragma once
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "ew_internal.h"
+
+namespace ew {
+
+// One multigrid level.  Storage type is double for the FP64 solver and float
+// for the FP32 inner solver of the mixed-precision defect correction.
+struct Level {
+    Geo g;
+    void* x[2] = {nullptr, nullptr};  // iterate and its out-of-place partner
+    void* b = nullptr;                // right-hand side (restricted residual)
+};
+
+struct Cnn;  // learned warm start (cnn.hip)
+
+struct Op {
+    // grid
+    int dim = 2, order = 2;
+    int64_t n[3] = {1, 1, 1};
+    double len[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+    Geo g{};
+    int64_t N = 0;
+    // operator
+    ew_op_desc desc{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool mixed = false, implicit = false;
+    double omega_used = 0, t_final = 0, dt = 0, alpha_d = 0, a = 0;
+    int n_t = 0;
+    std::vector<double> c;
+    // workspace
+    double* wA = nullptr;
+    double* wB = nullptr;
+    double* sbuf = nullptr;
+    float* f0 = nullptr;
+    float* fA = nullptr;
+    float* fB = nullptr;
+    float* acc32 = nullptr;
+    double* partial_dev = nullptr;
+    double* partial_host = nullptr;
+    std::vector<Level> levels;
+    std::vector<void*> allocations;
+    Cnn* cnn = nullptr;
+    ew_op_stats stats{};
+
+    ~Op();
+    ew_status alloc(void** p, size_t bytes);
+    ew_status host_sum_partials(double* out);
+    ew_status build_hierarchy();
+
+    // multigrid (wave.hip)
+    template <typename T>
+    ew_status vcycle(int level, T* x, T* xtmp, const T* b, double bscale);
+    template <typename T>
+    ew_status smooth(int level, T* x, T* xtmp, const T* b, double bscale, int sweeps);
+    ew_status mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);
+    ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);
+    ew_status implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess);
+    ew_status apply_filter(const double* v, double* out);
+};
+
+}  // namespace ew
+
+struct ew_op_s : public ew::Op {};

@@ -1,0 +1,244 @@
+// ew_op: the WaveHoltz operator S (one wave-solve + trapezoidal time filter)
+// on the device, with the implicit step's multigrid solver.
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "op.h"
+
+namespace ew {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+ew_status fail(ew_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+Geo make_geo(int dim, const int64_t* n, const double* h) {
+    Geo g;
+    g.dim = dim;
+    g.nx = (int)n[0];
+    g.ny = (int)n[1];
+    g.nz = dim == 3 ? (int)n[2] : 1;
+    g.ihx2 = 1.0 / (h[0] * h[0]);
+    g.ihy2 = 1.0 / (h[1] * h[1]);
+    g.ihz2 = dim == 3 ? 1.0 / (h[2] * h[2]) : 0.0;
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Time plan (host, FP64), computed in the same order of operations as the
+// definition: T_f = N_p 2 pi / omega; implicit N_t = N_p N_its; explicit
+// dt_max = 2 / sqrt(rho), rho = sum_d c / h_d^2, N_t = ceil(T_f / (cfl dt_max));
+// dt = T_f / N_t; c_n = (2/T_f) sigma_n (cos(omega n dt) - shift) with
+// trapezoid weights sigma_0 = sigma_{N_t} = dt/2, dt otherwise, and
+// shift = alpha_d/2 = tan(omega dt/2) / tan(omega dt) / 2 or 1/4.
+// ---------------------------------------------------------------------------
+static void make_plan(Op* op) {
+    const ew_op_desc& d = op->desc;
+    double om = d.omega;
+    if (d.adjust_omega) {
+        const double s = std::sin(M_PI / d.n_its);
+        const double s2 = s * s;
+        om = d.omega * M_PI / d.n_its * std::sqrt((1.0 - 2.0 * s2) / s2);
+    }
+    op->omega_used = om;
+    op->t_final = d.n_p * 2.0 * M_PI / om;
+    if (d.ts == EW_TS_IMPLICIT) {
+        op->n_t = d.n_p * d.n_its;
+    } else {
+        const double c = op->order == 2 ? 4.0 : 16.0 / 3.0;
+        double rho = 0.0;
+        for (int k = 0; k < op->dim; ++k) rho += c / (op->h[k] * op->h[k]);
+        const double dt_max = 2.0 / std::sqrt(rho);
+        op->n_t = (int)std::ceil(op->t_final / (d.cfl * dt_max));
+    }
+    op->dt = op->t_final / op->n_t;
+    op->alpha_d = std::tan(om * op->dt / 2.0) / std::tan(om * op->dt);
+    const double shift = d.filter_const == EW_FILTER_ALPHA_D ? op->alpha_d / 2.0 : 0.25;
+    op->c.resize(op->n_t + 1);
+    for (int k = 0; k <= op->n_t; ++k) {
+        const double sigma = (k == 0 || k == op->n_t) ? op->dt / 2.0 : op->dt;
+        op->c[k] = (2.0 / op->t_final) * sigma * (std::cos(om * k * op->dt) - shift);
+    }
+}
+
+Op::~Op() {
+    for (void* p : allocations) hipFree(p);
+    if (partial_host) hipHostFree(partial_host);
+}
+
+ew_status Op::alloc(void** p, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(EW_ERR_OOM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " +
+                                    hipGetErrorString(e));
+    }
+    allocations.push_back(*p);
+    return EW_OK;
+}
+
+// Sum of the kRedBlocks partials on the host, in a fixed order.
+ew_status Op::host_sum_partials(double* out) {
+    EW_HIP_TRY(hipMemcpyAsync(partial_host, partial_dev, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, stream));
+    EW_HIP_TRY(hipStreamSynchronize(stream));
+    double s = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) s += partial_host[b];
+    *out = s;
+    return EW_OK;
+}
+
+static ew_status validate(const ew_grid_desc* g, const ew_op_desc* d) {
+    if (!g || !d) return fail(EW_ERR_INVALID_ARG, "null descriptor");
+    if (g->dim != 2 && g->dim != 3) return fail(EW_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (g->order != 2 && g->order != 4) return fail(EW_ERR_INVALID_ARG, "order must be 2 or 4");
+    int64_t total = 1;
+    for (int k = 0; k < g->dim; ++k) {
+        if (g->n[k] < 1 || g->n[k] > 65535) return fail(EW_ERR_INVALID_ARG, "n[d] must be in [1, 65535]");
+        if (!(g->len[k] > 0.0) || !std::isfinite(g->len[k])) return fail(EW_ERR_INVALID_ARG, "len[d] must be > 0");
+        total *= g->n[k];
+    }
+    if (total > (int64_t)1 << 34) return fail(EW_ERR_INVALID_ARG, "grid too large");
+    if (!(d->omega > 0.0) || !std::isfinite(d->omega)) return fail(EW_ERR_INVALID_ARG, "omega must be > 0");
+    if (d->ts != EW_TS_EXPLICIT && d->ts != EW_TS_IMPLICIT) return fail(EW_ERR_INVALID_ARG, "ts must be explicit or implicit");
+    if (d->n_p < 1) return fail(EW_ERR_INVALID_ARG, "n_p must be >= 1");
+    if (d->filter_const != EW_FILTER_ALPHA_D && d->filter_const != EW_FILTER_QUARTER)
+        return fail(EW_ERR_INVALID_ARG, "filter_const must be ALPHA_D or QUARTER");
+    if (d->precision != EW_PREC_FP64 && d->precision != EW_PREC_MIXED)
+        return fail(EW_ERR_INVALID_ARG, "precision must be FP64 or MIXED");
+    if (d->ts == EW_TS_EXPLICIT) {
+        if (!(d->cfl > 0.0 && d->cfl <= 1.0)) return fail(EW_ERR_INVALID_ARG, "cfl must be in (0, 1]");
+        if (d->adjust_omega) return fail(EW_ERR_INVALID_ARG, "adjust_omega applies to implicit stepping only");
+    } else {
+        if (d->n_its < 5) return fail(EW_ERR_INVALID_ARG, "n_its must be >= 5");
+        if (!(d->mg_tol > 0.0 && d->mg_tol < 1.0)) return fail(EW_ERR_INVALID_ARG, "mg_tol must be in (0, 1)");
+        if (d->mg_nu1 < 0 || d->mg_nu2 < 0 || d->mg_nu1 + d->mg_nu2 < 1 || d->mg_nu1 > 8 || d->mg_nu2 > 8)
+            return fail(EW_ERR_INVALID_ARG, "mg_nu1, mg_nu2 must be in [0, 8] with nu1 + nu2 >= 1");
+        if (d->mg_max_cycles < 1 || d->mg_max_cycles > 10000) return fail(EW_ERR_INVALID_ARG, "mg_max_cycles must be in [1, 10000]");
+        if (d->mg_coarse_sweeps < 1 || d->mg_coarse_sweeps > 10000)
+            return fail(EW_ERR_INVALID_ARG, "mg_coarse_sweeps must be in [1, 10000]");
+        if (d->predictor != EW_PRED_ZERO && d->predictor != EW_PRED_SCALED && d->predictor != EW_PRED_CNN)
+            return fail(EW_ERR_INVALID_ARG, "unknown predictor");
+        if (d->predictor == EW_PRED_CNN && (g->dim != 2))
+            return fail(EW_ERR_UNSUPPORTED, "the learned predictor is implemented for 2D grids");
+    }
+    return EW_OK;
+}
+
+ew_status Op::build_hierarchy() {
+    // Level sizes: halve (n-1)/2 while every n_d is odd and >= 3.
+    std::vector<std::array<int64_t, 3>> sizes;
+    std::array<int64_t, 3> cur = {n[0], n[1], dim == 3 ? n[2] : 1};
+    sizes.push_back(cur);
+    while (sizes.size() < 64) {
+        bool ok = true;
+        for (int k = 0; k < dim; ++k) ok = ok && (cur[k] % 2 == 1) && cur[k] >= 3;
+        if (!ok) break;
+        for (int k = 0; k < dim; ++k) cur[k] = (cur[k] - 1) / 2;
+        sizes.push_back(cur);
+    }
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    levels.resize(sizes.size());
+    for (size_t l = 0; l < sizes.size(); ++l) {
+        Level& L = levels[l];
+        double hl[3];
+        for (int k = 0; k < 3; ++k) hl[k] = h[k] * std::ldexp(1.0, (int)l);
+        L.g = make_geo(dim, sizes[l].data(), hl);
+        const int64_t m = L.g.size();
+        // Level 0 of the FP64 solver works on the caller's x with one partner
+        // buffer; every other level (and every level of the FP32 inner solver)
+        // owns x, its partner and b.
+        EW_TRY(alloc(&L.x[1], m * es));
+        if (l > 0 || mixed) {
+            EW_TRY(alloc(&L.x[0], m * es));
+            EW_TRY(alloc(&L.b, m * es));
+        }
+    }
+    return EW_OK;
+}
+
+}  // namespace ew
+
+using namespace ew;
+
+extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* hip_stream, ew_op* out) {
+    if (!out) return fail(EW_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    EW_TRY(validate(grid, desc));
+    std::unique_ptr<ew_op_s> op(new ew_op_s());
+    op->dim = grid->dim;
+    op->order = grid->order;
+    for (int k = 0; k < 3; ++k) {
+        op->n[k] = k < grid->dim ? grid->n[k] : 1;
+        op->len[k] = k < grid->dim ? grid->len[k] : 1.0;
+        op->h[k] = op->len[k] / (double)(op->n[k] + 1);
+    }
+    op->desc = *desc;
+    op->stream = (hipStream_t)hip_stream;
+    op->mixed = desc->precision == EW_PREC_MIXED;
+    op->implicit = desc->ts == EW_TS_IMPLICIT;
+    op->g = make_geo(op->dim, op->n, op->h);
+    op->N = op->g.size();
+    EW_HIP_TRY(hipGetDevice(&op->device));
+    make_plan(op.get());
+    op->a = 0.5 * op->dt * op->dt;
+
+    const int64_t N = op->N;
+    EW_TRY(op->alloc((void**)&op->partial_dev, kRedBlocks * sizeof(double) * 4));
+    EW_HIP_TRY(hipHostMalloc((void**)&op->partial_host, kRedBlocks * sizeof(double) * 4, hipHostMallocDefault));
+    EW_TRY(op->alloc((void**)&op->wA, N * sizeof(double)));
+    EW_TRY(op->alloc((void**)&op->wB, N * sizeof(double)));
+    if (op->implicit) {
+        EW_TRY(op->alloc((void**)&op->sbuf, N * sizeof(double)));
+        EW_TRY(op->build_hierarchy());
+        if (op->mixed) {
+            EW_TRY(op->alloc((void**)&op->acc32, N * sizeof(float)));
+        }
+    } else if (op->mixed) {
+        EW_TRY(op->alloc((void**)&op->f0, N * sizeof(float)));
+        EW_TRY(op->alloc((void**)&op->fA, N * sizeof(float)));
+        EW_TRY(op->alloc((void**)&op->fB, N * sizeof(float)));
+        EW_TRY(op->alloc((void**)&op->acc32, N * sizeof(float)));
+    }
+    *out = op.release();
+    return EW_OK;
+}
+
+extern "C" void ew_op_destroy(ew_op op) { delete op; }
+
+extern "C" ew_status ew_op_get_info(ew_op op, ew_op_info* out) {
+    if (!op || !out) return fail(EW_ERR_INVALID_ARG, "null argument");
+    out->n_active = op->N;
+    out->n_t = op->n_t;
+    out->dt = op->dt;
+    out->omega_used = op->omega_used;
+    out->t_final = op->t_final;
+    out->alpha_d = op->alpha_d;
+    out->mg_levels = (int)op->levels.size();
+    return EW_OK;
+}
+
+extern "C" ew_status ew_op_get_stats(ew_op op, ew_op_stats* out) {
+    if (!op || !out) return fail(EW_ERR_INVALID_ARG, "null argument");
+    *out = op->stats;
+    return EW_OK;
+}
+
+extern "C" ew_status ew_op_reset_stats(ew_op op) {
+    if (!op) return fail(EW_ERR_INVALID_ARG, "null op");
+    std::memset(&op->stats, 0, sizeof(op->stats));
+    return EW_OK;
+}
+
+extern "C" ew_status ew_op_apply_laplacian(ew_op op, const double* v_dev, double* out_dev) {
+    if (!op || !v_dev || !out_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
+    if (v_dev == out_dev) return fail(EW_ERR_INVALID_ARG, "v and out may not alias");
+    EW_HIP_TRY(launch_laplacian<double>(v_dev, out_dev, op->g, op->order, op->stream));
+    op->stats.laplacian_applies++;
+    return EW_OK;
+}

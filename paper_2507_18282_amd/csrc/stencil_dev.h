@@ -1,0 +1,105 @@
+// Device helpers: thread-to-point mapping, stencils with the wall closure,
+// the diagonal of M = I - a L, and deterministic block reductions.
+#pragma once
+
+#include "ew_internal.h"
+
+namespace ew {
+
+constexpr int kTileX = 64;  // one wavefront along x: coalesced rows
+constexpr int kTileY = 4;
+
+__host__ inline dim3 tile_grid(const Geo& g) {
+    return dim3((unsigned)((g.nx + kTileX - 1) / kTileX), (unsigned)((g.ny + kTileY - 1) / kTileY), (unsigned)g.nz);
+}
+
+__device__ __forceinline__ bool tile_coords(const Geo& g, int& i, int& j, int& k) {
+    i = blockIdx.x * kTileX + threadIdx.x;
+    j = blockIdx.y * kTileY + threadIdx.y;
+    k = blockIdx.z;
+    return i < g.nx && j < g.ny;
+}
+
+__device__ __forceinline__ int64_t lin(const Geo& g, int i, int j, int k) {
+    return ((int64_t)k * g.ny + j) * g.nx + i;
+}
+
+// Second difference along one axis at interior index i (0-based) of n points,
+// un-scaled: order 2 returns u_{i-1} - 2u_i + u_{i+1}; order 4 returns
+// -u_{i-2} + 16u_{i-1} - 30u_i + 16u_{i+1} - u_{i+2}.  Index -1 and n are the
+// wall (value 0); index -2 and n+1 are ghosts equal to -u_0 and -u_{n-1}.
+template <typename T, int ORDER>
+__device__ __forceinline__ T d2_axis(const T* __restrict__ u, int64_t c, int i, int n, int64_t stride, T uc) {
+    const T l1 = (i > 0) ? u[c - stride] : T(0);
+    const T r1 = (i < n - 1) ? u[c + stride] : T(0);
+    if (ORDER == 2) {
+        return l1 + r1 - T(2) * uc;
+    } else {
+        const T l2 = (i > 1) ? u[c - 2 * stride] : (i == 1 ? T(0) : -uc);
+        const T r2 = (i < n - 2) ? u[c + 2 * stride] : (i == n - 2 ? T(0) : -uc);
+        return T(16) * (l1 + r1) - (l2 + r2) - T(30) * uc;
+    }
+}
+
+template <typename T, int ORDER>
+__device__ __forceinline__ T axis_coef(double ih2) {
+    return ORDER == 2 ? (T)ih2 : (T)(ih2 / 12.0);
+}
+
+template <typename T, int ORDER, int DIM>
+__device__ __forceinline__ T lap_at(const T* __restrict__ u, int64_t c, int i, int j, int k, const Geo& g, T uc) {
+    T s = d2_axis<T, ORDER>(u, c, i, g.nx, 1, uc) * axis_coef<T, ORDER>(g.ihx2);
+    s += d2_axis<T, ORDER>(u, c, j, g.ny, g.nx, uc) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3) s += d2_axis<T, ORDER>(u, c, k, g.nz, (int64_t)g.nx * g.ny, uc) * axis_coef<T, ORDER>(g.ihz2);
+    return s;
+}
+
+// Diagonal entry of L along one axis (un-scaled): -2 for order 2; order 4:
+// -30, plus 1 at each end where the odd-reflection ghost refers back to the
+// point itself.
+template <typename T, int ORDER>
+__device__ __forceinline__ T ldiag_axis(int i, int n) {
+    if (ORDER == 2) return T(-2);
+    T d = T(-30);
+    if (i == 0) d += T(1);
+    if (i == n - 1) d += T(1);
+    return d;
+}
+
+template <typename T, int ORDER, int DIM>
+__device__ __forceinline__ T mdiag_at(int i, int j, int k, const Geo& g, T a) {
+    T l = ldiag_axis<T, ORDER>(i, g.nx) * axis_coef<T, ORDER>(g.ihx2) +
+          ldiag_axis<T, ORDER>(j, g.ny) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3) l += ldiag_axis<T, ORDER>(k, g.nz) * axis_coef<T, ORDER>(g.ihz2);
+    return T(1) - a * l;
+}
+
+// Block-wide sum for 256 threads (4 wavefronts of 64): wavefront shuffles then
+// LDS.  The order of additions is fixed, so results are bitwise reproducible.
+// `tid` is the linear thread index within the block.
+__device__ __forceinline__ double block_sum_256(double v, int tid) {
+    __shared__ double red[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = tid & 63, wid = tid >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    return r;  // valid in thread 0 only
+}
+
+// Sum of the kRedBlocks partials, the same value in every thread of a
+// one-dimensional block of 256 threads.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p) {
+    __shared__ double total;
+    double v = 0.0;
+    for (int t = threadIdx.x; t < kRedBlocks; t += 256) v += p[t];
+    double r = block_sum_256(v, threadIdx.x);
+    if (threadIdx.x == 0) total = r;
+    __syncthreads();
+    return total;
+}
+
+}  // namespace ew

@@ -1,0 +1,239 @@
+// The wave-solve with time filter (S v) and the implicit step's multigrid
+// solver, orchestrated on the host and executed by the kernels of
+// stencil.hip and mg.hip on the operator's stream.
+#include <cmath>
+
+#include "op.h"
+
+namespace ew {
+
+template <typename T>
+ew_status Op::smooth(int l, T* x, T* xtmp, const T* b, double bscale, int sweeps) {
+    const Level& L = levels[l];
+    for (int s = 0; s < sweeps; ++s) {
+        EW_HIP_TRY(launch_rb_half<T>(x, xtmp, b, bscale, L.g, order, a, 0, stream));
+        EW_HIP_TRY(launch_rb_half<T>(xtmp, x, b, bscale, L.g, order, a, 1, stream));
+    }
+    return EW_OK;
+}
+
+// V(nu1, nu2) cycle on level l; on the coarsest level, exact for one point and
+// otherwise mg_coarse_sweeps sweeps from the incoming iterate.
+template <typename T>
+ew_status Op::vcycle(int l, T* x, T* xtmp, const T* b, double bscale) {
+    const int last = (int)levels.size() - 1;
+    const Level& L = levels[l];
+    if (l == last) {
+        const int sweeps = L.g.size() == 1 ? 1 : desc.mg_coarse_sweeps;
+        return smooth<T>(l, x, xtmp, b, bscale, sweeps);
+    }
+    EW_TRY(smooth<T>(l, x, xtmp, b, bscale, desc.mg_nu1));
+    const Level& C = levels[l + 1];
+    T* xc = (T*)C.x[0];
+    T* bc = (T*)C.b;
+    EW_HIP_TRY(launch_residual_restrict<T>(x, b, bscale, L.g, order, a, bc, C.g, stream));
+    EW_HIP_TRY(launch_fill<T>(xc, C.g.size(), T(0), stream));
+    EW_TRY(vcycle<T>(l + 1, xc, (T*)C.x[1], bc, 1.0));
+    EW_HIP_TRY(launch_prolong_correct<T>(x, xc, L.g, C.g, stream));
+    return smooth<T>(l, x, xtmp, b, bscale, desc.mg_nu2);
+}
+
+static ew_status check_rel(double rel) {
+    if (!std::isfinite(rel)) return fail(EW_ERR_NONFINITE, "non-finite multigrid residual");
+    return EW_OK;
+}
+
+// FP64 multigrid: x <- M^{-1} (bscale b) to ||r||_2 <= mg_tol ||bscale b||_2.
+ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel_out) {
+    EW_HIP_TRY(launch_dot_partial(b, b, N, partial_dev, stream));
+    double bb = 0.0;
+    EW_TRY(host_sum_partials(&bb));
+    const double bn = std::sqrt(bb) * std::fabs(bscale);
+    if (!std::isfinite(bn)) return fail(EW_ERR_NONFINITE, "non-finite right-hand side");
+    int cyc = 0;
+    double rel = 0.0;
+    if (bn == 0.0) {
+        EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
+    } else {
+        if (x_is_zero) {
+            rel = 1.0;
+        } else {
+            EW_HIP_TRY((launch_residual_norm<double, double>(x, b, bscale, g, order, a, partial_dev, nullptr, stream)));
+            double rr;
+            EW_TRY(host_sum_partials(&rr));
+            rel = std::sqrt(rr) / bn;
+            EW_TRY(check_rel(rel));
+        }
+        double* xtmp = (double*)levels[0].x[1];
+        while (rel > desc.mg_tol && cyc < desc.mg_max_cycles) {
+            EW_TRY(vcycle<double>(0, x, xtmp, b, bscale));
+            ++cyc;
+            EW_HIP_TRY((launch_residual_norm<double, double>(x, b, bscale, g, order, a, partial_dev, nullptr, stream)));
+            double rr;
+            EW_TRY(host_sum_partials(&rr));
+            rel = std::sqrt(rr) / bn;
+            EW_TRY(check_rel(rel));
+        }
+    }
+    stats.mg_solves++;
+    stats.mg_cycles += cyc;
+    if (cycles) *cycles = cyc;
+    if (rel_out) *rel_out = rel;
+    if (rel > desc.mg_tol)
+        return fail(EW_ERR_MG_NOT_CONVERGED, "multigrid reached mg_max_cycles with relative residual " +
+                                                 std::to_string(rel));
+    return EW_OK;
+}
+
+// Mixed precision: FP64 defect correction around FP32 V-cycles.  Each outer
+// iteration forms r = bscale b - M x in FP64 (stored as FP32 for the inner
+// solve), stops if ||r|| <= mg_tol ||bscale b||, else solves M e = r with one
+// FP32 V-cycle from zero and updates x += e in FP64.
+ew_status Op::mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles,
+                             double* rel_out) {
+    EW_HIP_TRY(launch_dot_partial(b, b, N, partial_dev, stream));
+    double bb = 0.0;
+    EW_TRY(host_sum_partials(&bb));
+    const double bn = std::sqrt(bb) * std::fabs(bscale);
+    if (!std::isfinite(bn)) return fail(EW_ERR_NONFINITE, "non-finite right-hand side");
+    if (x_is_zero) EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
+    int cyc = 0;
+    double rel = 0.0;
+    if (bn != 0.0) {
+        Level& L0 = levels[0];
+        float* r32 = (float*)L0.b;
+        float* e32 = (float*)L0.x[0];
+        float* t32 = (float*)L0.x[1];
+        for (;;) {
+            EW_HIP_TRY((launch_residual_norm<double, float>(x, b, bscale, g, order, a, partial_dev, r32, stream)));
+            double rr;
+            EW_TRY(host_sum_partials(&rr));
+            rel = std::sqrt(rr) / bn;
+            EW_TRY(check_rel(rel));
+            if (rel <= desc.mg_tol || cyc >= desc.mg_max_cycles) break;
+            EW_HIP_TRY(launch_fill<float>(e32, N, 0.0f, stream));
+            EW_TRY(vcycle<float>(0, e32, t32, r32, 1.0));
+            EW_HIP_TRY((launch_add_inplace<double, float>(x, e32, N, stream)));
+            ++cyc;
+        }
+    }
+    stats.mg_solves++;
+    stats.mg_cycles += cyc;
+    if (cycles) *cycles = cyc;
+    if (rel_out) *rel_out = rel;
+    if (rel > desc.mg_tol)
+        return fail(EW_ERR_MG_NOT_CONVERGED, "multigrid reached mg_max_cycles with relative residual " +
+                                                 std::to_string(rel));
+    return EW_OK;
+}
+
+ew_status cnn_predict(Op* op, const double* wcur, const double* wprev, double* guess_S);
+
+// One implicit solve M x = bscale b with the operator's initial-guess rule.
+ew_status Op::implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess) {
+    bool zero = false;
+    if (desc.predictor == EW_PRED_ZERO) {
+        zero = true;
+        if (!mixed) EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
+    } else if (desc.predictor == EW_PRED_SCALED || wprev_for_guess == nullptr || cnn == nullptr) {
+        // M phi = (1 + a mu) phi: exact for every mode at mu = omega^2.
+        const double s = bscale / (1.0 + a * omega_used * omega_used);
+        EW_HIP_TRY(launch_scale_copy<double>(x, b, N, s, stream));
+    } else {
+        EW_TRY(cnn_predict(this, b, wprev_for_guess, x));
+    }
+    if (mixed) return mg_solve_mixed(b, bscale, x, zero, nullptr, nullptr);
+    return mg_solve64(b, bscale, x, zero, nullptr, nullptr);
+}
+
+ew_status Op::apply_filter(const double* v, double* out) {
+    const double dt2 = dt * dt;
+    if (!implicit && !mixed) {
+        EW_HIP_TRY(launch_leapfrog<double>(v, nullptr, wA, out, g, order, dt2, c[0], c[1], 1, stream));
+        const double* prev = v;
+        double* cur = wA;
+        for (int k = 1; k < n_t; ++k) {
+            double* next = (prev == v) ? wB : const_cast<double*>(prev);
+            EW_HIP_TRY(launch_leapfrog<double>(cur, prev, next, out, g, order, dt2, 0.0, c[k + 1], 0, stream));
+            prev = cur;
+            cur = next;
+        }
+    } else if (!implicit && mixed) {
+        EW_HIP_TRY((launch_convert<float, double>(f0, v, N, 1.0, stream)));
+        EW_HIP_TRY(launch_leapfrog<float>(f0, nullptr, fA, acc32, g, order, dt2, c[0], c[1], 1, stream));
+        float* prev = f0;
+        float* cur = fA;
+        for (int k = 1; k < n_t; ++k) {
+            float* next = (prev == f0) ? fB : prev;
+            EW_HIP_TRY(launch_leapfrog<float>(cur, prev, next, acc32, g, order, dt2, 0.0, c[k + 1], 0, stream));
+            prev = cur;
+            cur = next;
+        }
+        EW_HIP_TRY((launch_convert<double, float>(out, acc32, N, 1.0, stream)));
+    } else {
+        // Implicit: M W^1 = W^0, then M S = 2 W^n, W^{n+1} = S - W^{n-1}.
+        EW_TRY(implicit_solve(v, 1.0, wA, nullptr));
+        if (mixed) EW_HIP_TRY((launch_implicit_update<double, float>(wA, v, wA, acc32, N, c[0], c[1], 1, stream)));
+        else EW_HIP_TRY((launch_implicit_update<double, double>(wA, v, wA, out, N, c[0], c[1], 1, stream)));
+        const double* prev = v;
+        double* cur = wA;
+        for (int k = 1; k < n_t; ++k) {
+            EW_TRY(implicit_solve(cur, 2.0, sbuf, prev));
+            double* next = (prev == v) ? wB : const_cast<double*>(prev);
+            if (mixed)
+                EW_HIP_TRY((launch_implicit_update<double, float>(sbuf, prev, next, acc32, N, 0.0, c[k + 1], 0, stream)));
+            else
+                EW_HIP_TRY((launch_implicit_update<double, double>(sbuf, prev, next, out, N, 0.0, c[k + 1], 0, stream)));
+            prev = cur;
+            cur = next;
+        }
+        if (mixed) EW_HIP_TRY((launch_convert<double, float>(out, acc32, N, 1.0, stream)));
+    }
+    stats.wave_solves++;
+    stats.time_steps += n_t;
+    stats.pt_updates += N * (int64_t)n_t;
+    return EW_OK;
+}
+
+template ew_status Op::vcycle<double>(int, double*, double*, const double*, double);
+template ew_status Op::vcycle<float>(int, float*, float*, const float*, double);
+
+}  // namespace ew
+
+using namespace ew;
+
+extern "C" ew_status ew_op_apply_filter(ew_op op, const double* v_dev, double* out_dev) {
+    if (!op || !v_dev || !out_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
+    if (v_dev == out_dev) return fail(EW_ERR_INVALID_ARG, "v and out may not alias");
+    return op->apply_filter(v_dev, out_dev);
+}
+
+extern "C" ew_status ew_op_mg_solve(ew_op op, const double* b_dev, double* x_dev, int* cycles_host,
+                                    double* rel_res_host) {
+    if (!op || !b_dev || !x_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
+    if (!op->implicit) return fail(EW_ERR_INVALID_ARG, "operator is not implicit");
+    if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
+    ew_status st = op->mixed ? op->mg_solve_mixed(b_dev, 1.0, x_dev, false, cycles_host, rel_res_host)
+                             : op->mg_solve64(b_dev, 1.0, x_dev, false, cycles_host, rel_res_host);
+    if (st != EW_OK) return st;
+    EW_HIP_TRY(hipStreamSynchronize(op->stream));
+    return EW_OK;
+}
+
+extern "C" ew_status ew_op_mg_vcycle(ew_op op, const double* b_dev, double* x_dev) {
+    if (!op || !b_dev || !x_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
+    if (!op->implicit || op->mixed) return fail(EW_ERR_INVALID_ARG, "needs an implicit FP64 operator");
+    if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
+    return op->vcycle<double>(0, x_dev, (double*)op->levels[0].x[1], b_dev, 1.0);
+}
+
+extern "C" ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* x_dev, int colour) {
+    if (!op || !b_dev || !x_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
+    if (!op->implicit || op->mixed) return fail(EW_ERR_INVALID_ARG, "needs an implicit FP64 operator");
+    if (colour != 0 && colour != 1) return fail(EW_ERR_INVALID_ARG, "colour must be 0 or 1");
+    if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
+    double* tmp = (double*)op->levels[0].x[1];
+    EW_HIP_TRY(launch_rb_half<double>(x_dev, tmp, b_dev, 1.0, op->g, op->order, op->a, colour, op->stream));
+    EW_HIP_TRY(hipMemcpyAsync(x_dev, tmp, op->N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));
+    return EW_OK;
+}

@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every function include/eigenwave.h
+declares (no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(ew_[a-z0-9_]+)\s*\(", text, flags=re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for want in ("ew_op_create", "ew_op_apply_filter", "ew_eigs", "ew_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2507_18282_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libeigenwave.so is not built (run python -m paper_2507_18282_amd.build)")
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # the binding declares a signature for exactly the header's functions
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+
+
+def test_version_and_last_error_need_no_gpu():
+    from paper_2507_18282_amd import _lib
+    lib = _lib.load()
+    assert b"gfx950" in lib.ew_version()
+    assert lib.ew_last_error() is not None
+
+
+def test_invalid_arguments_rejected_on_host():
+    """Argument validation happens before any device call."""
+    from paper_2507_18282_amd import _lib
+    lib = _lib.load()
+    g = _lib.GridDesc()
+    g.dim = 2
+    g.n[0] = g.n[1] = 8
+    g.len[0] = g.len[1] = 1.0
+    g.order = 3
+    d = _lib.OpDesc()
+    d.omega = 10.0
+    d.ts = 0
+    d.cfl = 0.5
+    d.n_p = 1
+    h = ctypes.c_void_p()
+    assert lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h)) == -1
+    assert b"order" in lib.ew_last_error()
+    g.order = 2
+    d.cfl = 1.5
+    assert lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h)) == -1
+    d.cfl = 0.5
+    d.ts = 1
+    d.n_its = 4
+    d.mg_tol = 1e-10
+    d.mg_nu1, d.mg_nu2, d.mg_max_cycles, d.mg_coarse_sweeps = 2, 1, 50, 8
+    assert lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h)) == -1
+    assert b"n_its" in lib.ew_last_error()
+    d.n_its = 10
+    d.omega = -1.0
+    assert lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h)) == -1
+    assert lib.ew_op_apply_filter(None, None, None) == -1
+
+
+def test_single_hip_runtime_in_process():
+    """The library binds to the HIP runtime PyTorch already loaded (a second
+    runtime in the process would not see the same devices and streams)."""
+    from paper_2507_18282_amd import _lib
+    _lib.load()
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    assert len(paths) == 1, paths

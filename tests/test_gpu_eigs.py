@@ -1,0 +1,114 @@
+"""Eigensolver on the GPU against the closed-form discrete spectrum.
+
+Bar (FP64): every returned eigenvalue within 1e-10 relative of a closed-form
+mu_h, every eigenvalue whose beta reaches the k-th largest present with its
+multiplicity, and L_h residuals <= 1e-8.  Mixed precision: 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import discrete as D
+from tests.gpu_helpers import make_op, oracle_plan, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def closed_form(P):
+    h, plan = oracle_plan(P)
+    mu = D.mu_all(P.n, h, P.order).ravel()
+    beta = D.beta_corrected(mu, plan)
+    order = np.argsort(-np.abs(beta), kind="stable")
+    return mu, beta, np.abs(beta[order[P.k - 1]])
+
+
+def check_result(P, r, rel_tol=1e-10, res_tol=1e-8):
+    mu_all, beta_all, beta_k = closed_form(P)
+    mu = np.array(r.mu)
+    assert r.n_conv >= P.k
+    for x in mu:
+        assert np.min(np.abs(mu_all - x)) / x < rel_tol
+    band = np.sort(mu_all[np.abs(beta_all) >= beta_k * (1 - 1e-10)])
+    for x in band:
+        want = np.sum(np.abs(band - x) <= 1e-9 * x)
+        assert np.sum(np.abs(mu - x) <= max(rel_tol, 1e-9) * x) >= want, (x, mu)
+    if res_tol is not None:
+        assert max(r.res) <= res_tol
+    # beta of each pair matches the closed form at its mu
+    h, plan = oracle_plan(P)
+    assert np.max(np.abs(D.beta_corrected(mu, plan) - np.array(r.beta))) < max(1e-8, 10 * rel_tol)
+
+
+def test_eigs_small_explicit_square():
+    """64^2 interior, order 2, explicit CFL 0.5, omega 15, k = 4, m = 16."""
+    P = synthetic.config_small_explicit()
+    op = make_op(P)
+    say("eigs small explicit")
+    r = op.eigs(P.k, P.m, seed=P.seed)
+    check_result(P, r)
+    # eigenvectors: unit norm and orthogonal
+    Y = to_host(r.Y.contiguous()).reshape(P.n_active, -1) if False else r.Y.cpu().numpy()
+    assert np.max(np.abs(Y.T @ Y - np.eye(Y.shape[1]))) < 1e-9
+    # four wanted: the two double eigenvalues (3,4)/(4,3) and (2,4)/(4,2)
+    want = sorted([D.mu_closed_form(mm, P.n, D.spacing(P.n, P.length), 2) for mm in ((3, 4), (4, 3), (2, 4), (4, 2))])
+    got = sorted(r.mu[:4])
+    assert np.max(np.abs(np.array(got) - np.array(want)) / np.array(want)) < 1e-10
+
+
+def test_eigs_start_vector_from_caller_matches_seeded():
+    P = synthetic.config_small_explicit()
+    op = make_op(P)
+    r1 = op.eigs(P.k, P.m, seed=P.seed)
+    v0 = synthetic.start_vector(P.seed, P.n_active)
+    r2 = op.eigs(P.k, P.m, seed=P.seed, v0=to_dev(v0))
+    assert r1.wave_solves == r2.wave_solves
+    assert np.array_equal(np.array(r1.mu), np.array(r2.mu))
+
+
+def test_eigs_repeatable_bitwise():
+    P = synthetic.config_small_explicit()
+    op = make_op(P)
+    r1 = op.eigs(P.k, P.m, seed=3)
+    r2 = op.eigs(P.k, P.m, seed=3)
+    assert np.array_equal(np.array(r1.mu), np.array(r2.mu))
+    assert np.array_equal(r1.Y.cpu().numpy(), r2.Y.cpu().numpy())
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_eigs_implicit_square(order):
+    P = synthetic.Problem(n=(63, 63), length=(1.0, 1.0), order=order, omega=20.0, ts="implicit",
+                          adjust_omega=True, k=6, m=16, seed=7)
+    op = make_op(P)
+    say("eigs implicit", order)
+    r = op.eigs(P.k, P.m, seed=P.seed)
+    check_result(P, r)
+
+
+def test_eigs_cube_multiplicity_three():
+    P = synthetic.Problem(n=(15, 15, 15), length=(1.0, 1.0, 1.0), order=2, omega=8.0, ts="implicit",
+                          adjust_omega=True, k=4, m=12, seed=9)
+    op = make_op(P)
+    say("eigs cube")
+    r = op.eigs(P.k, P.m, seed=P.seed)
+    check_result(P, r)
+
+
+def test_eigs_mixed_precision_rectangle():
+    P = synthetic.Problem(n=(63, 47), length=(1.0, 0.75), order=2, omega=18.0, ts="implicit",
+                          adjust_omega=True, precision="mixed", k=4, m=12, seed=5)
+    op = make_op(P)
+    say("eigs mixed")
+    r = op.eigs(P.k, P.m, seed=P.seed, tol_ritz=1e-7, tol_res=1e-4)
+    check_result(P, r, rel_tol=1e-5, res_tol=None)
+
+
+def test_eigs_lucky_breakdown_sine_start():
+    """Start vector = an exact eigenvector: the Krylov space is invariant after
+    one step; the solver must continue from a fresh direction and still find
+    the wanted set."""
+    P = synthetic.Problem(n=(31, 23), length=(1.0, 0.8), order=2, omega=14.0, ts="explicit", cfl=0.5,
+                          k=2, m=8, seed=2)
+    op = make_op(P)
+    v0 = D.sine_mode((3, 2), P.n).ravel()
+    r = op.eigs(P.k, P.m, v0=to_dev(v0), seed=P.seed)
+    check_result(P, r)
