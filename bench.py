@@ -1,0 +1,178 @@
+"""Benchmark of the WaveHoltz-filter eigensolver on one MI355X.
+
+A step is one Arnoldi step of the eigensolver on the headline workload: one
+wave-solve (S v: 10 implicit steps over one period, each solved by FP64
+multigrid V(2,1) cycles to relative residual 1e-10, filter accumulated in the
+same loop) plus the modified Gram-Schmidt orthogonalisation against the basis,
+with the Krylov-Schur restarts that fall inside the timed steps.
+
+Headline workload: unit square, 2049 x 2049 grid points (2047^2 interior
+unknowns, h = 1/2048), 4th-order Laplacian, implicit stepping with 10 steps
+per period, omega = 120 (adjusted to 109.7306), Krylov dimension 32 for 16
+eigenpairs, SplitMix64 start vector (seed 2).  Inputs are synthetic and
+resident in HBM before the timed region starts.
+
+value = grid-point updates per second (active points x time steps advanced)
+over the K timed steps.  Eigenpairs per second at residual <= 1e-8 are
+measured on a complete solve of the 64^2 explicit workload (the largest one
+whose complete solve fits the bench's time budget) and reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "grid-pt updates/s + eigenpairs/s at resid 1e-8; learned/batched vs plain"
+SMOOTH_SRC = os.path.join(ROOT, "paper_2507_18282_amd", "csrc", "mg.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_square2047_order4.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the smoother from the committed rocprofv3 counter
+    summary, or None when the counters were taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != source_digest(SMOOTH_SRC):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(P, n_solves: int):
+    """The oracle, as it stands, on a bounded sample: n_solves wave-solves of the
+    headline grid (exact sine-transform implicit solves; single-threaded numpy
+    and scipy.fft)."""
+    import numpy as np
+    import synthetic
+    from oracle import discrete as D
+    from oracle import wave as W
+    h = D.spacing(P.n, P.length)
+    plan = D.time_plan(h, P.order, P.omega, P.ts, n_its=P.n_its, n_p=P.n_p, adjust_omega=P.adjust_omega)
+    v = synthetic.start_vector(P.seed, P.n_active).reshape(P.n[::-1])
+    t0 = time.perf_counter()
+    for _ in range(n_solves):
+        v = W.apply_filter(v, h, P.order, plan)
+        v = v / np.linalg.norm(v)
+    dt = time.perf_counter() - t0
+    return {"value": P.n_active * plan.n_t * n_solves / dt, "unit": "grid-pt updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_solves} wave-solves of the 2047^2 order-4 implicit grid ({plan.n_t} steps each, "
+                      f"exact DST solves instead of multigrid), {dt:.1f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-solves", type=int, default=4)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU decomposition is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        return 2
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Operator
+
+    torch.cuda.set_device(0)
+    P = synthetic.config_square_order4_implicit()
+    op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=P.n_p,
+                  adjust_omega=P.adjust_omega, precision=P.precision, mg_tol=P.mg_tol)
+    log(f"workload {P.n} order {P.order} n_t {op.n_t} omega_used {op.omega_used:.4f} levels {op.mg_levels}")
+    if a.warmup > 0:
+        op.eigs(P.k, P.m, seed=P.seed, max_wave_solves=a.warmup, want_vectors=False, raise_on_error=False)
+    log("warmup done")
+    torch.cuda.synchronize()
+    op.profile_begin("smooth", level=0)
+    t0 = time.perf_counter()
+    r = op.eigs(P.k, P.m, seed=P.seed, max_wave_solves=a.steps, want_vectors=False, raise_on_error=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = op.profile_end()
+    elapsed = t1 - t0
+    assert r.wave_solves == a.steps, (r.wave_solves, a.steps)
+    value = r.pt_updates / elapsed
+    log(f"timed {a.steps} steps in {elapsed:.3f} s; MG cycles per implicit solve "
+        f"{r.mg_cycles / max(1, r.time_steps):.2f}")
+
+    avg_ms = prof["total_ms"] / max(1, prof["launches"])
+    bytes_per_launch = prof["bytes_alg"] / max(1, prof["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "kernel": "red-black Gauss-Seidel half-sweep, finest level (k_rb_half<double,4,2>)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "launches": prof["launches"], "avg_us": round(avg_ms * 1e3, 3),
+                "bytes_alg_per_launch": bytes_per_launch,
+                "kernel_share_of_step": round(prof["total_ms"] * 1e-3 / elapsed, 3)}
+
+    # Eigenpairs per second: a complete solve of the 64^2 explicit workload.
+    P1 = synthetic.config_small_explicit()
+    op1 = Operator(n=P1.n, length=P1.length, order=P1.order, omega=P1.omega, ts=P1.ts, cfl=P1.cfl)
+    op1.eigs(P1.k, P1.m, seed=P1.seed, want_vectors=False)  # warm
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    r1 = op1.eigs(P1.k, P1.m, seed=P1.seed, want_vectors=False)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    n_ok = sum(1 for x in r1.res if x <= 1e-8)
+    eig = {"value": n_ok / (t3 - t2), "unit": "eigenpairs/s", "pairs": n_ok, "requested": P1.k,
+           "wave_solves": r1.wave_solves, "seconds": round(t3 - t2, 4), "max_res": max(r1.res),
+           "pt_updates_per_s": r1.pt_updates / (t3 - t2),
+           "workload": "unit square 64^2 interior (h = 1/65), order 2, explicit leapfrog CFL 0.5 (78 steps), "
+                       "omega 15, Krylov dimension 16, 4 requested, seed 1"}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(P, a.cpu_solves)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid-pt updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": elapsed / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "unit square 2049^2 points (2047^2 interior, h=1/2048), 4th-order Laplacian, "
+                               "implicit 10 steps/period, FP64 multigrid V(2,1) to rel. residual 1e-10, "
+                               "omega 120 (adjusted 109.7306), Arnoldi m=32 for k=16, seed 2",
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "mg_cycles_per_implicit_solve": round(r.mg_cycles / max(1, r.time_steps), 3),
+        "eigenpairs_per_s": eig,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -209,6 +209,31 @@ typedef struct {
 ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host, double* beta_host,
                   double* res_host, double* Y_dev, ew_eigs_stats* stats);
 
+/* Kernel timing inside an operator (the tracing facility).  Between
+ * ew_op_profile_begin and ew_op_profile_end, every launch of kernel class
+ * `kclass` that the operator issues on multigrid level `level` (any level if
+ * level < 0; levels count from 0 = finest) is bracketed by hipEvents recorded
+ * on the operator's stream.  bytes_alg accumulates, per launch, the
+ * algorithmic bytes of that kernel: every array it must read or write counted
+ * once at its storage precision.  At most 65536 launches are timed per
+ * session.  ew_op_profile_end is host-blocking. */
+enum {
+    EW_K_LEAPFROG = 0,  /* explicit step + filter accumulation */
+    EW_K_SMOOTH = 1,    /* red-black Gauss-Seidel sweep */
+    EW_K_RESTRICT = 2,  /* residual + full-weighting restriction */
+    EW_K_PROLONG = 3,   /* prolongation + correction */
+    EW_K_RESNORM = 4,   /* residual norm (convergence test) */
+    EW_K_UPDATE = 5,    /* implicit update + filter accumulation */
+    EW_K_COARSE = 6     /* coarse-level V-cycle in one workgroup */
+};
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double bytes_alg;
+} ew_kernel_profile;
+ew_status ew_op_profile_begin(ew_op op, int kclass, int level);
+ew_status ew_op_profile_end(ew_op op, ew_kernel_profile* out);
+
 /* Fill x_dev (n FP64, device) with SplitMix64 uniform[-1,1) values of stream
  * `seed`: element i is 2*((z_i >> 11) * 2^-53) - 1 with z_i the SplitMix64
  * output for counter i+1.  Stream-ordered on `hip_stream`. */

@@ -125,6 +125,15 @@ class Operator:
     def reset_stats(self) -> None:
         check(self._lib.ew_op_reset_stats(self._h))
 
+    def profile_begin(self, kclass: str, level: int = -1) -> None:
+        """Start timing every launch of one kernel class with hipEvents (see ew_op_profile_begin)."""
+        check(self._lib.ew_op_profile_begin(self._h, _lib.KCLASS[kclass], int(level)))
+
+    def profile_end(self) -> dict:
+        p = _lib.KernelProfile()
+        check(self._lib.ew_op_profile_end(self._h, ctypes.byref(p)))
+        return {"launches": int(p.launches), "total_ms": float(p.total_ms), "bytes_alg": float(p.bytes_alg)}
+
     def apply_filter(self, v, out=None):
         out = self._new() if out is None else out
         check(self._lib.ew_op_apply_filter(self._h, _dev_ptr(v, self.n_active), _dev_ptr(out, self.n_active)))

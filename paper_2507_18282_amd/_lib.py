@@ -53,6 +53,13 @@ class EigsStats(ctypes.Structure):
                 ("seconds", c_double), ("max_res", c_double)]
 
 
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", c_int64), ("total_ms", c_double), ("bytes_alg", c_double)]
+
+
+KCLASS = {"leapfrog": 0, "smooth": 1, "restrict": 2, "prolong": 3, "resnorm": 4, "update": 5, "coarse": 6}
+
+
 # name -> (restype, argtypes); every symbol include/eigenwave.h declares.
 SIGNATURES = {
     "ew_op_create": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
@@ -67,6 +74,8 @@ SIGNATURES = {
     "ew_op_mg_half_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     "ew_eigs": (c_int, [c_void_p, POINTER(EigsDesc), c_int, POINTER(c_double), POINTER(c_double),
                         POINTER(c_double), c_void_p, POINTER(EigsStats)]),
+    "ew_op_profile_begin": (c_int, [c_void_p, c_int, c_int]),
+    "ew_op_profile_end": (c_int, [c_void_p, POINTER(KernelProfile)]),
     "ew_fill_uniform": (c_int, [c_void_p, c_int64, c_uint64, c_void_p]),
     "ew_last_error": (c_char_p, []),
     "ew_version": (c_char_p, []),

@@ -120,6 +120,13 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
     for (;;) {
         for (int j = p; j < m; ++j) {
             double* w = ws.col(ws.V, j + 1);
+            if (wave_solves >= ws_budget) {
+                // Budget reached inside a cycle: report no converged pairs.
+                out.theta.clear();
+                out.conv.clear();
+                out.Q = Mat(m, m);
+                return EW_OK;
+            }
             EW_TRY(op->apply_filter(ws.col(ws.V, j), w));
             ++wave_solves;
             u.clear();
@@ -228,7 +235,7 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
     const int64_t N = op->N;
     if (k < 1 || m <= k || m > 256 || (int64_t)m > N) return fail(EW_ERR_INVALID_ARG, "need 1 <= k < m <= min(256, n_active)");
     if (!(desc->tol_ritz > 0.0) || !(desc->tol_res > 0.0)) return fail(EW_ERR_INVALID_ARG, "tolerances must be > 0");
-    if (desc->max_wave_solves < m) return fail(EW_ERR_INVALID_ARG, "max_wave_solves must be >= m");
+    if (desc->max_wave_solves < 1) return fail(EW_ERR_INVALID_ARG, "max_wave_solves must be >= 1");
     if (k_cap < 0 || (k_cap > 0 && (!mu_host || !beta_host || !res_host)))
         return fail(EW_ERR_INVALID_ARG, "k_cap > 0 needs mu_host, beta_host and res_host");
     int n_keep = desc->n_keep > 0 ? desc->n_keep : std::max(k, (m + k) / 2);
@@ -276,8 +283,9 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
         EW_TRY(ks_run(ws, nl, n_keep, desc->tol_ritz, probe, k, floor_abs, desc->max_wave_solves, desc->seed,
                       wave_solves, restarts, rr));
         ++runs;
-        int nlead = leading_converged(rr.conv);
         if (wave_solves >= desc->max_wave_solves) budget_hit = true;
+        if (rr.theta.empty()) break;  // stopped by the budget inside a cycle
+        int nlead = leading_converged(rr.conv);
         if (probe == 0 && nlead < k) break;  // budget exhausted before the first k converged
         if (probe > 0) {
             if (!rr.conv[0] || std::fabs(rr.theta[0]) < floor_abs) {
@@ -297,6 +305,17 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
     }
 
     if (nl < k) {
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->wave_solves = wave_solves;
+            stats->restarts = restarts;
+            stats->probes = runs;
+            stats->time_steps = op->stats.time_steps - s0.time_steps;
+            stats->pt_updates = op->stats.pt_updates - s0.pt_updates;
+            stats->mg_cycles = op->stats.mg_cycles - s0.mg_cycles;
+            EW_HIP_TRY(hipStreamSynchronize(op->stream));
+            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
         return fail(EW_ERR_NOT_CONVERGED, "eigensolver reached max_wave_solves with " + std::to_string(nl) +
                                               " converged pairs");
     }

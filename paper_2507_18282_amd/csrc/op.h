@@ -19,6 +19,26 @@ struct Level {
 
 struct Cnn;  // learned warm start (cnn.hip)
 
+// hipEvent timing of one kernel class (ew_op_profile_*).
+struct Profiler {
+    int kclass = -1, level = -1;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    int64_t launches = 0;
+    double bytes = 0.0;
+    static constexpr size_t kMaxLaunches = 65536;
+    bool wants(int kc, int lv) const { return kc == kclass && (level < 0 || level == lv) && used + 2 <= 2 * kMaxLaunches; }
+};
+
+struct Op;
+// Brackets one launch with events when the profiler asks for it.
+struct ProfScope {
+    Op* op;
+    bool on;
+    ProfScope(Op* o, int kclass, int level, double bytes);
+    ~ProfScope();
+};
+
 struct Op {
     // grid
     int dim = 2, order = 2;
@@ -48,6 +68,7 @@ struct Op {
     std::vector<void*> allocations;
     Cnn* cnn = nullptr;
     ew_op_stats stats{};
+    Profiler prof;
 
     ~Op();
     ew_status alloc(void** p, size_t bytes);

@@ -69,6 +69,28 @@ static void make_plan(Op* op) {
 Op::~Op() {
     for (void* p : allocations) hipFree(p);
     if (partial_host) hipHostFree(partial_host);
+    for (hipEvent_t e : prof.pool) hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Op* o, int kclass, int level, double bytes) : op(o), on(false) {
+    Profiler& p = op->prof;
+    if (!p.wants(kclass, level)) return;
+    while (p.pool.size() < p.used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        p.pool.push_back(e);
+    }
+    if (hipEventRecord(p.pool[p.used], op->stream) != hipSuccess) return;
+    on = true;
+    p.launches++;
+    p.bytes += bytes;
+}
+
+ProfScope::~ProfScope() {
+    if (!on) return;
+    Profiler& p = op->prof;
+    hipEventRecord(p.pool[p.used + 1], op->stream);
+    p.used += 2;
 }
 
 ew_status Op::alloc(void** p, size_t bytes) {
@@ -240,5 +262,34 @@ extern "C" ew_status ew_op_apply_laplacian(ew_op op, const double* v_dev, double
     if (v_dev == out_dev) return fail(EW_ERR_INVALID_ARG, "v and out may not alias");
     EW_HIP_TRY(launch_laplacian<double>(v_dev, out_dev, op->g, op->order, op->stream));
     op->stats.laplacian_applies++;
+    return EW_OK;
+}
+
+extern "C" ew_status ew_op_profile_begin(ew_op op, int kclass, int level) {
+    if (!op) return fail(EW_ERR_INVALID_ARG, "null op");
+    if (kclass < EW_K_LEAPFROG || kclass > EW_K_COARSE) return fail(EW_ERR_INVALID_ARG, "unknown kernel class");
+    op->prof.kclass = kclass;
+    op->prof.level = level;
+    op->prof.used = 0;
+    op->prof.launches = 0;
+    op->prof.bytes = 0.0;
+    return EW_OK;
+}
+
+extern "C" ew_status ew_op_profile_end(ew_op op, ew_kernel_profile* out) {
+    if (!op || !out) return fail(EW_ERR_INVALID_ARG, "null argument");
+    Profiler& p = op->prof;
+    double total = 0.0;
+    if (p.used > 0) EW_HIP_TRY(hipEventSynchronize(p.pool[p.used - 1]));
+    for (size_t i = 0; i + 1 < p.used; i += 2) {
+        float ms = 0.0f;
+        EW_HIP_TRY(hipEventElapsedTime(&ms, p.pool[i], p.pool[i + 1]));
+        total += ms;
+    }
+    out->launches = p.launches;
+    out->total_ms = total;
+    out->bytes_alg = p.bytes;
+    p.kclass = -1;
+    p.used = 0;
     return EW_OK;
 }

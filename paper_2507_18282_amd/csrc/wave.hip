@@ -10,9 +10,18 @@ namespace ew {
 template <typename T>
 ew_status Op::smooth(int l, T* x, T* xtmp, const T* b, double bscale, int sweeps) {
     const Level& L = levels[l];
+    // algorithmic bytes of a half-sweep: read x everywhere, read b and write x
+    // at the points of one colour
+    const double bytes = 2.0 * sizeof(T) * (double)L.g.size();
     for (int s = 0; s < sweeps; ++s) {
-        EW_HIP_TRY(launch_rb_half<T>(x, xtmp, b, bscale, L.g, order, a, 0, stream));
-        EW_HIP_TRY(launch_rb_half<T>(xtmp, x, b, bscale, L.g, order, a, 1, stream));
+        {
+            ProfScope ps(this, EW_K_SMOOTH, l, bytes);
+            EW_HIP_TRY(launch_rb_half<T>(x, xtmp, b, bscale, L.g, order, a, 0, stream));
+        }
+        {
+            ProfScope ps(this, EW_K_SMOOTH, l, bytes);
+            EW_HIP_TRY(launch_rb_half<T>(xtmp, x, b, bscale, L.g, order, a, 1, stream));
+        }
     }
     return EW_OK;
 }
@@ -31,10 +40,16 @@ ew_status Op::vcycle(int l, T* x, T* xtmp, const T* b, double bscale) {
     const Level& C = levels[l + 1];
     T* xc = (T*)C.x[0];
     T* bc = (T*)C.b;
-    EW_HIP_TRY(launch_residual_restrict<T>(x, b, bscale, L.g, order, a, bc, C.g, stream));
+    {
+        ProfScope ps(this, EW_K_RESTRICT, l, sizeof(T) * (2.0 * L.g.size() + C.g.size()));
+        EW_HIP_TRY(launch_residual_restrict<T>(x, b, bscale, L.g, order, a, bc, C.g, stream));
+    }
     EW_HIP_TRY(launch_fill<T>(xc, C.g.size(), T(0), stream));
     EW_TRY(vcycle<T>(l + 1, xc, (T*)C.x[1], bc, 1.0));
-    EW_HIP_TRY(launch_prolong_correct<T>(x, xc, L.g, C.g, stream));
+    {
+        ProfScope ps(this, EW_K_PROLONG, l, sizeof(T) * (2.0 * L.g.size() + C.g.size()));
+        EW_HIP_TRY(launch_prolong_correct<T>(x, xc, L.g, C.g, stream));
+    }
     return smooth<T>(l, x, xtmp, b, bscale, desc.mg_nu2);
 }
 
@@ -68,7 +83,10 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
         while (rel > desc.mg_tol && cyc < desc.mg_max_cycles) {
             EW_TRY(vcycle<double>(0, x, xtmp, b, bscale));
             ++cyc;
-            EW_HIP_TRY((launch_residual_norm<double, double>(x, b, bscale, g, order, a, partial_dev, nullptr, stream)));
+            {
+                ProfScope ps(this, EW_K_RESNORM, 0, 16.0 * (double)N);
+                EW_HIP_TRY((launch_residual_norm<double, double>(x, b, bscale, g, order, a, partial_dev, nullptr, stream)));
+            }
             double rr;
             EW_TRY(host_sum_partials(&rr));
             rel = std::sqrt(rr) / bn;
@@ -105,7 +123,10 @@ ew_status Op::mg_solve_mixed(const double* b, double bscale, double* x, bool x_i
         float* e32 = (float*)L0.x[0];
         float* t32 = (float*)L0.x[1];
         for (;;) {
-            EW_HIP_TRY((launch_residual_norm<double, float>(x, b, bscale, g, order, a, partial_dev, r32, stream)));
+            {
+                ProfScope ps(this, EW_K_RESNORM, 0, 20.0 * (double)N);
+                EW_HIP_TRY((launch_residual_norm<double, float>(x, b, bscale, g, order, a, partial_dev, r32, stream)));
+            }
             double rr;
             EW_TRY(host_sum_partials(&rr));
             rel = std::sqrt(rr) / bn;
@@ -149,22 +170,30 @@ ew_status Op::implicit_solve(const double* b, double bscale, double* x, const do
 ew_status Op::apply_filter(const double* v, double* out) {
     const double dt2 = dt * dt;
     if (!implicit && !mixed) {
-        EW_HIP_TRY(launch_leapfrog<double>(v, nullptr, wA, out, g, order, dt2, c[0], c[1], 1, stream));
+        {
+            ProfScope ps(this, EW_K_LEAPFROG, 0, 24.0 * (double)N);
+            EW_HIP_TRY(launch_leapfrog<double>(v, nullptr, wA, out, g, order, dt2, c[0], c[1], 1, stream));
+        }
         const double* prev = v;
         double* cur = wA;
         for (int k = 1; k < n_t; ++k) {
             double* next = (prev == v) ? wB : const_cast<double*>(prev);
+            ProfScope ps(this, EW_K_LEAPFROG, 0, 40.0 * (double)N);
             EW_HIP_TRY(launch_leapfrog<double>(cur, prev, next, out, g, order, dt2, 0.0, c[k + 1], 0, stream));
             prev = cur;
             cur = next;
         }
     } else if (!implicit && mixed) {
         EW_HIP_TRY((launch_convert<float, double>(f0, v, N, 1.0, stream)));
-        EW_HIP_TRY(launch_leapfrog<float>(f0, nullptr, fA, acc32, g, order, dt2, c[0], c[1], 1, stream));
+        {
+            ProfScope ps(this, EW_K_LEAPFROG, 0, 12.0 * (double)N);
+            EW_HIP_TRY(launch_leapfrog<float>(f0, nullptr, fA, acc32, g, order, dt2, c[0], c[1], 1, stream));
+        }
         float* prev = f0;
         float* cur = fA;
         for (int k = 1; k < n_t; ++k) {
             float* next = (prev == f0) ? fB : prev;
+            ProfScope ps(this, EW_K_LEAPFROG, 0, 20.0 * (double)N);
             EW_HIP_TRY(launch_leapfrog<float>(cur, prev, next, acc32, g, order, dt2, 0.0, c[k + 1], 0, stream));
             prev = cur;
             cur = next;
@@ -180,6 +209,7 @@ ew_status Op::apply_filter(const double* v, double* out) {
         for (int k = 1; k < n_t; ++k) {
             EW_TRY(implicit_solve(cur, 2.0, sbuf, prev));
             double* next = (prev == v) ? wB : const_cast<double*>(prev);
+            ProfScope ps(this, EW_K_UPDATE, 0, (mixed ? 32.0 : 40.0) * (double)N);
             if (mixed)
                 EW_HIP_TRY((launch_implicit_update<double, float>(sbuf, prev, next, acc32, N, 0.0, c[k + 1], 0, stream)));
             else
