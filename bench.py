@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-pt updates/s + eigenpairs/s at resid 1e-8; learned/batched vs plain"
-SMOOTH_SRC = os.path.join(ROOT, "paper_2507_18282_amd", "csrc", "mg.hip")
+SMOOTH_SRC = os.path.join(ROOT, "paper_2507_18282_amd", "csrc", "sweep2d.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_square2047_order4.txt")
 
 
@@ -129,7 +129,8 @@ def main(argv=None) -> int:
     bytes_per_launch = prof["bytes_alg"] / max(1, prof["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic()
-    roofline = {"bound": "hbm", "kernel": "red-black Gauss-Seidel half-sweep, finest level (k_rb_half<double,4,2>)",
+    roofline = {"bound": "hbm",
+                "kernel": "red-black Gauss-Seidel sweep, finest level (k_sweep_tile2d<double, 4, 32, false, false>)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "launches": prof["launches"], "avg_us": round(avg_ms * 1e3, 3),

@@ -87,7 +87,14 @@ typedef struct {
  *   mg_tol, mg_nu1, mg_nu2, mg_max_cycles, mg_coarse_sweeps
  *                      implicit only: V(nu1,nu2) cycles of red-black
  *                      Gauss-Seidel multigrid on M = I - (dt^2/2) L_h (eq.
- *                      impMatrix) until ||b - M x||_2 <= mg_tol ||b||_2.
+ *                      impMatrix) until ||b - M x||_2 <= mg_tol ||b||_2;
+ *                      mg_coarse_sweeps sweeps on a coarsest level of more
+ *                      than one point.
+ *   mg_coarse_points   largest level (in points) that is handed to the
+ *                      single-workgroup kernel that runs all remaining coarser
+ *                      levels in LDS; 0 = the largest that fits (<= 8192 points
+ *                      and 160 KB of LDS for the arrays of all those levels).
+ *                      Results do not depend on it beyond rounding order.
  *   predictor          initial guess of each implicit solve: EW_PRED_ZERO, or
  *                      EW_PRED_SCALED (x0 = b / (1 + a omega^2), exact for
  *                      every mode with lambda = omega since M phi = (1 + a mu) phi), or
@@ -106,6 +113,7 @@ typedef struct {
     int mg_nu2;
     int mg_max_cycles;
     int mg_coarse_sweeps;
+    int mg_coarse_points;
     int predictor;
 } ew_op_desc;
 
@@ -219,12 +227,13 @@ ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host
  * session.  ew_op_profile_end is host-blocking. */
 enum {
     EW_K_LEAPFROG = 0,  /* explicit step + filter accumulation */
-    EW_K_SMOOTH = 1,    /* red-black Gauss-Seidel sweep */
+    EW_K_SMOOTH = 1,    /* red-black Gauss-Seidel sweep reading the iterate */
     EW_K_RESTRICT = 2,  /* residual + full-weighting restriction */
-    EW_K_PROLONG = 3,   /* prolongation + correction */
+    EW_K_PROLONG = 3,   /* prolongation + correction (fused with the first post-sweep) */
     EW_K_RESNORM = 4,   /* residual norm (convergence test) */
     EW_K_UPDATE = 5,    /* implicit update + filter accumulation */
-    EW_K_COARSE = 6     /* coarse-level V-cycle in one workgroup */
+    EW_K_COARSE = 6,    /* coarse-level V-cycle in one workgroup */
+    EW_K_SMOOTH_ZERO = 7 /* first sweep from a zero iterate (iterate not read) */
 };
 typedef struct {
     int64_t launches;

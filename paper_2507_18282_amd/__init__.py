@@ -63,7 +63,7 @@ class Operator:
                  cfl: float = 0.5, n_its: int = 10, n_p: int = 1, adjust_omega: bool = False,
                  filter_const: str = "alpha_d", precision: str = "fp64", mg_tol: float = 1e-10,
                  mg_nu1: int = 2, mg_nu2: int = 1, mg_max_cycles: int = 100, mg_coarse_sweeps: int = 8,
-                 predictor: str = "zero", stream=None):
+                 mg_coarse_points: int = 0, predictor: str = "zero", stream=None):
         lib = load()
         self._lib = lib
         g = _lib.GridDesc()
@@ -86,6 +86,7 @@ class Operator:
         d.mg_nu2 = int(mg_nu2)
         d.mg_max_cycles = int(mg_max_cycles)
         d.mg_coarse_sweeps = int(mg_coarse_sweeps)
+        d.mg_coarse_points = int(mg_coarse_points)
         d.predictor = _lib.PREDICTOR[predictor]
         self._stream = stream
         self._h = ctypes.c_void_p()

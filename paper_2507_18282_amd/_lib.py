@@ -28,7 +28,7 @@ class OpDesc(ctypes.Structure):
     _fields_ = [("omega", c_double), ("ts", c_int), ("cfl", c_double), ("n_its", c_int), ("n_p", c_int),
                 ("adjust_omega", c_int), ("filter_const", c_int), ("precision", c_int), ("mg_tol", c_double),
                 ("mg_nu1", c_int), ("mg_nu2", c_int), ("mg_max_cycles", c_int), ("mg_coarse_sweeps", c_int),
-                ("predictor", c_int)]
+                ("mg_coarse_points", c_int), ("predictor", c_int)]
 
 
 class OpInfo(ctypes.Structure):
@@ -57,7 +57,8 @@ class KernelProfile(ctypes.Structure):
     _fields_ = [("launches", c_int64), ("total_ms", c_double), ("bytes_alg", c_double)]
 
 
-KCLASS = {"leapfrog": 0, "smooth": 1, "restrict": 2, "prolong": 3, "resnorm": 4, "update": 5, "coarse": 6}
+KCLASS = {"leapfrog": 0, "smooth": 1, "restrict": 2, "prolong": 3, "resnorm": 4, "update": 5, "coarse": 6,
+          "smooth_zero": 7}
 
 
 # name -> (restype, argtypes); every symbol include/eigenwave.h declares.

@@ -1,0 +1,44 @@
+"""Workload for rocprofv3 counter runs: one plain device copy of a known size
+(the calibration for FETCH_SIZE / WRITE_SIZE) followed by wave-solves of the
+headline implicit workload (2047^2 interior, order 4, FP64 multigrid).
+
+  rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2507_18282_amd.counters_probe
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--wave-solves", type=int, default=1)
+    a = ap.parse_args(argv)
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Operator, fill_uniform
+    torch.cuda.set_device(0)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    P = synthetic.config_square_order4_implicit()
+    op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=P.n_p,
+                  adjust_omega=P.adjust_omega, precision=P.precision, mg_tol=P.mg_tol)
+    v = fill_uniform(op.n_active, P.seed)
+    for _ in range(a.wave_solves):
+        v = op.apply_filter(v)
+    torch.cuda.synchronize()
+    print("counters probe done", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

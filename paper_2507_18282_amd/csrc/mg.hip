@@ -44,71 +44,6 @@ hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, cons
 }
 
 // --------------------------------------------------------------------------
-// Residual fused with full-weighting restriction: one thread per coarse point
-// I, fine centre 2I+1, weights prod_d w(o_d) with w(0) = 1/2, w(+-1) = 1/4.
-// --------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM>
-__device__ __forceinline__ T fine_residual(const T* __restrict__ x, const T* __restrict__ b, T bscale, const Geo& g,
-                                           T a, int i, int j, int k) {
-    const int64_t c = lin(g, i, j, k);
-    const T xc = x[c];
-    return bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM>(x, c, i, j, k, g, xc));
-}
-
-template <typename T, int ORDER, int DIM>
-__global__ __launch_bounds__(256) void k_residual_restrict(const T* __restrict__ x, const T* __restrict__ b,
-                                                           T bscale, Geo gf, T a, T* __restrict__ bc, Geo gc) {
-    int ic, jc, kc;
-    if (!tile_coords(gc, ic, jc, kc)) return;
-    const int fi = 2 * ic + 1, fj = 2 * jc + 1, fk = (DIM == 3) ? 2 * kc + 1 : 0;
-    T sum = T(0);
-    if (DIM == 2) {
-#pragma unroll
-        for (int oy = -1; oy <= 1; ++oy) {
-            T row = T(0);
-#pragma unroll
-            for (int ox = -1; ox <= 1; ++ox) {
-                const T w = ox == 0 ? T(0.5) : T(0.25);
-                row += w * fine_residual<T, ORDER, DIM>(x, b, bscale, gf, a, fi + ox, fj + oy, 0);
-            }
-            sum += (oy == 0 ? T(0.5) : T(0.25)) * row;
-        }
-    } else {
-#pragma unroll
-        for (int oz = -1; oz <= 1; ++oz) {
-            T plane = T(0);
-#pragma unroll
-            for (int oy = -1; oy <= 1; ++oy) {
-                T row = T(0);
-#pragma unroll
-                for (int ox = -1; ox <= 1; ++ox) {
-                    const T w = ox == 0 ? T(0.5) : T(0.25);
-                    row += w * fine_residual<T, ORDER, DIM>(x, b, bscale, gf, a, fi + ox, fj + oy, fk + oz);
-                }
-                plane += (oy == 0 ? T(0.5) : T(0.25)) * row;
-            }
-            sum += (oz == 0 ? T(0.5) : T(0.25)) * plane;
-        }
-    }
-    bc[lin(gc, ic, jc, kc)] = sum;
-}
-
-template <typename T>
-hipError_t launch_residual_restrict(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
-                                    const Geo& gc, hipStream_t s) {
-    dim3 grid = tile_grid(gc), block(kTileX, kTileY, 1);
-    const T bs = (T)bscale, aa = (T)a;
-    if (gf.dim == 2) {
-        if (order == 2) k_residual_restrict<T, 2, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-        else k_residual_restrict<T, 4, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-    } else {
-        if (order == 2) k_residual_restrict<T, 2, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-        else k_residual_restrict<T, 4, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-    }
-    return hipGetLastError();
-}
-
-// --------------------------------------------------------------------------
 // Prolongation (multilinear) fused with the correction x += P xc.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void interp_1d(int f, int nc, int& c0, int& c1, float& w0, float& w1) {
@@ -205,8 +140,6 @@ hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo
 #define EW_INST_MG(T)                                                                                          \
     template hipError_t launch_rb_half<T>(const T*, T*, const T*, double, const Geo&, int, double, int,         \
                                           hipStream_t);                                                        \
-    template hipError_t launch_residual_restrict<T>(const T*, const T*, double, const Geo&, int, double, T*,    \
-                                                    const Geo&, hipStream_t);                                  \
     template hipError_t launch_prolong_correct<T>(T*, const T*, const Geo&, const Geo&, hipStream_t);
 EW_INST_MG(double)
 EW_INST_MG(float)

@@ -1,0 +1,48 @@
+// Declarations of the LDS-tiled multigrid kernels (mg_tile.hip).
+#pragma once
+
+#include "ew_internal.h"
+
+namespace ew {
+
+// Levels handled by the single-workgroup coarse kernel.  Level arrays live in
+// dynamic LDS at the given element offsets, each padded by two zero cells per
+// side.  The first such level must have nx, ny <= 64 in 2D, or nx, ny, nz <= 16
+// in 3D (the kernel's fixed thread-to-column map).
+constexpr int kMaxCoarseLevels = 16;
+constexpr int kCoarseMax2D = 64;
+constexpr int kCoarseMax3D = 16;
+constexpr size_t kCoarseMaxLdsBytes = 160 * 1024;
+struct CoarseLevels {
+    int nlev;
+    int lds_elems;
+    int off_r;  // scratch residual array, sized for level 0
+    int off_x[kMaxCoarseLevels];
+    int off_b[kMaxCoarseLevels];
+    Geo g[kMaxCoarseLevels];
+};
+
+// One full red-black sweep xout = RB(xin (+ P xc if prolong), bscale b), tile by tile.
+// xin is not read when zero_in.  xin and xout must not alias.
+// ev0/ev1 (may be null) are recorded at the start and end of the sweep's dispatch.
+template <typename T>
+hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g,
+                             const Geo& gc, int order, double a, bool zero_in, bool prolong, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// bc = full-weighting restriction of the residual bscale b - M x.
+template <typename T>
+hipError_t launch_restrict_tile(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
+                                const Geo& gc, hipStream_t s);
+// V-cycle over the levels of c in one workgroup; x_in may be null (zero start).
+template <typename T>
+hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_out, const CoarseLevels& c, int order,
+                                double a, int nu1, int nu2, int coarse_sweeps, hipStream_t s);
+template <typename T>
+hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes);
+// 2D grids (sweep2d.hip).
+template <typename T>
+hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,
+                          int order, double a, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1);
+
+}  // namespace ew

@@ -1,0 +1,590 @@
+// Multigrid kernels tiled through LDS for the implicit step matrix
+// M = I - a L_h (a = dt^2/2):
+//
+//  * k_sweep_tile    one full red-black Gauss-Seidel sweep (red half-sweep,
+//                    then black) in a single pass: read x and b once, write x
+//                    once.  Optionally the prolongation + correction of the
+//                    coarse-grid solution is applied while the tile is loaded,
+//                    and optionally the incoming iterate is known to be zero.
+//  * k_restrict_tile residual at the fine points of a tile computed once in
+//                    LDS, then full-weighting restriction.
+//  * k_coarse_vcycle every level from a given one down to the coarsest, in
+//                    one workgroup, with all level arrays resident in LDS.
+//
+// The arithmetic of each red or black half-sweep is the same as the simple
+// kernels in mg.hip: x_i + (b - M x)_i / M_ii with every neighbour taken from
+// the values before that half-sweep.
+#include <hip/hip_ext.h>
+
+#include "mg_tile.h"
+#include "stencil_dev.h"
+
+#define EW_RET_ON_ERR(x)                   \
+    do {                                   \
+        hipError_t e_ = (x);               \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+
+namespace ew {
+
+// ---------------------------------------------------------------------------
+// Tile shapes
+// ---------------------------------------------------------------------------
+template <int DIM> struct SweepTile;
+template <> struct SweepTile<2> { static constexpr int TX = 64, TY = 32, TZ = 1; };
+template <> struct SweepTile<3> { static constexpr int TX = 32, TY = 8, TZ = 8; };
+template <int DIM> struct RestrictTile;
+template <> struct RestrictTile<2> { static constexpr int CX = 32, CY = 16, CZ = 1; };
+template <> struct RestrictTile<3> { static constexpr int CX = 16, CY = 4, CZ = 4; };
+
+constexpr int kTileThreads = 256;
+
+__device__ __forceinline__ void interp_axis(int f, int nc, int& c0, int& c1, double& w0, double& w1) {
+    if (f & 1) {
+        c0 = (f - 1) >> 1; c1 = -1; w0 = 1.0; w1 = 0.0;
+    } else {
+        c0 = (f >> 1) - 1; c1 = f >> 1; w0 = 0.5; w1 = 0.5;
+        if (c1 >= nc) c1 = -1;
+    }
+}
+
+// Multilinear interpolation of the coarse grid function at fine point (i,j,k).
+template <typename T, int DIM>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ xc, const Geo& gc, int i, int j, int k) {
+    int xi[2], yj[2], zk[2];
+    double wx[2], wy[2], wz[2];
+    interp_axis(i, gc.nx, xi[0], xi[1], wx[0], wx[1]);
+    interp_axis(j, gc.ny, yj[0], yj[1], wy[0], wy[1]);
+    if (DIM == 3) interp_axis(k, gc.nz, zk[0], zk[1], wz[0], wz[1]);
+    else { zk[0] = 0; zk[1] = -1; wz[0] = 1.0; wz[1] = 0.0; }
+    T v = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (zk[c] < 0) continue;
+        T plane = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+            if (yj[bb] < 0) continue;
+            T row = T(0);
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa) {
+                if (xi[aa] < 0) continue;
+                row += (T)wx[aa] * xc[lin(gc, xi[aa], yj[bb], zk[c])];
+            }
+            plane += (T)wy[bb] * row;
+        }
+        v += (T)wz[c] * plane;
+    }
+    return v;
+}
+
+// Second difference along one axis of an LDS tile (un-scaled), where cells
+// outside the domain hold 0 (the wall); the order-4 ghost beyond the wall is
+// the odd reflection of the point itself when it is the first or last point.
+template <typename T, int ORDER>
+__device__ __forceinline__ T d2_lds(const T* X, int p, int stride, int gi, int n, T uc) {
+    const T l1 = X[p - stride], r1 = X[p + stride];
+    if (ORDER == 2) return l1 + r1 - T(2) * uc;
+    const T l2 = (gi == 0) ? -uc : X[p - 2 * stride];
+    const T r2 = (gi == n - 1) ? -uc : X[p + 2 * stride];
+    return T(16) * (l1 + r1) - (l2 + r2) - T(30) * uc;
+}
+
+template <typename T, int ORDER, int DIM>
+__device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, int gj, int gk, const Geo& g, T uc) {
+    T s = d2_lds<T, ORDER>(X, p, 1, gi, g.nx, uc) * axis_coef<T, ORDER>(g.ihx2);
+    s += d2_lds<T, ORDER>(X, p, sy, gj, g.ny, uc) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3) s += d2_lds<T, ORDER>(X, p, sz, gk, g.nz, uc) * axis_coef<T, ORDER>(g.ihz2);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// One full red-black sweep per tile.
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER, int DIM, bool ZERO_IN, bool PROLONG>
+__global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict__ xin, const T* __restrict__ xc,
+                                                             const T* __restrict__ b, T bscale, T* __restrict__ xout,
+                                                             Geo g, Geo gc, T a) {
+    constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
+    constexpr int R = ORDER / 2;        // stencil radius
+    constexpr int H = R + 1;            // red is relaxed on the tile plus one layer
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H, LZ = (DIM == 3) ? TZ + 2 * H : 1;
+    constexpr int BX = TX + 2, BY = TY + 2, BZ = (DIM == 3) ? TZ + 2 : 1;
+    constexpr int NRED = BX * BY * BZ;
+    constexpr int RED_ITERS = (NRED + kTileThreads - 1) / kTileThreads;
+    __shared__ T X[LX * LY * LZ];
+    __shared__ T B[BX * BY * BZ];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = (DIM == 3) ? blockIdx.z * TZ : 0;
+
+    // load x (tile + H), zero outside the domain, prolongation folded in
+    for (int q = tid; q < LX * LY * LZ; q += kTileThreads) {
+        const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
+        const int gi = x0 - H + lx, gj = y0 - H + ly, gk = (DIM == 3) ? z0 - H + lz : 0;
+        T v = T(0);
+        if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) {
+            if (!ZERO_IN) v = xin[lin(g, gi, gj, gk)];
+            if (PROLONG) v += prolong_at<T, DIM>(xc, gc, gi, gj, gk);
+        }
+        X[q] = v;
+    }
+    // load b (tile + 1)
+    for (int q = tid; q < BX * BY * BZ; q += kTileThreads) {
+        const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
+        const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
+        T v = T(0);
+        if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) v = bscale * b[lin(g, gi, gj, gk)];
+        B[q] = v;
+    }
+    __syncthreads();
+
+    // red half-sweep on tile + 1 layer: new values to registers first (order 4
+    // couples red points to red points), then into LDS
+    T rv[RED_ITERS];
+    int rp[RED_ITERS];
+#pragma unroll
+    for (int t = 0; t < RED_ITERS; ++t) {
+        rp[t] = -1;
+        const int q = tid + t * kTileThreads;
+        if (q >= NRED) continue;
+        const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
+        const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
+        if (gi < 0 || gi >= g.nx || gj < 0 || gj >= g.ny || gk < 0 || gk >= g.nz) continue;
+        if (((gi + gj + gk) & 1) != 0) continue;
+        const int p = (bx + H - 1) + LX * ((by + H - 1) + LY * ((DIM == 3) ? (bz + H - 1) : 0));
+        const T uc = X[p];
+        const T lap = lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
+        const T r = B[q] - (uc - a * lap);
+        rv[t] = uc + r / mdiag_at<T, ORDER, DIM>(gi, gj, gk, g, a);
+        rp[t] = p;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RED_ITERS; ++t)
+        if (rp[t] >= 0) X[rp[t]] = rv[t];
+    __syncthreads();
+
+    // black half-sweep on the tile, written straight to global memory
+    for (int q = tid; q < TX * TY * TZ; q += kTileThreads) {
+        const int tx = q % TX, ty = (q / TX) % TY, tz = q / (TX * TY);
+        const int gi = x0 + tx, gj = y0 + ty, gk = z0 + tz;
+        if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
+        const int p = (tx + H) + LX * ((ty + H) + LY * ((DIM == 3) ? (tz + H) : 0));
+        const T uc = X[p];
+        T out = uc;
+        if (((gi + gj + gk) & 1) == 1) {
+            const T lap = lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
+            const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
+            const T r = B[qb] - (uc - a * lap);
+            out = uc + r / mdiag_at<T, ORDER, DIM>(gi, gj, gk, g, a);
+        }
+        xout[lin(g, gi, gj, gk)] = out;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residual + full-weighting restriction per coarse tile.
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER, int DIM, int CY>
+__global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restrict__ x, const T* __restrict__ b,
+                                                                T bscale, Geo gf, T a, T* __restrict__ bc, Geo gc) {
+    constexpr int CX = RestrictTile<DIM>::CX, CZ = RestrictTile<DIM>::CZ;
+    constexpr int R = ORDER / 2;
+    constexpr int FX = 2 * CX + 1, FY = 2 * CY + 1, FZ = (DIM == 3) ? 2 * CZ + 1 : 1;
+    constexpr int LX = FX + 2 * R, LY = FY + 2 * R, LZ = (DIM == 3) ? FZ + 2 * R : 1;
+    __shared__ T X[LX * LY * LZ];
+    __shared__ T Rf[FX * FY * FZ];
+    const int tid = threadIdx.x;
+    const int cx0 = blockIdx.x * CX, cy0 = blockIdx.y * CY, cz0 = (DIM == 3) ? blockIdx.z * CZ : 0;
+    const int fx0 = 2 * cx0, fy0 = 2 * cy0, fz0 = (DIM == 3) ? 2 * cz0 : 0;  // first fine point of the region
+    for (int q = tid; q < LX * LY * LZ; q += kTileThreads) {
+        const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
+        const int gi = fx0 - R + lx, gj = fy0 - R + ly, gk = (DIM == 3) ? fz0 - R + lz : 0;
+        T v = T(0);
+        if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) v = x[lin(gf, gi, gj, gk)];
+        X[q] = v;
+    }
+    __syncthreads();
+    for (int q = tid; q < FX * FY * FZ; q += kTileThreads) {
+        const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
+        const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
+        T r = T(0);
+        if (gi < gf.nx && gj < gf.ny && gk < gf.nz) {
+            const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
+            const T uc = X[p];
+            r = bscale * b[lin(gf, gi, gj, gk)] - (uc - a * lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
+        }
+        Rf[q] = r;
+    }
+    __syncthreads();
+    for (int q = tid; q < CX * CY * CZ; q += kTileThreads) {
+        const int cx = q % CX, cy = (q / CX) % CY, cz = q / (CX * CY);
+        const int ic = cx0 + cx, jc = cy0 + cy, kc = cz0 + cz;
+        if (ic >= gc.nx || jc >= gc.ny || kc >= gc.nz) continue;
+        const int fx = 2 * cx + 1, fy = 2 * cy + 1, fz = (DIM == 3) ? 2 * cz + 1 : 0;
+        T sum = T(0);
+        if (DIM == 2) {
+#pragma unroll
+            for (int oy = -1; oy <= 1; ++oy) {
+                T row = T(0);
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox)
+                    row += (ox == 0 ? T(0.5) : T(0.25)) * Rf[(fx + ox) + FX * (fy + oy)];
+                sum += (oy == 0 ? T(0.5) : T(0.25)) * row;
+            }
+        } else {
+#pragma unroll
+            for (int oz = -1; oz <= 1; ++oz) {
+                T plane = T(0);
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy) {
+                    T row = T(0);
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox)
+                        row += (ox == 0 ? T(0.5) : T(0.25)) * Rf[(fx + ox) + FX * ((fy + oy) + FY * (fz + oz))];
+                    plane += (oy == 0 ? T(0.5) : T(0.25)) * row;
+                }
+                sum += (oz == 0 ? T(0.5) : T(0.25)) * plane;
+            }
+        }
+        bc[lin(gc, ic, jc, kc)] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse levels in one workgroup: V(nu1, nu2) from level 0 of `c` (whose
+// right-hand side is read from global memory) down to the coarsest, all level
+// arrays in dynamic LDS.  Each level is stored with a zero halo of two cells
+// (the wall, and the cell beyond it that only the order-4 ghost would use, which
+// is handled explicitly), so stencils need no bounds tests.  Threads own fixed
+// columns (2D: i = tid % 64, rows j = tid / 64 + 16 t; 3D: i = tid % 16,
+// j = tid / 16 % 16, planes k = tid / 256 + 4 t), so no index divisions occur.
+// The result on level 0 is written to x_out.
+// ---------------------------------------------------------------------------
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseIters = 4;  // rows (2D) or planes (3D) per thread and level
+
+template <int DIM>
+struct CoarseMap {
+    // thread -> (i, j, k) of iteration t; false when outside the level
+    static __device__ __forceinline__ bool at(const Geo& g, int t, int& i, int& j, int& k) {
+        const int tid = threadIdx.x;
+        if (DIM == 2) {
+            i = tid & 63;
+            j = (tid >> 6) + 16 * t;
+            k = 0;
+        } else {
+            i = tid & 15;
+            j = (tid >> 4) & 15;
+            k = (tid >> 8) + 4 * t;
+        }
+        return i < g.nx && j < g.ny && k < g.nz;
+    }
+};
+
+__device__ __forceinline__ int cpad_idx(const Geo& g, int i, int j, int k) {
+    const int px = g.nx + 4, py = g.ny + 4;
+    return ((k + (g.dim == 3 ? 2 : 0)) * py + (j + 2)) * px + (i + 2);
+}
+
+template <typename T, int ORDER, int DIM>
+__device__ __forceinline__ T lap_pad(const T* X, const Geo& g, int p, int i, int j, int k, T uc) {
+    const int sy = g.nx + 4, sz = (g.nx + 4) * (g.ny + 4);
+    T s = d2_lds<T, ORDER>(X, p, 1, i, g.nx, uc) * axis_coef<T, ORDER>(g.ihx2);
+    s += d2_lds<T, ORDER>(X, p, sy, j, g.ny, uc) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3) s += d2_lds<T, ORDER>(X, p, sz, k, g.nz, uc) * axis_coef<T, ORDER>(g.ihz2);
+    return s;
+}
+
+// Points of one colour: every lane owns one (2D: i = 2 (tid % 32) + parity,
+// j = tid / 32 + 32 t; 3D: i = 2 (tid % 8) + parity, j = tid / 8 % 16,
+// k = tid / 128 + 8 t), so two passes cover a 64 x 64 or 16^3 level.
+constexpr int kCoarseColourIters = 2;
+template <int DIM>
+__device__ __forceinline__ bool colour_point(const Geo& g, int t, int colour, int& i, int& j, int& k) {
+    const int tid = threadIdx.x;
+    if (DIM == 2) {
+        j = (tid >> 5) + 32 * t;
+        k = 0;
+        i = 2 * (tid & 31) + ((j + colour) & 1);
+    } else {
+        j = (tid >> 3) & 15;
+        k = (tid >> 7) + 8 * t;
+        i = 2 * (tid & 7) + ((j + k + colour) & 1);
+    }
+    return i < g.nx && j < g.ny && k < g.nz;
+}
+
+// Reciprocal of the diagonal of M at points whose stencil does not reach a ghost.
+template <typename T, int ORDER, int DIM>
+__device__ __forceinline__ T interior_inv_diag(const Geo& g, T a) {
+    const T c0 = ORDER == 2 ? T(2) : T(30.0 / 12.0);
+    T s = (T)g.ihx2 + (T)g.ihy2;
+    if (DIM == 3) s += (T)g.ihz2;
+    return T(1) / (T(1) + a * c0 * s);
+}
+
+template <typename T, int ORDER, int DIM>
+__device__ void pad_half_sweep(T* x, const T* b, const Geo& g, T a, int colour) {
+    const T inv_diag = interior_inv_diag<T, ORDER, DIM>(g, a);
+    T nv[kCoarseColourIters];
+    int np[kCoarseColourIters];
+#pragma unroll
+    for (int t = 0; t < kCoarseColourIters; ++t) {
+        np[t] = -1;
+        int i, j, k;
+        if (!colour_point<DIM>(g, t, colour, i, j, k)) continue;
+        const int p = cpad_idx(g, i, j, k);
+        const T xc = x[p];
+        const T lap = lap_pad<T, ORDER, DIM>(x, g, p, i, j, k, xc);
+        const T r = b[p] - (xc - a * lap);
+        const bool edge = ORDER == 4 && (i == 0 || i == g.nx - 1 || j == 0 || j == g.ny - 1 ||
+                                         (DIM == 3 && (k == 0 || k == g.nz - 1)));
+        nv[t] = edge ? xc + r / mdiag_at<T, ORDER, DIM>(i, j, k, g, a) : xc + r * inv_diag;
+        np[t] = p;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kCoarseColourIters; ++t)
+        if (np[t] >= 0) x[np[t]] = nv[t];
+    __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void pad_zero(T* x, const Geo& g) {
+    const int tot = (g.nx + 4) * (g.ny + 4) * (DIM == 3 ? g.nz + 4 : 1);
+    for (int q = threadIdx.x; q < tot; q += kCoarseThreads) x[q] = T(0);
+}
+
+// Residual b - M x of a level into the scratch array r (same padded layout),
+// then full-weighting restriction of r into bc.
+template <typename T, int ORDER, int DIM>
+__device__ void pad_restrict(const T* x, const T* b, const Geo& gf, T a, T* bc, const Geo& gc, T* r) {
+#pragma unroll
+    for (int t = 0; t < kCoarseIters; ++t) {
+        int i, j, k;
+        if (!CoarseMap<DIM>::at(gf, t, i, j, k)) continue;
+        const int p = cpad_idx(gf, i, j, k);
+        const T xf = x[p];
+        r[p] = b[p] - (xf - a * lap_pad<T, ORDER, DIM>(x, gf, p, i, j, k, xf));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kCoarseIters; ++t) {
+        int ic, jc, kc;
+        if (!CoarseMap<DIM>::at(gc, t, ic, jc, kc)) continue;
+        const int fi = 2 * ic + 1, fj = 2 * jc + 1, fk = (DIM == 3) ? 2 * kc + 1 : 0;
+        T sum = T(0);
+        const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
+        for (int oz = zlo; oz <= zhi; ++oz) {
+            T plane = T(0);
+            for (int oy = -1; oy <= 1; ++oy) {
+                T row = T(0);
+                for (int ox = -1; ox <= 1; ++ox)
+                    row += (ox == 0 ? T(0.5) : T(0.25)) * r[cpad_idx(gf, fi + ox, fj + oy, fk + oz)];
+                plane += (oy == 0 ? T(0.5) : T(0.25)) * row;
+            }
+            sum += (DIM == 3) ? (oz == 0 ? T(0.5) : T(0.25)) * plane : plane;
+        }
+        bc[cpad_idx(gc, ic, jc, kc)] = sum;
+    }
+    __syncthreads();
+}
+
+// x_f += P x_c with the zero halo standing in for the walls.
+template <typename T, int DIM>
+__device__ void pad_prolong(T* xf, const Geo& gf, const T* xc, const Geo& gc) {
+#pragma unroll
+    for (int t = 0; t < kCoarseIters; ++t) {
+        int i, j, k;
+        if (!CoarseMap<DIM>::at(gf, t, i, j, k)) continue;
+        int ci[2], cj[2], ck[2];
+        T wi[2], wj[2], wk[2];
+        ci[0] = (i - 1) >> 1; ci[1] = i >> 1; wi[0] = (i & 1) ? T(1) : T(0.5); wi[1] = (i & 1) ? T(0) : T(0.5);
+        if (i & 1) ci[1] = ci[0];
+        cj[0] = (j - 1) >> 1; cj[1] = j >> 1; wj[0] = (j & 1) ? T(1) : T(0.5); wj[1] = (j & 1) ? T(0) : T(0.5);
+        if (j & 1) cj[1] = cj[0];
+        if (DIM == 3) {
+            ck[0] = (k - 1) >> 1; ck[1] = k >> 1; wk[0] = (k & 1) ? T(1) : T(0.5); wk[1] = (k & 1) ? T(0) : T(0.5);
+            if (k & 1) ck[1] = ck[0];
+        } else {
+            ck[0] = ck[1] = 0; wk[0] = T(1); wk[1] = T(0);
+        }
+        T v = T(0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T plane = T(0);
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+                T row = T(0);
+#pragma unroll
+                for (int aa = 0; aa < 2; ++aa) row += wi[aa] * xc[cpad_idx(gc, ci[aa], cj[bb], ck[c])];
+                plane += wj[bb] * row;
+            }
+            v += wk[c] * plane;
+        }
+        xf[cpad_idx(gf, i, j, k)] += v;
+    }
+    __syncthreads();
+}
+
+template <typename T, int ORDER, int DIM>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __restrict__ b_in, const T* __restrict__ x_in,
+                                                                  T* __restrict__ x_out, CoarseLevels c, T a,
+                                                                  int nu1, int nu2, int coarse_sweeps, T bscale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* smem = reinterpret_cast<T*>(smem_raw);
+    const int L = c.nlev;
+    for (int l = 0; l < L; ++l) {
+        pad_zero<T, DIM>(smem + c.off_x[l], c.g[l]);
+        pad_zero<T, DIM>(smem + c.off_b[l], c.g[l]);
+    }
+    __syncthreads();
+    {
+        const Geo& g0 = c.g[0];
+        T* x0 = smem + c.off_x[0];
+        T* b0 = smem + c.off_b[0];
+#pragma unroll
+        for (int t = 0; t < kCoarseIters; ++t) {
+            int i, j, k;
+            if (!CoarseMap<DIM>::at(g0, t, i, j, k)) continue;
+            const int64_t gq = lin(g0, i, j, k);
+            const int p = cpad_idx(g0, i, j, k);
+            b0[p] = bscale * b_in[gq];
+            if (x_in) x0[p] = x_in[gq];
+        }
+        __syncthreads();
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        T* x = smem + c.off_x[l];
+        T* b = smem + c.off_b[l];
+        for (int s = 0; s < nu1; ++s) {
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 1);
+        }
+        pad_restrict<T, ORDER, DIM>(x, b, c.g[l], a, smem + c.off_b[l + 1], c.g[l + 1], smem + c.off_r);
+    }
+    {
+        const int l = L - 1;
+        T* x = smem + c.off_x[l];
+        T* b = smem + c.off_b[l];
+        const int sweeps = c.g[l].size() == 1 ? 1 : coarse_sweeps;
+        for (int s = 0; s < sweeps; ++s) {
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 1);
+        }
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        T* x = smem + c.off_x[l];
+        T* b = smem + c.off_b[l];
+        pad_prolong<T, DIM>(x, c.g[l], smem + c.off_x[l + 1], c.g[l + 1]);
+        for (int s = 0; s < nu2; ++s) {
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 1);
+        }
+    }
+    {
+        const Geo& g0 = c.g[0];
+        const T* x0 = smem + c.off_x[0];
+#pragma unroll
+        for (int t = 0; t < kCoarseIters; ++t) {
+            int i, j, k;
+            if (!CoarseMap<DIM>::at(g0, t, i, j, k)) continue;
+            x_out[lin(g0, i, j, k)] = x0[cpad_idx(g0, i, j, k)];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER, int DIM>
+static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
+                                 T a, bool zero_in, bool prolong, hipStream_t s) {
+    constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
+    dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, DIM == 3 ? (g.nz + TZ - 1) / TZ : 1);
+    if (zero_in && prolong) k_sweep_tile<T, ORDER, DIM, true, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
+    else if (zero_in) k_sweep_tile<T, ORDER, DIM, true, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
+    else if (prolong) k_sweep_tile<T, ORDER, DIM, false, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
+    else k_sweep_tile<T, ORDER, DIM, false, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g,
+                             const Geo& gc, int order, double a, bool zero_in, bool prolong, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1) {
+    const T bs = (T)bscale, aa = (T)a;
+    if (g.dim == 2) return launch_sweep2d<T>(xin, xc, b, bscale, xout, g, gc, order, a, zero_in, prolong, s, ev0, ev1);
+    if (ev0) EW_RET_ON_ERR(hipEventRecord(ev0, s));
+    hipError_t e = order == 2 ? sweep_dispatch<T, 2, 3>(xin, xc, b, bs, xout, g, gc, aa, zero_in, prolong, s)
+                              : sweep_dispatch<T, 4, 3>(xin, xc, b, bs, xout, g, gc, aa, zero_in, prolong, s);
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    return e;
+}
+
+template <typename T, int ORDER, int DIM>
+static hipError_t restrict_dispatch(const T* x, const T* b, T bs, const Geo& gf, T a, T* bc, const Geo& gc,
+                                    hipStream_t s) {
+    constexpr int CX = RestrictTile<DIM>::CX, CY = RestrictTile<DIM>::CY, CZ = RestrictTile<DIM>::CZ;
+    // short tiles (less serial work per block) when tall ones would not fill the chip
+    const int64_t tall = (int64_t)((gc.nx + CX - 1) / CX) * ((gc.ny + CY - 1) / CY) * (DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
+    if (DIM == 2 && tall < 1024) {
+        dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + 3) / 4, 1);
+        k_restrict_tile<T, ORDER, DIM, 4><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+    } else {
+        dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + CY - 1) / CY, DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
+        k_restrict_tile<T, ORDER, DIM, CY><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict_tile(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
+                                const Geo& gc, hipStream_t s) {
+    const T bs = (T)bscale, aa = (T)a;
+    if (gf.dim == 2) {
+        if (order == 2) return restrict_dispatch<T, 2, 2>(x, b, bs, gf, aa, bc, gc, s);
+        return restrict_dispatch<T, 4, 2>(x, b, bs, gf, aa, bc, gc, s);
+    }
+    if (order == 2) return restrict_dispatch<T, 2, 3>(x, b, bs, gf, aa, bc, gc, s);
+    return restrict_dispatch<T, 4, 3>(x, b, bs, gf, aa, bc, gc, s);
+}
+
+template <typename T>
+hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_out, const CoarseLevels& c, int order,
+                                double a, int nu1, int nu2, int coarse_sweeps, hipStream_t s) {
+    const size_t lds = (size_t)c.lds_elems * sizeof(T);
+    const T aa = (T)a, bs = (T)bscale;
+    if (c.g[0].dim == 2) {
+        if (order == 2) k_coarse_vcycle<T, 2, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
+        else k_coarse_vcycle<T, 4, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
+    } else {
+        if (order == 2) k_coarse_vcycle<T, 2, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
+        else k_coarse_vcycle<T, 4, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
+    }
+    return hipGetLastError();
+}
+
+// Dynamic LDS above 64 KB must be enabled per kernel.
+template <typename T>
+hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes) {
+    const void* f = nullptr;
+    if (dim == 2) f = order == 2 ? (const void*)k_coarse_vcycle<T, 2, 2> : (const void*)k_coarse_vcycle<T, 4, 2>;
+    else f = order == 2 ? (const void*)k_coarse_vcycle<T, 2, 3> : (const void*)k_coarse_vcycle<T, 4, 3>;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+#define EW_INST_TILE(T)                                                                                          \
+    template hipError_t launch_sweep_tile<T>(const T*, const T*, const T*, double, T*, const Geo&, const Geo&,    \
+                                             int, double, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);       \
+    template hipError_t launch_restrict_tile<T>(const T*, const T*, double, const Geo&, int, double, T*,         \
+                                                const Geo&, hipStream_t);                                         \
+    template hipError_t launch_coarse_vcycle<T>(const T*, double, const T*, T*, const CoarseLevels&, int, double, \
+                                                int, int, int, hipStream_t);                                      \
+    template hipError_t prepare_coarse_vcycle<T>(int, int, size_t);
+EW_INST_TILE(double)
+EW_INST_TILE(float)
+#undef EW_INST_TILE
+
+}  // namespace ew

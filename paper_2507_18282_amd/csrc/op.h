@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "ew_internal.h"
+#include "mg_tile.h"
 
 namespace ew {
 
@@ -35,8 +36,11 @@ struct Op;
 struct ProfScope {
     Op* op;
     bool on;
-    ProfScope(Op* o, int kclass, int level, double bytes);
+    bool external;  // the launch records the events itself (start_event/stop_event)
+    ProfScope(Op* o, int kclass, int level, double bytes, bool external_events = false);
     ~ProfScope();
+    hipEvent_t start_event() const;
+    hipEvent_t stop_event() const;
 };
 
 struct Op {
@@ -65,6 +69,9 @@ struct Op {
     double* partial_dev = nullptr;
     double* partial_host = nullptr;
     std::vector<Level> levels;
+    int coarse_level = 0;      // first level run by the single-workgroup kernel
+    CoarseLevels coarse{};
+    int last_cycles = 0;       // V-cycles of the previous implicit solve
     std::vector<void*> allocations;
     Cnn* cnn = nullptr;
     ew_op_stats stats{};
@@ -77,10 +84,11 @@ struct Op {
 
     // multigrid (wave.hip)
     template <typename T>
-    ew_status vcycle(int level, T* x, T* xtmp, const T* b, double bscale);
+    ew_status vcycle(int level, T* cur, T* other, const T* b, double bscale, bool zero, T** result);
     template <typename T>
-    ew_status smooth(int level, T* x, T* xtmp, const T* b, double bscale, int sweeps);
-    ew_status mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);
+    ew_status sweep(int level, T*& cur, T*& other, const T* b, double bscale, bool zero, const T* xc);
+    ew_status mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel,
+                         bool speculate = false);
     ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);
     ew_status implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess);
     ew_status apply_filter(const double* v, double* out);

@@ -72,7 +72,8 @@ Op::~Op() {
     for (hipEvent_t e : prof.pool) hipEventDestroy(e);
 }
 
-ProfScope::ProfScope(Op* o, int kclass, int level, double bytes) : op(o), on(false) {
+ProfScope::ProfScope(Op* o, int kclass, int level, double bytes, bool external_events)
+    : op(o), on(false), external(external_events) {
     Profiler& p = op->prof;
     if (!p.wants(kclass, level)) return;
     while (p.pool.size() < p.used + 2) {
@@ -80,16 +81,19 @@ ProfScope::ProfScope(Op* o, int kclass, int level, double bytes) : op(o), on(fal
         if (hipEventCreate(&e) != hipSuccess) return;
         p.pool.push_back(e);
     }
-    if (hipEventRecord(p.pool[p.used], op->stream) != hipSuccess) return;
+    if (!external && hipEventRecord(p.pool[p.used], op->stream) != hipSuccess) return;
     on = true;
     p.launches++;
     p.bytes += bytes;
 }
 
+hipEvent_t ProfScope::start_event() const { return on ? op->prof.pool[op->prof.used] : nullptr; }
+hipEvent_t ProfScope::stop_event() const { return on ? op->prof.pool[op->prof.used + 1] : nullptr; }
+
 ProfScope::~ProfScope() {
     if (!on) return;
     Profiler& p = op->prof;
-    hipEventRecord(p.pool[p.used + 1], op->stream);
+    if (!external) hipEventRecord(p.pool[p.used + 1], op->stream);
     p.used += 2;
 }
 
@@ -144,6 +148,7 @@ static ew_status validate(const ew_grid_desc* g, const ew_op_desc* d) {
         if (d->mg_max_cycles < 1 || d->mg_max_cycles > 10000) return fail(EW_ERR_INVALID_ARG, "mg_max_cycles must be in [1, 10000]");
         if (d->mg_coarse_sweeps < 1 || d->mg_coarse_sweeps > 10000)
             return fail(EW_ERR_INVALID_ARG, "mg_coarse_sweeps must be in [1, 10000]");
+        if (d->mg_coarse_points < 0) return fail(EW_ERR_INVALID_ARG, "mg_coarse_points must be >= 0");
         if (d->predictor != EW_PRED_ZERO && d->predictor != EW_PRED_SCALED && d->predictor != EW_PRED_CNN)
             return fail(EW_ERR_INVALID_ARG, "unknown predictor");
         if (d->predictor == EW_PRED_CNN && (g->dim != 2))
@@ -180,6 +185,46 @@ ew_status Op::build_hierarchy() {
             EW_TRY(alloc(&L.x[0], m * es));
             EW_TRY(alloc(&L.b, m * es));
         }
+    }
+    // Levels from coarse_level down run in one workgroup with x and b of every
+    // such level resident in LDS.
+    const int nlev = (int)levels.size();
+    coarse_level = nlev;
+    const int64_t cap_pts = desc.mg_coarse_points > 0 ? desc.mg_coarse_points : (int64_t)1 << 40;
+    auto padded = [&](const Geo& gq) -> int64_t {
+        return (int64_t)(gq.nx + 4) * (gq.ny + 4) * (dim == 3 ? gq.nz + 4 : 1);
+    };
+    for (int l = nlev - 1; l >= 0; --l) {
+        const Geo& gl = levels[l].g;
+        const int64_t m = gl.size();
+        const int cap = dim == 2 ? kCoarseMax2D : kCoarseMax3D;
+        if (gl.nx > cap || gl.ny > cap || (dim == 3 && gl.nz > cap) || m > cap_pts) break;
+        if (nlev - l > kMaxCoarseLevels) break;
+        int64_t elems = (padded(gl) + 1) & ~(int64_t)1;  // residual scratch
+        for (int q = l; q < nlev; ++q) elems += (2 * padded(levels[q].g) + 1) & ~(int64_t)1;
+        if (elems * (int64_t)es > (int64_t)kCoarseMaxLdsBytes) break;
+        coarse_level = l;
+    }
+    if (coarse_level < nlev) {
+        coarse.nlev = nlev - coarse_level;
+        int off = 0;
+        for (int q = 0; q < coarse.nlev; ++q) {
+            const Geo& gq = levels[coarse_level + q].g;
+            coarse.g[q] = gq;
+            coarse.off_x[q] = off;
+            off += (int)padded(gq);
+            coarse.off_b[q] = off;
+            off += (int)padded(gq);
+            off = (off + 1) & ~1;  // keep 16-byte alignment for FP32 pairs
+        }
+        coarse.off_r = off;
+        off += (int)padded(coarse.g[0]);
+        off = (off + 1) & ~1;
+        coarse.lds_elems = off;
+        // The attribute is per kernel, not per operator: always allow the maximum.
+        hipError_t e = mixed ? prepare_coarse_vcycle<float>(dim, order, kCoarseMaxLdsBytes)
+                             : prepare_coarse_vcycle<double>(dim, order, kCoarseMaxLdsBytes);
+        if (e != hipSuccess) return fail(EW_ERR_HIP, std::string("coarse kernel LDS: ") + hipGetErrorString(e));
     }
     return EW_OK;
 }
@@ -267,7 +312,7 @@ extern "C" ew_status ew_op_apply_laplacian(ew_op op, const double* v_dev, double
 
 extern "C" ew_status ew_op_profile_begin(ew_op op, int kclass, int level) {
     if (!op) return fail(EW_ERR_INVALID_ARG, "null op");
-    if (kclass < EW_K_LEAPFROG || kclass > EW_K_COARSE) return fail(EW_ERR_INVALID_ARG, "unknown kernel class");
+    if (kclass < EW_K_LEAPFROG || kclass > EW_K_SMOOTH_ZERO) return fail(EW_ERR_INVALID_ARG, "unknown kernel class");
     op->prof.kclass = kclass;
     op->prof.level = level;
     op->prof.used = 0;

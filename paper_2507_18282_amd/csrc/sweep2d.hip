@@ -1,0 +1,195 @@
+// The finest-level smoother for 2D grids: one full red-black Gauss-Seidel
+// sweep of M = I - a L_h per pass over memory, tiled through LDS (the kernel
+// that dominates the implicit wave-solve on large 2D grids).
+#include <hip/hip_ext.h>
+
+#include "mg_tile.h"
+#include "stencil_dev.h"
+
+namespace ew {
+
+constexpr int kTileThreads = 256;
+
+// ---------------------------------------------------------------------------
+// 2D sweep, one tile of 64 x TY outputs per block of 256 threads.  x is staged
+// in LDS with a halo of H = R + 1, b with a halo of 1; with PROLONG the coarse
+// values under the tile are staged as well and interpolated from LDS.  During
+// each half-sweep every lane owns one point of the colour being relaxed
+// (a wavefront covers two rows of 32 same-colour points), so no lane idles on a
+// point of the other colour.  Interior points multiply by the reciprocal of
+// the constant interior diagonal; points whose diagonal carries an order-4
+// ghost divide.
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG>
+__global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restrict__ xin, const T* __restrict__ xc,
+                                                               const T* __restrict__ b, T bscale, T* __restrict__ xout,
+                                                               Geo g, Geo gc, T a, T inv_diag) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 1;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BX = TX + 2, BY = TY + 2;
+    constexpr int CXW = (LX + 5) / 2 + 1, CYW = (LY + 5) / 2 + 1;  // coarse cells under the x tile
+    __shared__ T X[LY * LX];
+    __shared__ T B[BY * BX];
+    __shared__ T XC[PROLONG ? CYW * CXW : 1];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    int cx0 = 0, cy0 = 0;
+    if (PROLONG) {
+        cx0 = (x0 - H - 1) >> 1;
+        cy0 = (y0 - H - 1) >> 1;
+        for (int q = tid; q < CYW * CXW; q += kTileThreads) {
+            const int cy = q / CXW, cxx = q - cy * CXW;
+            const int ic = cx0 + cxx, jc = cy0 + cy;
+            XC[q] = (ic >= 0 && ic < gc.nx && jc >= 0 && jc < gc.ny) ? xc[(int64_t)jc * gc.nx + ic] : T(0);
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < LY * LX; q += kTileThreads) {
+        const int ly = q / LX, lx = q - ly * LX;
+        const int gi = x0 - H + lx, gj = y0 - H + ly;
+        T v = T(0);
+        if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
+            if (!ZERO_IN) v = xin[(int64_t)gj * g.nx + gi];
+            if (PROLONG) {
+                // fine index odd -> coarse (f-1)/2; even -> mean of f/2-1 and f/2
+                const int ia = ((gi - 1) >> 1) - cx0, ib = (gi >> 1) - cx0;
+                const int ja = ((gj - 1) >> 1) - cy0, jb = (gj >> 1) - cy0;
+                const T wia = (gi & 1) ? T(1) : T(0.5), wib = (gi & 1) ? T(0) : T(0.5);
+                const T wja = (gj & 1) ? T(1) : T(0.5), wjb = (gj & 1) ? T(0) : T(0.5);
+                const T rowa = wia * XC[ja * CXW + ia] + wib * XC[ja * CXW + ib];
+                const T rowb = wia * XC[jb * CXW + ia] + wib * XC[jb * CXW + ib];
+                v += wja * rowa + wjb * rowb;
+            }
+        }
+        X[q] = v;
+    }
+    for (int q = tid; q < BY * BX; q += kTileThreads) {
+        const int by = q / BX, bx = q - by * BX;
+        const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
+        B[q] = (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) ? bscale * b[(int64_t)gj * g.nx + gi] : T(0);
+    }
+    __syncthreads();
+
+    const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
+    // relaxed value at LDS cell (lx, ly) = global (gi, gj)
+    auto relax = [&](int lx, int ly, int gi, int gj, T bval) -> T {
+        const int p = ly * LX + lx;
+        const T uc = X[p];
+        T dx, dy;
+        if (ORDER == 2) {
+            dx = X[p - 1] + X[p + 1] - T(2) * uc;
+            dy = X[p - LX] + X[p + LX] - T(2) * uc;
+        } else {
+            const T l2 = (gi == 0) ? -uc : X[p - 2];
+            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
+            dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
+        }
+        const T r = bval - (uc - a * (dx * cxc + dy * cyc));
+        const bool edge = ORDER == 4 && (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1);
+        return edge ? uc + r / mdiag_at<T, ORDER, 2>(gi, gj, 0, g, a) : uc + r * inv_diag;
+    };
+
+    const int rowsel = tid >> 5;  // 8 rows per pass, 32 lanes per row
+    const int m = tid & 31;
+    // red half-sweep on tile rows -1..TY, tile columns 0..63 (one red point per lane) ...
+    constexpr int NRP = (BY + 7) / 8;
+    T rv[NRP + 1];
+    int rp[NRP + 1];
+#pragma unroll
+    for (int t = 0; t < NRP; ++t) {
+        rp[t] = -1;
+        const int by = rowsel + 8 * t;
+        if (by >= BY) continue;
+        const int gj = y0 - 1 + by;
+        const int c = 2 * m + (gj & 1);  // tile column of the red point (x0 is even)
+        const int gi = x0 + c;
+        if (gj < 0 || gj >= g.ny || gi >= g.nx) continue;
+        rv[t] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
+        rp[t] = (by + H - 1) * LX + c + H;
+    }
+    // ... plus the red point of each row in tile column -1 or 64
+    rp[NRP] = -1;
+    if (tid < BY) {
+        const int by = tid, gj = y0 - 1 + by;
+        const int c = (gj & 1) ? -1 : 64;
+        const int gi = x0 + c;
+        if (gj >= 0 && gj < g.ny && gi >= 0 && gi < g.nx) {
+            rv[NRP] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
+            rp[NRP] = (by + H - 1) * LX + c + H;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t <= NRP; ++t)
+        if (rp[t] >= 0) X[rp[t]] = rv[t];
+    __syncthreads();
+
+    // black half-sweep on the tile; each lane writes its black point and the
+    // red point beside it
+#pragma unroll
+    for (int t = 0; t < TY / 8; ++t) {
+        const int ty = rowsel + 8 * t;
+        const int gj = y0 + ty;
+        if (gj >= g.ny) continue;
+        const int cb = 2 * m + 1 - (gj & 1), cr = 2 * m + (gj & 1);
+        const int gib = x0 + cb, gir = x0 + cr;
+        T* row = xout + (int64_t)gj * g.nx;
+        if (gib < g.nx) row[gib] = relax(cb + H, ty + H, gib, gj, B[(ty + 1) * BX + cb + 1]);
+        if (gir < g.nx) row[gir] = X[(ty + H) * LX + cr + H];
+    }
+}
+
+// hipExtLaunchKernelGGL records ev0/ev1 (when given) at the dispatch's own
+// start and end, so profiling this kernel adds no separate event commands.
+template <typename T, int ORDER, int TY>
+static hipError_t sweep2d_launch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
+                                 T aa, T inv, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                                 hipEvent_t ev1) {
+    dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
+    dim3 block(kTileThreads);
+    if (zero_in && prolong)
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, true>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+    else if (zero_in)
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, false>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+    else if (prolong)
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, true>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+    else
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, false>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+    return hipGetLastError();
+}
+
+template <typename T, int ORDER>
+static hipError_t sweep2d_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
+                                   double a, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                                   hipEvent_t ev1) {
+    // interior diagonal of M = I - a L: 1 + a c_0 (1/hx^2 + 1/hy^2), c_0 = 2 (order 2) or 30/12 (order 4)
+    const double c0 = ORDER == 2 ? 2.0 : 30.0 / 12.0;
+    const T inv = (T)(1.0 / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
+    const T aa = (T)a;
+    // tall tiles where there are enough of them to fill the chip, short ones
+    // (less serial work per block) on smaller levels
+    const int64_t tall_tiles = (int64_t)((g.nx + 63) / 64) * ((g.ny + 31) / 32);
+    if (tall_tiles >= 1024)
+        return sweep2d_launch<T, ORDER, 32>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+    return sweep2d_launch<T, ORDER, 8>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+}
+
+template <typename T>
+hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,
+                          int order, double a, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1) {
+    const T bs = (T)bscale;
+    if (order == 2) return sweep2d_dispatch<T, 2>(xin, xc, b, bs, xout, g, gc, a, zero_in, prolong, s, ev0, ev1);
+    return sweep2d_dispatch<T, 4>(xin, xc, b, bs, xout, g, gc, a, zero_in, prolong, s, ev0, ev1);
+}
+
+template hipError_t launch_sweep2d<double>(const double*, const double*, const double*, double, double*, const Geo&,
+                                           const Geo&, int, double, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_sweep2d<float>(const float*, const float*, const float*, double, float*, const Geo&,
+                                          const Geo&, int, double, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);
+
+}  // namespace ew

@@ -7,50 +7,70 @@
 
 namespace ew {
 
+// One full red-black sweep on level l, out of place: cur -> other, then the
+// two pointers swap so that cur holds the result.  With xc != nullptr the
+// prolongation of xc (level l+1) is added to the iterate first; with zero the
+// incoming iterate is taken as zero without being read.
 template <typename T>
-ew_status Op::smooth(int l, T* x, T* xtmp, const T* b, double bscale, int sweeps) {
+ew_status Op::sweep(int l, T*& cur, T*& other, const T* b, double bscale, bool zero, const T* xc) {
     const Level& L = levels[l];
-    // algorithmic bytes of a half-sweep: read x everywhere, read b and write x
-    // at the points of one colour
-    const double bytes = 2.0 * sizeof(T) * (double)L.g.size();
-    for (int s = 0; s < sweeps; ++s) {
-        {
-            ProfScope ps(this, EW_K_SMOOTH, l, bytes);
-            EW_HIP_TRY(launch_rb_half<T>(x, xtmp, b, bscale, L.g, order, a, 0, stream));
-        }
-        {
-            ProfScope ps(this, EW_K_SMOOTH, l, bytes);
-            EW_HIP_TRY(launch_rb_half<T>(xtmp, x, b, bscale, L.g, order, a, 1, stream));
-        }
+    const Geo gc = (xc != nullptr) ? levels[l + 1].g : L.g;
+    const double n = (double)L.g.size();
+    double bytes = sizeof(T) * ((zero ? 2.0 : 3.0) * n);
+    if (xc) bytes += sizeof(T) * (double)gc.size();
+    {
+        ProfScope ps(this, xc ? EW_K_PROLONG : (zero ? EW_K_SMOOTH_ZERO : EW_K_SMOOTH), l, bytes, true);
+        EW_HIP_TRY(launch_sweep_tile<T>(cur, xc, b, bscale, other, L.g, gc, order, a, zero, xc != nullptr, stream,
+                                        ps.start_event(), ps.stop_event()));
     }
+    std::swap(cur, other);
     return EW_OK;
 }
 
-// V(nu1, nu2) cycle on level l; on the coarsest level, exact for one point and
-// otherwise mg_coarse_sweeps sweeps from the incoming iterate.
+// V(nu1, nu2) cycle on level l starting from the iterate in cur (zero if
+// `zero`); other is its partner buffer.  *result receives the buffer that holds
+// the new iterate (cur or other).  Levels from coarse_level down run in one
+// workgroup; a coarsest level of one point is solved exactly and a larger one
+// gets mg_coarse_sweeps sweeps.
 template <typename T>
-ew_status Op::vcycle(int l, T* x, T* xtmp, const T* b, double bscale) {
+ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool zero, T** result) {
     const int last = (int)levels.size() - 1;
     const Level& L = levels[l];
+    if (l >= coarse_level) {
+        // the coarse range must start at this level
+        CoarseLevels c = coarse;
+        {
+            ProfScope ps(this, EW_K_COARSE, l, sizeof(T) * 3.0 * (double)L.g.size());
+            EW_HIP_TRY(launch_coarse_vcycle<T>(b, bscale, zero ? nullptr : cur, cur, c, order, a, desc.mg_nu1,
+                                               desc.mg_nu2, desc.mg_coarse_sweeps, stream));
+        }
+        *result = cur;
+        return EW_OK;
+    }
     if (l == last) {
         const int sweeps = L.g.size() == 1 ? 1 : desc.mg_coarse_sweeps;
-        return smooth<T>(l, x, xtmp, b, bscale, sweeps);
+        for (int s = 0; s < sweeps; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, zero && s == 0, nullptr));
+        *result = cur;
+        return EW_OK;
     }
-    EW_TRY(smooth<T>(l, x, xtmp, b, bscale, desc.mg_nu1));
+    for (int s = 0; s < desc.mg_nu1; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, zero && s == 0, nullptr));
+    if (desc.mg_nu1 == 0 && zero) EW_HIP_TRY(launch_fill<T>(cur, L.g.size(), T(0), stream));
     const Level& C = levels[l + 1];
-    T* xc = (T*)C.x[0];
-    T* bc = (T*)C.b;
     {
         ProfScope ps(this, EW_K_RESTRICT, l, sizeof(T) * (2.0 * L.g.size() + C.g.size()));
-        EW_HIP_TRY(launch_residual_restrict<T>(x, b, bscale, L.g, order, a, bc, C.g, stream));
+        EW_HIP_TRY(launch_restrict_tile<T>(cur, b, bscale, L.g, order, a, (T*)C.b, C.g, stream));
     }
-    EW_HIP_TRY(launch_fill<T>(xc, C.g.size(), T(0), stream));
-    EW_TRY(vcycle<T>(l + 1, xc, (T*)C.x[1], bc, 1.0));
-    {
+    T* xc = nullptr;
+    EW_TRY(vcycle<T>(l + 1, (T*)C.x[0], (T*)C.x[1], (T*)C.b, 1.0, true, &xc));
+    if (desc.mg_nu2 >= 1) {
+        EW_TRY(sweep<T>(l, cur, other, b, bscale, false, xc));
+        for (int s = 1; s < desc.mg_nu2; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, false, nullptr));
+    } else {
         ProfScope ps(this, EW_K_PROLONG, l, sizeof(T) * (2.0 * L.g.size() + C.g.size()));
-        EW_HIP_TRY(launch_prolong_correct<T>(x, xc, L.g, C.g, stream));
+        EW_HIP_TRY(launch_prolong_correct<T>(cur, xc, L.g, C.g, stream));
     }
-    return smooth<T>(l, x, xtmp, b, bscale, desc.mg_nu2);
+    *result = cur;
+    return EW_OK;
 }
 
 static ew_status check_rel(double rel) {
@@ -59,7 +79,12 @@ static ew_status check_rel(double rel) {
 }
 
 // FP64 multigrid: x <- M^{-1} (bscale b) to ||r||_2 <= mg_tol ||bscale b||_2.
-ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel_out) {
+// With `speculate`, the first (previous solve's count - 1) cycles run without
+// the residual test, which costs a pass over x and b and a host round trip;
+// the test then runs after every further cycle, so the solve still stops at
+// the first tested cycle that meets the tolerance.
+ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel_out,
+                         bool speculate) {
     EW_HIP_TRY(launch_dot_partial(b, b, N, partial_dev, stream));
     double bb = 0.0;
     EW_TRY(host_sum_partials(&bb));
@@ -70,31 +95,38 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
     if (bn == 0.0) {
         EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
     } else {
-        if (x_is_zero) {
-            rel = 1.0;
-        } else {
-            EW_HIP_TRY((launch_residual_norm<double, double>(x, b, bscale, g, order, a, partial_dev, nullptr, stream)));
-            double rr;
-            EW_TRY(host_sum_partials(&rr));
-            rel = std::sqrt(rr) / bn;
-            EW_TRY(check_rel(rel));
-        }
-        double* xtmp = (double*)levels[0].x[1];
-        while (rel > desc.mg_tol && cyc < desc.mg_max_cycles) {
-            EW_TRY(vcycle<double>(0, x, xtmp, b, bscale));
-            ++cyc;
-            {
-                ProfScope ps(this, EW_K_RESNORM, 0, 16.0 * (double)N);
-                EW_HIP_TRY((launch_residual_norm<double, double>(x, b, bscale, g, order, a, partial_dev, nullptr, stream)));
+        const int skip = speculate && last_cycles > 0 ? last_cycles - 1 : 0;
+        double* cur = x;
+        double* other = (double*)levels[0].x[1];
+        bool zero = x_is_zero;
+        for (;;) {
+            const bool test = cyc >= skip && !(zero && cyc == 0);
+            if (test) {
+                {
+                    ProfScope ps(this, EW_K_RESNORM, 0, 16.0 * (double)N);
+                    EW_HIP_TRY((launch_residual_norm<double, double>(cur, b, bscale, g, order, a, partial_dev, nullptr,
+                                                                     stream)));
+                }
+                double rr;
+                EW_TRY(host_sum_partials(&rr));
+                rel = std::sqrt(rr) / bn;
+                EW_TRY(check_rel(rel));
+                if (rel <= desc.mg_tol) break;
+            } else {
+                rel = 1.0;
             }
-            double rr;
-            EW_TRY(host_sum_partials(&rr));
-            rel = std::sqrt(rr) / bn;
-            EW_TRY(check_rel(rel));
+            if (cyc >= desc.mg_max_cycles) break;
+            double* res = nullptr;
+            EW_TRY(vcycle<double>(0, cur, other, b, bscale, zero, &res));
+            if (res != cur) std::swap(cur, other);
+            zero = false;
+            ++cyc;
         }
+        if (cur != x) EW_HIP_TRY(hipMemcpyAsync(x, cur, N * sizeof(double), hipMemcpyDeviceToDevice, stream));
     }
     stats.mg_solves++;
     stats.mg_cycles += cyc;
+    last_cycles = cyc;
     if (cycles) *cycles = cyc;
     if (rel_out) *rel_out = rel;
     if (rel > desc.mg_tol)
@@ -132,9 +164,9 @@ ew_status Op::mg_solve_mixed(const double* b, double bscale, double* x, bool x_i
             rel = std::sqrt(rr) / bn;
             EW_TRY(check_rel(rel));
             if (rel <= desc.mg_tol || cyc >= desc.mg_max_cycles) break;
-            EW_HIP_TRY(launch_fill<float>(e32, N, 0.0f, stream));
-            EW_TRY(vcycle<float>(0, e32, t32, r32, 1.0));
-            EW_HIP_TRY((launch_add_inplace<double, float>(x, e32, N, stream)));
+            float* e = nullptr;
+            EW_TRY(vcycle<float>(0, e32, t32, r32, 1.0, true, &e));
+            EW_HIP_TRY((launch_add_inplace<double, float>(x, e, N, stream)));
             ++cyc;
         }
     }
@@ -155,7 +187,6 @@ ew_status Op::implicit_solve(const double* b, double bscale, double* x, const do
     bool zero = false;
     if (desc.predictor == EW_PRED_ZERO) {
         zero = true;
-        if (!mixed) EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
     } else if (desc.predictor == EW_PRED_SCALED || wprev_for_guess == nullptr || cnn == nullptr) {
         // M phi = (1 + a mu) phi: exact for every mode at mu = omega^2.
         const double s = bscale / (1.0 + a * omega_used * omega_used);
@@ -164,7 +195,7 @@ ew_status Op::implicit_solve(const double* b, double bscale, double* x, const do
         EW_TRY(cnn_predict(this, b, wprev_for_guess, x));
     }
     if (mixed) return mg_solve_mixed(b, bscale, x, zero, nullptr, nullptr);
-    return mg_solve64(b, bscale, x, zero, nullptr, nullptr);
+    return mg_solve64(b, bscale, x, zero, nullptr, nullptr, true);
 }
 
 ew_status Op::apply_filter(const double* v, double* out) {
@@ -225,8 +256,8 @@ ew_status Op::apply_filter(const double* v, double* out) {
     return EW_OK;
 }
 
-template ew_status Op::vcycle<double>(int, double*, double*, const double*, double);
-template ew_status Op::vcycle<float>(int, float*, float*, const float*, double);
+template ew_status Op::vcycle<double>(int, double*, double*, const double*, double, bool, double**);
+template ew_status Op::vcycle<float>(int, float*, float*, const float*, double, bool, float**);
 
 }  // namespace ew
 
@@ -254,7 +285,11 @@ extern "C" ew_status ew_op_mg_vcycle(ew_op op, const double* b_dev, double* x_de
     if (!op || !b_dev || !x_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
     if (!op->implicit || op->mixed) return fail(EW_ERR_INVALID_ARG, "needs an implicit FP64 operator");
     if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
-    return op->vcycle<double>(0, x_dev, (double*)op->levels[0].x[1], b_dev, 1.0);
+    double* res = nullptr;
+    EW_TRY(op->vcycle<double>(0, x_dev, (double*)op->levels[0].x[1], b_dev, 1.0, false, &res));
+    if (res != x_dev)
+        EW_HIP_TRY(hipMemcpyAsync(x_dev, res, op->N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));
+    return EW_OK;
 }
 
 extern "C" ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* x_dev, int colour) {

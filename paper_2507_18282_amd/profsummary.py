@@ -75,8 +75,9 @@ def counter_summary(fetch_csv: str, write_csv: str, out_txt: str, kernel: str, g
 
     kf, nf = pick(fetch, kernel, grid)
     kw, nw = pick(write, kernel, grid)
-    cf, _ = pick(fetch, "copyBuffer", None)
-    cw, _ = pick(write, "copyBuffer", None)
+    # the calibration copy is the copy dispatch that moved the most bytes
+    cf = max((v for (n, _), vs in fetch.items() if "copyBuffer" in n for v in vs), default=float("nan"))
+    cw = max((v for (n, _), vs in write.items() if "copyBuffer" in n for v in vs), default=float("nan"))
     # scale factors: bytes the copy really moved per KiB the counter reported
     sf = copy_bytes / cf if cf == cf and cf > 0 else float("nan")
     sw = copy_bytes / cw if cw == cw and cw > 0 else float("nan")

@@ -98,6 +98,8 @@ def test_explicit_filter_mixed_precision(P):
 
 IMPLICIT_CASES = [
     synthetic.Problem(n=(63, 63), length=(1.0, 1.0), order=2, omega=30.0, ts="implicit", adjust_omega=True),
+    synthetic.Problem(n=(127, 95), length=(1.0, 0.75), order=4, omega=50.0, ts="implicit", adjust_omega=True),
+    synthetic.Problem(n=(31, 15, 31), length=(1.0, 0.5, 1.0), order=2, omega=15.0, ts="implicit"),
     synthetic.Problem(n=(63, 31), length=(1.0, 0.5), order=4, omega=30.0, ts="implicit", adjust_omega=True),
     synthetic.Problem(n=(95, 47), length=(1.0, 0.5), order=4, omega=40.0, ts="implicit", n_p=2),
     synthetic.Problem(n=(15, 15, 15), length=(1.0, 1.0, 1.0), order=2, omega=12.0, ts="implicit",
@@ -111,9 +113,12 @@ def _mg_hierarchy(P, a):
     return OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=8)
 
 
+# mg_coarse_points: 0 lets the single-workgroup kernel take every level that
+# fits in LDS; 40 sends all but the last levels through the tiled kernels.
+@pytest.mark.parametrize("coarse_points", [0, 40])
 @pytest.mark.parametrize("P", IMPLICIT_CASES, ids=lambda P: f"{P.n}-o{P.order}")
-def test_mg_half_sweep_and_vcycle_match_oracle(P):
-    op = make_op(P)
+def test_mg_half_sweep_and_vcycle_match_oracle(P, coarse_points):
+    op = make_op(P, mg_coarse_points=coarse_points)
     h, plan = oracle_plan(P)
     a = 0.5 * plan.dt ** 2
     hier = _mg_hierarchy(P, a)
@@ -132,9 +137,10 @@ def test_mg_half_sweep_and_vcycle_match_oracle(P):
     assert rel_err(got, want) < 1e-12
 
 
+@pytest.mark.parametrize("coarse_points", [0, 40])
 @pytest.mark.parametrize("P", IMPLICIT_CASES, ids=lambda P: f"{P.n}-o{P.order}")
-def test_mg_solve_reaches_exact_solution(P):
-    op = make_op(P)
+def test_mg_solve_reaches_exact_solution(P, coarse_points):
+    op = make_op(P, mg_coarse_points=coarse_points)
     h, plan = oracle_plan(P)
     b = synthetic.uniform_pm1(31, P.n_active)
     x0 = np.zeros(P.n_active)
@@ -165,14 +171,14 @@ def test_implicit_filter_matches_oracle(P):
 
 @pytest.mark.parametrize("pred", ["zero", "scaled"])
 def test_implicit_filter_predictors_agree(pred):
-    P = IMPLICIT_CASES[1]
+    P = IMPLICIT_CASES[3]
     op = make_op(P, predictor=pred)
     v = synthetic.uniform_pm1(43, P.n_active)
     got = to_host(op.apply_filter(to_dev(v)))
     assert rel_err(got, oracle_S(P, v)) < 100 * P.mg_tol * np.sqrt(P.n_active)
 
 
-@pytest.mark.parametrize("P", [IMPLICIT_CASES[0], IMPLICIT_CASES[3]], ids=lambda P: f"{P.n}")
+@pytest.mark.parametrize("P", [IMPLICIT_CASES[0], IMPLICIT_CASES[2], IMPLICIT_CASES[5]], ids=lambda P: f"{P.n}")
 def test_implicit_filter_mixed_precision(P):
     import dataclasses
     Pm = dataclasses.replace(P, precision="mixed")
