@@ -243,6 +243,52 @@ typedef struct {
 ew_status ew_op_profile_begin(ew_op op, int kclass, int level);
 ew_status ew_op_profile_end(ew_op op, ew_kernel_profile* out);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent 2D Dirichlet rectangles, explicit leapfrog,
+ * FP32 state and filter accumulation (precision EW_PREC_MIXED), FP64 vectors
+ * and Arnoldi.  All problems share one stencil order.  Problems with
+ * nx, ny <= 128 run their whole wave-solve inside one workgroup; larger ones
+ * advance one time step per batched launch.  One batched wave-solve is a
+ * captured hipGraph replayed on a private stream and joined to the caller's
+ * stream with events.  At creation the tile height of the batched step kernel
+ * is chosen by timing the candidates on the batch (ew_batch_info.tune_us).
+ * ------------------------------------------------------------------------ */
+typedef struct ew_batch_s* ew_batch;
+
+typedef struct {
+    int nprob;
+    int n_small;                 /* problems solved inside one workgroup */
+    int n_large;                 /* problems advanced by the batched step kernel */
+    int max_steps_large;         /* step launches per batched wave-solve */
+    int step_rows_per_thread;    /* tile height chosen by the autotuner (rows = 4 x this) */
+    double tune_us[4];           /* measured time per step launch for 1, 2, 4, 8 rows per thread */
+    int64_t total_steps;         /* sum of N_t over the problems */
+    int64_t pt_updates_per_wave_solve;
+} ew_batch_info;
+
+/* grids[i], descs[i] describe problem i (same rules as ew_op_create, plus:
+ * dim 2, ts EW_TS_EXPLICIT, precision EW_PREC_MIXED, one order for all).
+ * Allocates every problem's workspace, autotunes and captures the graph.
+ * Host-blocking. */
+ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const ew_op_desc* descs, void* hip_stream,
+                          ew_batch* out);
+void ew_batch_destroy(ew_batch b);
+ew_status ew_batch_get_info(ew_batch b, ew_batch_info* out);
+/* n_active and N_t of problem i (either output may be NULL). */
+ew_status ew_batch_n_active(ew_batch b, int i, int64_t* n_active, int* n_t);
+/* out_dev[i] = S_i v_dev[i] for every problem (host arrays of nprob device
+ * pointers to n_active_i FP64 values; out may not alias v).  Stream-ordered
+ * on the stream given at creation. */
+ew_status ew_batch_apply_filter(ew_batch b, const double* const* v_dev, double* const* out_dev);
+/* The eigensolver of ew_eigs for every problem, advanced in lock-step
+ * (descs: nprob entries).  Outputs of problem i start at i*k_cap in mu_host,
+ * beta_host, res_host; n_conv_host[i] (may be NULL) gets its converged count;
+ * Y_dev (may be NULL) is a host array of nprob device pointers, each to
+ * n_active_i x k_cap FP64.  stats (may be NULL) sums over the problems.
+ * Host-blocking.  EW_ERR_NOT_CONVERGED if any problem hit its budget. */
+ew_status ew_batch_eigs(ew_batch b, const ew_eigs_desc* descs, int k_cap, double* mu_host, double* beta_host,
+                        double* res_host, int* n_conv_host, double* const* Y_dev, ew_eigs_stats* stats);
+
 /* Fill x_dev (n FP64, device) with SplitMix64 uniform[-1,1) values of stream
  * `seed`: element i is 2*((z_i >> 11) * 2^-53) - 1 with z_i the SplitMix64
  * output for counter i+1.  Stream-ordered on `hip_stream`. */

@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import EigenwaveError, check, load
 
-__all__ = ["Operator", "EigsResult", "fill_uniform", "EigenwaveError", "load", "version"]
+__all__ = ["Operator", "Batch", "EigsResult", "fill_uniform", "EigenwaveError", "load", "version"]
 
 
 def _torch():
@@ -190,6 +190,124 @@ class Operator:
                           wave_solves=int(st.wave_solves), restarts=int(st.restarts), probes=int(st.probes),
                           time_steps=int(st.time_steps), pt_updates=int(st.pt_updates),
                           mg_cycles=int(st.mg_cycles), seconds=float(st.seconds), status=int(status))
+
+
+def _grid_desc(n, length, order):
+    g = _lib.GridDesc()
+    g.dim = len(n)
+    for d in range(3):
+        g.n[d] = int(n[d]) if d < len(n) else 1
+        g.len[d] = float(length[d]) if d < len(n) else 1.0
+    g.order = int(order)
+    return g
+
+
+def _op_desc(omega, ts, cfl=0.5, n_its=10, n_p=1, adjust_omega=False, filter_const="alpha_d", precision="fp64",
+             mg_tol=1e-10, mg_nu1=2, mg_nu2=1, mg_max_cycles=100, mg_coarse_sweeps=8, mg_coarse_points=0,
+             predictor="zero"):
+    d = _lib.OpDesc()
+    d.omega, d.ts, d.cfl, d.n_its, d.n_p = float(omega), _lib.TS[ts], float(cfl), int(n_its), int(n_p)
+    d.adjust_omega, d.filter_const = int(bool(adjust_omega)), _lib.FILTER[filter_const]
+    d.precision, d.mg_tol = _lib.PRECISION[precision], float(mg_tol)
+    d.mg_nu1, d.mg_nu2, d.mg_max_cycles = int(mg_nu1), int(mg_nu2), int(mg_max_cycles)
+    d.mg_coarse_sweeps, d.mg_coarse_points, d.predictor = int(mg_coarse_sweeps), int(mg_coarse_points), \
+        _lib.PREDICTOR[predictor]
+    return d
+
+
+class Batch:
+    """Many independent 2D explicit problems solved together (see ew_batch_create).
+
+    ``problems`` is a list of dicts with keys n, length, order, omega and the
+    optional operator keywords (cfl, n_p, filter_const); every problem uses
+    explicit stepping with FP32 state."""
+
+    def __init__(self, problems, stream=None):
+        lib = load()
+        self._lib = lib
+        n = len(problems)
+        G = (_lib.GridDesc * n)()
+        D = (_lib.OpDesc * n)()
+        for i, p in enumerate(problems):
+            G[i] = _grid_desc(p["n"], p["length"], p["order"])
+            kw = {k: v for k, v in p.items() if k not in ("n", "length", "order", "omega")}
+            kw.setdefault("precision", "mixed")
+            D[i] = _op_desc(p["omega"], "explicit", **kw)
+        self._h = ctypes.c_void_p()
+        check(lib.ew_batch_create(n, G, D, ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(self._h)))
+        self.nprob = n
+        self.n_active = []
+        self.n_t = []
+        for i in range(n):
+            na, nt = ctypes.c_int64(), ctypes.c_int()
+            check(lib.ew_batch_n_active(self._h, i, ctypes.byref(na), ctypes.byref(nt)))
+            self.n_active.append(int(na.value))
+            self.n_t.append(int(nt.value))
+        info = _lib.BatchInfo()
+        check(lib.ew_batch_get_info(self._h, ctypes.byref(info)))
+        self.info = {"n_small": info.n_small, "n_large": info.n_large, "max_steps_large": info.max_steps_large,
+                     "step_rows_per_thread": info.step_rows_per_thread, "tune_us": list(info.tune_us),
+                     "total_steps": int(info.total_steps),
+                     "pt_updates_per_wave_solve": int(info.pt_updates_per_wave_solve)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ew_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_filter(self, vs, outs=None):
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty(n, dtype=torch.float64, device="cuda") for n in self.n_active]
+        V = (ctypes.c_void_p * self.nprob)(*[_dev_ptr(v, n) for v, n in zip(vs, self.n_active)])
+        O = (ctypes.c_void_p * self.nprob)(*[_dev_ptr(o, n) for o, n in zip(outs, self.n_active)])
+        check(self._lib.ew_batch_apply_filter(self._h, V, O))
+        return outs
+
+    def eigs(self, k: int, m: int, tol_ritz: float = 1e-12, tol_res: float = 1e-8, max_wave_solves: int = 100000,
+             seeds=None, n_keep: int = 0, max_probes: int = 16, k_cap: Optional[int] = None,
+             want_vectors: bool = False, raise_on_error: bool = True):
+        torch = _torch()
+        n = self.nprob
+        D = (_lib.EigsDesc * n)()
+        for i in range(n):
+            D[i].k, D[i].m = int(k), int(m)
+            D[i].tol_ritz, D[i].tol_res = float(tol_ritz), float(tol_res)
+            D[i].max_wave_solves = int(max_wave_solves)
+            D[i].seed = int(seeds[i]) if seeds is not None else 1 + i
+            D[i].v0_dev = None
+            D[i].n_keep, D[i].max_probes = int(n_keep), int(max_probes)
+        cap = int(k_cap) if k_cap is not None else 3 * m + k
+        mu = (ctypes.c_double * (cap * n))()
+        beta = (ctypes.c_double * (cap * n))()
+        res = (ctypes.c_double * (cap * n))()
+        nconv = (ctypes.c_int * n)()
+        Ys = None
+        Yp = None
+        if want_vectors:
+            Ys = [torch.zeros((cap, na), dtype=torch.float64, device="cuda") for na in self.n_active]
+            Yp = (ctypes.c_void_p * n)(*[int(y.data_ptr()) for y in Ys])
+        st = _lib.EigsStats()
+        status = self._lib.ew_batch_eigs(self._h, D, cap, mu, beta, res, nconv, Yp, ctypes.byref(st))
+        if status != _lib.EW_OK and raise_on_error:
+            check(status)
+        out = []
+        for i in range(n):
+            nc = int(nconv[i])
+            # returned pairs: every pair Stage 2 produced, up to k_cap (converged or not)
+            rows = [j for j in range(cap) if mu[i * cap + j] != 0.0]
+            out.append({"mu": [mu[i * cap + j] for j in rows], "beta": [beta[i * cap + j] for j in rows],
+                        "res": [res[i * cap + j] for j in rows], "n_conv": nc,
+                        "Y": (Ys[i][:len(rows)].T if Ys is not None else None)})
+        return out, {"wave_solves": int(st.wave_solves), "restarts": int(st.restarts), "probes": int(st.probes),
+                     "pt_updates": int(st.pt_updates), "seconds": float(st.seconds), "n_conv": int(st.n_conv),
+                     "max_res": float(st.max_res), "status": int(status)}
 
 
 def fill_uniform(n: int, seed: int, stream=None):

@@ -61,6 +61,12 @@ KCLASS = {"leapfrog": 0, "smooth": 1, "restrict": 2, "prolong": 3, "resnorm": 4,
           "smooth_zero": 7}
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("nprob", c_int), ("n_small", c_int), ("n_large", c_int), ("max_steps_large", c_int),
+                ("step_rows_per_thread", c_int), ("tune_us", c_double * 4), ("total_steps", c_int64),
+                ("pt_updates_per_wave_solve", c_int64)]
+
+
 # name -> (restype, argtypes); every symbol include/eigenwave.h declares.
 SIGNATURES = {
     "ew_op_create": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
@@ -77,6 +83,13 @@ SIGNATURES = {
                         POINTER(c_double), c_void_p, POINTER(EigsStats)]),
     "ew_op_profile_begin": (c_int, [c_void_p, c_int, c_int]),
     "ew_op_profile_end": (c_int, [c_void_p, POINTER(KernelProfile)]),
+    "ew_batch_create": (c_int, [c_int, POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
+    "ew_batch_destroy": (None, [c_void_p]),
+    "ew_batch_get_info": (c_int, [c_void_p, POINTER(BatchInfo)]),
+    "ew_batch_n_active": (c_int, [c_void_p, c_int, POINTER(c_int64), POINTER(c_int)]),
+    "ew_batch_apply_filter": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),
+    "ew_batch_eigs": (c_int, [c_void_p, POINTER(EigsDesc), c_int, POINTER(c_double), POINTER(c_double),
+                              POINTER(c_double), POINTER(c_int), POINTER(c_void_p), POINTER(EigsStats)]),
     "ew_fill_uniform": (c_int, [c_void_p, c_int64, c_uint64, c_void_p]),
     "ew_last_error": (c_char_p, []),
     "ew_version": (c_char_p, []),

@@ -1,0 +1,55 @@
+// Declarations shared by the batched form (batch.hip, batch_kernels.hip).
+#pragma once
+
+#include "ew_internal.h"
+
+namespace ew {
+
+constexpr int kBatchSmallThreads = 1024;
+constexpr int kBatchSmallPts = 16;       // points per thread: small problems have <= 16384 points
+constexpr int kBatchSmallMaxSide = 128;  // and nx, ny <= 128 (LDS (nx+4)(ny+4) floats <= 70 KB)
+constexpr int kConvPerThread = 8;
+
+// Per-problem state visible to the kernels (device array, refreshed before
+// every batched wave-solve).
+struct BatchProbDev {
+    Geo g;
+    int order;
+    int n_t;
+    float dt2;
+    int coef_off;
+    int active;
+    int pad;
+    const double* v;   // W^0 (FP64, caller's vector)
+    double* out;       // S v (FP64)
+    float* f0;         // W^0 in FP32
+    float* fA;         // odd time levels
+    float* fB;         // even time levels >= 2
+    float* acc;        // filter accumulator
+};
+
+// Per-problem description of one batched Gram-Schmidt chain.
+struct BatchMgsDev {
+    double* w;
+    int64_t n;
+    int q;         // chain length: number of basis vectors + 1 (0 = problem idle this step)
+    int nblk;      // reduction blocks of this problem
+    int part_off;  // offset of its two partial-sum arrays
+    int h_off;     // offset of its coefficients in the output
+};
+
+struct MgsLink {
+    const double* u;
+};
+
+hipError_t launch_batch_small(BatchProbDev* probs, const int* small_ids, int nsmall, const float* coef, int order,
+                              size_t lds_bytes, hipStream_t s);
+hipError_t prepare_batch_small(int order, size_t lds_bytes);
+hipError_t launch_batch_step(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
+                             const float* coef, int step, int order, int tyr, hipStream_t s);
+hipError_t launch_batch_convert(BatchProbDev* probs, const int* ids, const int* blk_start, int nseg, int nblocks,
+                                int to_fp32, hipStream_t s);
+hipError_t launch_batch_mgs(const BatchMgsDev* info, const MgsLink* links, int nprob, const int* blk_start,
+                            int nblocks, int ell, double* partial, double* hout, hipStream_t s);
+
+}  // namespace ew

@@ -9,48 +9,15 @@
 #include <cmath>
 #include <cstring>
 
-#include "dense.h"
+#include "eigs_core.h"
 #include "op.h"
 
 namespace ew {
 
-namespace {
-
-struct Workspace {
-    Op* op = nullptr;
-    int64_t N = 0;
-    int m = 0, cap_lock = 0;
-    double* V = nullptr;      // N x (m+1)
-    double* Vt = nullptr;     // N x (m+1), rotation target
-    double* Y = nullptr;      // N x cap_lock, locked vectors
-    double* LY = nullptr;     // N x cap_lock, L_h applied to them / scratch
-    double* Z = nullptr;      // N x cap_lock, Rayleigh-Ritz vectors
-    double* P = nullptr;      // 2 x kRedBlocks partial sums (ping-pong)
-    double* h_dev = nullptr;  // Gram-Schmidt coefficients of one step
-    double* q_dev = nullptr;  // small matrices for basis rotations
-    double* gram_dev = nullptr;
-    double* h_host = nullptr;
-    std::vector<void*> owned;
-    ~Workspace() {
-        for (void* p : owned) hipFree(p);
-        if (h_host) hipHostFree(h_host);
-    }
-    ew_status alloc(double** p, size_t count) {
-        hipError_t e = hipMalloc((void**)p, count * sizeof(double) + 256);
-        if (e != hipSuccess) return fail(EW_ERR_OOM, std::string("eigensolver workspace: ") + hipGetErrorString(e));
-        owned.push_back(*p);
-        return EW_OK;
-    }
-    double* col(double* base, int j) const { return base + (int64_t)j * N; }
-};
-
-constexpr int kGramBlocks = 256;
-
 // w <- w - sum_i (w, u_i) u_i over the vector list by chained MGS links, then
 // w <- w / ||w||.  coeff receives the n_u coefficients and the norm (n_u + 1).
 ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const double*>& u, std::vector<double>& coeff) {
-    Op* op = ws.op;
-    hipStream_t s = op->stream;
+    hipStream_t s = ws.stream;
     const int nu = (int)u.size();
     double* P0 = ws.P;
     double* P1 = ws.P + kRedBlocks;
@@ -81,10 +48,10 @@ ew_status rotate(Workspace& ws, const double* X, int nx, const Mat& Qm, int ncol
     std::vector<double> qc((size_t)nx * ncols);
     for (int c = 0; c < ncols; ++c)
         for (int i = 0; i < nx; ++i) qc[(size_t)c * nx + i] = Qm(i, c);
-    EW_HIP_TRY(hipMemcpyAsync(ws.q_dev, qc.data(), qc.size() * sizeof(double), hipMemcpyHostToDevice, ws.op->stream));
-    EW_HIP_TRY(launch_tall_gemm(X, ws.N, nx, ws.q_dev, nx, ncols, Y, ws.op->stream));
+    EW_HIP_TRY(hipMemcpyAsync(ws.q_dev, qc.data(), qc.size() * sizeof(double), hipMemcpyHostToDevice, ws.stream));
+    EW_HIP_TRY(launch_tall_gemm(X, ws.N, nx, ws.q_dev, nx, ncols, Y, ws.stream));
     // qc must outlive the copy: the stream is synchronised before it goes out of scope.
-    EW_HIP_TRY(hipStreamSynchronize(ws.op->stream));
+    EW_HIP_TRY(hipStreamSynchronize(ws.stream));
     return EW_OK;
 }
 
@@ -197,12 +164,11 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
 
 // Sum nblocks partial Gram blocks on the host, in block order.
 ew_status gram(Workspace& ws, const double* A, int na, const double* B, int nb, Mat& G, int r0, int c0) {
-    Op* op = ws.op;
-    EW_HIP_TRY(launch_gram_partial(A, na, B, nb, ws.N, ws.gram_dev, kGramBlocks, op->stream));
+    EW_HIP_TRY(launch_gram_partial(A, na, B, nb, ws.N, ws.gram_dev, kGramBlocks, ws.stream));
     std::vector<double> hbuf((size_t)kGramBlocks * na * nb);
     EW_HIP_TRY(hipMemcpyAsync(hbuf.data(), ws.gram_dev, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost,
-                              op->stream));
-    EW_HIP_TRY(hipStreamSynchronize(op->stream));
+                              ws.stream));
+    EW_HIP_TRY(hipStreamSynchronize(ws.stream));
     for (int i = 0; i < na; ++i)
         for (int j = 0; j < nb; ++j) {
             double s = 0.0;
@@ -221,7 +187,96 @@ ew_status full_gram(Workspace& ws, const double* A, const double* B, int n, Mat&
     return EW_OK;
 }
 
-}  // namespace
+}  // namespace ew
+
+namespace ew {
+
+// Stage 2: Rayleigh-Ritz of L_h on the nl locked vectors Y (eq.
+// discreteRayleighQuotient applied blockwise): G q = mu B q with G = -Y^T L Y
+// and B = Y^T Y; residuals ||L z + mu z|| / (mu ||z||); pairs written ordered by
+// |beta| descending, beta of each Rayleigh-Ritz vector being the locked Ritz
+// values averaged with weights q_i^2.
+ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, double tol_res, int k_cap,
+                 double* mu_host, double* beta_host, double* res_host, double* Y_dev, int* n_conv_out, int* n_ret_out,
+                 double* max_res_out) {
+    const int64_t N = ws.N;
+    for (int i = 0; i < nl; ++i)
+        EW_HIP_TRY(launch_laplacian<double>(ws.col(ws.Y, i), ws.col(ws.LY, i), ws.g, ws.order, ws.stream));
+    Mat G, B;
+    EW_TRY(full_gram(ws, ws.Y, ws.LY, nl, G));
+    EW_TRY(full_gram(ws, ws.Y, ws.Y, nl, B));
+    Mat Gs(nl, nl), Bs(nl, nl);
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+            Gs(i, j) = -0.5 * (G(i, j) + G(j, i));
+            Bs(i, j) = 0.5 * (B(i, j) + B(j, i));
+        }
+    Mat Lc;
+    if (!cholesky(Bs, Lc)) return fail(EW_ERR_NONFINITE, "locked vectors are not linearly independent");
+    Mat Li = lower_inverse(Lc);
+    Mat C(nl, nl);
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+            double s = 0.0;
+            for (int a = 0; a <= i; ++a)
+                for (int b = 0; b <= j; ++b) s += Li(i, a) * Gs(a, b) * Li(j, b);
+            C(i, j) = s;
+        }
+    std::vector<double> mu;
+    Mat Zc;
+    jacobi_eigh(C, mu, Zc);
+    Mat Qr(nl, nl);  // Q = Li^T Zc
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+            double s = 0.0;
+            for (int a = i; a < nl; ++a) s += Li(a, i) * Zc(a, j);
+            Qr(i, j) = s;
+        }
+    // beta of each Rayleigh-Ritz vector: theta averaged with weights Q^2
+    std::vector<double> beta(nl);
+    for (int j = 0; j < nl; ++j) {
+        double num = 0.0, den = 0.0;
+        for (int i = 0; i < nl; ++i) {
+            num += th_locked[i] * Qr(i, j) * Qr(i, j);
+            den += Qr(i, j) * Qr(i, j);
+        }
+        beta[j] = num / den;
+    }
+    EW_TRY(rotate(ws, ws.Y, nl, Qr, nl, ws.Z));
+    std::vector<double> res(nl), znorm(nl);
+    for (int j = 0; j < nl; ++j) {
+        // L z_j into the (no longer needed) L Y buffer, then ||L z + mu z||.
+        EW_HIP_TRY(launch_laplacian<double>(ws.col(ws.Z, j), ws.col(ws.LY, j), ws.g, ws.order, ws.stream));
+        EW_HIP_TRY(launch_eig_residual(ws.col(ws.LY, j), ws.col(ws.Z, j), mu[j], N, ws.P, ws.stream));
+        EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.P, 2 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, ws.stream));
+        EW_HIP_TRY(hipStreamSynchronize(ws.stream));
+        double r2 = 0.0, z2 = 0.0;
+        for (int b = 0; b < kRedBlocks; ++b) r2 += ws.h_host[b];
+        for (int b = 0; b < kRedBlocks; ++b) z2 += ws.h_host[kRedBlocks + b];
+        znorm[j] = std::sqrt(z2);
+        res[j] = std::sqrt(r2) / (std::fabs(mu[j]) * znorm[j]);
+    }
+    std::vector<int> order = order_by_abs_desc(beta);
+    int n_conv = 0;
+    for (int j = 0; j < nl; ++j) n_conv += res[j] <= tol_res;
+    const int n_ret = std::min(nl, k_cap);
+    double max_res = 0.0;
+    for (int r = 0; r < n_ret; ++r) {
+        const int j = order[r];
+        mu_host[r] = mu[j];
+        beta_host[r] = beta[j];
+        res_host[r] = res[j];
+        max_res = std::max(max_res, res[j]);
+        if (Y_dev) {
+            EW_HIP_TRY(launch_scale_copy<double>(Y_dev + (int64_t)r * N, ws.col(ws.Z, j), N, 1.0 / znorm[j], ws.stream));
+        }
+    }
+    EW_HIP_TRY(hipStreamSynchronize(ws.stream));
+    *n_conv_out = n_conv;
+    *n_ret_out = n_ret;
+    *max_res_out = max_res;
+    return EW_OK;
+}
 
 }  // namespace ew
 
@@ -245,19 +300,10 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
 
     Workspace ws;
     ws.op = op;
-    ws.N = N;
-    ws.m = m;
-    ws.cap_lock = (int)std::min<int64_t>(std::min<int64_t>(N, 3 * m + k), 320);
-    EW_TRY(ws.alloc(&ws.V, (size_t)N * (m + 1)));
-    EW_TRY(ws.alloc(&ws.Vt, (size_t)N * (m + 1)));
-    EW_TRY(ws.alloc(&ws.Y, (size_t)N * ws.cap_lock));
-    EW_TRY(ws.alloc(&ws.LY, (size_t)N * ws.cap_lock));
-    EW_TRY(ws.alloc(&ws.Z, (size_t)N * ws.cap_lock));
-    EW_TRY(ws.alloc(&ws.P, 2 * kRedBlocks));
-    EW_TRY(ws.alloc(&ws.h_dev, 4 * 256 + 64));
-    EW_TRY(ws.alloc(&ws.q_dev, (size_t)(4 * 256) * 256));
-    EW_TRY(ws.alloc(&ws.gram_dev, (size_t)kGramBlocks * 32 * 32));
-    EW_HIP_TRY(hipHostMalloc((void**)&ws.h_host, (4 * 256 + 64) * sizeof(double), hipHostMallocDefault));
+    ws.stream = op->stream;
+    ws.g = op->g;
+    ws.order = op->order;
+    EW_TRY(ws.setup(N, m, k));
 
     const ew_op_stats s0 = op->stats;
     int64_t wave_solves = 0, restarts = 0;
@@ -320,79 +366,10 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
                                               " converged pairs");
     }
 
-    // Stage 2: Rayleigh-Ritz of L_h on the locked vectors, G q = mu B q with
-    // G = -Y^T L Y and B = Y^T Y.
-    for (int i = 0; i < nl; ++i) EW_TRY((ew_status)ew_op_apply_laplacian(op, ws.col(ws.Y, i), ws.col(ws.LY, i)));
-    Mat G, B;
-    EW_TRY(full_gram(ws, ws.Y, ws.LY, nl, G));
-    EW_TRY(full_gram(ws, ws.Y, ws.Y, nl, B));
-    Mat Gs(nl, nl), Bs(nl, nl);
-    for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-            Gs(i, j) = -0.5 * (G(i, j) + G(j, i));
-            Bs(i, j) = 0.5 * (B(i, j) + B(j, i));
-        }
-    Mat Lc;
-    if (!cholesky(Bs, Lc)) return fail(EW_ERR_NONFINITE, "locked vectors are not linearly independent");
-    Mat Li = lower_inverse(Lc);
-    Mat C(nl, nl);
-    for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-            double s = 0.0;
-            for (int a = 0; a <= i; ++a)
-                for (int b = 0; b <= j; ++b) s += Li(i, a) * Gs(a, b) * Li(j, b);
-            C(i, j) = s;
-        }
-    std::vector<double> mu;
-    Mat Zc;
-    jacobi_eigh(C, mu, Zc);
-    Mat Qr(nl, nl);  // Q = Li^T Zc
-    for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-            double s = 0.0;
-            for (int a = i; a < nl; ++a) s += Li(a, i) * Zc(a, j);
-            Qr(i, j) = s;
-        }
-    // beta of each Rayleigh-Ritz vector: theta averaged with weights Q^2
-    std::vector<double> beta(nl);
-    for (int j = 0; j < nl; ++j) {
-        double num = 0.0, den = 0.0;
-        for (int i = 0; i < nl; ++i) {
-            num += th_locked[i] * Qr(i, j) * Qr(i, j);
-            den += Qr(i, j) * Qr(i, j);
-        }
-        beta[j] = num / den;
-    }
-    EW_TRY(rotate(ws, ws.Y, nl, Qr, nl, ws.Z));
-    std::vector<double> res(nl), znorm(nl);
-    for (int j = 0; j < nl; ++j) {
-        // L z_j into the (no longer needed) L Y buffer, then ||L z + mu z||.
-        EW_TRY((ew_status)ew_op_apply_laplacian(op, ws.col(ws.Z, j), ws.col(ws.LY, j)));
-        EW_HIP_TRY(launch_eig_residual(ws.col(ws.LY, j), ws.col(ws.Z, j), mu[j], N, ws.P, op->stream));
-        EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.P, 2 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, op->stream));
-        EW_HIP_TRY(hipStreamSynchronize(op->stream));
-        double r2 = 0.0, z2 = 0.0;
-        for (int b = 0; b < kRedBlocks; ++b) r2 += ws.h_host[b];
-        for (int b = 0; b < kRedBlocks; ++b) z2 += ws.h_host[kRedBlocks + b];
-        znorm[j] = std::sqrt(z2);
-        res[j] = std::sqrt(r2) / (std::fabs(mu[j]) * znorm[j]);
-    }
-    std::vector<int> order = order_by_abs_desc(beta);
-    int n_conv = 0;
-    for (int j = 0; j < nl; ++j) n_conv += res[j] <= desc->tol_res;
-    const int n_ret = std::min(nl, k_cap);
+    int n_conv = 0, n_ret = 0;
     double max_res = 0.0;
-    for (int r = 0; r < n_ret; ++r) {
-        const int j = order[r];
-        mu_host[r] = mu[j];
-        beta_host[r] = beta[j];
-        res_host[r] = res[j];
-        max_res = std::max(max_res, res[j]);
-        if (Y_dev) {
-            EW_HIP_TRY(launch_scale_copy<double>(Y_dev + (int64_t)r * N, ws.col(ws.Z, j), N, 1.0 / znorm[j], op->stream));
-        }
-    }
-    EW_HIP_TRY(hipStreamSynchronize(op->stream));
+    EW_TRY(stage2(ws, nl, th_locked, desc->tol_res, k_cap, mu_host, beta_host, res_host, Y_dev, &n_conv, &n_ret,
+                  &max_res));
     if (stats) {
         stats->n_conv = n_conv;
         stats->n_returned = n_ret;

@@ -31,6 +31,16 @@ struct Profiler {
     bool wants(int kc, int lv) const { return kc == kclass && (level < 0 || level == lv) && used + 2 <= 2 * kMaxLaunches; }
 };
 
+// Time step, step count and filter weights of one wave-solve (computed in
+// FP64 on the host, in the order of operations of the definition).
+struct TimePlan {
+    double omega_used = 0, t_final = 0, dt = 0, alpha_d = 0;
+    int n_t = 0;
+    std::vector<double> c;
+};
+void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp);
+ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d);
+
 struct Op;
 // Brackets one launch with events when the profiler asks for it.
 struct ProfScope {

@@ -37,33 +37,43 @@ Geo make_geo(int dim, const int64_t* n, const double* h) {
 // trapezoid weights sigma_0 = sigma_{N_t} = dt/2, dt otherwise, and
 // shift = alpha_d/2 = tan(omega dt/2) / tan(omega dt) / 2 or 1/4.
 // ---------------------------------------------------------------------------
-static void make_plan(Op* op) {
-    const ew_op_desc& d = op->desc;
+void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp) {
     double om = d.omega;
     if (d.adjust_omega) {
         const double s = std::sin(M_PI / d.n_its);
         const double s2 = s * s;
         om = d.omega * M_PI / d.n_its * std::sqrt((1.0 - 2.0 * s2) / s2);
     }
-    op->omega_used = om;
-    op->t_final = d.n_p * 2.0 * M_PI / om;
+    tp.omega_used = om;
+    tp.t_final = d.n_p * 2.0 * M_PI / om;
     if (d.ts == EW_TS_IMPLICIT) {
-        op->n_t = d.n_p * d.n_its;
+        tp.n_t = d.n_p * d.n_its;
     } else {
-        const double c = op->order == 2 ? 4.0 : 16.0 / 3.0;
+        const double c = order == 2 ? 4.0 : 16.0 / 3.0;
         double rho = 0.0;
-        for (int k = 0; k < op->dim; ++k) rho += c / (op->h[k] * op->h[k]);
+        for (int k = 0; k < dim; ++k) rho += c / (h[k] * h[k]);
         const double dt_max = 2.0 / std::sqrt(rho);
-        op->n_t = (int)std::ceil(op->t_final / (d.cfl * dt_max));
+        tp.n_t = (int)std::ceil(tp.t_final / (d.cfl * dt_max));
     }
-    op->dt = op->t_final / op->n_t;
-    op->alpha_d = std::tan(om * op->dt / 2.0) / std::tan(om * op->dt);
-    const double shift = d.filter_const == EW_FILTER_ALPHA_D ? op->alpha_d / 2.0 : 0.25;
-    op->c.resize(op->n_t + 1);
-    for (int k = 0; k <= op->n_t; ++k) {
-        const double sigma = (k == 0 || k == op->n_t) ? op->dt / 2.0 : op->dt;
-        op->c[k] = (2.0 / op->t_final) * sigma * (std::cos(om * k * op->dt) - shift);
+    tp.dt = tp.t_final / tp.n_t;
+    tp.alpha_d = std::tan(om * tp.dt / 2.0) / std::tan(om * tp.dt);
+    const double shift = d.filter_const == EW_FILTER_ALPHA_D ? tp.alpha_d / 2.0 : 0.25;
+    tp.c.resize(tp.n_t + 1);
+    for (int k = 0; k <= tp.n_t; ++k) {
+        const double sigma = (k == 0 || k == tp.n_t) ? tp.dt / 2.0 : tp.dt;
+        tp.c[k] = (2.0 / tp.t_final) * sigma * (std::cos(om * k * tp.dt) - shift);
     }
+}
+
+static void make_plan(Op* op) {
+    TimePlan tp;
+    make_time_plan(op->dim, op->order, op->h, op->desc, tp);
+    op->omega_used = tp.omega_used;
+    op->t_final = tp.t_final;
+    op->n_t = tp.n_t;
+    op->dt = tp.dt;
+    op->alpha_d = tp.alpha_d;
+    op->c = tp.c;
 }
 
 Op::~Op() {
@@ -119,7 +129,7 @@ ew_status Op::host_sum_partials(double* out) {
     return EW_OK;
 }
 
-static ew_status validate(const ew_grid_desc* g, const ew_op_desc* d) {
+ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
     if (!g || !d) return fail(EW_ERR_INVALID_ARG, "null descriptor");
     if (g->dim != 2 && g->dim != 3) return fail(EW_ERR_INVALID_ARG, "dim must be 2 or 3");
     if (g->order != 2 && g->order != 4) return fail(EW_ERR_INVALID_ARG, "order must be 2 or 4");
@@ -236,7 +246,7 @@ using namespace ew;
 extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* hip_stream, ew_op* out) {
     if (!out) return fail(EW_ERR_INVALID_ARG, "out is null");
     *out = nullptr;
-    EW_TRY(validate(grid, desc));
+    EW_TRY(validate_descs(grid, desc));
     std::unique_ptr<ew_op_s> op(new ew_op_s());
     op->dim = grid->dim;
     op->order = grid->order;
