@@ -88,6 +88,88 @@ def cpu_baseline(P, n_solves: int):
                       f"exact DST solves instead of multigrid), {dt:.1f} s"}
 
 
+BATCH_TOL_RITZ = 1e-5   # above the FP32 noise of S v (N_t up to ~1200 steps)
+BATCH_TOL_RES = 5e-3    # eigen-residual both forms are judged at (FP32 state floor ~2e-3)
+
+
+def batched_vs_plain(budget: int):
+    """96 independent rectangles (sides U[0.5,2], n^2 grids with n U[65,1025],
+    omega U[10,80], order 2, explicit CFL 0.5, FP32 state, FP64 Arnoldi, k = 4,
+    m = 16): one batched eigensolve against 96 standalone ones, same budget of
+    wave-solves per problem, pairs counted at eig-res <= BATCH_TOL_RES."""
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Batch, Operator
+    Ps = synthetic.batch_problems()
+    bt = Batch([{"n": P.n, "length": P.length, "order": 2, "omega": P.omega, "cfl": 0.5} for P in Ps])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, st = bt.eigs(k=4, m=16, seeds=[P.seed for P in Ps], tol_ritz=BATCH_TOL_RITZ, tol_res=BATCH_TOL_RES,
+                      max_wave_solves=budget, raise_on_error=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    nb = sum(sum(1 for x in r["res"] if x <= BATCH_TOL_RES) for r in res)
+    info = bt.info
+    bt.close()
+    log(f"batched: {nb} pairs in {tb:.2f} s")
+    t0 = time.perf_counter()
+    npl, wsp, ptp = 0, 0, 0
+    for P in Ps:
+        op = Operator(n=P.n, length=P.length, order=2, omega=P.omega, ts="explicit", cfl=0.5, precision="mixed")
+        r = op.eigs(4, 16, seed=P.seed, tol_ritz=BATCH_TOL_RITZ, tol_res=BATCH_TOL_RES, max_wave_solves=budget,
+                    want_vectors=False, raise_on_error=False)
+        npl += sum(1 for x in r.res if x <= BATCH_TOL_RES)
+        wsp += r.wave_solves
+        ptp += r.pt_updates
+        op.close()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    log(f"plain: {npl} pairs in {tp:.2f} s")
+    return {"workload": "96 Dirichlet rectangles, sides U[0.5,2], n^2 grids n U[65,1025], omega U[10,80], order 2, "
+                        "explicit CFL 0.5, FP32 state + FP64 Arnoldi, k=4, m=16",
+            "budget_wave_solves_per_problem": budget, "eig_res_tol": BATCH_TOL_RES,
+            "batched": {"eigenpairs_per_s": nb / tb, "pairs": nb, "seconds": tb, "wave_solves": st["wave_solves"],
+                        "pt_updates_per_s": st["pt_updates"] / tb, "small_problems": info["n_small"],
+                        "step_rows_per_thread": info["step_rows_per_thread"], "tune_us": info["tune_us"]},
+            "plain": {"eigenpairs_per_s": npl / tp, "pairs": npl, "seconds": tp, "wave_solves": wsp,
+                      "pt_updates_per_s": ptp / tp},
+            "speedup_eigenpairs_per_s": (nb / tb) / (npl / tp) if npl > 0 else None}
+
+
+def mixed_cube():
+    """255^3 cube, order 2, implicit 10 steps/period, omega 40: mixed precision
+    (FP32 inner multigrid + FP64 defect correction, FP32 filter accumulation)
+    against FP64, two wave-solves each from the same start vector."""
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Operator, fill_uniform
+    P = synthetic.config_cube_mixed()
+    out = {"workload": "unit cube 257^3 points (255^3 interior), order 2, implicit 10 steps/period, omega 40 "
+                       "(adjusted), multigrid to 1e-10"}
+    Sv = {}
+    for prec in ("mixed", "fp64"):
+        op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its,
+                      adjust_omega=True, precision=prec, mg_tol=P.mg_tol)
+        v = fill_uniform(op.n_active, P.seed)
+        w = op.apply_filter(v)  # warm
+        torch.cuda.synchronize()
+        op.reset_stats()
+        t0 = time.perf_counter()
+        w = op.apply_filter(v)
+        w2 = op.apply_filter(w)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = op.stats()
+        Sv[prec] = w2
+        out[prec] = {"pt_updates_per_s": st["pt_updates"] / dt, "ms_per_wave_solve": dt / 2 * 1e3,
+                     "mg_cycles_per_implicit_solve": st["mg_cycles"] / max(1, st["mg_solves"])}
+        op.close()
+    d = (Sv["mixed"] - Sv["fp64"]).abs().max().item() / Sv["fp64"].abs().max().item()
+    out["mixed_vs_fp64_rel_err_S2v"] = d
+    out["speedup"] = out["mixed"]["pt_updates_per_s"] / out["fp64"]["pt_updates_per_s"]
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +177,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-solves", type=int, default=4)
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and mixed-precision comparisons")
+    ap.add_argument("--batch-budget", type=int, default=150, help="wave-solves per problem in the batch comparison")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU decomposition is "
@@ -153,6 +237,11 @@ def main(argv=None) -> int:
            "workload": "unit square 64^2 interior (h = 1/65), order 2, explicit leapfrog CFL 0.5 (78 steps), "
                        "omega 15, Krylov dimension 16, 4 requested, seed 1"}
 
+    forms = {}
+    if not a.no_forms:
+        forms["batched_vs_plain"] = batched_vs_plain(a.batch_budget)
+        forms["mixed_cube"] = mixed_cube()
+
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -170,6 +259,7 @@ def main(argv=None) -> int:
         "eigenpairs_per_s": eig,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
     return 0
