@@ -1,0 +1,149 @@
+"""The small convolutional network used as the initial guess of each implicit
+solve, in FP64: forward, loss and backward.
+
+Test infrastructure only (see ``oracle/__init__``).  This network is not in
+the paper; it is this project's learned warm start, defined here:
+
+* input planes (4): W^n / s, W^{n-1} / s, and two constant planes
+  c2 = a w^2 / (1 + a w^2) and c3 = min(a / h^2, 100) / 100 that tell the
+  network which step it is looking at (a = dt^2/2, w the frequency used in the
+  filter, h the grid spacing); s is the RMS of W^n over the grid;
+* conv 3x3, 4 -> 16 channels, bias, ReLU; conv 3x3, 16 -> 16, bias, ReLU;
+  conv 3x3, 16 -> 1, bias; zero values outside the domain (the Dirichlet wall);
+* output y is a correction to the scaled guess: the initial guess of the
+  solve of M S = 2 W^n is  S0 = 2 W^n / (1 + a w^2) + s y,  and the training
+  target is y* = (S - 2 W^n / (1 + a w^2)) / s with S the converged solution;
+* loss = mean over the output pixels of (y - y*)^2.
+
+Parameters are one flat vector in the order W1[16][4][3][3], b1[16],
+W2[16][16][3][3], b2[16], W3[1][16][3][3], b3[1] (3057 values); a kernel
+index [o][i][ky][kx] multiplies the input at offset (ky - 1, kx - 1).
+Convolutions here are "valid" (an input of size H+6 gives an output of size H)
+so that a crop carrying a three-cell halo reproduces the whole-grid network
+exactly on its interior.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SHAPES = [("W1", (16, 4, 3, 3)), ("b1", (16,)), ("W2", (16, 16, 3, 3)), ("b2", (16,)),
+          ("W3", (1, 16, 3, 3)), ("b3", (1,))]
+N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def unpack(theta: np.ndarray) -> dict:
+    out, off = {}, 0
+    for name, shape in SHAPES:
+        n = int(np.prod(shape))
+        out[name] = theta[off:off + n].reshape(shape)
+        off += n
+    return out
+
+
+def pack(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[name], dtype=np.float64).ravel() for name, _ in SHAPES])
+
+
+def init_params(seed_values: np.ndarray) -> np.ndarray:
+    """He-style initialisation from given uniform[-1,1) draws (one per parameter):
+    weight ~ u * sqrt(6 / fan_in), biases zero."""
+    theta = np.zeros(N_PARAMS)
+    off = 0
+    for name, shape in SHAPES:
+        n = int(np.prod(shape))
+        if name.startswith("W"):
+            fan_in = shape[1] * 9
+            theta[off:off + n] = seed_values[off:off + n] * np.sqrt(6.0 / fan_in)
+        off += n
+    return theta
+
+
+def conv_valid(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """out[o, p, q] = b[o] + sum_{i,ky,kx} w[o,i,ky,kx] x[i, p+ky, q+kx]."""
+    C, H, W = x.shape
+    O = w.shape[0]
+    out = np.zeros((O, H - 2, W - 2))
+    for ky in range(3):
+        for kx in range(3):
+            out += np.einsum("oi,ipq->opq", w[:, :, ky, kx], x[:, ky:ky + H - 2, kx:kx + W - 2])
+    return out + b[:, None, None]
+
+
+def forward(theta: np.ndarray, x: np.ndarray):
+    """x: (4, H+6, W+6) -> y (H, W) and the cache for backward."""
+    p = unpack(theta)
+    z1 = conv_valid(x, p["W1"], p["b1"])
+    a1 = np.maximum(z1, 0.0)
+    z2 = conv_valid(a1, p["W2"], p["b2"])
+    a2 = np.maximum(z2, 0.0)
+    y = conv_valid(a2, p["W3"], p["b3"])[0]
+    return y, (x, z1, a1, z2, a2)
+
+
+def conv_valid_backward(x: np.ndarray, w: np.ndarray, dout: np.ndarray):
+    """Gradients of conv_valid with respect to w, b and x."""
+    C, H, W = x.shape
+    dw = np.zeros_like(w)
+    dx = np.zeros_like(x)
+    for ky in range(3):
+        for kx in range(3):
+            xs = x[:, ky:ky + H - 2, kx:kx + W - 2]
+            dw[:, :, ky, kx] = np.einsum("opq,ipq->oi", dout, xs)
+            dx[:, ky:ky + H - 2, kx:kx + W - 2] += np.einsum("oi,opq->ipq", w[:, :, ky, kx], dout)
+    db = dout.sum(axis=(1, 2))
+    return dw, db, dx
+
+
+def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
+    """Mean squared error of y against target and its gradient (backpropagation)."""
+    y, (x, z1, a1, z2, a2) = forward(theta, x)
+    npix = y.size
+    r = y - target
+    loss = float(np.sum(r * r) / npix)
+    dy = (2.0 / npix) * r
+    p = unpack(theta)
+    dW3, db3, da2 = conv_valid_backward(a2, p["W3"], dy[None])
+    dz2 = da2 * (z2 > 0)
+    dW2, db2, da1 = conv_valid_backward(a1, p["W2"], dz2)
+    dz1 = da1 * (z1 > 0)
+    dW1, db1, _ = conv_valid_backward(x, p["W1"], dz1)
+    grad = pack({"W1": dW1, "b1": db1, "W2": dW2, "b2": db2, "W3": dW3, "b3": db3})
+    return loss, grad
+
+
+def step_planes(a: float, omega: float, h: float):
+    """The two constant input planes of one implicit step."""
+    c2 = a * omega * omega / (1.0 + a * omega * omega)
+    c3 = min(a / (h * h), 100.0) / 100.0
+    return c2, c3
+
+
+def make_input(wn: np.ndarray, wprev: np.ndarray, s: float, c2: float, c3: float, halo: int = 3) -> np.ndarray:
+    """Network input over the whole grid with `halo` zero cells outside the walls."""
+    H, W = wn.shape
+    x = np.zeros((4, H + 2 * halo, W + 2 * halo))
+    x[0, halo:halo + H, halo:halo + W] = wn / s
+    x[1, halo:halo + H, halo:halo + W] = wprev / s
+    # the constant planes are zero outside the domain, like the fields
+    x[2, halo:halo + H, halo:halo + W] = c2
+    x[3, halo:halo + H, halo:halo + W] = c3
+    return x
+
+
+def predict_guess(theta: np.ndarray, wn: np.ndarray, wprev: np.ndarray, a: float, omega: float, h: float):
+    """Initial guess S0 = 2 W^n / (1 + a w^2) + s y for the solve of M S = 2 W^n."""
+    s = float(np.sqrt(np.mean(wn * wn)))
+    if s == 0.0:
+        return np.zeros_like(wn)
+    c2, c3 = step_planes(a, omega, h)
+    y, _ = forward(theta, make_input(wn, wprev, s, c2, c3))
+    return 2.0 * wn / (1.0 + a * omega * omega) + s * y
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to the nearest bfloat16 (ties to even), returned as FP64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)

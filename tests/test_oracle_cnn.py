@@ -1,0 +1,146 @@
+"""Pins of the FP64 network oracle (oracle/cnn.py) against things other than
+itself: scipy's 2D correlation for the forward pass, central finite
+differences for every parameter of the backward pass, crop/whole-grid
+consistency of the valid convolutions, and torch's bfloat16 rounding."""
+import numpy as np
+import pytest
+import scipy.signal
+import torch
+
+import synthetic
+from oracle import cnn as C
+
+
+def _theta(seed, scale=1.0):
+    u = synthetic.uniform_pm1(seed, C.N_PARAMS)
+    th = C.init_params(u) * scale
+    # non-zero biases so that their gradients are exercised
+    b = synthetic.uniform_pm1(seed + 1, C.N_PARAMS) * 0.1
+    p = C.unpack(th.copy())
+    for name in ("b1", "b2", "b3"):
+        n = p[name].size
+        p[name][...] = b[:n]
+    return C.pack(p)
+
+
+def _input(seed, h, w):
+    return synthetic.uniform_pm1(seed, 4 * (h + 6) * (w + 6)).reshape(4, h + 6, w + 6)
+
+
+def _forward_scipy(theta, x):
+    """The same network written with scipy.signal.correlate2d, channel by channel."""
+    p = C.unpack(theta)
+
+    def layer(inp, w, b, relu):
+        out = []
+        for o in range(w.shape[0]):
+            acc = np.full((inp.shape[1] - 2, inp.shape[2] - 2), b[o])
+            for i in range(w.shape[1]):
+                acc = acc + scipy.signal.correlate2d(inp[i], w[o, i], mode="valid")
+            out.append(np.maximum(acc, 0.0) if relu else acc)
+        return np.array(out)
+
+    a1 = layer(x, p["W1"], p["b1"], True)
+    a2 = layer(a1, p["W2"], p["b2"], True)
+    return layer(a2, p["W3"], p["b3"], False)[0]
+
+
+def test_param_count_and_layout():
+    assert C.N_PARAMS == 16 * 4 * 9 + 16 + 16 * 16 * 9 + 16 + 16 * 9 + 1 == 3057
+    th = np.arange(C.N_PARAMS, dtype=np.float64)
+    assert np.array_equal(C.pack(C.unpack(th)), th)
+    p = C.unpack(th)
+    assert p["W1"][0, 0, 0, 1] == 1 and p["b1"][0] == 576 and p["W2"][0, 0, 0, 0] == 592
+    assert p["b3"][0] == C.N_PARAMS - 1
+
+
+@pytest.mark.parametrize("hw", [(5, 7), (12, 9)])
+def test_forward_matches_scipy_correlate(hw):
+    th = _theta(11)
+    x = _input(21, *hw)
+    y, _ = C.forward(th, x)
+    assert y.shape == hw
+    ref = _forward_scipy(th, x)
+    assert np.max(np.abs(y - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_single_tap_kernel_is_a_shift():
+    """A network whose only non-zero weights pick input channel 0 at tap
+    (ky, kx) in each layer returns that channel shifted by the summed offsets
+    (inputs kept positive so that ReLU is the identity)."""
+    p = C.unpack(np.zeros(C.N_PARAMS))
+    p["W1"][0, 0, 2, 0] = 1.0   # offset (+1, -1)
+    p["W2"][0, 0, 1, 2] = 1.0   # offset (0, +1)
+    p["W3"][0, 0, 0, 0] = 1.0   # offset (-1, -1)
+    th = C.pack(p)
+    h, w = 6, 5
+    x = np.zeros((4, h + 6, w + 6))
+    x[0] = 1.0 + np.arange((h + 6) * (w + 6)).reshape(h + 6, w + 6)
+    y, _ = C.forward(th, x)
+    # output (p, q) reads input (p + 3 + dy, q + 3 + dx) with dy = 0, dx = -1
+    assert np.array_equal(y, x[0, 3:3 + h, 2:2 + w])
+
+
+def test_gradient_matches_central_differences_all_parameters():
+    th = _theta(31)
+    x = _input(41, 4, 5)
+    t = synthetic.uniform_pm1(51, 20).reshape(4, 5)
+    loss, g = C.loss_and_grad(th, x, t)
+    eps = 1e-6
+    fd = np.zeros(C.N_PARAMS)
+    for i in range(C.N_PARAMS):
+        tp = th.copy()
+        tp[i] += eps
+        tm = th.copy()
+        tm[i] -= eps
+        lp = np.mean((C.forward(tp, x)[0] - t) ** 2)
+        lm = np.mean((C.forward(tm, x)[0] - t) ** 2)
+        fd[i] = (lp - lm) / (2 * eps)
+    assert loss == pytest.approx(np.mean((C.forward(th, x)[0] - t) ** 2), rel=1e-14)
+    err = np.abs(fd - g)
+    assert np.max(err) <= 1e-6 * max(1.0, np.max(np.abs(g))), np.argmax(err)
+    # every layer's weights and biases actually receive gradient
+    p = C.unpack(g)
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert np.max(np.abs(p[name])) > 0, name
+
+
+def test_crop_with_halo_reproduces_whole_grid_output():
+    """Valid convolutions: a crop that carries three extra cells on each side
+    gives exactly the whole-grid output on its interior."""
+    th = _theta(61)
+    h, w = 20, 17
+    x = _input(71, h, w)
+    y, _ = C.forward(th, x)
+    r0, c0, hh, ww = 5, 3, 9, 11
+    yc, _ = C.forward(th, x[:, r0:r0 + hh + 6, c0:c0 + ww + 6])
+    assert np.array_equal(yc, y[r0:r0 + hh, c0:c0 + ww])
+
+
+def test_guess_residual_form():
+    """With W3 = 0 and b3 = 0 the guess is the scaled guess 2 W^n / (1 + a w^2);
+    with the exact target added it is the solution itself."""
+    th = _theta(81)
+    p = C.unpack(th.copy())
+    p["W3"][...] = 0.0
+    p["b3"][...] = 0.0
+    th0 = C.pack(p)
+    wn = synthetic.uniform_pm1(91, 12 * 10).reshape(12, 10)
+    wp = synthetic.uniform_pm1(92, 12 * 10).reshape(12, 10)
+    a, om, h = 2e-4, 30.0, 1.0 / 11
+    g = C.predict_guess(th0, wn, wp, a, om, h)
+    assert np.allclose(g, 2 * wn / (1 + a * om * om), rtol=0, atol=1e-15)
+    assert np.all(C.predict_guess(th, np.zeros_like(wn), wp, a, om, h) == 0.0)
+    c2, c3 = C.step_planes(a, om, h)
+    assert c2 == pytest.approx(a * om * om / (1 + a * om * om)) and 0 < c3 <= 1
+    x = C.make_input(wn, wp, 2.0, c2, c3)
+    assert x.shape == (4, 18, 16)
+    assert np.all(x[:, :3] == 0) and np.all(x[:, :, -3:] == 0)
+    assert np.all(x[2, 3:-3, 3:-3] == c2) and np.array_equal(x[0, 3:-3, 3:-3], wn / 2.0)
+
+
+def test_round_bf16_matches_torch():
+    v = np.concatenate([synthetic.uniform_pm1(101, 4000) * 10.0 ** np.arange(-20, 20, 0.01),
+                        [0.0, 1.0, -1.0, 1.00390625, 1.01171875, 3.0e38, 1e-40]])
+    ref = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(C.round_bf16(v), ref)
