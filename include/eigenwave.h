@@ -50,7 +50,7 @@ typedef enum {
 enum { EW_TS_EXPLICIT = 0, EW_TS_IMPLICIT = 1 };
 enum { EW_FILTER_ALPHA_D = 0, EW_FILTER_QUARTER = 1 };
 enum { EW_PREC_FP64 = 0, EW_PREC_MIXED = 1 };
-enum { EW_PRED_ZERO = 0, EW_PRED_SCALED = 1, EW_PRED_CNN = 2 };
+enum { EW_PRED_ZERO = 0, EW_PRED_SCALED = 1, EW_PRED_CNN = 2, EW_PRED_EXTRAP = 3 };
 
 typedef struct ew_op_s* ew_op;
 
@@ -98,7 +98,14 @@ typedef struct {
  *   predictor          initial guess of each implicit solve: EW_PRED_ZERO, or
  *                      EW_PRED_SCALED (x0 = b / (1 + a omega^2), exact for
  *                      every mode with lambda = omega since M phi = (1 + a mu) phi), or
- *                      EW_PRED_CNN (needs ew_op_set_cnn). */
+ *                      EW_PRED_CNN (the learned guess of ew_cnn_*, 2D only;
+ *                      needs ew_op_set_cnn, else it behaves as SCALED), or
+ *                      EW_PRED_EXTRAP (linear extrapolation in time,
+ *                      W^{n+1} ~ 2 W^n - W^{n-1}, i.e. x0 = b).  The first
+ *                      step of a wave-solve has no W^{n-1}: CNN uses SCALED
+ *                      there.  Whatever the guess, the multigrid iterates to
+ *                      mg_tol, so results agree with the zero guess to that
+ *                      tolerance. */
 typedef struct {
     double omega;
     int ts;
@@ -136,6 +143,7 @@ typedef struct {
     int64_t mg_solves;        /* implicit solves */
     int64_t mg_cycles;        /* V-cycles over all implicit solves */
     int64_t laplacian_applies;
+    int64_t cnn_guesses;      /* initial guesses made by the network */
 } ew_op_stats;
 
 /* Create an operator on the current device.  The filter weights c_n, dt and
@@ -288,6 +296,102 @@ ew_status ew_batch_apply_filter(ew_batch b, const double* const* v_dev, double* 
  * Host-blocking.  EW_ERR_NOT_CONVERGED if any problem hit its budget. */
 ew_status ew_batch_eigs(ew_batch b, const ew_eigs_desc* descs, int k_cap, double* mu_host, double* beta_host,
                         double* res_host, int* n_conv_host, double* const* Y_dev, ew_eigs_stats* stats);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start for the implicit solves (not part of the paper's method:
+ * a small network proposes the initial guess of each M S = 2 W^n solve; the
+ * multigrid still iterates to mg_tol, so a poor guess costs cycles, never
+ * accuracy).
+ *
+ * Network (3057 parameters, FP32 master copy, BF16 in the products with FP32
+ * accumulation): input planes W^n/s, W^{n-1}/s, c2 = a w^2/(1 + a w^2) and
+ * c3 = min(a/h^2, 100)/100 (a = dt^2/2, w = omega_used, h the spacing of the
+ * first axis, s = RMS of W^n over the grid; every plane is zero outside the
+ * grid); 3x3 convolution 4->16, bias, ReLU; 3x3 16->16, bias, ReLU; 3x3 16->1,
+ * bias.  Output y gives the guess S0 = 2 W^n / (1 + a w^2) + s y.  Parameter
+ * vector order: W1[16][4][3][3], b1[16], W2[16][16][3][3], b2[16],
+ * W3[1][16][3][3], b3[1]; W[o][i][ky][kx] multiplies the input at row offset
+ * ky-1 and column offset kx-1.
+ *
+ * Training data are crops: an output window of crop x crop points (crop a
+ * multiple of 16, 16..256) of the target (S - 2 W^n/(1 + a w^2))/s, with the
+ * two field planes over the window plus 3 points on every side (zero outside
+ * the grid), and per crop c2, c3 and the rectangle of the padded window that
+ * lies inside the grid.  Loss: mean over all output points of the batch of
+ * (y - target)^2.  Training: Adam (Kingma and Ba) on minibatches drawn with
+ * replacement by SplitMix64.
+ * ------------------------------------------------------------------------ */
+#define EW_CNN_PARAMS 3057
+#define EW_CNN_HALO 3
+
+typedef struct ew_cnn_s* ew_cnn;
+typedef struct ew_cnn_data_s* ew_cnn_data;
+
+/* New network on the current device; weights drawn He-uniform from the
+ * SplitMix64 stream `seed` (parameter i uses draw i: W = u sqrt(6/fan_in),
+ * fan_in = 9 x input channels; biases 0).  Work is ordered on hip_stream.
+ * Host-blocking. */
+ew_status ew_cnn_create(uint64_t seed, void* hip_stream, ew_cnn* out);
+void ew_cnn_destroy(ew_cnn cnn);
+/* Copy EW_CNN_PARAMS FP32 parameters in or out (host arrays); set_params also
+ * resets the optimiser state.  Host-blocking. */
+ew_status ew_cnn_set_params(ew_cnn cnn, const float* params_host);
+ew_status ew_cnn_get_params(ew_cnn cnn, float* params_host);
+
+/* Crop store with room for `capacity` crops of crop x crop outputs. */
+ew_status ew_cnn_data_create(int capacity, int crop, ew_cnn_data* out);
+void ew_cnn_data_destroy(ew_cnn_data d);
+ew_status ew_cnn_data_count(ew_cnn_data d, int* count);
+/* Append n caller-made crops: fields_dev [n][2][crop+6][crop+6] FP32
+ * (W^n/s then W^{n-1}/s), target_dev [n][crop][crop] FP32, planes_host [n][2]
+ * (c2, c3) and rect_host [n][4] (row0, row1, col0, col1: the half-open
+ * rectangle of the padded window inside the grid).  Host-blocking. */
+ew_status ew_cnn_data_append(ew_cnn_data d, int n, const float* fields_dev, const float* target_dev,
+                             const float* planes_host, const int* rect_host);
+/* Copy crops first..first+count-1 out, in the layout of ew_cnn_data_append
+ * (any of the four outputs may be NULL).  Host-blocking. */
+ew_status ew_cnn_data_read(ew_cnn_data d, int first, int count, float* fields_dev, float* target_dev,
+                           float* planes_host, int* rect_host);
+/* out_dev = S v_dev computed by the implicit FP64 2D operator `op` (as
+ * ew_op_apply_filter), recording crops_per_step crops at each step n >= 1
+ * (from the solve of M S = 2 W^n) until the store is full.  Window origins are
+ * drawn from the SplitMix64 stream `seed` (successive calls continue it);
+ * one eighth of the origin range on each side is clamped to the walls so that
+ * walls are sampled.  The grid needs n[0], n[1] >= crop.  Host-blocking. */
+ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* v_dev, double* out_dev, int crops_per_step,
+                              uint64_t seed);
+
+/* y_dev [count][crop][crop] FP32 = network output on crops first..first+count-1. */
+ew_status ew_cnn_forward(ew_cnn cnn, ew_cnn_data d, int first, int count, float* y_dev);
+/* Loss over crops first..first+count-1 (host, may be NULL) and its gradient
+ * with respect to the parameters (grad_dev, EW_CNN_PARAMS FP32, device).
+ * Host-blocking. */
+ew_status ew_cnn_loss_grad(ew_cnn cnn, ew_cnn_data d, int first, int count, double* loss_host, float* grad_dev);
+
+typedef struct {
+    int steps;        /* Adam steps */
+    int batch;        /* crops per step */
+    double lr;        /* step size */
+    double beta1, beta2, eps;
+    uint64_t seed;    /* SplitMix64 stream of the minibatch draws */
+} ew_cnn_train_desc;
+
+typedef struct {
+    int steps;
+    double first_loss, last_loss;  /* minibatch loss of the first and last step */
+    double seconds;
+} ew_cnn_train_stats;
+
+/* steps Adam updates (step t uses m_t/(1-beta1^t) and v_t/(1-beta2^t)),
+ * continuing the optimiser state of earlier calls.  Host-blocking. */
+ew_status ew_cnn_train(ew_cnn cnn, ew_cnn_data d, const ew_cnn_train_desc* desc, ew_cnn_train_stats* stats);
+
+/* Attach (cnn != NULL) or detach the network used by EW_PRED_CNN.  The
+ * network is not owned and must outlive its use by op. */
+ew_status ew_op_set_cnn(ew_op op, ew_cnn cnn);
+/* guess_dev = the network's initial guess for M S = 2 wn_dev given W^{n-1} =
+ * wprev_dev (implicit 2D operator with a network attached).  Stream-ordered. */
+ew_status ew_op_cnn_guess(ew_op op, const double* wn_dev, const double* wprev_dev, double* guess_dev);
 
 /* Fill x_dev (n FP64, device) with SplitMix64 uniform[-1,1) values of stream
  * `seed`: element i is 2*((z_i >> 11) * 2^-53) - 1 with z_i the SplitMix64

@@ -147,3 +147,14 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
     lsb = (u >> np.uint64(16)) & np.uint64(1)
     u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def adam_step(theta: np.ndarray, m: np.ndarray, v: np.ndarray, g: np.ndarray, t: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba, 2015), step number t >= 1: moment
+    estimates, their bias corrections 1/(1 - beta^t), and the scaled step."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -14,7 +14,8 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import EigenwaveError, check, load
 
-__all__ = ["Operator", "Batch", "EigsResult", "fill_uniform", "EigenwaveError", "load", "version"]
+__all__ = ["Operator", "Batch", "EigsResult", "Cnn", "CropStore", "fill_uniform", "EigenwaveError", "load",
+           "version"]
 
 
 def _torch():
@@ -161,6 +162,17 @@ class Operator:
                                             int(colour)))
         return x
 
+    def set_cnn(self, cnn: Optional["Cnn"]) -> None:
+        """Attach the network used by predictor="cnn" (kept alive by this object)."""
+        check(self._lib.ew_op_set_cnn(self._h, cnn._h if cnn is not None else None))
+        self._cnn = cnn
+
+    def cnn_guess(self, wn, wprev, out=None):
+        out = self._new() if out is None else out
+        check(self._lib.ew_op_cnn_guess(self._h, _dev_ptr(wn, self.n_active), _dev_ptr(wprev, self.n_active),
+                                        _dev_ptr(out, self.n_active)))
+        return out
+
     def eigs(self, k: int, m: int, tol_ritz: float = 1e-12, tol_res: float = 1e-8,
              max_wave_solves: int = 100000, seed: int = 1, v0=None, n_keep: int = 0, max_probes: int = 16,
              k_cap: Optional[int] = None, want_vectors: bool = True, raise_on_error: bool = True) -> EigsResult:
@@ -270,6 +282,17 @@ class Batch:
         check(self._lib.ew_batch_apply_filter(self._h, V, O))
         return outs
 
+    def set_cnn(self, cnn: Optional["Cnn"]) -> None:
+        """Attach the network used by predictor="cnn" (kept alive by this object)."""
+        check(self._lib.ew_op_set_cnn(self._h, cnn._h if cnn is not None else None))
+        self._cnn = cnn
+
+    def cnn_guess(self, wn, wprev, out=None):
+        out = self._new() if out is None else out
+        check(self._lib.ew_op_cnn_guess(self._h, _dev_ptr(wn, self.n_active), _dev_ptr(wprev, self.n_active),
+                                        _dev_ptr(out, self.n_active)))
+        return out
+
     def eigs(self, k: int, m: int, tol_ritz: float = 1e-12, tol_res: float = 1e-8, max_wave_solves: int = 100000,
              seeds=None, n_keep: int = 0, max_probes: int = 16, k_cap: Optional[int] = None,
              want_vectors: bool = False, raise_on_error: bool = True):
@@ -317,3 +340,128 @@ def fill_uniform(n: int, seed: int, stream=None):
     check(load().ew_fill_uniform(ctypes.c_void_p(int(x.data_ptr())), int(n), int(seed),
                                  ctypes.c_void_p(_stream_handle(stream))))
     return x
+
+
+def _f32_ptr(t, n: int) -> int:
+    torch = _torch()
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.numel() < n:
+        raise ValueError("expected a contiguous float32 CUDA tensor with at least %d elements" % n)
+    return int(t.data_ptr())
+
+
+class Cnn:
+    """The learned warm-start network (see ew_cnn_create)."""
+
+    n_params = _lib.CNN_PARAMS
+
+    def __init__(self, seed: int = 0, stream=None):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        check(self._lib.ew_cnn_create(int(seed), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(self._h)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ew_cnn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        buf = (ctypes.c_float * self.n_params)()
+        check(self._lib.ew_cnn_get_params(self._h, buf))
+        return np.frombuffer(buf, dtype=np.float32).copy()
+
+    def set_params(self, params) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError("expected %d parameters" % self.n_params)
+        check(self._lib.ew_cnn_set_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def forward(self, store: "CropStore", first: int, count: int, out=None):
+        torch = _torch()
+        n = count * store.crop * store.crop
+        out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+        check(self._lib.ew_cnn_forward(self._h, store._h, int(first), int(count), _f32_ptr(out, n)))
+        return out.view(count, store.crop, store.crop)
+
+    def loss_grad(self, store: "CropStore", first: int, count: int):
+        torch = _torch()
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        check(self._lib.ew_cnn_loss_grad(self._h, store._h, int(first), int(count), ctypes.byref(loss),
+                                         _f32_ptr(g, self.n_params)))
+        return float(loss.value), g
+
+    def train(self, store: "CropStore", steps: int, batch: int, lr: float = 1e-3, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, seed: int = 0) -> dict:
+        d = _lib.CnnTrainDesc(int(steps), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(seed))
+        st = _lib.CnnTrainStats()
+        check(self._lib.ew_cnn_train(self._h, store._h, ctypes.byref(d), ctypes.byref(st)))
+        return {"steps": int(st.steps), "first_loss": float(st.first_loss), "last_loss": float(st.last_loss),
+                "seconds": float(st.seconds)}
+
+
+class CropStore:
+    """Training crops for the network (see ew_cnn_data_create)."""
+
+    def __init__(self, capacity: int, crop: int = 128):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        check(self._lib.ew_cnn_data_create(int(capacity), int(crop), ctypes.byref(self._h)))
+        self.capacity = int(capacity)
+        self.crop = int(crop)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ew_cnn_data_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def count(self) -> int:
+        c = ctypes.c_int()
+        check(self._lib.ew_cnn_data_count(self._h, ctypes.byref(c)))
+        return int(c.value)
+
+    def append(self, fields, target, planes, rects) -> None:
+        import numpy as np
+        n = len(planes)
+        cp = self.crop + 2 * _lib.CNN_HALO
+        pl = np.ascontiguousarray(planes, dtype=np.float32).reshape(n, 2)
+        rc = np.ascontiguousarray(rects, dtype=np.int32).reshape(n, 4)
+        check(self._lib.ew_cnn_data_append(self._h, n, _f32_ptr(fields, n * 2 * cp * cp),
+                                           _f32_ptr(target, n * self.crop * self.crop),
+                                           pl.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                           rc.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+
+    def read(self, first: int, count: int):
+        """(fields, target, planes, rects) of crops first..first+count-1; tensors on the device."""
+        import numpy as np
+        torch = _torch()
+        cp = self.crop + 2 * _lib.CNN_HALO
+        fields = torch.empty((count, 2, cp, cp), dtype=torch.float32, device="cuda")
+        target = torch.empty((count, self.crop, self.crop), dtype=torch.float32, device="cuda")
+        planes = np.zeros((count, 2), dtype=np.float32)
+        rects = np.zeros((count, 4), dtype=np.int32)
+        check(self._lib.ew_cnn_data_read(self._h, int(first), int(count), int(fields.data_ptr()),
+                                         int(target.data_ptr()), planes.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         rects.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return fields, target, planes, rects
+
+    def collect(self, op: Operator, v, out=None, crops_per_step: int = 4, seed: int = 0):
+        """out = S v by op (implicit FP64 2D) while recording crops at every step."""
+        out = op._new() if out is None else out
+        check(self._lib.ew_cnn_data_collect(self._h, op._h, _dev_ptr(v, op.n_active), _dev_ptr(out, op.n_active),
+                                            int(crops_per_step), int(seed)))
+        return out

@@ -17,7 +17,9 @@ STATUS_NAMES = {
 TS = {"explicit": 0, "implicit": 1}
 FILTER = {"alpha_d": 0, "quarter": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
-PREDICTOR = {"zero": 0, "scaled": 1, "cnn": 2}
+PREDICTOR = {"zero": 0, "scaled": 1, "cnn": 2, "extrap": 3}
+CNN_PARAMS = 3057
+CNN_HALO = 3
 
 
 class GridDesc(ctypes.Structure):
@@ -38,7 +40,8 @@ class OpInfo(ctypes.Structure):
 
 class OpStats(ctypes.Structure):
     _fields_ = [("wave_solves", c_int64), ("time_steps", c_int64), ("pt_updates", c_int64),
-                ("mg_solves", c_int64), ("mg_cycles", c_int64), ("laplacian_applies", c_int64)]
+                ("mg_solves", c_int64), ("mg_cycles", c_int64), ("laplacian_applies", c_int64),
+                ("cnn_guesses", c_int64)]
 
 
 class EigsDesc(ctypes.Structure):
@@ -67,6 +70,15 @@ class BatchInfo(ctypes.Structure):
                 ("pt_updates_per_wave_solve", c_int64)]
 
 
+class CnnTrainDesc(ctypes.Structure):
+    _fields_ = [("steps", c_int), ("batch", c_int), ("lr", c_double), ("beta1", c_double), ("beta2", c_double),
+                ("eps", c_double), ("seed", c_uint64)]
+
+
+class CnnTrainStats(ctypes.Structure):
+    _fields_ = [("steps", c_int), ("first_loss", c_double), ("last_loss", c_double), ("seconds", c_double)]
+
+
 # name -> (restype, argtypes); every symbol include/eigenwave.h declares.
 SIGNATURES = {
     "ew_op_create": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
@@ -90,6 +102,22 @@ SIGNATURES = {
     "ew_batch_apply_filter": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),
     "ew_batch_eigs": (c_int, [c_void_p, POINTER(EigsDesc), c_int, POINTER(c_double), POINTER(c_double),
                               POINTER(c_double), POINTER(c_int), POINTER(c_void_p), POINTER(EigsStats)]),
+    "ew_cnn_create": (c_int, [c_uint64, c_void_p, POINTER(c_void_p)]),
+    "ew_cnn_destroy": (None, [c_void_p]),
+    "ew_cnn_set_params": (c_int, [c_void_p, POINTER(ctypes.c_float)]),
+    "ew_cnn_get_params": (c_int, [c_void_p, POINTER(ctypes.c_float)]),
+    "ew_cnn_data_create": (c_int, [c_int, c_int, POINTER(c_void_p)]),
+    "ew_cnn_data_destroy": (None, [c_void_p]),
+    "ew_cnn_data_count": (c_int, [c_void_p, POINTER(c_int)]),
+    "ew_cnn_data_append": (c_int, [c_void_p, c_int, c_void_p, c_void_p, POINTER(ctypes.c_float), POINTER(c_int)]),
+    "ew_cnn_data_read": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, POINTER(ctypes.c_float),
+                                 POINTER(c_int)]),
+    "ew_cnn_data_collect": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_uint64]),
+    "ew_cnn_forward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    "ew_cnn_loss_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, POINTER(c_double), c_void_p]),
+    "ew_cnn_train": (c_int, [c_void_p, c_void_p, POINTER(CnnTrainDesc), POINTER(CnnTrainStats)]),
+    "ew_op_set_cnn": (c_int, [c_void_p, c_void_p]),
+    "ew_op_cnn_guess": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ew_fill_uniform": (c_int, [c_void_p, c_int64, c_uint64, c_void_p]),
     "ew_last_error": (c_char_p, []),
     "ew_version": (c_char_p, []),

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <array>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -84,6 +85,13 @@ struct Op {
     int last_cycles = 0;       // V-cycles of the previous implicit solve
     std::vector<void*> allocations;
     Cnn* cnn = nullptr;
+    // ||b||^2 already known for the right-hand side b_src of the next solve
+    // (the learned guess computes it); consumed by that solve.
+    const double* bb_src = nullptr;
+    double bb_val = 0.0;
+    // Called after every implicit solve M S = 2 W^n of a wave-solve with
+    // (W^n, W^{n-1}, S); used to record training crops.
+    std::function<ew_status(const double*, const double*, const double*)> step_hook;
     ew_op_stats stats{};
     Profiler prof;
 
@@ -100,6 +108,7 @@ struct Op {
     ew_status mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel,
                          bool speculate = false);
     ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);
+    ew_status rhs_norm2(const double* b, double* bb);
     ew_status implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess);
     ew_status apply_filter(const double* v, double* out);
 };

@@ -159,7 +159,8 @@ ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
         if (d->mg_coarse_sweeps < 1 || d->mg_coarse_sweeps > 10000)
             return fail(EW_ERR_INVALID_ARG, "mg_coarse_sweeps must be in [1, 10000]");
         if (d->mg_coarse_points < 0) return fail(EW_ERR_INVALID_ARG, "mg_coarse_points must be >= 0");
-        if (d->predictor != EW_PRED_ZERO && d->predictor != EW_PRED_SCALED && d->predictor != EW_PRED_CNN)
+        if (d->predictor != EW_PRED_ZERO && d->predictor != EW_PRED_SCALED && d->predictor != EW_PRED_CNN &&
+            d->predictor != EW_PRED_EXTRAP)
             return fail(EW_ERR_INVALID_ARG, "unknown predictor");
         if (d->predictor == EW_PRED_CNN && (g->dim != 2))
             return fail(EW_ERR_UNSUPPORTED, "the learned predictor is implemented for 2D grids");

@@ -83,11 +83,21 @@ static ew_status check_rel(double rel) {
 // the residual test, which costs a pass over x and b and a host round trip;
 // the test then runs after every further cycle, so the solve still stops at
 // the first tested cycle that meets the tolerance.
+ew_status Op::rhs_norm2(const double* b, double* bb) {
+    if (bb_src == b) {
+        *bb = bb_val;
+        bb_src = nullptr;
+        return EW_OK;
+    }
+    bb_src = nullptr;
+    EW_HIP_TRY(launch_dot_partial(b, b, N, partial_dev, stream));
+    return host_sum_partials(bb);
+}
+
 ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel_out,
                          bool speculate) {
-    EW_HIP_TRY(launch_dot_partial(b, b, N, partial_dev, stream));
     double bb = 0.0;
-    EW_TRY(host_sum_partials(&bb));
+    EW_TRY(rhs_norm2(b, &bb));
     const double bn = std::sqrt(bb) * std::fabs(bscale);
     if (!std::isfinite(bn)) return fail(EW_ERR_NONFINITE, "non-finite right-hand side");
     int cyc = 0;
@@ -141,9 +151,8 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
 // FP32 V-cycle from zero and updates x += e in FP64.
 ew_status Op::mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles,
                              double* rel_out) {
-    EW_HIP_TRY(launch_dot_partial(b, b, N, partial_dev, stream));
     double bb = 0.0;
-    EW_TRY(host_sum_partials(&bb));
+    EW_TRY(rhs_norm2(b, &bb));
     const double bn = std::sqrt(bb) * std::fabs(bscale);
     if (!std::isfinite(bn)) return fail(EW_ERR_NONFINITE, "non-finite right-hand side");
     if (x_is_zero) EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
@@ -187,6 +196,9 @@ ew_status Op::implicit_solve(const double* b, double bscale, double* x, const do
     bool zero = false;
     if (desc.predictor == EW_PRED_ZERO) {
         zero = true;
+    } else if (desc.predictor == EW_PRED_EXTRAP) {
+        // W^{n+1} ~ 2 W^n - W^{n-1} gives S = W^{n+1} + W^{n-1} ~ 2 W^n (and W^1 ~ W^0).
+        EW_HIP_TRY(launch_scale_copy<double>(x, b, N, bscale, stream));
     } else if (desc.predictor == EW_PRED_SCALED || wprev_for_guess == nullptr || cnn == nullptr) {
         // M phi = (1 + a mu) phi: exact for every mode at mu = omega^2.
         const double s = bscale / (1.0 + a * omega_used * omega_used);
@@ -239,6 +251,7 @@ ew_status Op::apply_filter(const double* v, double* out) {
         double* cur = wA;
         for (int k = 1; k < n_t; ++k) {
             EW_TRY(implicit_solve(cur, 2.0, sbuf, prev));
+            if (step_hook) EW_TRY(step_hook(cur, prev, sbuf));
             double* next = (prev == v) ? wB : const_cast<double*>(prev);
             ProfScope ps(this, EW_K_UPDATE, 0, (mixed ? 32.0 : 40.0) * (double)N);
             if (mixed)

@@ -144,3 +144,19 @@ def test_round_bf16_matches_torch():
                         [0.0, 1.0, -1.0, 1.00390625, 1.01171875, 3.0e38, 1e-40]])
     ref = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(C.round_bf16(v), ref)
+
+
+def test_adam_first_step_and_constant_gradient():
+    """Adam's first step from zero moments is -lr g / (|g| + eps) (the bias
+    corrections cancel the (1 - beta) factors); under a constant gradient
+    every later step has the same size."""
+    g = synthetic.uniform_pm1(111, 50)
+    th0 = synthetic.uniform_pm1(112, 50)
+    lr, eps = 1e-3, 1e-8
+    th1, m, v = C.adam_step(th0, np.zeros(50), np.zeros(50), g, 1, lr, eps=eps)
+    assert np.allclose(th1, th0 - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    th = th1
+    for t in range(2, 6):
+        th_new, m, v = C.adam_step(th, m, v, g, t, lr, eps=eps)
+        assert np.allclose(th_new - th, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-18)
+        th = th_new
