@@ -50,7 +50,7 @@ typedef enum {
 enum { EW_TS_EXPLICIT = 0, EW_TS_IMPLICIT = 1 };
 enum { EW_FILTER_ALPHA_D = 0, EW_FILTER_QUARTER = 1 };
 enum { EW_PREC_FP64 = 0, EW_PREC_MIXED = 1 };
-enum { EW_PRED_ZERO = 0, EW_PRED_SCALED = 1, EW_PRED_CNN = 2, EW_PRED_EXTRAP = 3 };
+enum { EW_PRED_ZERO = 0, EW_PRED_SCALED = 1, EW_PRED_CNN = 2, EW_PRED_EXTRAP = 3, EW_PRED_PROJ = 4 };
 
 typedef struct ew_op_s* ew_op;
 
@@ -98,14 +98,22 @@ typedef struct {
  *   predictor          initial guess of each implicit solve: EW_PRED_ZERO, or
  *                      EW_PRED_SCALED (x0 = b / (1 + a omega^2), exact for
  *                      every mode with lambda = omega since M phi = (1 + a mu) phi), or
- *                      EW_PRED_CNN (the learned guess of ew_cnn_*, 2D only;
- *                      needs ew_op_set_cnn, else it behaves as SCALED), or
  *                      EW_PRED_EXTRAP (linear extrapolation in time,
- *                      W^{n+1} ~ 2 W^n - W^{n-1}, i.e. x0 = b).  The first
- *                      step of a wave-solve has no W^{n-1}: CNN uses SCALED
- *                      there.  Whatever the guess, the multigrid iterates to
- *                      mg_tol, so results agree with the zero guess to that
- *                      tolerance. */
+ *                      W^{n+1} ~ 2 W^n - W^{n-1}, i.e. x0 = b), or
+ *                      EW_PRED_PROJ (projection on earlier solves: x0 is the
+ *                      combination of the last proj_window solutions x_k
+ *                      (M x_k = b_k, kept in FP32 across wave-solves) that is
+ *                      closest to the new solution in the M-norm, found from
+ *                      the Gram matrix x_i . b_j and the products x_k . b;
+ *                      P. F. Fischer's method for successive right-hand
+ *                      sides), or EW_PRED_CNN (the PROJ guess, or zero with
+ *                      proj_window < 0, corrected by the learned network of
+ *                      ew_cnn_*; 2D only; needs ew_op_set_cnn, else it is
+ *                      that base guess).  Whatever the guess, the multigrid
+ *                      iterates to mg_tol, so results agree with the zero
+ *                      guess to that tolerance.
+ *   proj_window        solves kept for PROJ and CNN: 0 = 24, at most 32,
+ *                      negative = none. */
 typedef struct {
     double omega;
     int ts;
@@ -122,6 +130,7 @@ typedef struct {
     int mg_coarse_sweeps;
     int mg_coarse_points;
     int predictor;
+    int proj_window;
 } ew_op_desc;
 
 /* Read-only facts about an operator. */

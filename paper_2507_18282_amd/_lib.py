@@ -17,7 +17,7 @@ STATUS_NAMES = {
 TS = {"explicit": 0, "implicit": 1}
 FILTER = {"alpha_d": 0, "quarter": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
-PREDICTOR = {"zero": 0, "scaled": 1, "cnn": 2, "extrap": 3}
+PREDICTOR = {"zero": 0, "scaled": 1, "cnn": 2, "extrap": 3, "proj": 4}
 CNN_PARAMS = 3057
 CNN_HALO = 3
 
@@ -30,7 +30,7 @@ class OpDesc(ctypes.Structure):
     _fields_ = [("omega", c_double), ("ts", c_int), ("cfl", c_double), ("n_its", c_int), ("n_p", c_int),
                 ("adjust_omega", c_int), ("filter_const", c_int), ("precision", c_int), ("mg_tol", c_double),
                 ("mg_nu1", c_int), ("mg_nu2", c_int), ("mg_max_cycles", c_int), ("mg_coarse_sweeps", c_int),
-                ("mg_coarse_points", c_int), ("predictor", c_int)]
+                ("mg_coarse_points", c_int), ("predictor", c_int), ("proj_window", c_int)]
 
 
 class OpInfo(ctypes.Structure):

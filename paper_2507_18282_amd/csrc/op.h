@@ -21,6 +21,9 @@ struct Level {
 
 struct Cnn;  // learned warm start (cnn.hip)
 
+constexpr int kProjMax = 32;     // largest projection window
+constexpr int kProjBlocks = 1024; // reduction blocks of the projection kernels
+
 // hipEvent timing of one kernel class (ew_op_profile_*).
 struct Profiler {
     int kclass = -1, level = -1;
@@ -92,6 +95,21 @@ struct Op {
     // Called after every implicit solve M S = 2 W^n of a wave-solve with
     // (W^n, W^{n-1}, S); used to record training crops.
     std::function<ew_status(const double*, const double*, const double*)> step_hook;
+    // Projection guess (proj.hip): FP32 copies of the last proj_k solutions
+    // and right-hand sides in a ring of slots, and their Gram matrix
+    // G[s][t] = x_s . b_t on the host (row-major, kProjMax x kProjMax).
+    int proj_k = 0;            // window size (0 = projection off)
+    int proj_count = 0;        // filled slots
+    int proj_head = 0;         // slot the next pair goes to
+    bool proj_pending = false; // Gram row of the last added pair still on the device
+    int proj_pending_slot = -1;
+    float* proj_X = nullptr;
+    float* proj_B = nullptr;
+    double* proj_partial = nullptr;  // kProjBlocks x (kProjMax + 1) per result set
+    double* proj_res_dev = nullptr;  // 2 x (kProjMax + 1): products with b, Gram row of the last pair
+    double* proj_res_host = nullptr;
+    std::vector<double> proj_G;
+    int64_t proj_guesses = 0;
     ew_op_stats stats{};
     Profiler prof;
 
@@ -109,6 +127,9 @@ struct Op {
                          bool speculate = false);
     ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);
     ew_status rhs_norm2(const double* b, double* bb);
+    ew_status proj_setup();
+    ew_status proj_guess(const double* b, double bscale, double* x, bool* x_is_zero);
+    ew_status proj_add(const double* b, double bscale, const double* x);
     ew_status implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess);
     ew_status apply_filter(const double* v, double* out);
 };

@@ -79,6 +79,7 @@ static void make_plan(Op* op) {
 Op::~Op() {
     for (void* p : allocations) hipFree(p);
     if (partial_host) hipHostFree(partial_host);
+    if (proj_res_host) hipHostFree(proj_res_host);
     for (hipEvent_t e : prof.pool) hipEventDestroy(e);
 }
 
@@ -160,8 +161,9 @@ ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
             return fail(EW_ERR_INVALID_ARG, "mg_coarse_sweeps must be in [1, 10000]");
         if (d->mg_coarse_points < 0) return fail(EW_ERR_INVALID_ARG, "mg_coarse_points must be >= 0");
         if (d->predictor != EW_PRED_ZERO && d->predictor != EW_PRED_SCALED && d->predictor != EW_PRED_CNN &&
-            d->predictor != EW_PRED_EXTRAP)
+            d->predictor != EW_PRED_EXTRAP && d->predictor != EW_PRED_PROJ)
             return fail(EW_ERR_INVALID_ARG, "unknown predictor");
+        if (d->proj_window > 32) return fail(EW_ERR_INVALID_ARG, "proj_window must be at most 32");
         if (d->predictor == EW_PRED_CNN && (g->dim != 2))
             return fail(EW_ERR_UNSUPPORTED, "the learned predictor is implemented for 2D grids");
     }
@@ -274,6 +276,7 @@ extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* de
     if (op->implicit) {
         EW_TRY(op->alloc((void**)&op->sbuf, N * sizeof(double)));
         EW_TRY(op->build_hierarchy());
+        EW_TRY(op->proj_setup());
         if (op->mixed) {
             EW_TRY(op->alloc((void**)&op->acc32, N * sizeof(float)));
         }

@@ -194,6 +194,12 @@ ew_status cnn_predict(Op* op, const double* wcur, const double* wprev, double* g
 // One implicit solve M x = bscale b with the operator's initial-guess rule.
 ew_status Op::implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess) {
     bool zero = false;
+    if (desc.predictor == EW_PRED_PROJ || (desc.predictor == EW_PRED_CNN && proj_k > 0 && cnn == nullptr)) {
+        EW_TRY(proj_guess(b, bscale, x, &zero));
+        if (mixed) EW_TRY(mg_solve_mixed(b, bscale, x, zero, nullptr, nullptr));
+        else EW_TRY(mg_solve64(b, bscale, x, zero, nullptr, nullptr, true));
+        return proj_add(b, bscale, x);
+    }
     if (desc.predictor == EW_PRED_ZERO) {
         zero = true;
     } else if (desc.predictor == EW_PRED_EXTRAP) {

@@ -286,7 +286,7 @@ def test_training_lowers_loss_and_is_deterministic():
     assert runs[0][0]["last_loss"] == runs[1][0]["last_loss"]
 
 
-@pytest.mark.parametrize("predictor", ["cnn", "scaled", "extrap"])
+@pytest.mark.parametrize("predictor", ["cnn", "scaled", "extrap", "proj"])
 def test_warm_started_eigenpairs_equal_cold_start(predictor):
     """Whatever the initial guess (here an untrained network), multigrid runs
     to the same tolerance, so the eigenpairs agree with the cold start and with
