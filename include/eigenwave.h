@@ -113,7 +113,13 @@ typedef struct {
  *                      iterates to mg_tol, so results agree with the zero
  *                      guess to that tolerance.
  *   proj_window        solves kept for PROJ and CNN: 0 = 24, at most 32,
- *                      negative = none. */
+ *                      negative = none.
+ *   mg_max_levels      implicit only: most multigrid levels (the finest
+ *                      counts as one); 0 = coarsen while every n_d is odd
+ *                      and >= 3.  A truncated hierarchy ends on a level that
+ *                      gets mg_coarse_sweeps sweeps, which solve it well when
+ *                      (dt^2/2)/h_coarse^2 is small (M is then strongly
+ *                      diagonally dominant). */
 typedef struct {
     double omega;
     int ts;
@@ -131,6 +137,7 @@ typedef struct {
     int mg_coarse_points;
     int predictor;
     int proj_window;
+    int mg_max_levels;
 } ew_op_desc;
 
 /* Read-only facts about an operator. */

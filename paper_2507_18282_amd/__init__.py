@@ -64,7 +64,8 @@ class Operator:
                  cfl: float = 0.5, n_its: int = 10, n_p: int = 1, adjust_omega: bool = False,
                  filter_const: str = "alpha_d", precision: str = "fp64", mg_tol: float = 1e-10,
                  mg_nu1: int = 2, mg_nu2: int = 1, mg_max_cycles: int = 100, mg_coarse_sweeps: int = 8,
-                 mg_coarse_points: int = 0, predictor: str = "zero", proj_window: int = 0, stream=None):
+                 mg_coarse_points: int = 0, predictor: str = "zero", proj_window: int = 0,
+                 mg_max_levels: int = 0, stream=None):
         lib = load()
         self._lib = lib
         g = _lib.GridDesc()
@@ -90,6 +91,7 @@ class Operator:
         d.mg_coarse_points = int(mg_coarse_points)
         d.predictor = _lib.PREDICTOR[predictor]
         d.proj_window = int(proj_window)
+        d.mg_max_levels = int(mg_max_levels)
         self._stream = stream
         self._h = ctypes.c_void_p()
         check(lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)),
@@ -217,7 +219,7 @@ def _grid_desc(n, length, order):
 
 def _op_desc(omega, ts, cfl=0.5, n_its=10, n_p=1, adjust_omega=False, filter_const="alpha_d", precision="fp64",
              mg_tol=1e-10, mg_nu1=2, mg_nu2=1, mg_max_cycles=100, mg_coarse_sweeps=8, mg_coarse_points=0,
-             predictor="zero", proj_window=0):
+             predictor="zero", proj_window=0, mg_max_levels=0):
     d = _lib.OpDesc()
     d.omega, d.ts, d.cfl, d.n_its, d.n_p = float(omega), _lib.TS[ts], float(cfl), int(n_its), int(n_p)
     d.adjust_omega, d.filter_const = int(bool(adjust_omega)), _lib.FILTER[filter_const]
@@ -226,6 +228,7 @@ def _op_desc(omega, ts, cfl=0.5, n_its=10, n_p=1, adjust_omega=False, filter_con
     d.mg_coarse_sweeps, d.mg_coarse_points, d.predictor = int(mg_coarse_sweeps), int(mg_coarse_points), \
         _lib.PREDICTOR[predictor]
     d.proj_window = int(proj_window)
+    d.mg_max_levels = int(mg_max_levels)
     return d
 
 

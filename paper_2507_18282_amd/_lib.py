@@ -30,7 +30,8 @@ class OpDesc(ctypes.Structure):
     _fields_ = [("omega", c_double), ("ts", c_int), ("cfl", c_double), ("n_its", c_int), ("n_p", c_int),
                 ("adjust_omega", c_int), ("filter_const", c_int), ("precision", c_int), ("mg_tol", c_double),
                 ("mg_nu1", c_int), ("mg_nu2", c_int), ("mg_max_cycles", c_int), ("mg_coarse_sweeps", c_int),
-                ("mg_coarse_points", c_int), ("predictor", c_int), ("proj_window", c_int)]
+                ("mg_coarse_points", c_int), ("predictor", c_int), ("proj_window", c_int),
+                ("mg_max_levels", c_int)]
 
 
 class OpInfo(ctypes.Structure):

@@ -96,19 +96,21 @@ struct Op {
     // (W^n, W^{n-1}, S); used to record training crops.
     std::function<ew_status(const double*, const double*, const double*)> step_hook;
     // Projection guess (proj.hip): FP32 copies of the last proj_k solutions
-    // and right-hand sides in a ring of slots, and their Gram matrix
-    // G[s][t] = x_s . b_t on the host (row-major, kProjMax x kProjMax).
+    // in a ring of slots, and their Gram matrix G[s][t] = x_s . b_t on the
+    // host (row-major, kProjMax x kProjMax).
     int proj_k = 0;            // window size (0 = projection off)
     int proj_count = 0;        // filled slots
     int proj_head = 0;         // slot the next pair goes to
     bool proj_pending = false; // Gram row of the last added pair still on the device
     int proj_pending_slot = -1;
-    float* proj_X = nullptr;
-    float* proj_B = nullptr;
+    bool proj_rhs_ok = false;  // proj_c holds the products for the solve in progress
+    float* proj_X = nullptr;       // proj_k rows of proj_ld floats
+    int64_t proj_ld = 0;
     double* proj_partial = nullptr;  // kProjBlocks x (kProjMax + 1) per result set
     double* proj_res_dev = nullptr;  // 2 x (kProjMax + 1): products with b, Gram row of the last pair
     double* proj_res_host = nullptr;
     std::vector<double> proj_G;
+    std::vector<double> proj_c;   // x_v . (bscale b) for the solve in progress
     int64_t proj_guesses = 0;
     ew_op_stats stats{};
     Profiler prof;

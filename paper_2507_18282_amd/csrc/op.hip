@@ -164,6 +164,7 @@ ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
             d->predictor != EW_PRED_EXTRAP && d->predictor != EW_PRED_PROJ)
             return fail(EW_ERR_INVALID_ARG, "unknown predictor");
         if (d->proj_window > 32) return fail(EW_ERR_INVALID_ARG, "proj_window must be at most 32");
+        if (d->mg_max_levels < 0) return fail(EW_ERR_INVALID_ARG, "mg_max_levels must be >= 0");
         if (d->predictor == EW_PRED_CNN && (g->dim != 2))
             return fail(EW_ERR_UNSUPPORTED, "the learned predictor is implemented for 2D grids");
     }
@@ -175,7 +176,8 @@ ew_status Op::build_hierarchy() {
     std::vector<std::array<int64_t, 3>> sizes;
     std::array<int64_t, 3> cur = {n[0], n[1], dim == 3 ? n[2] : 1};
     sizes.push_back(cur);
-    while (sizes.size() < 64) {
+    const size_t max_levels = desc.mg_max_levels > 0 ? (size_t)desc.mg_max_levels : 64;
+    while (sizes.size() < max_levels) {
         bool ok = true;
         for (int k = 0; k < dim; ++k) ok = ok && (cur[k] % 2 == 1) && cur[k] >= 3;
         if (!ok) break;

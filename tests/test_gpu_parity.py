@@ -137,6 +137,32 @@ def test_mg_half_sweep_and_vcycle_match_oracle(P, coarse_points):
     assert rel_err(got, want) < 1e-12
 
 
+@pytest.mark.parametrize("max_levels", [2, 3])
+@pytest.mark.parametrize("P", IMPLICIT_CASES[:2] + IMPLICIT_CASES[4:5], ids=lambda P: f"{P.n}-o{P.order}")
+def test_truncated_hierarchy_vcycle_and_solve_match_oracle(P, max_levels):
+    """mg_max_levels stops the coarsening early; the last level then gets
+    mg_coarse_sweeps sweeps, as in the oracle hierarchy with the same limit."""
+    op = make_op(P, mg_max_levels=max_levels)
+    h, plan = oracle_plan(P)
+    a = 0.5 * plan.dt ** 2
+    hier = OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=8,
+                         max_levels=max_levels)
+    assert op.mg_levels == len(hier.sizes) == max_levels
+    shape = P.n[::-1]
+    b = synthetic.uniform_pm1(23, P.n_active)
+    x = synthetic.uniform_pm1(24, P.n_active)
+    say("truncated vcycle", P.n, P.order, max_levels)
+    got = to_host(op.mg_vcycle(to_dev(b), to_dev(x)))
+    want = OMG.vcycle(x.reshape(shape), b.reshape(shape), hier).ravel()
+    assert rel_err(got, want) < 1e-12
+    xd, cycles, rel = op.mg_solve(to_dev(b), to_dev(np.zeros(P.n_active)))
+    xe = W.solve_implicit_exact(b.reshape(shape), h, P.order, plan.dt).ravel()
+    assert rel <= P.mg_tol
+    assert np.linalg.norm(to_host(xd) - xe) <= P.mg_tol * np.linalg.norm(b) * 1.0001
+    _, oc, _ = OMG.solve(b.reshape(shape), hier, P.mg_tol)
+    assert abs(cycles - oc) <= 1
+
+
 @pytest.mark.parametrize("coarse_points", [0, 40])
 @pytest.mark.parametrize("P", IMPLICIT_CASES, ids=lambda P: f"{P.n}-o{P.order}")
 def test_mg_solve_reaches_exact_solution(P, coarse_points):
