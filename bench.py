@@ -38,7 +38,8 @@ LEARN_CROPS = 8640         # 40 chains x 3 wave-solves x 9 steps x 8 crops
 LEARN_STEPS = 2000         # Adam steps (half at 2e-3, half at 5e-4)
 LEARN_OMEGA_SEED = 4242
 LEARN_CROP_SEED = 777
-LEARN_BUDGET = 48          # wave-solves per predictor in the learned-form comparison
+LEARN_BUDGET = 32          # wave-solves per predictor in the learned-form comparison
+LEARN_OMEGAS = (40.0, 90.0, 140.0)
 METRIC = "grid-pt updates/s + eigenpairs/s at resid 1e-8; learned/batched vs plain"
 SMOOTH_SRC = os.path.join(ROOT, "paper_2507_18282_amd", "csrc", "sweep2d.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_square2047_order4.txt")
@@ -159,8 +160,8 @@ def batched_vs_plain(budget: int):
 
 
 def learned_vs_plain():
-    """1023^2 unit square, order 4, implicit 10 steps/period, omega 90 (adjusted),
-    FP64 multigrid to 1e-10, k = 16, m = 32: the eigensolver with the cold start
+    """1023^2 unit square, order 4, implicit 10 steps/period, omega 40, 90, 140
+    (adjusted), FP64 multigrid to 1e-10, k = 16, m = 32: the eigensolver with the cold start
     (zero guess) against the warm starts, LEARN_BUDGET wave-solves each.  Every
     guess leaves the multigrid iterating to the same tolerance, so S, and with
     it the Arnoldi sequence, is the same up to that tolerance (S v for one
@@ -198,35 +199,40 @@ def learned_vs_plain():
     tr2 = net.train(store, steps=LEARN_STEPS // 2, batch=16, lr=5e-4, seed=12)
     log(f"learned: {store.count} crops in {t_data:.2f} s, training {tr1['seconds'] + tr2['seconds']:.2f} s, "
         f"loss {tr1['first_loss']:.4g} -> {tr2['last_loss']:.4g}")
-    out = {"workload": "unit square 1025^2 points (1023^2 interior), order 4, implicit 10 steps/period, omega 90 "
-                       "(adjusted), FP64 multigrid to 1e-10, k=16, m=32, eig-res <= 1e-8",
+    out = {"workload": "unit square 1025^2 points (1023^2 interior), order 4, implicit 10 steps/period, omega "
+                       "40/90/140 (adjusted), FP64 multigrid to 1e-10 (levels 1023^2..63^2), k=16, m=32",
+           "budget_wave_solves": LEARN_BUDGET,
            "data": {"crops": store.count, "crop": 128, "seconds": t_data},
            "training": {"steps": LEARN_STEPS, "batch": 16, "seconds": tr1["seconds"] + tr2["seconds"],
                         "first_loss": tr1["first_loss"], "last_loss": tr2["last_loss"]}}
-    Sv = {}
     v_check = fill_uniform(n * n, 99)
-    for pred in ("zero", "proj", "cnn", "scaled"):
-        op = make(P.omega, pred)
-        if pred == "cnn":
-            op.set_cnn(net)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        r = op.eigs(P.k, P.m, seed=P.seed, tol_res=1e-8, max_wave_solves=LEARN_BUDGET, want_vectors=False,
-                    raise_on_error=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        Sv[pred] = op.apply_filter(v_check)
-        out[pred] = {"ms_per_wave_solve": dt / r.wave_solves * 1e3, "wave_solves": r.wave_solves,
-                     "mg_cycles_per_implicit_solve": r.mg_cycles / max(1, r.time_steps)}
-        log(f"learned form {pred}: {r.wave_solves} wave-solves in {dt:.2f} s, "
-            f"{out[pred]['mg_cycles_per_implicit_solve']:.2f} cycles/solve")
-        op.close()
-    z = out["zero"]
-    for pred in ("proj", "cnn", "scaled"):
-        o = out[pred]
-        o["vcycles_saved_per_implicit_solve"] = z["mg_cycles_per_implicit_solve"] - o["mg_cycles_per_implicit_solve"]
-        o["speedup_eigenpairs_per_s_vs_zero"] = z["ms_per_wave_solve"] / o["ms_per_wave_solve"]
-        o["Sv_rel_diff_vs_zero"] = ((Sv[pred] - Sv["zero"]).abs().max() / Sv["zero"].abs().max()).item()
+    preds = ("zero", "proj", "cnn", "extrap", "scaled")
+    for omega in LEARN_OMEGAS:
+        Sv = {}
+        res = {}
+        for pred in preds:
+            op = make(omega, pred)
+            if pred == "cnn":
+                op.set_cnn(net)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = op.eigs(P.k, P.m, seed=P.seed, tol_res=1e-8, max_wave_solves=LEARN_BUDGET, want_vectors=False,
+                        raise_on_error=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            Sv[pred] = op.apply_filter(v_check)
+            res[pred] = {"ms_per_wave_solve": dt / r.wave_solves * 1e3, "wave_solves": r.wave_solves,
+                         "mg_cycles_per_implicit_solve": r.mg_cycles / max(1, r.time_steps)}
+            log(f"learned form omega {omega} {pred}: {r.wave_solves} wave-solves in {dt:.2f} s, "
+                f"{res[pred]['mg_cycles_per_implicit_solve']:.2f} cycles/solve")
+            op.close()
+        z = res["zero"]
+        for pred in preds[1:]:
+            o = res[pred]
+            o["vcycles_saved_per_implicit_solve"] = z["mg_cycles_per_implicit_solve"] - o["mg_cycles_per_implicit_solve"]
+            o["speedup_eigenpairs_per_s_vs_zero"] = z["ms_per_wave_solve"] / o["ms_per_wave_solve"]
+            o["Sv_rel_diff_vs_zero"] = ((Sv[pred] - Sv["zero"]).abs().max() / Sv["zero"].abs().max()).item()
+        out[f"omega_{omega:g}"] = res
     return out
 
 
