@@ -315,7 +315,7 @@ def main(argv=None) -> int:
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic()
     roofline = {"bound": "hbm",
-                "kernel": "red-black Gauss-Seidel sweep, finest level (k_sweep_tile2d<double, 4, 32, false, false>)",
+                "kernel": "red-black Gauss-Seidel sweep, finest level (k_sweep_tile2d<double, 4, 16, false, false>)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "launches": prof["launches"], "avg_us": round(avg_ms * 1e3, 3),

@@ -183,15 +183,29 @@ __global__ __launch_bounds__(kInferThreads) void k_cnn_infer(const CnnPacked* __
     for (int i = tid; i < 144; i += kInferThreads) w3s[i] = pk->w3[i];
     LaneWeights w;
     load_lane_weights(pk, lane, w);
-    for (int i = tid; i < G::NXP; i += kInferThreads) {
+    // every global load of a thread is issued before the first conversion
+    constexpr int IT = (G::NXP + kInferThreads - 1) / kInferThreads;
+    double v0[IT], v1[IT];
+    bool in[IT];
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const int i = tid + t * kInferThreads;
         const int iy = i / G::XW, ix = i - iy * G::XW;
         const int gy = oy - kCnnHalo + iy, gx = ox - kCnnHalo + ix;
-        u32x2 v = {0u, 0u};
-        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+        in[t] = i < G::NXP && gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+        v0[t] = 0.0;
+        v1[t] = 0.0;
+        if (in[t]) {
             const int64_t idx = (int64_t)gy * nx + gx;
-            v = pack_bf4((float)(wn[idx] * inv_s), (float)(wprev[idx] * inv_s), c2, c3);
+            v0[t] = wn[idx];
+            v1[t] = wprev[idx];
         }
-        xs[i] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const int i = tid + t * kInferThreads;
+        if (i < G::NXP)
+            xs[i] = in[t] ? pack_bf4((float)(v0[t] * inv_s), (float)(v1[t] * inv_s), c2, c3) : u32x2{0u, 0u};
     }
     __syncthreads();
     conv1<G, NW>(xs, a1, w, wave, lane);

@@ -117,24 +117,53 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = (DIM == 3) ? blockIdx.z * TZ : 0;
 
-    // load x (tile + H), zero outside the domain, prolongation folded in
-    for (int q = tid; q < LX * LY * LZ; q += kTileThreads) {
-        const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
-        const int gi = x0 - H + lx, gj = y0 - H + ly, gk = (DIM == 3) ? z0 - H + lz : 0;
+    // Staging of x (tile + H, zero outside the domain) and b (tile + 1): every
+    // global load of a thread is issued into registers before its first LDS
+    // store, so the block waits for memory once.  The prolongation (coarse
+    // values read through the cache) is added afterwards, in LDS.
+    constexpr int NX = LX * LY * LZ, NB = BX * BY * BZ;
+    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IB = (NB + kTileThreads - 1) / kTileThreads;
+    T xv[IX], bv[IB];
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
         T v = T(0);
-        if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) {
-            if (!ZERO_IN) v = xin[lin(g, gi, gj, gk)];
-            if (PROLONG) v += prolong_at<T, DIM>(xc, gc, gi, gj, gk);
+        if (!ZERO_IN && q < NX) {
+            const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
+            const int gi = x0 - H + lx, gj = y0 - H + ly, gk = (DIM == 3) ? z0 - H + lz : 0;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) v = xin[lin(g, gi, gj, gk)];
         }
-        X[q] = v;
+        xv[t] = v;
     }
-    // load b (tile + 1)
-    for (int q = tid; q < BX * BY * BZ; q += kTileThreads) {
-        const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
-        const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
         T v = T(0);
-        if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) v = bscale * b[lin(g, gi, gj, gk)];
-        B[q] = v;
+        if (q < NB) {
+            const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
+            const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) v = b[lin(g, gi, gj, gk)];
+        }
+        bv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NX) X[q] = xv[t];
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NB) B[q] = bscale * bv[t];
+    }
+    if (PROLONG) {
+        // each thread updates only the cells it stored itself: no barrier needed before
+        for (int q = tid; q < NX; q += kTileThreads) {
+            const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
+            const int gi = x0 - H + lx, gj = y0 - H + ly, gk = (DIM == 3) ? z0 - H + lz : 0;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz)
+                X[q] += prolong_at<T, DIM>(xc, gc, gi, gj, gk);
+        }
     }
     __syncthreads();
 
@@ -197,22 +226,50 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
     const int tid = threadIdx.x;
     const int cx0 = blockIdx.x * CX, cy0 = blockIdx.y * CY, cz0 = (DIM == 3) ? blockIdx.z * CZ : 0;
     const int fx0 = 2 * cx0, fy0 = 2 * cy0, fz0 = (DIM == 3) ? 2 * cz0 : 0;  // first fine point of the region
-    for (int q = tid; q < LX * LY * LZ; q += kTileThreads) {
-        const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
-        const int gi = fx0 - R + lx, gj = fy0 - R + ly, gk = (DIM == 3) ? fz0 - R + lz : 0;
+    // Staging as in the sweep: x (region + R) and b (region) go to registers
+    // with every load issued before the first use.
+    constexpr int NX = LX * LY * LZ, NF = FX * FY * FZ;
+    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IF = (NF + kTileThreads - 1) / kTileThreads;
+    T xv[IX], bv[IF];
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
         T v = T(0);
-        if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) v = x[lin(gf, gi, gj, gk)];
-        X[q] = v;
+        if (q < NX) {
+            const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
+            const int gi = fx0 - R + lx, gj = fy0 - R + ly, gk = (DIM == 3) ? fz0 - R + lz : 0;
+            if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) v = x[lin(gf, gi, gj, gk)];
+        }
+        xv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IF; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (q < NF) {
+            const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
+            const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
+            if (gi < gf.nx && gj < gf.ny && gk < gf.nz) v = b[lin(gf, gi, gj, gk)];
+        }
+        bv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NX) X[q] = xv[t];
     }
     __syncthreads();
-    for (int q = tid; q < FX * FY * FZ; q += kTileThreads) {
+#pragma unroll
+    for (int t = 0; t < IF; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q >= NF) continue;
         const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
         const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
         T r = T(0);
         if (gi < gf.nx && gj < gf.ny && gk < gf.nz) {
             const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
             const T uc = X[p];
-            r = bscale * b[lin(gf, gi, gj, gk)] - (uc - a * lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
+            r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
         }
         Rf[q] = r;
     }
@@ -532,6 +589,10 @@ static hipError_t restrict_dispatch(const T* x, const T* b, T bs, const Geo& gf,
     if (DIM == 2 && tall < 1024) {
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + 3) / 4, 1);
         k_restrict_tile<T, ORDER, DIM, 4><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+    } else if (DIM == 2) {
+        // 32 x 8 coarse tiles: half the LDS of 32 x 16, twice the workgroups per CU
+        dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + 7) / 8, 1);
+        k_restrict_tile<T, ORDER, DIM, 8><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
     } else {
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + CY - 1) / CY, DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
         k_restrict_tile<T, ORDER, DIM, CY><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);

@@ -34,40 +34,82 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
     __shared__ T XC[PROLONG ? CYW * CXW : 1];
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    int cx0 = 0, cy0 = 0;
-    if (PROLONG) {
-        cx0 = (x0 - H - 1) >> 1;
-        cy0 = (y0 - H - 1) >> 1;
-        for (int q = tid; q < CYW * CXW; q += kTileThreads) {
+    const int cx0 = PROLONG ? (x0 - H - 1) >> 1 : 0, cy0 = PROLONG ? (y0 - H - 1) >> 1 : 0;
+
+    // Staging: every global load of a thread is issued (into registers) before
+    // its first LDS store, so a block waits for memory once, not once per row.
+    constexpr int NX = LY * LX, NB = BY * BX, NC = PROLONG ? CYW * CXW : 0;
+    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads;
+    constexpr int IB = (NB + kTileThreads - 1) / kTileThreads;
+    constexpr int IC = PROLONG ? (NC + kTileThreads - 1) / kTileThreads : 1;
+    T cv[IC], xv[IX], bv[IB];
+#pragma unroll
+    for (int t = 0; t < IC; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (PROLONG && q < NC) {
             const int cy = q / CXW, cxx = q - cy * CXW;
             const int ic = cx0 + cxx, jc = cy0 + cy;
-            XC[q] = (ic >= 0 && ic < gc.nx && jc >= 0 && jc < gc.ny) ? xc[(int64_t)jc * gc.nx + ic] : T(0);
+            if (ic >= 0 && ic < gc.nx && jc >= 0 && jc < gc.ny) v = xc[(int64_t)jc * gc.nx + ic];
+        }
+        cv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (!ZERO_IN && q < NX) {
+            const int ly = q / LX, lx = q - ly * LX;
+            const int gi = x0 - H + lx, gj = y0 - H + ly;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = xin[(int64_t)gj * g.nx + gi];
+        }
+        xv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (q < NB) {
+            const int by = q / BX, bx = q - by * BX;
+            const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = b[(int64_t)gj * g.nx + gi];
+        }
+        bv[t] = v;  // scaled at the LDS store: no arithmetic on a load in flight
+    }
+    if (PROLONG) {
+#pragma unroll
+        for (int t = 0; t < IC; ++t) {
+            const int q = tid + t * kTileThreads;
+            if (q < NC) XC[q] = cv[t];
         }
         __syncthreads();
     }
-    for (int q = tid; q < LY * LX; q += kTileThreads) {
-        const int ly = q / LX, lx = q - ly * LX;
-        const int gi = x0 - H + lx, gj = y0 - H + ly;
-        T v = T(0);
-        if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
-            if (!ZERO_IN) v = xin[(int64_t)gj * g.nx + gi];
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NX) {
+            T v = xv[t];
             if (PROLONG) {
-                // fine index odd -> coarse (f-1)/2; even -> mean of f/2-1 and f/2
-                const int ia = ((gi - 1) >> 1) - cx0, ib = (gi >> 1) - cx0;
-                const int ja = ((gj - 1) >> 1) - cy0, jb = (gj >> 1) - cy0;
-                const T wia = (gi & 1) ? T(1) : T(0.5), wib = (gi & 1) ? T(0) : T(0.5);
-                const T wja = (gj & 1) ? T(1) : T(0.5), wjb = (gj & 1) ? T(0) : T(0.5);
-                const T rowa = wia * XC[ja * CXW + ia] + wib * XC[ja * CXW + ib];
-                const T rowb = wia * XC[jb * CXW + ia] + wib * XC[jb * CXW + ib];
-                v += wja * rowa + wjb * rowb;
+                const int ly = q / LX, lx = q - ly * LX;
+                const int gi = x0 - H + lx, gj = y0 - H + ly;
+                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
+                    // fine index odd -> coarse (f-1)/2; even -> mean of f/2-1 and f/2
+                    const int ia = ((gi - 1) >> 1) - cx0, ib = (gi >> 1) - cx0;
+                    const int ja = ((gj - 1) >> 1) - cy0, jb = (gj >> 1) - cy0;
+                    const T wia = (gi & 1) ? T(1) : T(0.5), wib = (gi & 1) ? T(0) : T(0.5);
+                    const T wja = (gj & 1) ? T(1) : T(0.5), wjb = (gj & 1) ? T(0) : T(0.5);
+                    const T rowa = wia * XC[ja * CXW + ia] + wib * XC[ja * CXW + ib];
+                    const T rowb = wia * XC[jb * CXW + ia] + wib * XC[jb * CXW + ib];
+                    v += wja * rowa + wjb * rowb;
+                }
             }
+            X[q] = v;
         }
-        X[q] = v;
     }
-    for (int q = tid; q < BY * BX; q += kTileThreads) {
-        const int by = q / BX, bx = q - by * BX;
-        const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
-        B[q] = (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) ? bscale * b[(int64_t)gj * g.nx + gi] : T(0);
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NB) B[q] = bscale * bv[t];
     }
     __syncthreads();
 
@@ -170,11 +212,12 @@ static hipError_t sweep2d_dispatch(const T* xin, const T* xc, const T* b, T bs, 
     const double c0 = ORDER == 2 ? 2.0 : 30.0 / 12.0;
     const T inv = (T)(1.0 / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
     const T aa = (T)a;
-    // tall tiles where there are enough of them to fill the chip, short ones
-    // (less serial work per block) on smaller levels
-    const int64_t tall_tiles = (int64_t)((g.nx + 63) / 64) * ((g.ny + 31) / 32);
-    if (tall_tiles >= 1024)
-        return sweep2d_launch<T, ORDER, 32>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+    // 64 x 16 tiles (22 KB of LDS, 7 workgroups per CU) where there are
+    // enough of them to fill the chip, 64 x 8 (less serial work per block) on
+    // smaller levels; measured faster than 64 x 32 tiles on 2047^2
+    const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
+    if (tiles16 >= 2048)
+        return sweep2d_launch<T, ORDER, 16>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
     return sweep2d_launch<T, ORDER, 8>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
 }
 
