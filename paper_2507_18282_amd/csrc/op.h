@@ -45,6 +45,13 @@ struct TimePlan {
 void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp);
 ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d);
 
+// Whole explicit wave-solve of a small 2D grid in one workgroup (wave_small.hip).
+template <typename T>
+bool wave_small_fits(const Geo& g);
+template <typename T>
+hipError_t launch_wave_small(const double* v, double* out, const Geo& g, int order, double dt2, const double* c_dev,
+                             int n_t, hipStream_t s);
+
 struct Op;
 // Brackets one launch with events when the profiler asks for it.
 struct ProfScope {
@@ -80,6 +87,7 @@ struct Op {
     float* fA = nullptr;
     float* fB = nullptr;
     float* acc32 = nullptr;
+    double* c_dev = nullptr;   // filter weights c_0..c_{N_t} on the device (explicit operators)
     double* partial_dev = nullptr;
     double* partial_host = nullptr;
     std::vector<Level> levels;

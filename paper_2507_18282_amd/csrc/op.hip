@@ -282,7 +282,11 @@ extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* de
         if (op->mixed) {
             EW_TRY(op->alloc((void**)&op->acc32, N * sizeof(float)));
         }
-    } else if (op->mixed) {
+    } else {
+        EW_TRY(op->alloc((void**)&op->c_dev, op->c.size() * sizeof(double)));
+        EW_HIP_TRY(hipMemcpy(op->c_dev, op->c.data(), op->c.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (!op->implicit && op->mixed) {
         EW_TRY(op->alloc((void**)&op->f0, N * sizeof(float)));
         EW_TRY(op->alloc((void**)&op->fA, N * sizeof(float)));
         EW_TRY(op->alloc((void**)&op->fB, N * sizeof(float)));

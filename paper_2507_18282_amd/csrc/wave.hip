@@ -218,7 +218,11 @@ ew_status Op::implicit_solve(const double* b, double bscale, double* x, const do
 
 ew_status Op::apply_filter(const double* v, double* out) {
     const double dt2 = dt * dt;
-    if (!implicit && !mixed) {
+    if (!implicit && (mixed ? wave_small_fits<float>(g) : wave_small_fits<double>(g))) {
+        ProfScope ps(this, EW_K_LEAPFROG, 0, 16.0 * (double)N);
+        EW_HIP_TRY(mixed ? launch_wave_small<float>(v, out, g, order, dt2, c_dev, n_t, stream)
+                         : launch_wave_small<double>(v, out, g, order, dt2, c_dev, n_t, stream));
+    } else if (!implicit && !mixed) {
         {
             ProfScope ps(this, EW_K_LEAPFROG, 0, 24.0 * (double)N);
             EW_HIP_TRY(launch_leapfrog<double>(v, nullptr, wA, out, g, order, dt2, c[0], c[1], 1, stream));

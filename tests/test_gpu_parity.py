@@ -54,6 +54,8 @@ EXPLICIT_CASES = [
                       filter_const="quarter"),
     synthetic.Problem(n=(64, 64), length=(1.0, 1.0), order=2, omega=15.0, ts="explicit", cfl=0.5),
     synthetic.Problem(n=(130, 9), length=(1.3, 0.5), order=4, omega=9.0, ts="explicit", cfl=0.7, n_p=2),
+    # 9000 points: above the single-workgroup wave-solve, through the tiled leapfrog
+    synthetic.Problem(n=(100, 90), length=(1.0, 0.9), order=4, omega=10.0, ts="explicit", cfl=0.5),
     synthetic.Problem(n=(13, 11, 9), length=(1.0, 0.9, 1.1), order=2, omega=8.0, ts="explicit", cfl=0.5),
     synthetic.Problem(n=(13, 11, 9), length=(1.0, 0.9, 1.1), order=4, omega=8.0, ts="explicit", cfl=0.5),
 ]
@@ -84,7 +86,7 @@ def test_explicit_filter_on_sine_mode_is_beta_d():
         assert np.max(np.abs(got - beta * phi)) < 1e-13
 
 
-@pytest.mark.parametrize("P", EXPLICIT_CASES[:3] + EXPLICIT_CASES[4:5], ids=lambda P: f"{P.n}-o{P.order}")
+@pytest.mark.parametrize("P", EXPLICIT_CASES[:5] + EXPLICIT_CASES[5:6], ids=lambda P: f"{P.n}-o{P.order}")
 def test_explicit_filter_mixed_precision(P):
     import dataclasses
     Pm = dataclasses.replace(P, precision="mixed")
