@@ -250,14 +250,15 @@ ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host
  * once at its storage precision.  At most 65536 launches are timed per
  * session.  ew_op_profile_end is host-blocking. */
 enum {
-    EW_K_LEAPFROG = 0,  /* explicit step + filter accumulation */
-    EW_K_SMOOTH = 1,    /* red-black Gauss-Seidel sweep reading the iterate */
+    EW_K_LEAPFROG = 0,  /* explicit step + filter accumulation (a whole wave-solve on small 2D grids) */
+    EW_K_SMOOTH = 1,    /* red-black Gauss-Seidel sweep reading the iterate (on 2D levels a
+                           launch runs two consecutive sweeps from one pass over x and b) */
     EW_K_RESTRICT = 2,  /* residual + full-weighting restriction */
     EW_K_PROLONG = 3,   /* prolongation + correction (fused with the first post-sweep) */
     EW_K_RESNORM = 4,   /* residual norm (convergence test) */
     EW_K_UPDATE = 5,    /* implicit update + filter accumulation */
     EW_K_COARSE = 6,    /* coarse-level V-cycle in one workgroup */
-    EW_K_SMOOTH_ZERO = 7 /* first sweep from a zero iterate (iterate not read) */
+    EW_K_SMOOTH_ZERO = 7 /* first sweep (2D: first two) from a zero iterate (iterate not read) */
 };
 typedef struct {
     int64_t launches;

@@ -39,7 +39,11 @@ hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_o
                                 double a, int nu1, int nu2, int coarse_sweeps, hipStream_t s);
 template <typename T>
 hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes);
-// 2D grids (sweep2d.hip).
+// 2D grids (sweep2d.hip).  launch_sweep2x2d: two consecutive red-black
+// sweeps of a 2D level in one pass, out of place (xin may be null with zero_in).
+template <typename T>
+hipError_t launch_sweep2x2d(const T* xin, const T* b, double bscale, T* xout, const Geo& g, int order, double a,
+                            bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,
                           int order, double a, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,

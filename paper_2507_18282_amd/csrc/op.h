@@ -133,6 +133,8 @@ struct Op {
     ew_status vcycle(int level, T* cur, T* other, const T* b, double bscale, bool zero, T** result);
     template <typename T>
     ew_status sweep(int level, T*& cur, T*& other, const T* b, double bscale, bool zero, const T* xc);
+    template <typename T>
+    ew_status sweeps(int level, int count, T*& cur, T*& other, const T* b, double bscale, bool zero);
     ew_status mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel,
                          bool speculate = false);
     ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);

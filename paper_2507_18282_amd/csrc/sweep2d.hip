@@ -3,6 +3,8 @@
 // that dominates the implicit wave-solve on large 2D grids).
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "mg_tile.h"
 #include "stencil_dev.h"
 
@@ -185,6 +187,137 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two consecutive red-black sweeps of one 64 x TY tile from one staging of x
+// and b: red on the tile plus 3 layers, black on plus 2, red on plus 1, black
+// on the tile (each half-sweep relaxes one colour from the values before it,
+// so every phase needs the previous one on a region one layer wider, and the
+// order-4 same-colour neighbours two layers wider).  x is staged with a halo
+// of R + 3, b with a halo of 3.  The result equals two calls of the single
+// sweep bit for bit: every relaxed value is computed by the same expression
+// from the same inputs.  Halves the HBM traffic of the two pre-smoothing
+// sweeps and saves one launch per level.  (A layout with one LDS array per
+// colour, which makes the lanes' LDS reads contiguous, measured slower.)
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER, int TY, bool ZERO_IN>
+__global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __restrict__ xin, const T* __restrict__ b,
+                                                                 T bscale, T* __restrict__ xout, Geo g, T a,
+                                                                 T inv_diag) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 3;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BH = 3, BX = TX + 2 * BH, BY = TY + 2 * BH;
+    __shared__ T X[LY * LX];
+    __shared__ T B[BY * BX];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+
+    // staging, every global load issued before the first LDS store
+    constexpr int NX = LY * LX, NB = BY * BX;
+    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IB = (NB + kTileThreads - 1) / kTileThreads;
+    T xv[IX], bv[IB];
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (!ZERO_IN && q < NX) {
+            const int ly = q / LX, lx = q - ly * LX;
+            const int gi = x0 - H + lx, gj = y0 - H + ly;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = xin[(int64_t)gj * g.nx + gi];
+        }
+        xv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (q < NB) {
+            const int by = q / BX, bx = q - by * BX;
+            const int gi = x0 - BH + bx, gj = y0 - BH + by;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = b[(int64_t)gj * g.nx + gi];
+        }
+        bv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NX) X[q] = xv[t];
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NB) B[q] = bscale * bv[t];
+    }
+    __syncthreads();
+
+    const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
+    // relaxed value of global point (gi, gj) from the values now in LDS
+    auto relax = [&](int gi, int gj) -> T {
+        const int p = (gj - y0 + H) * LX + (gi - x0 + H);
+        const T bval = B[(gj - y0 + BH) * BX + (gi - x0 + BH)];
+        const T uc = X[p];
+        T dx, dy;
+        if (ORDER == 2) {
+            dx = X[p - 1] + X[p + 1] - T(2) * uc;
+            dy = X[p - LX] + X[p + LX] - T(2) * uc;
+        } else {
+            const T l2 = (gi == 0) ? -uc : X[p - 2];
+            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
+            dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
+        }
+        const T r = bval - (uc - a * (dx * cxc + dy * cyc));
+        const bool edge = ORDER == 4 && (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1);
+        return edge ? uc + r / mdiag_at<T, ORDER, 2>(gi, gj, 0, g, a) : uc + r * inv_diag;
+    };
+    // one half-sweep of colour `colour` on the tile plus K layers: new values to
+    // registers (same-colour neighbours must be read old), then into LDS
+    auto half = [&](auto kc, int colour) {
+        constexpr int K = decltype(kc)::value;
+        constexpr int W2 = (TX + 2 * K) / 2, NR = TY + 2 * K, NP = NR * W2;
+        constexpr int IT = (NP + kTileThreads - 1) / kTileThreads;
+        T rv[IT];
+        int rp[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            rp[t] = -1;
+            const int idx = tid + t * kTileThreads;
+            if (idx >= NP) continue;
+            const int r = idx / W2, k2 = idx - r * W2;
+            const int gj = y0 - K + r;
+            const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
+            if (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx) continue;
+            rv[t] = relax(gi, gj);
+            rp[t] = (gj - y0 + H) * LX + (gi - x0 + H);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < IT; ++t)
+            if (rp[t] >= 0) X[rp[t]] = rv[t];
+        __syncthreads();
+    };
+    half(std::integral_constant<int, 3>{}, 0);  // red, first sweep
+    half(std::integral_constant<int, 2>{}, 1);  // black, first sweep
+    half(std::integral_constant<int, 1>{}, 0);  // red, second sweep
+    // black of the second sweep on the tile, written out with the red point of
+    // the same pair of columns
+    constexpr int NP = TY * (TX / 2), IT = (NP + kTileThreads - 1) / kTileThreads;
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const int idx = tid + t * kTileThreads;
+        if (idx >= NP) continue;
+        const int r = idx / (TX / 2), k2 = idx - r * (TX / 2);
+        const int gj = y0 + r;
+        const int gib = x0 + ((1 + gj) & 1) + 2 * k2, gir = gib ^ 1;
+        if (gj >= g.ny) continue;
+        T* row = xout + (int64_t)gj * g.nx;
+        if (gib < g.nx) row[gib] = relax(gib, gj);
+        if (gir < g.nx) row[gir] = X[(gj - y0 + H) * LX + (gir - x0 + H)];
+    }
+}
+
 // hipExtLaunchKernelGGL records ev0/ev1 (when given) at the dispatch's own
 // start and end, so profiling this kernel adds no separate event commands.
 template <typename T, int ORDER, int TY>
@@ -220,6 +353,42 @@ static hipError_t sweep2d_dispatch(const T* xin, const T* xc, const T* b, T bs, 
         return sweep2d_launch<T, ORDER, 16>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
     return sweep2d_launch<T, ORDER, 8>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
 }
+
+template <typename T, int ORDER, int TY>
+static hipError_t sweep2x_launch(const T* xin, const T* b, T bs, T* xout, const Geo& g, T aa, T inv, bool zero_in,
+                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
+    dim3 block(kTileThreads);
+    if (zero_in)
+        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, true>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
+    else
+        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, false>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
+    return hipGetLastError();
+}
+
+template <typename T, int ORDER>
+static hipError_t sweep2x_dispatch(const T* xin, const T* b, T bs, T* xout, const Geo& g, double a, bool zero_in,
+                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const double c0 = ORDER == 2 ? 2.0 : 30.0 / 12.0;
+    const T inv = (T)(1.0 / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
+    const T aa = (T)a;
+    const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
+    if (tiles16 >= 2048) return sweep2x_launch<T, ORDER, 16>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+    return sweep2x_launch<T, ORDER, 8>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+}
+
+template <typename T>
+hipError_t launch_sweep2x2d(const T* xin, const T* b, double bscale, T* xout, const Geo& g, int order, double a,
+                            bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const T bs = (T)bscale;
+    if (order == 2) return sweep2x_dispatch<T, 2>(xin, b, bs, xout, g, a, zero_in, s, ev0, ev1);
+    return sweep2x_dispatch<T, 4>(xin, b, bs, xout, g, a, zero_in, s, ev0, ev1);
+}
+
+template hipError_t launch_sweep2x2d<double>(const double*, const double*, double, double*, const Geo&, int, double,
+                                             bool, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_sweep2x2d<float>(const float*, const float*, double, float*, const Geo&, int, double, bool,
+                                            hipStream_t, hipEvent_t, hipEvent_t);
 
 template <typename T>
 hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,

@@ -27,6 +27,28 @@ ew_status Op::sweep(int l, T*& cur, T*& other, const T* b, double bscale, bool z
     return EW_OK;
 }
 
+// `count` consecutive plain sweeps on level l (the first from zero if `zero`):
+// on 2D levels pairs of sweeps run as one fused pass.
+template <typename T>
+ew_status Op::sweeps(int l, int count, T*& cur, T*& other, const T* b, double bscale, bool zero) {
+    const Level& L = levels[l];
+    const double n = (double)L.g.size();
+    int s = 0;
+    if (L.g.dim == 2) {
+        for (; s + 1 < count; s += 2) {
+            const bool z = zero && s == 0;
+            // algorithmic bytes counted per sweep (x, b read and x written once per
+            // sweep), for the two sweeps this launch performs
+            ProfScope ps(this, z ? EW_K_SMOOTH_ZERO : EW_K_SMOOTH, l, sizeof(T) * ((z ? 5.0 : 6.0) * n), true);
+            EW_HIP_TRY(launch_sweep2x2d<T>(cur, b, bscale, other, L.g, order, a, z, stream, ps.start_event(),
+                                           ps.stop_event()));
+            std::swap(cur, other);
+        }
+    }
+    for (; s < count; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, zero && s == 0, nullptr));
+    return EW_OK;
+}
+
 // V(nu1, nu2) cycle on level l starting from the iterate in cur (zero if
 // `zero`); other is its partner buffer.  *result receives the buffer that holds
 // the new iterate (cur or other).  Levels from coarse_level down run in one
@@ -48,12 +70,11 @@ ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool ze
         return EW_OK;
     }
     if (l == last) {
-        const int sweeps = L.g.size() == 1 ? 1 : desc.mg_coarse_sweeps;
-        for (int s = 0; s < sweeps; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, zero && s == 0, nullptr));
+        EW_TRY(sweeps<T>(l, L.g.size() == 1 ? 1 : desc.mg_coarse_sweeps, cur, other, b, bscale, zero));
         *result = cur;
         return EW_OK;
     }
-    for (int s = 0; s < desc.mg_nu1; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, zero && s == 0, nullptr));
+    EW_TRY(sweeps<T>(l, desc.mg_nu1, cur, other, b, bscale, zero));
     if (desc.mg_nu1 == 0 && zero) EW_HIP_TRY(launch_fill<T>(cur, L.g.size(), T(0), stream));
     const Level& C = levels[l + 1];
     {
