@@ -40,6 +40,7 @@ LEARN_OMEGA_SEED = 4242
 LEARN_CROP_SEED = 777
 LEARN_BUDGET = 32          # wave-solves per predictor in the learned-form comparison
 LEARN_OMEGAS = (40.0, 90.0, 140.0)
+PERIODS_BUDGET_NP1 = 400   # wave-solves allowed to N_p = 1 in the periods-rule comparison
 METRIC = "grid-pt updates/s + eigenpairs/s at resid 1e-8; learned/batched vs plain"
 SMOOTH_SRC = os.path.join(ROOT, "paper_2507_18282_amd", "csrc", "sweep2d.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_square2047_order4.txt")
@@ -236,6 +237,38 @@ def learned_vs_plain():
     return out
 
 
+def periods_rule():
+    """255^2 unit square, order 4, implicit 10 steps/period, omega 40 (adjusted),
+    FP64 multigrid to 1e-10, k = 8, m = 17: complete eigensolves with the number
+    of filter periods from the lobe rule (ew_choose_periods) against N_p = 1,
+    which on this dense spectrum (about 70 eigenvalues with beta >= 0.8) does not
+    converge within PERIODS_BUDGET_NP1 wave-solves."""
+    import torch
+    from paper_2507_18282_amd import Operator, choose_periods
+    n, omega, k = 255, 40.0, 8
+    n_p, n_lobe = choose_periods((1.0, 1.0), omega, k)
+    out = {"workload": "unit square 257^2 points (255^2 interior), order 4, implicit 10 steps/period, omega 40 "
+                       "(adjusted), FP64 multigrid to 1e-10, k=8, m=17, eig-res <= 1e-8",
+           "rule": {"n_p": n_p, "eigenvalues_in_lobe": n_lobe}}
+    for label, npp, budget in (("np1", 1, PERIODS_BUDGET_NP1), ("rule", n_p, 100000)):
+        op = Operator(n=(n, n), length=(1.0, 1.0), order=4, omega=omega, ts="implicit", n_its=10, n_p=npp,
+                      adjust_omega=True, mg_tol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.eigs(k, 2 * k + 1, seed=3, tol_res=1e-8, max_wave_solves=budget, want_vectors=False,
+                    raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(1 for x in r.res if x <= 1e-8)
+        res = out.setdefault(label, {})
+        res.update({"n_p": npp, "pairs": ok, "wave_solves": r.wave_solves, "seconds": dt,
+                    "eigenpairs_per_s": ok / dt, "time_steps_per_eigenpair": r.time_steps / ok if ok else None,
+                    "status": r.status})
+        log(f"periods rule: N_p {npp}: {ok} pairs, {r.wave_solves} wave-solves, {dt:.2f} s")
+        op.close()
+    return out
+
+
 def mixed_cube():
     """255^3 cube, order 2, implicit 10 steps/period, omega 40: mixed precision
     (FP32 inner multigrid + FP64 defect correction, FP32 filter accumulation)
@@ -350,6 +383,7 @@ def main(argv=None) -> int:
         forms["batched_vs_plain"] = batched_vs_plain(a.batch_budget)
         forms["mixed_cube"] = mixed_cube()
         forms["learned_vs_plain"] = learned_vs_plain()
+        forms["periods_rule"] = periods_rule()
 
     cpu = None
     if not a.no_cpu_baseline:

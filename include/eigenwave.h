@@ -268,6 +268,23 @@ typedef struct {
 ew_status ew_op_profile_begin(ew_op op, int kclass, int level);
 ew_status ew_op_profile_end(ew_op op, ew_kernel_profile* out);
 
+/* Number of filter periods N_p for k wanted eigenpairs (Sec. "Changing the
+ * number of filter periods"; Sec. "Estimating the EigenWave convergence
+ * rate": the main lobe of the filter narrows like 1/N_p, the estimated
+ * convergence rate at the lobe's edge hardly depends on N_p, and the most
+ * efficient runs hold about the wanted eigenvalues above beta ~ 0.8).
+ * Returns the largest N_p <= np_max for which at least k frequencies of the
+ * continuous Dirichlet Laplacian on the box, lambda = pi sqrt(sum_d
+ * (m_d / len_d)^2), have continuous filter value beta(lambda; w, N_p) (eq.
+ * filterThreeSincs) >= beta_r, and 1 if even N_p = 1 holds fewer.  w is the
+ * frequency the operator's filter uses for desc (adjusted with desc->n_its
+ * when desc->adjust_omega; desc->n_p is ignored).  n_lobe_out receives the
+ * count for the returned N_p.  Outputs may be NULL.  Host only, no device
+ * work.  Errors: EW_ERR_INVALID_ARG (dim, lengths, omega, k < 1, beta_r
+ * outside [0.5, 1), np_max outside [1, 4096], more than 5e7 modes). */
+ew_status ew_choose_periods(const ew_grid_desc* grid, const ew_op_desc* desc, int k, double beta_r, int np_max,
+                            int* n_p_out, int* n_lobe_out);
+
 /* ------------------------------------------------------------------------
  * Batched form: many independent 2D Dirichlet rectangles, explicit leapfrog,
  * FP32 state and filter accumulation (precision EW_PREC_MIXED), FP64 vectors

@@ -249,3 +249,44 @@ def beta_corrected(mu, plan: TimePlan):
     else:
         lt = lambda_tilde_explicit(lam, plan.dt)
     return beta_discrete(lt, plan)
+
+
+def box_eigenvalues(length: Sequence[float], lam_max: float) -> np.ndarray:
+    """Frequencies lambda = pi sqrt(sum_d (m_d / L_d)^2), m_d >= 1, of the
+    continuous Dirichlet Laplacian on the box, all those <= lam_max (with
+    multiplicity), ascending."""
+    ranges = [np.arange(1, int(np.floor(lam_max * L / np.pi)) + 1) for L in length]
+    if any(r.size == 0 for r in ranges):
+        return np.zeros(0)
+    grids = np.meshgrid(*ranges, indexing="ij")
+    s = np.zeros_like(grids[0], dtype=np.float64)
+    for g, L in zip(grids, length):
+        s = s + (g / L) ** 2
+    lam = np.pi * np.sqrt(s.ravel())
+    return np.sort(lam[lam <= lam_max])
+
+
+def lobe_count(length: Sequence[float], omega: float, n_p: int, beta_r: float) -> int:
+    """Number of box eigenvalues (with multiplicity) whose continuous filter
+    value beta(lambda; omega, N_p) (eq. filterThreeSincs) is at least beta_r.
+    For beta_r >= 0.5 only the main lobe, |lambda - omega| < omega / 2, qualifies."""
+    lam = box_eigenvalues(length, 1.5 * omega)
+    return int(np.sum(beta_continuous(lam, omega, n_p) >= beta_r))
+
+
+def choose_periods(length: Sequence[float], omega: float, k: int, beta_r: float = 0.8, np_max: int = 256):
+    """Number of filter periods for k wanted eigenpairs (Sec. "Changing the
+    number of filter periods", Sec. "Estimating the EigenWave convergence
+    rate"): the main lobe narrows like 1/N_p, the simultaneous-iteration rate
+    beta(1 + 2 dw)/beta(1 + dw) at the lobe's edge beta_r hardly depends on
+    N_p, and the best runs keep about the wanted eigenvalues above beta ~ 0.8.
+    Reading: the largest N_p <= np_max whose lobe {beta >= beta_r} still holds
+    at least k eigenvalues (1 if even N_p = 1 holds fewer).  Returns
+    (N_p, eigenvalues in that lobe)."""
+    best = 1
+    for n_p in range(1, np_max + 1):
+        if lobe_count(length, omega, n_p, beta_r) >= k:
+            best = n_p
+        else:
+            break
+    return best, lobe_count(length, omega, best, beta_r)

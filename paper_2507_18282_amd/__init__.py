@@ -14,8 +14,8 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import EigenwaveError, check, load
 
-__all__ = ["Operator", "Batch", "EigsResult", "Cnn", "CropStore", "fill_uniform", "EigenwaveError", "load",
-           "version"]
+__all__ = ["Operator", "Batch", "EigsResult", "Cnn", "CropStore", "fill_uniform", "choose_periods",
+           "EigenwaveError", "load", "version"]
 
 
 def _torch():
@@ -470,3 +470,15 @@ class CropStore:
         check(self._lib.ew_cnn_data_collect(self._h, op._h, _dev_ptr(v, op.n_active), _dev_ptr(out, op.n_active),
                                             int(crops_per_step), int(seed)))
         return out
+
+
+def choose_periods(length: Sequence[float], omega: float, k: int, ts: str = "implicit", n_its: int = 10,
+                   adjust_omega: bool = True, beta_r: float = 0.8, np_max: int = 256):
+    """(N_p, eigenvalues in the lobe) for k wanted eigenpairs (see ew_choose_periods)."""
+    lib = load()
+    g = _grid_desc([1] * len(length), length, 2)
+    d = _op_desc(omega, ts, n_its=n_its, adjust_omega=adjust_omega)
+    n_p, n_lobe = ctypes.c_int(), ctypes.c_int()
+    check(lib.ew_choose_periods(ctypes.byref(g), ctypes.byref(d), int(k), float(beta_r), int(np_max),
+                                ctypes.byref(n_p), ctypes.byref(n_lobe)))
+    return int(n_p.value), int(n_lobe.value)

@@ -96,6 +96,8 @@ SIGNATURES = {
                         POINTER(c_double), c_void_p, POINTER(EigsStats)]),
     "ew_op_profile_begin": (c_int, [c_void_p, c_int, c_int]),
     "ew_op_profile_end": (c_int, [c_void_p, POINTER(KernelProfile)]),
+    "ew_choose_periods": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_int, c_double, c_int, POINTER(c_int),
+                                  POINTER(c_int)]),
     "ew_batch_create": (c_int, [c_int, POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
     "ew_batch_destroy": (None, [c_void_p]),
     "ew_batch_get_info": (c_int, [c_void_p, POINTER(BatchInfo)]),

@@ -168,3 +168,47 @@ def test_lambda_tilde_matches_mode_recurrences():
                 w.append(2 * w[n] - w[n - 1] - (lam * dt) ** 2 * w[n])
             lt = D.lambda_tilde_explicit(lam, dt)
             assert max(abs(w[n] - math.cos(lt * n * dt)) for n in range(31)) < 1e-11
+
+
+def test_box_eigenvalues_match_brute_force_and_weyl():
+    """Enumeration of pi sqrt(sum (m/L)^2) against a plain double loop, and the
+    two-term Weyl law N(L) ~ A L^2/(4 pi) - P L/(4 pi) for a rectangle."""
+    import itertools
+    length = (1.0, 0.7)
+    lam = D.box_eigenvalues(length, 60.0)
+    brute = sorted(np.pi * np.hypot(m / length[0], n / length[1])
+                   for m, n in itertools.product(range(1, 40), range(1, 40))
+                   if np.pi * np.hypot(m / length[0], n / length[1]) <= 60.0)
+    assert np.allclose(lam, brute, rtol=0, atol=1e-12)
+    big = D.box_eigenvalues(length, 400.0)
+    A, P = length[0] * length[1], 2 * (length[0] + length[1])
+    weyl = A * 400.0 ** 2 / (4 * np.pi) - P * 400.0 / (4 * np.pi)
+    assert abs(big.size - weyl) / weyl < 0.01
+    cube = D.box_eigenvalues((1.0, 1.0, 1.0), 20.0)
+    assert cube[0] == pytest.approx(np.pi * np.sqrt(3)) and np.sum(np.isclose(cube, np.pi * np.sqrt(6))) == 3
+
+
+def test_filter_lobe_width_and_rate_are_those_of_the_convergence_estimate():
+    """beta(1 + dw) = 0.8 gives dw N_p nearly independent of N_p, and the
+    simultaneous-iteration rate beta(1 + 2 dw) / beta(1 + dw) about 0.4 (the
+    values the convergence-rate estimate quotes for beta_r ~ 0.8)."""
+    from scipy.optimize import brentq
+    widths, rates = [], []
+    for n_p in (1, 2, 4, 8):
+        dw = brentq(lambda d: D.beta_continuous(1 + d, 1.0, n_p) - 0.8, 1e-9, 0.3 / n_p)
+        widths.append(dw * n_p)
+        rates.append(float(D.beta_continuous(1 + 2 * dw, 1.0, n_p)) / 0.8)
+    assert max(widths) - min(widths) < 0.02 * widths[0]
+    assert all(0.38 < r < 0.45 for r in rates)
+
+
+def test_choose_periods_keeps_k_eigenvalues_in_the_lobe():
+    length = (1.0, 1.0)
+    omega = 36.5769
+    n_p, n_lobe = D.choose_periods(length, omega, 8)
+    assert n_lobe >= 8
+    assert D.lobe_count(length, omega, n_p + 1, 0.8) < 8
+    assert 4 <= n_p <= 16
+    # more wanted eigenpairs -> fewer periods; too many for any N_p -> 1
+    assert D.choose_periods(length, omega, 24)[0] < n_p
+    assert D.choose_periods(length, omega, 10 ** 6)[0] == 1
