@@ -112,3 +112,19 @@ def test_eigs_lucky_breakdown_sine_start():
     v0 = D.sine_mode((3, 2), P.n).ravel()
     r = op.eigs(P.k, P.m, v0=to_dev(v0), seed=P.seed)
     check_result(P, r)
+
+
+def test_eigs_with_periods_from_the_lobe_rule():
+    """A dense-spectrum case (127^2, order 2, implicit, omega 30): with N_p from
+    the lobe rule the complete solve converges to the closed-form wanted set."""
+    import dataclasses
+    from paper_2507_18282_amd import choose_periods
+    base = synthetic.Problem(n=(127, 127), length=(1.0, 1.0), order=2, omega=30.0, ts="implicit",
+                             adjust_omega=True, k=4, m=9, seed=7)
+    n_p, n_lobe = choose_periods(base.length, base.omega, base.k)
+    assert n_p > 1 and n_lobe >= base.k
+    P = dataclasses.replace(base, n_p=n_p)
+    op = make_op(P)
+    say("eigs periods rule", n_p)
+    r = op.eigs(P.k, P.m, seed=P.seed, max_wave_solves=2000)
+    check_result(P, r)
