@@ -241,6 +241,17 @@ typedef struct {
 ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host, double* beta_host,
                   double* res_host, double* Y_dev, ew_eigs_stats* stats);
 
+/* The projected eigenproblem of the Krylov-Schur restart (Alg. "IRAM"; Sec.
+ * "Using Arnoldi-based algorithms"): A = Q diag(w) Q^T for a symmetric n x n
+ * matrix, the routine ew_eigs uses on its projected matrices.  a_host is
+ * row-major n x n (only symmetric input is meaningful; the matrix is read,
+ * not modified); w_host receives n eigenvalues (unordered), q_host (n x n,
+ * row-major, may be NULL) the orthonormal eigenvectors as columns.  Orders up
+ * to 64: cyclic Jacobi; above: Householder tridiagonalisation and implicit
+ * QR with Wilkinson shifts.  Host only, no device work.  Errors:
+ * EW_ERR_INVALID_ARG (n < 1, n > 8192, NULL a_host or w_host). */
+ew_status ew_sym_eig(int n, const double* a_host, double* w_host, double* q_host);
+
 /* Kernel timing inside an operator (the tracing facility).  Between
  * ew_op_profile_begin and ew_op_profile_end, every launch of kernel class
  * `kclass` that the operator issues on multigrid level `level` (any level if

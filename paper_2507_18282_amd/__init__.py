@@ -482,3 +482,18 @@ def choose_periods(length: Sequence[float], omega: float, k: int, ts: str = "imp
     check(lib.ew_choose_periods(ctypes.byref(g), ctypes.byref(d), int(k), float(beta_r), int(np_max),
                                 ctypes.byref(n_p), ctypes.byref(n_lobe)))
     return int(n_p.value), int(n_lobe.value)
+
+
+def sym_eig(a):
+    """(w, Q) with a = Q diag(w) Q^T for a symmetric float64 matrix (host
+    routine of the eigensolver's projected problems; see ew_sym_eig)."""
+    import numpy as np
+    lib = load()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    if a.shape != (n, n):
+        raise ValueError("square matrix expected")
+    w = np.empty(n)
+    q = np.empty((n, n))
+    check(lib.ew_sym_eig(int(n), a.ctypes.data, w.ctypes.data, q.ctypes.data))
+    return w, q

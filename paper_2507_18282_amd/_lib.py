@@ -122,6 +122,7 @@ SIGNATURES = {
     "ew_op_set_cnn": (c_int, [c_void_p, c_void_p]),
     "ew_op_cnn_guess": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ew_fill_uniform": (c_int, [c_void_p, c_int64, c_uint64, c_void_p]),
+    "ew_sym_eig": (c_int, [c_int, c_void_p, c_void_p, c_void_p]),
     "ew_last_error": (c_char_p, []),
     "ew_version": (c_char_p, []),
 }

@@ -343,7 +343,7 @@ ew_status end_of_cycle(BEig& e, bool& run_ended, std::vector<double>& theta, Mat
         for (int j = 0; j < m; ++j) A(i, j) = 0.5 * (e.T(i, j) + e.T(j, i));
     std::vector<double> w0;
     Mat Q0;
-    jacobi_eigh(A, w0, Q0);
+    sym_eigh(A, w0, Q0);
     std::vector<int> idx = order_by_abs_desc(w0);
     theta.assign(m, 0.0);
     Q = Mat(m, m);

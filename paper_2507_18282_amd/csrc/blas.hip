@@ -66,43 +66,194 @@ hipError_t launch_normalize_from_partial(const double* w, double* v, int64_t n, 
 }
 
 // Y[:, c] = V[:, 0:nv] Q[0:nv, c] for a chunk of up to 16 output columns per
-// launch pass; each thread owns one row, Q sits in LDS.
+// launch pass; each thread owns one row, and Q passes through LDS in slabs of
+// kGemmSlab rows (any nv).
 constexpr int kGemmCols = 16;
-constexpr int kMaxGemmRows = 320;  // nv bound: Krylov dimension + locked vectors
+constexpr int kGemmSlab = 320;
 
 __global__ __launch_bounds__(256) void k_tall_gemm(const double* __restrict__ V, int64_t n, int nv,
                                                    const double* __restrict__ Q, int ldq, int c0, int nc,
                                                    double* __restrict__ Y) {
-    __shared__ double q[kMaxGemmRows * kGemmCols];
-    for (int t = threadIdx.x; t < nv * nc; t += 256) {
-        const int i = t % nv, c = t / nv;
-        q[i * kGemmCols + c] = Q[i + (int64_t)(c0 + c) * ldq];
-    }
-    __syncthreads();
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
+    __shared__ double q[kGemmSlab * kGemmCols];
+    for (int64_t rb = (int64_t)blockIdx.x * 256; rb < n; rb += (int64_t)gridDim.x * 256) {
+        const int64_t r = rb + threadIdx.x;
         double acc[kGemmCols];
 #pragma unroll
         for (int c = 0; c < kGemmCols; ++c) acc[c] = 0.0;
-        for (int i = 0; i < nv; ++i) {
-            const double vi = V[(int64_t)i * n + r];
+        for (int i0 = 0; i0 < nv; i0 += kGemmSlab) {
+            const int ni = (nv - i0) < kGemmSlab ? (nv - i0) : kGemmSlab;
+            __syncthreads();
+            for (int t = threadIdx.x; t < ni * nc; t += 256) {
+                const int i = t % ni, c = t / ni;
+                q[i * kGemmCols + c] = Q[(i0 + i) + (int64_t)(c0 + c) * ldq];
+            }
+            __syncthreads();
+            if (r < n) {
+                for (int i = 0; i < ni; ++i) {
+                    const double vi = V[(int64_t)(i0 + i) * n + r];
 #pragma unroll
-            for (int c = 0; c < kGemmCols; ++c) acc[c] += vi * q[i * kGemmCols + c];
+                    for (int c = 0; c < kGemmCols; ++c) acc[c] += vi * q[i * kGemmCols + c];
+                }
+            }
         }
+        if (r < n) {
 #pragma unroll
-        for (int c = 0; c < kGemmCols; ++c)
-            if (c < nc) Y[(int64_t)(c0 + c) * n + r] = acc[c];
+            for (int c = 0; c < kGemmCols; ++c)
+                if (c < nc) Y[(int64_t)(c0 + c) * n + r] = acc[c];
+        }
     }
 }
 
 hipError_t launch_tall_gemm(const double* V, int64_t n, int nv, const double* Q_dev, int ldq, int ncols, double* Y,
                             hipStream_t s) {
-    if (nv > kMaxGemmRows) return hipErrorInvalidValue;
+    if (nv < 1 || ncols < 1) return hipErrorInvalidValue;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     for (int c0 = 0; c0 < ncols; c0 += kGemmCols) {
         const int nc = (ncols - c0) < kGemmCols ? (ncols - c0) : kGemmCols;
         k_tall_gemm<<<(unsigned)blocks, 256, 0, s>>>(V, n, nv, Q_dev, ldq, c0, nc, Y);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block classical Gram-Schmidt over a basis of many columns (the columns of
+// two column-major blocks, [U1 | U2], leading dimension n): h = U^T w by
+// row-slice partials, then w -= U h.  Twice applied this is CGS2, whose
+// orthogonality matches MGS's while every pass streams the basis once with
+// full parallelism instead of one launch per column.
+// ---------------------------------------------------------------------------
+struct ColPair {
+    const double* u1;
+    int n1;
+    const double* u2;
+};
+
+__device__ __forceinline__ const double* col_at(const ColPair& U, int c, int64_t n) {
+    return c < U.n1 ? U.u1 + (int64_t)c * n : U.u2 + (int64_t)(c - U.n1) * n;
+}
+
+// partial[s * nu + c] = sum over rows of slice s of U[:, c] * w; one wavefront
+// per (column, slice), four columns per workgroup.
+__global__ __launch_bounds__(256) void k_block_dot(ColPair U, int nu, const double* __restrict__ w, int64_t n,
+                                                   int64_t slice, double* __restrict__ partial) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nu) return;
+    const int64_t r0 = (int64_t)blockIdx.y * slice;
+    int64_t r1 = r0 + slice;
+    if (r1 > n) r1 = n;
+    const double* u = col_at(U, c, n);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t r = r0 + lane;
+    for (; r + 192 < r1; r += 256) {
+        a0 += u[r] * w[r];
+        a1 += u[r + 64] * w[r + 64];
+        a2 += u[r + 128] * w[r + 128];
+        a3 += u[r + 192] * w[r + 192];
+    }
+    for (; r < r1; r += 64) a0 += u[r] * w[r];
+    double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) partial[(int64_t)blockIdx.y * nu + c] = v;
+}
+
+// h_cur[c] = sum_s partial[s * nu + c] (slices in order); h_tot[c] = h_cur[c]
+// on the first pass, += on the second.
+__global__ __launch_bounds__(256) void k_block_dot_sum(const double* __restrict__ partial, int nslices, int nu,
+                                                       double* __restrict__ h_cur, double* __restrict__ h_tot,
+                                                       int accumulate) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= nu) return;
+    double v = 0.0;
+    for (int s = 0; s < nslices; ++s) v += partial[(int64_t)s * nu + c];
+    h_cur[c] = v;
+    h_tot[c] = accumulate ? h_tot[c] + v : v;
+}
+
+// Columns [k * chunk, (k+1) * chunk) of U times h for the rows of this block
+// (h passes through LDS in slabs of kAxpySlab): with one chunk, w -= U h
+// directly; else the chunk's product goes to tmp[k * n + r] for
+// k_block_axpy_sum.
+constexpr int kAxpySlab = 512;
+__global__ __launch_bounds__(256) void k_block_axpy(ColPair U, int nu, const double* __restrict__ h, int chunk,
+                                                    double* __restrict__ w, int64_t n, double* __restrict__ tmp) {
+    __shared__ double hs[kAxpySlab];
+    const int c0 = blockIdx.y * chunk;
+    int c1 = c0 + chunk;
+    if (c1 > nu) c1 = nu;
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = r < n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int s0 = c0; s0 < c1; s0 += kAxpySlab) {
+        const int ns = (c1 - s0) < kAxpySlab ? (c1 - s0) : kAxpySlab;
+        __syncthreads();
+        for (int t = threadIdx.x; t < ns; t += 256) hs[t] = h[s0 + t];
+        __syncthreads();
+        if (live) {
+            int c = 0;
+            for (; c + 3 < ns; c += 4) {
+                a0 += col_at(U, s0 + c, n)[r] * hs[c];
+                a1 += col_at(U, s0 + c + 1, n)[r] * hs[c + 1];
+                a2 += col_at(U, s0 + c + 2, n)[r] * hs[c + 2];
+                a3 += col_at(U, s0 + c + 3, n)[r] * hs[c + 3];
+            }
+            for (; c < ns; ++c) a0 += col_at(U, s0 + c, n)[r] * hs[c];
+        }
+    }
+    if (!live) return;
+    const double acc = (a0 + a1) + (a2 + a3);
+    if (gridDim.y == 1)
+        w[r] -= acc;
+    else
+        tmp[(int64_t)blockIdx.y * n + r] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_block_axpy_sum(const double* __restrict__ tmp, int nchunks,
+                                                        double* __restrict__ w, int64_t n) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    double v = 0.0;
+    for (int k = 0; k < nchunks; ++k) v += tmp[(int64_t)k * n + r];
+    w[r] -= v;
+}
+
+BlockGsPlan block_gs_plan(int64_t n, int nu) {
+    BlockGsPlan p{};
+    // dot: at least 4096 wavefronts where the slices stay >= 1024 rows
+    int64_t ns = (4096 + nu - 1) / nu;
+    const int64_t ns_max = (n + 1023) / 1024;
+    if (ns > ns_max) ns = ns_max;
+    if (ns > kBlockGsMaxSlices) ns = kBlockGsMaxSlices;
+    if (ns < 1) ns = 1;
+    p.slice = (n + ns - 1) / ns;
+    p.nslices = (int)((n + p.slice - 1) / p.slice);
+    // axpy: split the columns when there are fewer than 2048 row blocks
+    const int64_t rb = (n + 255) / 256;
+    int64_t nc = (2048 + rb - 1) / rb;
+    const int64_t nc_cols = (nu + 15) / 16;
+    if (nc > nc_cols) nc = nc_cols;
+    if (nc > kBlockGsMaxChunks) nc = kBlockGsMaxChunks;
+    if (nc < 1) nc = 1;
+    const int64_t chunk = (nu + nc - 1) / nc;
+    p.chunk = (int)chunk;
+    p.nchunks = (int)((nu + chunk - 1) / chunk);
+    return p;
+}
+
+hipError_t launch_block_gs_pass(const double* u1, int n1, const double* u2, int n2, double* w, int64_t n,
+                                const BlockGsPlan& p, double* partial, double* h_cur, double* h_tot, int accumulate,
+                                double* tmp, hipStream_t s) {
+    const int nu = n1 + n2;
+    if (nu < 1) return hipErrorInvalidValue;
+    if (p.nchunks > 1 && (int64_t)p.nchunks * n > kBlockGsTmpDoubles) return hipErrorInvalidValue;
+    const ColPair U{u1, n1, u2};
+    k_block_dot<<<dim3((unsigned)((nu + 3) / 4), (unsigned)p.nslices), 256, 0, s>>>(U, nu, w, n, p.slice, partial);
+    k_block_dot_sum<<<(nu + 255) / 256, 256, 0, s>>>(partial, p.nslices, nu, h_cur, h_tot, accumulate);
+    const unsigned rb = (unsigned)((n + 255) / 256);
+    k_block_axpy<<<dim3(rb, (unsigned)p.nchunks), 256, 0, s>>>(U, nu, h_cur, p.chunk, w, n, tmp);
+    if (p.nchunks > 1) k_block_axpy_sum<<<rb, 256, 0, s>>>(tmp, p.nchunks, w, n);
     return hipGetLastError();
 }
 

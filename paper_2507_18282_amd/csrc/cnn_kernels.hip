@@ -492,17 +492,43 @@ __global__ __launch_bounds__(kTrainThreads) void k_cnn_train(
     }
 }
 
-__global__ __launch_bounds__(256) void k_cnn_reduce(const float* __restrict__ pgrad, const double* __restrict__ ploss,
-                                                    int nb, float* __restrict__ grad, double* __restrict__ loss) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+// Sum of the per-block partials in a fixed order (deterministic).  A workgroup
+// owns 64 consecutive columns (the parameters, and the loss as column
+// kCnnParams); its 16 rows of lanes each add every 16th partial with eight
+// loads in flight, then one lane per column adds the 16 row sums in order.
+constexpr int kRedCols = 64, kRedRows = 16;
+
+__global__ __launch_bounds__(kRedCols * kRedRows) void k_cnn_reduce(const float* __restrict__ pgrad,
+                                                                   const double* __restrict__ ploss, int nb,
+                                                                   float* __restrict__ grad,
+                                                                   double* __restrict__ loss) {
+    __shared__ double part[kRedRows][kRedCols + 1];
+    const int col = threadIdx.x % kRedCols, row = threadIdx.x / kRedCols;
+    const int i = blockIdx.x * kRedCols + col;
+    double s = 0.0;
     if (i < kCnnParams) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += (double)pgrad[(int64_t)b * kCnnParams + i];
-        grad[i] = (float)s;
+        const float* src = pgrad + i;
+        int b = row;
+        for (; b + 7 * kRedRows < nb; b += 8 * kRedRows) {
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = src[(int64_t)(b + u * kRedRows) * kCnnParams];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)x[u];
+        }
+        for (; b < nb; b += kRedRows) s += (double)src[(int64_t)b * kCnnParams];
     } else if (i == kCnnParams) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += ploss[b];
-        *loss = s;
+        for (int b = row; b < nb; b += kRedRows) s += ploss[b];
+    }
+    part[row][col] = s;
+    __syncthreads();
+    if (row == 0 && i <= kCnnParams) {
+        double t = 0.0;
+        for (int r = 0; r < kRedRows; ++r) t += part[r][col];
+        if (i < kCnnParams)
+            grad[i] = (float)t;
+        else
+            *loss = t;
     }
 }
 
@@ -629,7 +655,7 @@ hipError_t launch_cnn_train(const CnnPacked* pk, const float* fields, const floa
 
 hipError_t launch_cnn_reduce(const float* pgrad, const double* ploss, int nblocks, float* grad, double* loss,
                              hipStream_t st) {
-    k_cnn_reduce<<<(kCnnParams + 1 + 255) / 256, 256, 0, st>>>(pgrad, ploss, nblocks, grad, loss);
+    k_cnn_reduce<<<(kCnnParams + kRedCols) / kRedCols, kRedCols * kRedRows, 0, st>>>(pgrad, ploss, nblocks, grad, loss);
     return hipGetLastError();
 }
 

@@ -1,5 +1,7 @@
-// Small dense FP64 linear algebra on the host (matrices of order <= a few
-// hundred): cyclic Jacobi for symmetric eigenproblems and Cholesky.
+// Dense FP64 linear algebra on the host for the projected problems of the
+// eigensolver: symmetric eigenproblems (cyclic Jacobi for small orders,
+// Householder tridiagonalisation + implicit QR for large ones), Cholesky and
+// triangular inverses.
 #pragma once
 
 #include <algorithm>
@@ -64,6 +66,141 @@ inline void jacobi_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
     for (int i = 0; i < n; ++i) w[i] = A(i, i);
 }
 
+// Symmetric eigendecomposition A = Q diag(w) Q^T for larger orders:
+// Householder reduction to tridiagonal form (Golub & Van Loan, Alg. 8.3.1),
+// then implicit symmetric QR steps with the Wilkinson shift and deflation
+// (Alg. 8.3.2/8.3.3).  The transform is kept transposed (row j = column j of
+// Q), so every Givens rotation updates two contiguous rows.  A is overwritten.
+// Returns false if the QR iteration has not converged after 30 n steps.
+inline bool tridiag_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
+    const int n = A.n;
+    std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
+    // Householder vectors, v[k] of length n - k - 1 with leading 1, and betas
+    std::vector<std::vector<double>> hv(n > 2 ? n - 2 : 0);
+    std::vector<double> hb(n > 2 ? n - 2 : 0, 0.0);
+    std::vector<double> p(n), wv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int len = n - k - 1;
+        std::vector<double>& v = hv[k];
+        v.assign(len, 0.0);
+        double sig = 0.0;
+        for (int i = 1; i < len; ++i) sig += A(k + 1 + i, k) * A(k + 1 + i, k);
+        const double x0 = A(k + 1, k);
+        v[0] = 1.0;
+        for (int i = 1; i < len; ++i) v[i] = A(k + 1 + i, k);
+        double beta = 0.0, alpha = x0;
+        if (sig != 0.0) {
+            const double mu = std::sqrt(x0 * x0 + sig);
+            const double v0 = x0 <= 0.0 ? x0 - mu : -sig / (x0 + mu);
+            beta = 2.0 * v0 * v0 / (sig + v0 * v0);
+            for (int i = 1; i < len; ++i) v[i] /= v0;
+            alpha = mu;  // (I - beta v v^T) x = mu e_1
+        }
+        hb[k] = beta;
+        if (beta != 0.0) {
+            // p = beta A22 v, w = p - (beta p^T v / 2) v, A22 -= v w^T + w v^T
+            double pv = 0.0;
+            for (int i = 0; i < len; ++i) {
+                const double* row = &A.a[(size_t)(k + 1 + i) * n + (k + 1)];
+                double s = 0.0;
+                for (int j = 0; j < len; ++j) s += row[j] * v[j];
+                p[i] = beta * s;
+                pv += p[i] * v[i];
+            }
+            const double half = 0.5 * beta * pv;
+            for (int i = 0; i < len; ++i) wv[i] = p[i] - half * v[i];
+            for (int i = 0; i < len; ++i) {
+                double* row = &A.a[(size_t)(k + 1 + i) * n + (k + 1)];
+                const double vi = v[i], wi = wv[i];
+                for (int j = 0; j < len; ++j) row[j] -= vi * wv[j] + wi * v[j];
+            }
+        }
+        A(k + 1, k) = A(k, k + 1) = alpha;
+        for (int i = 2; i <= len; ++i) A(k + i, k) = A(k, k + i) = 0.0;
+    }
+    for (int i = 0; i < n; ++i) d[i] = A(i, i);
+    for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
+    // Q = H_0 H_1 ... H_{n-3} by backward accumulation, stored transposed:
+    // Zt = Q^T, so H_k applied on the left of Q's trailing block is applied on
+    // the right of Zt's trailing block.
+    Mat Zt(n, n);
+    for (int i = 0; i < n; ++i) Zt(i, i) = 1.0;
+    for (int k = n - 3; k >= 0; --k) {
+        if (hb[k] == 0.0) continue;
+        const int len = n - k - 1;
+        const std::vector<double>& v = hv[k];
+        // Zt[r, k+1:] -= beta (Zt[r, k+1:] . v) v for rows r >= k+1
+        for (int r = k + 1; r < n; ++r) {
+            double* row = &Zt.a[(size_t)r * n + (k + 1)];
+            double s = 0.0;
+            for (int j = 0; j < len; ++j) s += row[j] * v[j];
+            s *= hb[k];
+            if (s != 0.0)
+                for (int j = 0; j < len; ++j) row[j] -= s * v[j];
+        }
+    }
+    // implicit QR on (d, e); rotations applied to rows of Zt
+    const double eps = 2.220446049250313e-16;
+    const double tiny = 1e-300;
+    int hi = n - 1;
+    int64_t steps = 0;
+    while (hi > 0) {
+        // deflate converged couplings at the bottom
+        if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi])) + tiny) {
+            e[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo])) + tiny) --lo;
+        if (lo > 0) e[lo - 1] = 0.0;
+        if (++steps > 30 * (int64_t)n) return false;
+        // Wilkinson shift from the trailing 2 x 2 block
+        const double del = 0.5 * (d[hi - 1] - d[hi]);
+        const double f = e[hi - 1];
+        const double den = del + (del >= 0.0 ? 1.0 : -1.0) * std::hypot(del, f);
+        const double mu = d[hi] - f * f / den;
+        double x = d[lo] - mu, z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, z);
+            const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : z / r;
+            if (k > lo) e[k - 1] = r;
+            const double a = d[k], b = d[k + 1], g = e[k];
+            d[k] = c * c * a + 2.0 * c * s * g + s * s * b;
+            d[k + 1] = s * s * a - 2.0 * c * s * g + c * c * b;
+            e[k] = c * s * (b - a) + (c * c - s * s) * g;
+            if (k + 1 < hi) {
+                z = s * e[k + 1];
+                e[k + 1] *= c;
+                x = e[k];
+            }
+            double* rk = &Zt.a[(size_t)k * n];
+            double* rk1 = &Zt.a[(size_t)(k + 1) * n];
+            for (int j = 0; j < n; ++j) {
+                const double u = rk[j], t = rk1[j];
+                rk[j] = c * u + s * t;
+                rk1[j] = c * t - s * u;
+            }
+        }
+    }
+    w = d;
+    Q = Mat(n, n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Q(i, j) = Zt(j, i);
+    return true;
+}
+
+// Symmetric eigendecomposition for any order: Jacobi up to order 64 (the
+// orders of the default Krylov dimensions), tridiagonal QR above; Jacobi if
+// QR fails to converge.  A is overwritten.
+inline void sym_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
+    if (A.n > 64) {
+        Mat B = A;
+        if (tridiag_eigh(B, w, Q)) return;
+    }
+    jacobi_eigh(A, w, Q);
+}
+
 // Lower Cholesky factor of a symmetric positive definite matrix; false if not SPD.
 inline bool cholesky(const Mat& A, Mat& Lc) {
     const int n = A.n;
@@ -84,15 +221,19 @@ inline bool cholesky(const Mat& A, Mat& Lc) {
 
 // Inverse of a lower-triangular matrix.
 inline Mat lower_inverse(const Mat& Lc) {
+    // row by row: X(i, :) = (e_i - sum_{k<i} Lc(i, k) X(k, :)) / Lc(i, i)
     const int n = Lc.n;
     Mat X(n, n);
-    for (int j = 0; j < n; ++j) {
-        X(j, j) = 1.0 / Lc(j, j);
-        for (int i = j + 1; i < n; ++i) {
-            double s = 0.0;
-            for (int k = j; k < i; ++k) s += Lc(i, k) * X(k, j);
-            X(i, j) = -s / Lc(i, i);
+    for (int i = 0; i < n; ++i) {
+        double* xi = &X.a[(size_t)i * n];
+        for (int k = 0; k < i; ++k) {
+            const double l = Lc(i, k);
+            const double* xk = &X.a[(size_t)k * n];
+            for (int j = 0; j <= k; ++j) xi[j] -= l * xk[j];
         }
+        const double inv = 1.0 / Lc(i, i);
+        for (int j = 0; j < i; ++j) xi[j] *= inv;
+        xi[i] = inv;
     }
     return X;
 }

@@ -14,6 +14,8 @@
 
 namespace ew {
 
+constexpr int kMaxKrylov = 4096;
+
 // w <- w - sum_i (w, u_i) u_i over the vector list by chained MGS links, then
 // w <- w / ||w||.  coeff receives the n_u coefficients and the norm (n_u + 1).
 ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const double*>& u, std::vector<double>& coeff) {
@@ -35,6 +37,34 @@ ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const d
         const double* plast = (nu % 2 == 1) ? P1 : P0;
         EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, plast, ws.h_dev + nu, s));
     }
+    EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    EW_HIP_TRY(hipStreamSynchronize(s));
+    coeff.assign(ws.h_host, ws.h_host + nu + 1);
+    for (double v : coeff)
+        if (!std::isfinite(v)) return fail(EW_ERR_NONFINITE, "non-finite value in Gram-Schmidt");
+    return EW_OK;
+}
+
+ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, const double* u2, int n2,
+                         std::vector<double>& coeff) {
+    const int nu = n1 + n2;
+    if (nu <= kMgsMaxCols) {
+        std::vector<const double*> u;
+        u.reserve(nu);
+        for (int i = 0; i < n1; ++i) u.push_back(u1 + (int64_t)i * ws.N);
+        for (int i = 0; i < n2; ++i) u.push_back(u2 + (int64_t)i * ws.N);
+        return mgs_orthonormalize(ws, w, u, coeff);
+    }
+    if (nu > ws.nu_max) return fail(EW_ERR_INVALID_ARG, "orthogonalisation basis exceeds the workspace");
+    EW_TRY(ws.setup_block_gs());
+    hipStream_t s = ws.stream;
+    const BlockGsPlan plan = block_gs_plan(ws.N, nu);
+    // CGS2: two passes, coefficients summed into h_dev[0:nu]
+    for (int pass = 0; pass < 2; ++pass)
+        EW_HIP_TRY(launch_block_gs_pass(u1, n1, u2, n2, w, ws.N, plan, ws.gs_partial, ws.h_cur, ws.h_dev, pass,
+                                        ws.gs_tmp, s));
+    EW_HIP_TRY(launch_dot_partial(w, w, ws.N, ws.P, s));
+    EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, ws.P, ws.h_dev + nu, s));
     EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     EW_HIP_TRY(hipStreamSynchronize(s));
     coeff.assign(ws.h_host, ws.h_host + nu + 1);
@@ -67,22 +97,73 @@ struct RunResult {
     std::vector<char> conv;
 };
 
+// Probe runs test for convergence before the basis is full, at these sizes
+// and their doublings (the last test is always at the full basis).
+constexpr int kProbeFirstCheck = 64;
+
 // One Krylov-Schur run on S deflated by the nl locked vectors, started from
 // column 0 of ws.V (already filled, not yet orthonormalised).
+//
+// Stopping rules: the first run stops when its k leading Ritz pairs (by
+// |theta|) have converged.  A probe run (probe > 0, deflation probes for
+// repeated eigenvalues) stops when every Ritz value with |theta| >= floor_abs
+// has converged, or when no eigenvalue of the deflated operator is left at or
+// above the floor: the leading Ritz value has converged below it, or both
+// extreme Ritz values, widened by their residual bounds, lie below it
+// (tested from kProbeFirstCheck basis vectors on; a Krylov space's extreme
+// Ritz values approach the extreme eigenvalues first).
 ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, int k, double floor_abs,
                  int64_t ws_budget, uint64_t seed_base, int64_t& wave_solves, int64_t& restarts, RunResult& out) {
     Op* op = ws.op;
     const int m = ws.m;
     Mat T(m + 1, m);
-    std::vector<double> coeff;
-    std::vector<const double*> u;
+    std::vector<double> coeff, res;
+    // Ritz pairs of the leading s x s projected matrix (symmetric up to
+    // rounding): out.theta, out.Q (s x s, columns by |theta| descending),
+    // residual bounds res and out.conv.
+    auto ritz = [&](int s) {
+        Mat A(s, s);
+        for (int i = 0; i < s; ++i)
+            for (int j = 0; j < s; ++j) A(i, j) = 0.5 * (T(i, j) + T(j, i));
+        std::vector<double> w0;
+        Mat Q0;
+        sym_eigh(A, w0, Q0);
+        std::vector<int> idx = order_by_abs_desc(w0);
+        out.theta.assign(s, 0.0);
+        out.Q = Mat(s, s);
+        for (int c = 0; c < s; ++c) {
+            out.theta[c] = w0[idx[c]];
+            for (int i = 0; i < s; ++i) out.Q(i, c) = Q0(i, idx[c]);
+        }
+        const double beta_s = T(s, s - 1);
+        res.assign(s, 0.0);
+        out.conv.assign(s, 0);
+        for (int c = 0; c < s; ++c) {
+            res[c] = std::fabs(beta_s * out.Q(s - 1, c));
+            out.conv[c] = res[c] <= tol_ritz * std::fabs(out.theta[c]);
+        }
+    };
+    auto stop_rule = [&](int s) -> bool {
+        const int nlead = leading_converged(out.conv);
+        if (probe == 0) return nlead >= k;
+        if (s >= kProbeFirstCheck) {
+            int cmax = 0, cmin = 0;
+            for (int c = 1; c < s; ++c) {
+                if (out.theta[c] > out.theta[cmax]) cmax = c;
+                if (out.theta[c] < out.theta[cmin]) cmin = c;
+            }
+            const double top = std::max(std::fabs(out.theta[cmax]) + res[cmax], std::fabs(out.theta[cmin]) + res[cmin]);
+            if (top < floor_abs) return true;
+        }
+        if (!out.conv[0]) return false;
+        if (std::fabs(out.theta[0]) < floor_abs) return true;
+        int n_band = 0;
+        for (int c = 0; c < s; ++c) n_band += std::fabs(out.theta[c]) >= floor_abs;
+        return nlead >= n_band;
+    };
     // normalise the start vector against the locked set
-    {
-        u.clear();
-        for (int i = 0; i < nl; ++i) u.push_back(ws.col(ws.Y, i));
-        EW_TRY(mgs_orthonormalize(ws, ws.col(ws.V, 0), u, coeff));
-        if (!(coeff.back() > 0.0)) return fail(EW_ERR_NONFINITE, "start vector lies in the locked space");
-    }
+    EW_TRY(orthonormalize(ws, ws.col(ws.V, 0), ws.Y, nl, nullptr, 0, coeff));
+    if (!(coeff.back() > 0.0)) return fail(EW_ERR_NONFINITE, "start vector lies in the locked space");
     int p = 0;
     for (;;) {
         for (int j = p; j < m; ++j) {
@@ -96,10 +177,7 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
             }
             EW_TRY(op->apply_filter(ws.col(ws.V, j), w));
             ++wave_solves;
-            u.clear();
-            for (int i = 0; i < nl; ++i) u.push_back(ws.col(ws.Y, i));
-            for (int i = 0; i <= j; ++i) u.push_back(ws.col(ws.V, i));
-            EW_TRY(mgs_orthonormalize(ws, w, u, coeff));
+            EW_TRY(orthonormalize(ws, w, ws.Y, nl, ws.V, j + 1, coeff));
             double hsq = 0.0;
             for (int i = 0; i <= j; ++i) {
                 T(i, j) = coeff[nl + i];
@@ -110,42 +188,19 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
                 // Breakdown: the Krylov space is invariant.  Continue from a
                 // fresh random direction orthogonal to everything so far.
                 EW_HIP_TRY(launch_splitmix_uniform(w, ws.N, seed_base + 0x100000ULL + (uint64_t)wave_solves, op->stream));
-                EW_TRY(mgs_orthonormalize(ws, w, u, coeff));
+                EW_TRY(orthonormalize(ws, w, ws.Y, nl, ws.V, j + 1, coeff));
                 nrm = 0.0;
             }
             T(j + 1, j) = nrm;
-        }
-        // Projected matrix (symmetric up to rounding) and its eigenpairs.
-        Mat A(m, m);
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) A(i, j) = 0.5 * (T(i, j) + T(j, i));
-        std::vector<double> w0;
-        Mat Q0;
-        jacobi_eigh(A, w0, Q0);
-        std::vector<int> idx = order_by_abs_desc(w0);
-        out.theta.assign(m, 0.0);
-        out.Q = Mat(m, m);
-        for (int c = 0; c < m; ++c) {
-            out.theta[c] = w0[idx[c]];
-            for (int i = 0; i < m; ++i) out.Q(i, c) = Q0(i, idx[c]);
-        }
-        const double beta_m = T(m, m - 1);
-        out.conv.assign(m, 0);
-        for (int c = 0; c < m; ++c)
-            out.conv[c] = std::fabs(beta_m * out.Q(m - 1, c)) <= tol_ritz * std::fabs(out.theta[c]);
-        // stopping rule
-        bool stop = false;
-        const int nlead = leading_converged(out.conv);
-        if (probe == 0) {
-            stop = nlead >= k;
-        } else if (out.conv[0]) {
-            if (std::fabs(out.theta[0]) < floor_abs) stop = true;
-            else {
-                int n_band = 0;
-                for (int c = 0; c < m; ++c) n_band += std::fabs(out.theta[c]) >= floor_abs;
-                stop = nlead >= n_band;
+            const int s = j + 1;
+            if (probe > 0 && s < m && s >= kProbeFirstCheck && (s & (s - 1)) == 0) {
+                ritz(s);
+                if (stop_rule(s)) return EW_OK;
             }
         }
+        ritz(m);
+        const double beta_m = T(m, m - 1);
+        const bool stop = stop_rule(m);
         if (stop || wave_solves >= ws_budget) return EW_OK;
         // Thick restart: keep the leading n_keep Ritz vectors and the residual vector.
         EW_TRY(rotate(ws, ws.V, m, out.Q, n_keep, ws.Vt));
@@ -214,24 +269,36 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
     Mat Lc;
     if (!cholesky(Bs, Lc)) return fail(EW_ERR_NONFINITE, "locked vectors are not linearly independent");
     Mat Li = lower_inverse(Lc);
-    Mat C(nl, nl);
+    // C = Li Gs Li^T as two products, then Q = Li^T Zc
+    Mat T1(nl, nl), C(nl, nl);
+    for (int i = 0; i < nl; ++i) {
+        double* t = &T1.a[(size_t)i * nl];
+        for (int a = 0; a <= i; ++a) {
+            const double l = Li(i, a);
+            const double* g = &Gs.a[(size_t)a * nl];
+            for (int b = 0; b < nl; ++b) t[b] += l * g[b];
+        }
+    }
     for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
+        for (int j = 0; j <= i; ++j) {
+            const double* t = &T1.a[(size_t)i * nl];
+            const double* l = &Li.a[(size_t)j * nl];
             double s = 0.0;
-            for (int a = 0; a <= i; ++a)
-                for (int b = 0; b <= j; ++b) s += Li(i, a) * Gs(a, b) * Li(j, b);
-            C(i, j) = s;
+            for (int b = 0; b <= j; ++b) s += t[b] * l[b];
+            C(i, j) = C(j, i) = s;
         }
     std::vector<double> mu;
     Mat Zc;
-    jacobi_eigh(C, mu, Zc);
+    sym_eigh(C, mu, Zc);
     Mat Qr(nl, nl);  // Q = Li^T Zc
-    for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-            double s = 0.0;
-            for (int a = i; a < nl; ++a) s += Li(a, i) * Zc(a, j);
-            Qr(i, j) = s;
+    for (int a = 0; a < nl; ++a) {
+        const double* z = &Zc.a[(size_t)a * nl];
+        for (int i = 0; i <= a; ++i) {
+            const double l = Li(a, i);
+            double* q = &Qr.a[(size_t)i * nl];
+            for (int j = 0; j < nl; ++j) q[j] += l * z[j];
         }
+    }
     // beta of each Rayleigh-Ritz vector: theta averaged with weights Q^2
     std::vector<double> beta(nl);
     for (int j = 0; j < nl; ++j) {
@@ -288,7 +355,8 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
     if (!op || !desc) return fail(EW_ERR_INVALID_ARG, "null argument");
     const int k = desc->k, m = desc->m;
     const int64_t N = op->N;
-    if (k < 1 || m <= k || m > 256 || (int64_t)m > N) return fail(EW_ERR_INVALID_ARG, "need 1 <= k < m <= min(256, n_active)");
+    if (k < 1 || m <= k || m > kMaxKrylov || (int64_t)m > N)
+        return fail(EW_ERR_INVALID_ARG, "need 1 <= k < m <= min(" + std::to_string(kMaxKrylov) + ", n_active)");
     if (!(desc->tol_ritz > 0.0) || !(desc->tol_res > 0.0)) return fail(EW_ERR_INVALID_ARG, "tolerances must be > 0");
     if (desc->max_wave_solves < 1) return fail(EW_ERR_INVALID_ARG, "max_wave_solves must be >= 1");
     if (k_cap < 0 || (k_cap > 0 && (!mu_host || !beta_host || !res_host)))
@@ -344,7 +412,7 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
         }
         nlead = std::min(nlead, ws.cap_lock - nl);
         if (nlead <= 0) break;
-        EW_TRY(rotate(ws, ws.V, m, rr.Q, nlead, ws.col(ws.Y, nl)));
+        EW_TRY(rotate(ws, ws.V, rr.Q.n, rr.Q, nlead, ws.col(ws.Y, nl)));
         for (int c = 0; c < nlead; ++c) th_locked.push_back(rr.theta[c]);
         nl += nlead;
         if (budget_hit || nl >= ws.cap_lock) break;
@@ -383,6 +451,18 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
         stats->max_res = max_res;
     }
     if (budget_hit) return fail(EW_ERR_NOT_CONVERGED, "eigensolver reached max_wave_solves");
+    return EW_OK;
+}
+
+extern "C" ew_status ew_sym_eig(int n, const double* a_host, double* w_host, double* q_host) {
+    if (n < 1 || n > 8192 || !a_host || !w_host) return fail(EW_ERR_INVALID_ARG, "need 1 <= n <= 8192 and a, w");
+    Mat A(n, n);
+    std::memcpy(A.a.data(), a_host, (size_t)n * n * sizeof(double));
+    std::vector<double> w;
+    Mat Q;
+    sym_eigh(A, w, Q);
+    std::memcpy(w_host, w.data(), (size_t)n * sizeof(double));
+    if (q_host) std::memcpy(q_host, Q.a.data(), (size_t)n * n * sizeof(double));
     return EW_OK;
 }
 

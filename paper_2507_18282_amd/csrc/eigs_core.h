@@ -27,10 +27,14 @@ struct Workspace {
     double* LY = nullptr;      // N x cap_lock L_h applied to them / scratch
     double* Z = nullptr;       // N x cap_lock Rayleigh-Ritz vectors
     double* P = nullptr;       // 2 x kRedBlocks partial sums (ping-pong)
-    double* h_dev = nullptr;   // Gram-Schmidt coefficients of one step
+    double* h_dev = nullptr;   // Gram-Schmidt coefficients of one step (nu + 1)
+    double* h_cur = nullptr;   // coefficients of one block Gram-Schmidt pass
+    double* gs_partial = nullptr;  // block Gram-Schmidt dot partials
+    double* gs_tmp = nullptr;      // block Gram-Schmidt column-chunk products
     double* q_dev = nullptr;   // small matrices for basis rotations
     double* gram_dev = nullptr;
     double* h_host = nullptr;
+    int nu_max = 0;            // columns one orthogonalisation may involve
     std::vector<void*> owned;
     ~Workspace() {
         for (void* p : owned) hipFree(p);
@@ -42,21 +46,34 @@ struct Workspace {
         owned.push_back(*p);
         return EW_OK;
     }
-    // Allocate for Krylov dimension m and k wanted pairs.
+    // Allocate for Krylov dimension m and k wanted pairs.  The locked set holds
+    // up to 3m + k vectors, capped at max(320, m + k) (and at N).
     ew_status setup(int64_t n, int m_, int k) {
         N = n;
         m = m_;
-        cap_lock = (int)std::min<int64_t>(std::min<int64_t>(N, 3 * m + k), 320);
+        const int64_t cap = std::min<int64_t>(3 * (int64_t)m + k, std::max<int64_t>(320, (int64_t)m + k));
+        cap_lock = (int)std::min<int64_t>(N, cap);
+        nu_max = cap_lock + m + 2;
+        const int64_t qdim = std::max<int64_t>(m + 1, cap_lock);
         EW_TRY(alloc(&V, (size_t)N * (m + 1)));
         EW_TRY(alloc(&Vt, (size_t)N * (m + 1)));
         EW_TRY(alloc(&Y, (size_t)N * cap_lock));
         EW_TRY(alloc(&LY, (size_t)N * cap_lock));
         EW_TRY(alloc(&Z, (size_t)N * cap_lock));
         EW_TRY(alloc(&P, 2 * kRedBlocks));
-        EW_TRY(alloc(&h_dev, 4 * 256 + 64));
-        EW_TRY(alloc(&q_dev, (size_t)(4 * 256) * 256));
+        const size_t hlen = std::max<size_t>((size_t)nu_max + 64, 2 * kRedBlocks + 64);  // also Stage-2 partials
+        EW_TRY(alloc(&h_dev, hlen));
+        EW_TRY(alloc(&q_dev, (size_t)qdim * qdim));
         EW_TRY(alloc(&gram_dev, (size_t)kGramBlocks * 32 * 32));
-        EW_HIP_TRY(hipHostMalloc((void**)&h_host, (4 * 256 + 64) * sizeof(double), hipHostMallocDefault));
+        EW_HIP_TRY(hipHostMalloc((void**)&h_host, hlen * sizeof(double), hipHostMallocDefault));
+        return EW_OK;
+    }
+    // Buffers of the block Gram-Schmidt, allocated at its first use.
+    ew_status setup_block_gs() {
+        if (gs_tmp) return EW_OK;
+        EW_TRY(alloc(&h_cur, (size_t)nu_max + 64));
+        EW_TRY(alloc(&gs_partial, (size_t)kBlockGsMaxSlices * nu_max));
+        EW_TRY(alloc(&gs_tmp, (size_t)kBlockGsTmpDoubles));
         return EW_OK;
     }
     double* col(double* base, int j) const { return base + (int64_t)j * N; }
@@ -65,6 +82,11 @@ struct Workspace {
 // w <- w - sum_i (w, u_i) u_i by chained MGS links, then w <- w / ||w||;
 // coeff receives the coefficients and the norm.  Host-blocking.
 ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const double*>& u, std::vector<double>& coeff);
+// The same against the columns of [U1 (n1 columns) | U2 (n2 columns)]: MGS
+// links up to kMgsMaxCols columns, block CGS2 beyond.  Host-blocking.
+constexpr int kMgsMaxCols = 64;
+ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, const double* u2, int n2,
+                         std::vector<double>& coeff);
 // Y[:, 0:ncols] = X[:, 0:nx] Qm[0:nx, 0:ncols].  Host-blocking.
 ew_status rotate(Workspace& ws, const double* X, int nx, const Mat& Qm, int ncols, double* Y);
 int leading_converged(const std::vector<char>& conv);

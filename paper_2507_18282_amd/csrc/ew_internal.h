@@ -104,6 +104,23 @@ hipError_t launch_normalize_from_partial(const double* w, double* v, int64_t n, 
 // Y[:, c] = sum_i V[:, i] * Q[i + c*ldq], c < ncols, i < nv (column-major, leading dim n).
 hipError_t launch_tall_gemm(const double* V, int64_t n, int nv, const double* Q_dev, int ldq, int ncols, double* Y,
                             hipStream_t s);
+// One classical Gram-Schmidt pass of w against the columns of [U1 | U2]
+// (n1 + n2 columns of length n, column-major): h_cur = U^T w (h_tot = h_cur,
+// or += with accumulate), then w -= U h_cur.  Buffers: partial holds
+// nslices * (n1 + n2) doubles, tmp nchunks * n (<= kBlockGsTmpDoubles).
+constexpr int kBlockGsMaxSlices = 256;
+constexpr int kBlockGsMaxChunks = 128;
+constexpr int64_t kBlockGsTmpDoubles = (int64_t)1 << 20;
+struct BlockGsPlan {
+    int64_t slice;
+    int nslices;
+    int chunk;
+    int nchunks;
+};
+BlockGsPlan block_gs_plan(int64_t n, int nu);
+hipError_t launch_block_gs_pass(const double* u1, int n1, const double* u2, int n2, double* w, int64_t n,
+                                const BlockGsPlan& p, double* partial, double* h_cur, double* h_tot, int accumulate,
+                                double* tmp, hipStream_t s);
 // Partial Gram blocks: block b writes P_b[i*nb + j] = sum over its rows of A[:,i]*B[:,j]
 // (na, nb <= 32; partial holds nblocks*na*nb doubles).
 hipError_t launch_gram_partial(const double* A, int na, const double* B, int nb, int64_t n, double* partial,

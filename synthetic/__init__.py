@@ -121,6 +121,14 @@ def config_learned(n: int = 1023, omega: float = 90.0, k: int = 16, m: int = 32,
                    n_its=10, adjust_omega=True, mg_tol=1e-10, k=k, m=m, seed=seed)
 
 
+def config_many_pairs(k: int = 256, n: int = 127, omega: float = 12.0, seed: int = 6) -> Problem:
+    """The square128 grid (h = 1/128, 127^2 interior), order 2, implicit 10
+    steps per period with multigrid to 1e-10, omega = 12 (adjusted), one
+    period; k eigenpairs with a Krylov dimension of 2k + 1."""
+    return Problem(n=(n, n), length=(1.0, 1.0), order=2, omega=omega, ts="implicit",
+                   n_its=10, adjust_omega=True, mg_tol=1e-10, k=k, m=2 * k + 1, seed=seed)
+
+
 def batch_problems(count: int = 96, seed: int = 4, n_lo: int = 65, n_hi: int = 1025,
                    len_lo: float = 0.5, len_hi: float = 2.0, om_lo: float = 10.0,
                    om_hi: float = 80.0) -> List[Problem]:
