@@ -46,19 +46,12 @@ SMOOTH_SRC = os.path.join(ROOT, "paper_2507_18282_amd", "csrc", "sweep2d.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_square2047_order4.txt")
 
 
-def levels_to_63(n: int) -> int:
-    """Multigrid levels from n points per side down to 63 (n = 2^k - 1): on the
-    2D workloads here (dt^2/2)/h^2 is about 0.07 at 63^2, where M is so
-    diagonally dominant that MG_COARSE_SWEEPS red-black sweeps solve the level
-    (each reduces its error about tenfold) and coarser levels only add
-    latency-bound launches."""
-    levels = 1
-    while n > 63 and n % 2 == 1:
-        n = (n - 1) // 2
-        levels += 1
-    return levels
-
-
+# Multigrid depth of the implicit workloads: the library's automatic rule
+# (EW_MG_LEVELS_AUTO) ends the hierarchy on the first level that
+# MG_COARSE_SWEEPS red-black sweeps contract by 0.1 (on 2047^2 at omega 120 that
+# is 127^2, on 1023^2 at omega 90 it is 63^2); coarser levels only add
+# latency-bound launches there.
+MG_LEVELS = -1
 MG_COARSE_SWEEPS = 4
 
 
@@ -180,7 +173,7 @@ def learned_vs_plain():
     def make(omega, predictor):
         return Operator(n=P.n, length=P.length, order=P.order, omega=omega, ts=P.ts, n_its=P.n_its,
                         adjust_omega=P.adjust_omega, mg_tol=P.mg_tol, predictor=predictor,
-                        mg_max_levels=levels_to_63(n), mg_coarse_sweeps=MG_COARSE_SWEEPS)
+                        mg_max_levels=MG_LEVELS, mg_coarse_sweeps=MG_COARSE_SWEEPS)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -201,7 +194,7 @@ def learned_vs_plain():
     log(f"learned: {store.count} crops in {t_data:.2f} s, training {tr1['seconds'] + tr2['seconds']:.2f} s, "
         f"loss {tr1['first_loss']:.4g} -> {tr2['last_loss']:.4g}")
     out = {"workload": "unit square 1025^2 points (1023^2 interior), order 4, implicit 10 steps/period, omega "
-                       "40/90/140 (adjusted), FP64 multigrid to 1e-10 (levels 1023^2..63^2), k=16, m=32",
+                       "40/90/140 (adjusted), FP64 multigrid to 1e-10 (automatic depth, 4 sweeps on the coarsest level), k=16, m=32",
            "budget_wave_solves": LEARN_BUDGET,
            "data": {"crops": store.count, "crop": 128, "seconds": t_data},
            "training": {"steps": LEARN_STEPS, "batch": 16, "seconds": tr1["seconds"] + tr2["seconds"],
@@ -248,11 +241,11 @@ def periods_rule():
     n, omega, k = 255, 40.0, 8
     n_p, n_lobe = choose_periods((1.0, 1.0), omega, k)
     out = {"workload": "unit square 257^2 points (255^2 interior), order 4, implicit 10 steps/period, omega 40 "
-                       "(adjusted), FP64 multigrid to 1e-10, k=8, m=17, eig-res <= 1e-8",
+                       "(adjusted), FP64 multigrid to 1e-10 (automatic depth), k=8, m=17, eig-res <= 1e-8",
            "rule": {"n_p": n_p, "eigenvalues_in_lobe": n_lobe}}
     for label, npp, budget in (("np1", 1, PERIODS_BUDGET_NP1), ("rule", n_p, 100000)):
         op = Operator(n=(n, n), length=(1.0, 1.0), order=4, omega=omega, ts="implicit", n_its=10, n_p=npp,
-                      adjust_omega=True, mg_tol=1e-10)
+                      adjust_omega=True, mg_tol=1e-10, mg_max_levels=MG_LEVELS, mg_coarse_sweeps=MG_COARSE_SWEEPS)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = op.eigs(k, 2 * k + 1, seed=3, tol_res=1e-8, max_wave_solves=budget, want_vectors=False,
@@ -265,6 +258,47 @@ def periods_rule():
                     "eigenpairs_per_s": ok / dt, "time_steps_per_eigenpair": r.time_steps / ok if ok else None,
                     "status": r.status})
         log(f"periods rule: N_p {npp}: {ok} pairs, {r.wave_solves} wave-solves, {dt:.2f} s")
+        op.close()
+    return out
+
+
+# Requested-eigenpairs table of the paper (Sec. "Changing the number of
+# requested eigenpairs"; square128, omega 12, N_a = 2 N_r + 1): requested ->
+# (converged, wave-solves), measured on CPUs with SLEPc.
+MANY_PAIRS_PAPER = {16: (16, 64), 64: (65, 209), 256: (285, 675), 512: (571, 1325)}
+
+
+def many_pairs(ks=None):
+    """The square128 grid (127^2 interior), order 2, implicit 10 steps/period,
+    omega 12 (adjusted), FP64 multigrid to 1e-10, one period: k eigenpairs at
+    once with a Krylov dimension of 2k + 1, for k = 16, 64, 256, 512."""
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Operator
+    out = {"workload": "unit square 129^2 points (127^2 interior, h=1/128), order 2, implicit 10 steps/period, "
+                       "omega 12 (adjusted), FP64 multigrid to 1e-10 (automatic depth: 127^2..15^2), N_p 1, "
+                       "Krylov dimension 2k+1, "
+                       "tol_ritz 1e-12, eig-res <= 1e-8"}
+    for k in (ks or sorted(MANY_PAIRS_PAPER)):
+        P = synthetic.config_many_pairs(k=k)
+        op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its,
+                      adjust_omega=P.adjust_omega, mg_tol=P.mg_tol, mg_max_levels=MG_LEVELS,
+                      mg_coarse_sweeps=MG_COARSE_SWEEPS)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.eigs(P.k, P.m, seed=P.seed, want_vectors=False, k_cap=3 * k, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        conv, ws = MANY_PAIRS_PAPER.get(k, (None, None))
+        out[f"k_{k}"] = {"m": P.m, "converged": r.n_conv, "wave_solves": r.wave_solves, "restarts": r.restarts,
+                         "probes": r.probes, "wave_solves_per_eigenpair": r.wave_solves / max(1, r.n_conv),
+                         "seconds": dt, "eigenpairs_per_s": r.n_conv / dt, "max_res": max(r.res) if r.res else None,
+                         "status": r.status,
+                         "paper": ({"converged": conv, "wave_solves": ws, "wave_solves_per_eigenpair": ws / conv}
+                                   if conv else None)}
+        log(f"many pairs: k {k} m {P.m}: {r.n_conv} converged, {r.wave_solves} wave-solves "
+            f"({r.wave_solves / max(1, r.n_conv):.2f} per pair" + (f"; paper {ws / conv:.2f}" if conv else "") +
+            f"), {dt:.2f} s")
         op.close()
     return out
 
@@ -312,6 +346,10 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-solves", type=int, default=4)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and mixed-precision comparisons")
     ap.add_argument("--batch-budget", type=int, default=150, help="wave-solves per problem in the batch comparison")
+    ap.add_argument("--many-k", type=int, nargs="*", default=None,
+                    help="requested counts of the many-pairs form (default: the paper's table rows)")
+    ap.add_argument("--only-many-pairs", action="store_true",
+                    help="run only the many-pairs form and print its JSON (for profiling)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU decomposition is "
@@ -322,11 +360,18 @@ def main(argv=None) -> int:
     from paper_2507_18282_amd import Operator
 
     torch.cuda.set_device(0)
+    if a.only_many_pairs:
+        print(json.dumps({"form": "many_pairs", "result": many_pairs(a.many_k)}), flush=True)
+        return 0
     P = synthetic.config_square_order4_implicit()
     op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=P.n_p,
                   adjust_omega=P.adjust_omega, precision=P.precision, mg_tol=P.mg_tol,
-                  mg_max_levels=levels_to_63(P.n[0]), mg_coarse_sweeps=MG_COARSE_SWEEPS)
-    log(f"workload {P.n} order {P.order} n_t {op.n_t} omega_used {op.omega_used:.4f} levels {op.mg_levels}")
+                  mg_max_levels=MG_LEVELS, mg_coarse_sweeps=MG_COARSE_SWEEPS)
+    coarsest = P.n[0]
+    for _ in range(op.mg_levels - 1):
+        coarsest = (coarsest - 1) // 2
+    log(f"workload {P.n} order {P.order} n_t {op.n_t} omega_used {op.omega_used:.4f} levels {op.mg_levels} "
+        f"(coarsest {coarsest}^2)")
     if a.warmup > 0:
         op.eigs(P.k, P.m, seed=P.seed, max_wave_solves=a.warmup, want_vectors=False, raise_on_error=False)
     log("warmup done")
@@ -384,6 +429,7 @@ def main(argv=None) -> int:
         forms["mixed_cube"] = mixed_cube()
         forms["learned_vs_plain"] = learned_vs_plain()
         forms["periods_rule"] = periods_rule()
+        forms["many_pairs"] = many_pairs(a.many_k)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -395,7 +441,7 @@ def main(argv=None) -> int:
         "warmup": a.warmup, "ms_per_step": elapsed / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "unit square 2049^2 points (2047^2 interior, h=1/2048), 4th-order Laplacian, "
-                               "implicit 10 steps/period, FP64 multigrid V(2,1) (levels 2047^2..63^2, 4 sweeps on 63^2) to rel. "
+                               f"implicit 10 steps/period, FP64 multigrid V(2,1) (levels 2047^2..{coarsest}^2, {MG_COARSE_SWEEPS} sweeps on {coarsest}^2) to rel. "
                                "residual 1e-10, "
                                "omega 120 (adjusted 109.7306), Arnoldi m=32 for k=16, seed 2",
                    "global_batch": 1, "parallelism": "single GPU"},

@@ -119,7 +119,14 @@ typedef struct {
  *                      and >= 3.  A truncated hierarchy ends on a level that
  *                      gets mg_coarse_sweeps sweeps, which solve it well when
  *                      (dt^2/2)/h_coarse^2 is small (M is then strongly
- *                      diagonally dominant). */
+ *                      diagonally dominant).  EW_MG_LEVELS_AUTO (-1): stop
+ *                      at the first level whose Gauss-Seidel contraction
+ *                      bound, rho_J^2 with rho_J the ratio of M's
+ *                      off-diagonal row sum to its diagonal (a = dt^2/2:
+ *                      2 a S / (1 + 2 a S) for order 2, (34/12) a S /
+ *                      (1 + (30/12) a S) for order 4, S = sum_d 1/h_d^2 on
+ *                      that level), raised to mg_coarse_sweeps, is <= 0.1. */
+enum { EW_MG_LEVELS_AUTO = -1 };
 typedef struct {
     double omega;
     int ts;

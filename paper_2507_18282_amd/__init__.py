@@ -91,7 +91,7 @@ class Operator:
         d.mg_coarse_points = int(mg_coarse_points)
         d.predictor = _lib.PREDICTOR[predictor]
         d.proj_window = int(proj_window)
-        d.mg_max_levels = int(mg_max_levels)
+        d.mg_max_levels = -1 if mg_max_levels == "auto" else int(mg_max_levels)
         self._stream = stream
         self._h = ctypes.c_void_p()
         check(lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)),

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
         rv[t] = uc + r / mdiag_at<T, ORDER, DIM>(gi, gj, gk, g, a);
         rp[t] = p;
     }
-    __syncthreads();
+    if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
 #pragma unroll
     for (int t = 0; t < RED_ITERS; ++t)
         if (rp[t] >= 0) X[rp[t]] = rv[t];
@@ -400,7 +400,10 @@ __device__ void pad_half_sweep(T* x, const T* b, const Geo& g, T a, int colour) 
         nv[t] = edge ? xc + r / mdiag_at<T, ORDER, DIM>(i, j, k, g, a) : xc + r * inv_diag;
         np[t] = p;
     }
-    __syncthreads();
+    // Order 4 reads same-colour neighbours (old values) that other threads are
+    // about to overwrite; order 2 reads only the other colour, and each point
+    // of this colour only by the thread that updates it.
+    if (ORDER == 4) __syncthreads();
 #pragma unroll
     for (int t = 0; t < kCoarseColourIters; ++t)
         if (np[t] >= 0) x[np[t]] = nv[t];

@@ -164,7 +164,8 @@ ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
             d->predictor != EW_PRED_EXTRAP && d->predictor != EW_PRED_PROJ)
             return fail(EW_ERR_INVALID_ARG, "unknown predictor");
         if (d->proj_window > 32) return fail(EW_ERR_INVALID_ARG, "proj_window must be at most 32");
-        if (d->mg_max_levels < 0) return fail(EW_ERR_INVALID_ARG, "mg_max_levels must be >= 0");
+        if (d->mg_max_levels < EW_MG_LEVELS_AUTO)
+            return fail(EW_ERR_INVALID_ARG, "mg_max_levels must be >= 0 or EW_MG_LEVELS_AUTO");
         if (d->predictor == EW_PRED_CNN && (g->dim != 2))
             return fail(EW_ERR_UNSUPPORTED, "the learned predictor is implemented for 2D grids");
     }
@@ -177,7 +178,22 @@ ew_status Op::build_hierarchy() {
     std::array<int64_t, 3> cur = {n[0], n[1], dim == 3 ? n[2] : 1};
     sizes.push_back(cur);
     const size_t max_levels = desc.mg_max_levels > 0 ? (size_t)desc.mg_max_levels : 64;
+    // EW_MG_LEVELS_AUTO: level l (spacings h 2^l) ends the hierarchy once
+    // mg_coarse_sweeps Gauss-Seidel sweeps contract it by 0.1 (Gershgorin
+    // bound of the Jacobi radius, squared for red-black Gauss-Seidel).
+    auto coarse_enough = [&](size_t l) -> bool {
+        double s = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            const double hl = h[k] * std::ldexp(1.0, (int)l);
+            s += 1.0 / (hl * hl);
+        }
+        const double off = (order == 2 ? 2.0 : 34.0 / 12.0) * a * s;
+        const double diag = 1.0 + (order == 2 ? 2.0 : 30.0 / 12.0) * a * s;
+        const double rho_gs = (off / diag) * (off / diag);
+        return off < diag && std::pow(rho_gs, desc.mg_coarse_sweeps) <= 0.1;
+    };
     while (sizes.size() < max_levels) {
+        if (desc.mg_max_levels == EW_MG_LEVELS_AUTO && coarse_enough(sizes.size() - 1)) break;
         bool ok = true;
         for (int k = 0; k < dim; ++k) ok = ok && (cur[k] % 2 == 1) && cur[k] >= 3;
         if (!ok) break;

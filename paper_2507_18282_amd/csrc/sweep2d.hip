@@ -166,7 +166,9 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
             rp[NRP] = (by + H - 1) * LX + c + H;
         }
     }
-    __syncthreads();
+    // order 4 reads red neighbours (old values) that other lanes overwrite;
+    // order 2 reads each red point only in the lane that updates it
+    if (ORDER == 4) __syncthreads();
 #pragma unroll
     for (int t = 0; t <= NRP; ++t)
         if (rp[t] >= 0) X[rp[t]] = rv[t];
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
             rv[t] = relax(gi, gj);
             rp[t] = (gj - y0 + H) * LX + (gi - x0 + H);
         }
-        __syncthreads();
+        if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
 #pragma unroll
         for (int t = 0; t < IT; ++t)
             if (rp[t] >= 0) X[rp[t]] = rv[t];

@@ -1,9 +1,10 @@
 """Parity at the full sizes of the measured workloads, in the launch
 configuration the benchmark times.
 
-* 2047^2 order-4 implicit (the headline, multigrid levels 2047^2..63^2 with 4
-  sweeps on 63^2): S v against the oracle's exact (sine-transform) implicit
-  solves, and S phi = beta~(mu) phi for sine modes (closed form).
+* 2047^2 order-4 implicit (the headline, multigrid of automatic depth, which
+  ends on 127^2 with 4 sweeps there): S v against the oracle's exact
+  (sine-transform) implicit solves, and S phi = beta~(mu) phi for sine modes
+  (closed form).
 * 255^3 order-2 implicit in mixed precision: sine modes against the closed
   form, and mixed against FP64 on a random vector.
 * the 96-rectangle batch: one sine mode per problem against the closed form.
@@ -27,7 +28,7 @@ from tests.gpu_helpers import oracle_plan, rel_err, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-HEADLINE_MG = dict(mg_max_levels=6, mg_coarse_sweeps=4)  # the benchmark's hierarchy for 2047^2
+HEADLINE_MG = dict(mg_max_levels=-1, mg_coarse_sweeps=4)  # the benchmark's hierarchy for 2047^2
 
 
 def _op(P, **kw):
@@ -42,7 +43,7 @@ def test_headline_filter_full_size_matches_oracle():
     P = synthetic.config_square_order4_implicit()
     say("full size 2047^2 S v")
     op = _op(P, **HEADLINE_MG)
-    assert op.mg_levels == 6
+    assert op.mg_levels == 5  # 2047^2 .. 127^2
     h, plan = oracle_plan(P)
     v = synthetic.uniform_pm1(P.seed, P.n_active)
     got = to_host(op.apply_filter(to_dev(v)))

@@ -165,6 +165,57 @@ def test_truncated_hierarchy_vcycle_and_solve_match_oracle(P, max_levels):
     assert abs(cycles - oc) <= 1
 
 
+def _auto_levels(P, a, sweeps):
+    """Depth the automatic rule documented for EW_MG_LEVELS_AUTO keeps: the
+    first level whose red-black Gauss-Seidel bound (Gershgorin ratio of M,
+    squared) to the power `sweeps` is <= 0.1, else the full hierarchy."""
+    h0 = D.spacing(P.n, P.length)
+    n = list(P.n)
+    levels = 1
+    while True:
+        s = sum(1.0 / (hd * 2.0 ** (levels - 1)) ** 2 for hd in h0)
+        off = (2.0 if P.order == 2 else 34.0 / 12.0) * a * s
+        diag = 1.0 + (2.0 if P.order == 2 else 30.0 / 12.0) * a * s
+        if off < diag and (off / diag) ** (2 * sweeps) <= 0.1:
+            return levels
+        if not all(k % 2 == 1 and k >= 3 for k in n):
+            return levels
+        n = [(k - 1) // 2 for k in n]
+        levels += 1
+
+
+AUTO_CASES = IMPLICIT_CASES[:3] + [
+    synthetic.config_many_pairs(k=16),                                          # ends on 15^2
+    synthetic.config_square_order4_implicit(n=255),                              # ends on 127^2
+    synthetic.config_learned(n=255, omega=40.0),
+]
+
+
+@pytest.mark.parametrize("P", AUTO_CASES, ids=lambda P: f"{P.n}-o{P.order}-w{P.omega:g}")
+def test_auto_depth_vcycle_and_solve_match_oracle(P):
+    """mg_max_levels = -1 picks the depth by its documented bound; the V-cycle
+    then matches the oracle hierarchy of that depth (4 sweeps on the last
+    level) and solves reach the exact solution to mg_tol."""
+    op = make_op(P, mg_max_levels=-1, mg_coarse_sweeps=4)
+    h, plan = oracle_plan(P)
+    a = 0.5 * plan.dt ** 2
+    want_levels = _auto_levels(P, a, 4)
+    assert op.mg_levels == want_levels
+    hier = OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=4,
+                         max_levels=want_levels)
+    shape = P.n[::-1]
+    b = synthetic.uniform_pm1(25, P.n_active)
+    x = synthetic.uniform_pm1(26, P.n_active)
+    say("auto depth vcycle", P.n, P.order, want_levels)
+    got = to_host(op.mg_vcycle(to_dev(b), to_dev(x)))
+    want = OMG.vcycle(x.reshape(shape), b.reshape(shape), hier).ravel()
+    assert rel_err(got, want) < 1e-12
+    xd, cycles, rel = op.mg_solve(to_dev(b), to_dev(np.zeros(P.n_active)))
+    xe = W.solve_implicit_exact(b.reshape(shape), h, P.order, plan.dt).ravel()
+    assert rel <= P.mg_tol
+    assert np.linalg.norm(to_host(xd) - xe) <= P.mg_tol * np.linalg.norm(b) * 1.0001
+
+
 @pytest.mark.parametrize("coarse_points", [0, 40])
 @pytest.mark.parametrize("P", IMPLICIT_CASES, ids=lambda P: f"{P.n}-o{P.order}")
 def test_mg_solve_reaches_exact_solution(P, coarse_points):
