@@ -5,10 +5,86 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 namespace ew {
+
+// A small pool of host threads for the O(n^3) loops of the large projected
+// problems: run(f) calls f(t) once on every thread t of the pool (t = 0 is the
+// calling thread) and returns when all have finished.  Thread t always gets
+// index t, so a caller that partitions data by t keeps each part in the same
+// core's cache from call to call.
+class HostPool {
+public:
+    explicit HostPool(int nthreads) {
+        for (int t = 1; t < nthreads; ++t) workers_.emplace_back([this, t] { loop(t); });
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_.store(true);
+        }
+        cv_.notify_all();
+        for (auto& w : workers_) w.join();
+    }
+    int size() const { return (int)workers_.size() + 1; }
+    void run(const std::function<void(int)>& f) {
+        if (workers_.empty()) {
+            f(0);
+            return;
+        }
+        job_ = &f;
+        remaining_.store((int)workers_.size(), std::memory_order_relaxed);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            gen_.fetch_add(1, std::memory_order_release);
+        }
+        cv_.notify_all();
+        f(0);
+        while (remaining_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
+    }
+    // threads for the projected problems: the host's cores, at most 16
+    static int default_threads() {
+        const unsigned hc = std::thread::hardware_concurrency();
+        return (int)std::max(1u, std::min(hc, 16u));
+    }
+
+private:
+    // Workers poll for the next job for a while (runs come in quick
+    // succession during a decomposition), then sleep on the condition variable.
+    void loop(int t) {
+        uint64_t seen = 0;
+        for (;;) {
+            uint64_t g;
+            int polls = 0;
+            while ((g = gen_.load(std::memory_order_acquire)) == seen && !stop_.load()) {
+                if (++polls < 4096) {
+                    std::this_thread::yield();
+                    continue;
+                }
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_.load() || gen_.load() != seen; });
+            }
+            if (stop_.load()) return;
+            seen = g;
+            (*job_)(t);
+            remaining_.fetch_sub(1, std::memory_order_release);
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    const std::function<void(int)>* job_ = nullptr;
+    std::atomic<int> remaining_{0};
+    std::atomic<uint64_t> gen_{0};
+    std::atomic<bool> stop_{false};
+};
 
 // Row-major n x n matrix helper.
 struct Mat {
@@ -74,6 +150,17 @@ inline void jacobi_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
 // Returns false if the QR iteration has not converged after 30 n steps.
 inline bool tridiag_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
     const int n = A.n;
+    HostPool pool(n >= 200 ? HostPool::default_threads() : 1);
+    // [lo, hi) split into one contiguous range per pool thread (range t to thread t)
+    auto split = [&](int lo, int hi, const std::function<void(int, int)>& f) {
+        const int len = hi - lo;
+        if (len <= 0) return;
+        const int parts = pool.size();
+        pool.run([&](int t) {
+            const int a = lo + (int)((int64_t)len * t / parts), b = lo + (int)((int64_t)len * (t + 1) / parts);
+            if (a < b) f(a, b);
+        });
+    };
     std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
     // Householder vectors, v[k] of length n - k - 1 with leading 1, and betas
     std::vector<std::vector<double>> hv(n > 2 ? n - 2 : 0);
@@ -99,21 +186,25 @@ inline bool tridiag_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
         hb[k] = beta;
         if (beta != 0.0) {
             // p = beta A22 v, w = p - (beta p^T v / 2) v, A22 -= v w^T + w v^T
+            split(0, len, [&](int i0, int i1) {
+                for (int i = i0; i < i1; ++i) {
+                    const double* row = &A.a[(size_t)(k + 1 + i) * n + (k + 1)];
+                    double s = 0.0;
+                    for (int j = 0; j < len; ++j) s += row[j] * v[j];
+                    p[i] = beta * s;
+                }
+            });
             double pv = 0.0;
-            for (int i = 0; i < len; ++i) {
-                const double* row = &A.a[(size_t)(k + 1 + i) * n + (k + 1)];
-                double s = 0.0;
-                for (int j = 0; j < len; ++j) s += row[j] * v[j];
-                p[i] = beta * s;
-                pv += p[i] * v[i];
-            }
+            for (int i = 0; i < len; ++i) pv += p[i] * v[i];
             const double half = 0.5 * beta * pv;
             for (int i = 0; i < len; ++i) wv[i] = p[i] - half * v[i];
-            for (int i = 0; i < len; ++i) {
-                double* row = &A.a[(size_t)(k + 1 + i) * n + (k + 1)];
-                const double vi = v[i], wi = wv[i];
-                for (int j = 0; j < len; ++j) row[j] -= vi * wv[j] + wi * v[j];
-            }
+            split(0, len, [&](int i0, int i1) {
+                for (int i = i0; i < i1; ++i) {
+                    double* row = &A.a[(size_t)(k + 1 + i) * n + (k + 1)];
+                    const double vi = v[i], wi = wv[i];
+                    for (int j = 0; j < len; ++j) row[j] -= vi * wv[j] + wi * v[j];
+                }
+            });
         }
         A(k + 1, k) = A(k, k + 1) = alpha;
         for (int i = 2; i <= len; ++i) A(k + i, k) = A(k, k + i) = 0.0;
@@ -122,26 +213,38 @@ inline bool tridiag_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
     for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
     // Q = H_0 H_1 ... H_{n-3} by backward accumulation, stored transposed:
     // Zt = Q^T, so H_k applied on the left of Q's trailing block is applied on
-    // the right of Zt's trailing block.
+    // the right of Zt's trailing block.  Row r changes only through the H_k
+    // with k < r, so each thread takes a range of rows through all k.
     Mat Zt(n, n);
     for (int i = 0; i < n; ++i) Zt(i, i) = 1.0;
-    for (int k = n - 3; k >= 0; --k) {
-        if (hb[k] == 0.0) continue;
-        const int len = n - k - 1;
-        const std::vector<double>& v = hv[k];
-        // Zt[r, k+1:] -= beta (Zt[r, k+1:] . v) v for rows r >= k+1
-        for (int r = k + 1; r < n; ++r) {
-            double* row = &Zt.a[(size_t)r * n + (k + 1)];
-            double s = 0.0;
-            for (int j = 0; j < len; ++j) s += row[j] * v[j];
-            s *= hb[k];
-            if (s != 0.0)
-                for (int j = 0; j < len; ++j) row[j] -= s * v[j];
+    split(0, n, [&](int r0, int r1) {
+        for (int k = n - 3; k >= 0; --k) {
+            if (hb[k] == 0.0) continue;
+            const int len = n - k - 1;
+            const std::vector<double>& v = hv[k];
+            // Zt[r, k+1:] -= beta (Zt[r, k+1:] . v) v for rows r >= k+1
+            for (int r = std::max(r0, k + 1); r < r1; ++r) {
+                double* row = &Zt.a[(size_t)r * n + (k + 1)];
+                double s = 0.0;
+                for (int j = 0; j < len; ++j) s += row[j] * v[j];
+                s *= hb[k];
+                if (s != 0.0)
+                    for (int j = 0; j < len; ++j) row[j] -= s * v[j];
+            }
         }
-    }
-    // implicit QR on (d, e); rotations applied to rows of Zt
+    });
+    // implicit QR on (d, e); the rotations are logged, then applied to the
+    // rows of Zt in one pass at the end, each thread taking a range of
+    // columns through the whole log (the same operations in the same order
+    // for every element, whatever the thread count)
     const double eps = 2.220446049250313e-16;
     const double tiny = 1e-300;
+    struct Rot {
+        int k;
+        double c, s;
+    };
+    std::vector<Rot> log;
+    log.reserve((size_t)n * 8);
     int hi = n - 1;
     int64_t steps = 0;
     while (hi > 0) {
@@ -174,19 +277,39 @@ inline bool tridiag_eigh(Mat& A, std::vector<double>& w, Mat& Q) {
                 e[k + 1] *= c;
                 x = e[k];
             }
-            double* rk = &Zt.a[(size_t)k * n];
-            double* rk1 = &Zt.a[(size_t)(k + 1) * n];
-            for (int j = 0; j < n; ++j) {
-                const double u = rk[j], t = rk1[j];
-                rk[j] = c * u + s * t;
-                rk1[j] = c * t - s * u;
-            }
+            log.push_back({k, c, s});
         }
     }
+    // Each thread copies its columns of Zt into a contiguous panel (rows of
+    // the panel stay within a few pages, so the long rotation log runs
+    // without TLB misses), applies the log, and writes its rows of Q = Zt^T.
     w = d;
     Q = Mat(n, n);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) Q(i, j) = Zt(j, i);
+    const int nb8 = (n + 7) / 8;
+    pool.run([&](int t) {
+        const int parts = pool.size();
+        const int j0 = std::min(n, 8 * (int)((int64_t)nb8 * t / parts));
+        const int j1 = std::min(n, 8 * (int)((int64_t)nb8 * (t + 1) / parts));
+        const int pw = j1 - j0;
+        if (pw <= 0) return;
+        std::vector<double> panel((size_t)n * pw);
+        for (int r = 0; r < n; ++r)
+            std::copy(&Zt.a[(size_t)r * n + j0], &Zt.a[(size_t)r * n + j1], &panel[(size_t)r * pw]);
+        for (const Rot& q : log) {
+            double* rk = &panel[(size_t)q.k * pw];
+            double* rk1 = rk + pw;
+            const double c = q.c, s = q.s;
+            for (int j = 0; j < pw; ++j) {
+                const double u = rk[j], v = rk1[j];
+                rk[j] = c * u + s * v;
+                rk1[j] = c * v - s * u;
+            }
+        }
+        for (int i = j0; i < j1; ++i) {
+            double* qrow = &Q.a[(size_t)i * n];
+            for (int r = 0; r < n; ++r) qrow[r] = panel[(size_t)r * pw + (i - j0)];
+        }
+    });
     return true;
 }
 
