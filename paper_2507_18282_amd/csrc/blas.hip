@@ -219,6 +219,93 @@ __global__ __launch_bounds__(256) void k_block_axpy_sum(const double* __restrict
     w[r] -= v;
 }
 
+// ---------------------------------------------------------------------------
+// Modified Gram-Schmidt of one short vector (n <= kMgsSmallMax) in a single
+// workgroup: w stays in registers (PTS points per thread), each basis column
+// is read once (its next column is loaded while the current inner product is
+// reduced), and every inner product is a fixed-order workgroup reduction, so
+// results are repeatable.  h_out[0:nu] receives the coefficients and h_out[nu]
+// the norm before normalisation; w is overwritten by w / ||w||.  Replaces the
+// chain of nu + 2 launches that latency dominates on grids of a few thousand
+// points.
+// ---------------------------------------------------------------------------
+constexpr int kMgsSmallThreads = 1024;
+
+__device__ __forceinline__ double wg_sum_1024(double v, double* red) {
+    // red: 16 doubles of this round's buffer; every thread gets the same total
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t += red[i];
+    return t;
+}
+
+template <int PTS>
+__global__ __launch_bounds__(kMgsSmallThreads) void k_mgs_small(ColPair U, int nu, double* __restrict__ w, int n,
+                                                                double* __restrict__ h_out) {
+    __shared__ double red[2][16];
+    const int tid = threadIdx.x;
+    double wr[PTS], ua[PTS], ub[PTS];
+#pragma unroll
+    for (int t = 0; t < PTS; ++t) {
+        const int q = tid + t * kMgsSmallThreads;
+        wr[t] = q < n ? w[q] : 0.0;
+    }
+    if (nu > 0) {
+        const double* u0 = col_at(U, 0, n);
+#pragma unroll
+        for (int t = 0; t < PTS; ++t) {
+            const int q = tid + t * kMgsSmallThreads;
+            ua[t] = q < n ? u0[q] : 0.0;
+        }
+    }
+    for (int c = 0; c < nu; ++c) {
+        // prefetch the next column
+        if (c + 1 < nu) {
+            const double* un = col_at(U, c + 1, n);
+#pragma unroll
+            for (int t = 0; t < PTS; ++t) {
+                const int q = tid + t * kMgsSmallThreads;
+                ub[t] = q < n ? un[q] : 0.0;
+            }
+        }
+        double part = 0.0;
+#pragma unroll
+        for (int t = 0; t < PTS; ++t) part += wr[t] * ua[t];
+        const double h = wg_sum_1024(part, red[c & 1]);
+#pragma unroll
+        for (int t = 0; t < PTS; ++t) wr[t] -= h * ua[t];
+        if (tid == 0) h_out[c] = h;
+#pragma unroll
+        for (int t = 0; t < PTS; ++t) ua[t] = ub[t];
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int t = 0; t < PTS; ++t) part += wr[t] * wr[t];
+    const double nrm = sqrt(wg_sum_1024(part, red[nu & 1]));
+    if (tid == 0) h_out[nu] = nrm;
+#pragma unroll
+    for (int t = 0; t < PTS; ++t) {
+        const int q = tid + t * kMgsSmallThreads;
+        if (q < n) w[q] = wr[t] / nrm;
+    }
+}
+
+hipError_t launch_mgs_small(const double* u1, int n1, const double* u2, int n2, double* w, int64_t n, double* h_out,
+                            hipStream_t s) {
+    if (n < 1 || n > kMgsSmallMax || n1 < 0 || n2 < 0) return hipErrorInvalidValue;
+    const ColPair U{u1, n1, u2};
+    const int nu = n1 + n2, ni = (int)n;
+    if (n <= 4 * kMgsSmallThreads)
+        k_mgs_small<4><<<1, kMgsSmallThreads, 0, s>>>(U, nu, w, ni, h_out);
+    else
+        k_mgs_small<8><<<1, kMgsSmallThreads, 0, s>>>(U, nu, w, ni, h_out);
+    return hipGetLastError();
+}
+
 BlockGsPlan block_gs_plan(int64_t n, int nu) {
     BlockGsPlan p{};
     // dot: at least 4096 wavefronts where the slices stay >= 1024 rows

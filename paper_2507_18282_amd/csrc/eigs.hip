@@ -48,6 +48,16 @@ ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const d
 ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, const double* u2, int n2,
                          std::vector<double>& coeff) {
     const int nu = n1 + n2;
+    if (ws.N <= kMgsSmallMax && nu <= kMgsMaxCols) {
+        // short vectors, short basis: the whole modified Gram-Schmidt in one workgroup
+        EW_HIP_TRY(launch_mgs_small(u1, n1, u2, n2, w, ws.N, ws.h_dev, ws.stream));
+        EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, ws.stream));
+        EW_HIP_TRY(hipStreamSynchronize(ws.stream));
+        coeff.assign(ws.h_host, ws.h_host + nu + 1);
+        for (double v : coeff)
+            if (!std::isfinite(v)) return fail(EW_ERR_NONFINITE, "non-finite value in Gram-Schmidt");
+        return EW_OK;
+    }
     if (nu <= kMgsMaxCols) {
         std::vector<const double*> u;
         u.reserve(nu);

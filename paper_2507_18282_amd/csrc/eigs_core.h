@@ -82,8 +82,10 @@ struct Workspace {
 // w <- w - sum_i (w, u_i) u_i by chained MGS links, then w <- w / ||w||;
 // coeff receives the coefficients and the norm.  Host-blocking.
 ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const double*>& u, std::vector<double>& coeff);
-// The same against the columns of [U1 (n1 columns) | U2 (n2 columns)]: MGS
-// links up to kMgsMaxCols columns, block CGS2 beyond.  Host-blocking.
+// The same against the columns of [U1 (n1 columns) | U2 (n2 columns)]: up to
+// kMgsMaxCols columns by MGS (in one workgroup for vectors of at most
+// kMgsSmallMax points, else by chained links), block CGS2 beyond.
+// Host-blocking.
 constexpr int kMgsMaxCols = 64;
 ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, const double* u2, int n2,
                          std::vector<double>& coeff);

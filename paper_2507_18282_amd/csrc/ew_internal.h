@@ -121,6 +121,12 @@ BlockGsPlan block_gs_plan(int64_t n, int nu);
 hipError_t launch_block_gs_pass(const double* u1, int n1, const double* u2, int n2, double* w, int64_t n,
                                 const BlockGsPlan& p, double* partial, double* h_cur, double* h_tot, int accumulate,
                                 double* tmp, hipStream_t s);
+// Modified Gram-Schmidt of w (n <= kMgsSmallMax points) against the columns of
+// [U1 | U2] in one workgroup: h_out[0:n1+n2] = coefficients, h_out[n1+n2] =
+// norm, w normalised.
+constexpr int64_t kMgsSmallMax = 8192;  // 8 points per thread of 1024 (registers, no spills)
+hipError_t launch_mgs_small(const double* u1, int n1, const double* u2, int n2, double* w, int64_t n, double* h_out,
+                            hipStream_t s);
 // Partial Gram blocks: block b writes P_b[i*nb + j] = sum over its rows of A[:,i]*B[:,j]
 // (na, nb <= 32; partial holds nblocks*na*nb doubles).
 hipError_t launch_gram_partial(const double* A, int na, const double* B, int nb, int64_t n, double* partial,

@@ -25,7 +25,10 @@ def closed_form(P):
 def check_result(P, r, rel_tol=1e-10, res_tol=1e-8):
     mu_all, beta_all, beta_k = closed_form(P)
     mu = np.array(r.mu)
-    assert r.n_conv >= P.k
+    if res_tol is not None:
+        assert r.n_conv >= P.k
+    else:
+        assert len(mu) >= P.k
     for x in mu:
         assert np.min(np.abs(mu_all - x)) / x < rel_tol
     band = np.sort(mu_all[np.abs(beta_all) >= beta_k * (1 - 1e-10)])
