@@ -268,6 +268,38 @@ def periods_rule():
 MANY_PAIRS_PAPER = {16: (16, 64), 64: (65, 209), 256: (285, 675), 512: (571, 1325)}
 
 
+def headline_np_rule(budget: int = 200):
+    """The headline eigenproblem (2047^2, order 4, implicit, omega 120, k = 16)
+    with N_p from the lobe rule and m = 2k + 1, within `budget` wave-solves.
+    At N_p = 1 the lobe holds about 1000 eigenvalues above beta 0.8 and the
+    solve does not finish; the rule's N_p narrows it to about k."""
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Operator, choose_periods
+    P = synthetic.config_square_order4_implicit()
+    n_p, n_lobe = choose_periods(P.length, P.omega, P.k)
+    op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=n_p,
+                  adjust_omega=P.adjust_omega, mg_tol=P.mg_tol, mg_max_levels=MG_LEVELS,
+                  mg_coarse_sweeps=MG_COARSE_SWEEPS)
+    log(f"headline with the N_p rule: N_p {n_p} ({n_lobe} eigenvalues in the lobe), budget {budget} wave-solves")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = op.eigs(P.k, 2 * P.k + 1, seed=P.seed, want_vectors=False, max_wave_solves=budget, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = sum(1 for x in r.res if x <= 1e-8)
+    log(f"headline with the N_p rule: {ok} pairs, {r.wave_solves} wave-solves, {r.restarts} restarts, "
+        f"{r.probes} runs, {dt:.1f} s")
+    out = {"workload": "unit square 2049^2 points (2047^2 interior), order 4, implicit 10 steps/period, omega 120 "
+                       "(adjusted), FP64 multigrid to 1e-10 (automatic depth), k=16, m=33",
+           "n_p": n_p, "eigenvalues_in_lobe": n_lobe, "pairs": ok, "wave_solves": r.wave_solves,
+           "restarts": r.restarts, "runs": r.probes, "seconds": dt, "max_res": max(r.res) if r.res else None,
+           "pt_updates_per_s": r.pt_updates / dt, "status": r.status,
+           "mu": list(r.mu)}
+    op.close()
+    return out
+
+
 def many_pairs(ks=None):
     """The square128 grid (127^2 interior), order 2, implicit 10 steps/period,
     omega 12 (adjusted), FP64 multigrid to 1e-10, one period: k eigenpairs at
@@ -350,6 +382,9 @@ def main(argv=None) -> int:
                     help="requested counts of the many-pairs form (default: the paper's table rows)")
     ap.add_argument("--only-many-pairs", action="store_true",
                     help="run only the many-pairs form and print its JSON (for profiling)")
+    ap.add_argument("--headline-np-rule", action="store_true",
+                    help="run only the headline eigenproblem with the N_p of the lobe rule (about 2.5 min) and "
+                         "print its JSON")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU decomposition is "
@@ -362,6 +397,9 @@ def main(argv=None) -> int:
     torch.cuda.set_device(0)
     if a.only_many_pairs:
         print(json.dumps({"form": "many_pairs", "result": many_pairs(a.many_k)}), flush=True)
+        return 0
+    if a.headline_np_rule:
+        print(json.dumps({"form": "headline_np_rule", "result": headline_np_rule()}), flush=True)
         return 0
     P = synthetic.config_square_order4_implicit()
     op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=P.n_p,

@@ -120,8 +120,8 @@ constexpr int kProbeFirstCheck = 64;
 // has converged, or when no eigenvalue of the deflated operator is left at or
 // above the floor: the leading Ritz value has converged below it, or both
 // extreme Ritz values, widened by their residual bounds, lie below it
-// (tested from kProbeFirstCheck basis vectors on; a Krylov space's extreme
-// Ritz values approach the extreme eigenvalues first).
+// (tested from min(kProbeFirstCheck, m) basis vectors on; a Krylov space's
+// extreme Ritz values approach the extreme eigenvalues first).
 ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, int k, double floor_abs,
                  int64_t ws_budget, uint64_t seed_base, int64_t& wave_solves, int64_t& restarts, RunResult& out) {
     Op* op = ws.op;
@@ -156,7 +156,7 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
     auto stop_rule = [&](int s) -> bool {
         const int nlead = leading_converged(out.conv);
         if (probe == 0) return nlead >= k;
-        if (s >= kProbeFirstCheck) {
+        if (s >= std::min(kProbeFirstCheck, m)) {
             int cmax = 0, cmin = 0;
             for (int c = 1; c < s; ++c) {
                 if (out.theta[c] > out.theta[cmax]) cmax = c;
