@@ -20,6 +20,9 @@ double precision, written so that it can be checked against the paper by eye:
   Krylov-Schur restarting, and the Rayleigh quotient stage.
 * ``cnn``       -- the small convolutional warm-start network, forward and
   backward, in FP64.
+* ``walls``     -- boxes with Neumann walls: the Laplacian with even-reflection
+  ghosts, its closed-form eigenpairs and symmetrising weights, and the
+  explicit wave-solve.
 
 Readings of the paper where it is silent (boundary closure for order 4,
 trapezoid weights, CFL definition, ...) are stated in each function.
