@@ -54,18 +54,30 @@ enum { EW_PRED_ZERO = 0, EW_PRED_SCALED = 1, EW_PRED_CNN = 2, EW_PRED_EXTRAP = 3
 
 typedef struct ew_op_s* ew_op;
 
-/* Grid: a box [0,len_0] x [0,len_1] (x [0,len_2]) with n[d] interior points per
- * dimension, spacing h_d = len_d / (n_d + 1), homogeneous Dirichlet walls.
- * dim in {2,3}; 1 <= n[d] <= 65535 for d < dim (entries beyond dim are ignored);
- * order in {2,4}: the 2nd-order (5/7-point) or 4th-order (width-5 cross)
- * Laplacian L_h of eq. eigBVPdiscrete.  Order 4 closes the stencil at a wall by
- * odd reflection (u_{-1} = -u_{1}), the form the paper's compatibility
- * conditions take for a flat Dirichlet wall (Sec. "Discrete approximations"). */
+/* Grid: a box [0,len_0] x [0,len_1] (x [0,len_2]) with n[d] active points per
+ * dimension.  dim in {2,3}; 1 <= n[d] <= 65535 for d < dim (entries beyond dim
+ * are ignored); order in {2,4}: the 2nd-order (5/7-point) or 4th-order
+ * (width-5 cross) Laplacian L_h of eq. eigBVPdiscrete.
+ *
+ * walls[d][0] (x_d = 0) and walls[d][1] (x_d = len_d) are EW_WALL_DIRICHLET
+ * (0, the default) or EW_WALL_NEUMANN (the boundary operator of Sec. "Problem
+ * specification and the EigenWave algorithm" may be either).  A Dirichlet
+ * wall is not an active point: value 0, and order 4 closes the stencil by odd
+ * reflection (u_{-1} = -u_{1}), the form the paper's compatibility conditions
+ * take for a flat wall (Sec. "Discrete approximations").  A Neumann wall point
+ * is active, and ghosts mirror the interior evenly about it (u_{-k} = u_{k}).
+ * Spacing h_d = len_d / (n_d + 1 - number of Neumann walls of dimension d);
+ * an axis with a Neumann wall needs n_d >= 3.  With Neumann walls L_h is
+ * self-adjoint in the inner product weighted by 1/2 per Neumann wall a point
+ * lies on; ew_eigs works in those weighted coordinates and returns the grid
+ * functions.  Neumann walls are implemented for the explicit scheme. */
+enum { EW_WALL_DIRICHLET = 0, EW_WALL_NEUMANN = 1 };
 typedef struct {
     int dim;
     int64_t n[3];
     double len[3];
     int order;
+    int walls[3][2];
 } ew_grid_desc;
 
 /* Operator: one wave-solve plus time filter, S v (eqs. explicitScheme or
@@ -242,9 +254,12 @@ typedef struct {
 
 /* Run the eigensolver.  Outputs (k_cap entries each, first n_returned valid,
  * ordered by |beta| descending): mu_host = lambda_h^2, beta_host = eigenvalue
- * of S, res_host = L_h residual, Y_dev = eigenvectors (n_active x k_cap FP64
- * column-major on the device, unit 2-norm; may be NULL).  Host-blocking.
- * EW_ERR_NOT_CONVERGED if max_wave_solves is reached first. */
+ * of S, res_host = L_h residual ||L z + mu z|| / (max(mu, 1) ||z||),
+ * Y_dev = eigenvectors (n_active x k_cap FP64 column-major on the device,
+ * unit 2-norm grid functions; may be NULL).  With Neumann walls the Krylov
+ * vectors, v0_dev and the residuals are in the coordinates y = W^{1/2} u (W =
+ * 1/2 per Neumann wall a point lies on), where S and L_h are symmetric.
+ * Host-blocking.  EW_ERR_NOT_CONVERGED if max_wave_solves is reached first. */
 ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host, double* beta_host,
                   double* res_host, double* Y_dev, ew_eigs_stats* stats);
 
@@ -299,7 +314,8 @@ ew_status ew_op_profile_end(ew_op op, ew_kernel_profile* out);
  * when desc->adjust_omega; desc->n_p is ignored).  n_lobe_out receives the
  * count for the returned N_p.  Outputs may be NULL.  Host only, no device
  * work.  Errors: EW_ERR_INVALID_ARG (dim, lengths, omega, k < 1, beta_r
- * outside [0.5, 1), np_max outside [1, 4096], more than 5e7 modes). */
+ * outside [0.5, 1), np_max outside [1, 4096], more than 5e7 modes);
+ * EW_ERR_UNSUPPORTED for Neumann walls (the rule counts Dirichlet modes). */
 ew_status ew_choose_periods(const ew_grid_desc* grid, const ew_op_desc* desc, int k, double beta_r, int np_max,
                             int* n_p_out, int* n_lobe_out);
 
@@ -327,7 +343,8 @@ typedef struct {
 } ew_batch_info;
 
 /* grids[i], descs[i] describe problem i (same rules as ew_op_create, plus:
- * dim 2, ts EW_TS_EXPLICIT, precision EW_PREC_MIXED, one order for all).
+ * dim 2, Dirichlet walls, ts EW_TS_EXPLICIT, precision EW_PREC_MIXED, one
+ * order for all).
  * Allocates every problem's workspace, autotunes and captures the graph.
  * Host-blocking. */
 ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const ew_op_desc* descs, void* hip_stream,

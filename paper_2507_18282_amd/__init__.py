@@ -57,15 +57,28 @@ class EigsResult:
     status: int
 
 
+def _set_walls(g, walls, dim: int) -> None:
+    """walls: None (all Dirichlet) or one (lo, hi) pair per dimension of 'D'/'N'."""
+    if walls is None:
+        return
+    if len(walls) != dim:
+        raise ValueError("one (lo, hi) wall pair per dimension")
+    code = {"D": _lib.WALL_DIRICHLET, "N": _lib.WALL_NEUMANN}
+    for d, (lo, hi) in enumerate(walls):
+        g.walls[d][0] = code[lo]
+        g.walls[d][1] = code[hi]
+
+
 class Operator:
-    """The WaveHoltz operator S on one Dirichlet box (see ew_op_create)."""
+    """The WaveHoltz operator S on one box (see ew_op_create); walls default to
+    Dirichlet, ``walls=(("N", "D"), ("D", "D"))`` makes the low x wall Neumann."""
 
     def __init__(self, n: Sequence[int], length: Sequence[float], order: int, omega: float, ts: str,
                  cfl: float = 0.5, n_its: int = 10, n_p: int = 1, adjust_omega: bool = False,
                  filter_const: str = "alpha_d", precision: str = "fp64", mg_tol: float = 1e-10,
                  mg_nu1: int = 2, mg_nu2: int = 1, mg_max_cycles: int = 100, mg_coarse_sweeps: int = 8,
                  mg_coarse_points: int = 0, predictor: str = "zero", proj_window: int = 0,
-                 mg_max_levels: int = 0, stream=None):
+                 mg_max_levels: int = 0, walls=None, stream=None):
         lib = load()
         self._lib = lib
         g = _lib.GridDesc()
@@ -74,6 +87,7 @@ class Operator:
             g.n[d] = int(n[d]) if d < len(n) else 1
             g.len[d] = float(length[d]) if d < len(n) else 1.0
         g.order = int(order)
+        _set_walls(g, walls, len(n))
         d = _lib.OpDesc()
         d.omega = float(omega)
         d.ts = _lib.TS[ts]

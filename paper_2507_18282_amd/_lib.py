@@ -18,12 +18,14 @@ TS = {"explicit": 0, "implicit": 1}
 FILTER = {"alpha_d": 0, "quarter": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 PREDICTOR = {"zero": 0, "scaled": 1, "cnn": 2, "extrap": 3, "proj": 4}
+WALL_DIRICHLET, WALL_NEUMANN = 0, 1
 CNN_PARAMS = 3057
 CNN_HALO = 3
 
 
 class GridDesc(ctypes.Structure):
-    _fields_ = [("dim", c_int), ("n", c_int64 * 3), ("len", c_double * 3), ("order", c_int)]
+    _fields_ = [("dim", c_int), ("n", c_int64 * 3), ("len", c_double * 3), ("order", c_int),
+                ("walls", (c_int * 2) * 3)]
 
 
 class OpDesc(ctypes.Structure):

@@ -206,6 +206,9 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
     for (int i = 0; i < nprob; ++i) {
         EW_TRY(validate_descs(&grids[i], &descs[i]));
         if (grids[i].dim != 2) return fail(EW_ERR_UNSUPPORTED, "the batched form takes 2D problems");
+        for (int d = 0; d < 2; ++d)
+            if (grids[i].walls[d][0] != EW_WALL_DIRICHLET || grids[i].walls[d][1] != EW_WALL_DIRICHLET)
+                return fail(EW_ERR_UNSUPPORTED, "the batched form takes Dirichlet rectangles");
         if (descs[i].ts != EW_TS_EXPLICIT) return fail(EW_ERR_UNSUPPORTED, "the batched form uses explicit stepping");
         if (descs[i].precision != EW_PREC_MIXED)
             return fail(EW_ERR_UNSUPPORTED, "the batched form keeps FP32 state (precision EW_PREC_MIXED)");

@@ -107,6 +107,28 @@ struct RunResult {
     std::vector<char> conv;
 };
 
+// The eigensolver's coordinates: y = W^{1/2} u with W the Neumann-wall
+// weights, in which S and L_h are symmetric (identity without Neumann walls).
+static ew_status apply_S_sym(Workspace& ws, const double* in, double* out) {
+    Op* op = ws.op;
+    if (!ws.g.wall) return op->apply_filter(in, out);
+    EW_HIP_TRY(launch_wall_scale(in, ws.wtmp, ws.g, -1, ws.stream));
+    EW_TRY(op->apply_filter(ws.wtmp, out));
+    EW_HIP_TRY(launch_wall_scale(out, out, ws.g, 1, ws.stream));
+    return EW_OK;
+}
+
+ew_status apply_L_sym(Workspace& ws, const double* in, double* out) {
+    if (!ws.g.wall) {
+        EW_HIP_TRY(launch_laplacian<double>(in, out, ws.g, ws.order, ws.stream));
+        return EW_OK;
+    }
+    EW_HIP_TRY(launch_wall_scale(in, ws.wtmp, ws.g, -1, ws.stream));
+    EW_HIP_TRY(launch_laplacian<double>(ws.wtmp, out, ws.g, ws.order, ws.stream));
+    EW_HIP_TRY(launch_wall_scale(out, out, ws.g, 1, ws.stream));
+    return EW_OK;
+}
+
 // Probe runs test for convergence before the basis is full, at these sizes
 // and their doublings (the last test is always at the full basis).
 constexpr int kProbeFirstCheck = 64;
@@ -185,7 +207,7 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
                 out.Q = Mat(m, m);
                 return EW_OK;
             }
-            EW_TRY(op->apply_filter(ws.col(ws.V, j), w));
+            EW_TRY(apply_S_sym(ws, ws.col(ws.V, j), w));
             ++wave_solves;
             EW_TRY(orthonormalize(ws, w, ws.Y, nl, ws.V, j + 1, coeff));
             double hsq = 0.0;
@@ -266,7 +288,7 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
                  double* max_res_out) {
     const int64_t N = ws.N;
     for (int i = 0; i < nl; ++i)
-        EW_HIP_TRY(launch_laplacian<double>(ws.col(ws.Y, i), ws.col(ws.LY, i), ws.g, ws.order, ws.stream));
+        EW_TRY(apply_L_sym(ws, ws.col(ws.Y, i), ws.col(ws.LY, i)));
     Mat G, B;
     EW_TRY(full_gram(ws, ws.Y, ws.LY, nl, G));
     EW_TRY(full_gram(ws, ws.Y, ws.Y, nl, B));
@@ -323,7 +345,7 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
     std::vector<double> res(nl), znorm(nl);
     for (int j = 0; j < nl; ++j) {
         // L z_j into the (no longer needed) L Y buffer, then ||L z + mu z||.
-        EW_HIP_TRY(launch_laplacian<double>(ws.col(ws.Z, j), ws.col(ws.LY, j), ws.g, ws.order, ws.stream));
+        EW_TRY(apply_L_sym(ws, ws.col(ws.Z, j), ws.col(ws.LY, j)));
         EW_HIP_TRY(launch_eig_residual(ws.col(ws.LY, j), ws.col(ws.Z, j), mu[j], N, ws.P, ws.stream));
         EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.P, 2 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, ws.stream));
         EW_HIP_TRY(hipStreamSynchronize(ws.stream));
@@ -331,7 +353,9 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
         for (int b = 0; b < kRedBlocks; ++b) r2 += ws.h_host[b];
         for (int b = 0; b < kRedBlocks; ++b) z2 += ws.h_host[kRedBlocks + b];
         znorm[j] = std::sqrt(z2);
-        res[j] = std::sqrt(r2) / (std::fabs(mu[j]) * znorm[j]);
+        // relative to mu; absolute for |mu| < 1 (the constant mode of a box
+        // with Neumann walls only has mu = 0)
+        res[j] = std::sqrt(r2) / (std::max(std::fabs(mu[j]), 1.0) * znorm[j]);
     }
     std::vector<int> order = order_by_abs_desc(beta);
     int n_conv = 0;
@@ -344,8 +368,14 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
         beta_host[r] = beta[j];
         res_host[r] = res[j];
         max_res = std::max(max_res, res[j]);
-        if (Y_dev) {
+        if (Y_dev && !ws.g.wall) {
             EW_HIP_TRY(launch_scale_copy<double>(Y_dev + (int64_t)r * N, ws.col(ws.Z, j), N, 1.0 / znorm[j], ws.stream));
+        } else if (Y_dev) {
+            // back to the grid function u = W^{-1/2} z, unit 2-norm
+            double* y = Y_dev + (int64_t)r * N;
+            EW_HIP_TRY(launch_wall_scale(ws.col(ws.Z, j), y, ws.g, -1, ws.stream));
+            EW_HIP_TRY(launch_dot_partial(y, y, N, ws.P, ws.stream));
+            EW_HIP_TRY(launch_normalize_from_partial(y, y, N, ws.P, nullptr, ws.stream));
         }
     }
     EW_HIP_TRY(hipStreamSynchronize(ws.stream));

@@ -39,10 +39,11 @@ struct Geo {
     int dim;
     int nx, ny, nz;        // nz = 1 in 2D
     double ihx2, ihy2, ihz2;  // 1/h^2 per dimension (ihz2 = 0 in 2D)
+    int wall;              // Neumann walls: bit 2d = low wall of dimension d, bit 2d+1 = high wall
     __host__ __device__ int64_t size() const { return (int64_t)nx * ny * nz; }
 };
 
-Geo make_geo(int dim, const int64_t* n, const double* h);
+Geo make_geo(int dim, const int64_t* n, const double* h, int wall = 0);
 
 // Number of partial sums written by the reduction kernels (one per block).
 constexpr int kRedBlocks = 512;
@@ -54,6 +55,10 @@ constexpr int kRedThreads = 256;
 // ---------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_laplacian(const T* u, T* out, const Geo& g, int order, hipStream_t s);
+
+// out = W^{e/2} in, W = Neumann-wall weights (1/2 per Neumann wall of the
+// point), e = +1 or -1; in and out may alias.
+hipError_t launch_wall_scale(const double* in, double* out, const Geo& g, int e, hipStream_t s);
 
 // Explicit leapfrog step fused with the filter accumulation.
 //   first != 0: wnext = wcur + (dt2/2) L wcur;  acc = ccur*wcur + cnext*wnext

@@ -17,9 +17,10 @@ ew_status fail(ew_status code, const std::string& msg) {
     return code;
 }
 
-Geo make_geo(int dim, const int64_t* n, const double* h) {
+Geo make_geo(int dim, const int64_t* n, const double* h, int wall) {
     Geo g;
     g.dim = dim;
+    g.wall = wall;
     g.nx = (int)n[0];
     g.ny = (int)n[1];
     g.nz = dim == 3 ? (int)n[2] : 1;
@@ -135,11 +136,22 @@ ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
     if (g->dim != 2 && g->dim != 3) return fail(EW_ERR_INVALID_ARG, "dim must be 2 or 3");
     if (g->order != 2 && g->order != 4) return fail(EW_ERR_INVALID_ARG, "order must be 2 or 4");
     int64_t total = 1;
+    bool neumann = false;
     for (int k = 0; k < g->dim; ++k) {
         if (g->n[k] < 1 || g->n[k] > 65535) return fail(EW_ERR_INVALID_ARG, "n[d] must be in [1, 65535]");
         if (!(g->len[k] > 0.0) || !std::isfinite(g->len[k])) return fail(EW_ERR_INVALID_ARG, "len[d] must be > 0");
+        for (int e = 0; e < 2; ++e) {
+            if (g->walls[k][e] != EW_WALL_DIRICHLET && g->walls[k][e] != EW_WALL_NEUMANN)
+                return fail(EW_ERR_INVALID_ARG, "walls[d][e] must be EW_WALL_DIRICHLET or EW_WALL_NEUMANN");
+            if (g->walls[k][e] == EW_WALL_NEUMANN) {
+                neumann = true;
+                if (g->n[k] < 3) return fail(EW_ERR_INVALID_ARG, "an axis with a Neumann wall needs n[d] >= 3");
+            }
+        }
         total *= g->n[k];
     }
+    if (neumann && d && d->ts == EW_TS_IMPLICIT)
+        return fail(EW_ERR_UNSUPPORTED, "Neumann walls are implemented for the explicit scheme");
     if (total > (int64_t)1 << 34) return fail(EW_ERR_INVALID_ARG, "grid too large");
     if (!(d->omega > 0.0) || !std::isfinite(d->omega)) return fail(EW_ERR_INVALID_ARG, "omega must be > 0");
     if (d->ts != EW_TS_EXPLICIT && d->ts != EW_TS_IMPLICIT) return fail(EW_ERR_INVALID_ARG, "ts must be explicit or implicit");
@@ -271,16 +283,24 @@ extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* de
     std::unique_ptr<ew_op_s> op(new ew_op_s());
     op->dim = grid->dim;
     op->order = grid->order;
+    int wall = 0;
     for (int k = 0; k < 3; ++k) {
         op->n[k] = k < grid->dim ? grid->n[k] : 1;
         op->len[k] = k < grid->dim ? grid->len[k] : 1.0;
-        op->h[k] = op->len[k] / (double)(op->n[k] + 1);
+        int nn = 0;
+        for (int e = 0; e < 2 && k < grid->dim; ++e)
+            if (grid->walls[k][e] == EW_WALL_NEUMANN) {
+                wall |= 1 << (2 * k + e);
+                ++nn;
+            }
+        // a Neumann wall point is active: h = len / (n + 1 - Neumann walls)
+        op->h[k] = op->len[k] / (double)(op->n[k] + 1 - nn);
     }
     op->desc = *desc;
     op->stream = (hipStream_t)hip_stream;
     op->mixed = desc->precision == EW_PREC_MIXED;
     op->implicit = desc->ts == EW_TS_IMPLICIT;
-    op->g = make_geo(op->dim, op->n, op->h);
+    op->g = make_geo(op->dim, op->n, op->h, wall);
     op->N = op->g.size();
     EW_HIP_TRY(hipGetDevice(&op->device));
     make_plan(op.get());

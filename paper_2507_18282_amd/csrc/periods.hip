@@ -56,8 +56,11 @@ extern "C" ew_status ew_choose_periods(const ew_grid_desc* grid, const ew_op_des
                                        int np_max, int* n_p_out, int* n_lobe_out) {
     if (!grid || !desc) return fail(EW_ERR_INVALID_ARG, "null descriptor");
     if (grid->dim != 2 && grid->dim != 3) return fail(EW_ERR_INVALID_ARG, "dim must be 2 or 3");
-    for (int d = 0; d < grid->dim; ++d)
+    for (int d = 0; d < grid->dim; ++d) {
         if (!(grid->len[d] > 0.0)) return fail(EW_ERR_INVALID_ARG, "side lengths must be positive");
+        if (grid->walls[d][0] != EW_WALL_DIRICHLET || grid->walls[d][1] != EW_WALL_DIRICHLET)
+            return fail(EW_ERR_UNSUPPORTED, "the periods rule counts Dirichlet box modes");
+    }
     if (!(desc->omega > 0.0)) return fail(EW_ERR_INVALID_ARG, "omega must be positive");
     if (desc->adjust_omega && desc->n_its < 5) return fail(EW_ERR_INVALID_ARG, "n_its must be >= 5");
     if (k < 1) return fail(EW_ERR_INVALID_ARG, "k must be positive");

@@ -34,6 +34,29 @@ hipError_t launch_laplacian(const T* u, T* out, const Geo& g, int order, hipStre
 }
 
 // --------------------------------------------------------------------------
+// out = W^{e/2} in with W the Neumann-wall weights (1/2 per Neumann wall the
+// point lies on): e = +1 multiplies a wall point by 1/sqrt(2) per wall, e = -1
+// by sqrt(2).  W^{1/2} L W^{-1/2} is symmetric, so the eigensolver works on
+// vectors y = W^{1/2} u.  in and out may alias.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_wall_scale(const double* in, double* out, Geo g, double f) {
+    int i, j, k;
+    if (!tile_coords(g, i, j, k)) return;
+    const int64_t c = lin(g, i, j, k);
+    double s = 1.0;
+    if (((g.wall & 1) && i == 0) || ((g.wall & 2) && i == g.nx - 1)) s *= f;
+    if (((g.wall & 4) && j == 0) || ((g.wall & 8) && j == g.ny - 1)) s *= f;
+    if (((g.wall & 16) && k == 0) || ((g.wall & 32) && k == g.nz - 1)) s *= f;
+    out[c] = in[c] * s;
+}
+
+hipError_t launch_wall_scale(const double* in, double* out, const Geo& g, int e, hipStream_t s) {
+    const double f = e > 0 ? 0.70710678118654752440 : 1.41421356237309504880;
+    k_wall_scale<<<tile_grid(g), dim3(kTileX, kTileY, 1), 0, s>>>(in, out, g, f);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // Explicit leapfrog step fused with the trapezoidal filter accumulation
 // (eqs. explicitStep1, explicitScheme, filterQuadrature).  One pass reads
 // W^n (stencil), W^{n-1} and the accumulator, and writes W^{n+1} over

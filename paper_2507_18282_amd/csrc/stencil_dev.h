@@ -24,21 +24,48 @@ __device__ __forceinline__ int64_t lin(const Geo& g, int i, int j, int k) {
     return ((int64_t)k * g.ny + j) * g.nx + i;
 }
 
-// Second difference along one axis at interior index i (0-based) of n points,
+// Second difference along one axis at index i (0-based) of n active points,
 // un-scaled: order 2 returns u_{i-1} - 2u_i + u_{i+1}; order 4 returns
-// -u_{i-2} + 16u_{i-1} - 30u_i + 16u_{i+1} - u_{i+2}.  Index -1 and n are the
-// wall (value 0); index -2 and n+1 are ghosts equal to -u_0 and -u_{n-1}.
+// -u_{i-2} + 16u_{i-1} - 30u_i + 16u_{i+1} - u_{i+2}.  w holds the axis's
+// Neumann walls (bit 0 low, bit 1 high).  Beyond a Dirichlet wall index -1
+// (or n) is the wall, value 0, and index -2 (or n+1) the odd-reflection ghost
+// -u_0 (or -u_{n-1}); beyond a Neumann wall ghosts mirror evenly about the
+// wall point, u_{-k} = u_k (u_{n-1+k} = u_{n-1-k}).
 template <typename T, int ORDER>
-__device__ __forceinline__ T d2_axis(const T* __restrict__ u, int64_t c, int i, int n, int64_t stride, T uc) {
-    const T l1 = (i > 0) ? u[c - stride] : T(0);
-    const T r1 = (i < n - 1) ? u[c + stride] : T(0);
+__device__ __forceinline__ T d2_axis(const T* __restrict__ u, int64_t c, int i, int n, int64_t stride, T uc,
+                                     int w = 0) {
+    const bool nlo = (w & 1) != 0, nhi = (w & 2) != 0;
+    const T l1 = (i > 0) ? u[c - stride] : (nlo ? u[c + stride] : T(0));
+    const T r1 = (i < n - 1) ? u[c + stride] : (nhi ? u[c - stride] : T(0));
     if (ORDER == 2) {
         return l1 + r1 - T(2) * uc;
     } else {
-        const T l2 = (i > 1) ? u[c - 2 * stride] : (i == 1 ? T(0) : -uc);
-        const T r2 = (i < n - 2) ? u[c + 2 * stride] : (i == n - 2 ? T(0) : -uc);
+        T l2, r2;
+        if (i > 1) l2 = u[c - 2 * stride];
+        else if (i == 1) l2 = nlo ? uc : T(0);
+        else l2 = nlo ? u[c + 2 * stride] : -uc;
+        if (i < n - 2) r2 = u[c + 2 * stride];
+        else if (i == n - 2) r2 = nhi ? uc : T(0);
+        else r2 = nhi ? u[c - 2 * stride] : -uc;
         return T(16) * (l1 + r1) - (l2 + r2) - T(30) * uc;
     }
+}
+
+// The same from a buffer whose neighbours beyond the walls read as 0 (an LDS
+// frame): the wall closures replace those values.
+template <typename T, int ORDER>
+__device__ __forceinline__ T d2_framed(const T* X, int p, int s, int i, int n, T uc, int w) {
+    const bool nlo = (w & 1) != 0, nhi = (w & 2) != 0;
+    T l1 = X[p - s], r1 = X[p + s];
+    if (i == 0 && nlo) l1 = r1;
+    if (i == n - 1 && nhi) r1 = l1;
+    if (ORDER == 2) return l1 + r1 - T(2) * uc;
+    T l2 = X[p - 2 * s], r2 = X[p + 2 * s];
+    if (i == 0) l2 = nlo ? r2 : -uc;
+    else if (i == 1 && nlo) l2 = uc;
+    if (i == n - 1) r2 = nhi ? X[p - 2 * s] : -uc;
+    else if (i == n - 2 && nhi) r2 = uc;
+    return T(16) * (l1 + r1) - (l2 + r2) - T(30) * uc;
 }
 
 template <typename T, int ORDER>
@@ -48,29 +75,35 @@ __device__ __forceinline__ T axis_coef(double ih2) {
 
 template <typename T, int ORDER, int DIM>
 __device__ __forceinline__ T lap_at(const T* __restrict__ u, int64_t c, int i, int j, int k, const Geo& g, T uc) {
-    T s = d2_axis<T, ORDER>(u, c, i, g.nx, 1, uc) * axis_coef<T, ORDER>(g.ihx2);
-    s += d2_axis<T, ORDER>(u, c, j, g.ny, g.nx, uc) * axis_coef<T, ORDER>(g.ihy2);
-    if (DIM == 3) s += d2_axis<T, ORDER>(u, c, k, g.nz, (int64_t)g.nx * g.ny, uc) * axis_coef<T, ORDER>(g.ihz2);
+    T s = d2_axis<T, ORDER>(u, c, i, g.nx, 1, uc, g.wall & 3) * axis_coef<T, ORDER>(g.ihx2);
+    s += d2_axis<T, ORDER>(u, c, j, g.ny, g.nx, uc, (g.wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3)
+        s += d2_axis<T, ORDER>(u, c, k, g.nz, (int64_t)g.nx * g.ny, uc, (g.wall >> 4) & 3) *
+             axis_coef<T, ORDER>(g.ihz2);
     return s;
 }
 
 // Diagonal entry of L along one axis (un-scaled): -2 for order 2; order 4:
-// -30, plus 1 at each end where the odd-reflection ghost refers back to the
-// point itself.
+// -30, plus 1 where a Dirichlet wall's odd-reflection ghost refers back to
+// the point itself (i = 0 or n-1), minus 1 where a Neumann wall's even ghost
+// does (i = 1 or n-2).
 template <typename T, int ORDER>
-__device__ __forceinline__ T ldiag_axis(int i, int n) {
+__device__ __forceinline__ T ldiag_axis(int i, int n, int w = 0) {
     if (ORDER == 2) return T(-2);
+    const bool nlo = (w & 1) != 0, nhi = (w & 2) != 0;
     T d = T(-30);
-    if (i == 0) d += T(1);
-    if (i == n - 1) d += T(1);
+    if (i == 0 && !nlo) d += T(1);
+    if (i == n - 1 && !nhi) d += T(1);
+    if (i == 1 && nlo) d -= T(1);
+    if (i == n - 2 && nhi) d -= T(1);
     return d;
 }
 
 template <typename T, int ORDER, int DIM>
 __device__ __forceinline__ T mdiag_at(int i, int j, int k, const Geo& g, T a) {
-    T l = ldiag_axis<T, ORDER>(i, g.nx) * axis_coef<T, ORDER>(g.ihx2) +
-          ldiag_axis<T, ORDER>(j, g.ny) * axis_coef<T, ORDER>(g.ihy2);
-    if (DIM == 3) l += ldiag_axis<T, ORDER>(k, g.nz) * axis_coef<T, ORDER>(g.ihz2);
+    T l = ldiag_axis<T, ORDER>(i, g.nx, g.wall & 3) * axis_coef<T, ORDER>(g.ihx2) +
+          ldiag_axis<T, ORDER>(j, g.ny, (g.wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3) l += ldiag_axis<T, ORDER>(k, g.nz, (g.wall >> 4) & 3) * axis_coef<T, ORDER>(g.ihz2);
     return T(1) - a * l;
 }
 

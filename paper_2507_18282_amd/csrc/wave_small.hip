@@ -9,6 +9,7 @@
 // grids of a few thousand points the per-step launches of the tiled leapfrog
 // are pure latency.
 #include "op.h"
+#include "stencil_dev.h"
 
 namespace ew {
 namespace {
@@ -53,16 +54,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_wave_small(const double* __re
             const int p = lp[t];
             const T uc = cur[t];
             T lap;
-            if (ORDER == 2) {
+            if (ORDER == 2 && g.wall == 0) {
                 lap = (Xs[p - 1] + Xs[p + 1] - T(2) * uc) * cx + (Xs[p - px] + Xs[p + px] - T(2) * uc) * cy;
             } else {
-                // order-4 ghost beyond the wall: odd reflection u_{-2} = -u_0
+                // wall closures (Dirichlet odd reflection, Neumann even
+                // reflection) replace the frame's zeros
                 const int i = lij[t] & 0xFFFF, j = lij[t] >> 16;
-                const T l2 = (i == 0) ? -uc : Xs[p - 2], r2 = (i == nx - 1) ? -uc : Xs[p + 2];
-                const T d2 = (j == 0) ? -uc : Xs[p - 2 * px], u2 = (j == ny - 1) ? -uc : Xs[p + 2 * px];
-                const T dx = T(16) * (Xs[p - 1] + Xs[p + 1]) - (l2 + r2) - T(30) * uc;
-                const T dy = T(16) * (Xs[p - px] + Xs[p + px]) - (d2 + u2) - T(30) * uc;
-                lap = dx * cx + dy * cy;
+                lap = d2_framed<T, ORDER>(Xs, p, 1, i, nx, uc, g.wall & 3) * cx +
+                      d2_framed<T, ORDER>(Xs, p, px, j, ny, uc, (g.wall >> 2) & 3) * cy;
             }
             const T nw = (step == 0) ? uc + (T(0.5) * dt2) * lap : T(2) * uc - prev[t] + dt2 * lap;
             acc[t] += cn * nw;

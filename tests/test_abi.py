@@ -89,3 +89,29 @@ def test_single_hip_runtime_in_process():
             if "libamdhip64" in line:
                 paths.add(line.split()[-1])
     assert len(paths) == 1, paths
+
+
+def test_neumann_walls_rejected_where_not_implemented():
+    """Validation runs before any device work, so it is checked here through
+    the raw ABI: the implicit scheme rejects Neumann walls (EW_ERR_UNSUPPORTED)
+    and an axis with a Neumann wall needs at least 3 points."""
+    import ctypes
+    from paper_2507_18282_amd import _lib
+    lib = _lib.load()
+
+    def create(n0, ts):
+        g = _lib.GridDesc()
+        g.dim = 2
+        g.n[0], g.n[1], g.n[2] = n0, 15, 1
+        g.len[0], g.len[1], g.len[2] = 1.0, 1.0, 1.0
+        g.order = 2
+        g.walls[0][0] = _lib.WALL_NEUMANN
+        d = _lib.OpDesc()
+        d.omega, d.ts, d.cfl, d.n_its, d.n_p = 10.0, _lib.TS[ts], 0.5, 10, 1
+        d.mg_tol, d.mg_nu1, d.mg_nu2, d.mg_max_cycles, d.mg_coarse_sweeps = 1e-10, 2, 1, 100, 8
+        h = ctypes.c_void_p()
+        return lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h))
+
+    assert create(15, "implicit") == -7  # EW_ERR_UNSUPPORTED
+    assert b"explicit" in lib.ew_last_error()
+    assert create(2, "explicit") == -1  # EW_ERR_INVALID_ARG
