@@ -206,3 +206,38 @@ def apply_filter_explicit(v: np.ndarray, h: Sequence[float], order: int, walls: 
         acc = acc + c[k + 1] * w_next
         w_prev, w_cur = w_cur, w_next
     return acc
+
+
+def solve_implicit_exact(b: np.ndarray, h: Sequence[float], order: int, walls: Walls, dt: float) -> np.ndarray:
+    """Exact solve of M x = b, M = I - (dt^2/2) L_h (eq. impMatrix), by
+    diagonalisation: L_h is a Kronecker sum of line operators, each of which
+    the sampled modes diagonalise, so x = P (P^{-1} b / (1 + (dt^2/2) mu))
+    with P the tensor product of the line mode matrices (a library solve with
+    each line's mode matrix does the change of basis)."""
+    n = b.shape[::-1]
+    mats = [line_modes(int(k), *w) for k, w in zip(n, walls)]
+    c = np.asarray(b, dtype=np.float64)
+    for d, P in enumerate(mats):
+        c = _apply_along(np.linalg.inv(P), c, d)
+    c = c / (1.0 + 0.5 * dt * dt * mu_all(n, h, order, walls))
+    for d, P in enumerate(mats):
+        c = _apply_along(P, c, d)
+    return c
+
+
+def apply_filter_implicit(v: np.ndarray, h: Sequence[float], order: int, walls: Walls, plan: TimePlan) -> np.ndarray:
+    """S v with the implicit scheme (eqs. implicitStep1, implicitScheme: M W^1
+    = W^0, M S = 2 W^n, W^{n+1} = S - W^{n-1}) and the trapezoidal filter,
+    exact solves."""
+    if plan.ts != "implicit":
+        raise ValueError("implicit plan expected")
+    c, dt = plan.c, plan.dt
+    w_prev = np.asarray(v, dtype=np.float64).copy()
+    acc = c[0] * w_prev
+    w_cur = solve_implicit_exact(w_prev, h, order, walls, dt)
+    acc = acc + c[1] * w_cur
+    for k in range(1, plan.n_t):
+        w_next = solve_implicit_exact(2.0 * w_cur, h, order, walls, dt) - w_prev
+        acc = acc + c[k + 1] * w_next
+        w_prev, w_cur = w_cur, w_next
+    return acc

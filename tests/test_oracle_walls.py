@@ -127,3 +127,25 @@ def test_explicit_filter_on_modes(walls, order):
         got = Wl.apply_filter_explicit(phi, h, order, walls, plan)
         beta = float(D.beta_corrected(mu[idx[1], idx[0]], plan))
         assert np.max(np.abs(got - beta * phi)) <= 1e-12
+
+
+@pytest.mark.parametrize("walls", [[("N", "D"), ("D", "N")], [("N", "N"), ("N", "D")], [("D", "D"), ("D", "N")]])
+@pytest.mark.parametrize("order", [2, 4])
+def test_implicit_exact_solve_and_filter(walls, order):
+    n = (7, 6)
+    h = Wl.spacing(n, (1.0, 0.8), walls)
+    dt = 0.05
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(n[::-1])
+    A = Wl.laplacian_matrix(n, h, order, walls)
+    M = np.eye(A.shape[0]) - 0.5 * dt * dt * A
+    want = np.linalg.solve(M, b.ravel())
+    got = Wl.solve_implicit_exact(b, h, order, walls, dt).ravel()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    plan = D.time_plan(h, order, 11.0, "implicit", n_its=10, adjust_omega=True)
+    mu = Wl.mu_all(n, h, order, walls)
+    for idx in ((0, 0), (3, 2), (6, 5)):
+        phi = Wl.mode(idx, n, walls)
+        got = Wl.apply_filter_implicit(phi, h, order, walls, plan)
+        beta = float(D.beta_corrected(mu[idx[1], idx[0]], plan))
+        assert np.max(np.abs(got - beta * phi)) <= 1e-12
