@@ -70,7 +70,10 @@ typedef struct ew_op_s* ew_op;
  * an axis with a Neumann wall needs n_d >= 3.  With Neumann walls L_h is
  * self-adjoint in the inner product weighted by 1/2 per Neumann wall a point
  * lies on; ew_eigs works in those weighted coordinates and returns the grid
- * functions.  Neumann walls are implemented for the explicit scheme. */
+ * functions.  Multigrid coarsening keeps the wall points (n = 2 n_c + 1,
+ * 2 n_c or 2 n_c - 1 for zero, one or two Neumann walls of an axis) and runs
+ * the plain kernels on boxes with Neumann walls; the implicit guesses PROJ and
+ * CNN are not available there (EW_ERR_UNSUPPORTED). */
 enum { EW_WALL_DIRICHLET = 0, EW_WALL_NEUMANN = 1 };
 typedef struct {
     int dim;

@@ -44,17 +44,23 @@ hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, cons
 }
 
 // --------------------------------------------------------------------------
-// Prolongation (multilinear) fused with the correction x += P xc.
+// Prolongation (multilinear) fused with the correction x += P xc.  Along an
+// axis whose low wall is Dirichlet the coarse point I sits at fine index
+// 2I + 1; behind a Neumann low wall (an active wall point) at 2I.  Fine points
+// between coarse points take the mean of their two neighbours; a neighbour
+// beyond a Dirichlet wall is the wall value 0 (a Neumann wall point is itself
+// a coarse point, so no neighbour lies beyond it).
 // --------------------------------------------------------------------------
-__device__ __forceinline__ void interp_1d(int f, int nc, int& c0, int& c1, float& w0, float& w1) {
-    if (f & 1) {  // coincides with coarse point (f-1)/2
-        c0 = (f - 1) >> 1;
+__device__ __forceinline__ void interp_1d(int f, int nc, int off, int& c0, int& c1, float& w0, float& w1) {
+    const int q = f - off;
+    if (q >= 0 && !(q & 1)) {  // coincides with coarse point q/2
+        c0 = q >> 1;
         c1 = -1;
         w0 = 1.0f;
         w1 = 0.0f;
-    } else {      // midway between coarse f/2-1 and f/2
-        c0 = (f >> 1) - 1;
-        c1 = f >> 1;
+    } else {                   // midway between coarse (q-1)/2 and (q+1)/2
+        c0 = (q - 1) >> 1;
+        c1 = c0 + 1;
         w0 = 0.5f;
         w1 = 0.5f;
         if (c1 >= nc) c1 = -1;
@@ -67,9 +73,10 @@ __global__ __launch_bounds__(256) void k_prolong_correct(T* __restrict__ x, cons
     if (!tile_coords(gf, i, j, k)) return;
     int xi[2], yj[2], zk[2];
     float wx[2], wy[2], wz[2];
-    interp_1d(i, gc.nx, xi[0], xi[1], wx[0], wx[1]);
-    interp_1d(j, gc.ny, yj[0], yj[1], wy[0], wy[1]);
-    if (DIM == 3) interp_1d(k, gc.nz, zk[0], zk[1], wz[0], wz[1]);
+    // offsets 1 behind a Dirichlet low wall, 0 behind a Neumann one
+    interp_1d(i, gc.nx, (gf.wall & 1) ? 0 : 1, xi[0], xi[1], wx[0], wx[1]);
+    interp_1d(j, gc.ny, (gf.wall & 4) ? 0 : 1, yj[0], yj[1], wy[0], wy[1]);
+    if (DIM == 3) interp_1d(k, gc.nz, (gf.wall & 16) ? 0 : 1, zk[0], zk[1], wz[0], wz[1]);
     else { zk[0] = 0; zk[1] = -1; wz[0] = 1.0f; wz[1] = 0.0f; }
     T v = T(0);
 #pragma unroll
@@ -91,6 +98,66 @@ __global__ __launch_bounds__(256) void k_prolong_correct(T* __restrict__ x, cons
     }
     const int64_t cf = lin(gf, i, j, k);
     x[cf] = x[cf] + v;
+}
+
+// --------------------------------------------------------------------------
+// Residual r = bscale b - M x and its full-weighting restriction in one pass
+// per coarse point, every residual evaluated from global memory (the plain
+// path used for boxes with Neumann walls).  The fine centre of coarse point I
+// is 2I + off (off as for the prolongation); a neighbour beyond a Neumann
+// wall point is its even mirror (the residual of the evenly extended problem).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int mirror_index(int f, int n, bool nlo, bool nhi) {
+    if (f < 0 && nlo) return -f;
+    if (f >= n && nhi) return 2 * (n - 1) - f;
+    return f;
+}
+
+template <typename T, int ORDER, int DIM>
+__global__ __launch_bounds__(256) void k_restrict_plain(const T* __restrict__ x, const T* __restrict__ b, T bscale,
+                                                        Geo gf, T a, T* __restrict__ bc, Geo gc) {
+    int I, J, K;
+    if (!tile_coords(gc, I, J, K)) return;
+    const int ox = (gf.wall & 1) ? 0 : 1, oy = (gf.wall & 4) ? 0 : 1, oz = (gf.wall & 16) ? 0 : 1;
+    const int fi = 2 * I + ox, fj = 2 * J + oy, fk = (DIM == 3) ? 2 * K + oz : 0;
+    T sum = T(0);
+    const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+        const int k = (DIM == 3) ? mirror_index(fk + dz, gf.nz, gf.wall & 16, gf.wall & 32) : 0;
+        T plane = T(0);
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int j = mirror_index(fj + dy, gf.ny, gf.wall & 4, gf.wall & 8);
+            T row = T(0);
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int i = mirror_index(fi + dx, gf.nx, gf.wall & 1, gf.wall & 2);
+                T r = T(0);
+                if (i >= 0 && i < gf.nx && j >= 0 && j < gf.ny && k >= 0 && k < gf.nz) {
+                    const int64_t c = lin(gf, i, j, k);
+                    const T xc = x[c];
+                    r = bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM>(x, c, i, j, k, gf, xc));
+                }
+                row += (dx == 0 ? T(0.5) : T(0.25)) * r;
+            }
+            plane += (dy == 0 ? T(0.5) : T(0.25)) * row;
+        }
+        sum += (DIM == 3) ? (dz == 0 ? T(0.5) : T(0.25)) * plane : plane;
+    }
+    bc[lin(gc, I, J, K)] = sum;
+}
+
+template <typename T>
+hipError_t launch_restrict_plain(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
+                                 const Geo& gc, hipStream_t s) {
+    dim3 grid = tile_grid(gc), block(kTileX, kTileY, 1);
+    const T bs = (T)bscale, aa = (T)a;
+    if (gf.dim == 2) {
+        if (order == 2) k_restrict_plain<T, 2, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+        else k_restrict_plain<T, 4, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+    } else {
+        if (order == 2) k_restrict_plain<T, 2, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+        else k_restrict_plain<T, 4, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
+    }
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -140,7 +207,9 @@ hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo
 #define EW_INST_MG(T)                                                                                          \
     template hipError_t launch_rb_half<T>(const T*, T*, const T*, double, const Geo&, int, double, int,         \
                                           hipStream_t);                                                        \
-    template hipError_t launch_prolong_correct<T>(T*, const T*, const Geo&, const Geo&, hipStream_t);
+    template hipError_t launch_prolong_correct<T>(T*, const T*, const Geo&, const Geo&, hipStream_t);            \
+    template hipError_t launch_restrict_plain<T>(const T*, const T*, double, const Geo&, int, double, T*, const Geo&, \
+                                                 hipStream_t);
 EW_INST_MG(double)
 EW_INST_MG(float)
 #undef EW_INST_MG

@@ -150,8 +150,10 @@ ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
         }
         total *= g->n[k];
     }
-    if (neumann && d && d->ts == EW_TS_IMPLICIT)
-        return fail(EW_ERR_UNSUPPORTED, "Neumann walls are implemented for the explicit scheme");
+    if (neumann && d && d->ts == EW_TS_IMPLICIT &&
+        (d->predictor == EW_PRED_CNN || d->predictor == EW_PRED_PROJ))
+        return fail(EW_ERR_UNSUPPORTED, "with Neumann walls the implicit guesses are ZERO, SCALED or EXTRAP "
+                                        "(the projection and the network assume a symmetric M)");
     if (total > (int64_t)1 << 34) return fail(EW_ERR_INVALID_ARG, "grid too large");
     if (!(d->omega > 0.0) || !std::isfinite(d->omega)) return fail(EW_ERR_INVALID_ARG, "omega must be > 0");
     if (d->ts != EW_TS_EXPLICIT && d->ts != EW_TS_IMPLICIT) return fail(EW_ERR_INVALID_ARG, "ts must be explicit or implicit");
@@ -204,12 +206,29 @@ ew_status Op::build_hierarchy() {
         const double rho_gs = (off / diag) * (off / diag);
         return off < diag && std::pow(rho_gs, desc.mg_coarse_sweeps) <= 0.1;
     };
+    // Coarsening per axis keeps the walls' points: Dirichlet-Dirichlet n = 2 n_c
+    // + 1; one Neumann wall n = 2 n_c (the wall point is a coarse point);
+    // Neumann-Neumann n = 2 n_c - 1.  An axis with a Neumann wall keeps at
+    // least 3 points.
+    auto coarsen = [&](int k, int64_t m, int64_t* mc) -> bool {
+        const int nn = ((g.wall >> (2 * k)) & 1) + ((g.wall >> (2 * k + 1)) & 1);
+        if (nn == 0) {
+            if (m % 2 != 1 || m < 3) return false;
+            *mc = (m - 1) / 2;
+            return true;
+        }
+        const int64_t c = nn == 1 ? (m % 2 == 0 ? m / 2 : -1) : (m % 2 == 1 ? (m + 1) / 2 : -1);
+        if (c < 3 || c >= m) return false;
+        *mc = c;
+        return true;
+    };
     while (sizes.size() < max_levels) {
         if (desc.mg_max_levels == EW_MG_LEVELS_AUTO && coarse_enough(sizes.size() - 1)) break;
+        std::array<int64_t, 3> nxt = cur;
         bool ok = true;
-        for (int k = 0; k < dim; ++k) ok = ok && (cur[k] % 2 == 1) && cur[k] >= 3;
+        for (int k = 0; k < dim; ++k) ok = ok && coarsen(k, cur[k], &nxt[k]);
         if (!ok) break;
-        for (int k = 0; k < dim; ++k) cur[k] = (cur[k] - 1) / 2;
+        cur = nxt;
         sizes.push_back(cur);
     }
     const size_t es = mixed ? sizeof(float) : sizeof(double);
@@ -218,7 +237,7 @@ ew_status Op::build_hierarchy() {
         Level& L = levels[l];
         double hl[3];
         for (int k = 0; k < 3; ++k) hl[k] = h[k] * std::ldexp(1.0, (int)l);
-        L.g = make_geo(dim, sizes[l].data(), hl);
+        L.g = make_geo(dim, sizes[l].data(), hl, g.wall);
         const int64_t m = L.g.size();
         // Level 0 of the FP64 solver works on the caller's x with one partner
         // buffer; every other level (and every level of the FP32 inner solver)
@@ -233,6 +252,7 @@ ew_status Op::build_hierarchy() {
     // such level resident in LDS.
     const int nlev = (int)levels.size();
     coarse_level = nlev;
+    if (g.wall) return EW_OK;  // boxes with Neumann walls use the plain kernels on every level
     const int64_t cap_pts = desc.mg_coarse_points > 0 ? desc.mg_coarse_points : (int64_t)1 << 40;
     auto padded = [&](const Geo& gq) -> int64_t {
         return (int64_t)(gq.nx + 4) * (gq.ny + 4) * (dim == 3 ? gq.nz + 4 : 1);

@@ -93,13 +93,14 @@ def test_single_hip_runtime_in_process():
 
 def test_neumann_walls_rejected_where_not_implemented():
     """Validation runs before any device work, so it is checked here through
-    the raw ABI: the implicit scheme rejects Neumann walls (EW_ERR_UNSUPPORTED)
-    and an axis with a Neumann wall needs at least 3 points."""
+    the raw ABI: with Neumann walls the implicit projection and network
+    guesses are rejected (EW_ERR_UNSUPPORTED; both assume a symmetric M), and
+    an axis with a Neumann wall needs at least 3 points."""
     import ctypes
     from paper_2507_18282_amd import _lib
     lib = _lib.load()
 
-    def create(n0, ts):
+    def create(n0, ts, predictor="zero"):
         g = _lib.GridDesc()
         g.dim = 2
         g.n[0], g.n[1], g.n[2] = n0, 15, 1
@@ -109,9 +110,11 @@ def test_neumann_walls_rejected_where_not_implemented():
         d = _lib.OpDesc()
         d.omega, d.ts, d.cfl, d.n_its, d.n_p = 10.0, _lib.TS[ts], 0.5, 10, 1
         d.mg_tol, d.mg_nu1, d.mg_nu2, d.mg_max_cycles, d.mg_coarse_sweeps = 1e-10, 2, 1, 100, 8
+        d.predictor = _lib.PREDICTOR[predictor]
         h = ctypes.c_void_p()
         return lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h))
 
-    assert create(15, "implicit") == -7  # EW_ERR_UNSUPPORTED
-    assert b"explicit" in lib.ew_last_error()
+    assert create(15, "implicit", "proj") == -7  # EW_ERR_UNSUPPORTED
+    assert b"symmetric" in lib.ew_last_error()
+    assert create(15, "implicit", "cnn") == -7
     assert create(2, "explicit") == -1  # EW_ERR_INVALID_ARG
