@@ -268,6 +268,55 @@ def periods_rule():
 MANY_PAIRS_PAPER = {16: (16, 64), 64: (65, 209), 256: (285, 675), 512: (571, 1325)}
 
 
+def walls_form():
+    """Neumann walls beside Dirichlet ones on the same work: the headline grid
+    with a symmetry plane (2047 x 2048 points, Neumann wall at y = 0, order 4,
+    implicit, omega 120, automatic multigrid depth) against the all-Dirichlet
+    2047^2, two wave-solves each; and the small explicit eigensolve on a 64 x
+    65 square with a Neumann wall at y = 0 against the Dirichlet 64^2 one."""
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Operator, fill_uniform
+    out = {"workload": "implicit: 2047 x 2048 (Neumann y=0) vs 2047^2 (Dirichlet), order 4, omega 120 (adjusted), "
+                       "multigrid to 1e-10, 2 wave-solves; explicit: 64 x 65 (Neumann y=0) vs 64^2, order 2, "
+                       "CFL 0.5, omega 15, k=4, m=16, eig-res <= 1e-8"}
+    P = synthetic.config_square_order4_implicit()
+    for label, n, walls in (("implicit_dirichlet", (2047, 2047), None),
+                            ("implicit_neumann_y0", (2047, 2048), (("D", "D"), ("N", "D")))):
+        op = Operator(n=n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its,
+                      adjust_omega=P.adjust_omega, mg_tol=P.mg_tol, mg_max_levels=MG_LEVELS,
+                      mg_coarse_sweeps=MG_COARSE_SWEEPS, walls=walls)
+        v = fill_uniform(op.n_active, 3)
+        w = op.apply_filter(v)
+        torch.cuda.synchronize()
+        op.reset_stats()
+        t0 = time.perf_counter()
+        w = op.apply_filter(v)
+        w = op.apply_filter(v)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = op.stats()
+        out[label] = {"pt_updates_per_s": st["pt_updates"] / dt, "ms_per_wave_solve": dt / 2 * 1e3,
+                      "mg_levels": op.mg_levels, "mg_cycles_per_implicit_solve": st["mg_cycles"] / max(1, st["mg_solves"])}
+        log(f"walls form: {label}: {dt / 2 * 1e3:.1f} ms per wave-solve, {op.mg_levels} levels")
+        op.close()
+    for label, n, walls in (("explicit_dirichlet", (64, 64), None),
+                            ("explicit_neumann_y0", (64, 65), (("D", "D"), ("N", "D")))):
+        op = Operator(n=n, length=(1.0, 1.0), order=2, omega=15.0, ts="explicit", cfl=0.5, walls=walls)
+        r = op.eigs(4, 16, seed=1, want_vectors=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.eigs(4, 16, seed=1, want_vectors=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(1 for x in r.res if x <= 1e-8)
+        out[label] = {"pairs": ok, "wave_solves": r.wave_solves, "seconds": dt, "eigenpairs_per_s": ok / dt,
+                      "max_res": max(r.res)}
+        log(f"walls form: {label}: {ok} pairs, {r.wave_solves} wave-solves, {dt * 1e3:.1f} ms")
+        op.close()
+    return out
+
+
 def headline_np_rule(budget: int = 200):
     """The headline eigenproblem (2047^2, order 4, implicit, omega 120, k = 16)
     with N_p from the lobe rule and m = 2k + 1, within `budget` wave-solves.
@@ -382,6 +431,8 @@ def main(argv=None) -> int:
                     help="requested counts of the many-pairs form (default: the paper's table rows)")
     ap.add_argument("--only-many-pairs", action="store_true",
                     help="run only the many-pairs form and print its JSON (for profiling)")
+    ap.add_argument("--only-walls", action="store_true",
+                    help="run only the Neumann-walls form and print its JSON (for profiling)")
     ap.add_argument("--headline-np-rule", action="store_true",
                     help="run only the headline eigenproblem with the N_p of the lobe rule (about 2.5 min) and "
                          "print its JSON")
@@ -397,6 +448,9 @@ def main(argv=None) -> int:
     torch.cuda.set_device(0)
     if a.only_many_pairs:
         print(json.dumps({"form": "many_pairs", "result": many_pairs(a.many_k)}), flush=True)
+        return 0
+    if a.only_walls:
+        print(json.dumps({"form": "walls", "result": walls_form()}), flush=True)
         return 0
     if a.headline_np_rule:
         print(json.dumps({"form": "headline_np_rule", "result": headline_np_rule()}), flush=True)
@@ -468,6 +522,7 @@ def main(argv=None) -> int:
         forms["learned_vs_plain"] = learned_vs_plain()
         forms["periods_rule"] = periods_rule()
         forms["many_pairs"] = many_pairs(a.many_k)
+        forms["walls"] = walls_form()
 
     cpu = None
     if not a.no_cpu_baseline:
