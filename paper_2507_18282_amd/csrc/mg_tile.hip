@@ -90,11 +90,13 @@ __device__ __forceinline__ T d2_lds(const T* X, int p, int stride, int gi, int n
     return T(16) * (l1 + r1) - (l2 + r2) - T(30) * uc;
 }
 
+// L_h at LDS cell p whose neighbours beyond a wall read 0: the wall closures
+// of d2_framed (Dirichlet odd reflection, Neumann even reflection).
 template <typename T, int ORDER, int DIM>
 __device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, int gj, int gk, const Geo& g, T uc) {
-    T s = d2_lds<T, ORDER>(X, p, 1, gi, g.nx, uc) * axis_coef<T, ORDER>(g.ihx2);
-    s += d2_lds<T, ORDER>(X, p, sy, gj, g.ny, uc) * axis_coef<T, ORDER>(g.ihy2);
-    if (DIM == 3) s += d2_lds<T, ORDER>(X, p, sz, gk, g.nz, uc) * axis_coef<T, ORDER>(g.ihz2);
+    T s = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3) * axis_coef<T, ORDER>(g.ihx2);
+    s += d2_framed<T, ORDER>(X, p, sy, gj, g.ny, uc, (g.wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3) s += d2_framed<T, ORDER>(X, p, sz, gk, g.nz, uc, (g.wall >> 4) & 3) * axis_coef<T, ORDER>(g.ihz2);
     return s;
 }
 
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
 // ---------------------------------------------------------------------------
 // Residual + full-weighting restriction per coarse tile.
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM, int CY>
+template <typename T, int ORDER, int DIM, int CY, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restrict__ x, const T* __restrict__ b,
                                                                 T bscale, Geo gf, T a, T* __restrict__ bc, Geo gc) {
     constexpr int CX = RestrictTile<DIM>::CX, CZ = RestrictTile<DIM>::CZ;
@@ -225,7 +227,10 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
     __shared__ T Rf[FX * FY * FZ];
     const int tid = threadIdx.x;
     const int cx0 = blockIdx.x * CX, cy0 = blockIdx.y * CY, cz0 = (DIM == 3) ? blockIdx.z * CZ : 0;
-    const int fx0 = 2 * cx0, fy0 = 2 * cy0, fz0 = (DIM == 3) ? 2 * cz0 : 0;  // first fine point of the region
+    // first fine point of the region: fine centre of coarse I is 2I + 1 behind
+    // a Dirichlet low wall, 2I behind a Neumann one (WALLS, 2D)
+    const int sx = (WALLS && (gf.wall & 1)) ? -1 : 0, sy = (WALLS && (gf.wall & 4)) ? -1 : 0;
+    const int fx0 = 2 * cx0 + sx, fy0 = 2 * cy0 + sy, fz0 = (DIM == 3) ? 2 * cz0 : 0;
     // Staging as in the sweep: x (region + R) and b (region) go to registers
     // with every load issued before the first use.
     constexpr int NX = LX * LY * LZ, NF = FX * FY * FZ;
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         if (q < NF) {
             const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
             const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
-            if (gi < gf.nx && gj < gf.ny && gk < gf.nz) v = b[lin(gf, gi, gj, gk)];
+            if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk < gf.nz) v = b[lin(gf, gi, gj, gk)];
         }
         bv[t] = v;
     }
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
         const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
         T r = T(0);
-        if (gi < gf.nx && gj < gf.ny && gk < gf.nz) {
+        if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk < gf.nz) {
             const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
             const T uc = X[p];
             r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
@@ -274,6 +279,23 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         Rf[q] = r;
     }
     __syncthreads();
+    if (WALLS) {
+        // region cells beyond a Neumann wall take the residual of their even
+        // mirror inside the box (only in-range cells are read here)
+        for (int q = tid; q < NF; q += kTileThreads) {
+            const int fx = q % FX, fy = q / FX;
+            int gi = fx0 + fx, gj = fy0 + fy;
+            const bool out = gi < 0 || gi >= gf.nx || gj < 0 || gj >= gf.ny;
+            if (!out) continue;
+            if (gi < 0 && (gf.wall & 1)) gi = -gi;
+            if (gi >= gf.nx && (gf.wall & 2)) gi = 2 * (gf.nx - 1) - gi;
+            if (gj < 0 && (gf.wall & 4)) gj = -gj;
+            if (gj >= gf.ny && (gf.wall & 8)) gj = 2 * (gf.ny - 1) - gj;
+            if (gi < 0 || gi >= gf.nx || gj < 0 || gj >= gf.ny) continue;  // beyond a Dirichlet wall: stays 0
+            Rf[q] = Rf[(gi - fx0) + FX * (gj - fy0)];
+        }
+        __syncthreads();
+    }
     for (int q = tid; q < CX * CY * CZ; q += kTileThreads) {
         const int cx = q % CX, cy = (q / CX) % CY, cz = q / (CX * CY);
         const int ic = cx0 + cx, jc = cy0 + cy, kc = cz0 + cz;
@@ -589,16 +611,20 @@ static hipError_t restrict_dispatch(const T* x, const T* b, T bs, const Geo& gf,
     constexpr int CX = RestrictTile<DIM>::CX, CY = RestrictTile<DIM>::CY, CZ = RestrictTile<DIM>::CZ;
     // short tiles (less serial work per block) when tall ones would not fill the chip
     const int64_t tall = (int64_t)((gc.nx + CX - 1) / CX) * ((gc.ny + CY - 1) / CY) * (DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
+    // Neumann walls: 2D only (3D boxes with Neumann walls restrict with the plain kernel)
+    if (gf.wall && DIM != 2) return hipErrorInvalidValue;
     if (DIM == 2 && tall < 1024) {
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + 3) / 4, 1);
-        k_restrict_tile<T, ORDER, DIM, 4><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+        if (gf.wall) k_restrict_tile<T, ORDER, DIM, 4, true><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+        else k_restrict_tile<T, ORDER, DIM, 4, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
     } else if (DIM == 2) {
         // 32 x 8 coarse tiles: half the LDS of 32 x 16, twice the workgroups per CU
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + 7) / 8, 1);
-        k_restrict_tile<T, ORDER, DIM, 8><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+        if (gf.wall) k_restrict_tile<T, ORDER, DIM, 8, true><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+        else k_restrict_tile<T, ORDER, DIM, 8, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
     } else {
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + CY - 1) / CY, DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
-        k_restrict_tile<T, ORDER, DIM, CY><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+        k_restrict_tile<T, ORDER, DIM, CY, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
     }
     return hipGetLastError();
 }

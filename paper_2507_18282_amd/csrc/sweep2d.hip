@@ -22,7 +22,7 @@ constexpr int kTileThreads = 256;
 // the constant interior diagonal; points whose diagonal carries an order-4
 // ghost divide.
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG>
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restrict__ xin, const T* __restrict__ xc,
                                                                const T* __restrict__ b, T bscale, T* __restrict__ xout,
                                                                Geo g, Geo gc, T a, T inv_diag) {
@@ -95,11 +95,14 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
                 const int ly = q / LX, lx = q - ly * LX;
                 const int gi = x0 - H + lx, gj = y0 - H + ly;
                 if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
-                    // fine index odd -> coarse (f-1)/2; even -> mean of f/2-1 and f/2
-                    const int ia = ((gi - 1) >> 1) - cx0, ib = (gi >> 1) - cx0;
-                    const int ja = ((gj - 1) >> 1) - cy0, jb = (gj >> 1) - cy0;
-                    const T wia = (gi & 1) ? T(1) : T(0.5), wib = (gi & 1) ? T(0) : T(0.5);
-                    const T wja = (gj & 1) ? T(1) : T(0.5), wjb = (gj & 1) ? T(0) : T(0.5);
+                    // q = f - off (off = 1 behind a Dirichlet low wall, 0 behind a
+                    // Neumann one): q even -> coarse q/2; odd -> mean of (q-1)/2 and (q+1)/2
+                    const int qi = WALLS ? gi - ((g.wall & 1) ? 0 : 1) : gi - 1;
+                    const int qj = WALLS ? gj - ((g.wall & 4) ? 0 : 1) : gj - 1;
+                    const int ia = (qi >> 1) - cx0, ib = ((qi + 1) >> 1) - cx0;
+                    const int ja = (qj >> 1) - cy0, jb = ((qj + 1) >> 1) - cy0;
+                    const T wia = (qi & 1) ? T(0.5) : T(1), wib = (qi & 1) ? T(0.5) : T(0);
+                    const T wja = (qj & 1) ? T(0.5) : T(1), wjb = (qj & 1) ? T(0.5) : T(0);
                     const T rowa = wia * XC[ja * CXW + ia] + wib * XC[ja * CXW + ib];
                     const T rowb = wia * XC[jb * CXW + ia] + wib * XC[jb * CXW + ib];
                     v += wja * rowa + wjb * rowb;
@@ -121,7 +124,11 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
         const int p = ly * LX + lx;
         const T uc = X[p];
         T dx, dy;
-        if (ORDER == 2) {
+        if (WALLS) {
+            // Neumann walls: the even-reflection closure replaces the zero halo
+            dx = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3);
+            dy = d2_framed<T, ORDER>(X, p, LX, gj, g.ny, uc, (g.wall >> 2) & 3);
+        } else if (ORDER == 2) {
             dx = X[p - 1] + X[p + 1] - T(2) * uc;
             dy = X[p - LX] + X[p + LX] - T(2) * uc;
         } else {
@@ -133,7 +140,10 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
             dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
         }
         const T r = bval - (uc - a * (dx * cxc + dy * cyc));
-        const bool edge = ORDER == 4 && (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1);
+        // the diagonal differs from the interior one where a ghost refers back to
+        // the point: at a Dirichlet wall point, one point inside a Neumann wall
+        const bool edge = ORDER == 4 && (WALLS ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
+                                               : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
         return edge ? uc + r / mdiag_at<T, ORDER, 2>(gi, gj, 0, g, a) : uc + r * inv_diag;
     };
 
@@ -201,7 +211,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
 // sweeps and saves one launch per level.  (A layout with one LDS array per
 // colour, which makes the lanes' LDS reads contiguous, measured slower.)
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int TY, bool ZERO_IN>
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __restrict__ xin, const T* __restrict__ b,
                                                                  T bscale, T* __restrict__ xout, Geo g, T a,
                                                                  T inv_diag) {
@@ -259,7 +269,10 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
         const T bval = B[(gj - y0 + BH) * BX + (gi - x0 + BH)];
         const T uc = X[p];
         T dx, dy;
-        if (ORDER == 2) {
+        if (WALLS) {
+            dx = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3);
+            dy = d2_framed<T, ORDER>(X, p, LX, gj, g.ny, uc, (g.wall >> 2) & 3);
+        } else if (ORDER == 2) {
             dx = X[p - 1] + X[p + 1] - T(2) * uc;
             dy = X[p - LX] + X[p + LX] - T(2) * uc;
         } else {
@@ -271,7 +284,8 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
             dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
         }
         const T r = bval - (uc - a * (dx * cxc + dy * cyc));
-        const bool edge = ORDER == 4 && (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1);
+        const bool edge = ORDER == 4 && (WALLS ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
+                                               : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
         return edge ? uc + r / mdiag_at<T, ORDER, 2>(gi, gj, 0, g, a) : uc + r * inv_diag;
     };
     // one half-sweep of colour `colour` on the tile plus K layers: new values to
@@ -322,20 +336,20 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
 
 // hipExtLaunchKernelGGL records ev0/ev1 (when given) at the dispatch's own
 // start and end, so profiling this kernel adds no separate event commands.
-template <typename T, int ORDER, int TY>
+template <typename T, int ORDER, int TY, bool WALLS>
 static hipError_t sweep2d_launch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
                                  T aa, T inv, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
                                  hipEvent_t ev1) {
     dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
     dim3 block(kTileThreads);
     if (zero_in && prolong)
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, true>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
     else if (zero_in)
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, false>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
     else if (prolong)
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, true>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
     else
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, false>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
     return hipGetLastError();
 }
 
@@ -351,20 +365,25 @@ static hipError_t sweep2d_dispatch(const T* xin, const T* xc, const T* b, T bs, 
     // enough of them to fill the chip, 64 x 8 (less serial work per block) on
     // smaller levels; measured faster than 64 x 32 tiles on 2047^2
     const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
+    if (g.wall) {
+        if (tiles16 >= 2048)
+            return sweep2d_launch<T, ORDER, 16, true>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+        return sweep2d_launch<T, ORDER, 8, true>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+    }
     if (tiles16 >= 2048)
-        return sweep2d_launch<T, ORDER, 16>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
-    return sweep2d_launch<T, ORDER, 8>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+        return sweep2d_launch<T, ORDER, 16, false>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+    return sweep2d_launch<T, ORDER, 8, false>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
 }
 
-template <typename T, int ORDER, int TY>
+template <typename T, int ORDER, int TY, bool WALLS>
 static hipError_t sweep2x_launch(const T* xin, const T* b, T bs, T* xout, const Geo& g, T aa, T inv, bool zero_in,
                                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
     dim3 block(kTileThreads);
     if (zero_in)
-        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, true>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
     else
-        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, false>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
     return hipGetLastError();
 }
 
@@ -375,8 +394,12 @@ static hipError_t sweep2x_dispatch(const T* xin, const T* b, T bs, T* xout, cons
     const T inv = (T)(1.0 / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
     const T aa = (T)a;
     const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
-    if (tiles16 >= 2048) return sweep2x_launch<T, ORDER, 16>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
-    return sweep2x_launch<T, ORDER, 8>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+    if (g.wall) {
+        if (tiles16 >= 2048) return sweep2x_launch<T, ORDER, 16, true>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+        return sweep2x_launch<T, ORDER, 8, true>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+    }
+    if (tiles16 >= 2048) return sweep2x_launch<T, ORDER, 16, false>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+    return sweep2x_launch<T, ORDER, 8, false>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
 }
 
 template <typename T>

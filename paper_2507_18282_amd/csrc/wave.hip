@@ -15,9 +15,9 @@ template <typename T>
 ew_status Op::sweep(int l, T*& cur, T*& other, const T* b, double bscale, bool zero, const T* xc) {
     const Level& L = levels[l];
     const Geo gc = (xc != nullptr) ? levels[l + 1].g : L.g;
-    if (L.g.wall) {
-        // boxes with Neumann walls: the plain kernels (wall-aware stencils and
-        // transfers from global memory), two out-of-place half-sweeps
+    if (L.g.wall && L.g.dim == 3) {
+        // 3D boxes with Neumann walls: the plain kernels (wall-aware stencils
+        // and transfers from global memory), two out-of-place half-sweeps
         if (zero) EW_HIP_TRY(launch_fill<T>(cur, L.g.size(), T(0), stream));
         if (xc) EW_HIP_TRY(launch_prolong_correct<T>(cur, xc, L.g, gc, stream));
         EW_HIP_TRY(launch_rb_half<T>(cur, other, b, bscale, L.g, order, a, 0, stream));
@@ -43,7 +43,7 @@ ew_status Op::sweeps(int l, int count, T*& cur, T*& other, const T* b, double bs
     const Level& L = levels[l];
     const double n = (double)L.g.size();
     int s = 0;
-    if (L.g.dim == 2 && !L.g.wall) {
+    if (L.g.dim == 2) {
         for (; s + 1 < count; s += 2) {
             const bool z = zero && s == 0;
             // algorithmic bytes counted per sweep (x, b read and x written once per
@@ -88,7 +88,7 @@ ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool ze
     const Level& C = levels[l + 1];
     {
         ProfScope ps(this, EW_K_RESTRICT, l, sizeof(T) * (2.0 * L.g.size() + C.g.size()));
-        if (L.g.wall)
+        if (L.g.wall && L.g.dim == 3)
             EW_HIP_TRY(launch_restrict_plain<T>(cur, b, bscale, L.g, order, a, (T*)C.b, C.g, stream));
         else
             EW_HIP_TRY(launch_restrict_tile<T>(cur, b, bscale, L.g, order, a, (T*)C.b, C.g, stream));
