@@ -490,7 +490,7 @@ def main(argv=None) -> int:
     # once, so its minimum traffic is half of that (frac_min_traffic).
     roofline = {"bound": "hbm",
                 "kernel": "two red-black Gauss-Seidel sweeps in one pass, finest level "
-                          "(k_sweep2x_tile2d<double, 4, 16, false>)",
+                          "(k_sweep2x_tile2d<double, 4, 16, false, false>)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "launches": prof["launches"], "avg_us": round(avg_ms * 1e3, 3),

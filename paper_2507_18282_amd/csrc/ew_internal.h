@@ -81,11 +81,7 @@ hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, cons
                           int colour, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& gc, hipStream_t s);
-// bc = full weighting of r = bscale b - M x, evaluated point by point from
-// global memory (any walls).
-template <typename T>
-hipError_t launch_restrict_plain(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
-                                 const Geo& gc, hipStream_t s);
+
 // Partial sums of r^2, r = bscale*b - (x - a L x), one per block (kRedBlocks).
 // With r_out != nullptr the residual is also stored (converted to TR).
 template <typename T, typename TR>

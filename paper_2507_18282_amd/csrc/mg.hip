@@ -100,66 +100,6 @@ __global__ __launch_bounds__(256) void k_prolong_correct(T* __restrict__ x, cons
     x[cf] = x[cf] + v;
 }
 
-// --------------------------------------------------------------------------
-// Residual r = bscale b - M x and its full-weighting restriction in one pass
-// per coarse point, every residual evaluated from global memory (the plain
-// path used for boxes with Neumann walls).  The fine centre of coarse point I
-// is 2I + off (off as for the prolongation); a neighbour beyond a Neumann
-// wall point is its even mirror (the residual of the evenly extended problem).
-// --------------------------------------------------------------------------
-__device__ __forceinline__ int mirror_index(int f, int n, bool nlo, bool nhi) {
-    if (f < 0 && nlo) return -f;
-    if (f >= n && nhi) return 2 * (n - 1) - f;
-    return f;
-}
-
-template <typename T, int ORDER, int DIM>
-__global__ __launch_bounds__(256) void k_restrict_plain(const T* __restrict__ x, const T* __restrict__ b, T bscale,
-                                                        Geo gf, T a, T* __restrict__ bc, Geo gc) {
-    int I, J, K;
-    if (!tile_coords(gc, I, J, K)) return;
-    const int ox = (gf.wall & 1) ? 0 : 1, oy = (gf.wall & 4) ? 0 : 1, oz = (gf.wall & 16) ? 0 : 1;
-    const int fi = 2 * I + ox, fj = 2 * J + oy, fk = (DIM == 3) ? 2 * K + oz : 0;
-    T sum = T(0);
-    const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
-    for (int dz = zlo; dz <= zhi; ++dz) {
-        const int k = (DIM == 3) ? mirror_index(fk + dz, gf.nz, gf.wall & 16, gf.wall & 32) : 0;
-        T plane = T(0);
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int j = mirror_index(fj + dy, gf.ny, gf.wall & 4, gf.wall & 8);
-            T row = T(0);
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int i = mirror_index(fi + dx, gf.nx, gf.wall & 1, gf.wall & 2);
-                T r = T(0);
-                if (i >= 0 && i < gf.nx && j >= 0 && j < gf.ny && k >= 0 && k < gf.nz) {
-                    const int64_t c = lin(gf, i, j, k);
-                    const T xc = x[c];
-                    r = bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM>(x, c, i, j, k, gf, xc));
-                }
-                row += (dx == 0 ? T(0.5) : T(0.25)) * r;
-            }
-            plane += (dy == 0 ? T(0.5) : T(0.25)) * row;
-        }
-        sum += (DIM == 3) ? (dz == 0 ? T(0.5) : T(0.25)) * plane : plane;
-    }
-    bc[lin(gc, I, J, K)] = sum;
-}
-
-template <typename T>
-hipError_t launch_restrict_plain(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
-                                 const Geo& gc, hipStream_t s) {
-    dim3 grid = tile_grid(gc), block(kTileX, kTileY, 1);
-    const T bs = (T)bscale, aa = (T)a;
-    if (gf.dim == 2) {
-        if (order == 2) k_restrict_plain<T, 2, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-        else k_restrict_plain<T, 4, 2><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-    } else {
-        if (order == 2) k_restrict_plain<T, 2, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-        else k_restrict_plain<T, 4, 3><<<grid, block, 0, s>>>(x, b, bs, gf, aa, bc, gc);
-    }
-    return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& gc, hipStream_t s) {
     dim3 grid = tile_grid(gf), block(kTileX, kTileY, 1);
@@ -207,9 +147,7 @@ hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo
 #define EW_INST_MG(T)                                                                                          \
     template hipError_t launch_rb_half<T>(const T*, T*, const T*, double, const Geo&, int, double, int,         \
                                           hipStream_t);                                                        \
-    template hipError_t launch_prolong_correct<T>(T*, const T*, const Geo&, const Geo&, hipStream_t);            \
-    template hipError_t launch_restrict_plain<T>(const T*, const T*, double, const Geo&, int, double, T*, const Geo&, \
-                                                 hipStream_t);
+    template hipError_t launch_prolong_correct<T>(T*, const T*, const Geo&, const Geo&, hipStream_t);
 EW_INST_MG(double)
 EW_INST_MG(float)
 #undef EW_INST_MG

@@ -39,23 +39,29 @@ template <> struct RestrictTile<3> { static constexpr int CX = 16, CY = 4, CZ = 
 
 constexpr int kTileThreads = 256;
 
-__device__ __forceinline__ void interp_axis(int f, int nc, int& c0, int& c1, double& w0, double& w1) {
-    if (f & 1) {
-        c0 = (f - 1) >> 1; c1 = -1; w0 = 1.0; w1 = 0.0;
+// Coarse neighbours of fine index f along one axis: q = f - off (off = 1
+// behind a Dirichlet low wall, where coarse I sits at fine 2I + 1; 0 behind a
+// Neumann one, where it sits at 2I); q even -> coarse q/2, odd -> mean of
+// (q-1)/2 and (q+1)/2; a neighbour beyond a Dirichlet wall is dropped (0).
+__device__ __forceinline__ void interp_axis(int f, int nc, int off, int& c0, int& c1, double& w0, double& w1) {
+    const int q = f - off;
+    if (q >= 0 && !(q & 1)) {
+        c0 = q >> 1; c1 = -1; w0 = 1.0; w1 = 0.0;
     } else {
-        c0 = (f >> 1) - 1; c1 = f >> 1; w0 = 0.5; w1 = 0.5;
+        c0 = (q - 1) >> 1; c1 = c0 + 1; w0 = 0.5; w1 = 0.5;
         if (c1 >= nc) c1 = -1;
     }
 }
 
-// Multilinear interpolation of the coarse grid function at fine point (i,j,k).
+// Multilinear interpolation of the coarse grid function at fine point (i,j,k);
+// wall = the fine level's Neumann-wall bits.
 template <typename T, int DIM>
-__device__ __forceinline__ T prolong_at(const T* __restrict__ xc, const Geo& gc, int i, int j, int k) {
+__device__ __forceinline__ T prolong_at(const T* __restrict__ xc, const Geo& gc, int i, int j, int k, int wall) {
     int xi[2], yj[2], zk[2];
     double wx[2], wy[2], wz[2];
-    interp_axis(i, gc.nx, xi[0], xi[1], wx[0], wx[1]);
-    interp_axis(j, gc.ny, yj[0], yj[1], wy[0], wy[1]);
-    if (DIM == 3) interp_axis(k, gc.nz, zk[0], zk[1], wz[0], wz[1]);
+    interp_axis(i, gc.nx, (wall & 1) ? 0 : 1, xi[0], xi[1], wx[0], wx[1]);
+    interp_axis(j, gc.ny, (wall & 4) ? 0 : 1, yj[0], yj[1], wy[0], wy[1]);
+    if (DIM == 3) interp_axis(k, gc.nz, (wall & 16) ? 0 : 1, zk[0], zk[1], wz[0], wz[1]);
     else { zk[0] = 0; zk[1] = -1; wz[0] = 1.0; wz[1] = 0.0; }
     T v = T(0);
 #pragma unroll
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
             const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
             const int gi = x0 - H + lx, gj = y0 - H + ly, gk = (DIM == 3) ? z0 - H + lz : 0;
             if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz)
-                X[q] += prolong_at<T, DIM>(xc, gc, gi, gj, gk);
+                X[q] += prolong_at<T, DIM>(xc, gc, gi, gj, gk, g.wall);
         }
     }
     __syncthreads();
@@ -230,7 +236,8 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
     // first fine point of the region: fine centre of coarse I is 2I + 1 behind
     // a Dirichlet low wall, 2I behind a Neumann one (WALLS, 2D)
     const int sx = (WALLS && (gf.wall & 1)) ? -1 : 0, sy = (WALLS && (gf.wall & 4)) ? -1 : 0;
-    const int fx0 = 2 * cx0 + sx, fy0 = 2 * cy0 + sy, fz0 = (DIM == 3) ? 2 * cz0 : 0;
+    const int sz = (WALLS && DIM == 3 && (gf.wall & 16)) ? -1 : 0;
+    const int fx0 = 2 * cx0 + sx, fy0 = 2 * cy0 + sy, fz0 = (DIM == 3) ? 2 * cz0 + sz : 0;
     // Staging as in the sweep: x (region + R) and b (region) go to registers
     // with every load issued before the first use.
     constexpr int NX = LX * LY * LZ, NF = FX * FY * FZ;
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         if (q < NF) {
             const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
             const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
-            if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk < gf.nz) v = b[lin(gf, gi, gj, gk)];
+            if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) v = b[lin(gf, gi, gj, gk)];
         }
         bv[t] = v;
     }
@@ -271,7 +278,7 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
         const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
         T r = T(0);
-        if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk < gf.nz) {
+        if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) {
             const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
             const T uc = X[p];
             r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
@@ -283,16 +290,19 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         // region cells beyond a Neumann wall take the residual of their even
         // mirror inside the box (only in-range cells are read here)
         for (int q = tid; q < NF; q += kTileThreads) {
-            const int fx = q % FX, fy = q / FX;
-            int gi = fx0 + fx, gj = fy0 + fy;
-            const bool out = gi < 0 || gi >= gf.nx || gj < 0 || gj >= gf.ny;
+            const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
+            int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
+            const bool out = gi < 0 || gi >= gf.nx || gj < 0 || gj >= gf.ny || gk < 0 || gk >= gf.nz;
             if (!out) continue;
             if (gi < 0 && (gf.wall & 1)) gi = -gi;
             if (gi >= gf.nx && (gf.wall & 2)) gi = 2 * (gf.nx - 1) - gi;
             if (gj < 0 && (gf.wall & 4)) gj = -gj;
             if (gj >= gf.ny && (gf.wall & 8)) gj = 2 * (gf.ny - 1) - gj;
-            if (gi < 0 || gi >= gf.nx || gj < 0 || gj >= gf.ny) continue;  // beyond a Dirichlet wall: stays 0
-            Rf[q] = Rf[(gi - fx0) + FX * (gj - fy0)];
+            if (DIM == 3 && gk < 0 && (gf.wall & 16)) gk = -gk;
+            if (DIM == 3 && gk >= gf.nz && (gf.wall & 32)) gk = 2 * (gf.nz - 1) - gk;
+            if (gi < 0 || gi >= gf.nx || gj < 0 || gj >= gf.ny || gk < 0 || gk >= gf.nz)
+                continue;  // beyond a Dirichlet wall: stays 0
+            Rf[q] = Rf[(gi - fx0) + FX * ((gj - fy0) + FY * (gk - fz0))];
         }
         __syncthreads();
     }
@@ -611,8 +621,6 @@ static hipError_t restrict_dispatch(const T* x, const T* b, T bs, const Geo& gf,
     constexpr int CX = RestrictTile<DIM>::CX, CY = RestrictTile<DIM>::CY, CZ = RestrictTile<DIM>::CZ;
     // short tiles (less serial work per block) when tall ones would not fill the chip
     const int64_t tall = (int64_t)((gc.nx + CX - 1) / CX) * ((gc.ny + CY - 1) / CY) * (DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
-    // Neumann walls: 2D only (3D boxes with Neumann walls restrict with the plain kernel)
-    if (gf.wall && DIM != 2) return hipErrorInvalidValue;
     if (DIM == 2 && tall < 1024) {
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + 3) / 4, 1);
         if (gf.wall) k_restrict_tile<T, ORDER, DIM, 4, true><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
@@ -624,7 +632,8 @@ static hipError_t restrict_dispatch(const T* x, const T* b, T bs, const Geo& gf,
         else k_restrict_tile<T, ORDER, DIM, 8, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
     } else {
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + CY - 1) / CY, DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
-        k_restrict_tile<T, ORDER, DIM, CY, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+        if (gf.wall) k_restrict_tile<T, ORDER, DIM, CY, true><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
+        else k_restrict_tile<T, ORDER, DIM, CY, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
     }
     return hipGetLastError();
 }

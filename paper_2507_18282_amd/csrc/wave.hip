@@ -15,15 +15,6 @@ template <typename T>
 ew_status Op::sweep(int l, T*& cur, T*& other, const T* b, double bscale, bool zero, const T* xc) {
     const Level& L = levels[l];
     const Geo gc = (xc != nullptr) ? levels[l + 1].g : L.g;
-    if (L.g.wall && L.g.dim == 3) {
-        // 3D boxes with Neumann walls: the plain kernels (wall-aware stencils
-        // and transfers from global memory), two out-of-place half-sweeps
-        if (zero) EW_HIP_TRY(launch_fill<T>(cur, L.g.size(), T(0), stream));
-        if (xc) EW_HIP_TRY(launch_prolong_correct<T>(cur, xc, L.g, gc, stream));
-        EW_HIP_TRY(launch_rb_half<T>(cur, other, b, bscale, L.g, order, a, 0, stream));
-        EW_HIP_TRY(launch_rb_half<T>(other, cur, b, bscale, L.g, order, a, 1, stream));
-        return EW_OK;
-    }
     const double n = (double)L.g.size();
     double bytes = sizeof(T) * ((zero ? 2.0 : 3.0) * n);
     if (xc) bytes += sizeof(T) * (double)gc.size();
@@ -88,10 +79,7 @@ ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool ze
     const Level& C = levels[l + 1];
     {
         ProfScope ps(this, EW_K_RESTRICT, l, sizeof(T) * (2.0 * L.g.size() + C.g.size()));
-        if (L.g.wall && L.g.dim == 3)
-            EW_HIP_TRY(launch_restrict_plain<T>(cur, b, bscale, L.g, order, a, (T*)C.b, C.g, stream));
-        else
-            EW_HIP_TRY(launch_restrict_tile<T>(cur, b, bscale, L.g, order, a, (T*)C.b, C.g, stream));
+        EW_HIP_TRY(launch_restrict_tile<T>(cur, b, bscale, L.g, order, a, (T*)C.b, C.g, stream));
     }
     T* xc = nullptr;
     EW_TRY(vcycle<T>(l + 1, (T*)C.x[0], (T*)C.x[1], (T*)C.b, 1.0, true, &xc));
