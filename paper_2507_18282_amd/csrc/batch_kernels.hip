@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_batch_step(BatchProbDev* __restrict__ p
         if (j >= g.ny) break;
         const int64_t cidx = (int64_t)j * g.nx + i;
         const float uc = wcur[cidx];
-        const float lap = lap_at<float, ORDER, 2>(wcur, cidx, i, j, 0, g, uc);
+        const float lap = lap_at<float, ORDER, 2, false>(wcur, cidx, i, j, 0, g, uc);
         float wn;
         if (step == 0) {
             wn = uc + (0.5f * dt2) * lap;

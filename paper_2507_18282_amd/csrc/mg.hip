@@ -12,7 +12,7 @@ namespace ew {
 // are copied.  Out of place because for order 4 the +-2 neighbours share the
 // colour and must be read before any of them is overwritten.
 // --------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM>
+template <typename T, int ORDER, int DIM, bool WALLS>
 __global__ __launch_bounds__(256) void k_rb_half(const T* __restrict__ xin, T* __restrict__ xout,
                                                  const T* __restrict__ b, T bscale, Geo g, T a, int colour) {
     int i, j, k;
@@ -23,9 +23,9 @@ __global__ __launch_bounds__(256) void k_rb_half(const T* __restrict__ xin, T* _
         xout[c] = xc;
         return;
     }
-    const T lap = lap_at<T, ORDER, DIM>(xin, c, i, j, k, g, xc);
+    const T lap = lap_at<T, ORDER, DIM, WALLS>(xin, c, i, j, k, g, xc);
     const T r = bscale * b[c] - (xc - a * lap);
-    xout[c] = xc + r / mdiag_at<T, ORDER, DIM>(i, j, k, g, a);
+    xout[c] = xc + r / mdiag_at<T, ORDER, DIM, WALLS>(i, j, k, g, a);
 }
 
 template <typename T>
@@ -33,13 +33,17 @@ hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, cons
                           int colour, hipStream_t s) {
     dim3 grid = tile_grid(g), block(kTileX, kTileY, 1);
     const T bs = (T)bscale, aa = (T)a;
+#define EW_RB(O, D)                                                                                   \
+    do {                                                                                              \
+        if (g.wall) k_rb_half<T, O, D, true><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);  \
+        else k_rb_half<T, O, D, false><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);       \
+    } while (0)
     if (g.dim == 2) {
-        if (order == 2) k_rb_half<T, 2, 2><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
-        else k_rb_half<T, 4, 2><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
+        if (order == 2) EW_RB(2, 2); else EW_RB(4, 2);
     } else {
-        if (order == 2) k_rb_half<T, 2, 3><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
-        else k_rb_half<T, 4, 3><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);
+        if (order == 2) EW_RB(2, 3); else EW_RB(4, 3);
     }
+#undef EW_RB
     return hipGetLastError();
 }
 
@@ -111,7 +115,7 @@ hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& g
 // --------------------------------------------------------------------------
 // Residual norm partials (and optionally the residual itself, converted).
 // --------------------------------------------------------------------------
-template <typename T, typename TR, int ORDER, int DIM>
+template <typename T, typename TR, int ORDER, int DIM, bool WALLS>
 __global__ __launch_bounds__(256) void k_residual_norm(const T* __restrict__ x, const T* __restrict__ b, T bscale,
                                                        Geo g, T a, double* __restrict__ partial, TR* __restrict__ r_out) {
     const int64_t n = g.size();
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(256) void k_residual_norm(const T* __restrict__ x, 
         const int j = (int)(q % g.ny);
         const int k = (int)(q / g.ny);
         const T xc = x[c];
-        const T r = bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM>(x, c, i, j, k, g, xc));
+        const T r = bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM, WALLS>(x, c, i, j, k, g, xc));
         if (r_out) r_out[c] = (TR)r;
         acc += (double)r * (double)r;
     }
@@ -134,13 +138,17 @@ template <typename T, typename TR>
 hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo& g, int order, double a,
                                 double* partial, TR* r_out, hipStream_t s) {
     const T bs = (T)bscale, aa = (T)a;
+#define EW_RN(O, D)                                                                                                \
+    do {                                                                                                           \
+        if (g.wall) k_residual_norm<T, TR, O, D, true><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out); \
+        else k_residual_norm<T, TR, O, D, false><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);      \
+    } while (0)
     if (g.dim == 2) {
-        if (order == 2) k_residual_norm<T, TR, 2, 2><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
-        else k_residual_norm<T, TR, 4, 2><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
+        if (order == 2) EW_RN(2, 2); else EW_RN(4, 2);
     } else {
-        if (order == 2) k_residual_norm<T, TR, 2, 3><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
-        else k_residual_norm<T, TR, 4, 3><<<kRedBlocks, 256, 0, s>>>(x, b, bs, g, aa, partial, r_out);
+        if (order == 2) EW_RN(2, 3); else EW_RN(4, 3);
     }
+#undef EW_RN
     return hipGetLastError();
 }
 

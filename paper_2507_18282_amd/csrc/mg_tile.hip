@@ -97,9 +97,16 @@ __device__ __forceinline__ T d2_lds(const T* X, int p, int stride, int gi, int n
 }
 
 // L_h at LDS cell p whose neighbours beyond a wall read 0: the wall closures
-// of d2_framed (Dirichlet odd reflection, Neumann even reflection).
-template <typename T, int ORDER, int DIM>
+// of d2_framed (Dirichlet odd reflection, Neumann even reflection).  WALLS =
+// false compiles the Dirichlet-only closure.
+template <typename T, int ORDER, int DIM, bool WALLS>
 __device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, int gj, int gk, const Geo& g, T uc) {
+    if (!WALLS) {
+        T s = d2_lds<T, ORDER>(X, p, 1, gi, g.nx, uc) * axis_coef<T, ORDER>(g.ihx2);
+        s += d2_lds<T, ORDER>(X, p, sy, gj, g.ny, uc) * axis_coef<T, ORDER>(g.ihy2);
+        if (DIM == 3) s += d2_lds<T, ORDER>(X, p, sz, gk, g.nz, uc) * axis_coef<T, ORDER>(g.ihz2);
+        return s;
+    }
     T s = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3) * axis_coef<T, ORDER>(g.ihx2);
     s += d2_framed<T, ORDER>(X, p, sy, gj, g.ny, uc, (g.wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
     if (DIM == 3) s += d2_framed<T, ORDER>(X, p, sz, gk, g.nz, uc, (g.wall >> 4) & 3) * axis_coef<T, ORDER>(g.ihz2);
@@ -109,7 +116,7 @@ __device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, 
 // ---------------------------------------------------------------------------
 // One full red-black sweep per tile.
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM, bool ZERO_IN, bool PROLONG>
+template <typename T, int ORDER, int DIM, bool ZERO_IN, bool PROLONG, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict__ xin, const T* __restrict__ xc,
                                                              const T* __restrict__ b, T bscale, T* __restrict__ xout,
                                                              Geo g, Geo gc, T a) {
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
             const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
             const int gi = x0 - H + lx, gj = y0 - H + ly, gk = (DIM == 3) ? z0 - H + lz : 0;
             if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz)
-                X[q] += prolong_at<T, DIM>(xc, gc, gi, gj, gk, g.wall);
+                X[q] += prolong_at<T, DIM>(xc, gc, gi, gj, gk, WALLS ? g.wall : 0);
         }
     }
     __syncthreads();
@@ -190,9 +197,9 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
         if (((gi + gj + gk) & 1) != 0) continue;
         const int p = (bx + H - 1) + LX * ((by + H - 1) + LY * ((DIM == 3) ? (bz + H - 1) : 0));
         const T uc = X[p];
-        const T lap = lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
+        const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
         const T r = B[q] - (uc - a * lap);
-        rv[t] = uc + r / mdiag_at<T, ORDER, DIM>(gi, gj, gk, g, a);
+        rv[t] = uc + r / mdiag_at<T, ORDER, DIM, WALLS>(gi, gj, gk, g, a);
         rp[t] = p;
     }
     if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
@@ -210,10 +217,10 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
         const T uc = X[p];
         T out = uc;
         if (((gi + gj + gk) & 1) == 1) {
-            const T lap = lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
+            const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
             const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
             const T r = B[qb] - (uc - a * lap);
-            out = uc + r / mdiag_at<T, ORDER, DIM>(gi, gj, gk, g, a);
+            out = uc + r / mdiag_at<T, ORDER, DIM, WALLS>(gi, gj, gk, g, a);
         }
         xout[lin(g, gi, gj, gk)] = out;
     }
@@ -261,7 +268,9 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         if (q < NF) {
             const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
             const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
-            if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) v = b[lin(gf, gi, gj, gk)];
+            // (a region starts below index 0 only when shifted)
+            if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz)
+                v = b[lin(gf, gi, gj, gk)];
         }
         bv[t] = v;
     }
@@ -278,10 +287,10 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
         const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
         T r = T(0);
-        if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) {
+        if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz) {
             const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
             const T uc = X[p];
-            r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
+            r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
         }
         Rf[q] = r;
     }
@@ -429,7 +438,7 @@ __device__ void pad_half_sweep(T* x, const T* b, const Geo& g, T a, int colour) 
         const T r = b[p] - (xc - a * lap);
         const bool edge = ORDER == 4 && (i == 0 || i == g.nx - 1 || j == 0 || j == g.ny - 1 ||
                                          (DIM == 3 && (k == 0 || k == g.nz - 1)));
-        nv[t] = edge ? xc + r / mdiag_at<T, ORDER, DIM>(i, j, k, g, a) : xc + r * inv_diag;
+        nv[t] = edge ? xc + r / mdiag_at<T, ORDER, DIM, false>(i, j, k, g, a) : xc + r * inv_diag;
         np[t] = p;
     }
     // Order 4 reads same-colour neighbours (old values) that other threads are
@@ -595,10 +604,16 @@ static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T*
                                  T a, bool zero_in, bool prolong, hipStream_t s) {
     constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, DIM == 3 ? (g.nz + TZ - 1) / TZ : 1);
-    if (zero_in && prolong) k_sweep_tile<T, ORDER, DIM, true, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
-    else if (zero_in) k_sweep_tile<T, ORDER, DIM, true, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
-    else if (prolong) k_sweep_tile<T, ORDER, DIM, false, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
-    else k_sweep_tile<T, ORDER, DIM, false, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);
+#define EW_ST(Z, P)                                                                                          \
+    do {                                                                                                     \
+        if (g.wall) k_sweep_tile<T, ORDER, DIM, Z, P, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a); \
+        else k_sweep_tile<T, ORDER, DIM, Z, P, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);      \
+    } while (0)
+    if (zero_in && prolong) EW_ST(true, true);
+    else if (zero_in) EW_ST(true, false);
+    else if (prolong) EW_ST(false, true);
+    else EW_ST(false, false);
+#undef EW_ST
     return hipGetLastError();
 }
 

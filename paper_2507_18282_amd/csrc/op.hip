@@ -252,7 +252,7 @@ ew_status Op::build_hierarchy() {
     // such level resident in LDS.
     const int nlev = (int)levels.size();
     coarse_level = nlev;
-    if (g.wall) return EW_OK;  // boxes with Neumann walls use the plain kernels on every level
+    if (g.wall) return EW_OK;  // the one-workgroup kernel has the Dirichlet closure only: tiles on every level
     const int64_t cap_pts = desc.mg_coarse_points > 0 ? desc.mg_coarse_points : (int64_t)1 << 40;
     auto padded = [&](const Geo& gq) -> int64_t {
         return (int64_t)(gq.nx + 4) * (gq.ny + 4) * (dim == 3 ? gq.nz + 4 : 1);

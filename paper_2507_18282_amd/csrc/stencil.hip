@@ -11,25 +11,29 @@ namespace ew {
 // --------------------------------------------------------------------------
 // L_h u
 // --------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM>
+template <typename T, int ORDER, int DIM, bool WALLS>
 __global__ __launch_bounds__(256) void k_laplacian(const T* __restrict__ u, T* __restrict__ out, Geo g) {
     int i, j, k;
     if (!tile_coords(g, i, j, k)) return;
     const int64_t c = lin(g, i, j, k);
     const T uc = u[c];
-    out[c] = lap_at<T, ORDER, DIM>(u, c, i, j, k, g, uc);
+    out[c] = lap_at<T, ORDER, DIM, WALLS>(u, c, i, j, k, g, uc);
 }
 
 template <typename T>
 hipError_t launch_laplacian(const T* u, T* out, const Geo& g, int order, hipStream_t s) {
     dim3 grid = tile_grid(g), block(kTileX, kTileY, 1);
+#define EW_LAP(O, D)                                                                   \
+    do {                                                                               \
+        if (g.wall) k_laplacian<T, O, D, true><<<grid, block, 0, s>>>(u, out, g);      \
+        else k_laplacian<T, O, D, false><<<grid, block, 0, s>>>(u, out, g);            \
+    } while (0)
     if (g.dim == 2) {
-        if (order == 2) k_laplacian<T, 2, 2><<<grid, block, 0, s>>>(u, out, g);
-        else k_laplacian<T, 4, 2><<<grid, block, 0, s>>>(u, out, g);
+        if (order == 2) EW_LAP(2, 2); else EW_LAP(4, 2);
     } else {
-        if (order == 2) k_laplacian<T, 2, 3><<<grid, block, 0, s>>>(u, out, g);
-        else k_laplacian<T, 4, 3><<<grid, block, 0, s>>>(u, out, g);
+        if (order == 2) EW_LAP(2, 3); else EW_LAP(4, 3);
     }
+#undef EW_LAP
     return hipGetLastError();
 }
 
@@ -62,14 +66,14 @@ hipError_t launch_wall_scale(const double* in, double* out, const Geo& g, int e,
 // W^n (stencil), W^{n-1} and the accumulator, and writes W^{n+1} over
 // W^{n-1} and the accumulator: 5 values per point.
 // --------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM, bool FIRST>
+template <typename T, int ORDER, int DIM, bool FIRST, bool WALLS>
 __global__ __launch_bounds__(256) void k_leapfrog(const T* __restrict__ wcur, const T* wprev, T* wnext,
                                                   T* __restrict__ acc, Geo g, T dt2, T ccur, T cnext) {
     int i, j, k;
     if (!tile_coords(g, i, j, k)) return;
     const int64_t c = lin(g, i, j, k);
     const T uc = wcur[c];
-    const T lap = lap_at<T, ORDER, DIM>(wcur, c, i, j, k, g, uc);
+    const T lap = lap_at<T, ORDER, DIM, WALLS>(wcur, c, i, j, k, g, uc);
     T wn;
     if (FIRST) {
         wn = uc + (T(0.5) * dt2) * lap;
@@ -86,10 +90,15 @@ hipError_t launch_leapfrog(const T* wcur, const T* wprev, T* wnext, T* acc, cons
                            double ccur, double cnext, int first, hipStream_t s) {
     dim3 grid = tile_grid(g), block(kTileX, kTileY, 1);
     const T d = (T)dt2, c0 = (T)ccur, c1 = (T)cnext;
-#define EW_LF(O, D)                                                                                   \
-    do {                                                                                              \
-        if (first) k_leapfrog<T, O, D, true><<<grid, block, 0, s>>>(wcur, wprev, wnext, acc, g, d, c0, c1); \
-        else k_leapfrog<T, O, D, false><<<grid, block, 0, s>>>(wcur, wprev, wnext, acc, g, d, c0, c1);      \
+#define EW_LF2(O, D, W)                                                                                  \
+    do {                                                                                                 \
+        if (first) k_leapfrog<T, O, D, true, W><<<grid, block, 0, s>>>(wcur, wprev, wnext, acc, g, d, c0, c1); \
+        else k_leapfrog<T, O, D, false, W><<<grid, block, 0, s>>>(wcur, wprev, wnext, acc, g, d, c0, c1);      \
+    } while (0)
+#define EW_LF(O, D)                   \
+    do {                              \
+        if (g.wall) EW_LF2(O, D, true); \
+        else EW_LF2(O, D, false);       \
     } while (0)
     if (g.dim == 2) {
         if (order == 2) EW_LF(2, 2); else EW_LF(4, 2);
@@ -97,6 +106,7 @@ hipError_t launch_leapfrog(const T* wcur, const T* wprev, T* wnext, T* acc, cons
         if (order == 2) EW_LF(2, 3); else EW_LF(4, 3);
     }
 #undef EW_LF
+#undef EW_LF2
     return hipGetLastError();
 }
 

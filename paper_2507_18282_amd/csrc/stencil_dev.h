@@ -73,12 +73,15 @@ __device__ __forceinline__ T axis_coef(double ih2) {
     return ORDER == 2 ? (T)ih2 : (T)(ih2 / 12.0);
 }
 
-template <typename T, int ORDER, int DIM>
+// L_h u at point c = (i, j, k).  WALLS = false compiles the Dirichlet-only
+// closure (g.wall is then ignored and must be 0).
+template <typename T, int ORDER, int DIM, bool WALLS = true>
 __device__ __forceinline__ T lap_at(const T* __restrict__ u, int64_t c, int i, int j, int k, const Geo& g, T uc) {
-    T s = d2_axis<T, ORDER>(u, c, i, g.nx, 1, uc, g.wall & 3) * axis_coef<T, ORDER>(g.ihx2);
-    s += d2_axis<T, ORDER>(u, c, j, g.ny, g.nx, uc, (g.wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
+    const int w = WALLS ? g.wall : 0;
+    T s = d2_axis<T, ORDER>(u, c, i, g.nx, 1, uc, w & 3) * axis_coef<T, ORDER>(g.ihx2);
+    s += d2_axis<T, ORDER>(u, c, j, g.ny, g.nx, uc, (w >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
     if (DIM == 3)
-        s += d2_axis<T, ORDER>(u, c, k, g.nz, (int64_t)g.nx * g.ny, uc, (g.wall >> 4) & 3) *
+        s += d2_axis<T, ORDER>(u, c, k, g.nz, (int64_t)g.nx * g.ny, uc, (w >> 4) & 3) *
              axis_coef<T, ORDER>(g.ihz2);
     return s;
 }
@@ -99,12 +102,20 @@ __device__ __forceinline__ T ldiag_axis(int i, int n, int w = 0) {
     return d;
 }
 
+// Diagonal of M = I - a L_h at (i, j, k) for the wall bits `wall` (Geo::wall
+// layout); kernels compiled for Dirichlet-only boxes pass a literal 0 so that
+// the Neumann cases fold away.
 template <typename T, int ORDER, int DIM>
-__device__ __forceinline__ T mdiag_at(int i, int j, int k, const Geo& g, T a) {
-    T l = ldiag_axis<T, ORDER>(i, g.nx, g.wall & 3) * axis_coef<T, ORDER>(g.ihx2) +
-          ldiag_axis<T, ORDER>(j, g.ny, (g.wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
-    if (DIM == 3) l += ldiag_axis<T, ORDER>(k, g.nz, (g.wall >> 4) & 3) * axis_coef<T, ORDER>(g.ihz2);
+__device__ __forceinline__ T mdiag_w(int i, int j, int k, const Geo& g, T a, int wall) {
+    T l = ldiag_axis<T, ORDER>(i, g.nx, wall & 3) * axis_coef<T, ORDER>(g.ihx2) +
+          ldiag_axis<T, ORDER>(j, g.ny, (wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
+    if (DIM == 3) l += ldiag_axis<T, ORDER>(k, g.nz, (wall >> 4) & 3) * axis_coef<T, ORDER>(g.ihz2);
     return T(1) - a * l;
+}
+
+template <typename T, int ORDER, int DIM, bool WALLS = true>
+__device__ __forceinline__ T mdiag_at(int i, int j, int k, const Geo& g, T a) {
+    return mdiag_w<T, ORDER, DIM>(i, j, k, g, a, WALLS ? g.wall : 0);
 }
 
 // Block-wide sum for 256 threads (4 wavefronts of 64): wavefront shuffles then

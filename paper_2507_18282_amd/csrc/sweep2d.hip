@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
         // the point: at a Dirichlet wall point, one point inside a Neumann wall
         const bool edge = ORDER == 4 && (WALLS ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
                                                : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
-        return edge ? uc + r / mdiag_at<T, ORDER, 2>(gi, gj, 0, g, a) : uc + r * inv_diag;
+        return edge ? uc + r / mdiag_at<T, ORDER, 2, WALLS>(gi, gj, 0, g, a) : uc + r * inv_diag;
     };
 
     const int rowsel = tid >> 5;  // 8 rows per pass, 32 lanes per row
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
         const T r = bval - (uc - a * (dx * cxc + dy * cyc));
         const bool edge = ORDER == 4 && (WALLS ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
                                                : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
-        return edge ? uc + r / mdiag_at<T, ORDER, 2>(gi, gj, 0, g, a) : uc + r * inv_diag;
+        return edge ? uc + r / mdiag_at<T, ORDER, 2, WALLS>(gi, gj, 0, g, a) : uc + r * inv_diag;
     };
     // one half-sweep of colour `colour` on the tile plus K layers: new values to
     // registers (same-colour neighbours must be read old), then into LDS
