@@ -71,9 +71,10 @@ typedef struct ew_op_s* ew_op;
  * self-adjoint in the inner product weighted by 1/2 per Neumann wall a point
  * lies on; ew_eigs works in those weighted coordinates and returns the grid
  * functions.  Multigrid coarsening keeps the wall points (n = 2 n_c + 1,
- * 2 n_c or 2 n_c - 1 for zero, one or two Neumann walls of an axis) and runs
- * the plain kernels on boxes with Neumann walls; the implicit guesses PROJ and
- * CNN are not available there (EW_ERR_UNSUPPORTED). */
+ * 2 n_c or 2 n_c - 1 for zero, one or two Neumann walls of an axis); boxes
+ * with Neumann walls run the tiled multigrid kernels on every level (not the
+ * single-workgroup coarse kernel), and the implicit guesses PROJ and CNN are
+ * not available there (EW_ERR_UNSUPPORTED). */
 enum { EW_WALL_DIRICHLET = 0, EW_WALL_NEUMANN = 1 };
 typedef struct {
     int dim;
