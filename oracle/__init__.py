@@ -23,6 +23,9 @@ double precision, written so that it can be checked against the paper by eye:
 * ``walls``     -- boxes with Neumann walls: the Laplacian with even-reflection
   ghosts, its closed-form eigenpairs and symmetrising weights, and the
   explicit wave-solve.
+* ``mapped``    -- a single curvilinear grid (mapping method): the order-2
+  conservative Laplacian with metric terms of the grid coordinates, its
+  J-weighted symmetry, Gershgorin time plan and explicit wave-solve.
 
 Readings of the paper where it is silent (boundary closure for order 4,
 trapezoid weights, CFL definition, ...) are stated in each function.

@@ -166,7 +166,7 @@ class TimePlan:
 
 def time_plan(h: Sequence[float], order: int, omega: float, ts: str, cfl: float = 0.5,
               n_its: int = 10, n_p: int = 1, adjust_omega: bool = False,
-              filter_const: str = "alpha_d") -> TimePlan:
+              filter_const: str = "alpha_d", rho: float = None) -> TimePlan:
     """Time step, step count and trapezoidal filter weights of one wave-solve.
 
     * T_f = N_p * 2 pi / omega (Sec. "Continuous algorithm").
@@ -175,7 +175,7 @@ def time_plan(h: Sequence[float], order: int, omega: float, ts: str, cfl: float 
       leapfrog scheme is stable for dt * sqrt(rho) <= 2 with rho the spectral
       radius bound of -L_h, so dt_max = 2 / sqrt(rho),
       N_t = ceil(T_f / (cfl * dt_max)) and dt = T_f / N_t, which lands on T_f
-      exactly.
+      exactly.  ``rho`` replaces the box bound (a mapped grid passes its own).
     * Trapezoid weights sigma_0 = sigma_{N_t} = dt/2, sigma_n = dt otherwise;
       c_n = (2/T_f) sigma_n (cos(omega t^n) - alpha_d/2) (eq. filterQuadrature),
       or with 1/4 in place of alpha_d/2 when ``filter_const == "quarter"``
@@ -188,7 +188,7 @@ def time_plan(h: Sequence[float], order: int, omega: float, ts: str, cfl: float 
     if ts == "implicit":
         n_t = n_p * n_its
     elif ts == "explicit":
-        dt_max = 2.0 / math.sqrt(spectral_radius_bound(h, order))
+        dt_max = 2.0 / math.sqrt(spectral_radius_bound(h, order) if rho is None else rho)
         n_t = int(math.ceil(t_final / (cfl * dt_max)))
     else:
         raise ValueError("ts must be 'explicit' or 'implicit'")

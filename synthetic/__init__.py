@@ -154,3 +154,52 @@ def batch_problems(count: int = 96, seed: int = 4, n_lo: int = 65, n_hi: int = 1
 def cnn_input_planes(seed: int, count: int) -> np.ndarray:
     """Uniform[-1,1] values for tiny network test inputs (brute-force checks)."""
     return uniform_pm1(seed, count)
+
+
+# ---------------------------------------------------------------------------
+# Mapped grids: coordinates x = G(r) of a single curvilinear grid, sampled at
+# r_i = (i + 1) / (n_1 + 1), s_j = (j + 1) / (n_2 + 1) for i in [-2, n_1 + 1],
+# j in [-2, n_2 + 1]: the active points are i in [0, n_1), the walls i = -1
+# and i = n_1, plus one layer beyond each wall.  Returned as an array of shape
+# (2, n_2 + 4, n_1 + 4): [0] holds x, [1] holds y, entry [., j + 2, i + 2].
+# Pure geometry (the mapping evaluated at the parameter points); the
+# discretisation lives in the oracle and in the library.
+# ---------------------------------------------------------------------------
+def _param_points(n: int) -> np.ndarray:
+    return (np.arange(-2, n + 2, dtype=np.float64) + 1.0) / (n + 1)
+
+
+def mapped_coords(kind: str, n1: int, n2: int, **p) -> np.ndarray:
+    """Coordinates of one of the synthetic mappings of the unit square:
+
+    * ``affine``: x = R(phi) (len1 r, len2 s) + shear * len2 s e_x (a
+      rotated rectangle, or a parallelogram with ``shear`` != 0);
+    * ``annulus``: sector of an annulus, radius a + (b - a) r, angle theta0 s;
+    * ``skew``: the smooth non-orthogonal map x = len1 (r + eps r sin(pi s)),
+      y = len2 (s + eps sin(pi r)).
+    """
+    r = _param_points(n1)[None, :]
+    s = _param_points(n2)[:, None]
+    if kind == "affine":
+        l1, l2 = p.get("len1", 1.0), p.get("len2", 1.0)
+        phi, shear = p.get("phi", 0.0), p.get("shear", 0.0)
+        u = l1 * r + shear * l2 * s
+        v = l2 * s + 0.0 * r
+        x = math.cos(phi) * u - math.sin(phi) * v
+        y = math.sin(phi) * u + math.cos(phi) * v
+    elif kind == "annulus":
+        a, b, th0 = p.get("a", 0.5), p.get("b", 1.0), p.get("theta0", 0.5 * math.pi)
+        rho = a + (b - a) * r
+        th = th0 * s
+        x = rho * np.cos(th)
+        y = rho * np.sin(th)
+    elif kind == "skew":
+        l1, l2, eps = p.get("len1", 1.0), p.get("len2", 1.0), p.get("eps", 0.15)
+        x = l1 * (r + eps * r * np.sin(math.pi * s))
+        y = l2 * (s + eps * np.sin(math.pi * r))
+    else:
+        raise ValueError(f"unknown mapping {kind!r}")
+    out = np.empty((2, n2 + 4, n1 + 4))
+    out[0] = np.broadcast_to(x, (n2 + 4, n1 + 4))
+    out[1] = np.broadcast_to(y, (n2 + 4, n1 + 4))
+    return out
