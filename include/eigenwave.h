@@ -189,6 +189,37 @@ typedef struct {
  * N_t are computed once here in FP64.  Errors: EW_ERR_INVALID_ARG for any
  * violated range above, EW_ERR_OOM, EW_ERR_HIP. */
 ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* hip_stream, ew_op* out);
+
+/* Create an explicit operator on a single curvilinear grid (the mapping
+ * method of Sec. "Discrete approximations": a smooth invertible map x = G(r)
+ * of the unit square, the equations written in r by the chain rule).  The
+ * paper prints no discrete form; this library uses the order-2 conservative
+ * one,
+ *   J L_h u = D+r(A11 D-r u) + D+s(A22 D-s u) + D0r(B D0s u) + D0s(B D0r u),
+ * J = x_r y_s - x_s y_r, J a^11 = (x_s^2 + y_s^2)/J, J a^22 = (x_r^2 + y_r^2)/J,
+ * B = J a^12 = -(x_r x_s + y_r y_s)/J, A11 (A22) at a half point the mean of
+ * J a^11 (J a^22) at its two nodes, metric derivatives by centred
+ * differences of the coordinates, Dirichlet walls.  L_h is self-adjoint in
+ * the J-weighted inner product; ew_eigs works in y = J^{1/2} u and returns
+ * grid functions.  The explicit step uses dt_max = 2 / sqrt(rho) with rho the
+ * Gershgorin bound max (1/J) sum |weights of J L_h| (ew_op_mapped_rho).
+ *   grid      dim 2, order 2, Dirichlet walls; n[0] x n[1] active points at
+ *             r = (i + 1)/(n[0] + 1), s = (j + 1)/(n[1] + 1); len is unused.
+ *   desc      ts EW_TS_EXPLICIT, precision EW_PREC_FP64.
+ *   xy_host   host array of 2 (n[0] + 4)(n[1] + 4) doubles: x, then y, of
+ *             nodes i in [-2, n[0] + 1], j in [-2, n[1] + 1] (the walls are
+ *             i = -1 and i = n[0], plus one layer beyond each) at
+ *             (i + 2) + (n[0] + 4)(j + 2).  Read during the call only.
+ * Errors: EW_ERR_INVALID_ARG (ranges of ew_op_create, null or non-finite
+ * coordinates, a Jacobian that is not positive at some node, walls
+ * included), EW_ERR_UNSUPPORTED (3D, order 4, Neumann walls, implicit or
+ * mixed precision), EW_ERR_OOM, EW_ERR_HIP.  The implicit, multigrid,
+ * network and batched entry points do not apply to such an operator. */
+ew_status ew_op_create_mapped(const ew_grid_desc* grid, const ew_op_desc* desc, const double* xy_host,
+                              void* hip_stream, ew_op* out);
+/* The Gershgorin bound rho of a mapped operator (EW_ERR_INVALID_ARG for any
+ * other operator). */
+ew_status ew_op_mapped_rho(ew_op op, double* rho_host);
 void ew_op_destroy(ew_op op);
 ew_status ew_op_get_info(ew_op op, ew_op_info* out);
 ew_status ew_op_get_stats(ew_op op, ew_op_stats* out);

@@ -71,14 +71,17 @@ def _set_walls(g, walls, dim: int) -> None:
 
 class Operator:
     """The WaveHoltz operator S on one box (see ew_op_create); walls default to
-    Dirichlet, ``walls=(("N", "D"), ("D", "D"))`` makes the low x wall Neumann."""
+    Dirichlet, ``walls=(("N", "D"), ("D", "D"))`` makes the low x wall Neumann.
+    ``coords`` (an array of shape (2, n[1] + 4, n[0] + 4): x and y of the
+    nodes i in [-2, n[0] + 1], j in [-2, n[1] + 1]) makes it an explicit
+    operator on that curvilinear grid (see ew_op_create_mapped)."""
 
     def __init__(self, n: Sequence[int], length: Sequence[float], order: int, omega: float, ts: str,
                  cfl: float = 0.5, n_its: int = 10, n_p: int = 1, adjust_omega: bool = False,
                  filter_const: str = "alpha_d", precision: str = "fp64", mg_tol: float = 1e-10,
                  mg_nu1: int = 2, mg_nu2: int = 1, mg_max_cycles: int = 100, mg_coarse_sweeps: int = 8,
                  mg_coarse_points: int = 0, predictor: str = "zero", proj_window: int = 0,
-                 mg_max_levels: int = 0, walls=None, stream=None):
+                 mg_max_levels: int = 0, walls=None, coords=None, stream=None):
         lib = load()
         self._lib = lib
         g = _lib.GridDesc()
@@ -108,8 +111,18 @@ class Operator:
         d.mg_max_levels = -1 if mg_max_levels == "auto" else int(mg_max_levels)
         self._stream = stream
         self._h = ctypes.c_void_p()
-        check(lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)),
-                               ctypes.byref(self._h)))
+        if coords is None:
+            check(lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)),
+                                   ctypes.byref(self._h)))
+        else:
+            import numpy as np
+            xy = np.ascontiguousarray(coords, dtype=np.float64)
+            if len(n) != 2 or xy.shape != (2, int(n[1]) + 4, int(n[0]) + 4):
+                raise ValueError("coords must have shape (2, n[1] + 4, n[0] + 4)")
+            check(lib.ew_op_create_mapped(ctypes.byref(g), ctypes.byref(d),
+                                          xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(self._h)))
+        self.mapped = coords is not None
         self.n = tuple(int(x) for x in n)
         info = _lib.OpInfo()
         check(lib.ew_op_get_info(self._h, ctypes.byref(info)))
@@ -135,6 +148,12 @@ class Operator:
     def _new(self):
         torch = _torch()
         return torch.empty(self.n_active, dtype=torch.float64, device="cuda")
+
+    def mapped_rho(self) -> float:
+        """Gershgorin bound on the spectrum of -L_h of a mapped operator."""
+        r = ctypes.c_double()
+        check(self._lib.ew_op_mapped_rho(self._h, ctypes.byref(r)))
+        return float(r.value)
 
     def stats(self) -> dict:
         s = _lib.OpStats()

@@ -85,6 +85,9 @@ class CnnTrainStats(ctypes.Structure):
 # name -> (restype, argtypes); every symbol include/eigenwave.h declares.
 SIGNATURES = {
     "ew_op_create": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
+    "ew_op_create_mapped": (c_int, [POINTER(GridDesc), POINTER(OpDesc), POINTER(c_double), c_void_p,
+                                    POINTER(c_void_p)]),
+    "ew_op_mapped_rho": (c_int, [c_void_p, POINTER(c_double)]),
     "ew_op_destroy": (None, [c_void_p]),
     "ew_op_get_info": (c_int, [c_void_p, POINTER(OpInfo)]),
     "ew_op_get_stats": (c_int, [c_void_p, POINTER(OpStats)]),

@@ -108,24 +108,38 @@ struct RunResult {
 };
 
 // The eigensolver's coordinates: y = W^{1/2} u with W the Neumann-wall
-// weights, in which S and L_h are symmetric (identity without Neumann walls).
+// weights, or J on a mapped grid, in which S and L_h are symmetric (identity
+// when there are neither).
+static bool weighted(const Workspace& ws) { return ws.g.wall != 0 || ws.wsq != nullptr; }
+
+// out = W^{e/2} in (in and out may alias)
+static hipError_t weight_scale(const Workspace& ws, const double* in, double* out, int e) {
+    if (ws.wsq) return launch_pointwise_mul(in, e > 0 ? ws.wsq : ws.wisq, out, ws.N, ws.stream);
+    return launch_wall_scale(in, out, ws.g, e, ws.stream);
+}
+
+static hipError_t plain_laplacian(const Workspace& ws, const double* in, double* out) {
+    if (ws.op && ws.op->mapped) return launch_laplacian_mapped(in, out, ws.g, ws.op->mc, ws.stream);
+    return launch_laplacian<double>(in, out, ws.g, ws.order, ws.stream);
+}
+
 static ew_status apply_S_sym(Workspace& ws, const double* in, double* out) {
     Op* op = ws.op;
-    if (!ws.g.wall) return op->apply_filter(in, out);
-    EW_HIP_TRY(launch_wall_scale(in, ws.wtmp, ws.g, -1, ws.stream));
+    if (!weighted(ws)) return op->apply_filter(in, out);
+    EW_HIP_TRY(weight_scale(ws, in, ws.wtmp, -1));
     EW_TRY(op->apply_filter(ws.wtmp, out));
-    EW_HIP_TRY(launch_wall_scale(out, out, ws.g, 1, ws.stream));
+    EW_HIP_TRY(weight_scale(ws, out, out, 1));
     return EW_OK;
 }
 
 ew_status apply_L_sym(Workspace& ws, const double* in, double* out) {
-    if (!ws.g.wall) {
-        EW_HIP_TRY(launch_laplacian<double>(in, out, ws.g, ws.order, ws.stream));
+    if (!weighted(ws)) {
+        EW_HIP_TRY(plain_laplacian(ws, in, out));
         return EW_OK;
     }
-    EW_HIP_TRY(launch_wall_scale(in, ws.wtmp, ws.g, -1, ws.stream));
-    EW_HIP_TRY(launch_laplacian<double>(ws.wtmp, out, ws.g, ws.order, ws.stream));
-    EW_HIP_TRY(launch_wall_scale(out, out, ws.g, 1, ws.stream));
+    EW_HIP_TRY(weight_scale(ws, in, ws.wtmp, -1));
+    EW_HIP_TRY(plain_laplacian(ws, ws.wtmp, out));
+    EW_HIP_TRY(weight_scale(ws, out, out, 1));
     return EW_OK;
 }
 
@@ -368,12 +382,12 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
         beta_host[r] = beta[j];
         res_host[r] = res[j];
         max_res = std::max(max_res, res[j]);
-        if (Y_dev && !ws.g.wall) {
+        if (Y_dev && !weighted(ws)) {
             EW_HIP_TRY(launch_scale_copy<double>(Y_dev + (int64_t)r * N, ws.col(ws.Z, j), N, 1.0 / znorm[j], ws.stream));
         } else if (Y_dev) {
             // back to the grid function u = W^{-1/2} z, unit 2-norm
             double* y = Y_dev + (int64_t)r * N;
-            EW_HIP_TRY(launch_wall_scale(ws.col(ws.Z, j), y, ws.g, -1, ws.stream));
+            EW_HIP_TRY(weight_scale(ws, ws.col(ws.Z, j), y, -1));
             EW_HIP_TRY(launch_dot_partial(y, y, N, ws.P, ws.stream));
             EW_HIP_TRY(launch_normalize_from_partial(y, y, N, ws.P, nullptr, ws.stream));
         }
@@ -411,6 +425,10 @@ extern "C" ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, doub
     ws.stream = op->stream;
     ws.g = op->g;
     ws.order = op->order;
+    if (op->mapped) {
+        ws.wsq = op->mc.sq;
+        ws.wisq = op->mc.isq;
+    }
     EW_TRY(ws.setup(N, m, k));
 
     const ew_op_stats s0 = op->stats;

@@ -34,7 +34,9 @@ struct Workspace {
     double* q_dev = nullptr;   // small matrices for basis rotations
     double* gram_dev = nullptr;
     double* h_host = nullptr;
-    double* wtmp = nullptr;    // one vector for the weighted coordinates (Neumann walls)
+    double* wtmp = nullptr;    // one vector for the weighted coordinates (Neumann walls, mapped grids)
+    const double* wsq = nullptr;   // mapped grid: sqrt(J) and 1/sqrt(J) (the weights are J)
+    const double* wisq = nullptr;
     int nu_max = 0;            // columns one orthogonalisation may involve
     std::vector<void*> owned;
     ~Workspace() {
@@ -66,7 +68,7 @@ struct Workspace {
         EW_TRY(alloc(&h_dev, hlen));
         EW_TRY(alloc(&q_dev, (size_t)qdim * qdim));
         EW_TRY(alloc(&gram_dev, (size_t)kGramBlocks * 32 * 32));
-        if (g.wall) EW_TRY(alloc(&wtmp, (size_t)N));
+        if (g.wall || wsq) EW_TRY(alloc(&wtmp, (size_t)N));
         EW_HIP_TRY(hipHostMalloc((void**)&h_host, hlen * sizeof(double), hipHostMallocDefault));
         return EW_OK;
     }
@@ -92,7 +94,8 @@ constexpr int kMgsMaxCols = 64;
 ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, const double* u2, int n2,
                          std::vector<double>& coeff);
 // out = W^{1/2} L_h W^{-1/2} in: the Laplacian in the eigensolver's
-// coordinates (plain L_h without Neumann walls).  in and out may not alias.
+// coordinates, W the Neumann-wall weights or J on a mapped grid (plain L_h
+// when there are none).  in and out may not alias.
 ew_status apply_L_sym(Workspace& ws, const double* in, double* out);
 // Y[:, 0:ncols] = X[:, 0:nx] Qm[0:nx, 0:ncols].  Host-blocking.
 ew_status rotate(Workspace& ws, const double* X, int nx, const Mat& Qm, int ncols, double* Y);

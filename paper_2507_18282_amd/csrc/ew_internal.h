@@ -142,4 +142,24 @@ hipError_t launch_eig_residual(const double* lz, const double* z, double mu, int
                                hipStream_t s);
 hipError_t launch_splitmix_uniform(double* x, int64_t n, uint64_t seed, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Single curvilinear grid (mapped.hip): device arrays of the order-2
+// conservative operator, built once from the grid coordinates.  nx x ny
+// active points, x fastest; half point i - 1/2 lies between nodes i - 1 and i.
+// ---------------------------------------------------------------------------
+struct MapCoef {
+    const double* cw;   // (nx + 1) x ny: A11 / dr^2 at half point i - 1/2, index i + (nx + 1) j
+    const double* cs;   // nx x (ny + 1): A22 / ds^2 at half point j - 1/2, index i + nx j
+    const double* cb;   // nx x ny: J a^12 / (4 dr ds) at the node
+    const double* ij;   // nx x ny: 1 / J
+    const double* sq;   // nx x ny: sqrt(J)
+    const double* isq;  // nx x ny: 1 / sqrt(J)
+};
+hipError_t launch_laplacian_mapped(const double* u, double* out, const Geo& g, const MapCoef& m, hipStream_t s);
+// The explicit leapfrog step of launch_leapfrog with the mapped operator.
+hipError_t launch_leapfrog_mapped(const double* wcur, const double* wprev, double* wnext, double* acc, const Geo& g,
+                                  const MapCoef& m, double dt2, double ccur, double cnext, int first, hipStream_t s);
+// out = in * f elementwise (in and out may alias).
+hipError_t launch_pointwise_mul(const double* in, const double* f, double* out, int64_t n, hipStream_t s);
+
 }  // namespace ew

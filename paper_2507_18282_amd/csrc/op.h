@@ -42,7 +42,10 @@ struct TimePlan {
     int n_t = 0;
     std::vector<double> c;
 };
-void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp);
+// rho_override > 0 replaces the box bound sum_d c / h_d^2 on the spectrum of
+// -L_h in the explicit time step (a mapped grid supplies its own).
+void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp,
+                    double rho_override = 0.0);
 ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d);
 
 // Whole explicit wave-solve of a small 2D grid in one workgroup (wave_small.hip).
@@ -79,6 +82,10 @@ struct Op {
     double omega_used = 0, t_final = 0, dt = 0, alpha_d = 0, a = 0;
     int n_t = 0;
     std::vector<double> c;
+    // single curvilinear grid (explicit FP64 only): coefficients of the mapped operator
+    bool mapped = false;
+    MapCoef mc{};
+    double map_rho = 0.0;      // Gershgorin bound on the spectrum of -L_h
     // workspace
     double* wA = nullptr;
     double* wB = nullptr;

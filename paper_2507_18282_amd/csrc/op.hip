@@ -38,7 +38,7 @@ Geo make_geo(int dim, const int64_t* n, const double* h, int wall) {
 // trapezoid weights sigma_0 = sigma_{N_t} = dt/2, dt otherwise, and
 // shift = alpha_d/2 = tan(omega dt/2) / tan(omega dt) / 2 or 1/4.
 // ---------------------------------------------------------------------------
-void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp) {
+void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp, double rho_override) {
     double om = d.omega;
     if (d.adjust_omega) {
         const double s = std::sin(M_PI / d.n_its);
@@ -53,6 +53,7 @@ void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, Ti
         const double c = order == 2 ? 4.0 : 16.0 / 3.0;
         double rho = 0.0;
         for (int k = 0; k < dim; ++k) rho += c / (h[k] * h[k]);
+        if (rho_override > 0.0) rho = rho_override;
         const double dt_max = 2.0 / std::sqrt(rho);
         tp.n_t = (int)std::ceil(tp.t_final / (d.cfl * dt_max));
     }
@@ -381,7 +382,8 @@ extern "C" ew_status ew_op_reset_stats(ew_op op) {
 extern "C" ew_status ew_op_apply_laplacian(ew_op op, const double* v_dev, double* out_dev) {
     if (!op || !v_dev || !out_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
     if (v_dev == out_dev) return fail(EW_ERR_INVALID_ARG, "v and out may not alias");
-    EW_HIP_TRY(launch_laplacian<double>(v_dev, out_dev, op->g, op->order, op->stream));
+    if (op->mapped) EW_HIP_TRY(launch_laplacian_mapped(v_dev, out_dev, op->g, op->mc, op->stream));
+    else EW_HIP_TRY(launch_laplacian<double>(v_dev, out_dev, op->g, op->order, op->stream));
     op->stats.laplacian_applies++;
     return EW_OK;
 }

@@ -239,7 +239,21 @@ ew_status Op::implicit_solve(const double* b, double bscale, double* x, const do
 
 ew_status Op::apply_filter(const double* v, double* out) {
     const double dt2 = dt * dt;
-    if (!implicit && (mixed ? wave_small_fits<float>(g) : wave_small_fits<double>(g))) {
+    if (mapped) {
+        {
+            ProfScope ps(this, EW_K_LEAPFROG, 0, 56.0 * (double)N);
+            EW_HIP_TRY(launch_leapfrog_mapped(v, nullptr, wA, out, g, mc, dt2, c[0], c[1], 1, stream));
+        }
+        const double* prev = v;
+        double* cur = wA;
+        for (int k = 1; k < n_t; ++k) {
+            double* next = (prev == v) ? wB : const_cast<double*>(prev);
+            ProfScope ps(this, EW_K_LEAPFROG, 0, 72.0 * (double)N);
+            EW_HIP_TRY(launch_leapfrog_mapped(cur, prev, next, out, g, mc, dt2, 0.0, c[k + 1], 0, stream));
+            prev = cur;
+            cur = next;
+        }
+    } else if (!implicit && (mixed ? wave_small_fits<float>(g) : wave_small_fits<double>(g))) {
         ProfScope ps(this, EW_K_LEAPFROG, 0, 16.0 * (double)N);
         EW_HIP_TRY(mixed ? launch_wave_small<float>(v, out, g, order, dt2, c_dev, n_t, stream)
                          : launch_wave_small<double>(v, out, g, order, dt2, c_dev, n_t, stream));

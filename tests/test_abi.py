@@ -118,3 +118,50 @@ def test_neumann_walls_rejected_where_not_implemented():
     assert b"symmetric" in lib.ew_last_error()
     assert create(15, "implicit", "cnn") == -7
     assert create(2, "explicit") == -1  # EW_ERR_INVALID_ARG
+
+
+def test_mapped_grid_validation():
+    """ew_op_create_mapped validates the combination and the coordinates on
+    the host before any device work: 3D, order 4, Neumann walls, implicit and
+    mixed precision are EW_ERR_UNSUPPORTED; null coordinates, non-finite
+    coordinates and a map whose Jacobian is not positive at some node
+    (walls included) are EW_ERR_INVALID_ARG."""
+    import ctypes
+
+    import numpy as np
+
+    import synthetic
+    from paper_2507_18282_amd import _lib
+    lib = _lib.load()
+    n = (12, 9)
+    good = synthetic.mapped_coords("skew", *n, eps=0.15)
+
+    def create(xy, order=2, ts="explicit", precision="fp64", neumann=False, dim=2):
+        g = _lib.GridDesc()
+        g.dim = dim
+        g.n[0], g.n[1], g.n[2] = n[0], n[1], 5
+        g.len[0], g.len[1], g.len[2] = 1.0, 1.0, 1.0
+        g.order = order
+        if neumann:
+            g.walls[1][0] = _lib.WALL_NEUMANN
+        d = _lib.OpDesc()
+        d.omega, d.ts, d.cfl, d.n_its, d.n_p = 10.0, _lib.TS[ts], 0.5, 10, 1
+        d.precision = _lib.PRECISION[precision]
+        d.mg_tol, d.mg_nu1, d.mg_nu2, d.mg_max_cycles, d.mg_coarse_sweeps = 1e-10, 2, 1, 100, 8
+        h = ctypes.c_void_p()
+        p = None if xy is None else np.ascontiguousarray(xy).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return lib.ew_op_create_mapped(ctypes.byref(g), ctypes.byref(d), p, None, ctypes.byref(h))
+
+    assert create(good, order=4) == -7
+    assert create(good, ts="implicit") == -7
+    assert create(good, precision="mixed") == -7
+    assert create(good, neumann=True) == -7
+    assert create(good, dim=3) == -7
+    assert create(None) == -1
+    flipped = good.copy()
+    flipped[0] = -flipped[0]  # mirror image: x_r < 0, so J < 0
+    assert create(flipped) == -1
+    assert b"Jacobian" in lib.ew_last_error()
+    bad = good.copy()
+    bad[1, 3, 4] = np.nan
+    assert create(bad) == -1

@@ -1,0 +1,134 @@
+"""Single curvilinear grids (mapping method) on the GPU against the oracle
+(oracle/mapped.py), element by element through the C ABI.
+
+Tolerances: L_h v to 1e-12 relative to max |L_h v| (the library folds
+1/dr^2, 1/ds^2 and 1/(4 dr ds) into its coefficients, the oracle divides
+after summing: rounding order only); one explicit wave-solve to 1e-10 (a few
+hundred FP64 steps of the same recurrence); S phi = beta phi to 1e-12 for
+discrete eigenvectors.  Eigensolves: every returned mu within 1e-9 relative
+of the dense spectrum, the wanted band present with multiplicity, eig-res <=
+1e-8, and the returned grid functions satisfy L_h u = -mu u.  At 2047^2 the
+Laplacian is compared everywhere, and S is checked for self-adjointness in
+the J-weighted product, which holds at any size.
+"""
+import numpy as np
+import pytest
+from scipy import linalg
+
+import synthetic
+from oracle import discrete as D
+from oracle import mapped as Mp
+from tests.gpu_helpers import rel_err, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (kind, n, params, omega, cfl)
+    ("skew", (70, 45), dict(eps=0.2, len1=1.1), 12.0, 0.5),                      # ragged tiles both ways
+    ("annulus", (130, 67), dict(a=0.5, b=1.0, theta0=1.2), 15.0, 0.5),
+    ("affine", (64, 33), dict(len1=1.0, len2=0.6, phi=0.5, shear=0.3), 10.0, 0.7),  # parallelogram
+    ("skew", (5, 3), dict(eps=0.1), 6.0, 0.5),                                    # smaller than one tile
+    ("annulus", (1, 4), dict(a=0.3, b=1.0, theta0=2.0), 4.0, 0.5),                # one column
+]
+
+
+def _op(kind, n, params, omega, cfl):
+    from paper_2507_18282_amd import Operator
+    xy = synthetic.mapped_coords(kind, *n, **params)
+    return xy, Operator(n=n, length=(1.0, 1.0), order=2, omega=omega, ts="explicit", cfl=cfl, coords=xy)
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[1]}")
+def test_laplacian_and_filter_match_oracle(case):
+    kind, n, params, omega, cfl = case
+    say("mapped create", kind, n)
+    xy, op = _op(*case)
+    plan = Mp.time_plan(xy, omega, cfl=cfl)
+    rho = Mp.spectral_radius_bound(xy)
+    assert abs(op.mapped_rho() - rho) <= 1e-13 * rho
+    assert op.n_t == plan.n_t and abs(op.dt - plan.dt) <= 1e-15 * plan.dt
+    N = n[0] * n[1]
+    v = synthetic.uniform_pm1(51, N)
+    say("mapped laplacian", kind, n)
+    got = to_host(op.apply_laplacian(to_dev(v)))
+    want = Mp.apply_laplacian(v.reshape(n[::-1]), xy).ravel()
+    assert rel_err(got, want) < 1e-12
+    say("mapped filter", kind, n, plan.n_t)
+    got = to_host(op.apply_filter(to_dev(v)))
+    want = Mp.apply_filter_explicit(v.reshape(n[::-1]), xy, plan).ravel()
+    assert rel_err(got, want) < 1e-10
+
+
+def test_filter_on_discrete_eigenvectors():
+    case = ("skew", (20, 16), dict(eps=0.2), 9.0, 0.5)
+    xy, op = _op(*case)
+    plan = Mp.time_plan(xy, 9.0, cfl=0.5)
+    A = Mp.laplacian_matrix(xy)
+    Wt = Mp.weights(xy).ravel()
+    mu, V = linalg.eigh(-(Wt[:, None] * A), np.diag(Wt))
+    for k in (0, 5, 60, len(mu) - 1):
+        phi = V[:, k] / np.max(np.abs(V[:, k]))
+        beta = float(D.beta_corrected(mu[k], plan))
+        got = to_host(op.apply_filter(to_dev(phi)))
+        assert np.max(np.abs(got - beta * phi)) < 1e-12, k
+
+
+EIG_CASES = [
+    # (kind, n, params, omega, cfl, k, m)
+    ("annulus", (48, 40), dict(a=0.5, b=1.0, theta0=0.5 * np.pi), 20.0, 0.5, 6, 16),
+    ("skew", (44, 36), dict(eps=0.2, len2=0.9), 14.0, 0.5, 6, 16),
+]
+
+
+@pytest.mark.parametrize("case", EIG_CASES, ids=lambda c: f"{c[0]}-{c[1]}")
+def test_eigs_match_dense_spectrum(case):
+    kind, n, params, omega, cfl, k, m = case
+    xy, op = _op(kind, n, params, omega, cfl)
+    plan = Mp.time_plan(xy, omega, cfl=cfl)
+    A = Mp.laplacian_matrix(xy)
+    Wt = Mp.weights(xy).ravel()
+    mu_all = linalg.eigh(-(Wt[:, None] * A), np.diag(Wt), eigvals_only=True)
+    beta_all = D.beta_corrected(mu_all, plan)
+    beta_k = np.sort(np.abs(beta_all))[::-1][k - 1]
+    say("mapped eigs", kind, n)
+    r = op.eigs(k, m, seed=4)
+    mu = np.array(r.mu)
+    assert r.n_conv >= k
+    for x in mu:
+        assert np.min(np.abs(mu_all - x)) / x < 1e-9
+    band = np.sort(mu_all[np.abs(beta_all) >= beta_k * (1 - 1e-10)])
+    for x in band:
+        want = np.sum(np.abs(band - x) <= 1e-9 * x)
+        assert np.sum(np.abs(mu - x) <= 1e-9 * x) >= want, (x, mu)
+    assert max(r.res) <= 1e-8
+    Y = r.Y.cpu().numpy()
+    for c in range(Y.shape[1]):
+        u = Y[:, c].reshape(n[::-1])
+        assert abs(np.linalg.norm(u) - 1.0) < 1e-12
+        res = Mp.apply_laplacian(u, xy) + mu[c] * u
+        assert np.linalg.norm(res) / mu[c] < 1e-7
+
+
+def test_full_size_laplacian_and_weighted_symmetry():
+    import torch
+    n = (2047, 2047)
+    xy = synthetic.mapped_coords("skew", *n, eps=0.15)
+    from paper_2507_18282_amd import Operator
+    say("mapped full size create", n)
+    op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="explicit", cfl=0.9, coords=xy)
+    N = n[0] * n[1]
+    v = synthetic.uniform_pm1(61, N)
+    say("mapped full size laplacian", n)
+    got = to_host(op.apply_laplacian(to_dev(v)))
+    want = Mp.apply_laplacian(v.reshape(n[::-1]), xy).ravel()
+    assert rel_err(got, want) < 1e-12
+    # <S u, w>_J = <u, S w>_J at any size (S is a polynomial in L_h, self-adjoint in it)
+    say("mapped full size symmetry", n, op.n_t)
+    J = to_dev(Mp.weights(xy).ravel())
+    u = to_dev(synthetic.uniform_pm1(62, N))
+    w = to_dev(synthetic.uniform_pm1(63, N))
+    Su, Sw = op.apply_filter(u), op.apply_filter(w)
+    a = float(torch.sum(J * Su * w))
+    b = float(torch.sum(J * u * Sw))
+    scale = float(torch.sqrt(torch.sum(J * Su * Su) * torch.sum(J * w * w)))
+    assert abs(a - b) <= 1e-10 * scale
