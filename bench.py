@@ -24,6 +24,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -317,6 +318,64 @@ def walls_form():
     return out
 
 
+def mapped_form():
+    """A single curvilinear grid beside the box: one explicit wave-solve on a
+    2047^2 grid mapped by the smooth non-orthogonal skew map (order 2,
+    omega 60, CFL 0.9) against the 2047^2 unit square with the same settings,
+    the mapped leapfrog kernel timed with hipEvents (72 algorithmic bytes
+    per point-step: the state as in the box kernel plus four coefficient
+    arrays); and an eigensolve on a 255^2 quarter annulus (radii 0.5 to 1,
+    omega 40, k = 8, m = 20)."""
+    import torch
+    import synthetic
+    from paper_2507_18282_amd import Operator, fill_uniform
+    out = {"workload": "explicit order 2, omega 60, CFL 0.9: 2047^2 skew-mapped grid (eps 0.15) vs 2047^2 unit "
+                       "square, 2 wave-solves each; eigensolve: 255^2 quarter annulus (radii 0.5..1), omega 40, "
+                       "CFL 0.5, k=8, m=20, eig-res <= 1e-8"}
+    n = (2047, 2047)
+    xy = synthetic.mapped_coords("skew", *n, eps=0.15)
+    for label, coords in (("box", None), ("mapped", xy)):
+        op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="explicit", cfl=0.9, coords=coords)
+        v = fill_uniform(op.n_active, 3)
+        w = op.apply_filter(v)
+        torch.cuda.synchronize()
+        op.reset_stats()
+        t0 = time.perf_counter()
+        w = op.apply_filter(v)
+        w = op.apply_filter(v)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = op.stats()
+        # kernel timing in a separate wave-solve: the events would add gaps to the timed ones
+        op.profile_begin("leapfrog")
+        w = op.apply_filter(v)
+        torch.cuda.synchronize()
+        prof = op.profile_end()
+        avg = prof["total_ms"] / max(1, prof["launches"])
+        gbs = prof["bytes_alg"] / max(1, prof["launches"]) / (avg * 1e-3) / 1e9
+        out[label] = {"n_t": op.n_t, "pt_updates_per_s": st["pt_updates"] / dt, "ms_per_wave_solve": dt / 2 * 1e3,
+                      "leapfrog_avg_us": round(avg * 1e3, 3), "leapfrog_GBs": round(gbs, 1),
+                      "leapfrog_frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"mapped form: {label}: n_t {op.n_t}, {dt / 2 * 1e3:.1f} ms per wave-solve, leapfrog {avg * 1e3:.1f} us "
+            f"({gbs:.0f} GB/s)")
+        op.close()
+    na = (255, 255)
+    xa = synthetic.mapped_coords("annulus", *na, a=0.5, b=1.0, theta0=0.5 * math.pi)
+    op = Operator(n=na, length=(1.0, 1.0), order=2, omega=40.0, ts="explicit", cfl=0.5, coords=xa)
+    r = op.eigs(8, 20, seed=2, want_vectors=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = op.eigs(8, 20, seed=2, want_vectors=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = sum(1 for x in r.res if x <= 1e-8)
+    out["annulus_eigs"] = {"pairs": ok, "wave_solves": r.wave_solves, "n_t": op.n_t, "seconds": dt,
+                           "eigenpairs_per_s": ok / dt, "max_res": max(r.res)}
+    log(f"mapped form: annulus eigs: {ok} pairs, {r.wave_solves} wave-solves, {dt:.2f} s")
+    op.close()
+    return out
+
+
 def headline_np_rule(budget: int = 200):
     """The headline eigenproblem (2047^2, order 4, implicit, omega 120, k = 16)
     with N_p from the lobe rule and m = 2k + 1, within `budget` wave-solves.
@@ -433,6 +492,8 @@ def main(argv=None) -> int:
                     help="run only the many-pairs form and print its JSON (for profiling)")
     ap.add_argument("--only-walls", action="store_true",
                     help="run only the Neumann-walls form and print its JSON (for profiling)")
+    ap.add_argument("--only-mapped", action="store_true",
+                    help="run only the curvilinear-grid form (mapped vs box wave-solve, annulus eigensolve)")
     ap.add_argument("--headline-np-rule", action="store_true",
                     help="run only the headline eigenproblem with the N_p of the lobe rule (about 2.5 min) and "
                          "print its JSON")
@@ -451,6 +512,9 @@ def main(argv=None) -> int:
         return 0
     if a.only_walls:
         print(json.dumps({"form": "walls", "result": walls_form()}), flush=True)
+        return 0
+    if a.only_mapped:
+        print(json.dumps({"form": "mapped", "result": mapped_form()}), flush=True)
         return 0
     if a.headline_np_rule:
         print(json.dumps({"form": "headline_np_rule", "result": headline_np_rule()}), flush=True)
@@ -523,6 +587,7 @@ def main(argv=None) -> int:
         forms["periods_rule"] = periods_rule()
         forms["many_pairs"] = many_pairs(a.many_k)
         forms["walls"] = walls_form()
+        forms["mapped"] = mapped_form()
 
     cpu = None
     if not a.no_cpu_baseline:

@@ -1,6 +1,8 @@
 """Workload for rocprofv3 counter runs: one plain device copy of a known size
 (the calibration for FETCH_SIZE / WRITE_SIZE) followed by wave-solves of the
-headline implicit workload (2047^2 interior, order 4, FP64 multigrid).
+headline implicit workload (2047^2 interior, order 4, FP64 multigrid), or
+with ``--workload mapped`` explicit wave-solves on the 2047^2 skew-mapped
+grid (order 2, omega 60, CFL 0.9).
 
   rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2507_18282_amd.counters_probe
 """
@@ -20,6 +22,7 @@ COPY_BYTES = 256 * 1024 * 1024
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--wave-solves", type=int, default=1)
+    ap.add_argument("--workload", choices=("headline", "mapped"), default="headline")
     a = ap.parse_args(argv)
     import torch
     import synthetic
@@ -29,6 +32,16 @@ def main(argv=None) -> int:
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
+    if a.workload == "mapped":
+        n = (2047, 2047)
+        op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="explicit", cfl=0.9,
+                      coords=synthetic.mapped_coords("skew", *n, eps=0.15))
+        v = fill_uniform(op.n_active, 3)
+        for _ in range(a.wave_solves):
+            v = op.apply_filter(v)
+        torch.cuda.synchronize()
+        print("counters probe done", flush=True)
+        return 0
     P = synthetic.config_square_order4_implicit()
     # the multigrid settings of the benchmark: automatic depth (down to 127^2), 4 sweeps there
     op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=P.n_p,
