@@ -1,7 +1,7 @@
 """A single curvilinear grid by the mapping method: the order-2 Laplacian in
 conservative form with the metric terms of a mapping x = G(r) of the unit
-square, its symmetrising weights, the explicit time plan and one explicit
-wave-solve.
+square, its symmetrising weights, the explicit time plan, and one wave-solve
+with the explicit scheme or with the implicit scheme (exact sparse solves).
 
 Test infrastructure only (see ``oracle/__init__``).
 
@@ -182,6 +182,60 @@ def apply_filter_explicit(v: np.ndarray, xy: np.ndarray, plan: TimePlan) -> np.n
     acc = acc + c[1] * w_cur
     for k in range(1, plan.n_t):
         w_next = 2.0 * w_cur - w_prev + dt * dt * apply_laplacian(w_cur, xy)
+        acc = acc + c[k + 1] * w_next
+        w_prev, w_cur = w_cur, w_next
+    return acc
+
+
+def laplacian_sparse(xy: np.ndarray):
+    """L_h as a sparse matrix (rows and columns x fastest), assembled from the
+    nine weights of :func:`stencil` divided by J; wall neighbours dropped."""
+    from scipy import sparse
+    n1, n2 = _sizes(xy)
+    w = stencil(xy)
+    iJ = 1.0 / weights(xy)
+    jj, ii = np.meshgrid(np.arange(n2), np.arange(n1), indexing="ij")
+    rows, cols, vals = [], [], []
+    for (di, dj), wk in w.items():
+        ti, tj = ii + di, jj + dj
+        ok = (ti >= 0) & (ti < n1) & (tj >= 0) & (tj < n2)
+        rows.append((jj * n1 + ii)[ok])
+        cols.append((tj * n1 + ti)[ok])
+        vals.append((wk * iJ)[ok])
+    N = n1 * n2
+    return sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
+def solve_implicit_exact(b: np.ndarray, xy: np.ndarray, dt: float) -> np.ndarray:
+    """Exact solve of M x = b, M = I - (dt^2/2) L_h (eq. impMatrix), by a
+    library sparse direct solve."""
+    from scipy import sparse
+    from scipy.sparse.linalg import spsolve
+    n1, n2 = _sizes(xy)
+    M = sparse.identity(n1 * n2, format="csc") - 0.5 * dt * dt * laplacian_sparse(xy).tocsc()
+    return spsolve(M, np.asarray(b, dtype=np.float64).ravel()).reshape(n2, n1)
+
+
+def implicit_plan(xy: np.ndarray, omega: float, n_its: int = 10, n_p: int = 1, adjust_omega: bool = True,
+                  filter_const: str = "alpha_d") -> TimePlan:
+    """Implicit plan: N_t = N_p N_its (it does not depend on the grid)."""
+    return discrete.time_plan((1.0, 1.0), 2, omega, "implicit", n_its=n_its, n_p=n_p,
+                              adjust_omega=adjust_omega, filter_const=filter_const)
+
+
+def apply_filter_implicit(v: np.ndarray, xy: np.ndarray, plan: TimePlan) -> np.ndarray:
+    """S v with the implicit scheme (eqs. implicitStep1, implicitScheme:
+    M W^1 = W^0, M S = 2 W^n, W^{n+1} = S - W^{n-1}) and the trapezoidal
+    filter, exact solves, on the mapped grid."""
+    if plan.ts != "implicit":
+        raise ValueError("implicit plan expected")
+    c, dt = plan.c, plan.dt
+    w_prev = np.asarray(v, dtype=np.float64).copy()
+    acc = c[0] * w_prev
+    w_cur = solve_implicit_exact(w_prev, xy, dt)
+    acc = acc + c[1] * w_cur
+    for k in range(1, plan.n_t):
+        w_next = solve_implicit_exact(2.0 * w_cur, xy, dt) - w_prev
         acc = acc + c[k + 1] * w_next
         w_prev, w_cur = w_cur, w_next
     return acc

@@ -139,3 +139,41 @@ def test_filter_on_discrete_eigenvectors():
         got = Mp.apply_filter_explicit(phi, xy, plan)
         beta = float(D.beta_corrected(mu[k], plan))
         assert np.max(np.abs(got - beta * phi)) <= 1e-11 * np.max(np.abs(phi)), k
+
+
+def test_sparse_operator_equals_the_stencil_form():
+    xy = syn.mapped_coords("annulus", 11, 9, a=0.4, b=1.0, theta0=1.3)
+    A = Mp.laplacian_sparse(xy).toarray()
+    assert np.max(np.abs(A - Mp.laplacian_matrix(xy))) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_implicit_on_rotated_rectangle_matches_box_oracle():
+    n, L = (9, 7), (1.0, 0.75)
+    xy = syn.mapped_coords("affine", *n, len1=L[0], len2=L[1], phi=0.9)
+    h = D.spacing(n, L)
+    plan = Mp.implicit_plan(xy, 12.0)
+    ref_plan = D.time_plan(h, 2, 12.0, "implicit", n_its=10, adjust_omega=True)
+    assert plan.n_t == ref_plan.n_t and plan.dt == ref_plan.dt
+    b = syn.start_vector(7, n[0] * n[1]).reshape(n[1], n[0])
+    x = Mp.solve_implicit_exact(b, xy, plan.dt)
+    assert np.max(np.abs(x - Wv.solve_implicit_exact(b, h, 2, plan.dt))) <= 1e-12 * np.max(np.abs(x))
+    got = Mp.apply_filter_implicit(b, xy, plan)
+    ref = Wv.apply_filter(b, h, 2, plan)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_implicit_filter_on_discrete_eigenvectors():
+    xy = syn.mapped_coords("skew", 10, 8, eps=0.2)
+    A = Mp.laplacian_matrix(xy)
+    Wt = Mp.weights(xy).ravel()
+    mu, V = linalg.eigh(-(Wt[:, None] * A), np.diag(Wt))
+    plan = Mp.implicit_plan(xy, 9.0)
+    # M phi = (1 + a mu) phi
+    phi = V[:, 4].reshape(8, 10)
+    x = Mp.solve_implicit_exact(phi, xy, plan.dt)
+    assert np.max(np.abs(x - phi / (1 + 0.5 * plan.dt ** 2 * mu[4]))) <= 1e-12 * np.max(np.abs(phi))
+    for k in (0, 4, 30, len(mu) - 1):
+        phi = V[:, k].reshape(8, 10)
+        got = Mp.apply_filter_implicit(phi, xy, plan)
+        beta = float(D.beta_corrected(mu[k], plan))
+        assert np.max(np.abs(got - beta * phi)) <= 1e-11 * np.max(np.abs(phi)), k
