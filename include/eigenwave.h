@@ -202,18 +202,27 @@ ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* h
  * differences of the coordinates, Dirichlet walls.  L_h is self-adjoint in
  * the J-weighted inner product; ew_eigs works in y = J^{1/2} u and returns
  * grid functions.  The explicit step uses dt_max = 2 / sqrt(rho) with rho the
- * Gershgorin bound max (1/J) sum |weights of J L_h| (ew_op_mapped_rho).
+ * Gershgorin bound max (1/J) sum |weights of J L_h| (ew_op_mapped_rho).  The
+ * implicit scheme solves M = I - (dt^2/2) L_h by multigrid on levels
+ * rediscretised from the node samples of J and J a^mn at their points
+ * (every coarse node is a fine node; n halves as (n - 1)/2 while both sizes
+ * are odd and >= 3, with mg_max_levels and EW_MG_LEVELS_AUTO as for boxes),
+ * red-black Gauss-Seidel half-sweeps (the corner neighbours share the
+ * colour and enter with their previous values), full weighting and bilinear
+ * prolongation; ew_op_mg_solve, ew_op_mg_vcycle and ew_op_mg_half_sweep
+ * apply to it.
  *   grid      dim 2, order 2, Dirichlet walls; n[0] x n[1] active points at
  *             r = (i + 1)/(n[0] + 1), s = (j + 1)/(n[1] + 1); len is unused.
- *   desc      ts EW_TS_EXPLICIT, precision EW_PREC_FP64.
+ *   desc      explicit or implicit, precision EW_PREC_FP64; implicit guesses
+ *             EW_PRED_ZERO, EW_PRED_SCALED or EW_PRED_EXTRAP.
  *   xy_host   host array of 2 (n[0] + 4)(n[1] + 4) doubles: x, then y, of
  *             nodes i in [-2, n[0] + 1], j in [-2, n[1] + 1] (the walls are
  *             i = -1 and i = n[0], plus one layer beyond each) at
  *             (i + 2) + (n[0] + 4)(j + 2).  Read during the call only.
  * Errors: EW_ERR_INVALID_ARG (ranges of ew_op_create, null or non-finite
  * coordinates, a Jacobian that is not positive at some node, walls
- * included), EW_ERR_UNSUPPORTED (3D, order 4, Neumann walls, implicit or
- * mixed precision), EW_ERR_OOM, EW_ERR_HIP.  The implicit, multigrid,
+ * included), EW_ERR_UNSUPPORTED (3D, order 4, Neumann walls, mixed
+ * precision, the PROJ and CNN guesses), EW_ERR_OOM, EW_ERR_HIP.  The
  * network and batched entry points do not apply to such an operator. */
 ew_status ew_op_create_mapped(const ew_grid_desc* grid, const ew_op_desc* desc, const double* xy_host,
                               void* hip_stream, ew_op* out);

@@ -161,5 +161,15 @@ hipError_t launch_leapfrog_mapped(const double* wcur, const double* wprev, doubl
                                   const MapCoef& m, double dt2, double ccur, double cnext, int first, hipStream_t s);
 // out = in * f elementwise (in and out may alias).
 hipError_t launch_pointwise_mul(const double* in, const double* f, double* out, int64_t n, hipStream_t s);
+// Multigrid for M = I - a L_h on a mapped level: out-of-place red-black
+// half-sweep (the points of one colour relaxed from the input values, the
+// others copied); residual r = bscale b - M x, stored when r_out != nullptr
+// and with per-block partial sums of r^2 (kRedBlocks) when partial !=
+// nullptr; full-weighting restriction of r to the level with n_c = (n - 1)/2.
+hipError_t launch_rb_half_mapped(const double* xin, double* xout, const double* b, double bscale, const Geo& g,
+                                 const MapCoef& m, double a, int colour, hipStream_t s);
+hipError_t launch_residual_mapped(const double* x, const double* b, double bscale, const Geo& g, const MapCoef& m,
+                                  double a, double* partial, double* r_out, hipStream_t s);
+hipError_t launch_restrict_fw(const double* r, const Geo& gf, double* bc, const Geo& gc, hipStream_t s);
 
 }  // namespace ew

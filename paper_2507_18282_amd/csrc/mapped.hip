@@ -13,7 +13,12 @@
 // The coefficients are built once on the host from the caller's coordinates
 // and kept on the device as four arrays (A11 / dr^2 at x half points, A22 /
 // ds^2 at y half points, B / (4 dr ds) and 1/J at the nodes): the leapfrog
-// step streams them with the three state arrays, 72 B per point-step.
+// step streams them with the three state arrays, 72 B per point-step.  The
+// implicit scheme solves M = I - (dt^2/2) L_h by multigrid whose coarse
+// levels are rediscretised from the node samples of J and J a^{mn} at their
+// own points (every coarse node is a fine node), with red-black
+// Gauss-Seidel half-sweeps (the corner neighbours share the colour and enter
+// with their previous values), full weighting and bilinear prolongation.
 #include <cmath>
 #include <memory>
 #include <vector>
@@ -103,28 +108,152 @@ hipError_t launch_pointwise_mul(const double* in, const double* f, double* out, 
 }
 
 // ---------------------------------------------------------------------------
+// Multigrid on mapped levels (implicit scheme): M = I - a L_h, every level
+// rediscretised from the node samples of J and J a^{mn} at its points.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double mdiag_mapped(int64_t c, int i, int j, const Geo& g, const MapCoef& m, double a) {
+    const int64_t hw = (int64_t)j * (g.nx + 1) + i;
+    const double centre = -(m.cw[hw + 1] + m.cw[hw] + m.cs[c + g.nx] + m.cs[c]);
+    return 1.0 - a * m.ij[c] * centre;
+}
+
+__global__ __launch_bounds__(256) void k_rb_half_mapped(const double* __restrict__ xin, double* __restrict__ xout,
+                                                        const double* __restrict__ b, double bscale, Geo g, MapCoef m,
+                                                        double a, int colour) {
+    int i, j, k;
+    if (!tile_coords(g, i, j, k)) return;
+    const int64_t c = lin(g, i, j, 0);
+    const double xc = xin[c];
+    if (((i + j) & 1) != colour) {
+        xout[c] = xc;
+        return;
+    }
+    const double r = bscale * b[c] - (xc - a * lap_mapped(xin, c, i, j, g, m));
+    xout[c] = xc + r / mdiag_mapped(c, i, j, g, m, a);
+}
+
+__global__ __launch_bounds__(256) void k_residual_mapped(const double* __restrict__ x, const double* __restrict__ b,
+                                                         double bscale, Geo g, MapCoef m, double a,
+                                                         double* __restrict__ partial, double* __restrict__ r_out) {
+    const int64_t n = g.size();
+    double acc = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+        const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+        const double r = bscale * b[c] - (x[c] - a * lap_mapped(x, c, i, j, g, m));
+        if (r_out) r_out[c] = r;
+        acc += r * r;
+    }
+    if (partial) {  // uniform over the block
+        const double s = block_sum_256(acc, threadIdx.x);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// Full weighting: coarse point (I, J) sits on fine point (2I + 1, 2J + 1);
+// weights 1/4, 1/2, 1/4 per direction (n_f = 2 n_c + 1, so every fine index
+// read is in range).
+__global__ __launch_bounds__(256) void k_restrict_fw(const double* __restrict__ r, Geo gf, double* __restrict__ bc,
+                                                     Geo gc) {
+    int I, J, k;
+    if (!tile_coords(gc, I, J, k)) return;
+    const int fi = 2 * I + 1, fj = 2 * J + 1;
+    double sum = 0.0;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+        const double* row = r + (int64_t)(fj + dj) * gf.nx + fi;
+        const double v = 0.25 * row[-1] + 0.5 * row[0] + 0.25 * row[1];
+        sum += (dj == 0 ? 0.5 : 0.25) * v;
+    }
+    bc[lin(gc, I, J, 0)] = sum;
+}
+
+hipError_t launch_rb_half_mapped(const double* xin, double* xout, const double* b, double bscale, const Geo& g,
+                                 const MapCoef& m, double a, int colour, hipStream_t s) {
+    k_rb_half_mapped<<<tile_grid(g), dim3(kTileX, kTileY, 1), 0, s>>>(xin, xout, b, bscale, g, m, a, colour);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_mapped(const double* x, const double* b, double bscale, const Geo& g, const MapCoef& m,
+                                  double a, double* partial, double* r_out, hipStream_t s) {
+    k_residual_mapped<<<kRedBlocks, 256, 0, s>>>(x, b, bscale, g, m, a, partial, r_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_fw(const double* r, const Geo& gf, double* bc, const Geo& gc, hipStream_t s) {
+    k_restrict_fw<<<tile_grid(gc), dim3(kTileX, kTileY, 1), 0, s>>>(r, gf, bc, gc);
+    return hipGetLastError();
+}
+
+// V(nu1, nu2) cycle on mapped level l from the iterate in cur (zero if
+// `zero`); other is its partner buffer and holds the residual while the
+// coarser levels run.  A full sweep is a red half-sweep into other and a
+// black one back, so the result is always in cur.
+ew_status Op::mapped_vcycle(int l, double* cur, double* other, const double* b, double bscale, bool zero,
+                            double** result) {
+    const Level& L = levels[l];
+    const MapCoef& m = mcoef[l];
+    const int64_t n = L.g.size();
+    auto sweeps = [&](int count, bool from_zero) -> ew_status {
+        if (from_zero) EW_HIP_TRY(launch_fill<double>(cur, n, 0.0, stream));
+        for (int s = 0; s < count; ++s) {
+            ProfScope ps(this, EW_K_SMOOTH, l, 48.0 * (double)n);
+            EW_HIP_TRY(launch_rb_half_mapped(cur, other, b, bscale, L.g, m, a, 0, stream));
+            EW_HIP_TRY(launch_rb_half_mapped(other, cur, b, bscale, L.g, m, a, 1, stream));
+        }
+        return EW_OK;
+    };
+    *result = cur;
+    if (l == (int)levels.size() - 1) return sweeps(n == 1 ? 1 : desc.mg_coarse_sweeps, zero);
+    EW_TRY(sweeps(desc.mg_nu1, zero));
+    const Level& C = levels[l + 1];
+    {
+        ProfScope ps(this, EW_K_RESTRICT, l, 8.0 * (3.0 * (double)n + (double)C.g.size()));
+        EW_HIP_TRY(launch_residual_mapped(cur, b, bscale, L.g, m, a, nullptr, other, stream));
+        EW_HIP_TRY(launch_restrict_fw(other, L.g, (double*)C.b, C.g, stream));
+    }
+    double* xc = nullptr;
+    EW_TRY(mapped_vcycle(l + 1, (double*)C.x[0], (double*)C.x[1], (const double*)C.b, 1.0, true, &xc));
+    {
+        ProfScope ps(this, EW_K_PROLONG, l, 8.0 * (2.0 * (double)n + (double)C.g.size()));
+        EW_HIP_TRY(launch_prolong_correct<double>(cur, xc, L.g, C.g, stream));
+    }
+    return sweeps(desc.mg_nu2, false);
+}
+
+// ---------------------------------------------------------------------------
 // Host: coefficients from the coordinates.  xy holds x then y, each
 // (n1 + 4) x (n2 + 4) with node (i, j), i in [-2, n1 + 1], at (i + 2) +
 // (n1 + 4)(j + 2); metric terms are formed at the nodes i in [-1, n1],
-// j in [-1, n2] (walls included).
+// j in [-1, n2] (walls included).  A coarse multigrid level with spacing
+// 2^l dr samples them at its own nodes, which are fine nodes.
 // ---------------------------------------------------------------------------
 namespace {
 
-struct HostCoef {
-    std::vector<double> cw, cs, cb, ij, sq, isq;
-    double rho = 0.0;
+struct Nodes {
+    int n1 = 0, n2 = 0;
+    std::vector<double> J, a11, a22, a12;  // (n1 + 2) x (n2 + 2), node (i, j) at (i + 1) + (n1 + 2)(j + 1)
 };
 
-ew_status build_coefficients(const double* xy, int n1, int n2, HostCoef& hc) {
+struct HostCoef {
+    std::vector<double> cw, cs, cb, ij, sq, isq;
+    double rho = 0.0;    // Gershgorin bound on the spectrum of -L_h
+    double rho_j = 0.0;  // Gershgorin ratio of M = I - a L_h: off-diagonal row sum over diagonal
+};
+
+ew_status node_metrics(const double* xy, int n1, int n2, Nodes& nd) {
     const int64_t px = n1 + 4, plane = px * (int64_t)(n2 + 4);
     for (int64_t q = 0; q < 2 * plane; ++q)
         if (!std::isfinite(xy[q])) return fail(EW_ERR_INVALID_ARG, "mapped grid coordinates must be finite");
     const double dr = 1.0 / (n1 + 1), ds = 1.0 / (n2 + 1);
     auto X = [&](int i, int j) { return xy[(i + 2) + px * (j + 2)]; };
     auto Y = [&](int i, int j) { return xy[plane + (i + 2) + px * (j + 2)]; };
-    // node arrays over i in [-1, n1], j in [-1, n2]: index (i + 1) + (n1 + 2)(j + 1)
     const int64_t nx2 = n1 + 2, ny2 = n2 + 2;
-    std::vector<double> J(nx2 * ny2), a11(nx2 * ny2), a22(nx2 * ny2), a12(nx2 * ny2);
+    nd.n1 = n1;
+    nd.n2 = n2;
+    nd.J.assign(nx2 * ny2, 0.0);
+    nd.a11.assign(nx2 * ny2, 0.0);
+    nd.a22.assign(nx2 * ny2, 0.0);
+    nd.a12.assign(nx2 * ny2, 0.0);
     for (int j = -1; j <= n2; ++j)
         for (int i = -1; i <= n1; ++i) {
             const double xr = (X(i + 1, j) - X(i - 1, j)) / (2.0 * dr), yr = (Y(i + 1, j) - Y(i - 1, j)) / (2.0 * dr);
@@ -134,48 +263,61 @@ ew_status build_coefficients(const double* xy, int n1, int n2, HostCoef& hc) {
                 return fail(EW_ERR_INVALID_ARG, "mapped grid: the Jacobian x_r y_s - x_s y_r must be positive at every "
                                                 "node (walls included)");
             const int64_t q = (i + 1) + nx2 * (j + 1);
-            J[q] = jac;
-            a11[q] = (xs * xs + ys * ys) / jac;
-            a22[q] = (xr * xr + yr * yr) / jac;
-            a12[q] = -(xr * xs + yr * ys) / jac;
+            nd.J[q] = jac;
+            nd.a11[q] = (xs * xs + ys * ys) / jac;
+            nd.a22[q] = (xr * xr + yr * yr) / jac;
+            nd.a12[q] = -(xr * xs + yr * ys) / jac;
         }
-    auto node = [&](const std::vector<double>& F, int i, int j) { return F[(i + 1) + nx2 * (j + 1)]; };
-    const int64_t N = (int64_t)n1 * n2;
-    hc.cw.assign((int64_t)(n1 + 1) * n2, 0.0);
-    hc.cs.assign((int64_t)n1 * (n2 + 1), 0.0);
+    return EW_OK;
+}
+
+// Coefficients of the level with nl1 x nl2 points whose node (I, J) is fine
+// node (stride (I + 1) - 1, stride (J + 1) - 1); a is the implicit weight (0
+// when only rho is wanted).
+void level_coefficients(const Nodes& nd, int stride, int nl1, int nl2, double a, HostCoef& hc) {
+    const int64_t nx2 = nd.n1 + 2;
+    auto at = [&](const std::vector<double>& F, int I, int J) {
+        const int i = stride * (I + 1) - 1, j = stride * (J + 1) - 1;
+        return F[(i + 1) + nx2 * (j + 1)];
+    };
+    const double dr = stride / (double)(nd.n1 + 1), ds = stride / (double)(nd.n2 + 1);
+    const int64_t N = (int64_t)nl1 * nl2;
+    hc.cw.assign((int64_t)(nl1 + 1) * nl2, 0.0);
+    hc.cs.assign((int64_t)nl1 * (nl2 + 1), 0.0);
     hc.cb.assign(N, 0.0);
     hc.ij.assign(N, 0.0);
     hc.sq.assign(N, 0.0);
     hc.isq.assign(N, 0.0);
     const double idr2 = 1.0 / (dr * dr), ids2 = 1.0 / (ds * ds), q4 = 1.0 / (4.0 * dr * ds);
-    for (int j = 0; j < n2; ++j)
-        for (int hi = 0; hi <= n1; ++hi)
-            hc.cw[hi + (int64_t)(n1 + 1) * j] = 0.5 * (node(a11, hi - 1, j) + node(a11, hi, j)) * idr2;
-    for (int hj = 0; hj <= n2; ++hj)
-        for (int i = 0; i < n1; ++i)
-            hc.cs[i + (int64_t)n1 * hj] = 0.5 * (node(a22, i, hj - 1) + node(a22, i, hj)) * ids2;
-    double rho = 0.0;
-    for (int j = 0; j < n2; ++j)
-        for (int i = 0; i < n1; ++i) {
-            const int64_t c = i + (int64_t)n1 * j;
-            const double jac = node(J, i, j);
-            hc.cb[c] = node(a12, i, j) * q4;
+    for (int j = 0; j < nl2; ++j)
+        for (int hi = 0; hi <= nl1; ++hi)
+            hc.cw[hi + (int64_t)(nl1 + 1) * j] = 0.5 * (at(nd.a11, hi - 1, j) + at(nd.a11, hi, j)) * idr2;
+    for (int hj = 0; hj <= nl2; ++hj)
+        for (int i = 0; i < nl1; ++i)
+            hc.cs[i + (int64_t)nl1 * hj] = 0.5 * (at(nd.a22, i, hj - 1) + at(nd.a22, i, hj)) * ids2;
+    double rho = 0.0, rho_j = 0.0;
+    for (int j = 0; j < nl2; ++j)
+        for (int i = 0; i < nl1; ++i) {
+            const int64_t c = i + (int64_t)nl1 * j;
+            const double jac = at(nd.J, i, j);
+            hc.cb[c] = at(nd.a12, i, j) * q4;
             hc.ij[c] = 1.0 / jac;
             hc.sq[c] = std::sqrt(jac);
             hc.isq[c] = 1.0 / hc.sq[c];
             // Gershgorin: (1/J) times the absolute sum of the nine weights of
             // J L_h, the cross weights of wall nodes included
-            const double wE = hc.cw[(i + 1) + (int64_t)(n1 + 1) * j], wW = hc.cw[i + (int64_t)(n1 + 1) * j];
-            const double wN = hc.cs[i + (int64_t)n1 * (j + 1)], wS = hc.cs[c];
-            const double bE = node(a12, i + 1, j) * q4, bW = node(a12, i - 1, j) * q4;
-            const double bN = node(a12, i, j + 1) * q4, bS = node(a12, i, j - 1) * q4;
-            const double sum = std::fabs(wE + wW + wN + wS) + std::fabs(wE) + std::fabs(wW) + std::fabs(wN) +
-                               std::fabs(wS) + std::fabs(bE + bN) + std::fabs(bE + bS) + std::fabs(bW + bN) +
-                               std::fabs(bW + bS);
-            rho = std::max(rho, sum / jac);
+            const double wE = hc.cw[(i + 1) + (int64_t)(nl1 + 1) * j], wW = hc.cw[i + (int64_t)(nl1 + 1) * j];
+            const double wN = hc.cs[i + (int64_t)nl1 * (j + 1)], wS = hc.cs[c];
+            const double bE = at(nd.a12, i + 1, j) * q4, bW = at(nd.a12, i - 1, j) * q4;
+            const double bN = at(nd.a12, i, j + 1) * q4, bS = at(nd.a12, i, j - 1) * q4;
+            const double centre = std::fabs(wE + wW + wN + wS);
+            const double off = std::fabs(wE) + std::fabs(wW) + std::fabs(wN) + std::fabs(wS) + std::fabs(bE + bN) +
+                               std::fabs(bE + bS) + std::fabs(bW + bN) + std::fabs(bW + bS);
+            rho = std::max(rho, (centre + off) / jac);
+            rho_j = std::max(rho_j, a * off / jac / (1.0 + a * centre / jac));
         }
     hc.rho = rho;
-    return EW_OK;
+    hc.rho_j = rho_j;
 }
 
 ew_status upload(Op* op, const std::vector<double>& h, const double** dst) {
@@ -183,6 +325,59 @@ ew_status upload(Op* op, const std::vector<double>& h, const double** dst) {
     EW_TRY(op->alloc((void**)&d, h.size() * sizeof(double)));
     EW_HIP_TRY(hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
     *dst = d;
+    return EW_OK;
+}
+
+ew_status upload_level(Op* op, const HostCoef& hc, MapCoef& m) {
+    EW_TRY(upload(op, hc.cw, &m.cw));
+    EW_TRY(upload(op, hc.cs, &m.cs));
+    EW_TRY(upload(op, hc.cb, &m.cb));
+    EW_TRY(upload(op, hc.ij, &m.ij));
+    EW_TRY(upload(op, hc.sq, &m.sq));
+    EW_TRY(upload(op, hc.isq, &m.isq));
+    return EW_OK;
+}
+
+// Levels halve (n - 1)/2 while both sizes are odd and >= 3, up to
+// mg_max_levels; with EW_MG_LEVELS_AUTO the hierarchy stops at the first
+// level whose Gauss-Seidel contraction bound rho_J^2, raised to
+// mg_coarse_sweeps, is at most 0.1 (rho_J from that level's coefficients).
+ew_status build_mapped_hierarchy(Op* op, const Nodes& nd, const HostCoef& fine) {
+    const ew_op_desc& d = op->desc;
+    const size_t max_levels = d.mg_max_levels > 0 ? (size_t)d.mg_max_levels : 64;
+    int nl1 = nd.n1, nl2 = nd.n2, stride = 1;
+    for (;;) {
+        Level L;
+        const int64_t nn[3] = {nl1, nl2, 1};
+        const double hh[3] = {stride / (double)(nd.n1 + 1), stride / (double)(nd.n2 + 1), 1.0};
+        L.g = make_geo(2, nn, hh, 0);
+        const int64_t n = L.g.size();
+        HostCoef hc;
+        const HostCoef* use = &fine;
+        if (stride > 1) {
+            level_coefficients(nd, stride, nl1, nl2, op->a, hc);
+            use = &hc;
+        }
+        MapCoef m{};
+        if (stride == 1) {
+            m = op->mc;
+            EW_TRY(op->alloc(&L.x[1], n * sizeof(double)));
+        } else {
+            EW_TRY(upload_level(op, hc, m));
+            EW_TRY(op->alloc(&L.x[0], n * sizeof(double)));
+            EW_TRY(op->alloc(&L.x[1], n * sizeof(double)));
+            EW_TRY(op->alloc(&L.b, n * sizeof(double)));
+        }
+        op->levels.push_back(L);
+        op->mcoef.push_back(m);
+        const bool can = (nl1 % 2 == 1) && (nl2 % 2 == 1) && nl1 >= 3 && nl2 >= 3;
+        const bool enough = d.mg_max_levels == EW_MG_LEVELS_AUTO &&
+                            std::pow(use->rho_j * use->rho_j, d.mg_coarse_sweeps) <= 0.1;
+        if (!can || op->levels.size() >= max_levels || enough) break;
+        nl1 = (nl1 - 1) / 2;
+        nl2 = (nl2 - 1) / 2;
+        stride *= 2;
+    }
     return EW_OK;
 }
 
@@ -202,11 +397,14 @@ extern "C" ew_status ew_op_create_mapped(const ew_grid_desc* grid, const ew_op_d
     for (int e = 0; e < 2; ++e)
         if (grid->walls[0][e] != EW_WALL_DIRICHLET || grid->walls[1][e] != EW_WALL_DIRICHLET)
             return fail(EW_ERR_UNSUPPORTED, "mapped grids have Dirichlet walls");
-    if (desc->ts != EW_TS_EXPLICIT) return fail(EW_ERR_UNSUPPORTED, "mapped grids use explicit time-stepping");
     if (desc->precision != EW_PREC_FP64) return fail(EW_ERR_UNSUPPORTED, "mapped grids run in FP64");
+    if (desc->ts == EW_TS_IMPLICIT && (desc->predictor == EW_PRED_PROJ || desc->predictor == EW_PRED_CNN))
+        return fail(EW_ERR_UNSUPPORTED, "on mapped grids the implicit guesses are ZERO, SCALED or EXTRAP");
     const int n1 = (int)grid->n[0], n2 = (int)grid->n[1];
+    Nodes nd;
+    EW_TRY(node_metrics(xy_host, n1, n2, nd));
     HostCoef hc;
-    EW_TRY(build_coefficients(xy_host, n1, n2, hc));
+    level_coefficients(nd, 1, n1, n2, 0.0, hc);
 
     std::unique_ptr<ew_op_s> op(new ew_op_s());
     op->dim = 2;
@@ -218,6 +416,7 @@ extern "C" ew_status ew_op_create_mapped(const ew_grid_desc* grid, const ew_op_d
     op->h[1] = 1.0 / (n2 + 1);
     op->desc = *desc;
     op->stream = (hipStream_t)hip_stream;
+    op->implicit = desc->ts == EW_TS_IMPLICIT;
     op->g = make_geo(2, op->n, op->h, 0);
     op->N = op->g.size();
     EW_HIP_TRY(hipGetDevice(&op->device));
@@ -232,19 +431,20 @@ extern "C" ew_status ew_op_create_mapped(const ew_grid_desc* grid, const ew_op_d
     op->alpha_d = tp.alpha_d;
     op->c = tp.c;
     op->a = 0.5 * op->dt * op->dt;
-    EW_TRY(upload(op.get(), hc.cw, &op->mc.cw));
-    EW_TRY(upload(op.get(), hc.cs, &op->mc.cs));
-    EW_TRY(upload(op.get(), hc.cb, &op->mc.cb));
-    EW_TRY(upload(op.get(), hc.ij, &op->mc.ij));
-    EW_TRY(upload(op.get(), hc.sq, &op->mc.sq));
-    EW_TRY(upload(op.get(), hc.isq, &op->mc.isq));
+    EW_TRY(upload_level(op.get(), hc, op->mc));
     const int64_t N = op->N;
     EW_TRY(op->alloc((void**)&op->partial_dev, kRedBlocks * sizeof(double) * 4));
     EW_HIP_TRY(hipHostMalloc((void**)&op->partial_host, kRedBlocks * sizeof(double) * 4, hipHostMallocDefault));
     EW_TRY(op->alloc((void**)&op->wA, N * sizeof(double)));
     EW_TRY(op->alloc((void**)&op->wB, N * sizeof(double)));
-    EW_TRY(op->alloc((void**)&op->c_dev, op->c.size() * sizeof(double)));
-    EW_HIP_TRY(hipMemcpy(op->c_dev, op->c.data(), op->c.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (op->implicit) {
+        EW_TRY(op->alloc((void**)&op->sbuf, N * sizeof(double)));
+        level_coefficients(nd, 1, n1, n2, op->a, hc);  // the fine level's rho_j needs a, known only now
+        EW_TRY(build_mapped_hierarchy(op.get(), nd, hc));
+    } else {
+        EW_TRY(op->alloc((void**)&op->c_dev, op->c.size() * sizeof(double)));
+        EW_HIP_TRY(hipMemcpy(op->c_dev, op->c.data(), op->c.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     *out = op.release();
     return EW_OK;
 }

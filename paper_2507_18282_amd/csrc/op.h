@@ -86,6 +86,7 @@ struct Op {
     bool mapped = false;
     MapCoef mc{};
     double map_rho = 0.0;      // Gershgorin bound on the spectrum of -L_h
+    std::vector<MapCoef> mcoef;  // per multigrid level (implicit)
     // workspace
     double* wA = nullptr;
     double* wB = nullptr;
@@ -142,6 +143,8 @@ struct Op {
     ew_status sweep(int level, T*& cur, T*& other, const T* b, double bscale, bool zero, const T* xc);
     template <typename T>
     ew_status sweeps(int level, int count, T*& cur, T*& other, const T* b, double bscale, bool zero);
+    ew_status mapped_vcycle(int level, double* cur, double* other, const double* b, double bscale, bool zero,
+                            double** result);
     ew_status mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel,
                          bool speculate = false);
     ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);

@@ -135,8 +135,11 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
             if (test) {
                 {
                     ProfScope ps(this, EW_K_RESNORM, 0, 16.0 * (double)N);
-                    EW_HIP_TRY((launch_residual_norm<double, double>(cur, b, bscale, g, order, a, partial_dev, nullptr,
-                                                                     stream)));
+                    if (mapped)
+                        EW_HIP_TRY(launch_residual_mapped(cur, b, bscale, g, mcoef[0], a, partial_dev, nullptr, stream));
+                    else
+                        EW_HIP_TRY((launch_residual_norm<double, double>(cur, b, bscale, g, order, a, partial_dev,
+                                                                         nullptr, stream)));
                 }
                 double rr;
                 EW_TRY(host_sum_partials(&rr));
@@ -148,7 +151,8 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
             }
             if (cyc >= desc.mg_max_cycles) break;
             double* res = nullptr;
-            EW_TRY(vcycle<double>(0, cur, other, b, bscale, zero, &res));
+            if (mapped) EW_TRY(mapped_vcycle(0, cur, other, b, bscale, zero, &res));
+            else EW_TRY(vcycle<double>(0, cur, other, b, bscale, zero, &res));
             if (res != cur) std::swap(cur, other);
             zero = false;
             ++cyc;
@@ -239,7 +243,7 @@ ew_status Op::implicit_solve(const double* b, double bscale, double* x, const do
 
 ew_status Op::apply_filter(const double* v, double* out) {
     const double dt2 = dt * dt;
-    if (mapped) {
+    if (mapped && !implicit) {
         {
             ProfScope ps(this, EW_K_LEAPFROG, 0, 56.0 * (double)N);
             EW_HIP_TRY(launch_leapfrog_mapped(v, nullptr, wA, out, g, mc, dt2, c[0], c[1], 1, stream));
@@ -344,7 +348,8 @@ extern "C" ew_status ew_op_mg_vcycle(ew_op op, const double* b_dev, double* x_de
     if (!op->implicit || op->mixed) return fail(EW_ERR_INVALID_ARG, "needs an implicit FP64 operator");
     if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
     double* res = nullptr;
-    EW_TRY(op->vcycle<double>(0, x_dev, (double*)op->levels[0].x[1], b_dev, 1.0, false, &res));
+    if (op->mapped) EW_TRY(op->mapped_vcycle(0, x_dev, (double*)op->levels[0].x[1], b_dev, 1.0, false, &res));
+    else EW_TRY(op->vcycle<double>(0, x_dev, (double*)op->levels[0].x[1], b_dev, 1.0, false, &res));
     if (res != x_dev)
         EW_HIP_TRY(hipMemcpyAsync(x_dev, res, op->N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));
     return EW_OK;
@@ -356,7 +361,10 @@ extern "C" ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* 
     if (colour != 0 && colour != 1) return fail(EW_ERR_INVALID_ARG, "colour must be 0 or 1");
     if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
     double* tmp = (double*)op->levels[0].x[1];
-    EW_HIP_TRY(launch_rb_half<double>(x_dev, tmp, b_dev, 1.0, op->g, op->order, op->a, colour, op->stream));
+    if (op->mapped)
+        EW_HIP_TRY(launch_rb_half_mapped(x_dev, tmp, b_dev, 1.0, op->g, op->mcoef[0], op->a, colour, op->stream));
+    else
+        EW_HIP_TRY(launch_rb_half<double>(x_dev, tmp, b_dev, 1.0, op->g, op->order, op->a, colour, op->stream));
     EW_HIP_TRY(hipMemcpyAsync(x_dev, tmp, op->N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));
     return EW_OK;
 }

@@ -122,10 +122,10 @@ def test_neumann_walls_rejected_where_not_implemented():
 
 def test_mapped_grid_validation():
     """ew_op_create_mapped validates the combination and the coordinates on
-    the host before any device work: 3D, order 4, Neumann walls, implicit and
-    mixed precision are EW_ERR_UNSUPPORTED; null coordinates, non-finite
-    coordinates and a map whose Jacobian is not positive at some node
-    (walls included) are EW_ERR_INVALID_ARG."""
+    the host before any device work: 3D, order 4, Neumann walls, mixed
+    precision and the implicit PROJ and CNN guesses are EW_ERR_UNSUPPORTED;
+    null coordinates, non-finite coordinates and a map whose Jacobian is not
+    positive at some node (walls included) are EW_ERR_INVALID_ARG."""
     import ctypes
 
     import numpy as np
@@ -136,7 +136,7 @@ def test_mapped_grid_validation():
     n = (12, 9)
     good = synthetic.mapped_coords("skew", *n, eps=0.15)
 
-    def create(xy, order=2, ts="explicit", precision="fp64", neumann=False, dim=2):
+    def create(xy, order=2, ts="explicit", precision="fp64", neumann=False, dim=2, predictor="zero"):
         g = _lib.GridDesc()
         g.dim = dim
         g.n[0], g.n[1], g.n[2] = n[0], n[1], 5
@@ -148,12 +148,14 @@ def test_mapped_grid_validation():
         d.omega, d.ts, d.cfl, d.n_its, d.n_p = 10.0, _lib.TS[ts], 0.5, 10, 1
         d.precision = _lib.PRECISION[precision]
         d.mg_tol, d.mg_nu1, d.mg_nu2, d.mg_max_cycles, d.mg_coarse_sweeps = 1e-10, 2, 1, 100, 8
+        d.predictor = _lib.PREDICTOR[predictor]
         h = ctypes.c_void_p()
         p = None if xy is None else np.ascontiguousarray(xy).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         return lib.ew_op_create_mapped(ctypes.byref(g), ctypes.byref(d), p, None, ctypes.byref(h))
 
     assert create(good, order=4) == -7
-    assert create(good, ts="implicit") == -7
+    assert create(good, ts="implicit", predictor="proj") == -7
+    assert create(good, ts="implicit", predictor="cnn") == -7
     assert create(good, precision="mixed") == -7
     assert create(good, neumann=True) == -7
     assert create(good, dim=3) == -7
