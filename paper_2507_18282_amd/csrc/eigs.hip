@@ -3,8 +3,10 @@
 // eigenvalues, and the Rayleigh-Ritz stage with L_h.
 //
 // Vectors live on the device; the host holds only the small projected
-// matrices.  Each Arnoldi step crosses the host/device boundary once (the
-// column of Gram-Schmidt coefficients, j+2 doubles).
+// matrices.  Arnoldi steps are queued back to back with their Gram-Schmidt
+// coefficients left in device columns, which the host reads once per run of
+// steps (at a restart or a probe's convergence test); when those columns would
+// not fit a small buffer, each step crosses the host/device boundary once.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -17,70 +19,70 @@ namespace ew {
 constexpr int kMaxKrylov = 4096;
 
 // w <- w - sum_i (w, u_i) u_i over the vector list by chained MGS links, then
-// w <- w / ||w||.  coeff receives the n_u coefficients and the norm (n_u + 1).
-ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const double*>& u, std::vector<double>& coeff) {
+// w <- w / ||w||.  hd (device) receives the n_u coefficients and the norm.
+static ew_status mgs_chain(Workspace& ws, double* w, const std::vector<const double*>& u, double* hd) {
     hipStream_t s = ws.stream;
     const int nu = (int)u.size();
     double* P0 = ws.P;
     double* P1 = ws.P + kRedBlocks;
     if (nu == 0) {
         EW_HIP_TRY(launch_dot_partial(w, w, ws.N, P0, s));
-        EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, P0, ws.h_dev, s));
+        EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, P0, hd, s));
     } else {
         EW_HIP_TRY(launch_dot_partial(w, u[0], ws.N, P0, s));
         for (int i = 1; i <= nu; ++i) {
             const double* pin = (i % 2 == 1) ? P0 : P1;
             double* pout = (i % 2 == 1) ? P1 : P0;
             const double* vnext = (i < nu) ? u[i] : w;
-            EW_HIP_TRY(launch_mgs_link(w, u[i - 1], vnext, ws.N, pin, pout, ws.h_dev + (i - 1), s));
+            EW_HIP_TRY(launch_mgs_link(w, u[i - 1], vnext, ws.N, pin, pout, hd + (i - 1), s));
         }
         const double* plast = (nu % 2 == 1) ? P1 : P0;
-        EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, plast, ws.h_dev + nu, s));
+        EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, plast, hd + nu, s));
     }
-    EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-    EW_HIP_TRY(hipStreamSynchronize(s));
+    return EW_OK;
+}
+
+static ew_status fetch_coeff(Workspace& ws, int nu, std::vector<double>& coeff) {
+    EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, ws.stream));
+    EW_HIP_TRY(hipStreamSynchronize(ws.stream));
     coeff.assign(ws.h_host, ws.h_host + nu + 1);
     for (double v : coeff)
         if (!std::isfinite(v)) return fail(EW_ERR_NONFINITE, "non-finite value in Gram-Schmidt");
     return EW_OK;
 }
 
+ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const double*>& u, std::vector<double>& coeff) {
+    EW_TRY(mgs_chain(ws, w, u, ws.h_dev));
+    return fetch_coeff(ws, (int)u.size(), coeff);
+}
+
 ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, const double* u2, int n2,
-                         std::vector<double>& coeff) {
+                         std::vector<double>& coeff, double* coeff_dev) {
     const int nu = n1 + n2;
+    double* hd = coeff_dev ? coeff_dev : ws.h_dev;
     if (ws.N <= kMgsSmallMax && nu <= kMgsMaxCols) {
         // short vectors, short basis: the whole modified Gram-Schmidt in one workgroup
-        EW_HIP_TRY(launch_mgs_small(u1, n1, u2, n2, w, ws.N, ws.h_dev, ws.stream));
-        EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, ws.stream));
-        EW_HIP_TRY(hipStreamSynchronize(ws.stream));
-        coeff.assign(ws.h_host, ws.h_host + nu + 1);
-        for (double v : coeff)
-            if (!std::isfinite(v)) return fail(EW_ERR_NONFINITE, "non-finite value in Gram-Schmidt");
-        return EW_OK;
-    }
-    if (nu <= kMgsMaxCols) {
+        EW_HIP_TRY(launch_mgs_small(u1, n1, u2, n2, w, ws.N, hd, ws.stream));
+    } else if (nu <= kMgsMaxCols) {
         std::vector<const double*> u;
         u.reserve(nu);
         for (int i = 0; i < n1; ++i) u.push_back(u1 + (int64_t)i * ws.N);
         for (int i = 0; i < n2; ++i) u.push_back(u2 + (int64_t)i * ws.N);
-        return mgs_orthonormalize(ws, w, u, coeff);
+        EW_TRY(mgs_chain(ws, w, u, hd));
+    } else {
+        if (nu > ws.nu_max) return fail(EW_ERR_INVALID_ARG, "orthogonalisation basis exceeds the workspace");
+        EW_TRY(ws.setup_block_gs());
+        hipStream_t s = ws.stream;
+        const BlockGsPlan plan = block_gs_plan(ws.N, nu);
+        // CGS2: two passes, coefficients summed into hd[0:nu]
+        for (int pass = 0; pass < 2; ++pass)
+            EW_HIP_TRY(launch_block_gs_pass(u1, n1, u2, n2, w, ws.N, plan, ws.gs_partial, ws.h_cur, hd, pass,
+                                            ws.gs_tmp, s));
+        EW_HIP_TRY(launch_dot_partial(w, w, ws.N, ws.P, s));
+        EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, ws.P, hd + nu, s));
     }
-    if (nu > ws.nu_max) return fail(EW_ERR_INVALID_ARG, "orthogonalisation basis exceeds the workspace");
-    EW_TRY(ws.setup_block_gs());
-    hipStream_t s = ws.stream;
-    const BlockGsPlan plan = block_gs_plan(ws.N, nu);
-    // CGS2: two passes, coefficients summed into h_dev[0:nu]
-    for (int pass = 0; pass < 2; ++pass)
-        EW_HIP_TRY(launch_block_gs_pass(u1, n1, u2, n2, w, ws.N, plan, ws.gs_partial, ws.h_cur, ws.h_dev, pass,
-                                        ws.gs_tmp, s));
-    EW_HIP_TRY(launch_dot_partial(w, w, ws.N, ws.P, s));
-    EW_HIP_TRY(launch_normalize_from_partial(w, w, ws.N, ws.P, ws.h_dev + nu, s));
-    EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.h_dev, (nu + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-    EW_HIP_TRY(hipStreamSynchronize(s));
-    coeff.assign(ws.h_host, ws.h_host + nu + 1);
-    for (double v : coeff)
-        if (!std::isfinite(v)) return fail(EW_ERR_NONFINITE, "non-finite value in Gram-Schmidt");
-    return EW_OK;
+    if (coeff_dev) return EW_OK;
+    return fetch_coeff(ws, nu, coeff);
 }
 
 // Y[:, 0:ncols] = X[:, 0:nx] Qm[0:nx, 0:ncols] (Qm row-major nx x qcols).
@@ -210,36 +212,101 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
     // normalise the start vector against the locked set
     EW_TRY(orthonormalize(ws, ws.col(ws.V, 0), ws.Y, nl, nullptr, 0, coeff));
     if (!(coeff.back() > 0.0)) return fail(EW_ERR_NONFINITE, "start vector lies in the locked space");
+    // probe runs test for convergence after the steps that reach these basis sizes
+    auto probe_check_at = [&](int s) {
+        return probe > 0 && s < m && s >= kProbeFirstCheck && (s & (s - 1)) == 0;
+    };
+    auto budget_hit = [&]() {
+        // Budget reached inside a cycle: report no converged pairs.
+        out.theta.clear();
+        out.conv.clear();
+        out.Q = Mat(m, m);
+    };
+    // One Arnoldi step j with the coefficients read back at once; a breakdown
+    // (the Krylov space is invariant) continues from a fresh random direction
+    // orthogonal to everything so far.
+    auto sync_step = [&](int j) -> ew_status {
+        double* w = ws.col(ws.V, j + 1);
+        EW_TRY(apply_S_sym(ws, ws.col(ws.V, j), w));
+        ++wave_solves;
+        EW_TRY(orthonormalize(ws, w, ws.Y, nl, ws.V, j + 1, coeff));
+        double hsq = 0.0;
+        for (int i = 0; i <= j; ++i) {
+            T(i, j) = coeff[nl + i];
+            hsq += coeff[nl + i] * coeff[nl + i];
+        }
+        double nrm = coeff.back();
+        if (!(nrm > 1e-12 * std::sqrt(hsq + nrm * nrm))) {
+            EW_HIP_TRY(launch_splitmix_uniform(w, ws.N, seed_base + 0x100000ULL + (uint64_t)wave_solves, op->stream));
+            EW_TRY(orthonormalize(ws, w, ws.Y, nl, ws.V, j + 1, coeff));
+            nrm = 0.0;
+        }
+        T(j + 1, j) = nrm;
+        return EW_OK;
+    };
     int p = 0;
     for (;;) {
-        for (int j = p; j < m; ++j) {
-            double* w = ws.col(ws.V, j + 1);
+        int j = p;
+        while (j < m) {
             if (wave_solves >= ws_budget) {
-                // Budget reached inside a cycle: report no converged pairs.
-                out.theta.clear();
-                out.conv.clear();
-                out.Q = Mat(m, m);
+                budget_hit();
                 return EW_OK;
             }
-            EW_TRY(apply_S_sym(ws, ws.col(ws.V, j), w));
-            ++wave_solves;
-            EW_TRY(orthonormalize(ws, w, ws.Y, nl, ws.V, j + 1, coeff));
-            double hsq = 0.0;
-            for (int i = 0; i <= j; ++i) {
-                T(i, j) = coeff[nl + i];
-                hsq += coeff[nl + i] * coeff[nl + i];
+            int jend = j + 1;  // steps j .. jend-1 run before the host looks at their coefficients
+            if (ws.hcols) {
+                jend = m;
+                for (int s = j + 1; s < m; ++s)
+                    if (probe_check_at(s)) {
+                        jend = s;
+                        break;
+                    }
+                jend = (int)std::min<int64_t>(jend, j + (ws_budget - wave_solves));
             }
-            double nrm = coeff.back();
-            if (!(nrm > 1e-12 * std::sqrt(hsq + nrm * nrm))) {
-                // Breakdown: the Krylov space is invariant.  Continue from a
-                // fresh random direction orthogonal to everything so far.
-                EW_HIP_TRY(launch_splitmix_uniform(w, ws.N, seed_base + 0x100000ULL + (uint64_t)wave_solves, op->stream));
-                EW_TRY(orthonormalize(ws, w, ws.Y, nl, ws.V, j + 1, coeff));
-                nrm = 0.0;
+            if (!ws.hcols || jend == j + 1) {
+                EW_TRY(sync_step(j));
+                ++j;
+            } else {
+                // Steps queued back to back: each leaves its coefficients in its
+                // own column of ws.hcols, read once at the end of the run.
+                for (int jj = j; jj < jend; ++jj) {
+                    EW_TRY(apply_S_sym(ws, ws.col(ws.V, jj), ws.col(ws.V, jj + 1)));
+                    ++wave_solves;
+                    EW_TRY(orthonormalize(ws, ws.col(ws.V, jj + 1), ws.Y, nl, ws.V, jj + 1, coeff,
+                                          ws.hcols + (size_t)(jj - j) * ws.hcols_ld));
+                }
+                EW_HIP_TRY(hipMemcpyAsync(ws.hcols_host, ws.hcols, (size_t)(jend - j) * ws.hcols_ld * sizeof(double),
+                                          hipMemcpyDeviceToHost, op->stream));
+                EW_HIP_TRY(hipStreamSynchronize(op->stream));
+                // the first step with a non-finite coefficient or a breakdown (later
+                // columns may carry what it spread) is redone on the host path
+                int broke = -1;
+                for (int jj = j; jj < jend && broke < 0; ++jj) {
+                    const double* c = ws.hcols_host + (size_t)(jj - j) * ws.hcols_ld;
+                    const int nu = nl + jj + 1;
+                    for (int i = 0; i <= nu && broke < 0; ++i)
+                        if (!std::isfinite(c[i])) broke = jj;
+                    if (broke >= 0) break;
+                    double hsq = 0.0;
+                    for (int i = 0; i <= jj; ++i) {
+                        T(i, jj) = c[nl + i];
+                        hsq += c[nl + i] * c[nl + i];
+                    }
+                    const double nrm = c[nu];
+                    if (!(nrm > 1e-12 * std::sqrt(hsq + nrm * nrm))) broke = jj;
+                    else T(jj + 1, jj) = nrm;
+                }
+                if (broke < 0) {
+                    j = jend;
+                } else {
+                    // same inputs as before (the basis up to column broke is
+                    // unchanged); a non-finite value there is reported as such
+                    EW_TRY(sync_step(broke));
+                    j = broke + 1;
+                    continue;
+                }
             }
-            T(j + 1, j) = nrm;
-            const int s = j + 1;
-            if (probe > 0 && s < m && s >= kProbeFirstCheck && (s & (s - 1)) == 0) {
+            const int s = j;
+            if (probe_check_at(s)) {
                 ritz(s);
                 if (stop_rule(s)) return EW_OK;
             }

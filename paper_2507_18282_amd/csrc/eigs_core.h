@@ -12,6 +12,7 @@ namespace ew {
 struct Op;
 
 constexpr int kGramBlocks = 256;
+constexpr size_t kHcolsMaxDoubles = (size_t)1 << 20;
 
 // Device workspace of one eigenproblem.
 struct Workspace {
@@ -34,6 +35,9 @@ struct Workspace {
     double* q_dev = nullptr;   // small matrices for basis rotations
     double* gram_dev = nullptr;
     double* h_host = nullptr;
+    double* hcols = nullptr;       // Gram-Schmidt coefficient columns of steps run without a round trip
+    double* hcols_host = nullptr;  // (pinned) host copy of them
+    int hcols_ld = 0;              // leading dimension (nu_max + 2)
     double* wtmp = nullptr;    // one vector for the weighted coordinates (Neumann walls, mapped grids)
     const double* wsq = nullptr;   // mapped grid: sqrt(J) and 1/sqrt(J) (the weights are J)
     const double* wisq = nullptr;
@@ -42,6 +46,7 @@ struct Workspace {
     ~Workspace() {
         for (void* p : owned) hipFree(p);
         if (h_host) hipHostFree(h_host);
+        if (hcols_host) hipHostFree(hcols_host);
     }
     ew_status alloc(double** p, size_t count) {
         hipError_t e = hipMalloc((void**)p, count * sizeof(double) + 256);
@@ -70,6 +75,14 @@ struct Workspace {
         EW_TRY(alloc(&gram_dev, (size_t)kGramBlocks * 32 * 32));
         if (g.wall || wsq) EW_TRY(alloc(&wtmp, (size_t)N));
         EW_HIP_TRY(hipHostMalloc((void**)&h_host, hlen * sizeof(double), hipHostMallocDefault));
+        // Arnoldi steps queue their coefficients on the device and the host reads
+        // a whole run of columns at once, when that buffer is small
+        hcols_ld = nu_max + 2;
+        const size_t hc = (size_t)m * hcols_ld;
+        if (hc <= kHcolsMaxDoubles) {
+            EW_TRY(alloc(&hcols, hc));
+            EW_HIP_TRY(hipHostMalloc((void**)&hcols_host, hc * sizeof(double), hipHostMallocDefault));
+        }
         return EW_OK;
     }
     // Buffers of the block Gram-Schmidt, allocated at its first use.
@@ -89,10 +102,12 @@ ew_status mgs_orthonormalize(Workspace& ws, double* w, const std::vector<const d
 // The same against the columns of [U1 (n1 columns) | U2 (n2 columns)]: up to
 // kMgsMaxCols columns by MGS (in one workgroup for vectors of at most
 // kMgsSmallMax points, else by chained links), block CGS2 beyond.
-// Host-blocking.
+// Host-blocking; with coeff_dev != nullptr the n1 + n2 coefficients and the
+// norm are left in coeff_dev on the device instead (nothing waits, coeff is
+// untouched).
 constexpr int kMgsMaxCols = 64;
 ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, const double* u2, int n2,
-                         std::vector<double>& coeff);
+                         std::vector<double>& coeff, double* coeff_dev = nullptr);
 // out = W^{1/2} L_h W^{-1/2} in: the Laplacian in the eigensolver's
 // coordinates, W the Neumann-wall weights or J on a mapped grid (plain L_h
 // when there are none).  in and out may not alias.
