@@ -4,7 +4,11 @@
 // W^n lives in LDS with a zero frame of two cells (the Dirichlet wall and the
 // cells the order-4 stencil reaches beyond it), double-buffered so that a step
 // needs one barrier; W^{n-1}, the accumulator and the point coordinates stay
-// in registers.  All N_t steps run in one launch,
+// in registers.  With STRIP (order 2, Dirichlet walls, nx dividing the
+// thread count) a thread owns PTS consecutive points of one column, so the
+// vertical neighbours inside its strip come from registers and a step reads
+// LDS 10 instead of 16 times per thread: one workgroup is LDS-bandwidth
+// bound.  All N_t steps run in one launch,
 // so the grid never goes back to HBM between reading v and writing S v: on
 // grids of a few thousand points the per-step launches of the tiled leapfrog
 // are pure latency.
@@ -16,7 +20,7 @@ namespace {
 
 constexpr int kSmallThreads = 1024;
 
-template <typename T, int ORDER, int PTS>
+template <typename T, int ORDER, int PTS, bool STRIP>
 __global__ __launch_bounds__(kSmallThreads) void k_wave_small(const double* __restrict__ v, double* __restrict__ out,
                                                               Geo g, T dt2, const double* __restrict__ c, int n_t) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -33,10 +37,21 @@ __global__ __launch_bounds__(kSmallThreads) void k_wave_small(const double* __re
     const T c0 = (T)c[0];
 #pragma unroll
     for (int t = 0; t < PTS; ++t) {
-        const int q = tid + t * kSmallThreads;
+        int q, i, j;
+        if (STRIP) {
+            i = tid % nx;
+            j = (tid / nx) * PTS + t;
+            q = j < ny ? j * nx + i : n;
+        } else {
+            q = tid + t * kSmallThreads;
+            i = q % nx;
+            j = q / nx;
+        }
         lp[t] = -1;
+        cur[t] = T(0);  // a point beyond the grid reads as the wall's 0
+        prev[t] = T(0);
+        acc[t] = T(0);
         if (q < n) {
-            const int i = q % nx, j = q / nx;
             lij[t] = i | (j << 16);
             lp[t] = (j + 2) * px + i + 2;
             cur[t] = (T)v[q];
@@ -48,13 +63,19 @@ __global__ __launch_bounds__(kSmallThreads) void k_wave_small(const double* __re
     __syncthreads();
     for (int step = 0; step < n_t; ++step) {
         const T cn = (T)c[step + 1];
+        T nxt[PTS];
 #pragma unroll
         for (int t = 0; t < PTS; ++t) {
+            nxt[t] = cur[t];
             if (lp[t] < 0) continue;
             const int p = lp[t];
             const T uc = cur[t];
             T lap;
-            if (ORDER == 2 && g.wall == 0) {
+            if (STRIP) {
+                const T dn = t > 0 ? cur[t - 1] : Xs[p - px];
+                const T up = t < PTS - 1 ? cur[t + 1] : Xs[p + px];
+                lap = (Xs[p - 1] + Xs[p + 1] - T(2) * uc) * cx + (dn + up - T(2) * uc) * cy;
+            } else if (ORDER == 2 && g.wall == 0) {
                 lap = (Xs[p - 1] + Xs[p + 1] - T(2) * uc) * cx + (Xs[p - px] + Xs[p + px] - T(2) * uc) * cy;
             } else {
                 // wall closures (Dirichlet odd reflection, Neumann even
@@ -67,8 +88,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_wave_small(const double* __re
             acc[t] += cn * nw;
             Xn[p] = nw;
             prev[t] = uc;
-            cur[t] = nw;
+            nxt[t] = nw;
         }
+#pragma unroll
+        for (int t = 0; t < PTS; ++t) cur[t] = nxt[t];  // the strip's neighbours were read old
         __syncthreads();  // W^{n+1} complete; W^n no longer read
         T* sw = Xs;
         Xs = Xn;
@@ -76,8 +99,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_wave_small(const double* __re
     }
 #pragma unroll
     for (int t = 0; t < PTS; ++t) {
-        const int q = tid + t * kSmallThreads;
-        if (q < n) out[q] = (double)acc[t];
+        if (lp[t] < 0) continue;
+        const int i = lij[t] & 0xFFFF, j = lij[t] >> 16;
+        out[j * nx + i] = (double)acc[t];
     }
 }
 
@@ -86,15 +110,25 @@ constexpr int small_pts_max() {
     return 8;  // keeps the per-thread state within the 1024-thread register budget (no spills)
 }
 
+template <typename T, int ORDER, int PTS, bool STRIP>
+hipError_t launch_small_as(const double* v, double* out, const Geo& g, double dt2, const double* c, int n_t,
+                           hipStream_t s) {
+    const size_t lds = 2 * (size_t)(g.nx + 4) * (g.ny + 4) * sizeof(T);
+    const void* f = (const void*)k_wave_small<T, ORDER, PTS, STRIP>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_wave_small<T, ORDER, PTS, STRIP><<<1, kSmallThreads, lds, s>>>(v, out, g, (T)dt2, c, n_t);
+    return hipGetLastError();
+}
+
+// Strips of PTS rows per column when nx divides the thread count and the
+// strips cover every row (order 2, Dirichlet walls).
 template <typename T, int ORDER, int PTS>
 hipError_t launch_small(const double* v, double* out, const Geo& g, double dt2, const double* c, int n_t,
                         hipStream_t s) {
-    const size_t lds = 2 * (size_t)(g.nx + 4) * (g.ny + 4) * sizeof(T);
-    const void* f = (const void*)k_wave_small<T, ORDER, PTS>;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    k_wave_small<T, ORDER, PTS><<<1, kSmallThreads, lds, s>>>(v, out, g, (T)dt2, c, n_t);
-    return hipGetLastError();
+    if (ORDER == 2 && g.wall == 0 && kSmallThreads % g.nx == 0 && (int64_t)(kSmallThreads / g.nx) * PTS >= g.ny)
+        return launch_small_as<T, ORDER, PTS, ORDER == 2>(v, out, g, dt2, c, n_t, s);
+    return launch_small_as<T, ORDER, PTS, false>(v, out, g, dt2, c, n_t, s);
 }
 
 }  // namespace
