@@ -15,6 +15,7 @@
 // kernels in mg.hip: x_i + (b - M x)_i / M_ii with every neighbour taken from
 // the values before that half-sweep.
 #include <hip/hip_ext.h>
+#include <type_traits>
 
 #include "mg_tile.h"
 #include "stencil_dev.h"
@@ -98,10 +99,12 @@ __device__ __forceinline__ T d2_lds(const T* X, int p, int stride, int gi, int n
 
 // L_h at LDS cell p whose neighbours beyond a wall read 0: the wall closures
 // of d2_framed (Dirichlet odd reflection, Neumann even reflection).  WALLS =
-// false compiles the Dirichlet-only closure.
+// false compiles the Dirichlet-only closure, which `walls` = false (a tile
+// away from Neumann walls) also selects.
 template <typename T, int ORDER, int DIM, bool WALLS>
-__device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, int gj, int gk, const Geo& g, T uc) {
-    if (!WALLS) {
+__device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, int gj, int gk, const Geo& g, T uc,
+                                     bool walls = true) {
+    if (!WALLS || !walls) {
         T s = d2_lds<T, ORDER>(X, p, 1, gi, g.nx, uc) * axis_coef<T, ORDER>(g.ihx2);
         s += d2_lds<T, ORDER>(X, p, sy, gj, g.ny, uc) * axis_coef<T, ORDER>(g.ihy2);
         if (DIM == 3) s += d2_lds<T, ORDER>(X, p, sz, gk, g.nz, uc) * axis_coef<T, ORDER>(g.ihz2);
@@ -131,6 +134,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
     __shared__ T B[BX * BY * BZ];
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = (DIM == 3) ? blockIdx.z * TZ : 0;
+    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, z0, z0 + TZ, H);  // uniform per tile
 
     // Staging of x (tile + H, zero outside the domain) and b (tile + 1): every
     // global load of a thread is issued into registers before its first LDS
@@ -182,47 +186,58 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
     }
     __syncthreads();
 
-    // red half-sweep on tile + 1 layer: new values to registers first (order 4
-    // couples red points to red points), then into LDS
-    T rv[RED_ITERS];
-    int rp[RED_ITERS];
-#pragma unroll
-    for (int t = 0; t < RED_ITERS; ++t) {
-        rp[t] = -1;
-        const int q = tid + t * kTileThreads;
-        if (q >= NRED) continue;
-        const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
-        const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
-        if (gi < 0 || gi >= g.nx || gj < 0 || gj >= g.ny || gk < 0 || gk >= g.nz) continue;
-        if (((gi + gj + gk) & 1) != 0) continue;
-        const int p = (bx + H - 1) + LX * ((by + H - 1) + LY * ((DIM == 3) ? (bz + H - 1) : 0));
-        const T uc = X[p];
-        const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
-        const T r = B[q] - (uc - a * lap);
-        rv[t] = uc + r / mdiag_at<T, ORDER, DIM, WALLS>(gi, gj, gk, g, a);
-        rp[t] = p;
-    }
-    if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
-#pragma unroll
-    for (int t = 0; t < RED_ITERS; ++t)
-        if (rp[t] >= 0) X[rp[t]] = rv[t];
-    __syncthreads();
-
-    // black half-sweep on the tile, written straight to global memory
-    for (int q = tid; q < TX * TY * TZ; q += kTileThreads) {
-        const int tx = q % TX, ty = (q / TX) % TY, tz = q / (TX * TY);
-        const int gi = x0 + tx, gj = y0 + ty, gk = z0 + tz;
-        if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
-        const int p = (tx + H) + LX * ((ty + H) + LY * ((DIM == 3) ? (tz + H) : 0));
-        const T uc = X[p];
-        T out = uc;
-        if (((gi + gj + gk) & 1) == 1) {
-            const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc);
-            const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
-            const T r = B[qb] - (uc - a * lap);
-            out = uc + r / mdiag_at<T, ORDER, DIM, WALLS>(gi, gj, gk, g, a);
+    // tiles near a Neumann wall run the wall closures; all others the
+    // Dirichlet-only code (a uniform branch, taken once per tile)
+    auto phases = [&](auto wt) {
+        constexpr bool NW = decltype(wt)::value;
+        // red half-sweep on tile + 1 layer: new values to registers first (order 4
+        // couples red points to red points), then into LDS
+        T rv[RED_ITERS];
+        int rp[RED_ITERS];
+    #pragma unroll
+        for (int t = 0; t < RED_ITERS; ++t) {
+            rp[t] = -1;
+            const int q = tid + t * kTileThreads;
+            if (q >= NRED) continue;
+            const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
+            const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
+            if (gi < 0 || gi >= g.nx || gj < 0 || gj >= g.ny || gk < 0 || gk >= g.nz) continue;
+            if (((gi + gj + gk) & 1) != 0) continue;
+            const int p = (bx + H - 1) + LX * ((by + H - 1) + LY * ((DIM == 3) ? (bz + H - 1) : 0));
+            const T uc = X[p];
+            const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, NW);
+            const T r = B[q] - (uc - a * lap);
+            rv[t] = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, NW ? g.wall : 0);
+            rp[t] = p;
         }
-        xout[lin(g, gi, gj, gk)] = out;
+        if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
+    #pragma unroll
+        for (int t = 0; t < RED_ITERS; ++t)
+            if (rp[t] >= 0) X[rp[t]] = rv[t];
+        __syncthreads();
+
+        // black half-sweep on the tile, written straight to global memory
+        for (int q = tid; q < TX * TY * TZ; q += kTileThreads) {
+            const int tx = q % TX, ty = (q / TX) % TY, tz = q / (TX * TY);
+            const int gi = x0 + tx, gj = y0 + ty, gk = z0 + tz;
+            if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
+            const int p = (tx + H) + LX * ((ty + H) + LY * ((DIM == 3) ? (tz + H) : 0));
+            const T uc = X[p];
+            T out = uc;
+            if (((gi + gj + gk) & 1) == 1) {
+                const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, NW);
+                const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
+                const T r = B[qb] - (uc - a * lap);
+                out = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, NW ? g.wall : 0);
+            }
+            xout[lin(g, gi, gj, gk)] = out;
+        }
+    };
+    if constexpr (WALLS) {
+        if (nw) phases(std::true_type{});
+        else phases(std::false_type{});
+    } else {
+        phases(std::false_type{});
     }
 }
 
@@ -245,6 +260,8 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
     const int sx = (WALLS && (gf.wall & 1)) ? -1 : 0, sy = (WALLS && (gf.wall & 4)) ? -1 : 0;
     const int sz = (WALLS && DIM == 3 && (gf.wall & 16)) ? -1 : 0;
     const int fx0 = 2 * cx0 + sx, fy0 = 2 * cy0 + sy, fz0 = (DIM == 3) ? 2 * cz0 + sz : 0;
+    // the region and its stencil reach: fine points [f0 - R, f0 + F + R) per direction
+    const bool nw = WALLS && near_neumann(gf, fx0, fx0 + FX, fy0, fy0 + FY, fz0, fz0 + FZ, R);  // uniform per tile
     // Staging as in the sweep: x (region + R) and b (region) go to registers
     // with every load issued before the first use.
     constexpr int NX = LX * LY * LZ, NF = FX * FY * FZ;
@@ -280,22 +297,31 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         if (q < NX) X[q] = xv[t];
     }
     __syncthreads();
+    auto residuals = [&](auto wt) {
+        constexpr bool NW = decltype(wt)::value;  // near a Neumann wall (as in k_sweep_tile)
 #pragma unroll
-    for (int t = 0; t < IF; ++t) {
-        const int q = tid + t * kTileThreads;
-        if (q >= NF) continue;
-        const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
-        const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
-        T r = T(0);
-        if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz) {
-            const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
-            const T uc = X[p];
-            r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, gf, uc));
+        for (int t = 0; t < IF; ++t) {
+            const int q = tid + t * kTileThreads;
+            if (q >= NF) continue;
+            const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
+            const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
+            T r = T(0);
+            if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz) {
+                const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
+                const T uc = X[p];
+                r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, gf, uc, NW));
+            }
+            Rf[q] = r;
         }
-        Rf[q] = r;
+    };
+    if constexpr (WALLS) {
+        if (nw) residuals(std::true_type{});
+        else residuals(std::false_type{});
+    } else {
+        residuals(std::false_type{});
     }
     __syncthreads();
-    if (WALLS) {
+    if (nw) {
         // region cells beyond a Neumann wall take the residual of their even
         // mirror inside the box (only in-range cells are read here)
         for (int q = tid; q < NF; q += kTileThreads) {

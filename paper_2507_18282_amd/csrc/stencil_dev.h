@@ -102,6 +102,16 @@ __device__ __forceinline__ T ldiag_axis(int i, int n, int w = 0) {
     return d;
 }
 
+// True when the box [x0 - h, x1 + h) x [y0 - h, y1 + h) x [z0 - h, z1 + h)
+// comes within two points of a Neumann wall: only tiles that do need the
+// wall closures; every other tile of a box with Neumann walls runs the
+// Dirichlet-only code, which is exact away from those walls.
+__device__ __forceinline__ bool near_neumann(const Geo& g, int x0, int x1, int y0, int y1, int z0, int z1, int h) {
+    return ((g.wall & 1) && x0 - h <= 1) || ((g.wall & 2) && x1 + h >= g.nx - 2) ||
+           ((g.wall & 4) && y0 - h <= 1) || ((g.wall & 8) && y1 + h >= g.ny - 2) ||
+           ((g.wall & 16) && z0 - h <= 1) || ((g.wall & 32) && z1 + h >= g.nz - 2);
+}
+
 // Diagonal of M = I - a L_h at (i, j, k) for the wall bits `wall` (Geo::wall
 // layout); kernels compiled for Dirichlet-only boxes pass a literal 0 so that
 // the Neumann cases fold away.
