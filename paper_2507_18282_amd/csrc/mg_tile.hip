@@ -186,58 +186,47 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
     }
     __syncthreads();
 
-    // tiles near a Neumann wall run the wall closures; all others the
-    // Dirichlet-only code (a uniform branch, taken once per tile)
-    auto phases = [&](auto wt) {
-        constexpr bool NW = decltype(wt)::value;
-        // red half-sweep on tile + 1 layer: new values to registers first (order 4
-        // couples red points to red points), then into LDS
-        T rv[RED_ITERS];
-        int rp[RED_ITERS];
-    #pragma unroll
-        for (int t = 0; t < RED_ITERS; ++t) {
-            rp[t] = -1;
-            const int q = tid + t * kTileThreads;
-            if (q >= NRED) continue;
-            const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
-            const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
-            if (gi < 0 || gi >= g.nx || gj < 0 || gj >= g.ny || gk < 0 || gk >= g.nz) continue;
-            if (((gi + gj + gk) & 1) != 0) continue;
-            const int p = (bx + H - 1) + LX * ((by + H - 1) + LY * ((DIM == 3) ? (bz + H - 1) : 0));
-            const T uc = X[p];
-            const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, NW);
-            const T r = B[q] - (uc - a * lap);
-            rv[t] = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, NW ? g.wall : 0);
-            rp[t] = p;
-        }
-        if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
-    #pragma unroll
-        for (int t = 0; t < RED_ITERS; ++t)
-            if (rp[t] >= 0) X[rp[t]] = rv[t];
-        __syncthreads();
+    // red half-sweep on tile + 1 layer: new values to registers first (order 4
+    // couples red points to red points), then into LDS
+    T rv[RED_ITERS];
+    int rp[RED_ITERS];
+#pragma unroll
+    for (int t = 0; t < RED_ITERS; ++t) {
+        rp[t] = -1;
+        const int q = tid + t * kTileThreads;
+        if (q >= NRED) continue;
+        const int bx = q % BX, by = (q / BX) % BY, bz = q / (BX * BY);
+        const int gi = x0 - 1 + bx, gj = y0 - 1 + by, gk = (DIM == 3) ? z0 - 1 + bz : 0;
+        if (gi < 0 || gi >= g.nx || gj < 0 || gj >= g.ny || gk < 0 || gk >= g.nz) continue;
+        if (((gi + gj + gk) & 1) != 0) continue;
+        const int p = (bx + H - 1) + LX * ((by + H - 1) + LY * ((DIM == 3) ? (bz + H - 1) : 0));
+        const T uc = X[p];
+        const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw);
+        const T r = B[q] - (uc - a * lap);
+        rv[t] = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
+        rp[t] = p;
+    }
+    if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
+#pragma unroll
+    for (int t = 0; t < RED_ITERS; ++t)
+        if (rp[t] >= 0) X[rp[t]] = rv[t];
+    __syncthreads();
 
-        // black half-sweep on the tile, written straight to global memory
-        for (int q = tid; q < TX * TY * TZ; q += kTileThreads) {
-            const int tx = q % TX, ty = (q / TX) % TY, tz = q / (TX * TY);
-            const int gi = x0 + tx, gj = y0 + ty, gk = z0 + tz;
-            if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
-            const int p = (tx + H) + LX * ((ty + H) + LY * ((DIM == 3) ? (tz + H) : 0));
-            const T uc = X[p];
-            T out = uc;
-            if (((gi + gj + gk) & 1) == 1) {
-                const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, NW);
-                const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
-                const T r = B[qb] - (uc - a * lap);
-                out = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, NW ? g.wall : 0);
-            }
-            xout[lin(g, gi, gj, gk)] = out;
+    // black half-sweep on the tile, written straight to global memory
+    for (int q = tid; q < TX * TY * TZ; q += kTileThreads) {
+        const int tx = q % TX, ty = (q / TX) % TY, tz = q / (TX * TY);
+        const int gi = x0 + tx, gj = y0 + ty, gk = z0 + tz;
+        if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
+        const int p = (tx + H) + LX * ((ty + H) + LY * ((DIM == 3) ? (tz + H) : 0));
+        const T uc = X[p];
+        T out = uc;
+        if (((gi + gj + gk) & 1) == 1) {
+            const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw);
+            const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
+            const T r = B[qb] - (uc - a * lap);
+            out = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
         }
-    };
-    if constexpr (WALLS) {
-        if (nw) phases(std::true_type{});
-        else phases(std::false_type{});
-    } else {
-        phases(std::false_type{});
+        xout[lin(g, gi, gj, gk)] = out;
     }
 }
 
@@ -297,28 +286,19 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         if (q < NX) X[q] = xv[t];
     }
     __syncthreads();
-    auto residuals = [&](auto wt) {
-        constexpr bool NW = decltype(wt)::value;  // near a Neumann wall (as in k_sweep_tile)
 #pragma unroll
-        for (int t = 0; t < IF; ++t) {
-            const int q = tid + t * kTileThreads;
-            if (q >= NF) continue;
-            const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
-            const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
-            T r = T(0);
-            if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz) {
-                const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
-                const T uc = X[p];
-                r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, gf, uc, NW));
-            }
-            Rf[q] = r;
+    for (int t = 0; t < IF; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q >= NF) continue;
+        const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
+        const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
+        T r = T(0);
+        if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz) {
+            const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
+            const T uc = X[p];
+            r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, gf, uc, nw));
         }
-    };
-    if constexpr (WALLS) {
-        if (nw) residuals(std::true_type{});
-        else residuals(std::false_type{});
-    } else {
-        residuals(std::false_type{});
+        Rf[q] = r;
     }
     __syncthreads();
     if (nw) {

@@ -22,6 +22,98 @@ constexpr int kTileThreads = 256;
 // the constant interior diagonal; points whose diagonal carries an order-4
 // ghost divide.
 // ---------------------------------------------------------------------------
+// The relaxation phases of k_sweep_tile2d after staging (x in X with a halo
+// of H, b in B with a halo of 1): red on the tile plus one layer, then black
+// on the tile written out with the red points beside it.  NW selects the
+// Neumann-wall closures.
+template <typename T, int ORDER, int TY, bool NW>
+__device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
+                                                    T inv_diag, T* __restrict__ xout) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 1;
+    constexpr int LX = TX + 2 * H;
+    constexpr int BX = TX + 2, BY = TY + 2;
+    const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
+    // relaxed value at LDS cell (lx, ly) = global (gi, gj)
+    auto relax = [&](int lx, int ly, int gi, int gj, T bval) -> T {
+        const int p = ly * LX + lx;
+        const T uc = X[p];
+        T dx, dy;
+        if (NW) {
+            // Neumann walls: the even-reflection closure replaces the zero halo
+            dx = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3);
+            dy = d2_framed<T, ORDER>(X, p, LX, gj, g.ny, uc, (g.wall >> 2) & 3);
+        } else if (ORDER == 2) {
+            dx = X[p - 1] + X[p + 1] - T(2) * uc;
+            dy = X[p - LX] + X[p + LX] - T(2) * uc;
+        } else {
+            const T l2 = (gi == 0) ? -uc : X[p - 2];
+            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
+            dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
+        }
+        const T r = bval - (uc - a * (dx * cxc + dy * cyc));
+        // the diagonal differs from the interior one where a ghost refers back to
+        // the point: at a Dirichlet wall point, one point inside a Neumann wall
+        const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
+                                            : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
+        return edge ? uc + r / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
+    };
+
+    const int rowsel = tid >> 5;  // 8 rows per pass, 32 lanes per row
+    const int m = tid & 31;
+    // red half-sweep on tile rows -1..TY, tile columns 0..63 (one red point per lane) ...
+    constexpr int NRP = (BY + 7) / 8;
+    T rv[NRP + 1];
+    int rp[NRP + 1];
+#pragma unroll
+    for (int t = 0; t < NRP; ++t) {
+        rp[t] = -1;
+        const int by = rowsel + 8 * t;
+        if (by >= BY) continue;
+        const int gj = y0 - 1 + by;
+        const int c = 2 * m + (gj & 1);  // tile column of the red point (x0 is even)
+        const int gi = x0 + c;
+        if (gj < 0 || gj >= g.ny || gi >= g.nx) continue;
+        rv[t] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
+        rp[t] = (by + H - 1) * LX + c + H;
+    }
+    // ... plus the red point of each row in tile column -1 or 64
+    rp[NRP] = -1;
+    if (tid < BY) {
+        const int by = tid, gj = y0 - 1 + by;
+        const int c = (gj & 1) ? -1 : 64;
+        const int gi = x0 + c;
+        if (gj >= 0 && gj < g.ny && gi >= 0 && gi < g.nx) {
+            rv[NRP] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
+            rp[NRP] = (by + H - 1) * LX + c + H;
+        }
+    }
+    // order 4 reads red neighbours (old values) that other lanes overwrite;
+    // order 2 reads each red point only in the lane that updates it
+    if (ORDER == 4) __syncthreads();
+#pragma unroll
+    for (int t = 0; t <= NRP; ++t)
+        if (rp[t] >= 0) X[rp[t]] = rv[t];
+    __syncthreads();
+
+    // black half-sweep on the tile; each lane writes its black point and the
+    // red point beside it
+#pragma unroll
+    for (int t = 0; t < TY / 8; ++t) {
+        const int ty = rowsel + 8 * t;
+        const int gj = y0 + ty;
+        if (gj >= g.ny) continue;
+        const int cb = 2 * m + 1 - (gj & 1), cr = 2 * m + (gj & 1);
+        const int gib = x0 + cb, gir = x0 + cr;
+        T* row = xout + (int64_t)gj * g.nx;
+        if (gib < g.nx) row[gib] = relax(cb + H, ty + H, gib, gj, B[(ty + 1) * BX + cb + 1]);
+        if (gir < g.nx) row[gir] = X[(ty + H) * LX + cr + H];
+    }
+}
+
 template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restrict__ xin, const T* __restrict__ xc,
                                                                const T* __restrict__ b, T bscale, T* __restrict__ xout,
@@ -121,93 +213,11 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
 
     // tiles near a Neumann wall run the wall closures; all others the
     // Dirichlet-only code (a uniform branch, taken once per tile)
-    auto phases = [&](auto wt) {
-        constexpr bool NW = decltype(wt)::value;
-        const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
-        // relaxed value at LDS cell (lx, ly) = global (gi, gj)
-        auto relax = [&](int lx, int ly, int gi, int gj, T bval) -> T {
-            const int p = ly * LX + lx;
-            const T uc = X[p];
-            T dx, dy;
-            if (NW) {
-                // Neumann walls: the even-reflection closure replaces the zero halo
-                dx = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3);
-                dy = d2_framed<T, ORDER>(X, p, LX, gj, g.ny, uc, (g.wall >> 2) & 3);
-            } else if (ORDER == 2) {
-                dx = X[p - 1] + X[p + 1] - T(2) * uc;
-                dy = X[p - LX] + X[p + LX] - T(2) * uc;
-            } else {
-                const T l2 = (gi == 0) ? -uc : X[p - 2];
-                const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
-                const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
-                const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
-                dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
-                dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
-            }
-            const T r = bval - (uc - a * (dx * cxc + dy * cyc));
-            // the diagonal differs from the interior one where a ghost refers back to
-            // the point: at a Dirichlet wall point, one point inside a Neumann wall
-            const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
-                                                : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
-            return edge ? uc + r / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
-        };
-
-        const int rowsel = tid >> 5;  // 8 rows per pass, 32 lanes per row
-        const int m = tid & 31;
-        // red half-sweep on tile rows -1..TY, tile columns 0..63 (one red point per lane) ...
-        constexpr int NRP = (BY + 7) / 8;
-        T rv[NRP + 1];
-        int rp[NRP + 1];
-    #pragma unroll
-        for (int t = 0; t < NRP; ++t) {
-            rp[t] = -1;
-            const int by = rowsel + 8 * t;
-            if (by >= BY) continue;
-            const int gj = y0 - 1 + by;
-            const int c = 2 * m + (gj & 1);  // tile column of the red point (x0 is even)
-            const int gi = x0 + c;
-            if (gj < 0 || gj >= g.ny || gi >= g.nx) continue;
-            rv[t] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
-            rp[t] = (by + H - 1) * LX + c + H;
-        }
-        // ... plus the red point of each row in tile column -1 or 64
-        rp[NRP] = -1;
-        if (tid < BY) {
-            const int by = tid, gj = y0 - 1 + by;
-            const int c = (gj & 1) ? -1 : 64;
-            const int gi = x0 + c;
-            if (gj >= 0 && gj < g.ny && gi >= 0 && gi < g.nx) {
-                rv[NRP] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
-                rp[NRP] = (by + H - 1) * LX + c + H;
-            }
-        }
-        // order 4 reads red neighbours (old values) that other lanes overwrite;
-        // order 2 reads each red point only in the lane that updates it
-        if (ORDER == 4) __syncthreads();
-    #pragma unroll
-        for (int t = 0; t <= NRP; ++t)
-            if (rp[t] >= 0) X[rp[t]] = rv[t];
-        __syncthreads();
-
-        // black half-sweep on the tile; each lane writes its black point and the
-        // red point beside it
-    #pragma unroll
-        for (int t = 0; t < TY / 8; ++t) {
-            const int ty = rowsel + 8 * t;
-            const int gj = y0 + ty;
-            if (gj >= g.ny) continue;
-            const int cb = 2 * m + 1 - (gj & 1), cr = 2 * m + (gj & 1);
-            const int gib = x0 + cb, gir = x0 + cr;
-            T* row = xout + (int64_t)gj * g.nx;
-            if (gib < g.nx) row[gib] = relax(cb + H, ty + H, gib, gj, B[(ty + 1) * BX + cb + 1]);
-            if (gir < g.nx) row[gir] = X[(ty + H) * LX + cr + H];
-        }
-    };
     if constexpr (WALLS) {
-        if (nw) phases(std::true_type{});
-        else phases(std::false_type{});
+        if (nw) sweep_tile2d_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, xout);
+        else sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
     } else {
-        phases(std::false_type{});
+        sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
     }
 }
 
@@ -223,6 +233,88 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
 // sweeps and saves one launch per level.  (A layout with one LDS array per
 // colour, which makes the lanes' LDS reads contiguous, measured slower.)
 // ---------------------------------------------------------------------------
+// The relaxation phases of k_sweep2x_tile2d after staging (x in X with a
+// halo of R + 3, b in B with a halo of 3).  NW selects the Neumann-wall
+// closures.
+template <typename T, int ORDER, int TY, bool NW>
+__device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
+                                               T inv_diag, T* __restrict__ xout) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 3;
+    constexpr int LX = TX + 2 * H;
+    constexpr int BH = 3, BX = TX + 2 * BH;
+    const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
+    // relaxed value of global point (gi, gj) from the values now in LDS
+    auto relax = [&](int gi, int gj) -> T {
+        const int p = (gj - y0 + H) * LX + (gi - x0 + H);
+        const T bval = B[(gj - y0 + BH) * BX + (gi - x0 + BH)];
+        const T uc = X[p];
+        T dx, dy;
+        if (NW) {
+            dx = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3);
+            dy = d2_framed<T, ORDER>(X, p, LX, gj, g.ny, uc, (g.wall >> 2) & 3);
+        } else if (ORDER == 2) {
+            dx = X[p - 1] + X[p + 1] - T(2) * uc;
+            dy = X[p - LX] + X[p + LX] - T(2) * uc;
+        } else {
+            const T l2 = (gi == 0) ? -uc : X[p - 2];
+            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
+            dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
+        }
+        const T r = bval - (uc - a * (dx * cxc + dy * cyc));
+        const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
+                                            : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
+        return edge ? uc + r / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
+    };
+    // one half-sweep of colour `colour` on the tile plus K layers: new values to
+    // registers (same-colour neighbours must be read old), then into LDS
+    auto half = [&](auto kc, int colour) {
+        constexpr int K = decltype(kc)::value;
+        constexpr int W2 = (TX + 2 * K) / 2, NR = TY + 2 * K, NP = NR * W2;
+        constexpr int IT = (NP + kTileThreads - 1) / kTileThreads;
+        T rv[IT];
+        int rp[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            rp[t] = -1;
+            const int idx = tid + t * kTileThreads;
+            if (idx >= NP) continue;
+            const int r = idx / W2, k2 = idx - r * W2;
+            const int gj = y0 - K + r;
+            const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
+            if (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx) continue;
+            rv[t] = relax(gi, gj);
+            rp[t] = (gj - y0 + H) * LX + (gi - x0 + H);
+        }
+        if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
+#pragma unroll
+        for (int t = 0; t < IT; ++t)
+            if (rp[t] >= 0) X[rp[t]] = rv[t];
+        __syncthreads();
+    };
+    half(std::integral_constant<int, 3>{}, 0);  // red, first sweep
+    half(std::integral_constant<int, 2>{}, 1);  // black, first sweep
+    half(std::integral_constant<int, 1>{}, 0);  // red, second sweep
+    // black of the second sweep on the tile, written out with the red point of
+    // the same pair of columns
+    constexpr int NP = TY * (TX / 2), IT = (NP + kTileThreads - 1) / kTileThreads;
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const int idx = tid + t * kTileThreads;
+        if (idx >= NP) continue;
+        const int r = idx / (TX / 2), k2 = idx - r * (TX / 2);
+        const int gj = y0 + r;
+        const int gib = x0 + ((1 + gj) & 1) + 2 * k2, gir = gib ^ 1;
+        if (gj >= g.ny) continue;
+        T* row = xout + (int64_t)gj * g.nx;
+        if (gib < g.nx) row[gib] = relax(gib, gj);
+        if (gir < g.nx) row[gir] = X[(gj - y0 + H) * LX + (gir - x0 + H)];
+    }
+}
+
 template <typename T, int ORDER, int TY, bool ZERO_IN, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __restrict__ xin, const T* __restrict__ b,
                                                                  T bscale, T* __restrict__ xout, Geo g, T a,
@@ -275,84 +367,11 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
     }
     __syncthreads();
 
-    auto phases = [&](auto wt) {
-        constexpr bool NW = decltype(wt)::value;  // near a Neumann wall (see k_sweep_tile2d)
-        const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
-        // relaxed value of global point (gi, gj) from the values now in LDS
-        auto relax = [&](int gi, int gj) -> T {
-            const int p = (gj - y0 + H) * LX + (gi - x0 + H);
-            const T bval = B[(gj - y0 + BH) * BX + (gi - x0 + BH)];
-            const T uc = X[p];
-            T dx, dy;
-            if (NW) {
-                dx = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3);
-                dy = d2_framed<T, ORDER>(X, p, LX, gj, g.ny, uc, (g.wall >> 2) & 3);
-            } else if (ORDER == 2) {
-                dx = X[p - 1] + X[p + 1] - T(2) * uc;
-                dy = X[p - LX] + X[p + LX] - T(2) * uc;
-            } else {
-                const T l2 = (gi == 0) ? -uc : X[p - 2];
-                const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
-                const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
-                const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
-                dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
-                dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
-            }
-            const T r = bval - (uc - a * (dx * cxc + dy * cyc));
-            const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
-                                                : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
-            return edge ? uc + r / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
-        };
-        // one half-sweep of colour `colour` on the tile plus K layers: new values to
-        // registers (same-colour neighbours must be read old), then into LDS
-        auto half = [&](auto kc, int colour) {
-            constexpr int K = decltype(kc)::value;
-            constexpr int W2 = (TX + 2 * K) / 2, NR = TY + 2 * K, NP = NR * W2;
-            constexpr int IT = (NP + kTileThreads - 1) / kTileThreads;
-            T rv[IT];
-            int rp[IT];
-    #pragma unroll
-            for (int t = 0; t < IT; ++t) {
-                rp[t] = -1;
-                const int idx = tid + t * kTileThreads;
-                if (idx >= NP) continue;
-                const int r = idx / W2, k2 = idx - r * W2;
-                const int gj = y0 - K + r;
-                const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
-                if (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx) continue;
-                rv[t] = relax(gi, gj);
-                rp[t] = (gj - y0 + H) * LX + (gi - x0 + H);
-            }
-            if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
-    #pragma unroll
-            for (int t = 0; t < IT; ++t)
-                if (rp[t] >= 0) X[rp[t]] = rv[t];
-            __syncthreads();
-        };
-        half(std::integral_constant<int, 3>{}, 0);  // red, first sweep
-        half(std::integral_constant<int, 2>{}, 1);  // black, first sweep
-        half(std::integral_constant<int, 1>{}, 0);  // red, second sweep
-        // black of the second sweep on the tile, written out with the red point of
-        // the same pair of columns
-        constexpr int NP = TY * (TX / 2), IT = (NP + kTileThreads - 1) / kTileThreads;
-    #pragma unroll
-        for (int t = 0; t < IT; ++t) {
-            const int idx = tid + t * kTileThreads;
-            if (idx >= NP) continue;
-            const int r = idx / (TX / 2), k2 = idx - r * (TX / 2);
-            const int gj = y0 + r;
-            const int gib = x0 + ((1 + gj) & 1) + 2 * k2, gir = gib ^ 1;
-            if (gj >= g.ny) continue;
-            T* row = xout + (int64_t)gj * g.nx;
-            if (gib < g.nx) row[gib] = relax(gib, gj);
-            if (gir < g.nx) row[gir] = X[(gj - y0 + H) * LX + (gir - x0 + H)];
-        }
-    };
     if constexpr (WALLS) {
-        if (nw) phases(std::true_type{});
-        else phases(std::false_type{});
+        if (nw) sweep2x_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, xout);
+        else sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
     } else {
-        phases(std::false_type{});
+        sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
     }
 }
 
