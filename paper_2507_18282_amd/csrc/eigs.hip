@@ -86,7 +86,19 @@ ew_status orthonormalize(Workspace& ws, double* w, const double* u1, int n1, con
 }
 
 // Y[:, 0:ncols] = X[:, 0:nx] Qm[0:nx, 0:ncols] (Qm row-major nx x qcols).
+// With the pinned staging buffer the call returns without waiting: the next
+// call first waits for the event that marks this copy done.
 ew_status rotate(Workspace& ws, const double* X, int nx, const Mat& Qm, int ncols, double* Y) {
+    if (ws.q_host && (size_t)nx * ncols <= ws.q_cap) {
+        EW_HIP_TRY(hipEventSynchronize(ws.q_ev));
+        for (int c = 0; c < ncols; ++c)
+            for (int i = 0; i < nx; ++i) ws.q_host[(size_t)c * nx + i] = Qm(i, c);
+        EW_HIP_TRY(hipMemcpyAsync(ws.q_dev, ws.q_host, (size_t)nx * ncols * sizeof(double), hipMemcpyHostToDevice,
+                                  ws.stream));
+        EW_HIP_TRY(hipEventRecord(ws.q_ev, ws.stream));
+        EW_HIP_TRY(launch_tall_gemm(X, ws.N, nx, ws.q_dev, nx, ncols, Y, ws.stream));
+        return EW_OK;
+    }
     std::vector<double> qc((size_t)nx * ncols);
     for (int c = 0; c < ncols; ++c)
         for (int i = 0; i < nx; ++i) qc[(size_t)c * nx + i] = Qm(i, c);
@@ -424,15 +436,29 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
     }
     EW_TRY(rotate(ws, ws.Y, nl, Qr, nl, ws.Z));
     std::vector<double> res(nl), znorm(nl);
+    // L z_j into the (no longer needed) L Y buffer and the partials of
+    // ||L z + mu z|| and ||z|| for every j, read back once
+    if (ws.res_cap < nl) {
+        EW_TRY(ws.alloc(&ws.res_part, (size_t)nl * 2 * kRedBlocks));
+        if (ws.res_part_host) hipHostFree(ws.res_part_host);
+        ws.res_part_host = nullptr;
+        EW_HIP_TRY(hipHostMalloc((void**)&ws.res_part_host, (size_t)nl * 2 * kRedBlocks * sizeof(double),
+                                 hipHostMallocDefault));
+        ws.res_cap = nl;
+    }
     for (int j = 0; j < nl; ++j) {
-        // L z_j into the (no longer needed) L Y buffer, then ||L z + mu z||.
         EW_TRY(apply_L_sym(ws, ws.col(ws.Z, j), ws.col(ws.LY, j)));
-        EW_HIP_TRY(launch_eig_residual(ws.col(ws.LY, j), ws.col(ws.Z, j), mu[j], N, ws.P, ws.stream));
-        EW_HIP_TRY(hipMemcpyAsync(ws.h_host, ws.P, 2 * kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, ws.stream));
-        EW_HIP_TRY(hipStreamSynchronize(ws.stream));
+        EW_HIP_TRY(launch_eig_residual(ws.col(ws.LY, j), ws.col(ws.Z, j), mu[j], N,
+                                       ws.res_part + (size_t)j * 2 * kRedBlocks, ws.stream));
+    }
+    EW_HIP_TRY(hipMemcpyAsync(ws.res_part_host, ws.res_part, (size_t)nl * 2 * kRedBlocks * sizeof(double),
+                              hipMemcpyDeviceToHost, ws.stream));
+    EW_HIP_TRY(hipStreamSynchronize(ws.stream));
+    for (int j = 0; j < nl; ++j) {
+        const double* hp = ws.res_part_host + (size_t)j * 2 * kRedBlocks;
         double r2 = 0.0, z2 = 0.0;
-        for (int b = 0; b < kRedBlocks; ++b) r2 += ws.h_host[b];
-        for (int b = 0; b < kRedBlocks; ++b) z2 += ws.h_host[kRedBlocks + b];
+        for (int b = 0; b < kRedBlocks; ++b) r2 += hp[b];
+        for (int b = 0; b < kRedBlocks; ++b) z2 += hp[kRedBlocks + b];
         znorm[j] = std::sqrt(z2);
         // relative to mu; absolute for |mu| < 1 (the constant mode of a box
         // with Neumann walls only has mu = 0)

@@ -38,6 +38,12 @@ struct Workspace {
     double* hcols = nullptr;       // Gram-Schmidt coefficient columns of steps run without a round trip
     double* hcols_host = nullptr;  // (pinned) host copy of them
     int hcols_ld = 0;              // leading dimension (nu_max + 2)
+    double* q_host = nullptr;      // pinned staging of rotation matrices (when small)
+    hipEvent_t q_ev = nullptr;     // recorded after the last copy out of q_host
+    size_t q_cap = 0;
+    double* res_part = nullptr;    // Rayleigh-Ritz residual partials, 2 kRedBlocks per vector
+    double* res_part_host = nullptr;
+    int res_cap = 0;
     double* wtmp = nullptr;    // one vector for the weighted coordinates (Neumann walls, mapped grids)
     const double* wsq = nullptr;   // mapped grid: sqrt(J) and 1/sqrt(J) (the weights are J)
     const double* wisq = nullptr;
@@ -47,6 +53,9 @@ struct Workspace {
         for (void* p : owned) hipFree(p);
         if (h_host) hipHostFree(h_host);
         if (hcols_host) hipHostFree(hcols_host);
+        if (q_host) hipHostFree(q_host);
+        if (q_ev) hipEventDestroy(q_ev);
+        if (res_part_host) hipHostFree(res_part_host);
     }
     ew_status alloc(double** p, size_t count) {
         hipError_t e = hipMalloc((void**)p, count * sizeof(double) + 256);
@@ -82,6 +91,12 @@ struct Workspace {
         if (hc <= kHcolsMaxDoubles) {
             EW_TRY(alloc(&hcols, hc));
             EW_HIP_TRY(hipHostMalloc((void**)&hcols_host, hc * sizeof(double), hipHostMallocDefault));
+        }
+        // rotation matrices staged in pinned memory need no wait after their copy
+        if ((size_t)qdim * qdim <= kHcolsMaxDoubles) {
+            q_cap = (size_t)qdim * qdim;
+            EW_HIP_TRY(hipHostMalloc((void**)&q_host, q_cap * sizeof(double), hipHostMallocDefault));
+            EW_HIP_TRY(hipEventCreateWithFlags(&q_ev, hipEventDisableTiming));
         }
         return EW_OK;
     }
