@@ -300,9 +300,11 @@ typedef struct {
  * ordered by |beta| descending): mu_host = lambda_h^2, beta_host = eigenvalue
  * of S, res_host = L_h residual ||L z + mu z|| / (max(mu, 1) ||z||),
  * Y_dev = eigenvectors (n_active x k_cap FP64 column-major on the device,
- * unit 2-norm grid functions; may be NULL).  With Neumann walls the Krylov
- * vectors, v0_dev and the residuals are in the coordinates y = W^{1/2} u (W =
- * 1/2 per Neumann wall a point lies on), where S and L_h are symmetric.
+ * unit 2-norm grid functions, each signed so that its entry of largest
+ * magnitude (the first such) is positive; may be NULL).  With Neumann walls
+ * (or on a mapped grid) the Krylov vectors, v0_dev and the residuals are in
+ * the coordinates y = W^{1/2} u (W = 1/2 per Neumann wall a point lies on;
+ * W = J on a mapped grid), where S and L_h are symmetric.
  * Host-blocking.  EW_ERR_NOT_CONVERGED if max_wave_solves is reached first. */
 ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host, double* beta_host,
                   double* res_host, double* Y_dev, ew_eigs_stats* stats);

@@ -417,6 +417,50 @@ hipError_t launch_eig_residual(const double* lz, const double* z, double mu, int
     return hipGetLastError();
 }
 
+// Per block: the entry of largest magnitude (the first such index) of y;
+// partial[b] = its value, partial[kRedBlocks + b] = its index (exact in FP64),
+// -1 for a block that sees no entry.
+__global__ __launch_bounds__(256) void k_absmax_partial(const double* __restrict__ y, int64_t n,
+                                                        double* __restrict__ partial) {
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    double bv = 0.0;
+    int64_t bi = -1;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)kRedBlocks * 256) {
+        const double v = y[c];
+        if (bi < 0 || fabs(v) > fabs(bv)) {  // indices grow along the scan, so ties keep the first
+            bv = v;
+            bi = c;
+        }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            const double ov = sv[threadIdx.x + off];
+            const int64_t oi = si[threadIdx.x + off];
+            const double mv = sv[threadIdx.x];
+            const int64_t mi = si[threadIdx.x];
+            const bool take = oi >= 0 && (mi < 0 || fabs(ov) > fabs(mv) || (fabs(ov) == fabs(mv) && oi < mi));
+            if (take) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = sv[0];
+        partial[kRedBlocks + blockIdx.x] = (double)si[0];
+    }
+}
+
+hipError_t launch_absmax_partial(const double* y, int64_t n, double* partial, hipStream_t s) {
+    k_absmax_partial<<<kRedBlocks, 256, 0, s>>>(y, n, partial);
+    return hipGetLastError();
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014; Vigna's finaliser constants), counter
 // form: z_i = mix(seed + (i+1) * golden); value = 2 * (z_i >> 11) * 2^-53 - 1.
 __device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t i) {

@@ -485,6 +485,30 @@ ew_status stage2(Workspace& ws, int nl, const std::vector<double>& th_locked, do
             EW_HIP_TRY(launch_normalize_from_partial(y, y, N, ws.P, nullptr, ws.stream));
         }
     }
+    if (Y_dev && n_ret > 0) {
+        // sign: the entry of largest magnitude (the first such) is positive
+        for (int r = 0; r < n_ret; ++r)
+            EW_HIP_TRY(launch_absmax_partial(Y_dev + (int64_t)r * N, N, ws.res_part + (size_t)r * 2 * kRedBlocks,
+                                             ws.stream));
+        EW_HIP_TRY(hipMemcpyAsync(ws.res_part_host, ws.res_part, (size_t)n_ret * 2 * kRedBlocks * sizeof(double),
+                                  hipMemcpyDeviceToHost, ws.stream));
+        EW_HIP_TRY(hipStreamSynchronize(ws.stream));
+        for (int r = 0; r < n_ret; ++r) {
+            const double* hp = ws.res_part_host + (size_t)r * 2 * kRedBlocks;
+            double bv = 0.0, bi = -1.0;
+            for (int b = 0; b < kRedBlocks; ++b) {
+                const double v = hp[b], i = hp[kRedBlocks + b];
+                if (i < 0.0) continue;
+                if (bi < 0.0 || std::fabs(v) > std::fabs(bv) || (std::fabs(v) == std::fabs(bv) && i < bi)) {
+                    bv = v;
+                    bi = i;
+                }
+            }
+            if (bv < 0.0)
+                EW_HIP_TRY(launch_scale_copy<double>(Y_dev + (int64_t)r * N, Y_dev + (int64_t)r * N, N, -1.0,
+                                                     ws.stream));
+        }
+    }
     EW_HIP_TRY(hipStreamSynchronize(ws.stream));
     *n_conv_out = n_conv;
     *n_ret_out = n_ret;

@@ -140,6 +140,9 @@ hipError_t launch_gram_partial(const double* A, int na, const double* B, int nb,
 // Partials of ||lz + mu z||^2 (partial[0:kRedBlocks]) and ||z||^2 (partial[kRedBlocks:2 kRedBlocks]).
 hipError_t launch_eig_residual(const double* lz, const double* z, double mu, int64_t n, double* partial,
                                hipStream_t s);
+// Per-block entry of largest magnitude (first index on ties): partial[0:kRedBlocks]
+// values, partial[kRedBlocks:2 kRedBlocks] indices (as doubles, -1 for none).
+hipError_t launch_absmax_partial(const double* y, int64_t n, double* partial, hipStream_t s);
 hipError_t launch_splitmix_uniform(double* x, int64_t n, uint64_t seed, hipStream_t s);
 
 // ---------------------------------------------------------------------------

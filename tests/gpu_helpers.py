@@ -45,6 +45,15 @@ def oracle_S(P: synthetic.Problem, v: np.ndarray) -> np.ndarray:
     return W.apply_filter(v.reshape(P.n[::-1]), h, P.order, plan).ravel()
 
 
+def assert_signs(Y):
+    """The returned eigenvectors' sign convention: in each column the entry of
+    largest magnitude (the first such) is positive."""
+    Y = np.asarray(Y)
+    for c in range(Y.shape[1]):
+        i = int(np.argmax(np.abs(Y[:, c])))
+        assert Y[i, c] > 0.0, (c, i, Y[i, c])
+
+
 def rel_err(a, b):
     a = np.asarray(a).ravel()
     b = np.asarray(b).ravel()

@@ -9,7 +9,7 @@ import pytest
 
 import synthetic
 from oracle import discrete as D
-from tests.gpu_helpers import make_op, oracle_plan, say, to_dev, to_host
+from tests.gpu_helpers import assert_signs, make_op, oracle_plan, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -52,6 +52,7 @@ def test_eigs_small_explicit_square():
     # eigenvectors: unit norm and orthogonal
     Y = to_host(r.Y.contiguous()).reshape(P.n_active, -1) if False else r.Y.cpu().numpy()
     assert np.max(np.abs(Y.T @ Y - np.eye(Y.shape[1]))) < 1e-9
+    assert_signs(Y)
     # four wanted: the two double eigenvalues (3,4)/(4,3) and (2,4)/(4,2)
     want = sorted([D.mu_closed_form(mm, P.n, D.spacing(P.n, P.length), 2) for mm in ((3, 4), (4, 3), (2, 4), (4, 2))])
     got = sorted(r.mu[:4])

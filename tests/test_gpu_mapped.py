@@ -18,7 +18,7 @@ from scipy import linalg
 import synthetic
 from oracle import discrete as D
 from oracle import mapped as Mp
-from tests.gpu_helpers import rel_err, say, to_dev, to_host
+from tests.gpu_helpers import assert_signs, rel_err, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -102,6 +102,7 @@ def test_eigs_match_dense_spectrum(case):
         assert np.sum(np.abs(mu - x) <= 1e-9 * x) >= want, (x, mu)
     assert max(r.res) <= 1e-8
     Y = r.Y.cpu().numpy()
+    assert_signs(Y)
     for c in range(Y.shape[1]):
         u = Y[:, c].reshape(n[::-1])
         assert abs(np.linalg.norm(u) - 1.0) < 1e-12
@@ -225,6 +226,7 @@ def test_implicit_eigs_match_dense_spectrum():
         assert np.sum(np.abs(mu - x) <= 1e-8 * x) >= want, (x, mu)
     assert max(r.res) <= 1e-8
     Y = r.Y.cpu().numpy()
+    assert_signs(Y)
     for c in range(Y.shape[1]):
         u = Y[:, c].reshape(n[::-1])
         res = Mp.apply_laplacian(u, xy) + mu[c] * u

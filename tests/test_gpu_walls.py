@@ -15,7 +15,7 @@ import pytest
 import synthetic
 from oracle import discrete as D
 from oracle import walls as Wl
-from tests.gpu_helpers import rel_err, say, to_dev, to_host
+from tests.gpu_helpers import assert_signs, rel_err, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -116,6 +116,7 @@ def test_eigs_match_closed_form(case):
     assert np.max(np.abs(D.beta_corrected(mu, plan) - np.array(r.beta))) < 1e-8
     # returned vectors are grid functions with L_h u = -mu u
     Y = r.Y.cpu().numpy()
+    assert_signs(Y)
     for c in range(Y.shape[1]):
         u = Y[:, c].reshape(n[::-1])
         assert abs(np.linalg.norm(u) - 1.0) < 1e-12
