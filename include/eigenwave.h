@@ -519,6 +519,22 @@ const char* ew_last_error(void);
 /* Library version string. */
 const char* ew_version(void);
 
+/* Device memory of the library's own buffers (operator workspaces,
+ * multigrid levels, Krylov bases, batch and network state): hipMalloc and
+ * hipFree by default.  alloc(bytes, device, stream, ctx) returns a device
+ * pointer (NULL on failure) to be used on `stream` (the owning object's
+ * stream, NULL for the default stream); free(ptr, ctx) releases a pointer
+ * that alloc returned, and is called only after the device has finished
+ * all queued work (as hipFree would wait).  Pass both or neither (NULL, NULL restores the
+ * default); ctx is handed back unchanged.  Process-wide, to be set while no
+ * library buffer exists: EW_ERR_INVALID_ARG while buffers from the current
+ * allocator are live.  Lets a caller route the workspace through a caching
+ * allocator such as PyTorch's.  (Pinned host staging buffers stay with
+ * hipHostMalloc.) */
+typedef void* (*ew_alloc_fn)(size_t bytes, int device, void* stream, void* ctx);
+typedef void (*ew_free_fn)(void* ptr, void* ctx);
+ew_status ew_set_allocator(ew_alloc_fn alloc, ew_free_fn free_fn, void* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import EigenwaveError, check, load
 
 __all__ = ["Operator", "Batch", "EigsResult", "Cnn", "CropStore", "fill_uniform", "choose_periods",
-           "EigenwaveError", "load", "version"]
+           "EigenwaveError", "load", "use_torch_allocator", "version"]
 
 
 def _torch():
@@ -369,6 +369,38 @@ class Batch:
         return out, {"wave_solves": int(st.wave_solves), "restarts": int(st.restarts), "probes": int(st.probes),
                      "pt_updates": int(st.pt_updates), "seconds": float(st.seconds), "n_conv": int(st.n_conv),
                      "max_res": float(st.max_res), "status": int(status)}
+
+
+_alloc_hooks = None   # the ctypes callbacks must outlive their registration
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device buffers through PyTorch's caching allocator
+    (``enable=False`` restores hipMalloc/hipFree).  Only while no operator,
+    batch or network exists: the library refuses otherwise."""
+    global _alloc_hooks
+    torch = _torch()
+    lib = load()
+    if not enable:
+        check(lib.ew_set_allocator(None, None, None))
+        _alloc_hooks = None
+        return
+
+    def _alloc(nbytes, device, stream, _ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), int(device), int(stream or 0)))
+        except Exception:
+            return None   # the library reports EW_ERR_OOM
+
+    def _free(ptr, _ctx):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    hooks = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+    check(lib.ew_set_allocator(ctypes.cast(hooks[0], ctypes.c_void_p), ctypes.cast(hooks[1], ctypes.c_void_p), None))
+    _alloc_hooks = hooks
 
 
 def fill_uniform(n: int, seed: int, stream=None):

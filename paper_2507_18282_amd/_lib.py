@@ -83,6 +83,10 @@ class CnnTrainStats(ctypes.Structure):
 
 
 # name -> (restype, argtypes); every symbol include/eigenwave.h declares.
+# ew_alloc_fn(bytes, device, stream, ctx) -> device pointer; ew_free_fn(ptr, ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_int, c_void_p, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
 SIGNATURES = {
     "ew_op_create": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, POINTER(c_void_p)]),
     "ew_op_create_mapped": (c_int, [POINTER(GridDesc), POINTER(OpDesc), POINTER(c_double), c_void_p,
@@ -128,6 +132,7 @@ SIGNATURES = {
     "ew_op_cnn_guess": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ew_fill_uniform": (c_int, [c_void_p, c_int64, c_uint64, c_void_p]),
     "ew_sym_eig": (c_int, [c_int, c_void_p, c_void_p, c_void_p]),
+    "ew_set_allocator": (c_int, [c_void_p, c_void_p, c_void_p]),   # ALLOC_FN, FREE_FN cast to pointers
     "ew_last_error": (c_char_p, []),
     "ew_version": (c_char_p, []),
 }

@@ -65,7 +65,7 @@ struct ew_batch_s {
 namespace ew {
 
 static ew_status balloc(ew_batch b, void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes == 0 ? 256 : bytes);
+    hipError_t e = dev_alloc(p, bytes, b->user_stream);
     if (e != hipSuccess) return fail(EW_ERR_OOM, std::string("batch allocation: ") + hipGetErrorString(e));
     b->allocs.push_back(*p);
     return EW_OK;
@@ -181,7 +181,7 @@ static ew_status batch_apply(ew_batch b, const double* const* v, double* const* 
 ew_batch_s::~ew_batch_s() {
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
-    for (void* p : allocs) hipFree(p);
+    for (void* p : allocs) ew::dev_free(p);
     if (probs_host) hipHostFree(probs_host);
     for (hipEvent_t e : {ev_fork, ev_join, ev_in, ev_out, ev_copy})
         if (e) hipEventDestroy(e);
@@ -505,7 +505,7 @@ extern "C" ew_status ew_batch_eigs(ew_batch b, const ew_eigs_desc* descs, int k_
     MgsLink* links_dev = nullptr;
     std::vector<void*> tmp;
     auto talloc = [&](void** p, size_t bytes) -> ew_status {
-        hipError_t e = hipMalloc(p, bytes);
+        hipError_t e = dev_alloc(p, bytes, b->user_stream);
         if (e != hipSuccess) return fail(EW_ERR_OOM, "batch eigensolver tables");
         tmp.push_back(*p);
         return EW_OK;
@@ -513,7 +513,7 @@ extern "C" ew_status ew_batch_eigs(ew_batch b, const ew_eigs_desc* descs, int k_
     struct Cleanup {
         std::vector<void*>& t;
         ~Cleanup() {
-            for (void* p : t) hipFree(p);
+            for (void* p : t) dev_free(p);
         }
     } cleanup{tmp};
     EW_TRY(talloc((void**)&partial, part_total * sizeof(double)));

@@ -30,11 +30,11 @@ struct Cnn {
     std::vector<void*> allocations;
 
     ~Cnn() {
-        for (void* p : allocations) hipFree(p);
+        for (void* p : allocations) dev_free(p);
         if (loss_host) hipHostFree(loss_host);
     }
     ew_status alloc(void** p, size_t bytes) {
-        hipError_t e = hipMalloc(p, bytes == 0 ? 256 : bytes);
+        hipError_t e = dev_alloc(p, bytes, stream);
         if (e != hipSuccess) {
             *p = nullptr;
             return fail(EW_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
@@ -64,7 +64,7 @@ struct CnnData {
     std::vector<void*> allocations;
 
     ~CnnData() {
-        for (void* p : allocations) hipFree(p);
+        for (void* p : allocations) dev_free(p);
     }
     int64_t field_elems() const { return 2LL * (crop + 2 * kCnnHalo) * (crop + 2 * kCnnHalo); }
     int64_t target_elems() const { return (int64_t)crop * crop; }
@@ -220,7 +220,7 @@ extern "C" ew_status ew_cnn_data_create(int capacity, int crop, ew_cnn_data* out
     void* p = nullptr;
     for (auto req : {std::make_pair((void**)&d->fields, fb), std::make_pair((void**)&d->target, tb),
                      std::make_pair((void**)&d->meta, (size_t)capacity * sizeof(CropMeta))}) {
-        hipError_t e = hipMalloc(&p, req.second);
+        hipError_t e = dev_alloc(&p, req.second, nullptr);
         if (e != hipSuccess) return fail(EW_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
         d->allocations.push_back(p);
         *req.first = p;
@@ -303,7 +303,7 @@ extern "C" ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* 
     if (nx < crop || ny < crop) return fail(EW_ERR_INVALID_ARG, "grid smaller than the crop");
     if (d->origins_cap < crops_per_step) {
         void* p = nullptr;
-        hipError_t e = hipMalloc(&p, (size_t)crops_per_step * 2 * sizeof(int));
+        hipError_t e = dev_alloc(&p, (size_t)crops_per_step * 2 * sizeof(int), op->stream);
         if (e != hipSuccess) return fail(EW_ERR_OOM, "hipMalloc of crop origins failed");
         d->allocations.push_back(p);
         d->origins_dev = (int*)p;
@@ -424,7 +424,7 @@ extern "C" ew_status ew_cnn_train(ew_cnn c, ew_cnn_data d, const ew_cnn_train_de
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     // release the per-call loss log
     c->allocations.pop_back();
-    hipFree(lp);
+    dev_free(lp);
     if (stats) {
         stats->steps = desc->steps;
         stats->first_loss = c->loss_host[0];

@@ -50,7 +50,7 @@ struct Workspace {
     int nu_max = 0;            // columns one orthogonalisation may involve
     std::vector<void*> owned;
     ~Workspace() {
-        for (void* p : owned) hipFree(p);
+        for (void* p : owned) dev_free(p);
         if (h_host) hipHostFree(h_host);
         if (hcols_host) hipHostFree(hcols_host);
         if (q_host) hipHostFree(q_host);
@@ -58,7 +58,7 @@ struct Workspace {
         if (res_part_host) hipHostFree(res_part_host);
     }
     ew_status alloc(double** p, size_t count) {
-        hipError_t e = hipMalloc((void**)p, count * sizeof(double) + 256);
+        hipError_t e = dev_alloc((void**)p, count * sizeof(double) + 256, stream);
         if (e != hipSuccess) return fail(EW_ERR_OOM, std::string("eigensolver workspace: ") + hipGetErrorString(e));
         owned.push_back(*p);
         return EW_OK;

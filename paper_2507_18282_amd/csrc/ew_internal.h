@@ -32,6 +32,12 @@ ew_status fail(ew_status code, const std::string& msg);
         if (s_ != EW_OK) return s_;          \
     } while (0)
 
+// Device memory for the library's buffers: hipMalloc/hipFree, or the
+// allocator installed with ew_set_allocator.  dev_free takes pointers from
+// dev_alloc only.
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p);
+
 // ---------------------------------------------------------------------------
 // Grid geometry passed by value to kernels.  Interior points only, x fastest.
 // ---------------------------------------------------------------------------

@@ -1,14 +1,75 @@
 // ew_op: the WaveHoltz operator S (one wave-solve + trapezoidal time filter)
 // on the device, with the implicit step's multigrid solver.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "op.h"
 
 namespace ew {
 
 thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------------------
+// Device allocator (ew_set_allocator): process-wide hooks and a count of the
+// live blocks they handed out.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_alloc_mu;
+ew_alloc_fn g_alloc = nullptr;
+ew_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+std::atomic<int64_t> g_live_blocks{0};
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 256;
+    *p = nullptr;
+    ew_alloc_fn fa;
+    void* ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        fa = g_alloc;
+        ctx = g_alloc_ctx;
+    }
+    if (fa) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        *p = fa(bytes, dev, (void*)s, ctx);
+        if (!*p) return hipErrorOutOfMemory;
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return e;
+        }
+    }
+    g_live_blocks.fetch_add(1);
+    return hipSuccess;
+}
+
+void dev_free(void* p) {
+    if (!p) return;
+    ew_free_fn ff;
+    void* ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        ff = g_free;
+        ctx = g_alloc_ctx;
+    }
+    if (ff) {
+        // hipFree waits for the device; a caller's allocator may hand the block
+        // out again at once, so wait here for every kernel that may still use it.
+        (void)hipDeviceSynchronize();
+        ff(p, ctx);
+    } else {
+        hipFree(p);
+    }
+    g_live_blocks.fetch_sub(1);
+}
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 const char* last_error_cstr() { return g_last_error.c_str(); }
@@ -79,7 +140,7 @@ static void make_plan(Op* op) {
 }
 
 Op::~Op() {
-    for (void* p : allocations) hipFree(p);
+    for (void* p : allocations) dev_free(p);
     if (partial_host) hipHostFree(partial_host);
     if (proj_res_host) hipHostFree(proj_res_host);
     for (hipEvent_t e : prof.pool) hipEventDestroy(e);
@@ -111,8 +172,7 @@ ProfScope::~ProfScope() {
 }
 
 ew_status Op::alloc(void** p, size_t bytes) {
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = dev_alloc(p, bytes, stream);
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(EW_ERR_OOM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " +
@@ -354,6 +414,20 @@ extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* de
 }
 
 extern "C" void ew_op_destroy(ew_op op) { delete op; }
+
+extern "C" ew_status ew_set_allocator(ew_alloc_fn alloc, ew_free_fn free_fn, void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(EW_ERR_INVALID_ARG, "ew_set_allocator needs both functions or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    const int64_t live = g_live_blocks.load();
+    if (live != 0)
+        return fail(EW_ERR_INVALID_ARG, std::to_string(live) + " library buffers are live; destroy every operator, "
+                                        "batch and network first");
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+    return EW_OK;
+}
 
 extern "C" ew_status ew_op_get_info(ew_op op, ew_op_info* out) {
     if (!op || !out) return fail(EW_ERR_INVALID_ARG, "null argument");

@@ -167,3 +167,15 @@ def test_mapped_grid_validation():
     bad = good.copy()
     bad[1, 3, 4] = np.nan
     assert create(bad) == -1
+
+
+def test_allocator_hooks_validated_on_host():
+    from paper_2507_18282_amd import _lib
+    lib = _lib.load()
+    hook = _lib.ALLOC_FN(lambda nbytes, dev, stream, ctx: None)
+    free = _lib.FREE_FN(lambda p, c: None)
+    assert lib.ew_set_allocator(ctypes.cast(hook, ctypes.c_void_p), None, None) == -1
+    assert b"both" in lib.ew_last_error()
+    assert lib.ew_set_allocator(None, ctypes.cast(free, ctypes.c_void_p), None) == -1
+    # restoring the default needs no device and succeeds while nothing is live
+    assert lib.ew_set_allocator(None, None, None) == 0
