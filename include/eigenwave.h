@@ -207,10 +207,11 @@ ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* h
  * rediscretised from the node samples of J and J a^mn at their points
  * (every coarse node is a fine node; n halves as (n - 1)/2 while both sizes
  * are odd and >= 3, with mg_max_levels and EW_MG_LEVELS_AUTO as for boxes),
- * red-black Gauss-Seidel half-sweeps (the corner neighbours share the
- * colour and enter with their previous values), full weighting and bilinear
- * prolongation; ew_op_mg_solve, ew_op_mg_vcycle and ew_op_mg_half_sweep
- * apply to it.
+ * zebra line relaxation along the first index (each grid line j of one
+ * parity solved exactly with lines j +- 1 held; levels with n[0] > 2474
+ * fall back to red-black point Gauss-Seidel, whose corner neighbours enter
+ * with their previous values), full weighting and bilinear prolongation;
+ * ew_op_mg_solve, ew_op_mg_vcycle and ew_op_mg_half_sweep apply to it.
  *   grid      dim 2, order 2, Dirichlet walls; n[0] x n[1] active points at
  *             r = (i + 1)/(n[0] + 1), s = (j + 1)/(n[1] + 1); len is unused.
  *   desc      explicit or implicit, precision EW_PREC_FP64; implicit guesses
@@ -257,9 +258,13 @@ ew_status ew_op_mg_solve(ew_op op, const double* b_dev, double* x_dev, int* cycl
  * component parity tests).  Stream-ordered. */
 ew_status ew_op_mg_vcycle(ew_op op, const double* b_dev, double* x_dev);
 
-/* One red-black half-sweep on the finest level: every point whose 0-based
- * index sum has parity `colour` gets x_i += (b - M x)_i / M_ii, all from the
- * values before the half-sweep (FP64 operators only).  Stream-ordered. */
+/* One half-sweep of the finest level's smoother (FP64 operators only).
+ * Boxes: every point whose 0-based index sum has parity `colour` gets
+ * x_i += (b - M x)_i / M_ii, all from the values before the half-sweep.
+ * Mapped grids with n[0] <= 2474: every line j with j % 2 == colour is
+ * replaced by the exact solution of its own equations (M x = b on the line)
+ * with the values on lines j +- 1 held; wider mapped grids: the point rule.
+ * Stream-ordered. */
 ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* x_dev, int colour);
 
 /* Eigensolver (Alg. "Krylov-Schur" interface of the paper):

@@ -163,6 +163,12 @@ struct MapCoef {
     const double* ij;   // nx x ny: 1 / J
     const double* sq;   // nx x ny: sqrt(J)
     const double* isq;  // nx x ny: 1 / sqrt(J)
+    // Thomas factors of M = I - a L_h restricted to each grid line of constant
+    // j (multigrid levels only; null where lines are relaxed point-wise):
+    // forward y_i = rhs_i tw_i - tl_i y_{i-1}, backward x_i = y_i - tu_i x_{i+1}
+    const double* tw;   // nx x ny: 1 / pivot
+    const double* tl;   // nx x ny: sub-diagonal entry / pivot (0 at i = 0)
+    const double* tu;   // nx x ny: super-diagonal entry / pivot
 };
 hipError_t launch_laplacian_mapped(const double* u, double* out, const Geo& g, const MapCoef& m, hipStream_t s);
 // The explicit leapfrog step of launch_leapfrog with the mapped operator.
@@ -177,6 +183,12 @@ hipError_t launch_pointwise_mul(const double* in, const double* f, double* out, 
 // nullptr; full-weighting restriction of r to the level with n_c = (n - 1)/2.
 hipError_t launch_rb_half_mapped(const double* xin, double* xout, const double* b, double bscale, const Geo& g,
                                  const MapCoef& m, double a, int colour, hipStream_t s);
+// Zebra line relaxation, in place: every line j of parity `parity` solved
+// exactly for its own points with the values on lines j +- 1 held (needs
+// m.tw and line_relax_fits(g.nx)).
+bool line_relax_fits(int nx);
+hipError_t launch_line_half_mapped(double* x, const double* b, double bscale, const Geo& g, const MapCoef& m,
+                                   double a, int parity, hipStream_t s);
 hipError_t launch_residual_mapped(const double* x, const double* b, double bscale, const Geo& g, const MapCoef& m,
                                   double a, double* partial, double* r_out, hipStream_t s);
 hipError_t launch_restrict_fw(const double* r, const Geo& gf, double* bc, const Geo& gc, hipStream_t s);

@@ -16,9 +16,10 @@
 // step streams them with the three state arrays, 72 B per point-step.  The
 // implicit scheme solves M = I - (dt^2/2) L_h by multigrid whose coarse
 // levels are rediscretised from the node samples of J and J a^{mn} at their
-// own points (every coarse node is a fine node), with red-black
-// Gauss-Seidel half-sweeps (the corner neighbours share the colour and enter
-// with their previous values), full weighting and bilinear prolongation.
+// own points (every coarse node is a fine node), with zebra line
+// relaxation along the first parameter direction (point red-black
+// Gauss-Seidel on levels whose lines exceed the LDS), full weighting and
+// bilinear prolongation.
 #include <cmath>
 #include <memory>
 #include <vector>
@@ -184,6 +185,165 @@ hipError_t launch_restrict_fw(const double* r, const Geo& gf, double* bc, const 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Zebra line relaxation.  On a mapped grid the coupling along one parameter
+// direction can be several times the coupling along the other (the cells of
+// an annulus sector are elongated in the angle), and point Gauss-Seidel stops
+// smoothing the error that varies slowly along the strong direction; relaxing
+// whole grid lines removes it.  One workgroup owns one line j of the parity
+// being relaxed.  It forms the line's right-hand side b_i + a/J (couplings to
+// lines j - 1 and j + 1, which no other workgroup of the launch writes) with
+// coalesced reads and solves the tridiagonal system with the Thomas factors
+// made on the host: the forward and backward substitutions are first-order
+// linear recurrences, each evaluated as a scan of affine maps y -> A + B y
+// over the 256 threads (one contiguous segment of the line per thread).
+// The line lives in LDS, padded by one slot per segment so that the threads'
+// strided segment reads fall in distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int kLineThreads = 256;
+
+__device__ __forceinline__ int line_seg(int nx) { return (nx + kLineThreads - 1) / kLineThreads; }
+
+// the three line arrays plus the scan's wave totals in 64 KB of LDS (nx <= 2474)
+bool line_relax_fits(int nx) {
+    return nx >= 1 && (3 * (size_t)(nx + kLineThreads) + 2 * (kLineThreads / 64)) * sizeof(double) <= 65536;
+}
+
+// (A, B) <- (A, B) o (A2, B2): the map that applies (A2, B2) first
+__device__ __forceinline__ void compose_after(double& A, double& B, double A2, double B2) {
+    A = A + B * A2;
+    B = B * B2;
+}
+
+// Inclusive scan of affine maps over the block; FORWARD: thread t gets
+// f_t o ... o f_0, else f_t o ... o f_255.  Returns, through `in`, the value
+// entering the thread's segment when the recurrence starts from 0 (the first
+// component of the composition of all segments before it).
+template <bool FORWARD>
+__device__ __forceinline__ double scan_entry(double A, double B, double* wsum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double Ao = FORWARD ? __shfl_up(A, off, 64) : __shfl_down(A, off, 64);
+        const double Bo = FORWARD ? __shfl_up(B, off, 64) : __shfl_down(B, off, 64);
+        if (FORWARD ? lane >= off : lane + off < 64) compose_after(A, B, Ao, Bo);
+    }
+    if (lane == (FORWARD ? 63 : 0)) {
+        wsum[2 * w] = A;
+        wsum[2 * w + 1] = B;
+    }
+    __syncthreads();
+    // composition of the other waves' totals that precede this wave in the
+    // direction of the recurrence
+    double PA = 0.0, PB = 1.0;
+    if (FORWARD) {
+        for (int v = 0; v < w; ++v) {
+            double TA = wsum[2 * v], TB = wsum[2 * v + 1];
+            compose_after(TA, TB, PA, PB);
+            PA = TA;
+            PB = TB;
+        }
+    } else {
+        for (int v = kLineThreads / 64 - 1; v > w; --v) {
+            double TA = wsum[2 * v], TB = wsum[2 * v + 1];
+            compose_after(TA, TB, PA, PB);
+            PA = TA;
+            PB = TB;
+        }
+    }
+    compose_after(A, B, PA, 0.0);  // only the first component is needed below
+    const double nb = FORWARD ? __shfl_up(A, 1, 64) : __shfl_down(A, 1, 64);
+    __syncthreads();  // wsum is reused by the next scan
+    return (FORWARD ? lane == 0 : lane == 63) ? PA : nb;
+}
+
+__global__ __launch_bounds__(kLineThreads) void k_line_half_mapped(double* x, const double* __restrict__ b,
+                                                                   double bscale, Geo g, MapCoef m, double a,
+                                                                   int parity) {
+    extern __shared__ double lds[];
+    __shared__ double wsum[2 * (kLineThreads / 64)];
+    const int nx = g.nx, ny = g.ny;
+    const int j = parity + 2 * (int)blockIdx.x;
+    if (j >= ny) return;  // uniform per block
+    const int S = line_seg(nx);
+    const int np = nx + kLineThreads;
+    double* P = lds;           // alpha -> y -> x
+    double* Q = lds + np;      // tl
+    double* R = lds + 2 * np;  // tu
+    const int64_t row = (int64_t)j * nx;
+    const bool has_s = j > 0, has_n = j < ny - 1;
+    for (int i = threadIdx.x; i < nx; i += kLineThreads) {
+        const int64_t c = row + i;
+        const bool w = i > 0, e = i < nx - 1;
+        double t = 0.0;
+        if (has_s) {
+            const double* xs = x + c - nx;
+            const double uS = xs[0], uSW = w ? xs[-1] : 0.0, uSE = e ? xs[1] : 0.0;
+            t += m.cs[c] * uS - m.cb[c - nx] * (uSE - uSW);
+            const double bE = e ? m.cb[c + 1] : 0.0, bW = w ? m.cb[c - 1] : 0.0;
+            t += bW * uSW - bE * uSE;
+        }
+        if (has_n) {
+            const double* xn = x + c + nx;
+            const double uN = xn[0], uNW = w ? xn[-1] : 0.0, uNE = e ? xn[1] : 0.0;
+            t += m.cs[c + nx] * uN + m.cb[c + nx] * (uNE - uNW);
+            const double bE = e ? m.cb[c + 1] : 0.0, bW = w ? m.cb[c - 1] : 0.0;
+            t += bE * uNE - bW * uNW;
+        }
+        const double rhs = bscale * b[c] + a * m.ij[c] * t;
+        const int p = i + i / S;
+        P[p] = rhs * m.tw[c];
+        Q[p] = m.tl[c];
+        R[p] = m.tu[c];
+    }
+    __syncthreads();
+    const int lo = threadIdx.x * S, hi = min(lo + S, nx);
+    const int pb = lo + (int)threadIdx.x;  // padded position of lo (lo / S = thread index)
+    // forward substitution y_i = alpha_i - tl_i y_{i-1}, y_{-1} = 0
+    double A = 0.0, B = 1.0;
+    for (int i = lo; i < hi; ++i) {
+        const int p = pb + (i - lo);
+        double gA = P[p], gB = -Q[p];
+        compose_after(gA, gB, A, B);
+        A = gA;
+        B = gB;
+    }
+    double y = scan_entry<true>(A, B, wsum);
+    for (int i = lo; i < hi; ++i) {
+        const int p = pb + (i - lo);
+        y = P[p] - Q[p] * y;
+        P[p] = y;
+    }
+    // backward substitution x_i = y_i - tu_i x_{i+1}, x_nx = 0
+    A = 0.0;
+    B = 1.0;
+    for (int i = hi - 1; i >= lo; --i) {
+        const int p = pb + (i - lo);
+        double gA = P[p], gB = -R[p];
+        compose_after(gA, gB, A, B);
+        A = gA;
+        B = gB;
+    }
+    double xv = scan_entry<false>(A, B, wsum);
+    for (int i = hi - 1; i >= lo; --i) {
+        const int p = pb + (i - lo);
+        xv = P[p] - R[p] * xv;
+        P[p] = xv;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nx; i += kLineThreads) x[row + i] = P[i + i / S];
+}
+
+hipError_t launch_line_half_mapped(double* x, const double* b, double bscale, const Geo& g, const MapCoef& m,
+                                   double a, int parity, hipStream_t s) {
+    if (!line_relax_fits(g.nx) || !m.tw || (parity != 0 && parity != 1)) return hipErrorInvalidValue;
+    const int lines = (g.ny - parity + 1) / 2;
+    if (lines <= 0) return hipSuccess;
+    const size_t lds = 3 * (size_t)(g.nx + kLineThreads) * sizeof(double);
+    k_line_half_mapped<<<lines, kLineThreads, lds, s>>>(x, b, bscale, g, m, a, parity);
+    return hipGetLastError();
+}
+
 // V(nu1, nu2) cycle on mapped level l from the iterate in cur (zero if
 // `zero`); other is its partner buffer and holds the residual while the
 // coarser levels run.  A full sweep is a red half-sweep into other and a
@@ -196,9 +356,17 @@ ew_status Op::mapped_vcycle(int l, double* cur, double* other, const double* b, 
     auto sweeps = [&](int count, bool from_zero) -> ew_status {
         if (from_zero) EW_HIP_TRY(launch_fill<double>(cur, n, 0.0, stream));
         for (int s = 0; s < count; ++s) {
-            ProfScope ps(this, EW_K_SMOOTH, l, 48.0 * (double)n);
-            EW_HIP_TRY(launch_rb_half_mapped(cur, other, b, bscale, L.g, m, a, 0, stream));
-            EW_HIP_TRY(launch_rb_half_mapped(other, cur, b, bscale, L.g, m, a, 1, stream));
+            if (m.tw) {
+                // per relaxed point: x on the two neighbouring lines, b, 1/J, two
+                // A22 and three B values, three factors; write x
+                ProfScope ps(this, EW_K_SMOOTH, l, 104.0 * (double)n);
+                EW_HIP_TRY(launch_line_half_mapped(cur, b, bscale, L.g, m, a, 0, stream));
+                EW_HIP_TRY(launch_line_half_mapped(cur, b, bscale, L.g, m, a, 1, stream));
+            } else {
+                ProfScope ps(this, EW_K_SMOOTH, l, 48.0 * (double)n);
+                EW_HIP_TRY(launch_rb_half_mapped(cur, other, b, bscale, L.g, m, a, 0, stream));
+                EW_HIP_TRY(launch_rb_half_mapped(other, cur, b, bscale, L.g, m, a, 1, stream));
+            }
         }
         return EW_OK;
     };
@@ -328,6 +496,32 @@ ew_status upload(Op* op, const std::vector<double>& h, const double** dst) {
     return EW_OK;
 }
 
+// Thomas factors of the line systems of M = I - a L_h on one level: along
+// line j, d_i x_i + l_i x_{i-1} + u_i x_{i+1} = rhs_i with d_i the diagonal
+// of M and l_i, u_i its couplings to the points beside i on the line (the
+// diagonally dominant rows need no pivoting).
+void line_factors(const HostCoef& hc, int nl1, int nl2, double a, std::vector<double>& tw, std::vector<double>& tl,
+                  std::vector<double>& tu) {
+    const int64_t N = (int64_t)nl1 * nl2;
+    tw.assign(N, 0.0);
+    tl.assign(N, 0.0);
+    tu.assign(N, 0.0);
+    for (int j = 0; j < nl2; ++j) {
+        double cp = 0.0;
+        for (int i = 0; i < nl1; ++i) {
+            const int64_t c = i + (int64_t)nl1 * j, hw = i + (int64_t)(nl1 + 1) * j;
+            const double s = a * hc.ij[c];
+            const double d = 1.0 + s * (hc.cw[hw] + hc.cw[hw + 1] + hc.cs[c] + hc.cs[c + nl1]);
+            const double l = i > 0 ? -s * hc.cw[hw] : 0.0;
+            const double u = i < nl1 - 1 ? -s * hc.cw[hw + 1] : 0.0;
+            const double w = 1.0 / (d - l * cp);
+            tw[c] = w;
+            tl[c] = l * w;
+            tu[c] = cp = u * w;
+        }
+    }
+}
+
 ew_status upload_level(Op* op, const HostCoef& hc, MapCoef& m) {
     EW_TRY(upload(op, hc.cw, &m.cw));
     EW_TRY(upload(op, hc.cs, &m.cs));
@@ -367,6 +561,13 @@ ew_status build_mapped_hierarchy(Op* op, const Nodes& nd, const HostCoef& fine) 
             EW_TRY(op->alloc(&L.x[0], n * sizeof(double)));
             EW_TRY(op->alloc(&L.x[1], n * sizeof(double)));
             EW_TRY(op->alloc(&L.b, n * sizeof(double)));
+        }
+        if (line_relax_fits(nl1)) {
+            std::vector<double> tw, tl, tu;
+            line_factors(*use, nl1, nl2, op->a, tw, tl, tu);
+            EW_TRY(upload(op, tw, &m.tw));
+            EW_TRY(upload(op, tl, &m.tl));
+            EW_TRY(upload(op, tu, &m.tu));
         }
         op->levels.push_back(L);
         op->mcoef.push_back(m);

@@ -361,6 +361,10 @@ extern "C" ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* 
     if (colour != 0 && colour != 1) return fail(EW_ERR_INVALID_ARG, "colour must be 0 or 1");
     if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
     double* tmp = (double*)op->levels[0].x[1];
+    if (op->mapped && op->mcoef[0].tw) {
+        EW_HIP_TRY(launch_line_half_mapped(x_dev, b_dev, 1.0, op->g, op->mcoef[0], op->a, colour, op->stream));
+        return EW_OK;
+    }
     if (op->mapped)
         EW_HIP_TRY(launch_rb_half_mapped(x_dev, tmp, b_dev, 1.0, op->g, op->mcoef[0], op->a, colour, op->stream));
     else

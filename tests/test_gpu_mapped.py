@@ -179,9 +179,20 @@ def test_implicit_solve_and_filter_match_oracle(case):
     assert rel_err(got, want) < 1e-8
 
 
-@pytest.mark.parametrize("case", IMPLICIT_CASES[:2], ids=lambda c: f"{c[0]}-{c[1]}")
+HALF_SWEEP_CASES = IMPLICIT_CASES[:2] + [
+    ("skew", (301, 9), dict(eps=0.15), 30.0),     # two points per thread of the line scan
+    ("skew", (1, 7), dict(eps=0.15), 30.0),       # lines of one point
+    ("skew", (2501, 3), dict(eps=0.15), 30.0),    # lines longer than the LDS holds: point rule
+]
+
+
+@pytest.mark.parametrize("case", HALF_SWEEP_CASES, ids=lambda c: f"{c[0]}-{c[1]}")
 def test_mapped_half_sweep_and_vcycle(case):
+    """A half-sweep relaxes whole lines j of one parity (the block
+    Gauss-Seidel step: M restricted to those lines solved exactly, lines
+    j +- 1 held), or points of one colour on grids too wide for that."""
     from scipy import sparse
+    from scipy.sparse import linalg as spl
     kind, n, params, omega = case
     xy, op = _iop(*case)
     plan = Mp.implicit_plan(xy, omega)
@@ -191,12 +202,20 @@ def test_mapped_half_sweep_and_vcycle(case):
     x0 = synthetic.uniform_pm1(74, N)
     ii = np.tile(np.arange(n[0]), n[1])
     jj = np.repeat(np.arange(n[1]), n[0])
+    lines = n[0] <= 2474
     for colour in (0, 1):
         say("mapped half sweep", kind, n, colour)
         got = to_host(op.mg_half_sweep(to_dev(b), to_dev(x0), colour))
-        want = x0 + (b - M @ x0) / M.diagonal()
-        want = np.where(((ii + jj) & 1) == colour, want, x0)
-        assert rel_err(got, want) < 1e-13
+        if lines:
+            sel = np.flatnonzero((jj & 1) == colour)
+            want = x0.copy()
+            want[sel] += spl.spsolve(M[sel][:, sel].tocsc(), (b - M @ x0)[sel])
+            assert np.array_equal(got[(jj & 1) != colour], x0[(jj & 1) != colour])
+            assert np.max(np.abs((b - M @ got)[sel])) <= 1e-12 * np.max(np.abs(b))
+        else:
+            want = x0 + (b - M @ x0) / M.diagonal()
+            want = np.where(((ii + jj) & 1) == colour, want, x0)
+        assert rel_err(got, want) < 1e-12
     # one V-cycle from zero contracts the residual (a property at any size)
     say("mapped vcycle", kind, n)
     x = to_host(op.mg_vcycle(to_dev(b), to_dev(np.zeros(N))))
