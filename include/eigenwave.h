@@ -203,10 +203,12 @@ ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* h
  * the J-weighted inner product; ew_eigs works in y = J^{1/2} u and returns
  * grid functions.  The explicit step uses dt_max = 2 / sqrt(rho) with rho the
  * Gershgorin bound max (1/J) sum |weights of J L_h| (ew_op_mapped_rho).  The
- * implicit scheme solves M = I - (dt^2/2) L_h by multigrid on levels
- * rediscretised from the node samples of J and J a^mn at their points
- * (every coarse node is a fine node; n halves as (n - 1)/2 while both sizes
- * are odd and >= 3, with mg_max_levels and EW_MG_LEVELS_AUTO as for boxes),
+ * implicit scheme solves M = I - (dt^2/2) L_h by multigrid whose coarse
+ * levels carry the Galerkin product R M P of the level above (bilinear P,
+ * full weighting R = P^T/4; every coarse node is a fine node; n halves as
+ * (n - 1)/2 while both sizes are odd and >= 3, with mg_max_levels and
+ * EW_MG_LEVELS_AUTO as for boxes, the latter judged on each level's
+ * operator),
  * zebra line relaxation along the first index (each grid line j of one
  * parity solved exactly with lines j +- 1 held; levels with n[0] > 2474
  * fall back to red-black point Gauss-Seidel, whose corner neighbours enter

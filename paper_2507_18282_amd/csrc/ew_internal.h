@@ -169,6 +169,11 @@ struct MapCoef {
     const double* tw;   // nx x ny: 1 / pivot
     const double* tl;   // nx x ny: sub-diagonal entry / pivot (0 at i = 0)
     const double* tu;   // nx x ny: super-diagonal entry / pivot
+    // Coarse multigrid levels: M itself as nine weights per point (Galerkin
+    // product of the level above), gw[k nx ny + c] for the neighbour offsets
+    // k = C, W, E, S, N, SW, SE, NW, NE; when set the kernels use these and
+    // not the coefficient arrays above
+    const double* gw;
 };
 hipError_t launch_laplacian_mapped(const double* u, double* out, const Geo& g, const MapCoef& m, hipStream_t s);
 // The explicit leapfrog step of launch_leapfrog with the mapped operator.
