@@ -210,7 +210,7 @@ ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* desc, void* h
  * EW_MG_LEVELS_AUTO as for boxes, the latter judged on each level's
  * operator),
  * zebra line relaxation along the first index (each grid line j of one
- * parity solved exactly with lines j +- 1 held; levels with n[0] > 2474
+ * parity solved exactly with lines j +- 1 held; levels with n[0] > 2816
  * fall back to red-black point Gauss-Seidel, whose corner neighbours enter
  * with their previous values), full weighting and bilinear prolongation;
  * ew_op_mg_solve, ew_op_mg_vcycle and ew_op_mg_half_sweep apply to it.
@@ -263,7 +263,7 @@ ew_status ew_op_mg_vcycle(ew_op op, const double* b_dev, double* x_dev);
 /* One half-sweep of the finest level's smoother (FP64 operators only).
  * Boxes: every point whose 0-based index sum has parity `colour` gets
  * x_i += (b - M x)_i / M_ii, all from the values before the half-sweep.
- * Mapped grids with n[0] <= 2474: every line j with j % 2 == colour is
+ * Mapped grids with n[0] <= 2816: every line j with j % 2 == colour is
  * replaced by the exact solution of its own equations (M x = b on the line)
  * with the values on lines j +- 1 held; wider mapped grids: the point rule.
  * Stream-ordered. */

@@ -2,7 +2,9 @@
 (the calibration for FETCH_SIZE / WRITE_SIZE) followed by wave-solves of the
 headline implicit workload (2047^2 interior, order 4, FP64 multigrid), or
 with ``--workload mapped`` explicit wave-solves on the 2047^2 skew-mapped
-grid (order 2, omega 60, CFL 0.9).
+grid (order 2, omega 60, CFL 0.9), or with ``--workload mapped-implicit``
+one implicit wave-solve there (omega 60 adjusted, 10 steps, multigrid to
+1e-10).
 
   rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2507_18282_amd.counters_probe
 """
@@ -22,7 +24,7 @@ COPY_BYTES = 256 * 1024 * 1024
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--wave-solves", type=int, default=1)
-    ap.add_argument("--workload", choices=("headline", "mapped"), default="headline")
+    ap.add_argument("--workload", choices=("headline", "mapped", "mapped-implicit"), default="headline")
     a = ap.parse_args(argv)
     import torch
     import synthetic
@@ -32,10 +34,14 @@ def main(argv=None) -> int:
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    if a.workload == "mapped":
+    if a.workload in ("mapped", "mapped-implicit"):
         n = (2047, 2047)
-        op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="explicit", cfl=0.9,
-                      coords=synthetic.mapped_coords("skew", *n, eps=0.15))
+        xy = synthetic.mapped_coords("skew", *n, eps=0.15)
+        if a.workload == "mapped":
+            op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="explicit", cfl=0.9, coords=xy)
+        else:
+            op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="implicit", n_its=10, adjust_omega=True,
+                          mg_tol=1e-10, mg_max_levels=-1, mg_coarse_sweeps=4, coords=xy)
         v = fill_uniform(op.n_active, 3)
         for _ in range(a.wave_solves):
             v = op.apply_filter(v)

@@ -235,15 +235,21 @@ hipError_t launch_restrict_fw(const double* r, const Geo& gf, double* bc, const 
 // linear recurrences, each evaluated as a scan of affine maps y -> A + B y
 // over the 256 threads (one contiguous segment of the line per thread).
 // The line lives in LDS, padded by one slot per segment so that the threads'
-// strided segment reads fall in distinct banks.
+// strided segment reads fall in distinct banks; the super-diagonal factors
+// wait in registers until the forward pass has used the sub-diagonal ones,
+// and then take their slots, so a line needs two arrays of LDS.
 // ---------------------------------------------------------------------------
 constexpr int kLineThreads = 256;
 
 __device__ __forceinline__ int line_seg(int nx) { return (nx + kLineThreads - 1) / kLineThreads; }
 
-// the three line arrays plus the scan's wave totals in 64 KB of LDS (nx <= 2474)
+// points a thread stages per line (lines of up to kLineStage * kLineThreads points)
+constexpr int kLineStage = 12;
+
+// two line arrays in 48 KB of LDS (nx <= 2816; with the scan's wave totals,
+// three workgroups fit in one CU's LDS)
 bool line_relax_fits(int nx) {
-    return nx >= 1 && (3 * (size_t)(nx + kLineThreads) + 2 * (kLineThreads / 64)) * sizeof(double) <= 65536;
+    return nx >= 1 && nx <= kLineStage * kLineThreads && 2 * (size_t)(nx + kLineThreads) * sizeof(double) <= 49152;
 }
 
 // (A, B) <- (A, B) o (A2, B2): the map that applies (A2, B2) first
@@ -305,12 +311,15 @@ __global__ __launch_bounds__(kLineThreads) void k_line_half_mapped(double* x, co
     if (j >= ny) return;  // uniform per block
     const int S = line_seg(nx);
     const int np = nx + kLineThreads;
-    double* P = lds;           // alpha -> y -> x
-    double* Q = lds + np;      // tl
-    double* R = lds + 2 * np;  // tu
+    double* P = lds;       // alpha -> y -> x
+    double* Q = lds + np;  // tl, then tu
     const int64_t row = (int64_t)j * nx;
     const bool has_s = j > 0, has_n = j < ny - 1;
-    for (int i = threadIdx.x; i < nx; i += kLineThreads) {
+    double tur[kLineStage];  // tu of the staged points, stored once tl is used up
+#pragma unroll
+    for (int k = 0; k < kLineStage; ++k) {
+        const int i = (int)threadIdx.x + k * kLineThreads;
+        if (i >= nx) break;
         const int64_t c = row + i;
         const bool w = i > 0, e = i < nx - 1;
         double rhs;
@@ -333,27 +342,27 @@ __global__ __launch_bounds__(kLineThreads) void k_line_half_mapped(double* x, co
             }
             rhs = bscale * b[c] - t;
         } else {
-        double t = 0.0;
-        if (has_s) {
-            const double* xs = x + c - nx;
-            const double uS = xs[0], uSW = w ? xs[-1] : 0.0, uSE = e ? xs[1] : 0.0;
-            t += m.cs[c] * uS - m.cb[c - nx] * (uSE - uSW);
-            const double bE = e ? m.cb[c + 1] : 0.0, bW = w ? m.cb[c - 1] : 0.0;
-            t += bW * uSW - bE * uSE;
-        }
-        if (has_n) {
-            const double* xn = x + c + nx;
-            const double uN = xn[0], uNW = w ? xn[-1] : 0.0, uNE = e ? xn[1] : 0.0;
-            t += m.cs[c + nx] * uN + m.cb[c + nx] * (uNE - uNW);
-            const double bE = e ? m.cb[c + 1] : 0.0, bW = w ? m.cb[c - 1] : 0.0;
-            t += bE * uNE - bW * uNW;
-        }
-        rhs = bscale * b[c] + a * m.ij[c] * t;
+            double t = 0.0;
+            if (has_s) {
+                const double* xs = x + c - nx;
+                const double uS = xs[0], uSW = w ? xs[-1] : 0.0, uSE = e ? xs[1] : 0.0;
+                t += m.cs[c] * uS - m.cb[c - nx] * (uSE - uSW);
+                const double bE = e ? m.cb[c + 1] : 0.0, bW = w ? m.cb[c - 1] : 0.0;
+                t += bW * uSW - bE * uSE;
+            }
+            if (has_n) {
+                const double* xn = x + c + nx;
+                const double uN = xn[0], uNW = w ? xn[-1] : 0.0, uNE = e ? xn[1] : 0.0;
+                t += m.cs[c + nx] * uN + m.cb[c + nx] * (uNE - uNW);
+                const double bE = e ? m.cb[c + 1] : 0.0, bW = w ? m.cb[c - 1] : 0.0;
+                t += bE * uNE - bW * uNW;
+            }
+            rhs = bscale * b[c] + a * m.ij[c] * t;
         }
         const int p = i + i / S;
         P[p] = rhs * m.tw[c];
         Q[p] = m.tl[c];
-        R[p] = m.tu[c];
+        tur[k] = m.tu[c];
     }
     __syncthreads();
     const int lo = threadIdx.x * S, hi = min(lo + S, nx);
@@ -373,12 +382,20 @@ __global__ __launch_bounds__(kLineThreads) void k_line_half_mapped(double* x, co
         y = P[p] - Q[p] * y;
         P[p] = y;
     }
+    __syncthreads();  // every tl read: the slots take tu
+#pragma unroll
+    for (int k = 0; k < kLineStage; ++k) {
+        const int i = (int)threadIdx.x + k * kLineThreads;
+        if (i >= nx) break;
+        Q[i + i / S] = tur[k];
+    }
+    __syncthreads();
     // backward substitution x_i = y_i - tu_i x_{i+1}, x_nx = 0
     A = 0.0;
     B = 1.0;
     for (int i = hi - 1; i >= lo; --i) {
         const int p = pb + (i - lo);
-        double gA = P[p], gB = -R[p];
+        double gA = P[p], gB = -Q[p];
         compose_after(gA, gB, A, B);
         A = gA;
         B = gB;
@@ -386,7 +403,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line_half_mapped(double* x, co
     double xv = scan_entry<false>(A, B, wsum);
     for (int i = hi - 1; i >= lo; --i) {
         const int p = pb + (i - lo);
-        xv = P[p] - R[p] * xv;
+        xv = P[p] - Q[p] * xv;
         P[p] = xv;
     }
     __syncthreads();
@@ -398,7 +415,7 @@ hipError_t launch_line_half_mapped(double* x, const double* b, double bscale, co
     if (!line_relax_fits(g.nx) || !m.tw || (parity != 0 && parity != 1)) return hipErrorInvalidValue;
     const int lines = (g.ny - parity + 1) / 2;
     if (lines <= 0) return hipSuccess;
-    const size_t lds = 3 * (size_t)(g.nx + kLineThreads) * sizeof(double);
+    const size_t lds = 2 * (size_t)(g.nx + kLineThreads) * sizeof(double);
     if (m.gw) k_line_half_mapped<true><<<lines, kLineThreads, lds, s>>>(x, b, bscale, g, m, a, parity);
     else k_line_half_mapped<false><<<lines, kLineThreads, lds, s>>>(x, b, bscale, g, m, a, parity);
     return hipGetLastError();

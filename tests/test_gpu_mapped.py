@@ -182,7 +182,7 @@ def test_implicit_solve_and_filter_match_oracle(case):
 HALF_SWEEP_CASES = IMPLICIT_CASES[:2] + [
     ("skew", (301, 9), dict(eps=0.15), 30.0),     # two points per thread of the line scan
     ("skew", (1, 7), dict(eps=0.15), 30.0),       # lines of one point
-    ("skew", (2501, 3), dict(eps=0.15), 30.0),    # lines longer than the LDS holds: point rule
+    ("skew", (2901, 3), dict(eps=0.15), 30.0),    # lines longer than the LDS holds: point rule
 ]
 
 
@@ -202,7 +202,7 @@ def test_mapped_half_sweep_and_vcycle(case):
     x0 = synthetic.uniform_pm1(74, N)
     ii = np.tile(np.arange(n[0]), n[1])
     jj = np.repeat(np.arange(n[1]), n[0])
-    lines = n[0] <= 2474
+    lines = n[0] <= 2816
     for colour in (0, 1):
         say("mapped half sweep", kind, n, colour)
         got = to_host(op.mg_half_sweep(to_dev(b), to_dev(x0), colour))
