@@ -20,6 +20,22 @@ __device__ __forceinline__ bool tile_coords(const Geo& g, int& i, int& j, int& k
     return i < g.nx && j < g.ny;
 }
 
+// As tile_coords for a 2D launch of tile_grid, with the workgroups renumbered
+// so that each XCD (workgroup w runs on XCD w % 8) takes one contiguous band
+// of tile rows: the rows a tile shares with the tiles above and below it are
+// then fetched into that XCD's L2 once.
+__device__ __forceinline__ bool tile_coords_xcd(const Geo& g, int& i, int& j, int& k) {
+    constexpr int kXcds = 8;
+    const int gx = gridDim.x, nb = gridDim.x * gridDim.y;
+    const int w = blockIdx.x + gx * blockIdx.y;
+    const int x = w % kXcds, q = nb / kXcds, r = nb % kXcds;
+    const int t = x * q + (x < r ? x : r) + w / kXcds;  // a bijection of [0, nb)
+    i = (t % gx) * kTileX + threadIdx.x;
+    j = (t / gx) * kTileY + threadIdx.y;
+    k = blockIdx.z;
+    return i < g.nx && j < g.ny;
+}
+
 __device__ __forceinline__ int64_t lin(const Geo& g, int i, int j, int k) {
     return ((int64_t)k * g.ny + j) * g.nx + i;
 }
