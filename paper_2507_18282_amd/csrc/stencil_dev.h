@@ -20,18 +20,26 @@ __device__ __forceinline__ bool tile_coords(const Geo& g, int& i, int& j, int& k
     return i < g.nx && j < g.ny;
 }
 
-// As tile_coords for a 2D launch of tile_grid, with the workgroups renumbered
-// so that each XCD (workgroup w runs on XCD w % 8) takes one contiguous band
-// of tile rows: the rows a tile shares with the tiles above and below it are
-// then fetched into that XCD's L2 once.
-__device__ __forceinline__ bool tile_coords_xcd(const Geo& g, int& i, int& j, int& k) {
+// Block coordinates of a 2D grid renumbered so that each XCD (workgroup w
+// runs on XCD w % 8) takes one contiguous band of tile rows: the rows a tile
+// shares with the tiles above and below it are then fetched into that XCD's
+// L2 once.  tile_coords_xcd is tile_coords for a 2D launch of tile_grid in
+// that order.
+__device__ __forceinline__ void xcd_block(int& bx, int& by) {
     constexpr int kXcds = 8;
     const int gx = gridDim.x, nb = gridDim.x * gridDim.y;
     const int w = blockIdx.x + gx * blockIdx.y;
     const int x = w % kXcds, q = nb / kXcds, r = nb % kXcds;
     const int t = x * q + (x < r ? x : r) + w / kXcds;  // a bijection of [0, nb)
-    i = (t % gx) * kTileX + threadIdx.x;
-    j = (t / gx) * kTileY + threadIdx.y;
+    bx = t % gx;
+    by = t / gx;
+}
+
+__device__ __forceinline__ bool tile_coords_xcd(const Geo& g, int& i, int& j, int& k) {
+    int bx, by;
+    xcd_block(bx, by);
+    i = bx * kTileX + threadIdx.x;
+    j = by * kTileY + threadIdx.y;
     k = blockIdx.z;
     return i < g.nx && j < g.ny;
 }

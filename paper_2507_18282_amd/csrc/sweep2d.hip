@@ -127,7 +127,9 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
     __shared__ T B[BY * BX];
     __shared__ T XC[PROLONG ? CYW * CXW : 1];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    int bx, by;
+    xcd_block(bx, by);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY;
     const int cx0 = PROLONG ? (x0 - H - 1) >> 1 : 0, cy0 = PROLONG ? (y0 - H - 1) >> 1 : 0;
     const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, 0, 1, H);  // uniform per tile
 
@@ -326,7 +328,9 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
     __shared__ T X[LY * LX];
     __shared__ T B[BY * BX];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    int bx, by;
+    xcd_block(bx, by);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY;
     const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, 0, 1, H);  // uniform per tile
 
     // staging, every global load issued before the first LDS store
