@@ -112,12 +112,14 @@ template <int ORDER, int TYR>
 __global__ __launch_bounds__(256) void k_batch_step(BatchProbDev* __restrict__ probs, const int* __restrict__ large_ids,
                                                     const int* __restrict__ blk_start, int nlarge,
                                                     const float* __restrict__ coef, int step) {
-    const int s = find_segment(blk_start, nlarge, blockIdx.x);
+    int wb, wy, wz;
+    xcd_block(wb, wy, wz);  // each XCD takes a contiguous run of tiles (rows of a problem share halos)
+    const int s = find_segment(blk_start, nlarge, wb);
     const BatchProbDev& P = probs[large_ids[s]];
     if (!P.active || step >= P.n_t) return;
     const Geo g = P.g;
     const int tiles_x = (g.nx + 63) >> 6;
-    const int tile = blockIdx.x - blk_start[s];
+    const int tile = wb - blk_start[s];
     const int i = (tile % tiles_x) * 64 + (threadIdx.x & 63);
     const int j0 = (tile / tiles_x) * (4 * TYR) + (threadIdx.x >> 6);
     if (i >= g.nx) return;

@@ -133,9 +133,9 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
     __shared__ T X[LX * LY * LZ];
     __shared__ T B[BX * BY * BZ];
     const int tid = threadIdx.x;
-    int bx = blockIdx.x, by = blockIdx.y;
-    if (DIM == 2) xcd_block(bx, by);  // XCD-contiguous bands of tiles
-    const int x0 = bx * TX, y0 = by * TY, z0 = (DIM == 3) ? blockIdx.z * TZ : 0;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY, z0 = (DIM == 3) ? bz * TZ : 0;
     const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, z0, z0 + TZ, H);  // uniform per tile
 
     // Staging of x (tile + H, zero outside the domain) and b (tile + 1): every
@@ -245,9 +245,9 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
     __shared__ T X[LX * LY * LZ];
     __shared__ T Rf[FX * FY * FZ];
     const int tid = threadIdx.x;
-    int bx = blockIdx.x, by = blockIdx.y;
-    if (DIM == 2) xcd_block(bx, by);  // XCD-contiguous bands of tiles
-    const int cx0 = bx * CX, cy0 = by * CY, cz0 = (DIM == 3) ? blockIdx.z * CZ : 0;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
+    const int cx0 = bx * CX, cy0 = by * CY, cz0 = (DIM == 3) ? bz * CZ : 0;
     // first fine point of the region: fine centre of coarse I is 2I + 1 behind
     // a Dirichlet low wall, 2I behind a Neumann one (WALLS, 2D)
     const int sx = (WALLS && (gf.wall & 1)) ? -1 : 0, sy = (WALLS && (gf.wall & 4)) ? -1 : 0;

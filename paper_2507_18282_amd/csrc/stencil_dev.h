@@ -20,27 +20,31 @@ __device__ __forceinline__ bool tile_coords(const Geo& g, int& i, int& j, int& k
     return i < g.nx && j < g.ny;
 }
 
-// Block coordinates of a 2D grid renumbered so that each XCD (workgroup w
-// runs on XCD w % 8) takes one contiguous band of tile rows: the rows a tile
-// shares with the tiles above and below it are then fetched into that XCD's
-// L2 once.  tile_coords_xcd is tile_coords for a 2D launch of tile_grid in
-// that order.
-__device__ __forceinline__ void xcd_block(int& bx, int& by) {
+// Block coordinates of a launch renumbered so that each XCD (workgroup w
+// runs on XCD w % 8) takes one contiguous band of tile rows (of tile planes
+// in 3D): the rows a tile shares with its neighbours are then fetched into
+// that XCD's L2 once.  tile_coords_xcd is tile_coords in that order.
+__device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
     constexpr int kXcds = 8;
-    const int gx = gridDim.x, nb = gridDim.x * gridDim.y;
-    const int w = blockIdx.x + gx * blockIdx.y;
+    const int gx = gridDim.x, gy = gridDim.y, nb = gridDim.x * gridDim.y * gridDim.z;
+    const int w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
     const int x = w % kXcds, q = nb / kXcds, r = nb % kXcds;
     const int t = x * q + (x < r ? x : r) + w / kXcds;  // a bijection of [0, nb)
     bx = t % gx;
-    by = t / gx;
+    by = (t / gx) % gy;
+    bz = t / (gx * gy);
+}
+
+__device__ __forceinline__ void xcd_block(int& bx, int& by) {
+    int bz;
+    xcd_block(bx, by, bz);
 }
 
 __device__ __forceinline__ bool tile_coords_xcd(const Geo& g, int& i, int& j, int& k) {
     int bx, by;
-    xcd_block(bx, by);
+    xcd_block(bx, by, k);
     i = bx * kTileX + threadIdx.x;
     j = by * kTileY + threadIdx.y;
-    k = blockIdx.z;
     return i < g.nx && j < g.ny;
 }
 
