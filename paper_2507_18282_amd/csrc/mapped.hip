@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_leapfrog_mapped(const double* __restric
                                                          double* wnext, double* __restrict__ acc, Geo g, MapCoef m,
                                                          double dt2, double ccur, double cnext) {
     int i, j, k;
-    if (!tile_coords_xcd(g, i, j, k)) return;
+    if (!tile_coords(g, i, j, k)) return;
     const int64_t c = lin(g, i, j, 0);
     const double uc = wcur[c];
     const double lap = lap_mapped(wcur, c, i, j, g, m);

@@ -70,7 +70,7 @@ template <typename T, int ORDER, int DIM, bool FIRST, bool WALLS>
 __global__ __launch_bounds__(256) void k_leapfrog(const T* __restrict__ wcur, const T* wprev, T* wnext,
                                                   T* __restrict__ acc, Geo g, T dt2, T ccur, T cnext) {
     int i, j, k;
-    if (!tile_coords_xcd(g, i, j, k)) return;
+    if (!tile_coords(g, i, j, k)) return;
     const int64_t c = lin(g, i, j, k);
     const T uc = wcur[c];
     const T lap = lap_at<T, ORDER, DIM, WALLS>(wcur, c, i, j, k, g, uc);

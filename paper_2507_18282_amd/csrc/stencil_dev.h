@@ -13,17 +13,10 @@ __host__ inline dim3 tile_grid(const Geo& g) {
     return dim3((unsigned)((g.nx + kTileX - 1) / kTileX), (unsigned)((g.ny + kTileY - 1) / kTileY), (unsigned)g.nz);
 }
 
-__device__ __forceinline__ bool tile_coords(const Geo& g, int& i, int& j, int& k) {
-    i = blockIdx.x * kTileX + threadIdx.x;
-    j = blockIdx.y * kTileY + threadIdx.y;
-    k = blockIdx.z;
-    return i < g.nx && j < g.ny;
-}
-
 // Block coordinates of a launch renumbered so that each XCD (workgroup w
 // runs on XCD w % 8) takes one contiguous band of tile rows (of tile planes
 // in 3D): the rows a tile shares with its neighbours are then fetched into
-// that XCD's L2 once.  tile_coords_xcd is tile_coords in that order.
+// that XCD's L2 once.
 __device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
     constexpr int kXcds = 8;
     const int gx = gridDim.x, gy = gridDim.y, nb = gridDim.x * gridDim.y * gridDim.z;
@@ -40,7 +33,8 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by) {
     xcd_block(bx, by, bz);
 }
 
-__device__ __forceinline__ bool tile_coords_xcd(const Geo& g, int& i, int& j, int& k) {
+// Point (i, j, k) of a thread in a launch of tile_grid, tiles in XCD order.
+__device__ __forceinline__ bool tile_coords(const Geo& g, int& i, int& j, int& k) {
     int bx, by;
     xcd_block(bx, by, k);
     i = bx * kTileX + threadIdx.x;
