@@ -406,16 +406,17 @@ static hipError_t sweep2d_dispatch(const T* xin, const T* xc, const T* b, T bs, 
     const double c0 = ORDER == 2 ? 2.0 : 30.0 / 12.0;
     const T inv = (T)(1.0 / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
     const T aa = (T)a;
-    // 64 x 16 tiles (22 KB of LDS, 7 workgroups per CU) where there are
-    // enough of them to fill the chip, 64 x 8 (less serial work per block) on
-    // smaller levels; measured faster than 64 x 32 tiles on 2047^2
+    // 64 x 16 tiles (22 KB of LDS, 7 workgroups per CU) from 1024 tiles up
+    // (1023^2 and larger), 64 x 8 (less serial work per block) on smaller
+    // levels; measured faster than 64 x 32 tiles on 2047^2, and on 1023^2
+    // than 64 x 8 once the tiles run in XCD order
     const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
     if (g.wall) {
-        if (tiles16 >= 2048)
+        if (tiles16 >= 1024)
             return sweep2d_launch<T, ORDER, 16, true>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
         return sweep2d_launch<T, ORDER, 8, true>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
     }
-    if (tiles16 >= 2048)
+    if (tiles16 >= 1024)
         return sweep2d_launch<T, ORDER, 16, false>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
     return sweep2d_launch<T, ORDER, 8, false>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
 }
@@ -440,10 +441,10 @@ static hipError_t sweep2x_dispatch(const T* xin, const T* b, T bs, T* xout, cons
     const T aa = (T)a;
     const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
     if (g.wall) {
-        if (tiles16 >= 2048) return sweep2x_launch<T, ORDER, 16, true>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+        if (tiles16 >= 1024) return sweep2x_launch<T, ORDER, 16, true>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
         return sweep2x_launch<T, ORDER, 8, true>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
     }
-    if (tiles16 >= 2048) return sweep2x_launch<T, ORDER, 16, false>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+    if (tiles16 >= 1024) return sweep2x_launch<T, ORDER, 16, false>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
     return sweep2x_launch<T, ORDER, 8, false>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
 }
 
