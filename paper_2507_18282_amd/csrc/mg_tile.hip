@@ -644,9 +644,10 @@ template <typename T, int ORDER, int DIM>
 static hipError_t restrict_dispatch(const T* x, const T* b, T bs, const Geo& gf, T a, T* bc, const Geo& gc,
                                     hipStream_t s) {
     constexpr int CX = RestrictTile<DIM>::CX, CY = RestrictTile<DIM>::CY, CZ = RestrictTile<DIM>::CZ;
-    // short tiles (less serial work per block) when tall ones would not fill the chip
+    // short tiles (less serial work per block) below 512 tall ones (coarse
+    // grids smaller than 511^2; measured on the 1023^2 level in XCD order)
     const int64_t tall = (int64_t)((gc.nx + CX - 1) / CX) * ((gc.ny + CY - 1) / CY) * (DIM == 3 ? (gc.nz + CZ - 1) / CZ : 1);
-    if (DIM == 2 && tall < 1024) {
+    if (DIM == 2 && tall < 512) {
         dim3 grid((gc.nx + CX - 1) / CX, (gc.ny + 3) / 4, 1);
         if (gf.wall) k_restrict_tile<T, ORDER, DIM, 4, true><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
         else k_restrict_tile<T, ORDER, DIM, 4, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, gf, a, bc, gc);
