@@ -141,7 +141,13 @@ typedef struct {
  *                      off-diagonal row sum to its diagonal (a = dt^2/2:
  *                      2 a S / (1 + 2 a S) for order 2, (34/12) a S /
  *                      (1 + (30/12) a S) for order 4, S = sum_d 1/h_d^2 on
- *                      that level), raised to mg_coarse_sweeps, is <= 0.1. */
+ *                      that level), raised to mg_coarse_sweeps, is <= 0.1.
+ *   mg_relax           implicit boxes only: relaxation weight w of every
+ *                      red-black half-sweep, x_i += w (b - M x)_i / M_ii
+ *                      (w > 1: over-relaxed red-black Gauss-Seidel); 0 = the
+ *                      default, 1.1 in 2D and 1.15 in 3D (the weights that
+ *                      took fewest V-cycles per solve); else in (0, 2).
+ *                      Mapped grids ignore it. */
 enum { EW_MG_LEVELS_AUTO = -1 };
 typedef struct {
     double omega;
@@ -161,6 +167,7 @@ typedef struct {
     int predictor;
     int proj_window;
     int mg_max_levels;
+    double mg_relax;
 } ew_op_desc;
 
 /* Read-only facts about an operator. */
@@ -172,6 +179,7 @@ typedef struct {
     double t_final;       /* T_f */
     double alpha_d;       /* eq. alphad at omega_used * dt */
     int mg_levels;        /* multigrid levels (implicit), else 0 */
+    double mg_relax;      /* relaxation weight of the box smoothers in use */
 } ew_op_info;
 
 /* Cumulative counters of an operator (reset by ew_op_reset_stats). */
@@ -271,7 +279,7 @@ ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* x_dev, int 
 
 /* Eigensolver (Alg. "Krylov-Schur" interface of the paper):
  *   k >= 1 wanted pairs (largest |beta|, the paper's "largestAbs"), Krylov
- *   dimension m with k < m <= n_active and m <= 256, Ritz tolerance tol_ritz
+ *   dimension m with k < m <= n_active and m <= 4096, Ritz tolerance tol_ritz
  *   (relative |S y - theta y| / |theta|) and L_h residual tolerance tol_res
  *   (||L y + mu y||_2 / (mu ||y||_2)), wave-solve cap max_wave_solves.
  *   The start vector is v0_dev if non-NULL, else SplitMix64 uniform[-1,1) of

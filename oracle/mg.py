@@ -18,6 +18,10 @@ remaining choices are this project's readings, stated here once:
   the first and last interior point folds into it).  For order 2 this is
   exact red-black Gauss-Seidel; for order 4 the +-2 neighbours share the
   point's colour and enter with their values from before the half-sweep.
+  With a relaxation weight w the correction is scaled,
+  x_i <- x_i + w (b - M x)_i / M_ii (w = 1: the plain sweep; w > 1:
+  over-relaxed red-black Gauss-Seidel, a standard variant of the same
+  smoother family).
 * restriction: full weighting, tensor product of [1 2 1]/4.
 * prolongation: multilinear interpolation (the transpose of full weighting
   up to the factor 2^dim), zero boundary values.
@@ -86,20 +90,22 @@ def residual(x: np.ndarray, b: np.ndarray, h, order: int, a: float) -> np.ndarra
     return b - apply_M(x, h, order, a)
 
 
-def rb_half_sweep(x: np.ndarray, b: np.ndarray, h, order: int, a: float, colour: int) -> np.ndarray:
-    """Relax every point of one colour simultaneously; returns the new x."""
+def rb_half_sweep(x: np.ndarray, b: np.ndarray, h, order: int, a: float, colour: int,
+                  relax: float = 1.0) -> np.ndarray:
+    """Relax every point of one colour simultaneously with weight ``relax``;
+    returns the new x."""
     r = residual(x, b, h, order, a)
     d = diag_M(x.shape, h, order, a)
     m = colour_mask(x.shape, colour)
     out = x.copy()
-    out[m] = x[m] + r[m] / d[m]
+    out[m] = x[m] + relax * r[m] / d[m]
     return out
 
 
-def rb_sweep(x, b, h, order, a):
+def rb_sweep(x, b, h, order, a, relax: float = 1.0):
     """One red-black Gauss-Seidel sweep (red, then black)."""
-    x = rb_half_sweep(x, b, h, order, a, 0)
-    return rb_half_sweep(x, b, h, order, a, 1)
+    x = rb_half_sweep(x, b, h, order, a, 0, relax)
+    return rb_half_sweep(x, b, h, order, a, 1, relax)
 
 
 def restrict_full_weighting(r: np.ndarray) -> np.ndarray:
@@ -148,7 +154,8 @@ class Hierarchy:
     """Level sizes and spacings for one grid and one implicit step size."""
 
     def __init__(self, n: Sequence[int], h: Sequence[float], order: int, a: float,
-                 nu1: int = 2, nu2: int = 1, coarse_sweeps: int = 8, max_levels: int = 64):
+                 nu1: int = 2, nu2: int = 1, coarse_sweeps: int = 8, max_levels: int = 64,
+                 relax: float = 1.0):
         self.sizes = level_sizes(n, max_levels)
         self.h = [tuple(hd * (2 ** l) for hd in h) for l in range(len(self.sizes))]
         self.order = order
@@ -156,6 +163,7 @@ class Hierarchy:
         self.nu1 = nu1
         self.nu2 = nu2
         self.coarse_sweeps = coarse_sweeps
+        self.relax = relax
 
     def shape(self, level: int) -> Tuple[int, ...]:
         return self.sizes[level][::-1]
@@ -168,7 +176,7 @@ def coarse_solve(x: np.ndarray, b: np.ndarray, hier: Hierarchy, level: int) -> n
     if b.size == 1:
         return b / diag_M(b.shape, h, hier.order, hier.a)
     for _ in range(hier.coarse_sweeps):
-        x = rb_sweep(x, b, h, hier.order, hier.a)
+        x = rb_sweep(x, b, h, hier.order, hier.a, hier.relax)
     return x
 
 
@@ -178,13 +186,13 @@ def vcycle(x: np.ndarray, b: np.ndarray, hier: Hierarchy, level: int = 0) -> np.
     if level == len(hier.sizes) - 1:
         return coarse_solve(x, b, hier, level)
     for _ in range(hier.nu1):
-        x = rb_sweep(x, b, h, hier.order, hier.a)
+        x = rb_sweep(x, b, h, hier.order, hier.a, hier.relax)
     r = residual(x, b, h, hier.order, hier.a)
     bc = restrict_full_weighting(r)
     xc = vcycle(np.zeros_like(bc), bc, hier, level + 1)
     x = x + prolong_linear(xc, x.shape)
     for _ in range(hier.nu2):
-        x = rb_sweep(x, b, h, hier.order, hier.a)
+        x = rb_sweep(x, b, h, hier.order, hier.a, hier.relax)
     return x
 
 

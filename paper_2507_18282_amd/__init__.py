@@ -81,7 +81,7 @@ class Operator:
                  filter_const: str = "alpha_d", precision: str = "fp64", mg_tol: float = 1e-10,
                  mg_nu1: int = 2, mg_nu2: int = 1, mg_max_cycles: int = 100, mg_coarse_sweeps: int = 8,
                  mg_coarse_points: int = 0, predictor: str = "zero", proj_window: int = 0,
-                 mg_max_levels: int = 0, walls=None, coords=None, stream=None):
+                 mg_max_levels: int = 0, mg_relax: float = 0.0, walls=None, coords=None, stream=None):
         lib = load()
         self._lib = lib
         g = _lib.GridDesc()
@@ -109,6 +109,7 @@ class Operator:
         d.predictor = _lib.PREDICTOR[predictor]
         d.proj_window = int(proj_window)
         d.mg_max_levels = -1 if mg_max_levels == "auto" else int(mg_max_levels)
+        d.mg_relax = float(mg_relax)
         self._stream = stream
         self._h = ctypes.c_void_p()
         if coords is None:
@@ -133,6 +134,7 @@ class Operator:
         self.t_final = float(info.t_final)
         self.alpha_d = float(info.alpha_d)
         self.mg_levels = int(info.mg_levels)
+        self.mg_relax = float(info.mg_relax)
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -252,7 +254,7 @@ def _grid_desc(n, length, order):
 
 def _op_desc(omega, ts, cfl=0.5, n_its=10, n_p=1, adjust_omega=False, filter_const="alpha_d", precision="fp64",
              mg_tol=1e-10, mg_nu1=2, mg_nu2=1, mg_max_cycles=100, mg_coarse_sweeps=8, mg_coarse_points=0,
-             predictor="zero", proj_window=0, mg_max_levels=0):
+             predictor="zero", proj_window=0, mg_max_levels=0, mg_relax=0.0):
     d = _lib.OpDesc()
     d.omega, d.ts, d.cfl, d.n_its, d.n_p = float(omega), _lib.TS[ts], float(cfl), int(n_its), int(n_p)
     d.adjust_omega, d.filter_const = int(bool(adjust_omega)), _lib.FILTER[filter_const]
@@ -262,6 +264,7 @@ def _op_desc(omega, ts, cfl=0.5, n_its=10, n_p=1, adjust_omega=False, filter_con
         _lib.PREDICTOR[predictor]
     d.proj_window = int(proj_window)
     d.mg_max_levels = int(mg_max_levels)
+    d.mg_relax = float(mg_relax)
     return d
 
 
@@ -319,17 +322,6 @@ class Batch:
         O = (ctypes.c_void_p * self.nprob)(*[_dev_ptr(o, n) for o, n in zip(outs, self.n_active)])
         check(self._lib.ew_batch_apply_filter(self._h, V, O))
         return outs
-
-    def set_cnn(self, cnn: Optional["Cnn"]) -> None:
-        """Attach the network used by predictor="cnn" (kept alive by this object)."""
-        check(self._lib.ew_op_set_cnn(self._h, cnn._h if cnn is not None else None))
-        self._cnn = cnn
-
-    def cnn_guess(self, wn, wprev, out=None):
-        out = self._new() if out is None else out
-        check(self._lib.ew_op_cnn_guess(self._h, _dev_ptr(wn, self.n_active), _dev_ptr(wprev, self.n_active),
-                                        _dev_ptr(out, self.n_active)))
-        return out
 
     def eigs(self, k: int, m: int, tol_ritz: float = 1e-12, tol_res: float = 1e-8, max_wave_solves: int = 100000,
              seeds=None, n_keep: int = 0, max_probes: int = 16, k_cap: Optional[int] = None,

@@ -223,6 +223,7 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
     };
     // normalise the start vector against the locked set
     EW_TRY(orthonormalize(ws, ws.col(ws.V, 0), ws.Y, nl, nullptr, 0, coeff));
+    if (!std::isfinite(coeff.back())) return fail(EW_ERR_NONFINITE, "non-finite start vector");
     if (!(coeff.back() > 0.0)) return fail(EW_ERR_NONFINITE, "start vector lies in the locked space");
     // probe runs test for convergence after the steps that reach these basis sizes
     auto probe_check_at = [&](int s) {
@@ -311,7 +312,10 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
                     j = jend;
                 } else {
                     // same inputs as before (the basis up to column broke is
-                    // unchanged); a non-finite value there is reported as such
+                    // unchanged); a non-finite value there is reported as such.
+                    // The queued steps from broke on are discarded: they leave
+                    // the count of kept Arnoldi steps and are run again.
+                    wave_solves -= jend - broke;
                     EW_TRY(sync_step(broke));
                     j = broke + 1;
                     continue;

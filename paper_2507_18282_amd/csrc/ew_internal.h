@@ -81,10 +81,11 @@ hipError_t launch_implicit_update(const T* sol, const T* wprev, T* wnext, TA* ac
                                   double ccur, double cnext, int first, hipStream_t s);
 
 // Multigrid pieces for M = I - a L.
-// Out of place: xout = xin with the points of one colour relaxed.
+// Out of place: xout = xin with the points of one colour relaxed,
+// x + w (b - M x)_i / M_ii (w: relaxation weight).
 template <typename T>
 hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, const Geo& g, int order, double a,
-                          int colour, hipStream_t s);
+                          double w, int colour, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& gc, hipStream_t s);
 

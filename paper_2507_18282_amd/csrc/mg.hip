@@ -14,7 +14,8 @@ namespace ew {
 // --------------------------------------------------------------------------
 template <typename T, int ORDER, int DIM, bool WALLS>
 __global__ __launch_bounds__(256) void k_rb_half(const T* __restrict__ xin, T* __restrict__ xout,
-                                                 const T* __restrict__ b, T bscale, Geo g, T a, int colour) {
+                                                 const T* __restrict__ b, T bscale, Geo g, T a, T w,
+                                                 int colour) {
     int i, j, k;
     if (!tile_coords(g, i, j, k)) return;
     const int64_t c = lin(g, i, j, k);
@@ -25,18 +26,18 @@ __global__ __launch_bounds__(256) void k_rb_half(const T* __restrict__ xin, T* _
     }
     const T lap = lap_at<T, ORDER, DIM, WALLS>(xin, c, i, j, k, g, xc);
     const T r = bscale * b[c] - (xc - a * lap);
-    xout[c] = xc + r / mdiag_at<T, ORDER, DIM, WALLS>(i, j, k, g, a);
+    xout[c] = xc + (w * r) / mdiag_at<T, ORDER, DIM, WALLS>(i, j, k, g, a);
 }
 
 template <typename T>
 hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, const Geo& g, int order, double a,
-                          int colour, hipStream_t s) {
+                          double w, int colour, hipStream_t s) {
     dim3 grid = tile_grid(g), block(kTileX, kTileY, 1);
-    const T bs = (T)bscale, aa = (T)a;
+    const T bs = (T)bscale, aa = (T)a, ww = (T)w;
 #define EW_RB(O, D)                                                                                   \
     do {                                                                                              \
-        if (g.wall) k_rb_half<T, O, D, true><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);  \
-        else k_rb_half<T, O, D, false><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, colour);       \
+        if (g.wall) k_rb_half<T, O, D, true><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, ww, colour);  \
+        else k_rb_half<T, O, D, false><<<grid, block, 0, s>>>(xin, xout, b, bs, g, aa, ww, colour);       \
     } while (0)
     if (g.dim == 2) {
         if (order == 2) EW_RB(2, 2); else EW_RB(4, 2);
@@ -153,7 +154,7 @@ hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo
 }
 
 #define EW_INST_MG(T)                                                                                          \
-    template hipError_t launch_rb_half<T>(const T*, T*, const T*, double, const Geo&, int, double, int,         \
+    template hipError_t launch_rb_half<T>(const T*, T*, const T*, double, const Geo&, int, double, double, int, \
                                           hipStream_t);                                                        \
     template hipError_t launch_prolong_correct<T>(T*, const T*, const Geo&, const Geo&, hipStream_t);
 EW_INST_MG(double)

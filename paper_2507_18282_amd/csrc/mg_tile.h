@@ -22,13 +22,14 @@ struct CoarseLevels {
     Geo g[kMaxCoarseLevels];
 };
 
-// One full red-black sweep xout = RB(xin (+ P xc if prolong), bscale b), tile by tile.
+// One full red-black sweep xout = RB(xin (+ P xc if prolong), bscale b), tile by tile;
+// every relaxed point gets x + w (b - M x)_i / M_ii (w: relaxation weight).
 // xin is not read when zero_in.  xin and xout must not alias.
 // ev0/ev1 (may be null) are recorded at the start and end of the sweep's dispatch.
 template <typename T>
 hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g,
-                             const Geo& gc, int order, double a, bool zero_in, bool prolong, hipStream_t s,
-                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                             const Geo& gc, int order, double a, double w, bool zero_in, bool prolong,
+                             hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // bc = full-weighting restriction of the residual bscale b - M x.
 template <typename T>
 hipError_t launch_restrict_tile(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
@@ -36,17 +37,17 @@ hipError_t launch_restrict_tile(const T* x, const T* b, double bscale, const Geo
 // V-cycle over the levels of c in one workgroup; x_in may be null (zero start).
 template <typename T>
 hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_out, const CoarseLevels& c, int order,
-                                double a, int nu1, int nu2, int coarse_sweeps, hipStream_t s);
+                                double a, double w, int nu1, int nu2, int coarse_sweeps, hipStream_t s);
 template <typename T>
 hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes);
 // 2D grids (sweep2d.hip).  launch_sweep2x2d: two consecutive red-black
 // sweeps of a 2D level in one pass, out of place (xin may be null with zero_in).
 template <typename T>
 hipError_t launch_sweep2x2d(const T* xin, const T* b, double bscale, T* xout, const Geo& g, int order, double a,
-                            bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                            double w, bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,
-                          int order, double a, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                          int order, double a, double w, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
                           hipEvent_t ev1);
 
 }  // namespace ew

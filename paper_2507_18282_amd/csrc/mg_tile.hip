@@ -122,7 +122,7 @@ __device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, 
 template <typename T, int ORDER, int DIM, bool ZERO_IN, bool PROLONG, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict__ xin, const T* __restrict__ xc,
                                                              const T* __restrict__ b, T bscale, T* __restrict__ xout,
-                                                             Geo g, Geo gc, T a) {
+                                                             Geo g, Geo gc, T a, T w) {
     constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
     constexpr int R = ORDER / 2;        // stencil radius
     constexpr int H = R + 1;            // red is relaxed on the tile plus one layer
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
         const T uc = X[p];
         const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw);
         const T r = B[q] - (uc - a * lap);
-        rv[t] = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
+        rv[t] = uc + (w * r) / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
         rp[t] = p;
     }
     if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
             const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw);
             const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
             const T r = B[qb] - (uc - a * lap);
-            out = uc + r / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
+            out = uc + (w * r) / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
         }
         xout[lin(g, gi, gj, gk)] = out;
     }
@@ -433,8 +433,8 @@ __device__ __forceinline__ T interior_inv_diag(const Geo& g, T a) {
 }
 
 template <typename T, int ORDER, int DIM>
-__device__ void pad_half_sweep(T* x, const T* b, const Geo& g, T a, int colour) {
-    const T inv_diag = interior_inv_diag<T, ORDER, DIM>(g, a);
+__device__ void pad_half_sweep(T* x, const T* b, const Geo& g, T a, T w, int colour) {
+    const T inv_diag = w * interior_inv_diag<T, ORDER, DIM>(g, a);
     T nv[kCoarseColourIters];
     int np[kCoarseColourIters];
 #pragma unroll
@@ -448,7 +448,7 @@ __device__ void pad_half_sweep(T* x, const T* b, const Geo& g, T a, int colour) 
         const T r = b[p] - (xc - a * lap);
         const bool edge = ORDER == 4 && (i == 0 || i == g.nx - 1 || j == 0 || j == g.ny - 1 ||
                                          (DIM == 3 && (k == 0 || k == g.nz - 1)));
-        nv[t] = edge ? xc + r / mdiag_at<T, ORDER, DIM, false>(i, j, k, g, a) : xc + r * inv_diag;
+        nv[t] = edge ? xc + (w * r) / mdiag_at<T, ORDER, DIM, false>(i, j, k, g, a) : xc + r * inv_diag;
         np[t] = p;
     }
     // Order 4 reads same-colour neighbours (old values) that other threads are
@@ -541,7 +541,7 @@ __device__ void pad_prolong(T* xf, const Geo& gf, const T* xc, const Geo& gc) {
 
 template <typename T, int ORDER, int DIM>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __restrict__ b_in, const T* __restrict__ x_in,
-                                                                  T* __restrict__ x_out, CoarseLevels c, T a,
+                                                                  T* __restrict__ x_out, CoarseLevels c, T a, T w,
                                                                   int nu1, int nu2, int coarse_sweeps, T bscale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* smem = reinterpret_cast<T*>(smem_raw);
@@ -570,8 +570,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
         T* x = smem + c.off_x[l];
         T* b = smem + c.off_b[l];
         for (int s = 0; s < nu1; ++s) {
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 0);
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 1);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 1);
         }
         pad_restrict<T, ORDER, DIM>(x, b, c.g[l], a, smem + c.off_b[l + 1], c.g[l + 1], smem + c.off_r);
     }
@@ -581,8 +581,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
         T* b = smem + c.off_b[l];
         const int sweeps = c.g[l].size() == 1 ? 1 : coarse_sweeps;
         for (int s = 0; s < sweeps; ++s) {
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 0);
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 1);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 1);
         }
     }
     for (int l = L - 2; l >= 0; --l) {
@@ -590,8 +590,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
         T* b = smem + c.off_b[l];
         pad_prolong<T, DIM>(x, c.g[l], smem + c.off_x[l + 1], c.g[l + 1]);
         for (int s = 0; s < nu2; ++s) {
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 0);
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, 1);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 1);
         }
     }
     {
@@ -611,13 +611,13 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
 // ---------------------------------------------------------------------------
 template <typename T, int ORDER, int DIM>
 static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
-                                 T a, bool zero_in, bool prolong, hipStream_t s) {
+                                 T a, T w, bool zero_in, bool prolong, hipStream_t s) {
     constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, DIM == 3 ? (g.nz + TZ - 1) / TZ : 1);
 #define EW_ST(Z, P)                                                                                          \
     do {                                                                                                     \
-        if (g.wall) k_sweep_tile<T, ORDER, DIM, Z, P, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a); \
-        else k_sweep_tile<T, ORDER, DIM, Z, P, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a);      \
+        if (g.wall) k_sweep_tile<T, ORDER, DIM, Z, P, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a, w); \
+        else k_sweep_tile<T, ORDER, DIM, Z, P, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a, w);   \
     } while (0)
     if (zero_in && prolong) EW_ST(true, true);
     else if (zero_in) EW_ST(true, false);
@@ -629,13 +629,14 @@ static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T*
 
 template <typename T>
 hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g,
-                             const Geo& gc, int order, double a, bool zero_in, bool prolong, hipStream_t s,
-                             hipEvent_t ev0, hipEvent_t ev1) {
-    const T bs = (T)bscale, aa = (T)a;
-    if (g.dim == 2) return launch_sweep2d<T>(xin, xc, b, bscale, xout, g, gc, order, a, zero_in, prolong, s, ev0, ev1);
+                             const Geo& gc, int order, double a, double w, bool zero_in, bool prolong,
+                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const T bs = (T)bscale, aa = (T)a, ww = (T)w;
+    if (g.dim == 2)
+        return launch_sweep2d<T>(xin, xc, b, bscale, xout, g, gc, order, a, w, zero_in, prolong, s, ev0, ev1);
     if (ev0) EW_RET_ON_ERR(hipEventRecord(ev0, s));
-    hipError_t e = order == 2 ? sweep_dispatch<T, 2, 3>(xin, xc, b, bs, xout, g, gc, aa, zero_in, prolong, s)
-                              : sweep_dispatch<T, 4, 3>(xin, xc, b, bs, xout, g, gc, aa, zero_in, prolong, s);
+    hipError_t e = order == 2 ? sweep_dispatch<T, 2, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s)
+                              : sweep_dispatch<T, 4, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     return e;
 }
@@ -678,15 +679,15 @@ hipError_t launch_restrict_tile(const T* x, const T* b, double bscale, const Geo
 
 template <typename T>
 hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_out, const CoarseLevels& c, int order,
-                                double a, int nu1, int nu2, int coarse_sweeps, hipStream_t s) {
+                                double a, double w, int nu1, int nu2, int coarse_sweeps, hipStream_t s) {
     const size_t lds = (size_t)c.lds_elems * sizeof(T);
-    const T aa = (T)a, bs = (T)bscale;
+    const T aa = (T)a, bs = (T)bscale, ww = (T)w;
     if (c.g[0].dim == 2) {
-        if (order == 2) k_coarse_vcycle<T, 2, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
-        else k_coarse_vcycle<T, 4, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
+        if (order == 2) k_coarse_vcycle<T, 2, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
+        else k_coarse_vcycle<T, 4, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
     } else {
-        if (order == 2) k_coarse_vcycle<T, 2, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
-        else k_coarse_vcycle<T, 4, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, nu1, nu2, coarse_sweeps, bs);
+        if (order == 2) k_coarse_vcycle<T, 2, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
+        else k_coarse_vcycle<T, 4, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
     }
     return hipGetLastError();
 }
@@ -702,11 +703,12 @@ hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes) {
 
 #define EW_INST_TILE(T)                                                                                          \
     template hipError_t launch_sweep_tile<T>(const T*, const T*, const T*, double, T*, const Geo&, const Geo&,    \
-                                             int, double, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);       \
+                                             int, double, double, bool, bool, hipStream_t, hipEvent_t,            \
+                                             hipEvent_t);                                                         \
     template hipError_t launch_restrict_tile<T>(const T*, const T*, double, const Geo&, int, double, T*,         \
                                                 const Geo&, hipStream_t);                                         \
     template hipError_t launch_coarse_vcycle<T>(const T*, double, const T*, T*, const CoarseLevels&, int, double, \
-                                                int, int, int, hipStream_t);                                      \
+                                                double, int, int, int, hipStream_t);                              \
     template hipError_t prepare_coarse_vcycle<T>(int, int, size_t);
 EW_INST_TILE(double)
 EW_INST_TILE(float)

@@ -47,6 +47,7 @@ struct TimePlan {
 void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp,
                     double rho_override = 0.0);
 ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d);
+double default_relax(double mg_relax, int dim, int order);
 
 // Whole explicit wave-solve of a small 2D grid in one workgroup (wave_small.hip).
 template <typename T>
@@ -80,6 +81,7 @@ struct Op {
     int device = 0;
     bool mixed = false, implicit = false;
     double omega_used = 0, t_final = 0, dt = 0, alpha_d = 0, a = 0;
+    double relax = 1.0;        // relaxation weight of the box smoothers (resolved mg_relax)
     int n_t = 0;
     std::vector<double> c;
     // single curvilinear grid (explicit FP64 only): coefficients of the mapped operator
@@ -101,7 +103,14 @@ struct Op {
     std::vector<Level> levels;
     int coarse_level = 0;      // first level run by the single-workgroup kernel
     CoarseLevels coarse{};
-    int last_cycles = 0;       // V-cycles of the previous implicit solve
+    // Speculative residual tests, kept per kind of solve (0: the first step's
+    // M W^1 = W^0 of a wave-solve, 1: the steps M S = 2 W^n, whose guesses
+    // differ): V-cycles of the previous solve of that kind, and whether it met
+    // the tolerance at its first test (then it may have run more cycles than it
+    // needed, and the next solve of the kind tests one cycle earlier).
+    int spec_cycles[2] = {0, 0};
+    bool spec_first_pass[2] = {false, false};
+    int solve_kind = 1;        // kind of the solve in progress
     std::vector<void*> allocations;
     Cnn* cnn = nullptr;
     // ||b||^2 already known for the right-hand side b_src of the next solve

@@ -28,7 +28,7 @@ constexpr int kTileThreads = 256;
 // Neumann-wall closures.
 template <typename T, int ORDER, int TY, bool NW>
 __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
-                                                    T inv_diag, T* __restrict__ xout) {
+                                                    T inv_diag, T w, T* __restrict__ xout) {
     constexpr int TX = 64;
     constexpr int R = ORDER / 2, H = R + 1;
     constexpr int LX = TX + 2 * H;
@@ -59,7 +59,7 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
         // the point: at a Dirichlet wall point, one point inside a Neumann wall
         const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
                                             : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
-        return edge ? uc + r / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
+        return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
     };
 
     const int rowsel = tid >> 5;  // 8 rows per pass, 32 lanes per row
@@ -117,7 +117,7 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
 template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restrict__ xin, const T* __restrict__ xc,
                                                                const T* __restrict__ b, T bscale, T* __restrict__ xout,
-                                                               Geo g, Geo gc, T a, T inv_diag) {
+                                                               Geo g, Geo gc, T a, T inv_diag, T w) {
     constexpr int TX = 64;
     constexpr int R = ORDER / 2, H = R + 1;
     constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
@@ -216,10 +216,10 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
     // tiles near a Neumann wall run the wall closures; all others the
     // Dirichlet-only code (a uniform branch, taken once per tile)
     if constexpr (WALLS) {
-        if (nw) sweep_tile2d_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, xout);
-        else sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
+        if (nw) sweep_tile2d_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        else sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     } else {
-        sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
+        sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     }
 }
 
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
 // closures.
 template <typename T, int ORDER, int TY, bool NW>
 __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
-                                               T inv_diag, T* __restrict__ xout) {
+                                               T inv_diag, T w, T* __restrict__ xout) {
     constexpr int TX = 64;
     constexpr int R = ORDER / 2, H = R + 3;
     constexpr int LX = TX + 2 * H;
@@ -269,7 +269,7 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
         const T r = bval - (uc - a * (dx * cxc + dy * cyc));
         const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
                                             : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
-        return edge ? uc + r / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
+        return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
     };
     // one half-sweep of colour `colour` on the tile plus K layers: new values to
     // registers (same-colour neighbours must be read old), then into LDS
@@ -320,7 +320,7 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
 template <typename T, int ORDER, int TY, bool ZERO_IN, bool WALLS>
 __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __restrict__ xin, const T* __restrict__ b,
                                                                  T bscale, T* __restrict__ xout, Geo g, T a,
-                                                                 T inv_diag) {
+                                                                 T inv_diag, T w) {
     constexpr int TX = 64;
     constexpr int R = ORDER / 2, H = R + 3;
     constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
@@ -372,10 +372,10 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
     __syncthreads();
 
     if constexpr (WALLS) {
-        if (nw) sweep2x_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, xout);
-        else sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
+        if (nw) sweep2x_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        else sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     } else {
-        sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, xout);
+        sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     }
 }
 
@@ -383,28 +383,30 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
 // start and end, so profiling this kernel adds no separate event commands.
 template <typename T, int ORDER, int TY, bool WALLS>
 static hipError_t sweep2d_launch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
-                                 T aa, T inv, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                                 T aa, T inv, T w, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
                                  hipEvent_t ev1) {
     dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
     dim3 block(kTileThreads);
     if (zero_in && prolong)
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv, w);
     else if (zero_in)
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv, w);
     else if (prolong)
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv, w);
     else
-        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, false, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv, w);
     return hipGetLastError();
 }
 
 template <typename T, int ORDER>
 static hipError_t sweep2d_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
-                                   double a, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                                   double a, double w, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
                                    hipEvent_t ev1) {
-    // interior diagonal of M = I - a L: 1 + a c_0 (1/hx^2 + 1/hy^2), c_0 = 2 (order 2) or 30/12 (order 4)
+    // interior diagonal of M = I - a L: 1 + a c_0 (1/hx^2 + 1/hy^2), c_0 = 2 (order 2) or 30/12 (order 4);
+    // the relaxation weight w is folded into its reciprocal
     const double c0 = ORDER == 2 ? 2.0 : 30.0 / 12.0;
-    const T inv = (T)(1.0 / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
+    const T inv = (T)(w / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
+    const T ww = (T)w;
     const T aa = (T)a;
     // 64 x 16 tiles (22 KB of LDS, 7 workgroups per CU) from 1024 tiles up
     // (1023^2 and larger), 64 x 8 (less serial work per block) on smaller
@@ -413,66 +415,69 @@ static hipError_t sweep2d_dispatch(const T* xin, const T* xc, const T* b, T bs, 
     const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
     if (g.wall) {
         if (tiles16 >= 1024)
-            return sweep2d_launch<T, ORDER, 16, true>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
-        return sweep2d_launch<T, ORDER, 8, true>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+            return sweep2d_launch<T, ORDER, 16, true>(xin, xc, b, bs, xout, g, gc, aa, inv, ww, zero_in, prolong, s, ev0, ev1);
+        return sweep2d_launch<T, ORDER, 8, true>(xin, xc, b, bs, xout, g, gc, aa, inv, ww, zero_in, prolong, s, ev0, ev1);
     }
     if (tiles16 >= 1024)
-        return sweep2d_launch<T, ORDER, 16, false>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
-    return sweep2d_launch<T, ORDER, 8, false>(xin, xc, b, bs, xout, g, gc, aa, inv, zero_in, prolong, s, ev0, ev1);
+        return sweep2d_launch<T, ORDER, 16, false>(xin, xc, b, bs, xout, g, gc, aa, inv, ww, zero_in, prolong, s, ev0, ev1);
+    return sweep2d_launch<T, ORDER, 8, false>(xin, xc, b, bs, xout, g, gc, aa, inv, ww, zero_in, prolong, s, ev0, ev1);
 }
 
 template <typename T, int ORDER, int TY, bool WALLS>
-static hipError_t sweep2x_launch(const T* xin, const T* b, T bs, T* xout, const Geo& g, T aa, T inv, bool zero_in,
-                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+static hipError_t sweep2x_launch(const T* xin, const T* b, T bs, T* xout, const Geo& g, T aa, T inv, T w,
+                                 bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
     dim3 block(kTileThreads);
     if (zero_in)
-        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv, w);
     else
-        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv);
+        hipExtLaunchKernelGGL((k_sweep2x_tile2d<T, ORDER, TY, false, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv, w);
     return hipGetLastError();
 }
 
 template <typename T, int ORDER>
-static hipError_t sweep2x_dispatch(const T* xin, const T* b, T bs, T* xout, const Geo& g, double a, bool zero_in,
-                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+static hipError_t sweep2x_dispatch(const T* xin, const T* b, T bs, T* xout, const Geo& g, double a, double w,
+                                   bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const double c0 = ORDER == 2 ? 2.0 : 30.0 / 12.0;
-    const T inv = (T)(1.0 / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
+    const T inv = (T)(w / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
+    const T ww = (T)w;
     const T aa = (T)a;
     const int64_t tiles16 = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
     if (g.wall) {
-        if (tiles16 >= 1024) return sweep2x_launch<T, ORDER, 16, true>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
-        return sweep2x_launch<T, ORDER, 8, true>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+        if (tiles16 >= 1024) return sweep2x_launch<T, ORDER, 16, true>(xin, b, bs, xout, g, aa, inv, ww, zero_in, s, ev0, ev1);
+        return sweep2x_launch<T, ORDER, 8, true>(xin, b, bs, xout, g, aa, inv, ww, zero_in, s, ev0, ev1);
     }
-    if (tiles16 >= 1024) return sweep2x_launch<T, ORDER, 16, false>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
-    return sweep2x_launch<T, ORDER, 8, false>(xin, b, bs, xout, g, aa, inv, zero_in, s, ev0, ev1);
+    if (tiles16 >= 1024) return sweep2x_launch<T, ORDER, 16, false>(xin, b, bs, xout, g, aa, inv, ww, zero_in, s, ev0, ev1);
+    return sweep2x_launch<T, ORDER, 8, false>(xin, b, bs, xout, g, aa, inv, ww, zero_in, s, ev0, ev1);
 }
 
 template <typename T>
 hipError_t launch_sweep2x2d(const T* xin, const T* b, double bscale, T* xout, const Geo& g, int order, double a,
-                            bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                            double w, bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const T bs = (T)bscale;
-    if (order == 2) return sweep2x_dispatch<T, 2>(xin, b, bs, xout, g, a, zero_in, s, ev0, ev1);
-    return sweep2x_dispatch<T, 4>(xin, b, bs, xout, g, a, zero_in, s, ev0, ev1);
+    if (order == 2) return sweep2x_dispatch<T, 2>(xin, b, bs, xout, g, a, w, zero_in, s, ev0, ev1);
+    return sweep2x_dispatch<T, 4>(xin, b, bs, xout, g, a, w, zero_in, s, ev0, ev1);
 }
 
 template hipError_t launch_sweep2x2d<double>(const double*, const double*, double, double*, const Geo&, int, double,
-                                             bool, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_sweep2x2d<float>(const float*, const float*, double, float*, const Geo&, int, double, bool,
-                                            hipStream_t, hipEvent_t, hipEvent_t);
+                                             double, bool, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_sweep2x2d<float>(const float*, const float*, double, float*, const Geo&, int, double,
+                                            double, bool, hipStream_t, hipEvent_t, hipEvent_t);
 
 template <typename T>
 hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,
-                          int order, double a, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
+                          int order, double a, double w, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
                           hipEvent_t ev1) {
     const T bs = (T)bscale;
-    if (order == 2) return sweep2d_dispatch<T, 2>(xin, xc, b, bs, xout, g, gc, a, zero_in, prolong, s, ev0, ev1);
-    return sweep2d_dispatch<T, 4>(xin, xc, b, bs, xout, g, gc, a, zero_in, prolong, s, ev0, ev1);
+    if (order == 2) return sweep2d_dispatch<T, 2>(xin, xc, b, bs, xout, g, gc, a, w, zero_in, prolong, s, ev0, ev1);
+    return sweep2d_dispatch<T, 4>(xin, xc, b, bs, xout, g, gc, a, w, zero_in, prolong, s, ev0, ev1);
 }
 
 template hipError_t launch_sweep2d<double>(const double*, const double*, const double*, double, double*, const Geo&,
-                                           const Geo&, int, double, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                           const Geo&, int, double, double, bool, bool, hipStream_t, hipEvent_t,
+                                           hipEvent_t);
 template hipError_t launch_sweep2d<float>(const float*, const float*, const float*, double, float*, const Geo&,
-                                          const Geo&, int, double, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                          const Geo&, int, double, double, bool, bool, hipStream_t, hipEvent_t,
+                                          hipEvent_t);
 
 }  // namespace ew

@@ -1,6 +1,7 @@
 // The wave-solve with time filter (S v) and the implicit step's multigrid
 // solver, orchestrated on the host and executed by the kernels of
 // stencil.hip and mg.hip on the operator's stream.
+#include <algorithm>
 #include <cmath>
 
 #include "op.h"
@@ -20,7 +21,7 @@ ew_status Op::sweep(int l, T*& cur, T*& other, const T* b, double bscale, bool z
     if (xc) bytes += sizeof(T) * (double)gc.size();
     {
         ProfScope ps(this, xc ? EW_K_PROLONG : (zero ? EW_K_SMOOTH_ZERO : EW_K_SMOOTH), l, bytes, true);
-        EW_HIP_TRY(launch_sweep_tile<T>(cur, xc, b, bscale, other, L.g, gc, order, a, zero, xc != nullptr, stream,
+        EW_HIP_TRY(launch_sweep_tile<T>(cur, xc, b, bscale, other, L.g, gc, order, a, relax, zero, xc != nullptr, stream,
                                         ps.start_event(), ps.stop_event()));
     }
     std::swap(cur, other);
@@ -40,7 +41,7 @@ ew_status Op::sweeps(int l, int count, T*& cur, T*& other, const T* b, double bs
             // algorithmic bytes counted per sweep (x, b read and x written once per
             // sweep), for the two sweeps this launch performs
             ProfScope ps(this, z ? EW_K_SMOOTH_ZERO : EW_K_SMOOTH, l, sizeof(T) * ((z ? 5.0 : 6.0) * n), true);
-            EW_HIP_TRY(launch_sweep2x2d<T>(cur, b, bscale, other, L.g, order, a, z, stream, ps.start_event(),
+            EW_HIP_TRY(launch_sweep2x2d<T>(cur, b, bscale, other, L.g, order, a, relax, z, stream, ps.start_event(),
                                            ps.stop_event()));
             std::swap(cur, other);
         }
@@ -63,7 +64,7 @@ ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool ze
         CoarseLevels c = coarse;
         {
             ProfScope ps(this, EW_K_COARSE, l, sizeof(T) * 3.0 * (double)L.g.size());
-            EW_HIP_TRY(launch_coarse_vcycle<T>(b, bscale, zero ? nullptr : cur, cur, c, order, a, desc.mg_nu1,
+            EW_HIP_TRY(launch_coarse_vcycle<T>(b, bscale, zero ? nullptr : cur, cur, c, order, a, relax, desc.mg_nu1,
                                                desc.mg_nu2, desc.mg_coarse_sweeps, stream));
         }
         *result = cur;
@@ -100,10 +101,12 @@ static ew_status check_rel(double rel) {
 }
 
 // FP64 multigrid: x <- M^{-1} (bscale b) to ||r||_2 <= mg_tol ||bscale b||_2.
-// With `speculate`, the first (previous solve's count - 1) cycles run without
-// the residual test, which costs a pass over x and b and a host round trip;
-// the test then runs after every further cycle, so the solve still stops at
-// the first tested cycle that meets the tolerance.
+// With `speculate`, the first cycles run without the residual test, which
+// costs a pass over x and b and a host round trip: as many as the previous
+// solve of the same kind took minus one (minus two if that solve met the
+// tolerance at its first test, so that a falling count is followed); the test
+// then runs after every further cycle, so the solve still stops at the first
+// tested cycle that meets the tolerance.
 ew_status Op::rhs_norm2(const double* b, double* bb) {
     if (bb_src == b) {
         *bb = bb_val;
@@ -126,7 +129,11 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
     if (bn == 0.0) {
         EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
     } else {
-        const int skip = speculate && last_cycles > 0 ? last_cycles - 1 : 0;
+        const int kind = solve_kind;
+        const int skip = speculate && spec_cycles[kind] > 0
+                             ? std::max(0, spec_cycles[kind] - (spec_first_pass[kind] ? 2 : 1))
+                             : 0;
+        int tests = 0;
         double* cur = x;
         double* other = (double*)levels[0].x[1];
         bool zero = x_is_zero;
@@ -145,6 +152,7 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
                 EW_TRY(host_sum_partials(&rr));
                 rel = std::sqrt(rr) / bn;
                 EW_TRY(check_rel(rel));
+                ++tests;
                 if (rel <= desc.mg_tol) break;
             } else {
                 rel = 1.0;
@@ -158,10 +166,11 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
             ++cyc;
         }
         if (cur != x) EW_HIP_TRY(hipMemcpyAsync(x, cur, N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        spec_cycles[kind] = cyc;
+        spec_first_pass[kind] = tests == 1 && skip > 0;
     }
     stats.mg_solves++;
     stats.mg_cycles += cyc;
-    last_cycles = cyc;
     if (cycles) *cycles = cyc;
     if (rel_out) *rel_out = rel;
     if (rel > desc.mg_tol)
@@ -219,6 +228,7 @@ ew_status cnn_predict(Op* op, const double* wcur, const double* wprev, double* g
 // One implicit solve M x = bscale b with the operator's initial-guess rule.
 ew_status Op::implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess) {
     bool zero = false;
+    solve_kind = wprev_for_guess == nullptr ? 0 : 1;
     if (desc.predictor == EW_PRED_PROJ || (desc.predictor == EW_PRED_CNN && proj_k > 0 && cnn == nullptr)) {
         EW_TRY(proj_guess(b, bscale, x, &zero));
         if (mixed) EW_TRY(mg_solve_mixed(b, bscale, x, zero, nullptr, nullptr));
@@ -368,7 +378,7 @@ extern "C" ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* 
     if (op->mapped)
         EW_HIP_TRY(launch_rb_half_mapped(x_dev, tmp, b_dev, 1.0, op->g, op->mcoef[0], op->a, colour, op->stream));
     else
-        EW_HIP_TRY(launch_rb_half<double>(x_dev, tmp, b_dev, 1.0, op->g, op->order, op->a, colour, op->stream));
+        EW_HIP_TRY(launch_rb_half<double>(x_dev, tmp, b_dev, 1.0, op->g, op->order, op->a, op->relax, colour, op->stream));
     EW_HIP_TRY(hipMemcpyAsync(x_dev, tmp, op->N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));
     return EW_OK;
 }

@@ -124,3 +124,59 @@ def test_single_point_coarsest_is_exact():
     b = np.array([[0.7]])
     x = mg.vcycle(np.zeros_like(b), b, hier)
     assert abs(mg.residual(x, b, (0.5, 0.5), 4, 0.01)[0, 0]) < 1e-15
+
+
+@pytest.mark.parametrize("w", [0.8, 1.15, 1.4])
+def test_order2_weighted_red_black_is_point_sor(w):
+    """Order 2 with relaxation weight w: the red-black sweep equals point
+    successive over-relaxation (SOR) in red-then-black order done one point at
+    a time with the dense matrix, y_i <- y_i + w (b_i - (M y)_i) / M_ii."""
+    n = (7, 6)
+    h = D.spacing(n, (1.0, 1.0))
+    a = 2e-3
+    b = synthetic.uniform_pm1(23, 42).reshape(6, 7)
+    x = synthetic.uniform_pm1(24, 42).reshape(6, 7)
+    got = mg.rb_sweep(x, b, h, 2, a, w).ravel()
+    M = np.eye(42) - a * D.laplacian_matrix(n, h, 2)
+    y = x.ravel().copy()
+    for colour in (0, 1):
+        for idx in range(42):
+            i, j = idx % 7, idx // 7
+            if (i + j) % 2 == colour:
+                y[idx] = y[idx] + w * (b.ravel()[idx] - M[idx] @ y) / M[idx, idx]
+    assert np.max(np.abs(y - got)) < 1e-13
+
+
+def test_order4_weighted_half_sweep_with_old_values():
+    """Order 4, weight w: the half-sweep gives x_i + w (b - M x)_i / M_ii from
+    the values before it on its colour, and leaves the other colour alone."""
+    n = (6, 5)
+    h = D.spacing(n, (1.0, 1.0))
+    a = 1e-3
+    w = 1.15
+    b = synthetic.uniform_pm1(33, 30).reshape(5, 6)
+    x = synthetic.uniform_pm1(34, 30).reshape(5, 6)
+    M = np.eye(30) - a * D.laplacian_matrix(n, h, 4)
+    xf = x.ravel()
+    for colour in (0, 1):
+        got = mg.rb_half_sweep(x, b, h, 4, a, colour, w).ravel()
+        for idx in range(30):
+            i, j = idx % 6, idx // 6
+            want = xf[idx] + (w * (b.ravel()[idx] - M[idx] @ xf) / M[idx, idx] if (i + j) % 2 == colour else 0.0)
+            assert abs(got[idx] - want) < 1e-13
+
+
+@pytest.mark.parametrize("order,w", [(2, 1.1), (4, 1.15)])
+def test_weighted_mg_converges_to_exact_solution(order, w):
+    """The over-relaxed V(2,1) cycle reaches the exact implicit solve and
+    needs no more cycles than the plain one on a 63^2 grid with a/h^2 = 15."""
+    n = (63, 63)
+    h = D.spacing(n, (1.0, 1.0))
+    plan = D.time_plan(h, order, 8.0, "implicit", n_its=10, adjust_omega=True)
+    a = 0.5 * plan.dt ** 2
+    b = synthetic.uniform_pm1(52, 63 * 63).reshape(63, 63)
+    xw, cw, rel = mg.solve(b, mg.Hierarchy(n, h, order, a, relax=w), 1e-10)
+    x1, c1, _ = mg.solve(b, mg.Hierarchy(n, h, order, a), 1e-10)
+    assert rel <= 1e-10 and cw <= c1
+    xe = W.solve_implicit_exact(b, h, order, plan.dt)
+    assert np.linalg.norm(xw - xe) <= 1e-10 * np.linalg.norm(b) * 1.0000001
