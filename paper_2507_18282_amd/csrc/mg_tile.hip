@@ -579,10 +579,13 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
         const int l = L - 1;
         T* x = smem + c.off_x[l];
         T* b = smem + c.off_b[l];
-        const int sweeps = c.g[l].size() == 1 ? 1 : coarse_sweeps;
+        // one point: a single half-sweep with weight 1 is the exact solve
+        const bool one = c.g[l].size() == 1;
+        const int sweeps = one ? 1 : coarse_sweeps;
+        const T wl = one ? T(1) : w;
         for (int s = 0; s < sweeps; ++s) {
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 0);
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 1);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 1);
         }
     }
     for (int l = L - 2; l >= 0; --l) {

@@ -39,13 +39,19 @@ struct Profiler {
 // FP64 on the host, in the order of operations of the definition).
 struct TimePlan {
     double omega_used = 0, t_final = 0, dt = 0, alpha_d = 0;
+    double shift = 0;          // the filter constant: alpha_d / 2 or 1/4
     int n_t = 0;
     std::vector<double> c;
 };
 // rho_override > 0 replaces the box bound sum_d c / h_d^2 on the spectrum of
-// -L_h in the explicit time step (a mapped grid supplies its own).
+// -L_h in the explicit time step (a mapped grid supplies its own).  With
+// with_weights = false the weights c_k are left out (filter_weight gives each).
 void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp,
-                    double rho_override = 0.0);
+                    double rho_override = 0.0, bool with_weights = true);
+double filter_weight(const TimePlan& tp, int k);
+// Active-point counts, spacings and Neumann-wall bits of a validated grid
+// descriptor (h = len / (n + 1 - Neumann walls of the axis)).
+void grid_geometry(const ew_grid_desc* grid, int64_t n[3], double len[3], double h[3], int* wall);
 ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d);
 double default_relax(double mg_relax, int dim, int order);
 
@@ -146,6 +152,9 @@ struct Op {
     ew_status build_hierarchy();
 
     // multigrid (wave.hip)
+    // Relaxation weight of level l: 1 on a single-point level, where one
+    // half-sweep with weight 1 is the exact solve.
+    double level_relax(int l) const { return levels[l].g.size() == 1 ? 1.0 : relax; }
     template <typename T>
     ew_status vcycle(int level, T* cur, T* other, const T* b, double bscale, bool zero, T** result);
     template <typename T>

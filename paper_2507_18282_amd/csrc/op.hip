@@ -99,7 +99,8 @@ Geo make_geo(int dim, const int64_t* n, const double* h, int wall) {
 // trapezoid weights sigma_0 = sigma_{N_t} = dt/2, dt otherwise, and
 // shift = alpha_d/2 = tan(omega dt/2) / tan(omega dt) / 2 or 1/4.
 // ---------------------------------------------------------------------------
-void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp, double rho_override) {
+void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, TimePlan& tp, double rho_override,
+                    bool with_weights) {
     double om = d.omega;
     if (d.adjust_omega) {
         const double s = std::sin(M_PI / d.n_its);
@@ -120,12 +121,16 @@ void make_time_plan(int dim, int order, const double* h, const ew_op_desc& d, Ti
     }
     tp.dt = tp.t_final / tp.n_t;
     tp.alpha_d = std::tan(om * tp.dt / 2.0) / std::tan(om * tp.dt);
-    const double shift = d.filter_const == EW_FILTER_ALPHA_D ? tp.alpha_d / 2.0 : 0.25;
+    tp.shift = d.filter_const == EW_FILTER_ALPHA_D ? tp.alpha_d / 2.0 : 0.25;
+    if (!with_weights) return;
     tp.c.resize(tp.n_t + 1);
-    for (int k = 0; k <= tp.n_t; ++k) {
-        const double sigma = (k == 0 || k == tp.n_t) ? tp.dt / 2.0 : tp.dt;
-        tp.c[k] = (2.0 / tp.t_final) * sigma * (std::cos(om * k * tp.dt) - shift);
-    }
+    for (int k = 0; k <= tp.n_t; ++k) tp.c[k] = filter_weight(tp, k);
+}
+
+// c_k = (2 / T_f) sigma_k (cos(omega t_k) - shift), trapezoidal sigma_k.
+double filter_weight(const TimePlan& tp, int k) {
+    const double sigma = (k == 0 || k == tp.n_t) ? tp.dt / 2.0 : tp.dt;
+    return (2.0 / tp.t_final) * sigma * (std::cos(tp.omega_used * k * tp.dt) - tp.shift);
 }
 
 static void make_plan(Op* op) {
@@ -360,6 +365,22 @@ ew_status Op::build_hierarchy() {
 using namespace ew;
 
 namespace ew {
+void grid_geometry(const ew_grid_desc* grid, int64_t n[3], double len[3], double h[3], int* wall) {
+    *wall = 0;
+    for (int k = 0; k < 3; ++k) {
+        n[k] = k < grid->dim ? grid->n[k] : 1;
+        len[k] = k < grid->dim ? grid->len[k] : 1.0;
+        int nn = 0;
+        for (int e = 0; e < 2 && k < grid->dim; ++e)
+            if (grid->walls[k][e] == EW_WALL_NEUMANN) {
+                *wall |= 1 << (2 * k + e);
+                ++nn;
+            }
+        // a Neumann wall point is active: h = len / (n + 1 - Neumann walls)
+        h[k] = len[k] / (double)(n[k] + 1 - nn);
+    }
+}
+
 // Relaxation weight of the red-black box smoothers: the caller's, or for 0 the
 // weight that took fewest V(2,1) cycles per implicit solve to 1e-10 on MI355X
 // (weights 1 to 1.25 in steps of 0.05): 2047^2 order 4 at omega 120, 9.97 ->
@@ -381,18 +402,7 @@ extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* de
     op->dim = grid->dim;
     op->order = grid->order;
     int wall = 0;
-    for (int k = 0; k < 3; ++k) {
-        op->n[k] = k < grid->dim ? grid->n[k] : 1;
-        op->len[k] = k < grid->dim ? grid->len[k] : 1.0;
-        int nn = 0;
-        for (int e = 0; e < 2 && k < grid->dim; ++e)
-            if (grid->walls[k][e] == EW_WALL_NEUMANN) {
-                wall |= 1 << (2 * k + e);
-                ++nn;
-            }
-        // a Neumann wall point is active: h = len / (n + 1 - Neumann walls)
-        op->h[k] = op->len[k] / (double)(op->n[k] + 1 - nn);
-    }
+    grid_geometry(grid, op->n, op->len, op->h, &wall);
     op->desc = *desc;
     op->stream = (hipStream_t)hip_stream;
     op->mixed = desc->precision == EW_PREC_MIXED;

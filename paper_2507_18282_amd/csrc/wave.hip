@@ -17,11 +17,12 @@ ew_status Op::sweep(int l, T*& cur, T*& other, const T* b, double bscale, bool z
     const Level& L = levels[l];
     const Geo gc = (xc != nullptr) ? levels[l + 1].g : L.g;
     const double n = (double)L.g.size();
+    const double w = level_relax(l);
     double bytes = sizeof(T) * ((zero ? 2.0 : 3.0) * n);
     if (xc) bytes += sizeof(T) * (double)gc.size();
     {
         ProfScope ps(this, xc ? EW_K_PROLONG : (zero ? EW_K_SMOOTH_ZERO : EW_K_SMOOTH), l, bytes, true);
-        EW_HIP_TRY(launch_sweep_tile<T>(cur, xc, b, bscale, other, L.g, gc, order, a, relax, zero, xc != nullptr, stream,
+        EW_HIP_TRY(launch_sweep_tile<T>(cur, xc, b, bscale, other, L.g, gc, order, a, w, zero, xc != nullptr, stream,
                                         ps.start_event(), ps.stop_event()));
     }
     std::swap(cur, other);
@@ -41,7 +42,8 @@ ew_status Op::sweeps(int l, int count, T*& cur, T*& other, const T* b, double bs
             // algorithmic bytes counted per sweep (x, b read and x written once per
             // sweep), for the two sweeps this launch performs
             ProfScope ps(this, z ? EW_K_SMOOTH_ZERO : EW_K_SMOOTH, l, sizeof(T) * ((z ? 5.0 : 6.0) * n), true);
-            EW_HIP_TRY(launch_sweep2x2d<T>(cur, b, bscale, other, L.g, order, a, relax, z, stream, ps.start_event(),
+            EW_HIP_TRY(launch_sweep2x2d<T>(cur, b, bscale, other, L.g, order, a, level_relax(l), z, stream,
+                                           ps.start_event(),
                                            ps.stop_event()));
             std::swap(cur, other);
         }
