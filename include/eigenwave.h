@@ -253,6 +253,33 @@ ew_status ew_op_reset_stats(ew_op op);
  * cycle to test convergence.  EW_ERR_MG_NOT_CONVERGED if a solve fails. */
 ew_status ew_op_apply_filter(ew_op op, const double* v_dev, double* out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): out_dev =
+ * S v_dev as ew_op_apply_filter computes it for an explicit operator created
+ * from the same descriptors, with no operator object.  The time plan (dt,
+ * N_t, the weights c_n) is computed on the host for each call; the time levels
+ * live in a device array of 2^23 doubles (64 MiB) that the library holds on
+ * each GPU it runs on until the process ends, its address resolved on the
+ * first call on that GPU.  The call makes no device or pinned-host
+ * allocation, creates no event and does not synchronise: it is stream-ordered
+ * on hip_stream (NULL = the null stream) of the current device.
+ *   grid, desc  as for ew_op_create, with desc->ts = EW_TS_EXPLICIT and
+ *               precision EW_PREC_FP64 or EW_PREC_MIXED; at most 2^22 active
+ *               points (2047^2 fits).
+ *   v_dev, out_dev  n_active FP64 device vectors (may not alias); read and
+ *               written only by the stream-ordered work.
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time
+ * on one GPU (other streams, other host threads) race and give undefined
+ * results; calls ordered on one stream are safe.  Nothing of an earlier
+ * call's contents enters a result (every array is written before it is
+ * read).  Small grids take the per-step kernels (ew_op_apply_filter may run
+ * them in one workgroup), so results agree with it to rounding.
+ * Errors: EW_ERR_INVALID_ARG (the ranges of ew_op_create, null pointers,
+ * aliasing, more than 2^22 points), EW_ERR_UNSUPPORTED (implicit stepping),
+ * EW_ERR_HIP. */
+ew_status ew_apply_filter_noalloc(const ew_grid_desc* grid, const ew_op_desc* desc, const double* v_dev,
+                                  double* out_dev, void* hip_stream);
+
 /* out_dev = L_h v_dev (FP64, device; may not alias), the operator of eq.
  * eigBVPdiscrete with the order's closure.  Stream-ordered. */
 ew_status ew_op_apply_laplacian(ew_op op, const double* v_dev, double* out_dev);

@@ -99,6 +99,7 @@ SIGNATURES = {
     "ew_op_reset_stats": (c_int, [c_void_p]),
     "ew_op_apply_filter": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ew_op_apply_laplacian": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ew_apply_filter_noalloc": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, c_void_p, c_void_p]),
     "ew_op_mg_solve": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_int), POINTER(c_double)]),
     "ew_op_mg_vcycle": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ew_op_mg_half_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
