@@ -160,3 +160,104 @@ def test_adam_first_step_and_constant_gradient():
         th_new, m, v = C.adam_step(th, m, v, g, t, lr, eps=eps)
         assert np.allclose(th_new - th, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-18)
         th = th_new
+
+
+# ---------------------------------------------------------------------------
+# The residual form: loss points, the crop operator, the residual loss and its
+# gradient, and the corrected guess.
+# ---------------------------------------------------------------------------
+from oracle import discrete as D  # noqa: E402
+from oracle import wave as W  # noqa: E402
+
+
+def test_crop_loss_points_interior_and_walls():
+    """Order 4 reaches two cells: an interior crop loses two rows and columns
+    on every side; a crop at the grid's corner keeps the rows and columns on
+    its wall sides (the closure replaces the neighbours beyond a wall)."""
+    m = C.crop_loss_points((40, 50), (10, 12), 16, 4)
+    assert m.shape == (16, 16) and m.sum() == 12 * 12
+    assert m[2:14, 2:14].all() and not m[:2].any() and not m[:, 14:].any()
+    m = C.crop_loss_points((40, 50), (0, 34), 16, 4)      # top wall, right wall (34 + 16 = 50)
+    assert m[0:14, 2:16].all() and not m[14:].any() and not m[:, :2].any()
+    assert C.crop_loss_points((40, 50), (10, 12), 16, 2).sum() == 14 * 14
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("origin", [(3, 5), (0, 0), (13, 11)])
+def test_residual_loss_matches_dense_operator(order, origin):
+    """The residual loss equals sum over the loss points of (t - M y)^2 / npix
+    with M = I - a L_h assembled as a dense matrix on the whole grid and y
+    placed in the window (zero elsewhere)."""
+    ny, nx, crop = 20, 18, 7
+    shape = (ny, nx)
+    h = D.spacing((nx, ny), (1.0, 1.1))
+    a = 3e-4
+    th = _theta(121)
+    x = _input(122, crop, crop)
+    t = synthetic.uniform_pm1(123, crop * crop).reshape(crop, crop)
+    loss, _ = C.residual_loss_and_grad(th, x, t, shape, origin, h, order, a)
+    y, _ = C.forward(th, x)
+    M = np.eye(nx * ny) - a * D.laplacian_matrix((nx, ny), h, order)
+    full = np.zeros(shape)
+    oy, ox = origin
+    full[oy:oy + crop, ox:ox + crop] = y
+    My = (M @ full.ravel()).reshape(shape)[oy:oy + crop, ox:ox + crop]
+    mask = C.crop_loss_points(shape, origin, crop, order)
+    want = np.sum(np.where(mask, t - My, 0.0) ** 2) / crop ** 2
+    assert loss == pytest.approx(want, rel=1e-13)
+    # and on the loss points M y does not depend on values outside the window
+    full2 = full.copy()
+    full2[:oy] = 7.0
+    full2[oy + crop:] = -3.0
+    My2 = (M @ full2.ravel()).reshape(shape)[oy:oy + crop, ox:ox + crop]
+    assert np.max(np.abs(np.where(mask, My - My2, 0.0))) == 0.0
+
+
+@pytest.mark.parametrize("origin", [(4, 6), (0, 11)])
+def test_residual_loss_gradient_matches_central_differences(origin):
+    ny, nx, crop = 16, 16, 5
+    shape = (ny, nx)
+    h = D.spacing((nx, ny), (1.0, 1.0))
+    a = 5e-3
+    th = _theta(131)
+    x = _input(132, crop, crop)
+    t = synthetic.uniform_pm1(133, crop * crop).reshape(crop, crop)
+    loss, g = C.residual_loss_and_grad(th, x, t, shape, origin, h, 4, a)
+    idx = np.concatenate([np.arange(0, C.N_PARAMS, 7), [C.N_PARAMS - 1, 575, 591, 2911]])
+    eps = 1e-6
+    for i in idx:
+        tp = th.copy()
+        tp[i] += eps
+        tm = th.copy()
+        tm[i] -= eps
+        lp, _ = C.residual_loss_and_grad(tp, x, t, shape, origin, h, 4, a)
+        lm, _ = C.residual_loss_and_grad(tm, x, t, shape, origin, h, 4, a)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, np.max(np.abs(g))), (i, fd, g[i])
+    p = C.unpack(g)
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert np.max(np.abs(p[name])) > 0, name
+
+
+def test_corrected_guess_degenerate_cases():
+    """A network that outputs the constant beta (all weights zero, b3 = beta)
+    moves the base guess by s * beta with s the RMS of its residual; an exact
+    base guess has no residual and is returned unchanged."""
+    n = (12, 10)
+    h = D.spacing(n, (1.0, 1.0))
+    a, om = 4e-4, 20.0
+    p = C.unpack(np.zeros(C.N_PARAMS))
+    p["b3"][0] = 0.25
+    th = C.pack(p)
+    b = synthetic.uniform_pm1(141, 120).reshape(10, 12)
+    x0 = synthetic.uniform_pm1(142, 120).reshape(10, 12) * 0.1
+    r = b - C.apply_M(x0, h, 4, a)
+    s = np.sqrt(np.mean(r * r))
+    g = C.predict_correction(th, x0, b, h, 4, a, om)
+    assert np.allclose(g, x0 + 0.25 * s, rtol=0, atol=1e-14)
+    xe = W.solve_implicit_exact(b, h, 4, np.sqrt(2 * a))
+    ge = C.predict_correction(_theta(143), xe, b, h, 4, a, om)
+    assert np.max(np.abs(ge - xe)) <= 1e-12 * np.max(np.abs(xe))
+    xin = C.make_input_residual(r, b, s, 2.0, 0.5, 0.25)
+    assert np.array_equal(xin[0, 3:-3, 3:-3], r / s) and np.array_equal(xin[1, 3:-3, 3:-3], b / 2.0)
+    assert np.all(xin[:, :3] == 0) and np.all(xin[3, 3:-3, 3:-3] == 0.25)
