@@ -14,8 +14,9 @@ resident in HBM before the timed region starts.
 
 value = grid-point updates per second (active points x time steps advanced)
 over the K timed steps.  Eigenpairs per second at residual <= 1e-8 are
-measured on a complete solve of the 64^2 explicit workload (the largest one
-whose complete solve fits the bench's time budget) and reported beside it.
+measured on complete solves of the headline eigenproblem (with the number of
+filter periods from the lobe rule; about 1000 eigenvalues lie in the main lobe
+at one period) and of the 64^2 explicit workload, and reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -35,12 +36,17 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 LEARN_CHAINS = 40          # wave-solve chains that generate training crops
-LEARN_CROPS = 8640         # 40 chains x 3 wave-solves x 9 steps x 8 crops
-LEARN_STEPS = 2000         # Adam steps (half at 2e-3, half at 5e-4)
+LEARN_CROPS_PER_STEP = 19  # 40 chains x 3 wave-solves x 9 steps x 19 crops = 20520 crops
+LEARN_STEPS = 3000         # Adam steps per phase (one phase at 2e-3, one at 5e-4)
+LEARN_BATCH = 32
 LEARN_OMEGA_SEED = 4242
 LEARN_CROP_SEED = 777
-LEARN_BUDGET = 32          # wave-solves per predictor in the learned-form comparison
+LEARN_BUDGET = 32          # wave-solves per predictor in the one-period comparisons
 LEARN_OMEGAS = (40.0, 90.0, 140.0)
+LEARN_COMPLETE_OMEGA = 90.0  # complete eigensolves (N_p from the lobe rule) for every predictor
+CUBE_N = 63                # side of the mixed-vs-FP64 cube eigensolve (--cube-n: 127, 255)
+MIXED_TOL_RITZ = 1e-7      # Ritz tolerance above the FP32 accumulation noise of S v
+CUBE_BUDGET = 400          # wave-solves per precision in the cube eigensolves
 PERIODS_BUDGET_NP1 = 400   # wave-solves allowed to N_p = 1 in the periods-rule comparison
 METRIC = "grid-pt updates/s + eigenpairs/s at resid 1e-8; learned/batched vs plain"
 SMOOTH_SRC = os.path.join(ROOT, "paper_2507_18282_amd", "csrc", "sweep2d.hip")
@@ -84,31 +90,50 @@ def measured_traffic():
         return None
 
 
+def host_cpu():
+    """Logical CPUs and model name of the host the bench runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
 def cpu_baseline(P, n_solves: int):
     """The oracle, as it stands, on a bounded sample: n_solves wave-solves of the
-    headline grid (exact sine-transform implicit solves; single-threaded numpy
-    and scipy.fft)."""
+    headline grid (exact sine-transform implicit solves, numpy and scipy.fft),
+    once on one core and once with scipy.fft's transforms on every host core
+    (scipy.fft.set_workers); the faster is `value`."""
     import numpy as np
+    import scipy.fft
     import synthetic
     from oracle import discrete as D
     from oracle import wave as W
     h = D.spacing(P.n, P.length)
     plan = D.time_plan(h, P.order, P.omega, P.ts, n_its=P.n_its, n_p=P.n_p, adjust_omega=P.adjust_omega)
-    v = synthetic.start_vector(P.seed, P.n_active).reshape(P.n[::-1])
-    t0 = time.perf_counter()
-    for _ in range(n_solves):
-        v = W.apply_filter(v, h, P.order, plan)
-        v = v / np.linalg.norm(v)
-    dt = time.perf_counter() - t0
-    return {"value": P.n_active * plan.n_t * n_solves / dt, "unit": "grid-pt updates/s", "cores": 1,
-            "kind": "oracle",
+    ncpu, model = host_cpu()
+    runs = {}
+    for cores in (1, ncpu):
+        v = synthetic.start_vector(P.seed, P.n_active).reshape(P.n[::-1])
+        t0 = time.perf_counter()
+        with scipy.fft.set_workers(cores):
+            for _ in range(n_solves):
+                v = W.apply_filter(v, h, P.order, plan)
+                v = v / np.linalg.norm(v)
+        runs[cores] = time.perf_counter() - t0
+        log(f"cpu baseline: {n_solves} wave-solves on {cores} cores in {runs[cores]:.1f} s")
+    best = min(runs, key=runs.get)
+    rate = {c: P.n_active * plan.n_t * n_solves / t for c, t in runs.items()}
+    return {"value": rate[best], "unit": "grid-pt updates/s", "cores": best, "kind": "oracle",
             "sample": f"{n_solves} wave-solves of the 2047^2 order-4 implicit grid ({plan.n_t} steps each, "
-                      f"exact DST solves instead of multigrid), {dt:.1f} s"}
-
-
-BATCH_TOL_RITZ = 1e-5   # above the FP32 noise of S v (N_t up to ~1200 steps)
-BATCH_TOL_RES = 5e-3    # eigen-residual both forms are judged at (FP32 state floor ~2e-3)
-
+                      f"exact DST solves instead of multigrid), {runs[best]:.1f} s",
+            "host": {"logical_cpus": ncpu, "model": model},
+            "per_cores": {str(c): {"value": rate[c], "seconds": runs[c]} for c in runs}}
 
 def batched_vs_plain(budget: int):
     """96 independent rectangles (sides U[0.5,2], n^2 grids with n U[65,1025],
@@ -155,55 +180,85 @@ def batched_vs_plain(budget: int):
 
 
 def learned_vs_plain():
-    """1023^2 unit square, order 4, implicit 10 steps/period, omega 40, 90, 140
-    (adjusted), FP64 multigrid to 1e-10, k = 16, m = 32: the eigensolver with the cold start
-    (zero guess) against the warm starts, LEARN_BUDGET wave-solves each.  Every
-    guess leaves the multigrid iterating to the same tolerance, so S, and with
-    it the Arnoldi sequence, is the same up to that tolerance (S v for one
-    vector is compared) and the ratio of wave-solve times is the ratio of
-    eigenpairs/s at the same eigen-residual.  (A complete solve of this dense-spectrum workload takes
-    thousands of wave-solves.)  The network is trained first on crops of
-    solver-generated time levels (40 chains of 3 wave-solves from SplitMix64
-    starts 5000.., omega U[30, 150]); data and training time are reported."""
+    """1023^2 unit square, order 4, implicit 10 steps/period, FP64 multigrid to
+    1e-10, k = 16, m = 32.  Training: 20520 crops of 128^2 (40 chains of 3
+    wave-solves from SplitMix64 starts 5000.., omega U[30, 150], projection
+    guesses; 19 crops per step) at the projection guess's residual, Adam on the
+    residual loss.  Then: complete eigensolves at omega 90 with N_p from the
+    lobe rule for the zero, projection and learned guesses (multigrid always to
+    the same tolerance, so the eigenpairs agree), eigenpairs/s at eig-res <=
+    1e-8; the initial residuals of the guesses measured inside the solves; and
+    one-period runs of LEARN_BUDGET wave-solves at omega 40, 90, 140."""
     import torch
     import synthetic
-    from paper_2507_18282_amd import Cnn, CropStore, Operator, fill_uniform
+    from paper_2507_18282_amd import Cnn, CropStore, Operator, choose_periods, fill_uniform
     P = synthetic.config_learned()
     n = P.n[0]
 
-    def make(omega, predictor):
-        return Operator(n=P.n, length=P.length, order=P.order, omega=omega, ts=P.ts, n_its=P.n_its,
+    def make(omega, predictor, n_p=1):
+        return Operator(n=P.n, length=P.length, order=P.order, omega=omega, ts=P.ts, n_its=P.n_its, n_p=n_p,
                         adjust_omega=P.adjust_omega, mg_tol=P.mg_tol, predictor=predictor,
                         mg_max_levels=MG_LEVELS, mg_coarse_sweeps=MG_COARSE_SWEEPS)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    store = CropStore(LEARN_CROPS, 128)
+    store = CropStore(LEARN_CHAINS * 3 * 9 * LEARN_CROPS_PER_STEP, 128, P.order)
     u = synthetic.uniform01(LEARN_OMEGA_SEED, LEARN_CHAINS)
     for c in range(LEARN_CHAINS):
-        op = make(30.0 + 120.0 * u[c], "zero")
+        op = make(30.0 + 120.0 * u[c], "proj")
         v = fill_uniform(op.n_active, 5000 + c)
         for _ in range(3):
-            w = store.collect(op, v, crops_per_step=8, seed=LEARN_CROP_SEED)
+            w = store.collect(op, v, crops_per_step=LEARN_CROPS_PER_STEP, seed=LEARN_CROP_SEED)
             v = w / w.norm()
         op.close()
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = Cnn(1)
-    tr1 = net.train(store, steps=LEARN_STEPS // 2, batch=16, lr=2e-3, seed=11)
-    tr2 = net.train(store, steps=LEARN_STEPS // 2, batch=16, lr=5e-4, seed=12)
+    tr1 = net.train(store, steps=LEARN_STEPS, batch=LEARN_BATCH, lr=2e-3, seed=11)
+    tr2 = net.train(store, steps=LEARN_STEPS, batch=LEARN_BATCH, lr=5e-4, seed=12)
     log(f"learned: {store.count} crops in {t_data:.2f} s, training {tr1['seconds'] + tr2['seconds']:.2f} s, "
         f"loss {tr1['first_loss']:.4g} -> {tr2['last_loss']:.4g}")
-    out = {"workload": "unit square 1025^2 points (1023^2 interior), order 4, implicit 10 steps/period, omega "
-                       "40/90/140 (adjusted), FP64 multigrid to 1e-10 (automatic depth, 4 sweeps on the coarsest level), k=16, m=32",
-           "budget_wave_solves": LEARN_BUDGET,
-           "data": {"crops": store.count, "crop": 128, "seconds": t_data},
-           "training": {"steps": LEARN_STEPS, "batch": 16, "seconds": tr1["seconds"] + tr2["seconds"],
-                        "first_loss": tr1["first_loss"], "last_loss": tr2["last_loss"]}}
-    v_check = fill_uniform(n * n, 99)
-    preds = ("zero", "proj", "cnn", "extrap", "scaled")
+    out = {"workload": "unit square 1025^2 points (1023^2 interior), order 4, implicit 10 steps/period, FP64 "
+                       "multigrid to 1e-10 (automatic depth, 4 sweeps on the coarsest level), k=16, m=32",
+           "data": {"crops": store.count, "crop": 128, "seconds": t_data, "base_guess": "projection"},
+           "training": {"steps": 2 * LEARN_STEPS, "batch": LEARN_BATCH, "seconds": tr1["seconds"] + tr2["seconds"],
+                        "first_loss": tr1["first_loss"], "last_loss": tr2["last_loss"],
+                        "loss": "mean over window points of (r/s - M y)^2; 1.0 = the base guess's residual"}}
+    preds = ("zero", "proj", "cnn")
+    # complete eigensolves at the rule's N_p
+    omega = LEARN_COMPLETE_OMEGA
+    n_p, n_lobe = choose_periods(P.length, omega, P.k)
+    comp = {"omega": omega, "n_p": n_p, "eigenvalues_in_lobe": n_lobe}
+    for pred in preds:
+        op = make(omega, pred, n_p)
+        if pred == "cnn":
+            op.set_cnn(net)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = op.eigs(P.k, P.m, seed=P.seed, tol_res=1e-8, want_vectors=False, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ok = sum(1 for x in r.res if x <= 1e-8)
+        comp[pred] = {"pairs": ok, "wave_solves": r.wave_solves, "seconds": dt, "eigenpairs_per_s": ok / dt,
+                      "ms_per_wave_solve": dt / max(1, r.wave_solves) * 1e3,
+                      "mg_cycles_per_implicit_solve": r.mg_cycles / max(1, r.time_steps),
+                      "max_res": max(r.res) if r.res else None, "status": r.status, "mu": list(r.mu)}
+        log(f"learned form complete omega {omega} N_p {n_p} {pred}: {ok} pairs, {r.wave_solves} wave-solves, "
+            f"{dt:.1f} s, {comp[pred]['mg_cycles_per_implicit_solve']:.2f} cycles/solve")
+        op.close()
+    for pred in preds[1:]:
+        c = comp[pred]
+        c["speedup_eigenpairs_per_s_vs_zero"] = c["eigenpairs_per_s"] / comp["zero"]["eigenpairs_per_s"] \
+            if comp["zero"]["eigenpairs_per_s"] else None
+        c["vcycles_saved_per_implicit_solve"] = comp["zero"]["mg_cycles_per_implicit_solve"] - \
+            c["mg_cycles_per_implicit_solve"]
+        if comp["zero"]["mu"] and c["mu"]:
+            c["max_mu_rel_diff_vs_zero"] = max(abs(a - b) / b for a, b in zip(sorted(c["mu"]), sorted(comp["zero"]["mu"])))
+    comp["cnn"]["speedup_eigenpairs_per_s_vs_proj"] = comp["cnn"]["eigenpairs_per_s"] / \
+        comp["proj"]["eigenpairs_per_s"] if comp["proj"]["eigenpairs_per_s"] else None
+    out["complete_solves"] = comp
+    # one-period runs: wave-solve cost and cycles, and the guesses' initial residuals (separate probed runs)
     for omega in LEARN_OMEGAS:
-        Sv = {}
         res = {}
         for pred in preds:
             op = make(omega, pred)
@@ -215,21 +270,29 @@ def learned_vs_plain():
                         raise_on_error=False)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
-            Sv[pred] = op.apply_filter(v_check)
             res[pred] = {"ms_per_wave_solve": dt / r.wave_solves * 1e3, "wave_solves": r.wave_solves,
                          "mg_cycles_per_implicit_solve": r.mg_cycles / max(1, r.time_steps)}
+            if pred != "zero":
+                op.reset_stats()
+                op.probe_guesses(True)
+                w = fill_uniform(op.n_active, 99)
+                for _ in range(2):
+                    w = op.apply_filter(w / w.norm())
+                st = op.stats()
+                res[pred]["guess_rel_res"] = st["guess_rel_res_sum"] / max(1, st["guess_probes"])
+                res[pred]["base_rel_res"] = st["base_rel_res_sum"] / max(1, st["guess_probes"])
             log(f"learned form omega {omega} {pred}: {r.wave_solves} wave-solves in {dt:.2f} s, "
-                f"{res[pred]['mg_cycles_per_implicit_solve']:.2f} cycles/solve")
+                f"{res[pred]['mg_cycles_per_implicit_solve']:.2f} cycles/solve"
+                + (f", initial residual {res[pred]['guess_rel_res']:.3g} (base {res[pred]['base_rel_res']:.3g})"
+                   if pred != "zero" else ""))
             op.close()
         z = res["zero"]
         for pred in preds[1:]:
             o = res[pred]
             o["vcycles_saved_per_implicit_solve"] = z["mg_cycles_per_implicit_solve"] - o["mg_cycles_per_implicit_solve"]
-            o["speedup_eigenpairs_per_s_vs_zero"] = z["ms_per_wave_solve"] / o["ms_per_wave_solve"]
-            o["Sv_rel_diff_vs_zero"] = ((Sv[pred] - Sv["zero"]).abs().max() / Sv["zero"].abs().max()).item()
-        out[f"omega_{omega:g}"] = res
+            o["speedup_wave_solve_vs_zero"] = z["ms_per_wave_solve"] / o["ms_per_wave_solve"]
+        out[f"one_period_omega_{omega:g}"] = res
     return out
-
 
 def periods_rule():
     """255^2 unit square, order 4, implicit 10 steps/period, omega 40 (adjusted),
@@ -399,13 +462,16 @@ def mapped_form():
     return out
 
 
-def headline_np_rule(budget: int = 200):
+def headline_np_rule(budget: int = 400):
     """The headline eigenproblem (2047^2, order 4, implicit, omega 120, k = 16)
-    with N_p from the lobe rule and m = 2k + 1, within `budget` wave-solves.
-    At N_p = 1 the lobe holds about 1000 eigenvalues above beta 0.8 and the
-    solve does not finish; the rule's N_p narrows it to about k."""
+    as a complete eigensolve, with N_p from the lobe rule and m = 2k + 1: at
+    N_p = 1 the lobe holds about 1000 eigenvalues above beta 0.8 and the solve
+    does not finish; the rule's N_p narrows it to about k.  Eigenpairs/s at
+    eig-res <= 1e-8, every eigenvalue checked against the closed form."""
+    import numpy as np
     import torch
     import synthetic
+    from oracle import discrete as D
     from paper_2507_18282_amd import Operator, choose_periods
     P = synthetic.config_square_order4_implicit()
     n_p, n_lobe = choose_periods(P.length, P.omega, P.k)
@@ -419,17 +485,22 @@ def headline_np_rule(budget: int = 200):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ok = sum(1 for x in r.res if x <= 1e-8)
+    h = D.spacing(P.n, P.length)
+    mu_cf = np.sort(D.mu_all(P.n, h, P.order).ravel())
+    errs = [float(np.min(np.abs(mu_cf - m)) / m) for m in r.mu]
     log(f"headline with the N_p rule: {ok} pairs, {r.wave_solves} wave-solves, {r.restarts} restarts, "
         f"{r.probes} runs, {dt:.1f} s")
     out = {"workload": "unit square 2049^2 points (2047^2 interior), order 4, implicit 10 steps/period, omega 120 "
                        "(adjusted), FP64 multigrid to 1e-10 (automatic depth), k=16, m=33",
+           "value": ok / dt, "unit": "eigenpairs/s",
            "n_p": n_p, "eigenvalues_in_lobe": n_lobe, "pairs": ok, "wave_solves": r.wave_solves,
            "restarts": r.restarts, "runs": r.probes, "seconds": dt, "max_res": max(r.res) if r.res else None,
-           "pt_updates_per_s": r.pt_updates / dt, "status": r.status,
+           "max_mu_rel_err_vs_closed_form": max(errs) if errs else None,
+           "pt_updates_per_s": r.pt_updates / dt,
+           "mg_cycles_per_implicit_solve": r.mg_cycles / max(1, r.time_steps), "status": r.status,
            "mu": list(r.mu)}
     op.close()
     return out
-
 
 def many_pairs(ks=None):
     """The square128 grid (127^2 interior), order 2, implicit 10 steps/period,
@@ -466,22 +537,68 @@ def many_pairs(ks=None):
     return out
 
 
-def mixed_cube():
-    """255^3 cube, order 2, implicit 10 steps/period, omega 40: mixed precision
+def mixed_cube(n_cube: int = CUBE_N):
+    """Unit cube, order 2, implicit 10 steps/period, omega 40 (adjusted), k = 8,
+    m = 17, N_p from the lobe rule: complete eigensolves in mixed precision
     (FP32 inner multigrid + FP64 defect correction, FP32 filter accumulation)
-    against FP64, two wave-solves each from the same start vector."""
+    and in FP64 with the same solver settings (Ritz tolerance MIXED_TOL_RITZ,
+    deflation probes for the repeated eigenvalues, CUBE_BUDGET wave-solves),
+    each eigenvalue compared with the closed form and with the FP64 solve's,
+    eig-res stated; and the cost of one period on the 255^3 grid in both
+    precisions (S^2 v compared)."""
+    import numpy as np
     import torch
     import synthetic
-    from paper_2507_18282_amd import Operator, fill_uniform
-    P = synthetic.config_cube_mixed()
-    out = {"workload": "unit cube 257^3 points (255^3 interior), order 2, implicit 10 steps/period, omega 40 "
-                       "(adjusted), multigrid to 1e-10"}
-    Sv = {}
+    from oracle import discrete as D
+    from paper_2507_18282_amd import Operator, choose_periods, fill_uniform
+    P = synthetic.config_cube_mixed(n=n_cube)
+    n_p, n_lobe = choose_periods(P.length, P.omega, P.k)
+    h = D.spacing(P.n, P.length)
+    mu_cf = np.sort(D.mu_all(P.n, h, P.order).ravel())
+    out = {"workload": f"unit cube {n_cube + 2}^3 points ({n_cube}^3 interior), order 2, implicit 10 steps/period, "
+                       f"omega 40 (adjusted), N_p {n_p} (lobe rule), k=8, m=17, multigrid to 1e-10",
+           "n_p": n_p, "eigenvalues_in_lobe": n_lobe}
+    res = {}
     for prec in ("mixed", "fp64"):
-        op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its,
-                      adjust_omega=True, precision=prec, mg_tol=P.mg_tol)
-        v = fill_uniform(op.n_active, P.seed)
-        w = op.apply_filter(v)  # warm
+        op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=n_p,
+                      adjust_omega=True, precision=prec, mg_tol=P.mg_tol, mg_max_levels=MG_LEVELS,
+                      mg_coarse_sweeps=MG_COARSE_SWEEPS)
+        # the same solver settings for both precisions: a Ritz tolerance above the
+        # FP32 noise of the mixed S v, and the same wave-solve budget
+        tol_ritz = MIXED_TOL_RITZ
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.eigs(P.k, P.m, seed=P.seed, tol_ritz=tol_ritz, tol_res=1e-4, want_vectors=False,
+                    raise_on_error=False, max_wave_solves=CUBE_BUDGET)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        errs = [float(np.min(np.abs(mu_cf - m)) / m) for m in r.mu]
+        res[prec] = r
+        ok = sum(1 for e in errs if e <= (1e-5 if prec == "mixed" else 1e-10))
+        out[prec] = {"pairs_returned": len(r.mu), "pairs_within_tolerance": ok,
+                     "tolerance_vs_closed_form": 1e-5 if prec == "mixed" else 1e-10,
+                     "wave_solves": r.wave_solves, "seconds": dt, "eigenpairs_per_s": ok / dt,
+                     "ms_per_wave_solve": dt / max(1, r.wave_solves) * 1e3,
+                     "mg_cycles_per_implicit_solve": r.mg_cycles / max(1, r.time_steps), "status": r.status,
+                     "tol_ritz": tol_ritz, "max_res": max(r.res) if r.res else None,
+                     "per_pair": [{"mu": m, "rel_err_vs_closed_form": e, "eig_res": q}
+                                  for m, e, q in zip(r.mu, errs, r.res)]}
+        log(f"mixed cube {n_cube}^3 {prec}: {len(r.mu)} pairs, {r.wave_solves} wave-solves, {dt:.1f} s, "
+            f"max err vs closed form {max(errs) if errs else float('nan'):.2e}, "
+            f"max eig-res {max(r.res) if r.res else float('nan'):.2e}")
+        op.close()
+    a, b = sorted(res["mixed"].mu), sorted(res["fp64"].mu)
+    if a and b and len(a) == len(b):
+        out["mixed_vs_fp64_mu_rel_diff"] = [abs(x - y) / y for x, y in zip(a, b)]
+    # one period on 255^3: cost of each precision, S^2 v compared
+    Pb = synthetic.config_cube_mixed()
+    Sv, cost = {}, {}
+    for prec in ("mixed", "fp64"):
+        op = Operator(n=Pb.n, length=Pb.length, order=Pb.order, omega=Pb.omega, ts=Pb.ts, n_its=Pb.n_its,
+                      adjust_omega=True, precision=prec, mg_tol=Pb.mg_tol, mg_max_levels=MG_LEVELS,
+                      mg_coarse_sweeps=MG_COARSE_SWEEPS)
+        v = fill_uniform(op.n_active, Pb.seed)
+        w = op.apply_filter(v)
         torch.cuda.synchronize()
         op.reset_stats()
         t0 = time.perf_counter()
@@ -491,14 +608,13 @@ def mixed_cube():
         dt = time.perf_counter() - t0
         st = op.stats()
         Sv[prec] = w2
-        out[prec] = {"pt_updates_per_s": st["pt_updates"] / dt, "ms_per_wave_solve": dt / 2 * 1e3,
-                     "mg_cycles_per_implicit_solve": st["mg_cycles"] / max(1, st["mg_solves"])}
+        cost[prec] = {"pt_updates_per_s": st["pt_updates"] / dt, "ms_per_wave_solve": dt / 2 * 1e3,
+                      "mg_cycles_per_implicit_solve": st["mg_cycles"] / max(1, st["mg_solves"])}
         op.close()
-    d = (Sv["mixed"] - Sv["fp64"]).abs().max().item() / Sv["fp64"].abs().max().item()
-    out["mixed_vs_fp64_rel_err_S2v"] = d
-    out["speedup"] = out["mixed"]["pt_updates_per_s"] / out["fp64"]["pt_updates_per_s"]
+    cost["mixed_vs_fp64_rel_err_S2v"] = (Sv["mixed"] - Sv["fp64"]).abs().max().item() / Sv["fp64"].abs().max().item()
+    cost["speedup"] = cost["mixed"]["pt_updates_per_s"] / cost["fp64"]["pt_updates_per_s"]
+    out["one_period_255"] = cost
     return out
-
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
@@ -518,8 +634,14 @@ def main(argv=None) -> int:
     ap.add_argument("--only-mapped", action="store_true",
                     help="run only the curvilinear-grid form (mapped vs box wave-solve, annulus eigensolve)")
     ap.add_argument("--headline-np-rule", action="store_true",
-                    help="run only the headline eigenproblem with the N_p of the lobe rule (about 2.5 min) and "
-                         "print its JSON")
+                    help="run only the complete headline eigensolve with the N_p of the lobe rule and print its JSON")
+    ap.add_argument("--only-learned", action="store_true", help="run only the learned-guess form and print its JSON")
+    ap.add_argument("--only-cube", action="store_true", help="run only the mixed-vs-FP64 cube form and print its JSON")
+    ap.add_argument("--only-batch", action="store_true", help="run only the batched form and print its JSON")
+    ap.add_argument("--cube-n", type=int, default=CUBE_N,
+                    help="cube side of the mixed-vs-FP64 eigensolves (63 by default; 127 and 255 are longer runs)")
+    ap.add_argument("--no-headline-eigs", action="store_true",
+                    help="skip the complete headline eigensolve (the eigenpairs/s of the headline workload)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU decomposition is "
@@ -541,6 +663,15 @@ def main(argv=None) -> int:
         return 0
     if a.headline_np_rule:
         print(json.dumps({"form": "headline_np_rule", "result": headline_np_rule()}), flush=True)
+        return 0
+    if a.only_learned:
+        print(json.dumps({"form": "learned_vs_plain", "result": learned_vs_plain()}), flush=True)
+        return 0
+    if a.only_cube:
+        print(json.dumps({"form": "mixed_cube", "result": mixed_cube(a.cube_n)}), flush=True)
+        return 0
+    if a.only_batch:
+        print(json.dumps({"form": "batched_vs_plain", "result": batched_vs_plain(a.batch_budget)}), flush=True)
         return 0
     P = synthetic.config_square_order4_implicit()
     op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=P.n_p,
@@ -602,10 +733,14 @@ def main(argv=None) -> int:
            "workload": "unit square 64^2 interior (h = 1/65), order 2, explicit leapfrog CFL 0.5 (78 steps), "
                        "omega 15, Krylov dimension 16, 4 requested, seed 1"}
 
+    headline_eigs = None
+    if not a.no_headline_eigs:
+        headline_eigs = headline_np_rule()
+
     forms = {}
     if not a.no_forms:
         forms["batched_vs_plain"] = batched_vs_plain(a.batch_budget)
-        forms["mixed_cube"] = mixed_cube()
+        forms["mixed_cube"] = mixed_cube(a.cube_n)
         forms["learned_vs_plain"] = learned_vs_plain()
         forms["periods_rule"] = periods_rule()
         forms["many_pairs"] = many_pairs(a.many_k)
@@ -628,6 +763,7 @@ def main(argv=None) -> int:
                    "global_batch": 1, "parallelism": "single GPU"},
         "mg_cycles_per_implicit_solve": round(r.mg_cycles / max(1, r.time_steps), 3),
         "eigenpairs_per_s": eig,
+        "eigenpairs_per_s_headline": headline_eigs,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,

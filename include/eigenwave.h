@@ -123,11 +123,12 @@ typedef struct {
  *                      the Gram matrix x_i . b_j and the products x_k . b;
  *                      P. F. Fischer's method for successive right-hand
  *                      sides), or EW_PRED_CNN (the PROJ guess, or zero with
- *                      proj_window < 0, corrected by the learned network of
- *                      ew_cnn_*; 2D only; needs ew_op_set_cnn, else it is
- *                      that base guess).  Whatever the guess, the multigrid
- *                      iterates to mg_tol, so results agree with the zero
- *                      guess to that tolerance.
+ *                      proj_window < 0 or an empty window, corrected at the
+ *                      steps n >= 1 by the learned network of ew_cnn_* from
+ *                      its residual; 2D FP64 only; needs ew_op_set_cnn, else
+ *                      it is that base guess).  Whatever the guess, the
+ *                      multigrid iterates to mg_tol, so results agree with
+ *                      the zero guess to that tolerance.
  *   proj_window        solves kept for PROJ and CNN: 0 = 24, at most 32,
  *                      negative = none.
  *   mg_max_levels      implicit only: most multigrid levels (the finest
@@ -191,6 +192,9 @@ typedef struct {
     int64_t mg_cycles;        /* V-cycles over all implicit solves */
     int64_t laplacian_applies;
     int64_t cnn_guesses;      /* initial guesses made by the network */
+    int64_t guess_probes;     /* solves measured by ew_op_probe_guesses */
+    double base_rel_res_sum;  /* sum of ||b - M x0||/||b|| of the base guesses measured */
+    double guess_rel_res_sum; /* the same for the guesses the multigrid started from */
 } ew_op_stats;
 
 /* Create an operator on the current device.  The filter weights c_n, dt and
@@ -244,6 +248,14 @@ void ew_op_destroy(ew_op op);
 ew_status ew_op_get_info(ew_op op, ew_op_info* out);
 ew_status ew_op_get_stats(ew_op op, ew_op_stats* out);
 ew_status ew_op_reset_stats(ew_op op);
+/* Measurement of the initial guesses (implicit FP64 operators): while on,
+ * every solve of a step n >= 1 computes ||b - M x0||_2 / ||b||_2 for the base
+ * guess of its predictor and for the guess the multigrid starts from (they
+ * differ for EW_PRED_CNN with a network attached, where the base is the
+ * projection guess) and adds them to ew_op_stats (base_rel_res_sum,
+ * guess_rel_res_sum, guess_probes).  It costs a residual pass and a host
+ * round trip per measured guess; results do not change.  Host only. */
+ew_status ew_op_probe_guesses(ew_op op, int on);
 
 /* out_dev = S v_dev (both n_active FP64, device; may not alias).  This is the
  * paper's matVec (Alg. "WaveHoltz matrix-vector product"): the vector is the
@@ -456,26 +468,32 @@ ew_status ew_batch_eigs(ew_batch b, const ew_eigs_desc* descs, int k_cap, double
 
 /* ------------------------------------------------------------------------
  * Learned warm start for the implicit solves (not part of the paper's method:
- * a small network proposes the initial guess of each M S = 2 W^n solve; the
- * multigrid still iterates to mg_tol, so a poor guess costs cycles, never
- * accuracy).
+ * the paper solves each implicit step by multigrid to a relative residual
+ * tolerance, Sec. "An optimal O(N) eigenvalue solver", so an initial guess
+ * saves cycles only through its residual).  A small network corrects a base
+ * guess x0 of M x = b from that guess's residual; the multigrid still
+ * iterates to mg_tol, so a poor guess costs cycles, never accuracy.
  *
  * Network (3057 parameters, FP32 master copy, BF16 in the products with FP32
- * accumulation): input planes W^n/s, W^{n-1}/s, c2 = a w^2/(1 + a w^2) and
- * c3 = min(a/h^2, 100)/100 (a = dt^2/2, w = omega_used, h the spacing of the
- * first axis, s = RMS of W^n over the grid; every plane is zero outside the
- * grid); 3x3 convolution 4->16, bias, ReLU; 3x3 16->16, bias, ReLU; 3x3 16->1,
- * bias.  Output y gives the guess S0 = 2 W^n / (1 + a w^2) + s y.  Parameter
- * vector order: W1[16][4][3][3], b1[16], W2[16][16][3][3], b2[16],
+ * accumulation): input planes r/s, b/s_b, c2 = a w^2/(1 + a w^2) and
+ * c3 = min(a/h^2, 100)/100 (r = b - M x0, s = RMS of r, s_b = RMS of b over
+ * the grid, a = dt^2/2, w = omega_used, h the spacing of the first axis; every
+ * plane is zero outside the grid); 3x3 convolution 4->16, bias, ReLU; 3x3
+ * 16->16, bias, ReLU; 3x3 16->1, bias.  Output y gives the guess x0 + s y.
+ * Parameter vector order: W1[16][4][3][3], b1[16], W2[16][16][3][3], b2[16],
  * W3[1][16][3][3], b3[1]; W[o][i][ky][kx] multiplies the input at row offset
  * ky-1 and column offset kx-1.
  *
  * Training data are crops: an output window of crop x crop points (crop a
- * multiple of 16, 16..256) of the target (S - 2 W^n/(1 + a w^2))/s, with the
- * two field planes over the window plus 3 points on every side (zero outside
- * the grid), and per crop c2, c3 and the rectangle of the padded window that
- * lies inside the grid.  Loss: mean over all output points of the batch of
- * (y - target)^2.  Training: Adam (Kingma and Ba) on minibatches drawn with
+ * multiple of 16, 16..256) with the two field planes (r/s, b/s_b) over the
+ * window plus 3 points on every side (zero outside the grid), the target r/s
+ * over the window, and per crop c2, c3, a/h_x^2, a/h_y^2 and the rectangle of
+ * the padded window that lies inside the grid.  Loss: the mean over all
+ * window points of the batch of e^2, e = target - M y on the points whose
+ * stencil neighbours lie inside the window or beyond a wall of the grid (M =
+ * I - a L_h with L_h's wall closure, in units of the spacing), e = 0 on the
+ * other points; it is the squared initial residual left by the guess, divided
+ * by s^2.  Training: Adam (Kingma and Ba) on minibatches drawn with
  * replacement by SplitMix64.
  * ------------------------------------------------------------------------ */
 #define EW_CNN_PARAMS 3057
@@ -484,10 +502,11 @@ ew_status ew_batch_eigs(ew_batch b, const ew_eigs_desc* descs, int k_cap, double
 typedef struct ew_cnn_s* ew_cnn;
 typedef struct ew_cnn_data_s* ew_cnn_data;
 
-/* New network on the current device; weights drawn He-uniform from the
- * SplitMix64 stream `seed` (parameter i uses draw i: W = u sqrt(6/fan_in),
- * fan_in = 9 x input channels; biases 0).  Work is ordered on hip_stream.
- * Host-blocking. */
+/* New network on the current device; the weights of the two hidden layers
+ * drawn He-uniform from the SplitMix64 stream `seed` (parameter i uses draw i:
+ * W = u sqrt(6/fan_in), fan_in = 9 x input channels); the last layer and the
+ * biases start at 0, so that the untrained network returns the base guess.
+ * Work is ordered on hip_stream.  Host-blocking. */
 ew_status ew_cnn_create(uint64_t seed, void* hip_stream, ew_cnn* out);
 void ew_cnn_destroy(ew_cnn cnn);
 /* Copy EW_CNN_PARAMS FP32 parameters in or out (host arrays); set_params also
@@ -495,14 +514,16 @@ void ew_cnn_destroy(ew_cnn cnn);
 ew_status ew_cnn_set_params(ew_cnn cnn, const float* params_host);
 ew_status ew_cnn_get_params(ew_cnn cnn, float* params_host);
 
-/* Crop store with room for `capacity` crops of crop x crop outputs. */
-ew_status ew_cnn_data_create(int capacity, int crop, ew_cnn_data* out);
+/* Crop store with room for `capacity` crops of crop x crop outputs, for steps
+ * whose L_h has stencil order `order` (2 or 4). */
+ew_status ew_cnn_data_create(int capacity, int crop, int order, ew_cnn_data* out);
 void ew_cnn_data_destroy(ew_cnn_data d);
 ew_status ew_cnn_data_count(ew_cnn_data d, int* count);
 /* Append n caller-made crops: fields_dev [n][2][crop+6][crop+6] FP32
- * (W^n/s then W^{n-1}/s), target_dev [n][crop][crop] FP32, planes_host [n][2]
- * (c2, c3) and rect_host [n][4] (row0, row1, col0, col1: the half-open
- * rectangle of the padded window inside the grid).  Host-blocking. */
+ * (r/s then b/s_b), target_dev [n][crop][crop] FP32, planes_host [n][4]
+ * (c2, c3, a/h_x^2, a/h_y^2) and rect_host [n][4] (row0, row1, col0, col1: the
+ * half-open rectangle of the padded window inside the grid; a window edge on
+ * the grid's boundary is a wall).  Host-blocking. */
 ew_status ew_cnn_data_append(ew_cnn_data d, int n, const float* fields_dev, const float* target_dev,
                              const float* planes_host, const int* rect_host);
 /* Copy crops first..first+count-1 out, in the layout of ew_cnn_data_append
@@ -511,10 +532,12 @@ ew_status ew_cnn_data_read(ew_cnn_data d, int first, int count, float* fields_de
                            float* planes_host, int* rect_host);
 /* out_dev = S v_dev computed by the implicit FP64 2D operator `op` (as
  * ew_op_apply_filter), recording crops_per_step crops at each step n >= 1
- * (from the solve of M S = 2 W^n) until the store is full.  Window origins are
- * drawn from the SplitMix64 stream `seed` (successive calls continue it);
- * one eighth of the origin range on each side is clamped to the walls so that
- * walls are sampled.  The grid needs n[0], n[1] >= crop.  Host-blocking. */
+ * from the solve of M S = 2 W^n, at the operator's base guess x0 (the guess of
+ * its predictor; for EW_PRED_CNN the projection guess before the correction)
+ * until the store is full.  Window origins are drawn from the SplitMix64
+ * stream `seed` (successive calls continue it); one eighth of the origin range
+ * on each side is clamped to the walls so that walls are sampled.  The grid
+ * needs n[0], n[1] >= crop and the store's order.  Host-blocking. */
 ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* v_dev, double* out_dev, int crops_per_step,
                               uint64_t seed);
 
@@ -543,12 +566,18 @@ typedef struct {
  * continuing the optimiser state of earlier calls.  Host-blocking. */
 ew_status ew_cnn_train(ew_cnn cnn, ew_cnn_data d, const ew_cnn_train_desc* desc, ew_cnn_train_stats* stats);
 
-/* Attach (cnn != NULL) or detach the network used by EW_PRED_CNN.  The
- * network is not owned and must outlive its use by op. */
+/* Attach (cnn != NULL) or detach the network used by EW_PRED_CNN (implicit
+ * FP64 2D operators; EW_ERR_UNSUPPORTED for mixed precision).  The network is
+ * not owned and must outlive its use by op.  Attaching allocates one vector
+ * of the operator's size. */
 ew_status ew_op_set_cnn(ew_op op, ew_cnn cnn);
-/* guess_dev = the network's initial guess for M S = 2 wn_dev given W^{n-1} =
- * wprev_dev (implicit 2D operator with a network attached).  Stream-ordered. */
-ew_status ew_op_cnn_guess(ew_op op, const double* wn_dev, const double* wprev_dev, double* guess_dev);
+/* guess_dev = the learned guess for M x = b_dev (implicit 2D FP64 operator
+ * with a network attached): the base guess x0 (the projection on the
+ * operator's window of earlier solves for EW_PRED_PROJ and EW_PRED_CNN, else
+ * zero; nothing is added to the window) corrected by the network.  base_dev
+ * (may be NULL) receives x0.  Vectors n_active FP64, device, not aliased.
+ * Host-blocking. */
+ew_status ew_op_cnn_guess(ew_op op, const double* b_dev, double* base_dev, double* guess_dev);
 
 /* Fill x_dev (n FP64, device) with SplitMix64 uniform[-1,1) values of stream
  * `seed`: element i is 2*((z_i >> 11) * 2^-53) - 1 with z_i the SplitMix64

@@ -60,14 +60,18 @@ def pack(p: dict) -> np.ndarray:
     return np.concatenate([np.asarray(p[name], dtype=np.float64).ravel() for name, _ in SHAPES])
 
 
-def init_params(seed_values: np.ndarray) -> np.ndarray:
+def init_params(seed_values: np.ndarray, last_layer_zero: bool = True) -> np.ndarray:
     """He-style initialisation from given uniform[-1,1) draws (one per parameter):
-    weight ~ u * sqrt(6 / fan_in), biases zero."""
+    weight ~ u * sqrt(6 / fan_in), biases zero; with last_layer_zero the last
+    layer's weights start at zero too, so that the untrained network returns
+    the base guess unchanged (a He-scaled last layer starts from a guess whose
+    residual M y is hundreds of times that of the base, and Adam on the
+    residual loss then settles on y = 0 instead of a correction)."""
     theta = np.zeros(N_PARAMS)
     off = 0
     for name, shape in SHAPES:
         n = int(np.prod(shape))
-        if name.startswith("W"):
+        if name.startswith("W") and not (last_layer_zero and name == "W3"):
             fan_in = shape[1] * 9
             theta[off:off + n] = seed_values[off:off + n] * np.sqrt(6.0 / fan_in)
         off += n

@@ -160,7 +160,12 @@ class Operator:
     def stats(self) -> dict:
         s = _lib.OpStats()
         check(self._lib.ew_op_get_stats(self._h, ctypes.byref(s)))
-        return {f: int(getattr(s, f)) for f, _ in _lib.OpStats._fields_}
+        return {f: (float(getattr(s, f)) if t is ctypes.c_double else int(getattr(s, f)))
+                for f, t in _lib.OpStats._fields_}
+
+    def probe_guesses(self, on: bool = True) -> None:
+        """Measure the initial residuals of the guesses (see ew_op_probe_guesses)."""
+        check(self._lib.ew_op_probe_guesses(self._h, int(bool(on))))
 
     def reset_stats(self) -> None:
         check(self._lib.ew_op_reset_stats(self._h))
@@ -205,9 +210,12 @@ class Operator:
         check(self._lib.ew_op_set_cnn(self._h, cnn._h if cnn is not None else None))
         self._cnn = cnn
 
-    def cnn_guess(self, wn, wprev, out=None):
+    def cnn_guess(self, b, base=None, out=None):
+        """The learned guess for M x = b (see ew_op_cnn_guess); with `base` a
+        tensor, it also receives the base guess."""
         out = self._new() if out is None else out
-        check(self._lib.ew_op_cnn_guess(self._h, _dev_ptr(wn, self.n_active), _dev_ptr(wprev, self.n_active),
+        check(self._lib.ew_op_cnn_guess(self._h, _dev_ptr(b, self.n_active),
+                                        _dev_ptr(base, self.n_active) if base is not None else None,
                                         _dev_ptr(out, self.n_active)))
         return out
 
@@ -472,12 +480,13 @@ class Cnn:
 class CropStore:
     """Training crops for the network (see ew_cnn_data_create)."""
 
-    def __init__(self, capacity: int, crop: int = 128):
+    def __init__(self, capacity: int, crop: int = 128, order: int = 4):
         self._lib = load()
         self._h = ctypes.c_void_p()
-        check(self._lib.ew_cnn_data_create(int(capacity), int(crop), ctypes.byref(self._h)))
+        check(self._lib.ew_cnn_data_create(int(capacity), int(crop), int(order), ctypes.byref(self._h)))
         self.capacity = int(capacity)
         self.crop = int(crop)
+        self.order = int(order)
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -500,7 +509,7 @@ class CropStore:
         import numpy as np
         n = len(planes)
         cp = self.crop + 2 * _lib.CNN_HALO
-        pl = np.ascontiguousarray(planes, dtype=np.float32).reshape(n, 2)
+        pl = np.ascontiguousarray(planes, dtype=np.float32).reshape(n, 4)
         rc = np.ascontiguousarray(rects, dtype=np.int32).reshape(n, 4)
         check(self._lib.ew_cnn_data_append(self._h, n, _f32_ptr(fields, n * 2 * cp * cp),
                                            _f32_ptr(target, n * self.crop * self.crop),
@@ -514,7 +523,7 @@ class CropStore:
         cp = self.crop + 2 * _lib.CNN_HALO
         fields = torch.empty((count, 2, cp, cp), dtype=torch.float32, device="cuda")
         target = torch.empty((count, self.crop, self.crop), dtype=torch.float32, device="cuda")
-        planes = np.zeros((count, 2), dtype=np.float32)
+        planes = np.zeros((count, 4), dtype=np.float32)
         rects = np.zeros((count, 4), dtype=np.int32)
         check(self._lib.ew_cnn_data_read(self._h, int(first), int(count), int(fields.data_ptr()),
                                          int(target.data_ptr()), planes.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),

@@ -45,7 +45,8 @@ class OpInfo(ctypes.Structure):
 class OpStats(ctypes.Structure):
     _fields_ = [("wave_solves", c_int64), ("time_steps", c_int64), ("pt_updates", c_int64),
                 ("mg_solves", c_int64), ("mg_cycles", c_int64), ("laplacian_applies", c_int64),
-                ("cnn_guesses", c_int64)]
+                ("cnn_guesses", c_int64), ("guess_probes", c_int64), ("base_rel_res_sum", c_double),
+                ("guess_rel_res_sum", c_double)]
 
 
 class EigsDesc(ctypes.Structure):
@@ -97,6 +98,7 @@ SIGNATURES = {
     "ew_op_get_info": (c_int, [c_void_p, POINTER(OpInfo)]),
     "ew_op_get_stats": (c_int, [c_void_p, POINTER(OpStats)]),
     "ew_op_reset_stats": (c_int, [c_void_p]),
+    "ew_op_probe_guesses": (c_int, [c_void_p, c_int]),
     "ew_op_apply_filter": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ew_op_apply_laplacian": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ew_apply_filter_noalloc": (c_int, [POINTER(GridDesc), POINTER(OpDesc), c_void_p, c_void_p, c_void_p]),
@@ -120,7 +122,7 @@ SIGNATURES = {
     "ew_cnn_destroy": (None, [c_void_p]),
     "ew_cnn_set_params": (c_int, [c_void_p, POINTER(ctypes.c_float)]),
     "ew_cnn_get_params": (c_int, [c_void_p, POINTER(ctypes.c_float)]),
-    "ew_cnn_data_create": (c_int, [c_int, c_int, POINTER(c_void_p)]),
+    "ew_cnn_data_create": (c_int, [c_int, c_int, c_int, POINTER(c_void_p)]),
     "ew_cnn_data_destroy": (None, [c_void_p]),
     "ew_cnn_data_count": (c_int, [c_void_p, POINTER(c_int)]),
     "ew_cnn_data_append": (c_int, [c_void_p, c_int, c_void_p, c_void_p, POINTER(ctypes.c_float), POINTER(c_int)]),

@@ -27,32 +27,47 @@ struct CnnPacked {
     float pad[3];
 };
 
-// One training crop: constant planes and the half-open rectangle of the
-// padded window that lies inside the grid.
+// One training crop: constant planes, the half-open rectangle of the padded
+// window that lies inside the grid (a window edge on the grid's boundary is a
+// wall), and the step's operator M = I - a L_h in units of the spacing:
+// a / h_x^2, a / h_y^2 and the stencil order.
 struct CropMeta {
     float c2, c3;
     int r0, r1, c0, c1;
+    float ahx, ahy;
+    int order;
+    int pad;
 };
 
 hipError_t launch_cnn_pack(const float* params, CnnPacked* pk, hipStream_t s);
 
-// guess = base_scale * wn + s * y over an nx x ny grid, y the network output
-// on the planes (wn * inv_s, wprev * inv_s, c2, c3).
-hipError_t launch_cnn_infer(const CnnPacked* pk, const double* wn, const double* wprev, double* guess, int nx,
-                            int ny, double inv_s, double s, double base_scale, float c2, float c3, hipStream_t st);
+// x += s y over an nx x ny grid, y the network output on the planes
+// (r / s, b * b_scale, c2, c3); s = sqrt(sum of the kRedBlocks partials of
+// r^2 * inv_n) is read on the device (a zero residual leaves x unchanged).
+hipError_t launch_cnn_infer(const CnnPacked* pk, const double* r, const double* b, double* x, int nx, int ny,
+                            const double* r2_partials, double inv_n, double b_scale, float c2, float c3,
+                            hipStream_t st);
 
 // Crops from one implicit step: for crop j with window origin (oy[j], ox[j]),
-// fields (W^n, W^{n-1}) * inv_s over the padded window and target
-// (S - base_scale W^n) * inv_s over the window.
-hipError_t launch_cnn_extract(const double* wn, const double* wprev, const double* S, int nx, int ny,
-                              double inv_s, double base_scale, const int* origins_dev, int ncrop, int crop,
-                              float* fields_out, float* target_out, hipStream_t st);
+// fields (r * inv_s, b * b_scale) over the padded window and target
+// r * inv_s over the window.
+hipError_t launch_cnn_extract(const double* r, const double* b, int nx, int ny, double inv_s, double b_scale,
+                              const int* origins_dev, int ncrop, int crop, float* fields_out, float* target_out,
+                              hipStream_t st);
 
 // Over the crops ids[0..count): mode 0 writes y_out; mode 1 writes per-block
-// partial gradients (pgrad[block][kCnnParams]) and loss partials.
-hipError_t launch_cnn_train(const CnnPacked* pk, const float* fields, const float* target, const CropMeta* meta,
-                            const int* ids, int count, int crop, int mode, float* y_out, float inv_npix,
-                            float* pgrad, double* ploss, int nblocks, hipStream_t st);
+// partial gradients (pgrad[block][kCnnParams]) from dL/dy = dy_in and loss
+// partials sum e_in^2 * inv_npix (dy_in, e_in: [count][crop][crop]).
+hipError_t launch_cnn_train(const CnnPacked* pk, const float* fields, const CropMeta* meta, const int* ids,
+                            int count, int crop, int mode, float* y_out, const float* dy_in, const float* e_in,
+                            float inv_npix, float* pgrad, double* ploss, int nblocks, hipStream_t st);
+
+// Residual loss of the residual form on the crops ids[0..count) with network
+// outputs y ([count][crop][crop]): e = target - M y on the loss points (every
+// stencil neighbour inside the window or beyond a wall, the wall closures of
+// L_h applied), 0 elsewhere; then dy = -2 inv_npix M e (M is symmetric).
+hipError_t launch_cnn_resloss(const float* y, const float* target, const CropMeta* meta, const int* ids, int count,
+                              int crop, float inv_npix, float* e_out, float* dy_out, hipStream_t st);
 int cnn_train_blocks(int count, int crop);
 
 // grad[i] = sum over blocks of pgrad[b][i]; *loss = sum of ploss (fixed order).

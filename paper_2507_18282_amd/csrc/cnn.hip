@@ -1,7 +1,9 @@
 // Learned warm start for the implicit solves: the network object (FP32
 // master parameters, Adam state, the packed BF16 image), the crop store, data
-// collection from wave-solves, training, and the predictor used by the
-// implicit step.  All arithmetic runs in cnn_kernels.hip.
+// collection from wave-solves, training on the residual loss, and the
+// correction of the base guess used by the implicit step.  All arithmetic
+// runs in cnn_kernels.hip and the multigrid's residual kernel.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -26,6 +28,11 @@ struct Cnn {
     double* loss_host = nullptr;
     int* ids_dev = nullptr;
     int ids_cap = 0;
+    // per-batch outputs, residuals and dL/dy of the residual loss
+    float* ybuf = nullptr;
+    float* ebuf = nullptr;
+    float* dybuf = nullptr;
+    int64_t batch_cap = 0;     // elements of each of the three
     int64_t adam_t = 0;
     std::vector<void*> allocations;
 
@@ -42,6 +49,14 @@ struct Cnn {
         allocations.push_back(*p);
         return EW_OK;
     }
+    ew_status ensure_batch(int64_t elems) {
+        if (elems <= batch_cap) return EW_OK;
+        EW_TRY(alloc((void**)&ybuf, (size_t)elems * sizeof(float)));
+        EW_TRY(alloc((void**)&ebuf, (size_t)elems * sizeof(float)));
+        EW_TRY(alloc((void**)&dybuf, (size_t)elems * sizeof(float)));
+        batch_cap = elems;
+        return EW_OK;
+    }
     ew_status ensure_ids(int n) {
         if (n <= ids_cap) return EW_OK;
         void* p = nullptr;
@@ -55,6 +70,7 @@ struct Cnn {
 struct CnnData {
     int device = 0;
     int capacity = 0, crop = 0, count = 0;
+    int order = 4;             // stencil order of the steps' M
     float* fields = nullptr;   // [capacity][2][crop+6][crop+6]
     float* target = nullptr;   // [capacity][crop][crop]
     CropMeta* meta = nullptr;  // [capacity]
@@ -108,40 +124,65 @@ ew_status check_range(CnnData* d, int first, int count) {
     return EW_OK;
 }
 
-// One pass of the training kernel over ids[0..count) of d, then the gradient
-// reduction (mode 1).
+// One pass over ids[0..count) of d: mode 0 writes the network outputs to
+// y_out; mode 1 forms the outputs, the residual loss and dL/dy
+// (k_cnn_resid, k_cnn_resgrad), backpropagates, and reduces the gradient and
+// the loss (mean over the batch's window points of e^2).
 ew_status train_pass(Cnn* c, CnnData* d, const int* ids_dev, int count, int mode, float* y_out, float* grad,
                      double* loss_dev) {
     const int nb = cnn_train_blocks(count, d->crop);
     const float inv_npix = (float)(1.0 / ((double)count * d->crop * d->crop));
-    EW_HIP_TRY(launch_cnn_train(c->pk, d->fields, d->target, d->meta, ids_dev, count, d->crop, mode, y_out,
+    if (mode == 0) {
+        EW_HIP_TRY(launch_cnn_train(c->pk, d->fields, d->meta, ids_dev, count, d->crop, 0, y_out, nullptr, nullptr,
+                                    inv_npix, c->pgrad, c->ploss, nb, c->stream));
+        return EW_OK;
+    }
+    EW_TRY(c->ensure_batch((int64_t)count * d->crop * d->crop));
+    EW_HIP_TRY(launch_cnn_train(c->pk, d->fields, d->meta, ids_dev, count, d->crop, 0, c->ybuf, nullptr, nullptr,
                                 inv_npix, c->pgrad, c->ploss, nb, c->stream));
-    if (mode == 1) EW_HIP_TRY(launch_cnn_reduce(c->pgrad, c->ploss, nb, grad, loss_dev, c->stream));
+    EW_HIP_TRY(launch_cnn_resloss(c->ybuf, d->target, d->meta, ids_dev, count, d->crop, inv_npix, c->ebuf, c->dybuf,
+                                  c->stream));
+    EW_HIP_TRY(launch_cnn_train(c->pk, d->fields, d->meta, ids_dev, count, d->crop, 1, nullptr, c->dybuf, c->ebuf,
+                                inv_npix, c->pgrad, c->ploss, nb, c->stream));
+    EW_HIP_TRY(launch_cnn_reduce(c->pgrad, c->ploss, nb, grad, loss_dev, c->stream));
+    return EW_OK;
+}
+
+// ||bscale b||^2 from the value the projection guess left for b, or a reduction.
+ew_status rhs_sq(Op* op, const double* b, double bscale, double* out) {
+    double bb;
+    if (op->bb_src == b) {
+        bb = op->bb_val;
+    } else {
+        EW_HIP_TRY(launch_dot_partial(b, b, op->N, op->partial_dev, op->stream));
+        EW_TRY(op->host_sum_partials(&bb));
+        op->bb_src = b;
+        op->bb_val = bb;
+    }
+    if (!std::isfinite(bb)) return fail(EW_ERR_NONFINITE, "non-finite right-hand side");
+    *out = bb * bscale * bscale;
     return EW_OK;
 }
 
 }  // namespace
 
-// Initial guess S0 = 2 W^n / (1 + a w^2) + s y for M S = 2 W^n.
-ew_status cnn_predict(Op* op, const double* wcur, const double* wprev, double* guess_S) {
+// The network's correction of the base guess x of M x = bscale b:
+// r = bscale b - M x, then x += s y with y = network(r / s, b / s_b, c2, c3),
+// s = RMS(r) (read on the device from the residual's norm partials), s_b =
+// RMS(bscale b).  x must hold the base guess (zero filled by the caller).
+ew_status cnn_correct(Op* op, const double* b, double bscale, double* x) {
     Cnn* c = op->cnn;
     if (!c) return fail(EW_ERR_INVALID_ARG, "no network attached");
-    EW_HIP_TRY(launch_dot_partial(wcur, wcur, op->N, op->partial_dev, op->stream));
     double bb = 0.0;
-    EW_TRY(op->host_sum_partials(&bb));
-    if (!std::isfinite(bb)) return fail(EW_ERR_NONFINITE, "non-finite W^n");
-    op->bb_src = wcur;
-    op->bb_val = bb;
-    if (bb == 0.0) {
-        EW_HIP_TRY(launch_fill<double>(guess_S, op->N, 0.0, op->stream));
-        return EW_OK;
-    }
-    const double s = std::sqrt(bb / (double)op->N);
+    EW_TRY(rhs_sq(op, b, bscale, &bb));
+    if (bb == 0.0) return EW_OK;
+    const double sb = std::sqrt(bb / (double)op->N);
+    EW_HIP_TRY((launch_residual_tile<double, double>(x, b, bscale, op->g, op->order, op->a, op->tile_partial_dev,
+                                                     op->partial_dev, op->cnn_r, op->stream)));
     float c2, c3;
     step_planes(op->a, op->omega_used, op->h[0], &c2, &c3);
-    const double base = 2.0 / (1.0 + op->a * op->omega_used * op->omega_used);
-    EW_HIP_TRY(launch_cnn_infer(c->pk, wcur, wprev, guess_S, (int)op->n[0], (int)op->n[1], 1.0 / s, s, base, c2, c3,
-                                op->stream));
+    EW_HIP_TRY(launch_cnn_infer(c->pk, op->cnn_r, b, x, (int)op->n[0], (int)op->n[1], op->partial_dev,
+                                1.0 / (double)op->N, bscale / sb, c2, c3, op->stream));
     op->stats.cnn_guesses++;
     return EW_OK;
 }
@@ -167,10 +208,14 @@ extern "C" ew_status ew_cnn_create(uint64_t seed, void* hip_stream, ew_cnn* out)
     EW_TRY(c->alloc((void**)&c->pgrad, (size_t)kCnnTrainBlocks * kCnnParams * sizeof(float)));
     EW_TRY(c->alloc((void**)&c->ploss, kCnnTrainBlocks * sizeof(double)));
     EW_HIP_TRY(hipHostMalloc((void**)&c->loss_host, 2 * sizeof(double), hipHostMallocDefault));
-    // He-uniform initialisation: W = u sqrt(6 / fan_in), biases zero.
+    // He-uniform initialisation of the two hidden layers, W = u sqrt(6 / fan_in);
+    // the last layer and the biases start at zero, so that the untrained
+    // network returns the base guess (a He-scaled last layer starts from
+    // residuals hundreds of times the base's, from which training on the
+    // residual loss settles on a zero output instead of a correction).
     std::vector<float> init(kCnnParams, 0.f);
     struct Block { int off, n, fan_in; };
-    const Block blocks[3] = {{kOffW1, 576, 4 * 9}, {kOffW2, 2304, 16 * 9}, {kOffW3, 144, 16 * 9}};
+    const Block blocks[2] = {{kOffW1, 576, 4 * 9}, {kOffW2, 2304, 16 * 9}};
     for (const Block& b : blocks)
         for (int i = b.off; i < b.off + b.n; ++i)
             init[i] = (float)((2.0 * unit_at(seed, (uint64_t)i) - 1.0) * std::sqrt(6.0 / b.fan_in));
@@ -206,15 +251,17 @@ extern "C" ew_status ew_cnn_get_params(ew_cnn c, float* params_host) {
     return EW_OK;
 }
 
-extern "C" ew_status ew_cnn_data_create(int capacity, int crop, ew_cnn_data* out) {
+extern "C" ew_status ew_cnn_data_create(int capacity, int crop, int order, ew_cnn_data* out) {
     if (!out) return fail(EW_ERR_INVALID_ARG, "out is null");
     *out = nullptr;
     if (capacity <= 0) return fail(EW_ERR_INVALID_ARG, "capacity must be positive");
     if (crop < 16 || crop > 256 || crop % 16 != 0) return fail(EW_ERR_INVALID_ARG, "crop must be a multiple of 16 in [16, 256]");
+    if (order != 2 && order != 4) return fail(EW_ERR_INVALID_ARG, "order must be 2 or 4");
     std::unique_ptr<ew_cnn_data_s> d(new ew_cnn_data_s());
     EW_HIP_TRY(hipGetDevice(&d->device));
     d->capacity = capacity;
     d->crop = crop;
+    d->order = order;
     const size_t fb = (size_t)capacity * d->field_elems() * sizeof(float);
     const size_t tb = (size_t)capacity * d->target_elems() * sizeof(float);
     void* p = nullptr;
@@ -245,8 +292,14 @@ extern "C" ew_status ew_cnn_data_append(ew_cnn_data d, int n, const float* field
     std::vector<CropMeta> meta(n);
     for (int i = 0; i < n; ++i) {
         CropMeta& m = meta[i];
-        m.c2 = planes_host[2 * i];
-        m.c3 = planes_host[2 * i + 1];
+        m.c2 = planes_host[4 * i];
+        m.c3 = planes_host[4 * i + 1];
+        m.ahx = planes_host[4 * i + 2];
+        m.ahy = planes_host[4 * i + 3];
+        m.order = d->order;
+        m.pad = 0;
+        if (!(m.ahx >= 0.f) || !(m.ahy >= 0.f) || !std::isfinite(m.ahx) || !std::isfinite(m.ahy))
+            return fail(EW_ERR_INVALID_ARG, "a / h^2 must be finite and >= 0");
         m.r0 = rect_host[4 * i];
         m.r1 = rect_host[4 * i + 1];
         m.c0 = rect_host[4 * i + 2];
@@ -278,8 +331,10 @@ extern "C" ew_status ew_cnn_data_read(ew_cnn_data d, int first, int count, float
         EW_HIP_TRY(hipMemcpy(meta.data(), d->meta + first, count * sizeof(CropMeta), hipMemcpyDeviceToHost));
         for (int i = 0; i < count; ++i) {
             if (planes_host) {
-                planes_host[2 * i] = meta[i].c2;
-                planes_host[2 * i + 1] = meta[i].c3;
+                planes_host[4 * i] = meta[i].c2;
+                planes_host[4 * i + 1] = meta[i].c3;
+                planes_host[4 * i + 2] = meta[i].ahx;
+                planes_host[4 * i + 3] = meta[i].ahy;
             }
             if (rect_host) {
                 rect_host[4 * i] = meta[i].r0;
@@ -298,6 +353,7 @@ extern "C" ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* 
     if (v_dev == out_dev) return fail(EW_ERR_INVALID_ARG, "v and out may not alias");
     EW_TRY(check_cnn_op(op));
     if (op->mixed) return fail(EW_ERR_UNSUPPORTED, "crops are collected from FP64 operators");
+    if (op->order != d->order) return fail(EW_ERR_INVALID_ARG, "the operator's order differs from the store's");
     if (crops_per_step <= 0) return fail(EW_ERR_INVALID_ARG, "crops_per_step must be positive");
     const int nx = (int)op->n[0], ny = (int)op->n[1], crop = d->crop;
     if (nx < crop || ny < crop) return fail(EW_ERR_INVALID_ARG, "grid smaller than the crop");
@@ -309,9 +365,25 @@ extern "C" ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* 
         d->origins_dev = (int*)p;
         d->origins_cap = crops_per_step;
     }
+    // the base guess's residual of each step, for this call only
+    double* rbuf = nullptr;
+    {
+        void* p = nullptr;
+        hipError_t e = dev_alloc(&p, (size_t)op->N * sizeof(double), op->stream);
+        if (e != hipSuccess) return fail(EW_ERR_OOM, "hipMalloc of the residual buffer failed");
+        rbuf = (double*)p;
+    }
+    struct FreeOnExit {
+        void* p;
+        hipStream_t s;
+        ~FreeOnExit() {
+            (void)hipStreamSynchronize(s);
+            dev_free(p);
+        }
+    } free_rbuf{rbuf, op->stream};
     float c2, c3;
     step_planes(op->a, op->omega_used, op->h[0], &c2, &c3);
-    const double base = 2.0 / (1.0 + op->a * op->omega_used * op->omega_used);
+    const float ahx = (float)(op->a / (op->h[0] * op->h[0])), ahy = (float)(op->a / (op->h[1] * op->h[1]));
     const int CP = crop + 2 * kCnnHalo;
     // origin along an axis of n points: one eighth of the range beyond each end clamps to the wall
     auto origin = [&](int n) {
@@ -321,14 +393,22 @@ extern "C" ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* 
         int o = (int)std::floor(u * (double)(range + 2 * extra)) - extra;
         return o < 0 ? 0 : (o > range - 1 ? range - 1 : o);
     };
-    op->step_hook = [&](const double* wn, const double* wprev, const double* S) -> ew_status {
+    // At every solve M x = bscale b of a step n >= 1, once the operator's base
+    // guess x0 is formed (before the multigrid): r = bscale b - M x0, crops of
+    // (r / s, bscale b / s_b) and the target r / s.
+    op->guess_hook = [&](const double* b, double bscale, double* x0, bool x_is_zero) -> ew_status {
+        if (x_is_zero) EW_HIP_TRY(launch_fill<double>(x0, op->N, 0.0, op->stream));
         const int k = std::min(crops_per_step, d->capacity - d->count);
         if (k <= 0) return EW_OK;
-        EW_HIP_TRY(launch_dot_partial(wn, wn, op->N, op->partial_dev, op->stream));
         double bb = 0.0;
-        EW_TRY(op->host_sum_partials(&bb));
-        if (!(bb > 0.0) || !std::isfinite(bb)) return EW_OK;  // nothing to learn from a zero level
-        const double s = std::sqrt(bb / (double)op->N);
+        EW_TRY(rhs_sq(op, b, bscale, &bb));
+        if (!(bb > 0.0)) return EW_OK;  // nothing to learn from a zero right-hand side
+        EW_HIP_TRY((launch_residual_tile<double, double>(x0, b, bscale, op->g, op->order, op->a, op->tile_partial_dev,
+                                                         op->partial_dev, rbuf, op->stream)));
+        double rr = 0.0;
+        EW_TRY(op->host_sum_partials(&rr));
+        if (!(rr > 0.0) || !std::isfinite(rr)) return EW_OK;  // an exact base guess: nothing to correct
+        const double s = std::sqrt(rr / (double)op->N), sb = std::sqrt(bb / (double)op->N);
         std::vector<int> org(2 * k);
         std::vector<CropMeta> meta(k);
         for (int j = 0; j < k; ++j) {
@@ -342,12 +422,16 @@ extern "C" ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* 
             m.r1 = std::min(CP, ny - (oy - kCnnHalo));
             m.c0 = std::max(0, kCnnHalo - ox);
             m.c1 = std::min(CP, nx - (ox - kCnnHalo));
+            m.ahx = ahx;
+            m.ahy = ahy;
+            m.order = d->order;
+            m.pad = 0;
         }
         EW_HIP_TRY(hipMemcpyAsync(d->origins_dev, org.data(), org.size() * sizeof(int), hipMemcpyHostToDevice,
                                   op->stream));
         EW_HIP_TRY(hipMemcpyAsync(d->meta + d->count, meta.data(), k * sizeof(CropMeta), hipMemcpyHostToDevice,
                                   op->stream));
-        EW_HIP_TRY(launch_cnn_extract(wn, wprev, S, nx, ny, 1.0 / s, base, d->origins_dev, k, crop,
+        EW_HIP_TRY(launch_cnn_extract(rbuf, b, nx, ny, 1.0 / s, bscale / sb, d->origins_dev, k, crop,
                                       d->fields + (int64_t)d->count * d->field_elems(),
                                       d->target + (int64_t)d->count * d->target_elems(), op->stream));
         // the host vectors above are read by the copies: finish before they go out of scope
@@ -356,7 +440,7 @@ extern "C" ew_status ew_cnn_data_collect(ew_cnn_data d, ew_op op, const double* 
         return EW_OK;
     };
     ew_status st = op->apply_filter(v_dev, out_dev);
-    op->step_hook = nullptr;
+    op->guess_hook = nullptr;
     if (st != EW_OK) return st;
     EW_HIP_TRY(hipStreamSynchronize(op->stream));
     return EW_OK;
@@ -422,8 +506,9 @@ extern "C" ew_status ew_cnn_train(ew_cnn c, ew_cnn_data d, const ew_cnn_train_de
                               c->stream));
     EW_HIP_TRY(hipStreamSynchronize(c->stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    // release the per-call loss log
-    c->allocations.pop_back();
+    // release the per-call loss log (the batch buffers the steps may have
+    // added after it stay with the network)
+    c->allocations.erase(std::find(c->allocations.begin(), c->allocations.end(), lp));
     dev_free(lp);
     if (stats) {
         stats->steps = desc->steps;
@@ -436,17 +521,32 @@ extern "C" ew_status ew_cnn_train(ew_cnn c, ew_cnn_data d, const ew_cnn_train_de
 
 extern "C" ew_status ew_op_set_cnn(ew_op op, ew_cnn cnn) {
     if (!op) return fail(EW_ERR_INVALID_ARG, "null operator");
-    if (cnn) EW_TRY(check_cnn_op(op));
+    if (cnn) {
+        EW_TRY(check_cnn_op(op));
+        if (op->mixed) return fail(EW_ERR_UNSUPPORTED, "the learned guess corrects FP64 solves");
+        if (!op->cnn_r) EW_TRY(op->alloc((void**)&op->cnn_r, (size_t)op->N * sizeof(double)));
+    }
     op->cnn = cnn;
     return EW_OK;
 }
 
-extern "C" ew_status ew_op_cnn_guess(ew_op op, const double* wn_dev, const double* wprev_dev, double* guess_dev) {
-    if (!op || !wn_dev || !wprev_dev || !guess_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
+extern "C" ew_status ew_op_cnn_guess(ew_op op, const double* b_dev, double* base_dev, double* guess_dev) {
+    if (!op || !b_dev || !guess_dev) return fail(EW_ERR_INVALID_ARG, "null argument");
     EW_TRY(check_cnn_op(op));
     if (!op->cnn) return fail(EW_ERR_INVALID_ARG, "no network attached");
-    if (guess_dev == wn_dev || guess_dev == wprev_dev) return fail(EW_ERR_INVALID_ARG, "guess may not alias inputs");
-    EW_TRY(cnn_predict(op, wn_dev, wprev_dev, guess_dev));
+    if (guess_dev == b_dev || base_dev == b_dev || (base_dev && base_dev == guess_dev))
+        return fail(EW_ERR_INVALID_ARG, "b, base and guess may not alias");
+    op->solve_kind = 1;
+    bool zero = true;
+    if (op->desc.predictor == EW_PRED_PROJ || op->desc.predictor == EW_PRED_CNN)
+        EW_TRY(op->proj_guess(b_dev, 1.0, guess_dev, &zero));
+    if (zero) EW_HIP_TRY(launch_fill<double>(guess_dev, op->N, 0.0, op->stream));
+    if (base_dev)
+        EW_HIP_TRY(hipMemcpyAsync(base_dev, guess_dev, op->N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));
+    EW_TRY(cnn_correct(op, b_dev, 1.0, guess_dev));
+    // no solve follows: the projection keeps no pair for this right-hand side
+    op->proj_rhs_ok = false;
     op->bb_src = nullptr;
+    EW_HIP_TRY(hipStreamSynchronize(op->stream));
     return EW_OK;
 }

@@ -16,6 +16,7 @@
 // registers for the whole kernel and B[c][p] is 16 consecutive frame points
 // p, each lane reading the 4 channels 4 (l / 16).. of its own point (8 B).
 #include "cnn.h"
+#include "stencil_dev.h"
 
 namespace ew {
 namespace {
@@ -164,11 +165,11 @@ constexpr size_t kInferLdsBytes =
     (size_t)(InferGeo::NXP * 8 > InferGeo::N2 * 32 ? InferGeo::NXP * 8 : InferGeo::N2 * 32) + 144 * 4;
 
 __global__ __launch_bounds__(kInferThreads) void k_cnn_infer(const CnnPacked* __restrict__ pk,
-                                                             const double* __restrict__ wn,
-                                                             const double* __restrict__ wprev,
-                                                             double* __restrict__ guess, int nx, int ny,
-                                                             double inv_s, double s, double base_scale, float c2,
-                                                             float c3) {
+                                                             const double* __restrict__ r,
+                                                             const double* __restrict__ bvec,
+                                                             double* __restrict__ x, int nx, int ny,
+                                                             const double* __restrict__ r2_partials, double inv_n,
+                                                             double b_scale, float c2, float c3) {
     using G = InferGeo;
     constexpr int NW = kInferThreads / 64;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -179,6 +180,10 @@ __global__ __launch_bounds__(kInferThreads) void k_cnn_infer(const CnnPacked* __
     float* w3s = reinterpret_cast<float*>(xs + kUnion);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int oy = blockIdx.y * G::OH, ox = blockIdx.x * G::OW;
+    // the residual's RMS from its norm partials (every block sums them in the same order)
+    const double s = sqrt(sum_partials(r2_partials) * inv_n);
+    if (!(s > 0.0)) return;  // the base guess is exact: nothing to correct
+    const double inv_s = 1.0 / s;
 
     for (int i = tid; i < 144; i += kInferThreads) w3s[i] = pk->w3[i];
     LaneWeights w;
@@ -197,15 +202,15 @@ __global__ __launch_bounds__(kInferThreads) void k_cnn_infer(const CnnPacked* __
         v1[t] = 0.0;
         if (in[t]) {
             const int64_t idx = (int64_t)gy * nx + gx;
-            v0[t] = wn[idx];
-            v1[t] = wprev[idx];
+            v0[t] = r[idx];
+            v1[t] = bvec[idx];
         }
     }
 #pragma unroll
     for (int t = 0; t < IT; ++t) {
         const int i = tid + t * kInferThreads;
         if (i < G::NXP)
-            xs[i] = in[t] ? pack_bf4((float)(v0[t] * inv_s), (float)(v1[t] * inv_s), c2, c3) : u32x2{0u, 0u};
+            xs[i] = in[t] ? pack_bf4((float)(v0[t] * inv_s), (float)(v1[t] * b_scale), c2, c3) : u32x2{0u, 0u};
     }
     __syncthreads();
     conv1<G, NW>(xs, a1, w, wave, lane);
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(kInferThreads) void k_cnn_infer(const CnnPacked* __
         if (gy < ny && gx < nx) {
             const float y = conv3_at<G>(a2, w3s, b3, p);
             const int64_t idx = (int64_t)gy * nx + gx;
-            guess[idx] = base_scale * wn[idx] + s * (double)y;
+            x[idx] = x[idx] + s * (double)y;
         }
     }
 }
@@ -233,9 +238,10 @@ using TrainGeo = TileGeo<16, 16>;
 constexpr int kTrainThreads = 256;
 
 __global__ __launch_bounds__(kTrainThreads) void k_cnn_train(
-    const CnnPacked* __restrict__ pk, const float* __restrict__ fields, const float* __restrict__ target,
-    const CropMeta* __restrict__ meta, const int* __restrict__ ids, int count, int crop, int mode,
-    float* __restrict__ y_out, float inv_npix, float* __restrict__ pgrad, double* __restrict__ ploss) {
+    const CnnPacked* __restrict__ pk, const float* __restrict__ fields, const CropMeta* __restrict__ meta,
+    const int* __restrict__ ids, int count, int crop, int mode, float* __restrict__ y_out,
+    const float* __restrict__ dy_in, const float* __restrict__ e_in, float inv_npix, float* __restrict__ pgrad,
+    double* __restrict__ ploss) {
     using G = TrainGeo;
     constexpr int NW = kTrainThreads / 64;
     __shared__ __align__(16) u32x2 xs[G::NXP];
@@ -301,12 +307,14 @@ __global__ __launch_bounds__(kTrainThreads) void k_cnn_train(
             const float y = conv3_at<G>(a2, w3s, b3, p);
             const int py = p / 16, px = p - py * 16;
             const int64_t o = (int64_t)(ty * 16 + py) * crop + tx * 16 + px;
+            const int64_t q = (int64_t)j * crop * crop + o;
             if (mode == 0) {
-                y_out[(int64_t)j * crop * crop + o] = y;
+                y_out[q] = y;
             } else {
-                const float r = y - target[(int64_t)id * crop * crop + o];
-                lossacc += (double)r * (double)r;
-                const float d = 2.f * r * inv_npix;
+                // dL/dy of the residual loss, formed by k_cnn_resgrad from this batch's outputs
+                const float ev = e_in[q];
+                lossacc += (double)ev * (double)ev;
+                const float d = dy_in[q];
                 dys[p] = d;
                 gb3 += d;
             }
@@ -570,9 +578,9 @@ __global__ __launch_bounds__(1024) void k_cnn_adam_pack(float* __restrict__ para
     if (tid == 0) pk->b3 = params[kOffB3];
 }
 
-__global__ __launch_bounds__(256) void k_cnn_extract(const double* __restrict__ wn, const double* __restrict__ wprev,
-                                                     const double* __restrict__ S, int nx, int ny, double inv_s,
-                                                     double base_scale, const int* __restrict__ origins, int crop,
+__global__ __launch_bounds__(256) void k_cnn_extract(const double* __restrict__ r, const double* __restrict__ bvec,
+                                                     int nx, int ny, double inv_s, double b_scale,
+                                                     const int* __restrict__ origins, int crop,
                                                      float* __restrict__ fields_out, float* __restrict__ target_out) {
     const int j = blockIdx.y;
     const int oy = origins[2 * j], ox = origins[2 * j + 1];
@@ -587,8 +595,8 @@ __global__ __launch_bounds__(256) void k_cnn_extract(const double* __restrict__ 
         float v0 = 0.f, v1 = 0.f;
         if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
             const int64_t idx = (int64_t)gy * nx + gx;
-            v0 = (float)(wn[idx] * inv_s);
-            v1 = (float)(wprev[idx] * inv_s);
+            v0 = (float)(r[idx] * inv_s);
+            v1 = (float)(bvec[idx] * b_scale);
         }
         f0[i] = v0;
         f1[i] = v1;
@@ -596,7 +604,102 @@ __global__ __launch_bounds__(256) void k_cnn_extract(const double* __restrict__ 
     for (int i = blockIdx.x * 256 + threadIdx.x; i < crop * crop; i += stride) {
         const int iy = i / crop, ix = i - iy * crop;
         const int64_t idx = (int64_t)(oy + iy) * nx + (ox + ix);
-        tg[i] = (float)((S[idx] - base_scale * wn[idx]) * inv_s);
+        tg[i] = (float)(r[idx] * inv_s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residual loss of the residual form on one batch of crops.  M = I - a L_h in
+// units of the spacing (ahx = a / h_x^2, ahy = a / h_y^2); values beyond a
+// window edge that lies on a wall follow the wall closure of L_h (the wall
+// value 0, and for order 4 the odd-reflection ghost), values beyond any other
+// edge are never read for e (its loss points keep the stencil inside the
+// window) and read as 0 for dy (e is 0 outside the window).
+// ---------------------------------------------------------------------------
+struct CropEdges {
+    bool top, bot, left, right;  // window edges on a wall of the grid
+};
+
+__device__ __forceinline__ CropEdges crop_edges(const CropMeta& m, int crop) {
+    CropEdges e;
+    e.top = m.r0 == kCnnHalo;
+    e.bot = m.r1 == kCnnHalo + crop;
+    e.left = m.c0 == kCnnHalo;
+    e.right = m.c1 == kCnnHalo + crop;
+    return e;
+}
+
+// Value of window function f at (row, col), one or two cells beyond the
+// window included: beyond a wall edge the closure, beyond any other edge 0.
+__device__ __forceinline__ float crop_at(const float* f, int crop, const CropEdges& ed, int row, int col) {
+    if (row < 0) {
+        if (!ed.top || row == -1) return 0.f;
+        return -f[(int64_t)0 * crop + col];          // ghost -u_0 two cells beyond the wall
+    }
+    if (row >= crop) {
+        if (!ed.bot || row == crop) return 0.f;
+        return -f[(int64_t)(crop - 1) * crop + col];
+    }
+    if (col < 0) {
+        if (!ed.left || col == -1) return 0.f;
+        return -f[(int64_t)row * crop + 0];
+    }
+    if (col >= crop) {
+        if (!ed.right || col == crop) return 0.f;
+        return -f[(int64_t)row * crop + crop - 1];
+    }
+    return f[(int64_t)row * crop + col];
+}
+
+// (M f)(row, col) on the window with the closures of crop_at.
+__device__ __forceinline__ float crop_M_at(const float* f, int crop, const CropEdges& ed, const CropMeta& m, int row,
+                                           int col) {
+    const float c = f[(int64_t)row * crop + col];
+    float dx, dy;
+    if (m.order == 2) {
+        dx = crop_at(f, crop, ed, row, col - 1) + crop_at(f, crop, ed, row, col + 1) - 2.f * c;
+        dy = crop_at(f, crop, ed, row - 1, col) + crop_at(f, crop, ed, row + 1, col) - 2.f * c;
+    } else {
+        dx = (16.f * (crop_at(f, crop, ed, row, col - 1) + crop_at(f, crop, ed, row, col + 1)) -
+              (crop_at(f, crop, ed, row, col - 2) + crop_at(f, crop, ed, row, col + 2)) - 30.f * c) *
+             (1.f / 12.f);
+        dy = (16.f * (crop_at(f, crop, ed, row - 1, col) + crop_at(f, crop, ed, row + 1, col)) -
+              (crop_at(f, crop, ed, row - 2, col) + crop_at(f, crop, ed, row + 2, col)) - 30.f * c) *
+             (1.f / 12.f);
+    }
+    return c - (m.ahx * dx + m.ahy * dy);
+}
+
+__global__ __launch_bounds__(256) void k_cnn_resid(const float* __restrict__ y, const float* __restrict__ target,
+                                                   const CropMeta* __restrict__ meta, const int* __restrict__ ids,
+                                                   int crop, float* __restrict__ e_out) {
+    const int j = blockIdx.y;
+    const int id = ids[j];
+    const CropMeta m = meta[id];
+    const CropEdges ed = crop_edges(m, crop);
+    const int R = m.order / 2;
+    const float* yj = y + (int64_t)j * crop * crop;
+    const float* tj = target + (int64_t)id * crop * crop;
+    float* ej = e_out + (int64_t)j * crop * crop;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < crop * crop; i += gridDim.x * 256) {
+        const int row = i / crop, col = i - row * crop;
+        const bool ok = (row >= R || ed.top) && (row <= crop - 1 - R || ed.bot) && (col >= R || ed.left) &&
+                        (col <= crop - 1 - R || ed.right);
+        ej[i] = ok ? tj[i] - crop_M_at(yj, crop, ed, m, row, col) : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cnn_resgrad(const float* __restrict__ e, const CropMeta* __restrict__ meta,
+                                                     const int* __restrict__ ids, int crop, float scale,
+                                                     float* __restrict__ dy_out) {
+    const int j = blockIdx.y;
+    const CropMeta m = meta[ids[j]];
+    const CropEdges ed = crop_edges(m, crop);
+    const float* ej = e + (int64_t)j * crop * crop;
+    float* dj = dy_out + (int64_t)j * crop * crop;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < crop * crop; i += gridDim.x * 256) {
+        const int row = i / crop, col = i - row * crop;
+        dj[i] = scale * crop_M_at(ej, crop, ed, m, row, col);
     }
 }
 
@@ -614,8 +717,9 @@ hipError_t launch_cnn_adam_pack(float* params, float* m, float* v, const float* 
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_infer(const CnnPacked* pk, const double* wn, const double* wprev, double* guess, int nx,
-                            int ny, double inv_s, double s, double base_scale, float c2, float c3, hipStream_t st) {
+hipError_t launch_cnn_infer(const CnnPacked* pk, const double* r, const double* b, double* x, int nx, int ny,
+                            const double* r2_partials, double inv_n, double b_scale, float c2, float c3,
+                            hipStream_t st) {
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k_cnn_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -624,18 +728,28 @@ hipError_t launch_cnn_infer(const CnnPacked* pk, const double* wn, const double*
         attr_set = true;
     }
     dim3 grid((unsigned)((nx + InferGeo::OW - 1) / InferGeo::OW), (unsigned)((ny + InferGeo::OH - 1) / InferGeo::OH));
-    k_cnn_infer<<<grid, kInferThreads, kInferLdsBytes, st>>>(pk, wn, wprev, guess, nx, ny, inv_s, s, base_scale, c2,
+    k_cnn_infer<<<grid, kInferThreads, kInferLdsBytes, st>>>(pk, r, b, x, nx, ny, r2_partials, inv_n, b_scale, c2,
                                                              c3);
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_extract(const double* wn, const double* wprev, const double* S, int nx, int ny,
-                              double inv_s, double base_scale, const int* origins_dev, int ncrop, int crop,
-                              float* fields_out, float* target_out, hipStream_t st) {
+hipError_t launch_cnn_extract(const double* r, const double* b, int nx, int ny, double inv_s, double b_scale,
+                              const int* origins_dev, int ncrop, int crop, float* fields_out, float* target_out,
+                              hipStream_t st) {
     if (ncrop <= 0) return hipSuccess;
     dim3 grid(16u, (unsigned)ncrop);
-    k_cnn_extract<<<grid, 256, 0, st>>>(wn, wprev, S, nx, ny, inv_s, base_scale, origins_dev, crop, fields_out,
-                                        target_out);
+    k_cnn_extract<<<grid, 256, 0, st>>>(r, b, nx, ny, inv_s, b_scale, origins_dev, crop, fields_out, target_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_resloss(const float* y, const float* target, const CropMeta* meta, const int* ids, int count,
+                              int crop, float inv_npix, float* e_out, float* dy_out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    dim3 grid(16u, (unsigned)count);
+    k_cnn_resid<<<grid, 256, 0, st>>>(y, target, meta, ids, crop, e_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_cnn_resgrad<<<grid, 256, 0, st>>>(e_out, meta, ids, crop, -2.f * inv_npix, dy_out);
     return hipGetLastError();
 }
 
@@ -644,12 +758,12 @@ int cnn_train_blocks(int count, int crop) {
     return tiles < kCnnTrainBlocks ? tiles : kCnnTrainBlocks;
 }
 
-hipError_t launch_cnn_train(const CnnPacked* pk, const float* fields, const float* target, const CropMeta* meta,
-                            const int* ids, int count, int crop, int mode, float* y_out, float inv_npix,
-                            float* pgrad, double* ploss, int nblocks, hipStream_t st) {
+hipError_t launch_cnn_train(const CnnPacked* pk, const float* fields, const CropMeta* meta, const int* ids,
+                            int count, int crop, int mode, float* y_out, const float* dy_in, const float* e_in,
+                            float inv_npix, float* pgrad, double* ploss, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
-    k_cnn_train<<<nblocks, kTrainThreads, 0, st>>>(pk, fields, target, meta, ids, count, crop, mode, y_out, inv_npix,
-                                                   pgrad, ploss);
+    k_cnn_train<<<nblocks, kTrainThreads, 0, st>>>(pk, fields, meta, ids, count, crop, mode, y_out, dy_in, e_in,
+                                                   inv_npix, pgrad, ploss);
     return hipGetLastError();
 }
 

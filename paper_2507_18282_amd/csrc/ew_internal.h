@@ -89,11 +89,6 @@ hipError_t launch_rb_half(const T* xin, T* xout, const T* b, double bscale, cons
 template <typename T>
 hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& gc, hipStream_t s);
 
-// Partial sums of r^2, r = bscale*b - (x - a L x), one per block (kRedBlocks).
-// With r_out != nullptr the residual is also stored (converted to TR).
-template <typename T, typename TR>
-hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo& g, int order, double a,
-                                double* partial, TR* r_out, hipStream_t s);
 
 // Elementwise helpers.
 template <typename TD, typename TS>

@@ -113,73 +113,6 @@ hipError_t launch_prolong_correct(T* x, const T* xc, const Geo& gf, const Geo& g
     return hipGetLastError();
 }
 
-// --------------------------------------------------------------------------
-// Residual norm partials (and optionally the residual itself, converted).
-// Block b of the kRedBlocks blocks takes the grid rows (fixed j, k) from
-// b R / kRedBlocks to (b + 1) R / kRedBlocks, R = ny nz, each row split over
-// the block's 1024 threads: one division per row instead of per point, and
-// 16 wavefronts per block keep enough loads in flight for HBM.  The partial
-// of each block is its rows' sum in a fixed order.
-// --------------------------------------------------------------------------
-constexpr int kResThreads = 1024;
-
-__device__ __forceinline__ double block_sum_1024(double v, int tid) {
-    __shared__ double red[16];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = tid & 63, wid = tid >> 6;
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (tid == 0) {
-#pragma unroll
-        for (int w = 0; w < 16; ++w) r += red[w];
-    }
-    return r;  // valid in thread 0 only
-}
-
-template <typename T, typename TR, int ORDER, int DIM, bool WALLS>
-__global__ __launch_bounds__(kResThreads) void k_residual_norm(const T* __restrict__ x, const T* __restrict__ b,
-                                                               T bscale, Geo g, T a, double* __restrict__ partial,
-                                                               TR* __restrict__ r_out) {
-    const int64_t rows = (int64_t)g.ny * g.nz;
-    const int64_t r0 = rows * blockIdx.x / kRedBlocks, r1 = rows * (blockIdx.x + 1) / kRedBlocks;
-    double acc = 0.0;
-    for (int64_t row = r0; row < r1; ++row) {
-        const int j = (int)(row % g.ny), k = (int)(row / g.ny);
-        const int64_t base = row * g.nx;
-        for (int i = threadIdx.x; i < g.nx; i += kResThreads) {
-            const int64_t c = base + i;
-            const T xc = x[c];
-            const T r = bscale * b[c] - (xc - a * lap_at<T, ORDER, DIM, WALLS>(x, c, i, j, k, g, xc));
-            if (r_out) r_out[c] = (TR)r;
-            acc += (double)r * (double)r;
-        }
-    }
-    const double s = block_sum_1024(acc, threadIdx.x);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-template <typename T, typename TR>
-hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo& g, int order, double a,
-                                double* partial, TR* r_out, hipStream_t s) {
-    const T bs = (T)bscale, aa = (T)a;
-#define EW_RN(O, D)                                                                                              \
-    do {                                                                                                         \
-        if (g.wall)                                                                                              \
-            k_residual_norm<T, TR, O, D, true><<<kRedBlocks, kResThreads, 0, s>>>(x, b, bs, g, aa, partial, r_out); \
-        else                                                                                                     \
-            k_residual_norm<T, TR, O, D, false><<<kRedBlocks, kResThreads, 0, s>>>(x, b, bs, g, aa, partial, r_out); \
-    } while (0)
-    if (g.dim == 2) {
-        if (order == 2) EW_RN(2, 2); else EW_RN(4, 2);
-    } else {
-        if (order == 2) EW_RN(2, 3); else EW_RN(4, 3);
-    }
-#undef EW_RN
-    return hipGetLastError();
-}
-
 #define EW_INST_MG(T)                                                                                          \
     template hipError_t launch_rb_half<T>(const T*, T*, const T*, double, const Geo&, int, double, double, int, \
                                           hipStream_t);                                                        \
@@ -187,11 +120,5 @@ hipError_t launch_residual_norm(const T* x, const T* b, double bscale, const Geo
 EW_INST_MG(double)
 EW_INST_MG(float)
 #undef EW_INST_MG
-template hipError_t launch_residual_norm<double, double>(const double*, const double*, double, const Geo&, int,
-                                                         double, double*, double*, hipStream_t);
-template hipError_t launch_residual_norm<double, float>(const double*, const double*, double, const Geo&, int,
-                                                        double, double*, float*, hipStream_t);
-template hipError_t launch_residual_norm<float, float>(const float*, const float*, double, const Geo&, int, double,
-                                                       double*, float*, hipStream_t);
 
 }  // namespace ew

@@ -40,6 +40,14 @@ hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_o
                                 double a, double w, int nu1, int nu2, int coarse_sweeps, hipStream_t s);
 template <typename T>
 hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes);
+// Residual norm by tiles: tile_partial (residual_tiles(g) doubles) receives
+// the sum of r^2, r = bscale b - M x, per tile, and partial (kRedBlocks
+// doubles) the tile sums folded in a fixed order; with r_out != nullptr the
+// residual is stored too, converted to TR.
+int64_t residual_tiles(const Geo& g);
+template <typename T, typename TR>
+hipError_t launch_residual_tile(const T* x, const T* b, double bscale, const Geo& g, int order, double a,
+                                double* tile_partial, double* partial, TR* r_out, hipStream_t s);
 // 2D grids (sweep2d.hip).  launch_sweep2x2d: two consecutive red-black
 // sweeps of a 2D level in one pass, out of place (xin may be null with zero_in).
 template <typename T>

@@ -119,11 +119,10 @@ __device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, 
 // ---------------------------------------------------------------------------
 // One full red-black sweep per tile.
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM, bool ZERO_IN, bool PROLONG, bool WALLS>
+template <typename T, int ORDER, int DIM, bool ZERO_IN, bool PROLONG, bool WALLS, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict__ xin, const T* __restrict__ xc,
                                                              const T* __restrict__ b, T bscale, T* __restrict__ xout,
                                                              Geo g, Geo gc, T a, T w) {
-    constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
     constexpr int R = ORDER / 2;        // stencil radius
     constexpr int H = R + 1;            // red is relaxed on the tile plus one layer
     constexpr int LX = TX + 2 * H, LY = TY + 2 * H, LZ = (DIM == 3) ? TZ + 2 * H : 1;
@@ -231,6 +230,118 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
         xout[lin(g, gi, gj, gk)] = out;
     }
 }
+
+// ---------------------------------------------------------------------------
+// Residual norm per tile: x staged with a halo of R (zero outside the domain,
+// the wall closures of lap_lds), r = bscale b - M x at the tile's points,
+// optionally stored (converted to TR), and the tile's sum of r^2 written to
+// tile_partial[tile] (tiles in their logical order).  k_fold_partials then
+// sums the tile partials into the kRedBlocks partials the host reads, each in
+// a fixed order.
+// ---------------------------------------------------------------------------
+template <int DIM> struct ResTile;
+template <> struct ResTile<2> { static constexpr int TX = 64, TY = 8, TZ = 1; };
+template <> struct ResTile<3> { static constexpr int TX = 32, TY = 8, TZ = 4; };
+
+int64_t residual_tiles(const Geo& g) {
+    if (g.dim == 2)
+        return (int64_t)((g.nx + ResTile<2>::TX - 1) / ResTile<2>::TX) * ((g.ny + ResTile<2>::TY - 1) / ResTile<2>::TY);
+    return (int64_t)((g.nx + ResTile<3>::TX - 1) / ResTile<3>::TX) * ((g.ny + ResTile<3>::TY - 1) / ResTile<3>::TY) *
+           ((g.nz + ResTile<3>::TZ - 1) / ResTile<3>::TZ);
+}
+
+template <typename T, typename TR, int ORDER, int DIM, bool WALLS>
+__global__ __launch_bounds__(kTileThreads) void k_residual_tile(const T* __restrict__ x, const T* __restrict__ b,
+                                                                T bscale, Geo g, T a, double* __restrict__ tile_partial,
+                                                                TR* __restrict__ r_out) {
+    constexpr int TX = ResTile<DIM>::TX, TY = ResTile<DIM>::TY, TZ = ResTile<DIM>::TZ;
+    constexpr int R = ORDER / 2;
+    constexpr int LX = TX + 2 * R, LY = TY + 2 * R, LZ = (DIM == 3) ? TZ + 2 * R : 1;
+    constexpr int NX = LX * LY * LZ, NP = TX * TY * TZ;
+    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IP = NP / kTileThreads;
+    static_assert(NP % kTileThreads == 0, "whole points per thread");
+    __shared__ T X[NX];
+    const int tid = threadIdx.x;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY, z0 = (DIM == 3) ? bz * TZ : 0;
+    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, z0, z0 + TZ, R);  // uniform per tile
+    // every global load of a thread is issued before the first LDS store
+    T xv[IX], bv[IP];
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (q < NX) {
+            const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
+            const int gi = x0 - R + lx, gj = y0 - R + ly, gk = (DIM == 3) ? z0 - R + lz : 0;
+            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) v = x[lin(g, gi, gj, gk)];
+        }
+        xv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IP; ++t) {
+        const int q = tid + t * kTileThreads;
+        const int gi = x0 + q % TX, gj = y0 + (q / TX) % TY, gk = z0 + q / (TX * TY);
+        bv[t] = (gi < g.nx && gj < g.ny && gk < g.nz) ? b[lin(g, gi, gj, gk)] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NX) X[q] = xv[t];
+    }
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < IP; ++t) {
+        const int q = tid + t * kTileThreads;
+        const int tx = q % TX, ty = (q / TX) % TY, tz = q / (TX * TY);
+        const int gi = x0 + tx, gj = y0 + ty, gk = z0 + tz;
+        if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
+        const int p = (tx + R) + LX * ((ty + R) + LY * ((DIM == 3) ? (tz + R) : 0));
+        const T uc = X[p];
+        const T r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw));
+        if (r_out) r_out[lin(g, gi, gj, gk)] = (TR)r;
+        acc += (double)r * (double)r;
+    }
+    const double s = block_sum_256(acc, tid);
+    if (tid == 0) tile_partial[bx + gridDim.x * (by + gridDim.y * bz)] = s;
+}
+
+__global__ __launch_bounds__(kRedBlocks) void k_fold_partials(const double* __restrict__ tile_partial, int ntiles,
+                                                              double* __restrict__ partial) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += kRedBlocks) s += tile_partial[i];
+    partial[threadIdx.x] = s;
+}
+
+template <typename T, typename TR>
+hipError_t launch_residual_tile(const T* x, const T* b, double bscale, const Geo& g, int order, double a,
+                                double* tile_partial, double* partial, TR* r_out, hipStream_t s) {
+    const T bs = (T)bscale, aa = (T)a;
+#define EW_RT(O, D)                                                                                            \
+    do {                                                                                                       \
+        constexpr int TX = ResTile<D>::TX, TY = ResTile<D>::TY, TZ = ResTile<D>::TZ;                           \
+        dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, D == 3 ? (g.nz + TZ - 1) / TZ : 1);              \
+        if (g.wall)                                                                                            \
+            k_residual_tile<T, TR, O, D, true><<<grid, kTileThreads, 0, s>>>(x, b, bs, g, aa, tile_partial, r_out); \
+        else                                                                                                   \
+            k_residual_tile<T, TR, O, D, false><<<grid, kTileThreads, 0, s>>>(x, b, bs, g, aa, tile_partial, r_out); \
+    } while (0)
+    if (g.dim == 2) {
+        if (order == 2) EW_RT(2, 2); else EW_RT(4, 2);
+    } else {
+        if (order == 2) EW_RT(2, 3); else EW_RT(4, 3);
+    }
+#undef EW_RT
+    EW_RET_ON_ERR(hipGetLastError());
+    k_fold_partials<<<1, kRedBlocks, 0, s>>>(tile_partial, (int)residual_tiles(g), partial);
+    return hipGetLastError();
+}
+template hipError_t launch_residual_tile<double, double>(const double*, const double*, double, const Geo&, int, double,
+                                                         double*, double*, double*, hipStream_t);
+template hipError_t launch_residual_tile<double, float>(const double*, const double*, double, const Geo&, int, double,
+                                                        double*, double*, float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Residual + full-weighting restriction per coarse tile.
@@ -612,15 +723,16 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM>
-static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
-                                 T a, T w, bool zero_in, bool prolong, hipStream_t s) {
-    constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
+template <typename T, int ORDER, int DIM, int TX, int TY, int TZ>
+static hipError_t sweep_dispatch_tile(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g,
+                                      const Geo& gc, T a, T w, bool zero_in, bool prolong, hipStream_t s) {
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, DIM == 3 ? (g.nz + TZ - 1) / TZ : 1);
-#define EW_ST(Z, P)                                                                                          \
-    do {                                                                                                     \
-        if (g.wall) k_sweep_tile<T, ORDER, DIM, Z, P, true><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a, w); \
-        else k_sweep_tile<T, ORDER, DIM, Z, P, false><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a, w);   \
+#define EW_ST(Z, P)                                                                                              \
+    do {                                                                                                         \
+        if (g.wall)                                                                                              \
+            k_sweep_tile<T, ORDER, DIM, Z, P, true, TX, TY, TZ><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a, w); \
+        else                                                                                                     \
+            k_sweep_tile<T, ORDER, DIM, Z, P, false, TX, TY, TZ><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, a, w); \
     } while (0)
     if (zero_in && prolong) EW_ST(true, true);
     else if (zero_in) EW_ST(true, false);
@@ -628,6 +740,19 @@ static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T*
     else EW_ST(false, false);
 #undef EW_ST
     return hipGetLastError();
+}
+
+// 32 x 8 x 8 tiles from 1024 of them up (127^3 and larger); 16 x 8 x 4 tiles
+// (less serial work per workgroup, 8 times as many workgroups) on smaller
+// levels, where the large tiles leave most CUs idle.
+template <typename T, int ORDER, int DIM>
+static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
+                                 T a, T w, bool zero_in, bool prolong, hipStream_t s) {
+    constexpr int TX = SweepTile<DIM>::TX, TY = SweepTile<DIM>::TY, TZ = SweepTile<DIM>::TZ;
+    const int64_t big = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+    if (DIM == 3 && big < 1024)
+        return sweep_dispatch_tile<T, ORDER, DIM, 16, 8, 4>(xin, xc, b, bs, xout, g, gc, a, w, zero_in, prolong, s);
+    return sweep_dispatch_tile<T, ORDER, DIM, TX, TY, TZ>(xin, xc, b, bs, xout, g, gc, a, w, zero_in, prolong, s);
 }
 
 template <typename T>

@@ -106,6 +106,7 @@ struct Op {
     double* c_dev = nullptr;   // filter weights c_0..c_{N_t} on the device (explicit operators)
     double* partial_dev = nullptr;
     double* partial_host = nullptr;
+    double* tile_partial_dev = nullptr;  // per-tile residual sums of the finest level (implicit boxes)
     std::vector<Level> levels;
     int coarse_level = 0;      // first level run by the single-workgroup kernel
     CoarseLevels coarse{};
@@ -123,9 +124,12 @@ struct Op {
     // (the learned guess computes it); consumed by that solve.
     const double* bb_src = nullptr;
     double bb_val = 0.0;
-    // Called after every implicit solve M S = 2 W^n of a wave-solve with
-    // (W^n, W^{n-1}, S); used to record training crops.
-    std::function<ew_status(const double*, const double*, const double*)> step_hook;
+    // Called at every implicit solve M x = bscale b of a step n >= 1 once the
+    // base guess x0 is formed, before the multigrid, with (b, bscale, x0,
+    // x0 taken as zero and not yet written); used to record training crops.
+    std::function<ew_status(const double*, double, double*, bool)> guess_hook;
+    double* cnn_r = nullptr;   // residual of the base guess (learned correction)
+    bool probe_guess = false;  // measure the initial residuals (ew_op_probe_guesses)
     // Projection guess (proj.hip): FP32 copies of the last proj_k solutions
     // in a ring of slots, and their Gram matrix G[s][t] = x_s . b_t on the
     // host (row-major, kProjMax x kProjMax).
@@ -165,12 +169,14 @@ struct Op {
                             double** result);
     ew_status mg_solve64(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel,
                          bool speculate = false);
-    ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel);
+    ew_status mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles, double* rel,
+                             bool speculate = false);
     ew_status rhs_norm2(const double* b, double* bb);
     ew_status proj_setup();
     ew_status proj_guess(const double* b, double bscale, double* x, bool* x_is_zero);
     ew_status proj_add(const double* b, double bscale, const double* x);
     ew_status implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess);
+    ew_status guess_rel_res(const double* b, double bscale, const double* x, double* rel);
     ew_status apply_filter(const double* v, double* out);
 };
 

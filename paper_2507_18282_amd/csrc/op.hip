@@ -421,6 +421,7 @@ extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* de
     EW_TRY(op->alloc((void**)&op->wB, N * sizeof(double)));
     if (op->implicit) {
         EW_TRY(op->alloc((void**)&op->sbuf, N * sizeof(double)));
+        EW_TRY(op->alloc((void**)&op->tile_partial_dev, residual_tiles(op->g) * sizeof(double)));
         EW_TRY(op->build_hierarchy());
         EW_TRY(op->proj_setup());
         if (op->mixed) {
@@ -472,6 +473,14 @@ extern "C" ew_status ew_op_get_info(ew_op op, ew_op_info* out) {
 extern "C" ew_status ew_op_get_stats(ew_op op, ew_op_stats* out) {
     if (!op || !out) return fail(EW_ERR_INVALID_ARG, "null argument");
     *out = op->stats;
+    return EW_OK;
+}
+
+extern "C" ew_status ew_op_probe_guesses(ew_op op, int on) {
+    if (!op) return fail(EW_ERR_INVALID_ARG, "null op");
+    if (!op->implicit || op->mixed || op->mapped)
+        return fail(EW_ERR_INVALID_ARG, "guess probes need an implicit FP64 box operator");
+    op->probe_guess = on != 0;
     return EW_OK;
 }
 

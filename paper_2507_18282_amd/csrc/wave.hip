@@ -86,7 +86,15 @@ ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool ze
     }
     T* xc = nullptr;
     EW_TRY(vcycle<T>(l + 1, (T*)C.x[0], (T*)C.x[1], (T*)C.b, 1.0, true, &xc));
-    if (desc.mg_nu2 >= 1) {
+    if (desc.mg_nu2 >= 1 && L.g.dim == 3) {
+        // 3D: the prolongation as its own pass (interpolating inside the staged
+        // sweep tile reads each coarse value up to eight times from the cache)
+        {
+            ProfScope ps(this, EW_K_PROLONG, l, sizeof(T) * (2.0 * L.g.size() + C.g.size()));
+            EW_HIP_TRY(launch_prolong_correct<T>(cur, xc, L.g, C.g, stream));
+        }
+        for (int s = 0; s < desc.mg_nu2; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, false, nullptr));
+    } else if (desc.mg_nu2 >= 1) {
         EW_TRY(sweep<T>(l, cur, other, b, bscale, false, xc));
         for (int s = 1; s < desc.mg_nu2; ++s) EW_TRY(sweep<T>(l, cur, other, b, bscale, false, nullptr));
     } else {
@@ -147,8 +155,8 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
                     if (mapped)
                         EW_HIP_TRY(launch_residual_mapped(cur, b, bscale, g, mcoef[0], a, partial_dev, nullptr, stream));
                     else
-                        EW_HIP_TRY((launch_residual_norm<double, double>(cur, b, bscale, g, order, a, partial_dev,
-                                                                         nullptr, stream)));
+                        EW_HIP_TRY((launch_residual_tile<double, double>(cur, b, bscale, g, order, a, tile_partial_dev,
+                                                                         partial_dev, nullptr, stream)));
                 }
                 double rr;
                 EW_TRY(host_sum_partials(&rr));
@@ -186,7 +194,7 @@ ew_status Op::mg_solve64(const double* b, double bscale, double* x, bool x_is_ze
 // solve), stops if ||r|| <= mg_tol ||bscale b||, else solves M e = r with one
 // FP32 V-cycle from zero and updates x += e in FP64.
 ew_status Op::mg_solve_mixed(const double* b, double bscale, double* x, bool x_is_zero, int* cycles,
-                             double* rel_out) {
+                             double* rel_out, bool speculate) {
     double bb = 0.0;
     EW_TRY(rhs_norm2(b, &bb));
     const double bn = std::sqrt(bb) * std::fabs(bscale);
@@ -199,21 +207,38 @@ ew_status Op::mg_solve_mixed(const double* b, double bscale, double* x, bool x_i
         float* r32 = (float*)L0.b;
         float* e32 = (float*)L0.x[0];
         float* t32 = (float*)L0.x[1];
+        // speculative tests as in mg_solve64: the residual is formed every
+        // iteration (it is the inner solve's right-hand side), its norm read
+        // by the host only from the iteration the previous solve suggests
+        const int kind = solve_kind;
+        const int skip = speculate && spec_cycles[kind] > 0
+                             ? std::max(0, spec_cycles[kind] - (spec_first_pass[kind] ? 2 : 1))
+                             : 0;
+        int tests = 0;
         for (;;) {
             {
                 ProfScope ps(this, EW_K_RESNORM, 0, 20.0 * (double)N);
-                EW_HIP_TRY((launch_residual_norm<double, float>(x, b, bscale, g, order, a, partial_dev, r32, stream)));
+                EW_HIP_TRY((launch_residual_tile<double, float>(x, b, bscale, g, order, a, tile_partial_dev, partial_dev,
+                                                                r32, stream)));
             }
-            double rr;
-            EW_TRY(host_sum_partials(&rr));
-            rel = std::sqrt(rr) / bn;
-            EW_TRY(check_rel(rel));
-            if (rel <= desc.mg_tol || cyc >= desc.mg_max_cycles) break;
+            if (cyc >= skip) {
+                double rr;
+                EW_TRY(host_sum_partials(&rr));
+                rel = std::sqrt(rr) / bn;
+                EW_TRY(check_rel(rel));
+                ++tests;
+                if (rel <= desc.mg_tol) break;
+            } else {
+                rel = 1.0;
+            }
+            if (cyc >= desc.mg_max_cycles) break;
             float* e = nullptr;
             EW_TRY(vcycle<float>(0, e32, t32, r32, 1.0, true, &e));
             EW_HIP_TRY((launch_add_inplace<double, float>(x, e, N, stream)));
             ++cyc;
         }
+        spec_cycles[kind] = cyc;
+        spec_first_pass[kind] = tests == 1 && skip > 0;
     }
     stats.mg_solves++;
     stats.mg_cycles += cyc;
@@ -225,32 +250,73 @@ ew_status Op::mg_solve_mixed(const double* b, double bscale, double* x, bool x_i
     return EW_OK;
 }
 
-ew_status cnn_predict(Op* op, const double* wcur, const double* wprev, double* guess_S);
+ew_status cnn_correct(Op* op, const double* b, double bscale, double* x);
 
 // One implicit solve M x = bscale b with the operator's initial-guess rule.
+// The learned predictor corrects the projection guess (zero while the window
+// is empty or off) at the steps n >= 1, whose right-hand sides 2 W^n it was
+// trained on; the first step M W^1 = W^0 keeps the projection guess.
 ew_status Op::implicit_solve(const double* b, double bscale, double* x, const double* wprev_for_guess) {
     bool zero = false;
     solve_kind = wprev_for_guess == nullptr ? 0 : 1;
-    if (desc.predictor == EW_PRED_PROJ || (desc.predictor == EW_PRED_CNN && proj_k > 0 && cnn == nullptr)) {
+    const bool proj = desc.predictor == EW_PRED_PROJ || desc.predictor == EW_PRED_CNN;
+    if (proj) {
         EW_TRY(proj_guess(b, bscale, x, &zero));
-        if (mixed) EW_TRY(mg_solve_mixed(b, bscale, x, zero, nullptr, nullptr));
-        else EW_TRY(mg_solve64(b, bscale, x, zero, nullptr, nullptr, true));
-        return proj_add(b, bscale, x);
-    }
-    if (desc.predictor == EW_PRED_ZERO) {
+    } else if (desc.predictor == EW_PRED_ZERO) {
         zero = true;
     } else if (desc.predictor == EW_PRED_EXTRAP) {
         // W^{n+1} ~ 2 W^n - W^{n-1} gives S = W^{n+1} + W^{n-1} ~ 2 W^n (and W^1 ~ W^0).
         EW_HIP_TRY(launch_scale_copy<double>(x, b, N, bscale, stream));
-    } else if (desc.predictor == EW_PRED_SCALED || wprev_for_guess == nullptr || cnn == nullptr) {
+    } else {
         // M phi = (1 + a mu) phi: exact for every mode at mu = omega^2.
         const double s = bscale / (1.0 + a * omega_used * omega_used);
         EW_HIP_TRY(launch_scale_copy<double>(x, b, N, s, stream));
-    } else {
-        EW_TRY(cnn_predict(this, b, wprev_for_guess, x));
     }
-    if (mixed) return mg_solve_mixed(b, bscale, x, zero, nullptr, nullptr);
-    return mg_solve64(b, bscale, x, zero, nullptr, nullptr, true);
+    if (guess_hook && solve_kind == 1) {
+        EW_TRY(guess_hook(b, bscale, x, zero));
+        zero = false;  // the hook writes a zero guess out
+    }
+    double base_rel = -1.0;
+    if (probe_guess && solve_kind == 1 && !mixed && !mapped) {
+        if (zero) EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
+        zero = false;
+        EW_TRY(guess_rel_res(b, bscale, x, &base_rel));
+    }
+    if (desc.predictor == EW_PRED_CNN && cnn != nullptr && solve_kind == 1) {
+        if (zero) EW_HIP_TRY(launch_fill<double>(x, N, 0.0, stream));
+        EW_TRY(cnn_correct(this, b, bscale, x));
+        zero = false;
+    }
+    if (base_rel >= 0.0) {
+        double g = base_rel;
+        if (desc.predictor == EW_PRED_CNN && cnn != nullptr) EW_TRY(guess_rel_res(b, bscale, x, &g));
+        stats.guess_probes++;
+        stats.base_rel_res_sum += base_rel;
+        stats.guess_rel_res_sum += g;
+    }
+    if (mixed) EW_TRY(mg_solve_mixed(b, bscale, x, zero, nullptr, nullptr, true));
+    else EW_TRY(mg_solve64(b, bscale, x, zero, nullptr, nullptr, true));
+    return proj ? proj_add(b, bscale, x) : EW_OK;
+}
+
+// ||bscale b - M x||_2 / ||bscale b||_2 (host-blocking); leaves the cached
+// ||b||^2 for the solve that follows.
+ew_status Op::guess_rel_res(const double* b, double bscale, const double* x, double* rel) {
+    double bb;
+    if (bb_src == b) {
+        bb = bb_val;
+    } else {
+        EW_HIP_TRY(launch_dot_partial(b, b, N, partial_dev, stream));
+        EW_TRY(host_sum_partials(&bb));
+        bb_src = b;
+        bb_val = bb;
+    }
+    EW_HIP_TRY((launch_residual_tile<double, double>(x, b, bscale, g, order, a, tile_partial_dev, partial_dev, nullptr,
+                                                     stream)));
+    double rr;
+    EW_TRY(host_sum_partials(&rr));
+    *rel = bb > 0.0 ? std::sqrt(rr / bb) / std::fabs(bscale) : 0.0;
+    return EW_OK;
 }
 
 ew_status Op::apply_filter(const double* v, double* out) {
@@ -312,7 +378,6 @@ ew_status Op::apply_filter(const double* v, double* out) {
         double* cur = wA;
         for (int k = 1; k < n_t; ++k) {
             EW_TRY(implicit_solve(cur, 2.0, sbuf, prev));
-            if (step_hook) EW_TRY(step_hook(cur, prev, sbuf));
             double* next = (prev == v) ? wB : const_cast<double*>(prev);
             ProfScope ps(this, EW_K_UPDATE, 0, (mixed ? 32.0 : 40.0) * (double)N);
             if (mixed)

@@ -26,7 +26,7 @@ U_BF16 = 2.0 ** -8
 
 
 def _params(seed, bias_scale=0.1):
-    th = C.init_params(synthetic.uniform_pm1(seed, C.N_PARAMS))
+    th = C.init_params(synthetic.uniform_pm1(seed, C.N_PARAMS), last_layer_zero=False)
     b = synthetic.uniform_pm1(seed + 1, 64) * bias_scale
     p = C.unpack(th)
     p["b1"][...] = b[:16]
@@ -59,16 +59,39 @@ def _forward_with_bound(theta, x):
     return y, ey
 
 
+# Window geometries of test crops: (grid shape (ny, nx), origin (oy, ox)) for a
+# crop of side c; interior, top wall, right wall, bottom-left corner.
+def _geometry(i, c):
+    g = (c + 20, c + 20)
+    return g, [(10, 10), (0, 10), (10, 20), (20, 0)][i % 4]
+
+
+def _rect(grid, origin, c):
+    """The padded window's rectangle inside the grid, as the collection writes it."""
+    (ny, nx), (oy, ox) = grid, origin
+    cp = c + 6
+    return [max(0, 3 - oy), min(cp, ny - oy + 3), max(0, 3 - ox), min(cp, nx - ox + 3)]
+
+
+AH = (0.75, 0.5)   # a / h_x^2, a / h_y^2 of the test crops (exact in FP32)
+
+
 def _random_crops(n, crop, seed):
-    """Random fields and targets; every other crop touches a wall (partial rectangle)."""
+    """Random fields and targets on windows of the _geometry cases, zero outside
+    their grids; planes (c2, c3, a/h_x^2, a/h_y^2)."""
     cp = crop + 6
     fields = synthetic.uniform_pm1(seed, n * 2 * cp * cp).reshape(n, 2, cp, cp).astype(np.float32)
     target = (0.3 * synthetic.uniform_pm1(seed + 1, n * crop * crop)).reshape(n, crop, crop).astype(np.float32)
     u = synthetic.uniform01(seed + 2, 2 * n)
-    planes = np.stack([0.05 + 0.3 * u[:n], 0.9 * u[n:]], axis=1).astype(np.float32)
-    rects = np.tile(np.array([0, cp, 0, cp], dtype=np.int32), (n, 1))
-    for i in range(1, n, 2):
-        rects[i] = [3, cp, 0, cp - 3 - (i % 3)]
+    planes = np.stack([0.05 + 0.3 * u[:n], 0.9 * u[n:], np.full(n, AH[0]), np.full(n, AH[1])],
+                      axis=1).astype(np.float32)
+    rects = np.zeros((n, 4), dtype=np.int32)
+    for i in range(n):
+        rects[i] = _rect(*_geometry(i, crop), crop)
+        r0, r1, c0, c1 = rects[i]
+        mask = np.zeros((cp, cp), dtype=bool)
+        mask[r0:r1, c0:c1] = True
+        fields[i, :, ~mask] = 0.0
     return fields, target, planes, rects
 
 
@@ -83,9 +106,26 @@ def _oracle_input(fields, planes, rect):
     return x
 
 
-def _store(fields, target, planes, rects, crop, capacity=None):
+def _oracle_loss_grad(theta, fields, target, planes, rects, ids, crop, order):
+    """Mean residual loss over the crops ids and its gradient (oracle): h = 1 per
+    axis scaled so that a / h^2 are the crops' values."""
+    n = len(ids)
+    loss, g = 0.0, np.zeros(C.N_PARAMS)
+    for i in ids:
+        grid, origin = _geometry(i, crop)
+        ahx, ahy = float(planes[i, 2]), float(planes[i, 3])
+        h = (1.0, np.sqrt(ahx / ahy))          # a = ahx with h_x = 1 gives a / h_y^2 = ahy
+        li, gi = C.residual_loss_and_grad(theta, _oracle_input(fields[i], planes[i], rects[i]),
+                                          target[i].astype(np.float64), grid, origin, h, order, ahx,
+                                          npix=n * crop * crop)
+        loss += li
+        g += gi
+    return loss, g
+
+
+def _store(fields, target, planes, rects, crop, capacity=None, order=4):
     from paper_2507_18282_amd import CropStore
-    st = CropStore(capacity or len(planes), crop)
+    st = CropStore(capacity or len(planes), crop, order)
     st.append(to_dev(fields.ravel()).float(), to_dev(target.ravel()).float(), planes, rects)
     return st
 
@@ -131,23 +171,20 @@ def test_forward_subrange_and_repeatability():
     assert np.array_equal(y_all, to_host(net.forward(st, 0, 6)))
 
 
-def test_loss_and_gradient_match_oracle():
+@pytest.mark.parametrize("order", [4, 2])
+def test_residual_loss_and_gradient_match_oracle(order):
     from paper_2507_18282_amd import Cnn
-    say("cnn loss/grad")
+    say("cnn residual loss/grad", order)
     params = _params(8)
     crop, n = 32, 4
     fields, target, planes, rects = _random_crops(n, crop, 91)
-    st = _store(fields, target, planes, rects, crop)
+    st = _store(fields, target, planes, rects, crop, order=order)
     net = Cnn(0)
     net.set_params(params)
     loss, g = net.loss_grad(st, 0, n)
     g = to_host(g).astype(np.float64)
     theta = _effective(params)
-    loss_ref, g_ref = 0.0, np.zeros(C.N_PARAMS)
-    for i in range(n):
-        li, gi = C.loss_and_grad(theta, _oracle_input(fields[i], planes[i], rects[i]), target[i].astype(np.float64))
-        loss_ref += li / n
-        g_ref += gi / n
+    loss_ref, g_ref = _oracle_loss_grad(theta, fields, target, planes, rects, range(n), crop, order)
     assert abs(loss - loss_ref) <= 2e-2 * loss_ref
     gp, rp = C.unpack(g), C.unpack(g_ref)
     for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
@@ -171,10 +208,7 @@ def test_adam_first_step_matches_oracle():
     after = net.get_params().astype(np.float64)
     ids = np.minimum(np.floor(synthetic.uniform01(seed, batch) * n).astype(int), n - 1)
     theta = _effective(params)
-    g_ref = np.zeros(C.N_PARAMS)
-    for i in ids:
-        g_ref += C.loss_and_grad(theta, _oracle_input(fields[i], planes[i], rects[i]),
-                                 target[i].astype(np.float64))[1] / batch
+    _, g_ref = _oracle_loss_grad(theta, fields, target, planes, rects, ids, crop, 4)
     th1, _, _ = C.adam_step(params.astype(np.float64), np.zeros(C.N_PARAMS), np.zeros(C.N_PARAMS), g_ref, 1, lr)
     step = after - params.astype(np.float64)
     assert np.all(np.abs(step) <= lr * (1 + 1e-5) + 1e-7)
@@ -189,30 +223,32 @@ def _implicit_op(n, order, omega, predictor="zero"):
 
 
 def test_grid_guess_ragged_within_bound():
-    """The predictor on a ragged grid (tiles of 32 do not divide it) equals the
-    oracle's guess 2 W^n / (1 + a w^2) + s y within s times the bound."""
+    """The correction on a ragged grid (tiles of 32 do not divide it) from a zero
+    base (an empty projection window): the guess equals the oracle's s y, y the
+    network on (r / s, b / s_b, c2, c3) with r = b, within s times the bound."""
     from paper_2507_18282_amd import Cnn
     say("cnn grid guess")
     nx, ny = 70, 45
-    op = _implicit_op((nx, ny), 4, 25.0)
+    op = _implicit_op((nx, ny), 4, 25.0, predictor="cnn")
     net = Cnn(0)
     params = _params(12)
     net.set_params(params)
     op.set_cnn(net)
-    wn = 0.37 * synthetic.uniform_pm1(201, nx * ny)
-    wp = 0.21 * synthetic.uniform_pm1(202, nx * ny)
-    got = to_host(op.cnn_guess(to_dev(wn), to_dev(wp))).reshape(ny, nx)
+    b = 0.37 * synthetic.uniform_pm1(201, nx * ny)
+    base = to_dev(np.full(nx * ny, 5.0))
+    got = to_host(op.cnn_guess(to_dev(b), base=base)).reshape(ny, nx)
+    assert np.all(to_host(base) == 0.0)
     a = 0.5 * op.dt ** 2
-    h = 1.0 / (nx + 1)
+    h = (1.0 / (nx + 1), 1.0 / (ny + 1))
     theta = _effective(params)
-    W, Wp = wn.reshape(ny, nx), wp.reshape(ny, nx)
-    s = float(np.sqrt(np.mean(W * W)))
-    c2, c3 = C.step_planes(a, op.omega_used, h)
-    x = C.make_input(W, Wp, s, np.float32(c2), np.float32(c3))
-    y, bound = _forward_with_bound(theta, x)
-    ref = 2.0 * W / (1.0 + a * op.omega_used ** 2) + s * y
+    B = b.reshape(ny, nx)
+    s = float(np.sqrt(np.mean(B * B)))
+    c2, c3 = C.step_planes(a, op.omega_used, h[0])
+    y, bound = _forward_with_bound(theta, C.make_input_residual(B, B, s, s, np.float32(c2), np.float32(c3)))
+    ref = s * y
     assert np.all(np.abs(got - ref) <= s * bound + 1e-14)
-    assert np.allclose(ref, C.predict_guess(theta, W, Wp, a, op.omega_used, h), rtol=1e-6, atol=1e-6 * s)
+    assert np.allclose(ref, C.predict_correction(theta, np.zeros_like(B), B, h, 4, a, op.omega_used), rtol=1e-6,
+                       atol=1e-6 * s)
     assert op.stats()["cnn_guesses"] == 1
 
 
@@ -224,17 +260,20 @@ def _origin(n, crop, u):
 
 
 def test_collect_crops_match_oracle_levels():
-    """Crops recorded during a wave-solve are the oracle's time levels at the
-    documented window origins (draws oy, ox per crop from the SplitMix64 stream)."""
+    """Crops recorded during a wave-solve of an operator whose base guess is the
+    extrapolation x0 = b: fields (r / s, b / s_b) with b = 2 W^n from the
+    oracle's time levels and r = b - M b, at the documented window origins
+    (draws oy, ox per crop from the SplitMix64 stream)."""
     from paper_2507_18282_amd import CropStore
+    from oracle import mg as OMG
     say("cnn collect")
     nx, ny, crop, per = 80, 64, 32, 2
     P = synthetic.Problem(n=(nx, ny), length=(1.0, 1.0), order=4, omega=20.0, ts="implicit", n_its=10,
                           k=1, m=4, seed=3)
-    op = _implicit_op((nx, ny), 4, 20.0)
+    op = _implicit_op((nx, ny), 4, 20.0, predictor="extrap")
     h, plan = oracle_plan(P)
     v = synthetic.uniform_pm1(55, nx * ny)
-    store = CropStore(64, crop)
+    store = CropStore(64, crop, 4)
     seed = 17
     out = to_host(store.collect(op, to_dev(v), crops_per_step=per, seed=seed))
     acc, levels = W.apply_filter(v.reshape(ny, nx), h, 4, plan, return_levels=True)
@@ -245,23 +284,21 @@ def test_collect_crops_match_oracle_levels():
     fields, target = to_host(fields), to_host(target)
     u = synthetic.uniform01(seed, 2 * per * n_steps)
     a = 0.5 * plan.dt ** 2
-    base = 2.0 / (1.0 + a * plan.omega ** 2)
     c2, c3 = C.step_planes(a, plan.omega, h[0])
     cp = crop + 6
     j = 0
     for n in range(1, plan.n_t):
-        wn, wp = levels[n], levels[n - 1]
-        S = levels[n + 1] + levels[n - 1]
-        s = np.sqrt(np.mean(wn * wn))
-        pad_n = np.pad(wn, 3)
-        pad_p = np.pad(wp, 3)
+        b = 2.0 * levels[n]
+        r = b - OMG.apply_M(b, h, 4, a)
+        s, sb = np.sqrt(np.mean(r * r)), np.sqrt(np.mean(b * b))
+        pad_r, pad_b = np.pad(r / s, 3), np.pad(b / sb, 3)
         for _ in range(per):
             oy, ox = _origin(ny, crop, u[2 * j]), _origin(nx, crop, u[2 * j + 1])
-            np.testing.assert_allclose(fields[j, 0], pad_n[oy:oy + cp, ox:ox + cp] / s, rtol=0, atol=2e-6)
-            np.testing.assert_allclose(fields[j, 1], pad_p[oy:oy + cp, ox:ox + cp] / s, rtol=0, atol=2e-6)
-            tref = (S[oy:oy + crop, ox:ox + crop] - base * wn[oy:oy + crop, ox:ox + crop]) / s
-            np.testing.assert_allclose(target[j], tref, rtol=0, atol=2e-6 * max(1.0, np.max(np.abs(tref))))
+            np.testing.assert_allclose(fields[j, 0], pad_r[oy:oy + cp, ox:ox + cp], rtol=0, atol=2e-6 * np.max(np.abs(pad_r)))
+            np.testing.assert_allclose(fields[j, 1], pad_b[oy:oy + cp, ox:ox + cp], rtol=0, atol=2e-6 * np.max(np.abs(pad_b)))
+            np.testing.assert_array_equal(target[j], fields[j, 0, 3:3 + crop, 3:3 + crop])
             assert planes[j, 0] == np.float32(c2) and planes[j, 1] == np.float32(c3)
+            assert planes[j, 2] == np.float32(a / h[0] ** 2) and planes[j, 3] == np.float32(a / h[1] ** 2)
             assert list(rects[j]) == [max(0, 3 - oy), min(cp, ny - oy + 3), max(0, 3 - ox), min(cp, nx - ox + 3)]
             j += 1
 
@@ -270,8 +307,8 @@ def test_training_lowers_loss_and_is_deterministic():
     from paper_2507_18282_amd import Cnn, CropStore
     say("cnn train")
     nx = ny = 127
-    op = _implicit_op((nx, ny), 4, 30.0)
-    store = CropStore(256, 32)
+    op = _implicit_op((nx, ny), 4, 30.0, predictor="proj")
+    store = CropStore(256, 32, 4)
     for r in range(4):
         v = to_dev(synthetic.uniform_pm1(300 + r, nx * ny))
         store.collect(op, v, crops_per_step=6, seed=400)
@@ -307,3 +344,33 @@ def test_warm_started_eigenpairs_equal_cold_start(predictor):
     assert np.allclose(np.sort(rw.mu[:4]), np.sort(rc.mu[:4]), rtol=1e-9)
     if predictor == "cnn":
         assert warm.stats()["cnn_guesses"] > 0
+
+
+def test_trained_network_lowers_initial_residual_on_held_out_solves():
+    """Trained on the projection residuals of wave-solves from some start
+    vectors, the network's guesses on wave-solves from other start vectors
+    leave a smaller initial residual ||b - M x0|| / ||b|| than the projection
+    guess they correct (both measured inside the solves)."""
+    from paper_2507_18282_amd import Cnn, CropStore
+    say("cnn held-out residuals")
+    nx = ny = 127
+    store = CropStore(1200, 32, 4)
+    for r in range(4):
+        op = _implicit_op((nx, ny), 4, 30.0 + 10.0 * r, predictor="proj")
+        w = to_dev(synthetic.uniform_pm1(600 + r, nx * ny))
+        for _ in range(3):
+            w = store.collect(op, w / w.norm(), crops_per_step=10, seed=601)
+    net = Cnn(21)
+    net.train(store, steps=600, batch=16, lr=2e-3, seed=8)
+    net.train(store, steps=600, batch=16, lr=5e-4, seed=9)
+    op = _implicit_op((nx, ny), 4, 35.0, predictor="cnn")
+    op.set_cnn(net)
+    op.probe_guesses(True)
+    w = to_dev(synthetic.uniform_pm1(777, nx * ny))
+    for _ in range(4):
+        w = op.apply_filter(w / w.norm())
+    st = op.stats()
+    assert st["guess_probes"] == 4 * (op.n_t - 1) and st["cnn_guesses"] == st["guess_probes"]
+    base, guess = st["base_rel_res_sum"], st["guess_rel_res_sum"]
+    say("held-out mean relative residual: base", base / st["guess_probes"], "network", guess / st["guess_probes"])
+    assert guess < 0.8 * base

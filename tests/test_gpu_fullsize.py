@@ -98,28 +98,29 @@ def test_batch_full_config_sine_modes():
 
 
 def test_learned_guess_full_size_windows():
+    """The learned correction on the 1023^2 grid from a zero base (empty
+    projection window): windows of s y against the oracle network on the
+    whole-grid planes (b / s, b / s, c2, c3), within s times the BF16 bound."""
     from paper_2507_18282_amd import Cnn
     from tests.test_gpu_cnn import _effective, _forward_with_bound, _params
     P = synthetic.config_learned()
     say("full size 1023^2 guess")
-    op = _op(P, mg_max_levels=5, mg_coarse_sweeps=4)
+    op = _op(P, mg_max_levels=5, mg_coarse_sweeps=4, predictor="cnn")
     net = Cnn(0)
     params = _params(21)
     net.set_params(params)
     op.set_cnn(net)
     n = P.n[0]
-    wn = synthetic.uniform_pm1(501, n * n).reshape(n, n)
-    wp = synthetic.uniform_pm1(502, n * n).reshape(n, n)
-    got = to_host(op.cnn_guess(to_dev(wn), to_dev(wp))).reshape(n, n)
+    b = synthetic.uniform_pm1(501, n * n).reshape(n, n)
+    got = to_host(op.cnn_guess(to_dev(b))).reshape(n, n)
     h, plan = oracle_plan(P)
     a = 0.5 * plan.dt ** 2
-    s = float(np.sqrt(np.mean(wn * wn)))
+    s = float(np.sqrt(np.mean(b * b)))
     c2, c3 = C.step_planes(a, plan.omega, h[0])
-    x = C.make_input(wn, wp, s, np.float32(c2), np.float32(c3))  # whole grid plus the zero halo
+    x = C.make_input_residual(b, b, s, s, np.float32(c2), np.float32(c3))  # whole grid plus the zero halo
     theta = _effective(params)
-    base = 2.0 / (1.0 + a * plan.omega ** 2)
     win = 48
     for (r0, c0) in ((0, 0), (n - win, n - win), (0, n - win), (500, 333), (n - win, 17)):
         y, bound = _forward_with_bound(theta, x[:, r0:r0 + win + 6, c0:c0 + win + 6])
-        ref = base * wn[r0:r0 + win, c0:c0 + win] + s * y
+        ref = s * y
         assert np.all(np.abs(got[r0:r0 + win, c0:c0 + win] - ref) <= s * bound + 1e-14), (r0, c0)

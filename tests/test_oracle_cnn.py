@@ -13,7 +13,7 @@ from oracle import cnn as C
 
 def _theta(seed, scale=1.0):
     u = synthetic.uniform_pm1(seed, C.N_PARAMS)
-    th = C.init_params(u) * scale
+    th = C.init_params(u, last_layer_zero=False) * scale
     # non-zero biases so that their gradients are exercised
     b = synthetic.uniform_pm1(seed + 1, C.N_PARAMS) * 0.1
     p = C.unpack(th.copy())
@@ -261,3 +261,19 @@ def test_corrected_guess_degenerate_cases():
     xin = C.make_input_residual(r, b, s, 2.0, 0.5, 0.25)
     assert np.array_equal(xin[0, 3:-3, 3:-3], r / s) and np.array_equal(xin[1, 3:-3, 3:-3], b / 2.0)
     assert np.all(xin[:, :3] == 0) and np.all(xin[3, 3:-3, 3:-3] == 0.25)
+
+
+def test_default_init_returns_the_base_guess():
+    """The default initialisation zeroes the last layer: the untrained network
+    outputs 0, so the corrected guess is the base guess; the hidden layers are
+    the He-scaled draws."""
+    u = synthetic.uniform_pm1(151, C.N_PARAMS)
+    th = C.init_params(u)
+    p, q = C.unpack(th), C.unpack(C.init_params(u, last_layer_zero=False))
+    assert np.all(p["W3"] == 0) and np.all(p["b3"] == 0) and np.any(q["W3"] != 0)
+    assert np.array_equal(p["W1"], q["W1"]) and np.array_equal(p["W2"], q["W2"])
+    n = (9, 8)
+    h = D.spacing(n, (1.0, 1.0))
+    b = synthetic.uniform_pm1(152, 72).reshape(8, 9)
+    x0 = 0.1 * synthetic.uniform_pm1(153, 72).reshape(8, 9)
+    assert np.array_equal(C.predict_correction(th, x0, b, h, 4, 1e-3, 10.0), x0)
