@@ -421,13 +421,16 @@ ew_status ew_choose_periods(const ew_grid_desc* grid, const ew_op_desc* desc, in
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent 2D Dirichlet rectangles, explicit leapfrog,
- * FP32 state and filter accumulation (precision EW_PREC_MIXED), FP64 vectors
- * and Arnoldi.  All problems share one stencil order.  Problems with
- * nx, ny <= 128 run their whole wave-solve inside one workgroup; larger ones
- * advance one time step per batched launch.  One batched wave-solve is a
- * captured hipGraph replayed on a private stream and joined to the caller's
- * stream with events.  At creation the tile height of the batched step kernel
- * is chosen by timing the candidates on the batch (ew_batch_info.tune_us).
+ * FP64 vectors and Arnoldi.  The time levels and the filter accumulation are
+ * FP32 (precision EW_PREC_MIXED) or FP64 (EW_PREC_FP64), one precision and
+ * one stencil order for all problems.  With FP32 state, problems with
+ * nx, ny <= 128 run their whole wave-solve inside one workgroup and larger
+ * ones advance one time step per batched launch; with FP64 state every problem
+ * takes the batched step launches.  One batched wave-solve is a captured
+ * hipGraph (a graph of ordinary launches, not a persistent kernel) replayed
+ * on a private stream and joined to the caller's stream with events.  At
+ * creation the tile height of the batched step kernel is chosen by timing the
+ * candidates on the batch (ew_batch_info.tune_us).
  * ------------------------------------------------------------------------ */
 typedef struct ew_batch_s* ew_batch;
 
@@ -440,11 +443,13 @@ typedef struct {
     double tune_us[4];           /* measured time per step launch for 1, 2, 4, 8 rows per thread */
     int64_t total_steps;         /* sum of N_t over the problems */
     int64_t pt_updates_per_wave_solve;
+    int state_fp64;              /* 1: FP64 time levels and accumulation; 0: FP32 */
 } ew_batch_info;
 
 /* grids[i], descs[i] describe problem i (same rules as ew_op_create, plus:
- * dim 2, Dirichlet walls, ts EW_TS_EXPLICIT, precision EW_PREC_MIXED, one
- * order for all).
+ * dim 2, Dirichlet walls, ts EW_TS_EXPLICIT, precision EW_PREC_MIXED or
+ * EW_PREC_FP64, one order and one precision for all; EW_ERR_UNSUPPORTED or
+ * EW_ERR_INVALID_ARG otherwise).
  * Allocates every problem's workspace, autotunes and captures the graph.
  * Host-blocking. */
 ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const ew_op_desc* descs, void* hip_stream,

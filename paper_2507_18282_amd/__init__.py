@@ -280,8 +280,9 @@ class Batch:
     """Many independent 2D explicit problems solved together (see ew_batch_create).
 
     ``problems`` is a list of dicts with keys n, length, order, omega and the
-    optional operator keywords (cfl, n_p, filter_const); every problem uses
-    explicit stepping with FP32 state."""
+    optional operator keywords (cfl, n_p, filter_const, precision); every
+    problem uses explicit stepping, with FP32 state (precision "mixed", the
+    default) or FP64 state (precision "fp64", the same for all problems)."""
 
     def __init__(self, problems, stream=None):
         lib = load()
@@ -309,7 +310,8 @@ class Batch:
         self.info = {"n_small": info.n_small, "n_large": info.n_large, "max_steps_large": info.max_steps_large,
                      "step_rows_per_thread": info.step_rows_per_thread, "tune_us": list(info.tune_us),
                      "total_steps": int(info.total_steps),
-                     "pt_updates_per_wave_solve": int(info.pt_updates_per_wave_solve)}
+                     "pt_updates_per_wave_solve": int(info.pt_updates_per_wave_solve),
+                     "state_fp64": bool(info.state_fp64)}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -12,20 +12,22 @@ constexpr int kConvPerThread = 8;
 
 // Per-problem state visible to the kernels (device array, refreshed before
 // every batched wave-solve).
+// The state arrays hold the batch's state type T (float for FP32 state,
+// double for FP64 state); with FP64 state f0 is the caller's v and acc its
+// out, set before every batched wave-solve.
 struct BatchProbDev {
     Geo g;
     int order;
     int n_t;
-    float dt2;
     int coef_off;
     int active;
-    int pad;
+    double dt2;
     const double* v;   // W^0 (FP64, caller's vector)
     double* out;       // S v (FP64)
-    float* f0;         // W^0 in FP32
-    float* fA;         // odd time levels
-    float* fB;         // even time levels >= 2
-    float* acc;        // filter accumulator
+    void* f0;          // W^0 in the state type
+    void* fA;          // odd time levels
+    void* fB;          // even time levels >= 2
+    void* acc;         // filter accumulator
 };
 
 // Per-problem description of one batched Gram-Schmidt chain.
@@ -45,8 +47,9 @@ struct MgsLink {
 hipError_t launch_batch_small(BatchProbDev* probs, const int* small_ids, int nsmall, const float* coef, int order,
                               size_t lds_bytes, hipStream_t s);
 hipError_t prepare_batch_small(int order, size_t lds_bytes);
+// coef: float (FP32 state) or double (fp64 != 0) filter weights.
 hipError_t launch_batch_step(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
-                             const float* coef, int step, int order, int tyr, hipStream_t s);
+                             const void* coef, int step, int order, int tyr, int fp64, hipStream_t s);
 hipError_t launch_batch_convert(BatchProbDev* probs, const int* ids, const int* blk_start, int nseg, int nblocks,
                                 int to_fp32, hipStream_t s);
 hipError_t launch_batch_mgs(const BatchMgsDev* info, const MgsLink* links, int nprob, const int* blk_start,

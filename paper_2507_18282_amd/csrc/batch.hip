@@ -1,11 +1,14 @@
-// ew_batch: many independent Dirichlet rectangles (explicit leapfrog, FP32
-// state and filter accumulation, FP64 vectors and Arnoldi) advanced together.
+// ew_batch: many independent Dirichlet rectangles (explicit leapfrog, FP32 or
+// FP64 state and filter accumulation, FP64 vectors and Arnoldi) advanced
+// together.
 //
-// One batched wave-solve is a captured hipGraph: the small problems run their
-// whole wave-solve in one LDS-resident workgroup each (k_batch_small, on a
-// forked branch), while every large problem advances one time step per
-// k_batch_step launch (one launch per step index, blocks of problems that are
-// already done exit at once).  The tile height of k_batch_step is chosen at
+// One batched wave-solve is a captured hipGraph: with FP32 state the small
+// problems run their whole wave-solve in one LDS-resident workgroup each
+// (k_batch_small, on a forked branch), while every large problem advances one
+// time step per k_batch_step launch (one launch per step index, blocks of
+// problems that are already done exit at once).  With FP64 state every
+// problem takes the step launches, reading the caller's v as W^0 and
+// accumulating straight into the caller's out.  The tile height of k_batch_step is chosen at
 // creation by timing the candidates on the batch itself.  The Arnoldi process
 // of every problem advances in lock-step: one batched wave-solve, then one
 // batched chain of modified Gram-Schmidt links, then the small host-side
@@ -28,10 +31,10 @@ struct BProb {
     double h[3] = {1, 1, 1};
     TimePlan tp;
     bool small = false;
-    float* f0 = nullptr;
-    float* fA = nullptr;
-    float* fB = nullptr;
-    float* acc = nullptr;
+    void* f0 = nullptr;  // FP32 state only (FP64 state reads v and writes out)
+    void* fA = nullptr;
+    void* fB = nullptr;
+    void* acc = nullptr;
 };
 
 }  // namespace ew
@@ -39,6 +42,7 @@ struct BProb {
 struct ew_batch_s {
     int nprob = 0;
     int order = 2;
+    int fp64 = 0;  // state type: FP64 (precision EW_PREC_FP64) or FP32 (EW_PREC_MIXED)
     hipStream_t user_stream = nullptr;
     hipStream_t stream = nullptr;  // private stream the graph runs on
     hipStream_t side = nullptr;    // branch for the small problems
@@ -46,13 +50,16 @@ struct ew_batch_s {
     std::vector<ew::BProb> P;
     ew::BatchProbDev* probs_dev = nullptr;
     ew::BatchProbDev* probs_host = nullptr;  // pinned
-    float* coef_dev = nullptr;
+    void* coef_dev = nullptr;  // filter weights in the state type
     std::vector<int> small_ids, large_ids;
     int* small_ids_dev = nullptr;
     int* large_ids_dev = nullptr;
     int* step_blk_dev = nullptr;
     int* conv_blk_dev = nullptr;
     int nblocks_step = 0, nblocks_conv = 0, max_nt_large = 0, tyr = 4;
+    // Large problems are ordered by N_t, longest first, so the problems that
+    // still step at step index s are a prefix: step_nblk[s] blocks cover them.
+    std::vector<int> step_nblk;
     size_t small_lds = 0;
     double tune_us[4] = {0, 0, 0, 0};
     hipGraph_t graph = nullptr;
@@ -78,6 +85,12 @@ static ew_status build_step_table(ew_batch b, int tyr) {
     for (size_t s = 0; s < b->large_ids.size(); ++s)
         starts[s + 1] = starts[s] + step_tiles(b->P[b->large_ids[s]].g, tyr);
     b->nblocks_step = starts.back();
+    b->step_nblk.assign(b->max_nt_large, 0);
+    size_t cnt = b->large_ids.size();
+    for (int st = 0; st < b->max_nt_large; ++st) {  // cnt: problems with N_t > st
+        while (cnt > 0 && b->P[b->large_ids[cnt - 1]].tp.n_t <= st) --cnt;
+        b->step_nblk[st] = starts[cnt];
+    }
     EW_HIP_TRY(hipMemcpy(b->step_blk_dev, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice));
     b->tyr = tyr;
     return EW_OK;
@@ -89,18 +102,20 @@ static ew_status capture_graph(ew_batch b) {
     EW_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
     const int nl = (int)b->large_ids.size(), ns = (int)b->small_ids.size();
-    if (nl > 0) e = launch_batch_convert(b->probs_dev, b->large_ids_dev, b->conv_blk_dev, nl, b->nblocks_conv, 1, s);
+    if (nl > 0 && !b->fp64)
+        e = launch_batch_convert(b->probs_dev, b->large_ids_dev, b->conv_blk_dev, nl, b->nblocks_conv, 1, s);
     if (e == hipSuccess && ns > 0) {
         e = hipEventRecord(b->ev_fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
         if (e == hipSuccess)
-            e = launch_batch_small(b->probs_dev, b->small_ids_dev, ns, b->coef_dev, b->order, b->small_lds, b->side);
+            e = launch_batch_small(b->probs_dev, b->small_ids_dev, ns, static_cast<const float*>(b->coef_dev), b->order,
+                                   b->small_lds, b->side);
         if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
     }
     for (int step = 0; e == hipSuccess && step < b->max_nt_large; ++step)
-        e = launch_batch_step(b->probs_dev, b->large_ids_dev, b->step_blk_dev, nl, b->nblocks_step, b->coef_dev, step,
-                              b->order, b->tyr, s);
-    if (e == hipSuccess && nl > 0)
+        e = launch_batch_step(b->probs_dev, b->large_ids_dev, b->step_blk_dev, nl, b->step_nblk[step], b->coef_dev,
+                              step, b->order, b->tyr, b->fp64, s);
+    if (e == hipSuccess && nl > 0 && !b->fp64)
         e = launch_batch_convert(b->probs_dev, b->large_ids_dev, b->conv_blk_dev, nl, b->nblocks_conv, 0, s);
     if (e == hipSuccess && ns > 0) e = hipStreamWaitEvent(s, b->ev_join, 0);
     hipGraph_t g = nullptr;
@@ -113,13 +128,32 @@ static ew_status capture_graph(ew_batch b) {
 }
 
 // Time k_batch_step for every tile height on the batch itself (step index 1
-// on the zero-initialised buffers) and keep the fastest.
+// on the zero-initialised buffers) and keep the fastest.  With FP64 state, W^0
+// and the accumulator (the caller's v and out in a solve) are zeroed buffers
+// of the problem's size that live only for the tuning.
 static ew_status autotune(ew_batch b) {
     if (b->large_ids.empty()) return EW_OK;
+    std::vector<void*> tmp;
+    struct FreeTmp {
+        std::vector<void*>& t;
+        ~FreeTmp() {
+            for (void* p : t) dev_free(p);
+        }
+    } free_tmp{tmp};
     for (int i = 0; i < b->nprob; ++i) {
         b->probs_host[i].active = b->P[i].small ? 0 : 1;
         b->probs_host[i].v = nullptr;
         b->probs_host[i].out = nullptr;
+        if (b->fp64) {
+            for (void** q : {&b->probs_host[i].f0, &b->probs_host[i].acc}) {
+                void* p = nullptr;
+                const hipError_t e = dev_alloc(&p, b->P[i].N * sizeof(double), b->stream);
+                if (e != hipSuccess) return fail(EW_ERR_OOM, std::string("batch tuning buffer: ") + hipGetErrorString(e));
+                tmp.push_back(p);
+                EW_HIP_TRY(launch_fill<double>(static_cast<double*>(p), b->P[i].N, 0.0, b->stream));
+                *q = p;
+            }
+        }
     }
     EW_HIP_TRY(hipMemcpy(b->probs_dev, b->probs_host, b->nprob * sizeof(BatchProbDev), hipMemcpyHostToDevice));
     const int cand[4] = {1, 2, 4, 8};
@@ -132,11 +166,11 @@ static ew_status autotune(ew_batch b) {
         EW_TRY(build_step_table(b, cand[c]));
         const int nl = (int)b->large_ids.size();
         EW_HIP_TRY(launch_batch_step(b->probs_dev, b->large_ids_dev, b->step_blk_dev, nl, b->nblocks_step, b->coef_dev,
-                                     1, b->order, cand[c], b->stream));
+                                     1, b->order, cand[c], b->fp64, b->stream));
         EW_HIP_TRY(hipEventRecord(e0, b->stream));
         for (int r = 0; r < 8; ++r)
             EW_HIP_TRY(launch_batch_step(b->probs_dev, b->large_ids_dev, b->step_blk_dev, nl, b->nblocks_step,
-                                         b->coef_dev, 1, b->order, cand[c], b->stream));
+                                         b->coef_dev, 1, b->order, cand[c], b->fp64, b->stream));
         EW_HIP_TRY(hipEventRecord(e1, b->stream));
         EW_HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -149,6 +183,8 @@ static ew_status autotune(ew_batch b) {
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    EW_HIP_TRY(hipStreamSynchronize(b->stream));  // before the tuning buffers are freed
+    for (int i = 0; i < b->nprob && b->fp64; ++i) b->probs_host[i].f0 = b->probs_host[i].acc = nullptr;
     return build_step_table(b, best_tyr);
 }
 
@@ -159,6 +195,10 @@ static ew_status batch_apply(ew_batch b, const double* const* v, double* const* 
         b->probs_host[i].v = v[i];
         b->probs_host[i].out = out[i];
         b->probs_host[i].active = active ? (active[i] ? 1 : 0) : 1;
+        if (b->fp64) {
+            b->probs_host[i].f0 = const_cast<double*>(v[i]);
+            b->probs_host[i].acc = out[i];
+        }
     }
     EW_HIP_TRY(hipEventRecord(b->ev_in, b->user_stream));
     EW_HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0));
@@ -201,7 +241,8 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
     b->order = grids[0].order;
     b->user_stream = (hipStream_t)hip_stream;
     b->P.resize(nprob);
-    std::vector<float> coef;
+    b->fp64 = descs[0].precision == EW_PREC_FP64 ? 1 : 0;
+    std::vector<double> coef;
     std::vector<int> coef_off(nprob);
     for (int i = 0; i < nprob; ++i) {
         EW_TRY(validate_descs(&grids[i], &descs[i]));
@@ -210,17 +251,19 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
             if (grids[i].walls[d][0] != EW_WALL_DIRICHLET || grids[i].walls[d][1] != EW_WALL_DIRICHLET)
                 return fail(EW_ERR_UNSUPPORTED, "the batched form takes Dirichlet rectangles");
         if (descs[i].ts != EW_TS_EXPLICIT) return fail(EW_ERR_UNSUPPORTED, "the batched form uses explicit stepping");
-        if (descs[i].precision != EW_PREC_MIXED)
-            return fail(EW_ERR_UNSUPPORTED, "the batched form keeps FP32 state (precision EW_PREC_MIXED)");
+        if (descs[i].precision != EW_PREC_MIXED && descs[i].precision != EW_PREC_FP64)
+            return fail(EW_ERR_UNSUPPORTED, "the batched form keeps FP32 (EW_PREC_MIXED) or FP64 state");
+        if ((descs[i].precision == EW_PREC_FP64) != (b->fp64 != 0))
+            return fail(EW_ERR_INVALID_ARG, "all problems of a batch share one precision");
         if (grids[i].order != b->order) return fail(EW_ERR_INVALID_ARG, "all problems of a batch share one order");
         BProb& p = b->P[i];
         for (int k = 0; k < 2; ++k) p.h[k] = grids[i].len[k] / (double)(grids[i].n[k] + 1);
         p.g = make_geo(2, grids[i].n, p.h);
         p.N = p.g.size();
         make_time_plan(2, b->order, p.h, descs[i], p.tp);
-        p.small = p.g.nx <= kBatchSmallMaxSide && p.g.ny <= kBatchSmallMaxSide;
+        p.small = !b->fp64 && p.g.nx <= kBatchSmallMaxSide && p.g.ny <= kBatchSmallMaxSide;
         coef_off[i] = (int)coef.size();
-        for (double c : p.tp.c) coef.push_back((float)c);
+        for (double c : p.tp.c) coef.push_back(c);
     }
     EW_HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     EW_HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
@@ -230,8 +273,14 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
     EW_HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
     EW_HIP_TRY(hipEventCreateWithFlags(&b->ev_copy, hipEventDisableTiming));
     EW_HIP_TRY(hipEventRecord(b->ev_copy, b->stream));
-    EW_TRY(balloc(b.get(), (void**)&b->coef_dev, coef.size() * sizeof(float)));
-    EW_HIP_TRY(hipMemcpy(b->coef_dev, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (b->fp64) {
+        EW_TRY(balloc(b.get(), &b->coef_dev, coef.size() * sizeof(double)));
+        EW_HIP_TRY(hipMemcpy(b->coef_dev, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        const std::vector<float> cf(coef.begin(), coef.end());
+        EW_TRY(balloc(b.get(), &b->coef_dev, cf.size() * sizeof(float)));
+        EW_HIP_TRY(hipMemcpy(b->coef_dev, cf.data(), cf.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     EW_HIP_TRY(hipHostMalloc((void**)&b->probs_host, nprob * sizeof(BatchProbDev), hipHostMallocDefault));
     EW_TRY(balloc(b.get(), (void**)&b->probs_dev, nprob * sizeof(BatchProbDev)));
     std::vector<int> conv_starts(1, 0);
@@ -242,7 +291,7 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
         d.g = p.g;
         d.order = b->order;
         d.n_t = p.tp.n_t;
-        d.dt2 = (float)(p.tp.dt * p.tp.dt);
+        d.dt2 = b->fp64 ? p.tp.dt * p.tp.dt : (double)(float)(p.tp.dt * p.tp.dt);
         d.coef_off = coef_off[i];
         if (p.small) {
             b->small_ids.push_back(i);
@@ -250,18 +299,27 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
         } else {
             b->large_ids.push_back(i);
             b->max_nt_large = std::max(b->max_nt_large, p.tp.n_t);
-            EW_TRY(balloc(b.get(), (void**)&p.f0, p.N * sizeof(float)));
-            EW_TRY(balloc(b.get(), (void**)&p.fA, p.N * sizeof(float)));
-            EW_TRY(balloc(b.get(), (void**)&p.fB, p.N * sizeof(float)));
-            EW_TRY(balloc(b.get(), (void**)&p.acc, p.N * sizeof(float)));
-            for (float* z : {p.f0, p.fA, p.fB, p.acc}) EW_HIP_TRY(launch_fill<float>(z, p.N, 0.0f, b->stream));
+            if (b->fp64) {
+                EW_TRY(balloc(b.get(), &p.fA, p.N * sizeof(double)));
+                EW_TRY(balloc(b.get(), &p.fB, p.N * sizeof(double)));
+                for (void* z : {p.fA, p.fB}) EW_HIP_TRY(launch_fill<double>(static_cast<double*>(z), p.N, 0.0, b->stream));
+            } else {
+                for (void** z : {&p.f0, &p.fA, &p.fB, &p.acc}) {
+                    EW_TRY(balloc(b.get(), z, p.N * sizeof(float)));
+                    EW_HIP_TRY(launch_fill<float>(static_cast<float*>(*z), p.N, 0.0f, b->stream));
+                }
+            }
             d.f0 = p.f0;
             d.fA = p.fA;
             d.fB = p.fB;
             d.acc = p.acc;
-            conv_starts.push_back(conv_starts.back() + (int)((p.N + 256 * kConvPerThread - 1) / (256 * kConvPerThread)));
         }
     }
+    std::stable_sort(b->large_ids.begin(), b->large_ids.end(),
+                     [&](int x, int y) { return b->P[x].tp.n_t > b->P[y].tp.n_t; });
+    for (int i : b->large_ids)
+        conv_starts.push_back(conv_starts.back() +
+                              (int)((b->P[i].N + 256 * kConvPerThread - 1) / (256 * kConvPerThread)));
     b->nblocks_conv = conv_starts.back();
     EW_TRY(balloc(b.get(), (void**)&b->small_ids_dev, (b->small_ids.size() + 1) * sizeof(int)));
     EW_TRY(balloc(b.get(), (void**)&b->large_ids_dev, (b->large_ids.size() + 1) * sizeof(int)));
@@ -297,6 +355,7 @@ extern "C" ew_status ew_batch_get_info(ew_batch b, ew_batch_info* out) {
     }
     out->total_steps = steps;
     out->pt_updates_per_wave_solve = pts;
+    out->state_fp64 = b->fp64;
     return EW_OK;
 }
 

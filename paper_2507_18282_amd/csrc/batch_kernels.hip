@@ -1,5 +1,6 @@
 // Kernels of the batched form: many independent Dirichlet rectangles advanced
-// together, explicit leapfrog in FP32 with the filter accumulated in FP32.
+// together, explicit leapfrog with the filter accumulated in the state type
+// (FP32, or FP64 for k_batch_step).
 //
 //  * k_batch_small   one 1024-thread workgroup per small problem runs the
 //                    whole wave-solve (all N_t steps) with W^n resident in LDS
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kBatchSmallThreads) void k_batch_small(BatchProbDev
     const int tid = threadIdx.x;
     const float cx = ORDER == 2 ? (float)g.ihx2 : (float)(g.ihx2 / 12.0);
     const float cy = ORDER == 2 ? (float)g.ihy2 : (float)(g.ihy2 / 12.0);
-    const float dt2 = P.dt2;
+    const float dt2 = (float)P.dt2;
     const float* c = coef + P.coef_off;
     for (int q = tid; q < px * (ny + 4); q += kBatchSmallThreads) Xs[q] = 0.0f;
     __syncthreads();
@@ -108,10 +109,10 @@ __global__ __launch_bounds__(kBatchSmallThreads) void k_batch_small(BatchProbDev
 // --------------------------------------------------------------------------
 // Large problems: one step for every problem, tiles of 64 x (4 TYR) points.
 // --------------------------------------------------------------------------
-template <int ORDER, int TYR>
+template <int ORDER, int TYR, typename T>
 __global__ __launch_bounds__(256) void k_batch_step(BatchProbDev* __restrict__ probs, const int* __restrict__ large_ids,
                                                     const int* __restrict__ blk_start, int nlarge,
-                                                    const float* __restrict__ coef, int step) {
+                                                    const T* __restrict__ coef, int step) {
     int wb, wy, wz;
     xcd_block(wb, wy, wz);  // each XCD takes a contiguous run of tiles (rows of a problem share halos)
     const int s = find_segment(blk_start, nlarge, wb);
@@ -124,25 +125,29 @@ __global__ __launch_bounds__(256) void k_batch_step(BatchProbDev* __restrict__ p
     const int j0 = (tile / tiles_x) * (4 * TYR) + (threadIdx.x >> 6);
     if (i >= g.nx) return;
     // time level slots: W^0 in f0, odd levels in fA, even levels >= 2 in fB
-    const float* wcur = step == 0 ? P.f0 : ((step & 1) ? P.fA : P.fB);
-    const float* wprev = step == 1 ? P.f0 : ((step & 1) ? P.fB : P.fA);
-    float* wnext = ((step + 1) & 1) ? P.fA : P.fB;
-    const float dt2 = P.dt2;
-    const float c0 = coef[P.coef_off], cn = coef[P.coef_off + step + 1];
+    const T* f0 = static_cast<const T*>(P.f0);
+    T* fA = static_cast<T*>(P.fA);
+    T* fB = static_cast<T*>(P.fB);
+    T* acc = static_cast<T*>(P.acc);
+    const T* wcur = step == 0 ? f0 : ((step & 1) ? fA : fB);
+    const T* wprev = step == 1 ? f0 : ((step & 1) ? fB : fA);
+    T* wnext = ((step + 1) & 1) ? fA : fB;
+    const T dt2 = (T)P.dt2;
+    const T c0 = coef[P.coef_off], cn = coef[P.coef_off + step + 1];
 #pragma unroll
     for (int r = 0; r < TYR; ++r) {
         const int j = j0 + 4 * r;
         if (j >= g.ny) break;
         const int64_t cidx = (int64_t)j * g.nx + i;
-        const float uc = wcur[cidx];
-        const float lap = lap_at<float, ORDER, 2, false>(wcur, cidx, i, j, 0, g, uc);
-        float wn;
+        const T uc = wcur[cidx];
+        const T lap = lap_at<T, ORDER, 2, false>(wcur, cidx, i, j, 0, g, uc);
+        T wn;
         if (step == 0) {
-            wn = uc + (0.5f * dt2) * lap;
-            P.acc[cidx] = c0 * uc + cn * wn;
+            wn = uc + ((T)0.5 * dt2) * lap;
+            acc[cidx] = c0 * uc + cn * wn;
         } else {
-            wn = 2.0f * uc - wprev[cidx] + dt2 * lap;
-            P.acc[cidx] = P.acc[cidx] + cn * wn;
+            wn = (T)2 * uc - wprev[cidx] + dt2 * lap;
+            acc[cidx] = acc[cidx] + cn * wn;
         }
         wnext[cidx] = wn;
     }
@@ -162,8 +167,8 @@ __global__ __launch_bounds__(256) void k_batch_convert(BatchProbDev* __restrict_
     for (int t = 0; t < kConvPerThread; ++t) {
         const int64_t q = base + 256 * t;
         if (q >= n) break;
-        if (to_fp32) P.f0[q] = (float)P.v[q];
-        else P.out[q] = (double)P.acc[q];
+        if (to_fp32) static_cast<float*>(P.f0)[q] = (float)P.v[q];
+        else P.out[q] = (double)static_cast<const float*>(P.acc)[q];
     }
 }
 
@@ -233,16 +238,27 @@ hipError_t prepare_batch_small(int order, size_t lds_bytes) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-hipError_t launch_batch_step(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
-                             const float* coef, int step, int order, int tyr, hipStream_t s) {
-    if (nlarge == 0 || nblocks == 0) return hipSuccess;
-#define EW_BSTEP(O, T) k_batch_step<O, T><<<nblocks, 256, 0, s>>>(probs, large_ids, blk_start, nlarge, coef, step)
+template <typename T>
+static void batch_step_typed(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
+                             const T* coef, int step, int order, int tyr, hipStream_t s) {
+#define EW_BSTEP(O, R) k_batch_step<O, R, T><<<nblocks, 256, 0, s>>>(probs, large_ids, blk_start, nlarge, coef, step)
     if (order == 2) {
         switch (tyr) { case 1: EW_BSTEP(2, 1); break; case 2: EW_BSTEP(2, 2); break; case 4: EW_BSTEP(2, 4); break; default: EW_BSTEP(2, 8); }
     } else {
         switch (tyr) { case 1: EW_BSTEP(4, 1); break; case 2: EW_BSTEP(4, 2); break; case 4: EW_BSTEP(4, 4); break; default: EW_BSTEP(4, 8); }
     }
 #undef EW_BSTEP
+}
+
+hipError_t launch_batch_step(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
+                             const void* coef, int step, int order, int tyr, int fp64, hipStream_t s) {
+    if (nlarge == 0 || nblocks == 0) return hipSuccess;
+    if (fp64)
+        batch_step_typed<double>(probs, large_ids, blk_start, nlarge, nblocks, static_cast<const double*>(coef), step,
+                                 order, tyr, s);
+    else
+        batch_step_typed<float>(probs, large_ids, blk_start, nlarge, nblocks, static_cast<const float*>(coef), step,
+                                order, tyr, s);
     return hipGetLastError();
 }
 
