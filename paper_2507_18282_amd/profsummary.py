@@ -3,6 +3,10 @@
   python -m paper_2507_18282_amd.profsummary trace <kernel_trace.csv> <out.txt> --command "<cmd>"
       per-kernel totals, and per (kernel, grid size) averages so that one level
       of the multigrid hierarchy can be read off directly;
+  python -m paper_2507_18282_amd.profsummary pmc <counter_collection.csv> <out.txt> --kernel SUBSTR [...]
+      --command "<cmd>"
+      mean per dispatch of every counter collected, per (kernel, grid size),
+      for the kernels whose names contain one of the substrings;
   python -m paper_2507_18282_amd.profsummary counters <fetch.csv> <write.csv> <out.txt> --kernel SUBSTR
       --grid G --copy-bytes B --command "<cmd>"
       FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of one kernel at one grid
@@ -98,6 +102,29 @@ def counter_summary(fetch_csv: str, write_csv: str, out_txt: str, kernel: str, g
         f.write("\n".join(lines) + "\n")
 
 
+def pmc_summary(csv_path: str, out_txt: str, kernels, command: str) -> None:
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    disp = collections.defaultdict(set)
+    for r in _rows(csv_path):
+        name = r["Kernel_Name"]
+        if not any(k in name for k in kernels):
+            continue
+        key = (name, _grid(r))
+        per[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        disp[key].add(r.get("Dispatch_Id"))
+    lines = ["# rocprofv3 counter summary (mean per dispatch)", f"# command: {command}",
+             f"# kernel filter: {', '.join(kernels)}", ""]
+    for key in sorted(per, key=lambda k: (k[0], k[1])):
+        name, grid = key
+        lines.append(f"{name[:120]}")
+        lines.append(f"  grid {grid}, dispatches {len(disp[key])}")
+        for cn in sorted(per[key]):
+            vals = per[key][cn]
+            lines.append(f"  {cn} = {statistics.mean(vals):.6g}")
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -115,9 +142,16 @@ def main(argv=None) -> int:
     c.add_argument("--bytes-alg", type=float, required=True)
     c.add_argument("--source", required=True)
     c.add_argument("--command", required=True)
+    q = sub.add_parser("pmc")
+    q.add_argument("csv")
+    q.add_argument("out")
+    q.add_argument("--kernel", action="append", required=True)
+    q.add_argument("--command", required=True)
     a = ap.parse_args(argv)
     if a.mode == "trace":
         trace_summary(a.trace_csv, a.out, a.command)
+    elif a.mode == "pmc":
+        pmc_summary(a.csv, a.out, a.kernel, a.command)
     else:
         counter_summary(a.fetch_csv, a.write_csv, a.out, a.kernel, a.grid, a.copy_bytes, a.command, a.source,
                         a.bytes_alg)
