@@ -232,6 +232,168 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// One full red-black sweep of an order-2 3D level without Neumann walls, by
+// marching a 64 x TY column tile through a chunk of CZ planes.  Planes of x
+// (xy halo 2) and b (xy halo 1) pass through LDS rings of 5 and 3 slots.
+// Step k relaxes the red points of plane k on the tile plus one xy layer (its
+// z-neighbours on planes k +- 1 are black and still old), then the black
+// points of plane k-1 on the tile (all their neighbours are red and final),
+// and writes plane k-1.  The chunk starts one plane early: the red points of
+// plane z0-1 are recomputed from old values, as the chunk below computes
+// them (x is read from xin and written to xout, never in place).  The loads
+// of the next planes are issued one step ahead, into registers.  Same
+// arithmetic as k_sweep_tile except that the weight and the constant diagonal
+// enter as one reciprocal.
+// ---------------------------------------------------------------------------
+template <typename T, bool ZERO_IN, int TY, int CZ>
+__global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict__ xin, const T* __restrict__ b,
+                                                            T bscale, T* __restrict__ xout, Geo g, T a, T inv_diag) {
+    constexpr int TX = 64;
+    constexpr int LX = TX + 4, LY = TY + 4, NXP = LX * LY;  // x plane, halo 2
+    constexpr int BX = TX + 2, BY = TY + 2, NBP = BX * BY;  // b plane, halo 1
+    constexpr int IXP = (NXP + kTileThreads - 1) / kTileThreads, IBP = (NBP + kTileThreads - 1) / kTileThreads;
+    constexpr int NRP = (BY + 7) / 8;                       // red rows per lane
+    static_assert(TY % 8 == 0, "black rows are handed out 8 per pass");
+    __shared__ T X[5][NXP];
+    __shared__ T B[3][NBP];
+    const int tid = threadIdx.x;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * CZ;
+    const int z1 = min(z0 + CZ, g.nz);  // planes written: [z0, z1)
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    const T cx = (T)g.ihx2, cy = (T)g.ihy2, cz = (T)g.ihz2;
+    auto xslot = [](int k) { return (k + 5) % 5; };  // k >= -2
+    auto bslot = [](int k) { return (k + 3) % 3; };
+
+    T xv[IXP], bv[IBP];
+    // global loads of x plane k (tile + 2, zero outside the domain) into xv
+    auto load_x = [&](int k) {
+#pragma unroll
+        for (int t = 0; t < IXP; ++t) {
+            const int q = tid + t * kTileThreads;
+            T v = T(0);
+            if (!ZERO_IN && q < NXP && k >= 0 && k < g.nz) {
+                const int ly = q / LX, lx = q - ly * LX;
+                const int gi = x0 - 2 + lx, gj = y0 - 2 + ly;
+                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = xin[k * plane + (int64_t)gj * g.nx + gi];
+            }
+            xv[t] = v;
+        }
+    };
+    auto load_b = [&](int k) {
+#pragma unroll
+        for (int t = 0; t < IBP; ++t) {
+            const int q = tid + t * kTileThreads;
+            T v = T(0);
+            if (q < NBP && k >= 0 && k < g.nz) {
+                const int ly = q / BX, lx = q - ly * BX;
+                const int gi = x0 - 1 + lx, gj = y0 - 1 + ly;
+                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = b[k * plane + (int64_t)gj * g.nx + gi];
+            }
+            bv[t] = v;
+        }
+    };
+    auto store_x = [&](int k) {
+        T* dst = X[xslot(k)];
+#pragma unroll
+        for (int t = 0; t < IXP; ++t) {
+            const int q = tid + t * kTileThreads;
+            if (q < NXP) dst[q] = xv[t];
+        }
+    };
+    auto store_b = [&](int k) {
+        T* dst = B[bslot(k)];
+#pragma unroll
+        for (int t = 0; t < IBP; ++t) {
+            const int q = tid + t * kTileThreads;
+            if (q < NBP) dst[q] = bscale * bv[t];
+        }
+    };
+    // relaxed value of LDS cell p of plane k (slots of k-1, k, k+1 given)
+    auto relax = [&](const T* Xm, const T* X0, const T* Xp, int p, T bval) -> T {
+        const T uc = X0[p];
+        T s = (X0[p - 1] + X0[p + 1] - T(2) * uc) * cx;
+        s += (X0[p - LX] + X0[p + LX] - T(2) * uc) * cy;
+        s += (Xm[p] + Xp[p] - T(2) * uc) * cz;
+        const T r = bval - (uc - a * s);
+        return uc + r * inv_diag;
+    };
+
+    // prologue: x planes z0-2 and z0-1 in the ring, then the loads of x plane
+    // z0 and of b plane z0-1 in flight (step k stores x plane k+1 and b plane k)
+    load_x(z0 - 2);
+    store_x(z0 - 2);
+    load_x(z0 - 1);
+    store_x(z0 - 1);
+    load_x(z0);
+    load_b(z0 - 1);
+
+    const int rowsel = tid >> 5, m = tid & 31;
+    for (int k = z0 - 1; k <= z1; ++k) {
+        // planes k+1 (x) and k (b) arrive; issue the loads of the next step
+        store_x(k + 1);
+        store_b(k);
+        if (k < z1) {
+            load_x(k + 2);
+            load_b(k + 1);
+        }
+        __syncthreads();
+        // red points of plane k on the tile plus one xy layer
+        if (k >= 0 && k < g.nz) {
+            const T* Xm = X[xslot(k - 1)];
+            T* X0 = X[xslot(k)];
+            const T* Xp = X[xslot(k + 1)];
+            const T* Bk = B[bslot(k)];
+#pragma unroll
+            for (int t = 0; t < NRP; ++t) {
+                const int ry = rowsel + 8 * t;
+                if (ry >= BY) continue;
+                const int gj = y0 - 1 + ry;
+                const int c = 2 * m + ((gj + k) & 1);  // tile column of the red point (x0 is even)
+                const int gi = x0 + c;
+                if (gj < 0 || gj >= g.ny || gi >= g.nx) continue;
+                const int p = (ry + 1) * LX + c + 2;
+                X0[p] = relax(Xm, X0, Xp, p, Bk[ry * BX + c + 1]);
+            }
+            if (tid < BY) {  // the red point of each row in tile column -1 or 64
+                const int ry = tid, gj = y0 - 1 + ry;
+                const int c = ((gj + k) & 1) ? -1 : 64;
+                const int gi = x0 + c;
+                if (gj >= 0 && gj < g.ny && gi >= 0 && gi < g.nx) {
+                    const int p = (ry + 1) * LX + c + 2;
+                    X0[p] = relax(Xm, X0, Xp, p, Bk[ry * BX + c + 1]);
+                }
+            }
+        }
+        __syncthreads();
+        // black points of plane k-1 on the tile; each lane writes its black
+        // point and the red point beside it
+        const int kb = k - 1;
+        if (kb >= z0 && kb < z1) {
+            const T* Xm = X[xslot(kb - 1)];
+            const T* X0 = X[xslot(kb)];
+            const T* Xp = X[xslot(kb + 1)];
+            const T* Bk = B[bslot(kb)];
+#pragma unroll
+            for (int t = 0; t < TY / 8; ++t) {
+                const int ty = rowsel + 8 * t;
+                const int gj = y0 + ty;
+                if (gj >= g.ny) continue;
+                const int cb = 2 * m + ((gj + kb + 1) & 1), cr = cb ^ 1;
+                const int gib = x0 + cb, gir = x0 + cr;
+                T* row = xout + kb * plane + (int64_t)gj * g.nx;
+                const int pb = (ty + 2) * LX + cb + 2;
+                if (gib < g.nx) row[gib] = relax(Xm, X0, Xp, pb, Bk[(ty + 1) * BX + cb + 1]);
+                if (gir < g.nx) row[gir] = X0[(ty + 2) * LX + cr + 2];
+            }
+        }
+        // no barrier here: the next step stores into the slots of planes
+        // k-3 (x) and k+1 (b), which the black phase does not read
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Residual norm per tile: x staged with a halo of R (zero outside the domain,
 // the wall closures of lap_lds), r = bscale b - M x at the tile's points,
 // optionally stored (converted to TR), and the tile's sum of r^2 written to
@@ -745,6 +907,30 @@ static hipError_t sweep_dispatch_tile(const T* xin, const T* xc, const T* b, T b
 // 32 x 8 x 8 tiles from 1024 of them up (127^3 and larger); 16 x 8 x 4 tiles
 // (less serial work per workgroup, 8 times as many workgroups) on smaller
 // levels, where the large tiles leave most CUs idle.
+// Order-2 3D levels without walls and without the fused prolongation march
+// 64 x 8 column tiles through chunks of 16 planes (8 where 16 leave fewer
+// than 1024 workgroups) when that gives at least 512 workgroups.
+template <typename T>
+static bool sweep_z3d_dispatch(const T* xin, const T* b, T bs, T* xout, const Geo& g, double a, double w,
+                               bool zero_in, hipStream_t s, hipError_t* err) {
+    const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
+    const int64_t n16 = cols * ((g.nz + 15) / 16), n8 = cols * ((g.nz + 7) / 8);
+    if (n8 < 512) return false;
+    const T inv = (T)(w / (1.0 + 2.0 * a * (g.ihx2 + g.ihy2 + g.ihz2)));
+    const T aa = (T)a;
+    const bool big = n16 >= 1024;
+    dim3 grid((g.nx + 63) / 64, (g.ny + 7) / 8, big ? (g.nz + 15) / 16 : (g.nz + 7) / 8);
+    if (big) {
+        if (zero_in) k_sweep_z3d<T, true, 8, 16><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
+        else k_sweep_z3d<T, false, 8, 16><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
+    } else {
+        if (zero_in) k_sweep_z3d<T, true, 8, 8><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
+        else k_sweep_z3d<T, false, 8, 8><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
+    }
+    *err = hipGetLastError();
+    return true;
+}
+
 template <typename T, int ORDER, int DIM>
 static hipError_t sweep_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
                                  T a, T w, bool zero_in, bool prolong, hipStream_t s) {
@@ -763,8 +949,10 @@ hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscal
     if (g.dim == 2)
         return launch_sweep2d<T>(xin, xc, b, bscale, xout, g, gc, order, a, w, zero_in, prolong, s, ev0, ev1);
     if (ev0) EW_RET_ON_ERR(hipEventRecord(ev0, s));
-    hipError_t e = order == 2 ? sweep_dispatch<T, 2, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s)
-                              : sweep_dispatch<T, 4, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s);
+    hipError_t e = hipSuccess;
+    if (!(order == 2 && !g.wall && !prolong && sweep_z3d_dispatch<T>(xin, b, bs, xout, g, a, w, zero_in, s, &e)))
+        e = order == 2 ? sweep_dispatch<T, 2, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s)
+                       : sweep_dispatch<T, 4, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     return e;
 }
