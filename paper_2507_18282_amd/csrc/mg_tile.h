@@ -26,6 +26,11 @@ struct CoarseLevels {
 // every relaxed point gets x + w (b - M x)_i / M_ii (w: relaxation weight).
 // xin is not read when zero_in.  xin and xout must not alias.
 // ev0/ev1 (may be null) are recorded at the start and end of the sweep's dispatch.
+// True where the 3D sweep of level g (stencil order `order`) marches through
+// z and applies the prolongation inside the sweep (launch_sweep_tile with
+// prolong); elsewhere 3D V-cycles prolong in a pass of their own.
+bool sweep_z3d_fuses_prolong(const Geo& g, int order);
+
 template <typename T>
 hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g,
                              const Geo& gc, int order, double a, double w, bool zero_in, bool prolong,

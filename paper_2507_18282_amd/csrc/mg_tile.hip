@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
 
 // ---------------------------------------------------------------------------
 // One full red-black sweep of an order-2 3D level without Neumann walls, by
-// marching a 64 x TY column tile through a chunk of CZ planes.  Planes of x
+// marching a 64 x TY column tile through a chunk of `chunk` planes.  Planes of x
 // (xy halo 2) and b (xy halo 1) pass through LDS rings of 5 and 3 slots.
 // Step k relaxes the red points of plane k on the tile plus one xy layer (its
 // z-neighbours on planes k +- 1 are black and still old), then the black
@@ -244,31 +244,86 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
 // of the next planes are issued one step ahead, into registers.  Same
 // arithmetic as k_sweep_tile except that the weight and the constant diagonal
 // enter as one reciprocal.
+//
+// With PROLONG the trilinear interpolation of the coarse solution xc (the
+// prolongation of the V-cycle's coarse-grid correction) is added to every x
+// plane as it enters the ring: the coarse values under the tile are first
+// combined along z for that fine plane (Cz, two coarse planes, staged one
+// step ahead in a double-buffered LDS slot), then interpolated in x and y
+// from LDS.
 // ---------------------------------------------------------------------------
-template <typename T, bool ZERO_IN, int TY, int CZ>
-__global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict__ xin, const T* __restrict__ b,
-                                                            T bscale, T* __restrict__ xout, Geo g, T a, T inv_diag) {
+template <typename T, bool ZERO_IN, bool PROLONG, int TY>
+__global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict__ xin, const T* __restrict__ xc,
+                                                            const T* __restrict__ b, T bscale, T* __restrict__ xout,
+                                                            Geo g, Geo gc, T a, T inv_diag, int chunk) {
     constexpr int TX = 64;
     constexpr int LX = TX + 4, LY = TY + 4, NXP = LX * LY;  // x plane, halo 2
     constexpr int BX = TX + 2, BY = TY + 2, NBP = BX * BY;  // b plane, halo 1
     constexpr int IXP = (NXP + kTileThreads - 1) / kTileThreads, IBP = (NBP + kTileThreads - 1) / kTileThreads;
     constexpr int NRP = (BY + 7) / 8;                       // red rows per lane
+    // coarse cells under an x plane: columns x0/2 - 2 .. x0/2 + 32, rows
+    // y0/2 - 2 .. y0/2 + TY/2 (fine f interpolates coarse (f-1)/2 rounded down and up)
+    constexpr int CXW = 36, CYW = TY / 2 + 3, NCP = CXW * CYW;
+    constexpr int ICP = PROLONG ? (NCP + kTileThreads - 1) / kTileThreads : 1;
     static_assert(TY % 8 == 0, "black rows are handed out 8 per pass");
     __shared__ T X[5][NXP];
     __shared__ T B[3][NBP];
+    __shared__ T CZS[2][PROLONG ? NCP : 1];
     const int tid = threadIdx.x;
     int bx, by, bz;
     xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * CZ;
-    const int z1 = min(z0 + CZ, g.nz);  // planes written: [z0, z1)
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * chunk;
+    const int z1 = min(z0 + chunk, g.nz);  // planes written: [z0, z1)
     const int64_t plane = (int64_t)g.nx * g.ny;
     const T cx = (T)g.ihx2, cy = (T)g.ihy2, cz = (T)g.ihz2;
     auto xslot = [](int k) { return (k + 5) % 5; };  // k >= -2
     auto bslot = [](int k) { return (k + 3) % 3; };
+    const int ccx0 = (x0 >> 1) - 2, ccy0 = (y0 >> 1) - 2;
+    const int64_t cplane = (int64_t)gc.nx * gc.ny;
 
-    T xv[IXP], bv[IBP];
+    // registers of the planes in flight (issuing the loads two steps ahead,
+    // in two register sets, measured slower)
+    struct Regs {
+        T x[IXP], b[IBP], c[ICP];
+    };
+    Regs RA;
+    // coarse values for fine plane f combined along z: f interpolates coarse
+    // plane (f-1)/2 if f-1 is even, else the mean of (f-2)/2 and f/2 (planes
+    // beyond the coarse grid are the zero wall)
+    auto load_cz = [&](T(&cv)[ICP], int f) {
+#pragma unroll
+        for (int t = 0; t < ICP; ++t) {
+            const int q = tid + t * kTileThreads;
+            T v = T(0);
+            if (PROLONG && q < NCP && f >= 0 && f < g.nz) {
+                const int cy = q / CXW, cxx = q - cy * CXW;
+                const int ic = ccx0 + cxx, jc = ccy0 + cy;
+                if (ic >= 0 && ic < gc.nx && jc >= 0 && jc < gc.ny) {
+                    const int qz = f - 1;
+                    const int64_t o = (int64_t)jc * gc.nx + ic;
+                    if (!(qz & 1)) {
+                        v = xc[(qz >> 1) * cplane + o];
+                    } else {
+                        const int ka = (qz - 1) >> 1, kb2 = ka + 1;
+                        const T va = ka >= 0 ? xc[ka * cplane + o] : T(0);
+                        const T vb = kb2 < gc.nz ? xc[kb2 * cplane + o] : T(0);
+                        v = T(0.5) * va + T(0.5) * vb;
+                    }
+                }
+            }
+            cv[t] = v;
+        }
+    };
+    auto store_cz = [&](const T(&cv)[ICP], int f) {
+        T* dst = CZS[f & 1];
+#pragma unroll
+        for (int t = 0; t < ICP; ++t) {
+            const int q = tid + t * kTileThreads;
+            if (PROLONG && q < NCP) dst[q] = cv[t];
+        }
+    };
     // global loads of x plane k (tile + 2, zero outside the domain) into xv
-    auto load_x = [&](int k) {
+    auto load_x = [&](T(&xv)[IXP], int k) {
 #pragma unroll
         for (int t = 0; t < IXP; ++t) {
             const int q = tid + t * kTileThreads;
@@ -281,7 +336,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict_
             xv[t] = v;
         }
     };
-    auto load_b = [&](int k) {
+    auto load_b = [&](T(&bv)[IBP], int k) {
 #pragma unroll
         for (int t = 0; t < IBP; ++t) {
             const int q = tid + t * kTileThreads;
@@ -294,15 +349,34 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict_
             bv[t] = v;
         }
     };
-    auto store_x = [&](int k) {
+    // x plane k into its slot, plus the bilinear interpolation of Cz(k) (in
+    // CZS[k & 1]) at the cells inside the domain with PROLONG
+    auto store_x = [&](const T(&xv)[IXP], int k) {
         T* dst = X[xslot(k)];
+        const T* cz = CZS[k & 1];
 #pragma unroll
         for (int t = 0; t < IXP; ++t) {
             const int q = tid + t * kTileThreads;
-            if (q < NXP) dst[q] = xv[t];
+            if (q >= NXP) continue;
+            T v = xv[t];
+            if (PROLONG && k >= 0 && k < g.nz) {
+                const int ly = q / LX, lx = q - ly * LX;
+                const int gi = x0 - 2 + lx, gj = y0 - 2 + ly;
+                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
+                    const int qi = gi - 1, qj = gj - 1;
+                    const int ia = (qi >> 1) - ccx0, ib = ((qi + 1) >> 1) - ccx0;
+                    const int ja = (qj >> 1) - ccy0, jb = ((qj + 1) >> 1) - ccy0;
+                    const T wia = (qi & 1) ? T(0.5) : T(1), wib = (qi & 1) ? T(0.5) : T(0);
+                    const T wja = (qj & 1) ? T(0.5) : T(1), wjb = (qj & 1) ? T(0.5) : T(0);
+                    const T rowa = wia * cz[ja * CXW + ia] + wib * cz[ja * CXW + ib];
+                    const T rowb = wia * cz[jb * CXW + ia] + wib * cz[jb * CXW + ib];
+                    v += wja * rowa + wjb * rowb;
+                }
+            }
+            dst[q] = v;
         }
     };
-    auto store_b = [&](int k) {
+    auto store_b = [&](const T(&bv)[IBP], int k) {
         T* dst = B[bslot(k)];
 #pragma unroll
         for (int t = 0; t < IBP; ++t) {
@@ -320,23 +394,41 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict_
         return uc + r * inv_diag;
     };
 
-    // prologue: x planes z0-2 and z0-1 in the ring, then the loads of x plane
-    // z0 and of b plane z0-1 in flight (step k stores x plane k+1 and b plane k)
-    load_x(z0 - 2);
-    store_x(z0 - 2);
-    load_x(z0 - 1);
-    store_x(z0 - 1);
-    load_x(z0);
-    load_b(z0 - 1);
+    // prologue: x planes z0-2 and z0-1 in the ring (with PROLONG after Cz of
+    // those planes, and Cz(z0) in its slot), then the loads of x plane z0, b
+    // plane z0-1 and Cz(z0+1) in flight (step k stores x plane k+1, b plane k
+    // and Cz(k+2), and issues the loads of the next step)
+    if (PROLONG) {
+        load_cz(RA.c, z0 - 2);
+        store_cz(RA.c, z0 - 2);
+        load_cz(RA.c, z0 - 1);
+        store_cz(RA.c, z0 - 1);
+        __syncthreads();
+    }
+    load_x(RA.x, z0 - 2);
+    store_x(RA.x, z0 - 2);
+    load_x(RA.x, z0 - 1);
+    store_x(RA.x, z0 - 1);
+    if (PROLONG) {
+        __syncthreads();  // slot (z0-2) & 1 is read above; Cz(z0) replaces it
+        load_cz(RA.c, z0);
+        store_cz(RA.c, z0);
+        __syncthreads();
+        load_cz(RA.c, z0 + 1);
+    }
+    load_x(RA.x, z0);
+    load_b(RA.b, z0 - 1);
 
     const int rowsel = tid >> 5, m = tid & 31;
-    for (int k = z0 - 1; k <= z1; ++k) {
+    auto step = [&](int k, Regs& R) {
         // planes k+1 (x) and k (b) arrive; issue the loads of the next step
-        store_x(k + 1);
-        store_b(k);
+        store_x(R.x, k + 1);
+        store_b(R.b, k);
+        if (PROLONG) store_cz(R.c, k + 2);  // into the slot of Cz(k), last read at step k-1
         if (k < z1) {
-            load_x(k + 2);
-            load_b(k + 1);
+            load_x(R.x, k + 2);
+            load_b(R.b, k + 1);
+            if (PROLONG) load_cz(R.c, k + 3);
         }
         __syncthreads();
         // red points of plane k on the tile plus one xy layer
@@ -390,7 +482,8 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict_
         }
         // no barrier here: the next step stores into the slots of planes
         // k-3 (x) and k+1 (b), which the black phase does not read
-    }
+    };
+    for (int k = z0 - 1; k <= z1; ++k) step(k, RA);
 }
 
 // ---------------------------------------------------------------------------
@@ -907,28 +1000,34 @@ static hipError_t sweep_dispatch_tile(const T* xin, const T* xc, const T* b, T b
 // 32 x 8 x 8 tiles from 1024 of them up (127^3 and larger); 16 x 8 x 4 tiles
 // (less serial work per workgroup, 8 times as many workgroups) on smaller
 // levels, where the large tiles leave most CUs idle.
-// Order-2 3D levels without walls and without the fused prolongation march
-// 64 x 8 column tiles through chunks of 16 planes (8 where 16 leave fewer
-// than 1024 workgroups) when that gives at least 512 workgroups.
+// Order-2 3D levels without walls march 64 x 8 column tiles through chunks
+// of 16 planes (8 where 16 give fewer than 1024 workgroups) when chunks of 8
+// give at least 512 workgroups.  On 255^3 (FP32) chunks of 16 (2048
+// workgroups) measured faster than chunks sized so that every workgroup is
+// resident at once (22 planes, 1536) and than chunks of 11 (3072).
 template <typename T>
-static bool sweep_z3d_dispatch(const T* xin, const T* b, T bs, T* xout, const Geo& g, double a, double w,
-                               bool zero_in, hipStream_t s, hipError_t* err) {
+static bool sweep_z3d_dispatch(const T* xin, const T* xc, const T* b, T bs, T* xout, const Geo& g, const Geo& gc,
+                               double a, double w, bool zero_in, bool prolong, hipStream_t s, hipError_t* err) {
     const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
-    const int64_t n16 = cols * ((g.nz + 15) / 16), n8 = cols * ((g.nz + 7) / 8);
-    if (n8 < 512) return false;
+    if (cols * ((g.nz + 7) / 8) < 512) return false;
+    if (prolong && zero_in) return false;  // not a V-cycle combination
     const T inv = (T)(w / (1.0 + 2.0 * a * (g.ihx2 + g.ihy2 + g.ihz2)));
     const T aa = (T)a;
-    const bool big = n16 >= 1024;
-    dim3 grid((g.nx + 63) / 64, (g.ny + 7) / 8, big ? (g.nz + 15) / 16 : (g.nz + 7) / 8);
-    if (big) {
-        if (zero_in) k_sweep_z3d<T, true, 8, 16><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
-        else k_sweep_z3d<T, false, 8, 16><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
-    } else {
-        if (zero_in) k_sweep_z3d<T, true, 8, 8><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
-        else k_sweep_z3d<T, false, 8, 8><<<grid, kTileThreads, 0, s>>>(xin, b, bs, xout, g, aa, inv);
-    }
+    const int cz = cols * ((g.nz + 15) / 16) >= 1024 ? 16 : 8;
+    dim3 grid((g.nx + 63) / 64, (g.ny + 7) / 8, (g.nz + cz - 1) / cz);
+#define EW_Z3D(Z, P) k_sweep_z3d<T, Z, P, 8><<<grid, kTileThreads, 0, s>>>(xin, xc, b, bs, xout, g, gc, aa, inv, cz)
+    if (prolong) EW_Z3D(false, true);
+    else if (zero_in) EW_Z3D(true, false);
+    else EW_Z3D(false, false);
+#undef EW_Z3D
     *err = hipGetLastError();
     return true;
+}
+
+bool sweep_z3d_fuses_prolong(const Geo& g, int order) {
+    if (g.dim != 3 || order != 2 || g.wall) return false;
+    const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8);
+    return cols * ((g.nz + 7) / 8) >= 512;
 }
 
 template <typename T, int ORDER, int DIM>
@@ -950,7 +1049,7 @@ hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscal
         return launch_sweep2d<T>(xin, xc, b, bscale, xout, g, gc, order, a, w, zero_in, prolong, s, ev0, ev1);
     if (ev0) EW_RET_ON_ERR(hipEventRecord(ev0, s));
     hipError_t e = hipSuccess;
-    if (!(order == 2 && !g.wall && !prolong && sweep_z3d_dispatch<T>(xin, b, bs, xout, g, a, w, zero_in, s, &e)))
+    if (!(order == 2 && !g.wall && sweep_z3d_dispatch<T>(xin, xc, b, bs, xout, g, gc, a, w, zero_in, prolong, s, &e)))
         e = order == 2 ? sweep_dispatch<T, 2, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s)
                        : sweep_dispatch<T, 4, 3>(xin, xc, b, bs, xout, g, gc, aa, ww, zero_in, prolong, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);

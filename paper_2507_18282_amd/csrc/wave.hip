@@ -86,7 +86,7 @@ ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool ze
     }
     T* xc = nullptr;
     EW_TRY(vcycle<T>(l + 1, (T*)C.x[0], (T*)C.x[1], (T*)C.b, 1.0, true, &xc));
-    if (desc.mg_nu2 >= 1 && L.g.dim == 3) {
+    if (desc.mg_nu2 >= 1 && L.g.dim == 3 && !sweep_z3d_fuses_prolong(L.g, order)) {
         // 3D: the prolongation as its own pass (interpolating inside the staged
         // sweep tile reads each coarse value up to eight times from the cache)
         {
