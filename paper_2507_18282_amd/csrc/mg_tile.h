@@ -22,15 +22,15 @@ struct CoarseLevels {
     Geo g[kMaxCoarseLevels];
 };
 
-// One full red-black sweep xout = RB(xin (+ P xc if prolong), bscale b), tile by tile;
-// every relaxed point gets x + w (b - M x)_i / M_ii (w: relaxation weight).
-// xin is not read when zero_in.  xin and xout must not alias.
-// ev0/ev1 (may be null) are recorded at the start and end of the sweep's dispatch.
 // True where the 3D sweep of level g (stencil order `order`) marches through
 // z and applies the prolongation inside the sweep (launch_sweep_tile with
 // prolong); elsewhere 3D V-cycles prolong in a pass of their own.
 bool sweep_z3d_fuses_prolong(const Geo& g, int order);
 
+// One full red-black sweep xout = RB(xin (+ P xc if prolong), bscale b), tile by tile;
+// every relaxed point gets x + w (b - M x)_i / M_ii (w: relaxation weight).
+// xin is not read when zero_in.  xin and xout must not alias.
+// ev0/ev1 (may be null) are recorded at the start and end of the sweep's dispatch.
 template <typename T>
 hipError_t launch_sweep_tile(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g,
                              const Geo& gc, int order, double a, double w, bool zero_in, bool prolong,
@@ -58,6 +58,14 @@ hipError_t launch_residual_tile(const T* x, const T* b, double bscale, const Geo
 template <typename T>
 hipError_t launch_sweep2x2d(const T* xin, const T* b, double bscale, T* xout, const Geo& g, int order, double a,
                             double w, bool zero_in, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// launch_sweep2x_restrict2d: the same two sweeps, then from the same staging
+// bc = full-weighting restriction of the residual bscale b - M xout (what
+// launch_restrict_tile computes from xout); 2D levels without Neumann walls
+// whose coarse level gc has (n-1)/2 points per direction.
+template <typename T>
+hipError_t launch_sweep2x_restrict2d(const T* xin, const T* b, double bscale, T* xout, const Geo& g, int order,
+                                     double a, double w, bool zero_in, T* bc, const Geo& gc, hipStream_t s,
+                                     hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,
                           int order, double a, double w, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,

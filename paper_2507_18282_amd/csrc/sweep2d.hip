@@ -464,6 +464,221 @@ template hipError_t launch_sweep2x2d<double>(const double*, const double*, doubl
 template hipError_t launch_sweep2x2d<float>(const float*, const float*, double, float*, const Geo&, int, double,
                                             double, bool, hipStream_t, hipEvent_t, hipEvent_t);
 
+// ---------------------------------------------------------------------------
+// The two pre-smoothing sweeps of k_sweep2x_tile2d followed, from the same
+// staging, by the residual r = bscale b - M x of the result and its
+// full-weighting restriction (the work of k_restrict_tile), for 2D levels
+// without Neumann walls.  The coarse points of a 64 x TY tile are the 32 x
+// TY/2 whose fine centres 2I + 1, 2J + 1 lie in it; their weights reach one
+// fine row and column beyond the tile, where r needs x one stencil radius
+// further.  So the four half-sweeps relax the tile plus M + 3, M + 2, M + 1
+// and M layers (M = R + 1), x is staged with a halo of R + M + 3 and b with
+// M + 3, every half-sweep writes to LDS, and the tile is written out after
+// the last.  r is formed with the same expressions as k_restrict_tile, over
+// the (64 + 1) x (TY + 1) fine points from the tile's corner, into the LDS of
+// b (no longer needed), and restricted from there.
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER, int TY, bool ZERO_IN>
+__global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const T* __restrict__ xin,
+                                                                          const T* __restrict__ b, T bscale,
+                                                                          T* __restrict__ xout, Geo g, T a,
+                                                                          T inv_diag, T w, T* __restrict__ bc,
+                                                                          Geo gc) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, M = R + 1, H = R + M + 3;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BH = M + 3, BX = TX + 2 * BH, BY = TY + 2 * BH;
+    constexpr int RX = TX + 1, RY = TY + 1, NR = RX * RY;
+    static_assert(NR <= BX * BY, "the residual reuses the LDS of b");
+    static_assert(TY % 2 == 0, "coarse rows pair fine rows");
+    __shared__ T X[LY * LX];
+    __shared__ T B[BY * BX];
+    const int tid = threadIdx.x;
+    int bx, by;
+    xcd_block(bx, by);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY;
+
+    // staging, every global load issued before the first LDS store
+    constexpr int NX = LY * LX, NB = BY * BX;
+    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IB = (NB + kTileThreads - 1) / kTileThreads;
+    {
+        T xv[IX], bv[IB];
+#pragma unroll
+        for (int t = 0; t < IX; ++t) {
+            const int q = tid + t * kTileThreads;
+            T v = T(0);
+            if (!ZERO_IN && q < NX) {
+                const int ly = q / LX, lx = q - ly * LX;
+                const int gi = x0 - H + lx, gj = y0 - H + ly;
+                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = xin[(int64_t)gj * g.nx + gi];
+            }
+            xv[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < IB; ++t) {
+            const int q = tid + t * kTileThreads;
+            T v = T(0);
+            if (q < NB) {
+                const int ly = q / BX, lx = q - ly * BX;
+                const int gi = x0 - BH + lx, gj = y0 - BH + ly;
+                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = b[(int64_t)gj * g.nx + gi];
+            }
+            bv[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < IX; ++t) {
+            const int q = tid + t * kTileThreads;
+            if (q < NX) X[q] = xv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < IB; ++t) {
+            const int q = tid + t * kTileThreads;
+            if (q < NB) B[q] = bscale * bv[t];
+        }
+    }
+    __syncthreads();
+
+    const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
+    // L_h x at LDS cell p of global point (gi, gj) (the Dirichlet closure)
+    auto lap = [&](int p, int gi, int gj, T uc) -> T {
+        T dx, dy;
+        if (ORDER == 2) {
+            dx = X[p - 1] + X[p + 1] - T(2) * uc;
+            dy = X[p - LX] + X[p + LX] - T(2) * uc;
+        } else {
+            const T l2 = (gi == 0) ? -uc : X[p - 2];
+            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
+            dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
+        }
+        return dx * cxc + dy * cyc;
+    };
+    auto relax = [&](int gi, int gj) -> T {
+        const int p = (gj - y0 + H) * LX + (gi - x0 + H);
+        const T bval = B[(gj - y0 + BH) * BX + (gi - x0 + BH)];
+        const T uc = X[p];
+        const T r = bval - (uc - a * lap(p, gi, gj, uc));
+        const bool edge = ORDER == 4 && (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1);
+        return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, 0) : uc + r * inv_diag;
+    };
+    // one half-sweep of colour `colour` on the tile plus K layers, into LDS
+    auto half = [&](auto kc, int colour) {
+        constexpr int K = decltype(kc)::value;
+        constexpr int W2 = (TX + 2 * K) / 2, NRW = TY + 2 * K, NP = NRW * W2;
+        constexpr int IT = (NP + kTileThreads - 1) / kTileThreads;
+        T rv[IT];
+        int rp[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            rp[t] = -1;
+            const int idx = tid + t * kTileThreads;
+            if (idx >= NP) continue;
+            const int r = idx / W2, k2 = idx - r * W2;
+            const int gj = y0 - K + r;
+            const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
+            if (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx) continue;
+            rv[t] = relax(gi, gj);
+            rp[t] = (gj - y0 + H) * LX + (gi - x0 + H);
+        }
+        if (ORDER == 4) __syncthreads();  // same-colour neighbours are read old (order 4 only)
+#pragma unroll
+        for (int t = 0; t < IT; ++t)
+            if (rp[t] >= 0) X[rp[t]] = rv[t];
+        __syncthreads();
+    };
+    half(std::integral_constant<int, M + 3>{}, 0);  // red, first sweep
+    half(std::integral_constant<int, M + 2>{}, 1);  // black, first sweep
+    half(std::integral_constant<int, M + 1>{}, 0);  // red, second sweep
+    half(std::integral_constant<int, M>{}, 1);      // black, second sweep
+
+    // the tile's new iterate
+    for (int q = tid; q < TX * TY; q += kTileThreads) {
+        const int r = q / TX, c = q - r * TX;
+        const int gi = x0 + c, gj = y0 + r;
+        if (gi < g.nx && gj < g.ny) xout[(int64_t)gj * g.nx + gi] = X[(r + H) * LX + c + H];
+    }
+    // residual over fine points [x0, x0 + 64] x [y0, y0 + TY] (0 outside the grid)
+    constexpr int IR = (NR + kTileThreads - 1) / kTileThreads;
+    T rv[IR];
+#pragma unroll
+    for (int t = 0; t < IR; ++t) {
+        const int q = tid + t * kTileThreads;
+        T r = T(0);
+        if (q < NR) {
+            const int ry = q / RX, rx = q - ry * RX;
+            const int gi = x0 + rx, gj = y0 + ry;
+            if (gi < g.nx && gj < g.ny) {
+                const int p = (ry + H) * LX + rx + H;
+                const T uc = X[p];
+                r = B[(ry + BH) * BX + rx + BH] - (uc - a * lap(p, gi, gj, uc));
+            }
+        }
+        rv[t] = r;
+    }
+    __syncthreads();  // every read of b is done: its LDS takes r
+#pragma unroll
+    for (int t = 0; t < IR; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NR) B[q] = rv[t];
+    }
+    __syncthreads();
+    // full weighting onto the coarse points of the tile
+    for (int q = tid; q < (TX / 2) * (TY / 2); q += kTileThreads) {
+        const int cy = q / (TX / 2), cx = q - cy * (TX / 2);
+        const int ic = (x0 >> 1) + cx, jc = (y0 >> 1) + cy;
+        if (ic >= gc.nx || jc >= gc.ny) continue;
+        const int fx = 2 * cx + 1, fy = 2 * cy + 1;
+        T sum = T(0);
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+            T row = T(0);
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) row += (ox == 0 ? T(0.5) : T(0.25)) * B[(fy + oy) * RX + fx + ox];
+            sum += (oy == 0 ? T(0.5) : T(0.25)) * row;
+        }
+        bc[(int64_t)jc * gc.nx + ic] = sum;
+    }
+}
+
+template <typename T, int ORDER, int TY>
+static hipError_t sweep2x_restrict_launch(const T* xin, const T* b, T bs, T* xout, const Geo& g, T aa, T inv, T w,
+                                          bool zero_in, T* bc, const Geo& gc, hipStream_t s, hipEvent_t ev0,
+                                          hipEvent_t ev1) {
+    dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
+    dim3 block(kTileThreads);
+    if (zero_in)
+        hipExtLaunchKernelGGL((k_sweep2x_restrict_tile2d<T, ORDER, TY, true>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv, w, bc, gc);
+    else
+        hipExtLaunchKernelGGL((k_sweep2x_restrict_tile2d<T, ORDER, TY, false>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv, w, bc, gc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep2x_restrict2d(const T* xin, const T* b, double bscale, T* xout, const Geo& g, int order,
+                                     double a, double w, bool zero_in, T* bc, const Geo& gc, hipStream_t s,
+                                     hipEvent_t ev0, hipEvent_t ev1) {
+    if (g.dim != 2 || g.wall || gc.nx != (g.nx - 1) / 2 || gc.ny != (g.ny - 1) / 2) return hipErrorInvalidValue;
+    const double c0 = order == 2 ? 2.0 : 30.0 / 12.0;
+    const T inv = (T)(w / (1.0 + a * c0 * (g.ihx2 + g.ihy2)));
+    const T bs = (T)bscale, ww = (T)w, aa = (T)a;
+    // the tile heights of the plain fused pre-smoothing
+    const bool tall = (int64_t)((g.nx + 63) / 64) * ((g.ny + 15) / 16) >= 1024;
+    if (order == 2)
+        return tall ? sweep2x_restrict_launch<T, 2, 16>(xin, b, bs, xout, g, aa, inv, ww, zero_in, bc, gc, s, ev0, ev1)
+                    : sweep2x_restrict_launch<T, 2, 8>(xin, b, bs, xout, g, aa, inv, ww, zero_in, bc, gc, s, ev0, ev1);
+    return tall ? sweep2x_restrict_launch<T, 4, 16>(xin, b, bs, xout, g, aa, inv, ww, zero_in, bc, gc, s, ev0, ev1)
+                : sweep2x_restrict_launch<T, 4, 8>(xin, b, bs, xout, g, aa, inv, ww, zero_in, bc, gc, s, ev0, ev1);
+}
+
+template hipError_t launch_sweep2x_restrict2d<double>(const double*, const double*, double, double*, const Geo&, int,
+                                                      double, double, bool, double*, const Geo&, hipStream_t,
+                                                      hipEvent_t, hipEvent_t);
+template hipError_t launch_sweep2x_restrict2d<float>(const float*, const float*, double, float*, const Geo&, int,
+                                                     double, double, bool, float*, const Geo&, hipStream_t,
+                                                     hipEvent_t, hipEvent_t);
+
 template <typename T>
 hipError_t launch_sweep2d(const T* xin, const T* xc, const T* b, double bscale, T* xout, const Geo& g, const Geo& gc,
                           int order, double a, double w, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,

@@ -350,7 +350,9 @@ def test_trained_network_lowers_initial_residual_on_held_out_solves():
     """Trained on the projection residuals of wave-solves from some start
     vectors, the network's guesses on wave-solves from other start vectors
     leave a smaller initial residual ||b - M x0|| / ||b|| than the projection
-    guess they correct (both measured inside the solves)."""
+    guess they correct (both measured inside the solves), and the multigrid,
+    iterated to the same tolerance, needs fewer V-cycles than from the zero
+    guess on the same wave-solves."""
     from paper_2507_18282_amd import Cnn, CropStore
     say("cnn held-out residuals")
     nx = ny = 127
@@ -374,3 +376,10 @@ def test_trained_network_lowers_initial_residual_on_held_out_solves():
     base, guess = st["base_rel_res_sum"], st["guess_rel_res_sum"]
     say("held-out mean relative residual: base", base / st["guess_probes"], "network", guess / st["guess_probes"])
     assert guess < 0.8 * base
+    cold = _implicit_op((nx, ny), 4, 35.0, predictor="zero")
+    w = to_dev(synthetic.uniform_pm1(777, nx * ny))
+    for _ in range(4):
+        w = cold.apply_filter(w / w.norm())
+    warm_cycles, cold_cycles = st["mg_cycles"], cold.stats()["mg_cycles"]
+    say("V-cycles over 4 wave-solves: learned", warm_cycles, "zero guess", cold_cycles)
+    assert warm_cycles < cold_cycles
