@@ -157,9 +157,15 @@ ew_status apply_L_sym(Workspace& ws, const double* in, double* out) {
     return EW_OK;
 }
 
-// Probe runs test for convergence before the basis is full, at these sizes
-// and their doublings (the last test is always at the full basis).
-constexpr int kProbeFirstCheck = 64;
+// Probe runs test for convergence before the basis is full, at basis sizes
+// from kProbeFirstCheck on that are a power of two or three times one (16,
+// 24, 32, 48, 64, ...; the last test is always at the full basis).
+constexpr int kProbeFirstCheck = 16;
+static bool probe_check_size(int s) {
+    if (s < kProbeFirstCheck) return false;
+    while ((s & 1) == 0) s >>= 1;
+    return s == 1 || s == 3;
+}
 
 // One Krylov-Schur run on S deflated by the nl locked vectors, started from
 // column 0 of ws.V (already filled, not yet orthonormalised).
@@ -227,7 +233,7 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
     if (!(coeff.back() > 0.0)) return fail(EW_ERR_NONFINITE, "start vector lies in the locked space");
     // probe runs test for convergence after the steps that reach these basis sizes
     auto probe_check_at = [&](int s) {
-        return probe > 0 && s < m && s >= kProbeFirstCheck && (s & (s - 1)) == 0;
+        return probe > 0 && s < m && probe_check_size(s);
     };
     auto budget_hit = [&]() {
         // Budget reached inside a cycle: report no converged pairs.
