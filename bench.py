@@ -135,6 +135,47 @@ def cpu_baseline(P, n_solves: int):
             "host": {"logical_cpus": ncpu, "model": model},
             "per_cores": {str(c): {"value": rate[c], "seconds": runs[c]} for c in runs}}
 
+def vcycle_roofline(op, n_cycles: int = 20):
+    """Time whole V-cycles of the headline operator (ew_op_mg_vcycle, the
+    kernels of the solves, without convergence tests) and each finest-level
+    pass, against the algorithmic bytes of a V(2,1) cycle: 144 B per
+    finest-level point (13.5 FP64 arrays: 3 per red-black sweep, 2.25 for the
+    residual and restriction, 2.25 for the prolongation and correction, times
+    4/3 for the coarser levels)."""
+    import torch
+    from paper_2507_18282_amd import fill_uniform
+    n = op.n_active
+    b = fill_uniform(n, 71)
+    x = fill_uniform(n, 72)
+    op.mg_vcycle(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_cycles):
+        op.mg_vcycle(b, x)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) / n_cycles * 1e6
+    bytes_cycle = 144.0 * n
+    out = {"us_per_cycle": round(us, 2), "bytes_alg_per_cycle": bytes_cycle,
+           "achieved_GBs": round(bytes_cycle / (us * 1e-6) / 1e9, 1), "peak_GBs": HBM_PEAK_GBS,
+           "frac": round(bytes_cycle / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "finest_level": {}}
+    for cls, what in (("smooth", "two pre-smoothing sweeps in one pass"),
+                      ("prolong", "prolongation + post-smoothing sweep"),
+                      ("restrict", "residual + full-weighting restriction")):
+        op.profile_begin(cls, level=0)
+        for _ in range(n_cycles):
+            op.mg_vcycle(b, x)
+        torch.cuda.synchronize()
+        p = op.profile_end()
+        if p["launches"]:
+            avg = p["total_ms"] / p["launches"] * 1e3
+            gbs = p["bytes_alg"] / p["launches"] / (avg * 1e-6) / 1e9
+            out["finest_level"][cls] = {"kernel": what, "avg_us": round(avg, 2), "alg_GBs": round(gbs, 1),
+                                        "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "share_of_cycle": round(avg / us, 3)}
+    log(f"V-cycle: {us:.1f} us, {out['achieved_GBs']:.0f} GB/s algorithmic ({out['frac']:.2f} of peak)")
+    return out
+
+
 def _batch_run(Ps, precision: str, tol_ritz: float, tol_res: float, budget: int):
     """One batched eigensolve of every problem against the same problems solved
     one after the other, same budget of wave-solves per problem; pairs counted
@@ -731,6 +772,8 @@ def main(argv=None) -> int:
                 "frac_min_traffic": round(achieved / 2 / HBM_PEAK_GBS, 4),
                 "kernel_share_of_step": round(prof["total_ms"] * 1e-3 / elapsed, 3)}
 
+    vcycle = vcycle_roofline(op)
+
     # Eigenpairs per second: a complete solve of the 64^2 explicit workload.
     P1 = synthetic.config_small_explicit()
     op1 = Operator(n=P1.n, length=P1.length, order=P1.order, omega=P1.omega, ts=P1.ts, cfl=P1.cfl)
@@ -779,6 +822,7 @@ def main(argv=None) -> int:
         "eigenpairs_per_s": eig,
         "eigenpairs_per_s_headline": headline_eigs,
         "roofline": roofline,
+        "vcycle_roofline": vcycle,
         "cpu_baseline": cpu,
         "forms": forms,
     }
