@@ -699,8 +699,8 @@ def main(argv=None) -> int:
                     help="skip the complete headline eigensolve (the eigenpairs/s of the headline workload)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU decomposition is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); a multi-GPU decomposition "
+              "(slabs with a halo exchange per half-sweep) is not built", file=sys.stderr)
         return 2
     import torch
     import synthetic
