@@ -143,12 +143,16 @@ typedef struct {
  *                      2 a S / (1 + 2 a S) for order 2, (34/12) a S /
  *                      (1 + (30/12) a S) for order 4, S = sum_d 1/h_d^2 on
  *                      that level), raised to mg_coarse_sweeps, is <= 0.1.
- *   mg_relax           implicit boxes only: relaxation weight w of every
- *                      red-black half-sweep, x_i += w (b - M x)_i / M_ii
- *                      (w > 1: over-relaxed red-black Gauss-Seidel); 0 = the
- *                      default, 1.1 in 2D and 1.15 in 3D (the weights that
- *                      took fewest V-cycles per solve); else in (0, 2).
- *                      Mapped grids ignore it. */
+ *   mg_relax           implicit boxes only: relaxation weight w of the
+ *                      finest level's red-black half-sweeps,
+ *                      x_i += w (b - M x)_i / M_ii (w > 1: over-relaxed
+ *                      red-black Gauss-Seidel); 0 = the default 1.2; else in
+ *                      (0, 2).
+ *   mg_relax_coarse    the same weight on every coarser level (a level of one
+ *                      point always uses 1, an exact solve); 0 = the default
+ *                      1.05; else in (0, 2).  The defaults took the fewest
+ *                      V-cycles per solve on the 2D and 3D workloads tried.
+ *                      Mapped grids ignore both. */
 enum { EW_MG_LEVELS_AUTO = -1 };
 typedef struct {
     double omega;
@@ -169,6 +173,7 @@ typedef struct {
     int proj_window;
     int mg_max_levels;
     double mg_relax;
+    double mg_relax_coarse;
 } ew_op_desc;
 
 /* Read-only facts about an operator. */
@@ -180,7 +185,8 @@ typedef struct {
     double t_final;       /* T_f */
     double alpha_d;       /* eq. alphad at omega_used * dt */
     int mg_levels;        /* multigrid levels (implicit), else 0 */
-    double mg_relax;      /* relaxation weight of the box smoothers in use */
+    double mg_relax;      /* relaxation weight of the finest level's box smoother in use */
+    double mg_relax_coarse; /* ... and of the coarser levels */
 } ew_op_info;
 
 /* Cumulative counters of an operator (reset by ew_op_reset_stats). */

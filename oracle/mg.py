@@ -21,7 +21,8 @@ remaining choices are this project's readings, stated here once:
   With a relaxation weight w the correction is scaled,
   x_i <- x_i + w (b - M x)_i / M_ii (w = 1: the plain sweep; w > 1:
   over-relaxed red-black Gauss-Seidel, a standard variant of the same
-  smoother family).
+  smoother family).  The finest level may take its own weight (``relax``)
+  and every coarser level another (``relax_coarse``).
 * restriction: full weighting, tensor product of [1 2 1]/4.
 * prolongation: multilinear interpolation (the transpose of full weighting
   up to the factor 2^dim), zero boundary values.
@@ -155,7 +156,7 @@ class Hierarchy:
 
     def __init__(self, n: Sequence[int], h: Sequence[float], order: int, a: float,
                  nu1: int = 2, nu2: int = 1, coarse_sweeps: int = 8, max_levels: int = 64,
-                 relax: float = 1.0):
+                 relax: float = 1.0, relax_coarse: float = None):
         self.sizes = level_sizes(n, max_levels)
         self.h = [tuple(hd * (2 ** l) for hd in h) for l in range(len(self.sizes))]
         self.order = order
@@ -164,6 +165,12 @@ class Hierarchy:
         self.nu2 = nu2
         self.coarse_sweeps = coarse_sweeps
         self.relax = relax
+        self.relax_coarse = relax if relax_coarse is None else relax_coarse
+
+    def weight(self, level: int) -> float:
+        """Relaxation weight of the red-black sweeps on ``level``: ``relax`` on
+        the finest level, ``relax_coarse`` below it."""
+        return self.relax if level == 0 else self.relax_coarse
 
     def shape(self, level: int) -> Tuple[int, ...]:
         return self.sizes[level][::-1]
@@ -176,7 +183,7 @@ def coarse_solve(x: np.ndarray, b: np.ndarray, hier: Hierarchy, level: int) -> n
     if b.size == 1:
         return b / diag_M(b.shape, h, hier.order, hier.a)
     for _ in range(hier.coarse_sweeps):
-        x = rb_sweep(x, b, h, hier.order, hier.a, hier.relax)
+        x = rb_sweep(x, b, h, hier.order, hier.a, hier.weight(level))
     return x
 
 
@@ -186,13 +193,13 @@ def vcycle(x: np.ndarray, b: np.ndarray, hier: Hierarchy, level: int = 0) -> np.
     if level == len(hier.sizes) - 1:
         return coarse_solve(x, b, hier, level)
     for _ in range(hier.nu1):
-        x = rb_sweep(x, b, h, hier.order, hier.a, hier.relax)
+        x = rb_sweep(x, b, h, hier.order, hier.a, hier.weight(level))
     r = residual(x, b, h, hier.order, hier.a)
     bc = restrict_full_weighting(r)
     xc = vcycle(np.zeros_like(bc), bc, hier, level + 1)
     x = x + prolong_linear(xc, x.shape)
     for _ in range(hier.nu2):
-        x = rb_sweep(x, b, h, hier.order, hier.a, hier.relax)
+        x = rb_sweep(x, b, h, hier.order, hier.a, hier.weight(level))
     return x
 
 

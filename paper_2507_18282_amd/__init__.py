@@ -81,7 +81,8 @@ class Operator:
                  filter_const: str = "alpha_d", precision: str = "fp64", mg_tol: float = 1e-10,
                  mg_nu1: int = 2, mg_nu2: int = 1, mg_max_cycles: int = 100, mg_coarse_sweeps: int = 8,
                  mg_coarse_points: int = 0, predictor: str = "zero", proj_window: int = 0,
-                 mg_max_levels: int = 0, mg_relax: float = 0.0, walls=None, coords=None, stream=None):
+                 mg_max_levels: int = 0, mg_relax: float = 0.0, mg_relax_coarse: float = 0.0, walls=None,
+                 coords=None, stream=None):
         lib = load()
         self._lib = lib
         g = _lib.GridDesc()
@@ -110,6 +111,7 @@ class Operator:
         d.proj_window = int(proj_window)
         d.mg_max_levels = -1 if mg_max_levels == "auto" else int(mg_max_levels)
         d.mg_relax = float(mg_relax)
+        d.mg_relax_coarse = float(mg_relax_coarse)
         self._stream = stream
         self._h = ctypes.c_void_p()
         if coords is None:
@@ -135,6 +137,7 @@ class Operator:
         self.alpha_d = float(info.alpha_d)
         self.mg_levels = int(info.mg_levels)
         self.mg_relax = float(info.mg_relax)
+        self.mg_relax_coarse = float(info.mg_relax_coarse)
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -262,7 +265,7 @@ def _grid_desc(n, length, order):
 
 def _op_desc(omega, ts, cfl=0.5, n_its=10, n_p=1, adjust_omega=False, filter_const="alpha_d", precision="fp64",
              mg_tol=1e-10, mg_nu1=2, mg_nu2=1, mg_max_cycles=100, mg_coarse_sweeps=8, mg_coarse_points=0,
-             predictor="zero", proj_window=0, mg_max_levels=0, mg_relax=0.0):
+             predictor="zero", proj_window=0, mg_max_levels=0, mg_relax=0.0, mg_relax_coarse=0.0):
     d = _lib.OpDesc()
     d.omega, d.ts, d.cfl, d.n_its, d.n_p = float(omega), _lib.TS[ts], float(cfl), int(n_its), int(n_p)
     d.adjust_omega, d.filter_const = int(bool(adjust_omega)), _lib.FILTER[filter_const]
@@ -273,6 +276,7 @@ def _op_desc(omega, ts, cfl=0.5, n_its=10, n_p=1, adjust_omega=False, filter_con
     d.proj_window = int(proj_window)
     d.mg_max_levels = int(mg_max_levels)
     d.mg_relax = float(mg_relax)
+    d.mg_relax_coarse = float(mg_relax_coarse)
     return d
 
 

@@ -33,13 +33,13 @@ class OpDesc(ctypes.Structure):
                 ("adjust_omega", c_int), ("filter_const", c_int), ("precision", c_int), ("mg_tol", c_double),
                 ("mg_nu1", c_int), ("mg_nu2", c_int), ("mg_max_cycles", c_int), ("mg_coarse_sweeps", c_int),
                 ("mg_coarse_points", c_int), ("predictor", c_int), ("proj_window", c_int),
-                ("mg_max_levels", c_int), ("mg_relax", c_double)]
+                ("mg_max_levels", c_int), ("mg_relax", c_double), ("mg_relax_coarse", c_double)]
 
 
 class OpInfo(ctypes.Structure):
     _fields_ = [("n_active", c_int64), ("n_t", c_int), ("dt", c_double), ("omega_used", c_double),
                 ("t_final", c_double), ("alpha_d", c_double), ("mg_levels", c_int),
-                ("mg_relax", c_double)]
+                ("mg_relax", c_double), ("mg_relax_coarse", c_double)]
 
 
 class OpStats(ctypes.Structure):

@@ -40,9 +40,11 @@ template <typename T>
 hipError_t launch_restrict_tile(const T* x, const T* b, double bscale, const Geo& gf, int order, double a, T* bc,
                                 const Geo& gc, hipStream_t s);
 // V-cycle over the levels of c in one workgroup; x_in may be null (zero start).
+// w0: relaxation weight of c's first level, w: of the others (a level of one
+// point uses 1).
 template <typename T>
 hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_out, const CoarseLevels& c, int order,
-                                double a, double w, int nu1, int nu2, int coarse_sweeps, hipStream_t s);
+                                double a, double w0, double w, int nu1, int nu2, int coarse_sweeps, hipStream_t s);
 template <typename T>
 hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes);
 // Residual norm by tiles: tile_partial (residual_tiles(g) doubles) receives

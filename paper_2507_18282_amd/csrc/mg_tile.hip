@@ -907,8 +907,9 @@ __device__ void pad_prolong(T* xf, const Geo& gf, const T* xc, const Geo& gc) {
 
 template <typename T, int ORDER, int DIM>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __restrict__ b_in, const T* __restrict__ x_in,
-                                                                  T* __restrict__ x_out, CoarseLevels c, T a, T w,
-                                                                  int nu1, int nu2, int coarse_sweeps, T bscale) {
+                                                                  T* __restrict__ x_out, CoarseLevels c, T a, T w0,
+                                                                  T w, int nu1, int nu2, int coarse_sweeps,
+                                                                  T bscale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* smem = reinterpret_cast<T*>(smem_raw);
     const int L = c.nlev;
@@ -932,12 +933,14 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
         }
         __syncthreads();
     }
+    // weight of the kernel's first level w0 (the caller's level weight), w below
     for (int l = 0; l < L - 1; ++l) {
         T* x = smem + c.off_x[l];
         T* b = smem + c.off_b[l];
+        const T wl = l == 0 ? w0 : w;
         for (int s = 0; s < nu1; ++s) {
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 0);
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 1);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 1);
         }
         pad_restrict<T, ORDER, DIM>(x, b, c.g[l], a, smem + c.off_b[l + 1], c.g[l + 1], smem + c.off_r);
     }
@@ -948,7 +951,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
         // one point: a single half-sweep with weight 1 is the exact solve
         const bool one = c.g[l].size() == 1;
         const int sweeps = one ? 1 : coarse_sweeps;
-        const T wl = one ? T(1) : w;
+        const T wl = one ? T(1) : (l == 0 ? w0 : w);
         for (int s = 0; s < sweeps; ++s) {
             pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 0);
             pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 1);
@@ -958,9 +961,10 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(const T* __res
         T* x = smem + c.off_x[l];
         T* b = smem + c.off_b[l];
         pad_prolong<T, DIM>(x, c.g[l], smem + c.off_x[l + 1], c.g[l + 1]);
+        const T wl = l == 0 ? w0 : w;
         for (int s = 0; s < nu2; ++s) {
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 0);
-            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, w, 1);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 0);
+            pad_half_sweep<T, ORDER, DIM>(x, b, c.g[l], a, wl, 1);
         }
     }
     {
@@ -1094,15 +1098,15 @@ hipError_t launch_restrict_tile(const T* x, const T* b, double bscale, const Geo
 
 template <typename T>
 hipError_t launch_coarse_vcycle(const T* b, double bscale, const T* x_in, T* x_out, const CoarseLevels& c, int order,
-                                double a, double w, int nu1, int nu2, int coarse_sweeps, hipStream_t s) {
+                                double a, double w0, double w, int nu1, int nu2, int coarse_sweeps, hipStream_t s) {
     const size_t lds = (size_t)c.lds_elems * sizeof(T);
-    const T aa = (T)a, bs = (T)bscale, ww = (T)w;
+    const T aa = (T)a, bs = (T)bscale, ww0 = (T)w0, ww = (T)w;
     if (c.g[0].dim == 2) {
-        if (order == 2) k_coarse_vcycle<T, 2, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
-        else k_coarse_vcycle<T, 4, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
+        if (order == 2) k_coarse_vcycle<T, 2, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww0, ww, nu1, nu2, coarse_sweeps, bs);
+        else k_coarse_vcycle<T, 4, 2><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww0, ww, nu1, nu2, coarse_sweeps, bs);
     } else {
-        if (order == 2) k_coarse_vcycle<T, 2, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
-        else k_coarse_vcycle<T, 4, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww, nu1, nu2, coarse_sweeps, bs);
+        if (order == 2) k_coarse_vcycle<T, 2, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww0, ww, nu1, nu2, coarse_sweeps, bs);
+        else k_coarse_vcycle<T, 4, 3><<<1, kCoarseThreads, lds, s>>>(b, x_in, x_out, c, aa, ww0, ww, nu1, nu2, coarse_sweeps, bs);
     }
     return hipGetLastError();
 }
@@ -1122,7 +1126,7 @@ hipError_t prepare_coarse_vcycle(int dim, int order, size_t lds_bytes) {
                                              hipEvent_t);                                                         \
     template hipError_t launch_restrict_tile<T>(const T*, const T*, double, const Geo&, int, double, T*,         \
                                                 const Geo&, hipStream_t);                                         \
-    template hipError_t launch_coarse_vcycle<T>(const T*, double, const T*, T*, const CoarseLevels&, int, double, \
+    template hipError_t launch_coarse_vcycle<T>(const T*, double, const T*, T*, const CoarseLevels&, int, double, double, \
                                                 double, int, int, int, hipStream_t);                              \
     template hipError_t prepare_coarse_vcycle<T>(int, int, size_t);
 EW_INST_TILE(double)

@@ -54,6 +54,7 @@ double filter_weight(const TimePlan& tp, int k);
 void grid_geometry(const ew_grid_desc* grid, int64_t n[3], double len[3], double h[3], int* wall);
 ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d);
 double default_relax(double mg_relax, int dim, int order);
+constexpr double kDefaultRelaxCoarse = 1.05;  // weight of the coarser levels' box smoothers
 
 // Whole explicit wave-solve of a small 2D grid in one workgroup (wave_small.hip).
 template <typename T>
@@ -87,7 +88,8 @@ struct Op {
     int device = 0;
     bool mixed = false, implicit = false;
     double omega_used = 0, t_final = 0, dt = 0, alpha_d = 0, a = 0;
-    double relax = 1.0;        // relaxation weight of the box smoothers (resolved mg_relax)
+    double relax = 1.0;         // relaxation weight of the finest level's box smoother (resolved mg_relax)
+    double relax_coarse = 1.0;  // ... of the coarser levels (resolved mg_relax_coarse)
     int n_t = 0;
     std::vector<double> c;
     // single curvilinear grid (explicit FP64 only): coefficients of the mapped operator
@@ -158,7 +160,9 @@ struct Op {
     // multigrid (wave.hip)
     // Relaxation weight of level l: 1 on a single-point level, where one
     // half-sweep with weight 1 is the exact solve.
-    double level_relax(int l) const { return levels[l].g.size() == 1 ? 1.0 : relax; }
+    double level_relax(int l) const {
+        return levels[l].g.size() == 1 ? 1.0 : (l == 0 ? relax : relax_coarse);
+    }
     template <typename T>
     ew_status vcycle(int level, T* cur, T* other, const T* b, double bscale, bool zero, T** result);
     template <typename T>

@@ -248,6 +248,8 @@ ew_status validate_descs(const ew_grid_desc* g, const ew_op_desc* d) {
             return fail(EW_ERR_INVALID_ARG, "mg_max_levels must be >= 0 or EW_MG_LEVELS_AUTO");
         if (!(d->mg_relax == 0.0 || (d->mg_relax > 0.0 && d->mg_relax < 2.0)))
             return fail(EW_ERR_INVALID_ARG, "mg_relax must be 0 (default) or in (0, 2)");
+        if (!(d->mg_relax_coarse == 0.0 || (d->mg_relax_coarse > 0.0 && d->mg_relax_coarse < 2.0)))
+            return fail(EW_ERR_INVALID_ARG, "mg_relax_coarse must be 0 (default) or in (0, 2)");
         if (d->predictor == EW_PRED_CNN && (g->dim != 2))
             return fail(EW_ERR_UNSUPPORTED, "the learned predictor is implemented for 2D grids");
     }
@@ -381,16 +383,17 @@ void grid_geometry(const ew_grid_desc* grid, int64_t n[3], double len[3], double
     }
 }
 
-// Relaxation weight of the red-black box smoothers: the caller's, or for 0 the
-// weight that took fewest V(2,1) cycles per implicit solve to 1e-10 on MI355X
-// (weights 1 to 1.25 in steps of 0.05): 2047^2 order 4 at omega 120, 9.97 ->
-// 8.77 cycles with 1.1; 1023^2 order 4 at omega 90, 9.63 -> 8.77 with 1.1;
-// 2047^2 order 2 at omega 60, 8.5 -> 8.15 with 1.1; the 255^3 order-2 cube at
-// omega 40 (mixed), 9.95 -> 8.1 with 1.15.
+// Default relaxation weights of the box smoothers: 1.2 on the finest level,
+// 1.05 on the coarser ones.  Measured in the V-cycles per implicit solve of
+// an Arnoldi sequence (one weight on every level before): the 2047^2 order-4
+// headline 9.56 (1.1 everywhere) -> 8.99; 1023^2 order 4 at omega 90, 9.72 ->
+// 8.93; 2047^2 order 2 at omega 60, 8.86 -> 8.43; the 255^3 mixed cube, 9.2
+// (1.15 everywhere) -> 8.4; the 127^3 cube unchanged.  The finest level, where
+// a dt^2 / h^2 is largest, wants the most over-relaxation.
 double default_relax(double mg_relax, int dim, int order) {
+    (void)dim;
     (void)order;
-    if (mg_relax != 0.0) return mg_relax;
-    return dim == 2 ? 1.1 : 1.15;
+    return mg_relax != 0.0 ? mg_relax : 1.2;
 }
 }  // namespace ew
 
@@ -413,6 +416,7 @@ extern "C" ew_status ew_op_create(const ew_grid_desc* grid, const ew_op_desc* de
     make_plan(op.get());
     op->a = 0.5 * op->dt * op->dt;
     op->relax = default_relax(desc->mg_relax, op->dim, op->order);
+    op->relax_coarse = desc->mg_relax_coarse != 0.0 ? desc->mg_relax_coarse : kDefaultRelaxCoarse;
 
     const int64_t N = op->N;
     EW_TRY(op->alloc((void**)&op->partial_dev, kRedBlocks * sizeof(double) * 4));
@@ -467,6 +471,7 @@ extern "C" ew_status ew_op_get_info(ew_op op, ew_op_info* out) {
     out->alpha_d = op->alpha_d;
     out->mg_levels = (int)op->levels.size();
     out->mg_relax = op->relax;
+    out->mg_relax_coarse = op->relax_coarse;
     return EW_OK;
 }
 

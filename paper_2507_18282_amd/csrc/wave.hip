@@ -66,8 +66,9 @@ ew_status Op::vcycle(int l, T* cur, T* other, const T* b, double bscale, bool ze
         CoarseLevels c = coarse;
         {
             ProfScope ps(this, EW_K_COARSE, l, sizeof(T) * 3.0 * (double)L.g.size());
-            EW_HIP_TRY(launch_coarse_vcycle<T>(b, bscale, zero ? nullptr : cur, cur, c, order, a, relax, desc.mg_nu1,
-                                               desc.mg_nu2, desc.mg_coarse_sweeps, stream));
+            EW_HIP_TRY(launch_coarse_vcycle<T>(b, bscale, zero ? nullptr : cur, cur, c, order, a, level_relax(l),
+                                               relax_coarse, desc.mg_nu1, desc.mg_nu2, desc.mg_coarse_sweeps,
+                                               stream));
         }
         *result = cur;
         return EW_OK;

@@ -116,29 +116,33 @@ IMPLICIT_CASES = [
 ]
 
 
-def _mg_hierarchy(P, a, relax):
-    return OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=8, relax=relax)
+def _mg_hierarchy(P, a, op):
+    return OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=8,
+                         relax=op.mg_relax, relax_coarse=op.mg_relax_coarse)
 
 
 def test_default_relaxation_weights():
-    """mg_relax = 0 selects the documented defaults; a given weight is kept."""
-    assert make_op(IMPLICIT_CASES[0]).mg_relax == 1.1      # 2D order 2
-    assert make_op(IMPLICIT_CASES[1]).mg_relax == 1.1      # 2D order 4
-    assert make_op(IMPLICIT_CASES[2]).mg_relax == 1.15     # 3D order 2
-    assert make_op(IMPLICIT_CASES[1], mg_relax=1.0).mg_relax == 1.0
+    """mg_relax = mg_relax_coarse = 0 select the documented defaults (1.2 on
+    the finest level, 1.05 below); given weights are kept."""
+    for P in IMPLICIT_CASES[:3]:
+        op = make_op(P)
+        assert (op.mg_relax, op.mg_relax_coarse) == (1.2, 1.05)
+    op = make_op(IMPLICIT_CASES[1], mg_relax=1.0, mg_relax_coarse=1.3)
+    assert (op.mg_relax, op.mg_relax_coarse) == (1.0, 1.3)
 
 
 # mg_coarse_points: 0 lets the single-workgroup kernel take every level that
 # fits in LDS; 40 sends all but the last levels through the tiled kernels.
-# mg_relax: 0 = the default over-relaxed sweep, 1 = plain red-black Gauss-Seidel.
-@pytest.mark.parametrize("relax", [0.0, 1.0])
+# (mg_relax, mg_relax_coarse): the defaults, plain red-black Gauss-Seidel, and
+# a coarse weight above the finest one.
+@pytest.mark.parametrize("relax", [(0.0, 0.0), (1.0, 1.0), (1.1, 1.3)], ids=str)
 @pytest.mark.parametrize("coarse_points", [0, 40])
 @pytest.mark.parametrize("P", IMPLICIT_CASES, ids=lambda P: f"{P.n}-o{P.order}")
 def test_mg_half_sweep_and_vcycle_match_oracle(P, coarse_points, relax):
-    op = make_op(P, mg_coarse_points=coarse_points, mg_relax=relax)
+    op = make_op(P, mg_coarse_points=coarse_points, mg_relax=relax[0], mg_relax_coarse=relax[1])
     h, plan = oracle_plan(P)
     a = 0.5 * plan.dt ** 2
-    hier = _mg_hierarchy(P, a, op.mg_relax)
+    hier = _mg_hierarchy(P, a, op)
     assert op.mg_levels == len(hier.sizes)
     shape = P.n[::-1]
     b = synthetic.uniform_pm1(21, P.n_active)
@@ -163,7 +167,7 @@ def test_truncated_hierarchy_vcycle_and_solve_match_oracle(P, max_levels):
     h, plan = oracle_plan(P)
     a = 0.5 * plan.dt ** 2
     hier = OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=8,
-                         max_levels=max_levels, relax=op.mg_relax)
+                         max_levels=max_levels, relax=op.mg_relax, relax_coarse=op.mg_relax_coarse)
     assert op.mg_levels == len(hier.sizes) == max_levels
     shape = P.n[::-1]
     b = synthetic.uniform_pm1(23, P.n_active)
@@ -217,7 +221,7 @@ def test_auto_depth_vcycle_and_solve_match_oracle(P):
     want_levels = _auto_levels(P, a, 4)
     assert op.mg_levels == want_levels
     hier = OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=4,
-                         max_levels=want_levels, relax=op.mg_relax)
+                         max_levels=want_levels, relax=op.mg_relax, relax_coarse=op.mg_relax_coarse)
     shape = P.n[::-1]
     b = synthetic.uniform_pm1(25, P.n_active)
     x = synthetic.uniform_pm1(26, P.n_active)
@@ -245,7 +249,7 @@ def test_mg_solve_reaches_exact_solution(P, coarse_points):
     assert rel <= P.mg_tol
     assert np.linalg.norm(x - xe) <= P.mg_tol * np.linalg.norm(b) * 1.0001
     # same cycle count as the oracle solver from the same start
-    hier = _mg_hierarchy(P, 0.5 * plan.dt ** 2, op.mg_relax)
+    hier = _mg_hierarchy(P, 0.5 * plan.dt ** 2, op)
     _, oc, _ = OMG.solve(b.reshape(P.n[::-1]), hier, P.mg_tol)
     assert abs(cycles - oc) <= 1
 
@@ -297,7 +301,7 @@ def test_zmarch_sweep_vcycle_and_solve_match_oracle():
     op = make_op(P)
     h, plan = oracle_plan(P)
     a = 0.5 * plan.dt ** 2
-    hier = _mg_hierarchy(P, a, op.mg_relax)
+    hier = _mg_hierarchy(P, a, op)
     assert op.mg_levels == len(hier.sizes)
     shape = P.n[::-1]
     b = synthetic.uniform_pm1(41, P.n_active)

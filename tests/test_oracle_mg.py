@@ -180,3 +180,31 @@ def test_weighted_mg_converges_to_exact_solution(order, w):
     assert rel <= 1e-10 and cw <= c1
     xe = W.solve_implicit_exact(b, h, order, plan.dt)
     assert np.linalg.norm(xw - xe) <= 1e-10 * np.linalg.norm(b) * 1.0000001
+
+
+@pytest.mark.parametrize("n,order", [((63, 63), 2), ((63, 63), 4), ((15, 15, 15), 2)])
+def test_level_weights_converge_to_exact_solution(n, order):
+    """Weight 1.2 on the finest level and 1.05 below it: the V(2,1) solve
+    still reaches the exact implicit solve (dense / sine-transform), so the
+    per-level weights change the smoother, never the fixed point."""
+    h = D.spacing(n, (1.0,) * len(n))
+    plan = D.time_plan(h, order, 8.0, "implicit", n_its=10, adjust_omega=True)
+    a = 0.5 * plan.dt ** 2
+    b = synthetic.uniform_pm1(53, int(np.prod(n))).reshape(n[::-1])
+    hier = mg.Hierarchy(n, h, order, a, relax=1.2, relax_coarse=1.05)
+    assert hier.weight(0) == 1.2 and all(hier.weight(l) == 1.05 for l in range(1, len(hier.sizes)))
+    x, c, rel = mg.solve(b, hier, 1e-10)
+    assert rel <= 1e-10
+    xe = W.solve_implicit_exact(b, h, order, plan.dt)
+    assert np.linalg.norm(x - xe) <= 1e-10 * np.linalg.norm(b) * 1.0000001
+
+
+def test_equal_level_weights_reproduce_single_weight_cycle():
+    n = (31, 31)
+    h = D.spacing(n, (1.0, 1.0))
+    a = 0.002
+    b = synthetic.uniform_pm1(54, 31 * 31).reshape(31, 31)
+    x = synthetic.uniform_pm1(55, 31 * 31).reshape(31, 31)
+    one = mg.vcycle(x, b, mg.Hierarchy(n, h, 4, a, relax=1.1))
+    two = mg.vcycle(x, b, mg.Hierarchy(n, h, 4, a, relax=1.1, relax_coarse=1.1))
+    assert np.array_equal(one, two)
