@@ -568,14 +568,17 @@ def headline_np_rule(budget: int = 400):
 def many_pairs(ks=None):
     """The square128 grid (127^2 interior), order 2, implicit 10 steps/period,
     omega 12 (adjusted), FP64 multigrid to 1e-10, one period: k eigenpairs at
-    once with a Krylov dimension of 2k + 1, for k = 16, 64, 256, 512."""
+    once with a Krylov dimension of 2k + 1, for k = 16, 64, 256, 512.  The
+    Ritz tolerance equals the multigrid tolerance: S is applied to that
+    accuracy, so a smaller one cannot be met reliably (with 1e-12 the counts
+    of wave-solves follow the rounding of the multigrid)."""
     import torch
     import synthetic
     from paper_2507_18282_amd import Operator
     out = {"workload": "unit square 129^2 points (127^2 interior, h=1/128), order 2, implicit 10 steps/period, "
                        "omega 12 (adjusted), FP64 multigrid to 1e-10 (automatic depth: 127^2..15^2), N_p 1, "
                        "Krylov dimension 2k+1, "
-                       "tol_ritz 1e-12, eig-res <= 1e-8"}
+                       "tol_ritz 1e-10 (= the multigrid tolerance), eig-res <= 1e-8"}
     for k in (ks or sorted(MANY_PAIRS_PAPER)):
         P = synthetic.config_many_pairs(k=k)
         op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its,
@@ -583,7 +586,8 @@ def many_pairs(ks=None):
                       mg_coarse_sweeps=MG_COARSE_SWEEPS)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = op.eigs(P.k, P.m, seed=P.seed, want_vectors=False, k_cap=3 * k, raise_on_error=False)
+        r = op.eigs(P.k, P.m, seed=P.seed, tol_ritz=P.mg_tol, want_vectors=False, k_cap=3 * k,
+                    raise_on_error=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         conv, ws = MANY_PAIRS_PAPER.get(k, (None, None))
