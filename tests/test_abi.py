@@ -73,6 +73,11 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h)) == -1
     assert b"n_its" in lib.ew_last_error()
     d.n_its = 10
+    for field, bad in (("mg_relax", 2.0), ("mg_relax", -0.5), ("mg_relax_coarse", 2.5)):
+        setattr(d, field, bad)
+        assert lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h)) == -1
+        assert field.encode() in lib.ew_last_error()
+        setattr(d, field, 0.0)
     d.omega = -1.0
     assert lib.ew_op_create(ctypes.byref(g), ctypes.byref(d), None, ctypes.byref(h)) == -1
     assert lib.ew_op_apply_filter(None, None, None) == -1
