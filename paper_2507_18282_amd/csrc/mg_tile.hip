@@ -88,31 +88,43 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ xc, const Geo& gc,
 // Second difference along one axis of an LDS tile (un-scaled), where cells
 // outside the domain hold 0 (the wall); the order-4 ghost beyond the wall is
 // the odd reflection of the point itself when it is the first or last point.
-template <typename T, int ORDER>
+// IN: the point lies at least two points inside the grid (no ghost).
+template <typename T, int ORDER, bool IN = false>
 __device__ __forceinline__ T d2_lds(const T* X, int p, int stride, int gi, int n, T uc) {
     const T l1 = X[p - stride], r1 = X[p + stride];
     if (ORDER == 2) return l1 + r1 - T(2) * uc;
-    const T l2 = (gi == 0) ? -uc : X[p - 2 * stride];
-    const T r2 = (gi == n - 1) ? -uc : X[p + 2 * stride];
+    const T l2 = (!IN && gi == 0) ? -uc : X[p - 2 * stride];
+    const T r2 = (!IN && gi == n - 1) ? -uc : X[p + 2 * stride];
     return T(16) * (l1 + r1) - (l2 + r2) - T(30) * uc;
 }
 
 // L_h at LDS cell p whose neighbours beyond a wall read 0: the wall closures
 // of d2_framed (Dirichlet odd reflection, Neumann even reflection).  WALLS =
 // false compiles the Dirichlet-only closure, which `walls` = false (a tile
-// away from Neumann walls) also selects.
-template <typename T, int ORDER, int DIM, bool WALLS>
+// away from Neumann walls) also selects; IN (a point at least two points
+// inside the grid) drops the ghost tests of that closure.
+// The axis coefficients of L_h, formed once per kernel (each is a division).
+template <typename T>
+struct AxisCoefs {
+    T x, y, z;
+};
+template <typename T, int ORDER>
+__device__ __forceinline__ AxisCoefs<T> axis_coefs(const Geo& g) {
+    return {axis_coef<T, ORDER>(g.ihx2), axis_coef<T, ORDER>(g.ihy2), axis_coef<T, ORDER>(g.ihz2)};
+}
+
+template <typename T, int ORDER, int DIM, bool WALLS, bool IN = false>
 __device__ __forceinline__ T lap_lds(const T* X, int p, int sy, int sz, int gi, int gj, int gk, const Geo& g, T uc,
-                                     bool walls = true) {
-    if (!WALLS || !walls) {
-        T s = d2_lds<T, ORDER>(X, p, 1, gi, g.nx, uc) * axis_coef<T, ORDER>(g.ihx2);
-        s += d2_lds<T, ORDER>(X, p, sy, gj, g.ny, uc) * axis_coef<T, ORDER>(g.ihy2);
-        if (DIM == 3) s += d2_lds<T, ORDER>(X, p, sz, gk, g.nz, uc) * axis_coef<T, ORDER>(g.ihz2);
+                                     const AxisCoefs<T>& k, bool walls = true) {
+    if (IN || !WALLS || !walls) {
+        T s = d2_lds<T, ORDER, IN>(X, p, 1, gi, g.nx, uc) * k.x;
+        s += d2_lds<T, ORDER, IN>(X, p, sy, gj, g.ny, uc) * k.y;
+        if (DIM == 3) s += d2_lds<T, ORDER, IN>(X, p, sz, gk, g.nz, uc) * k.z;
         return s;
     }
-    T s = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3) * axis_coef<T, ORDER>(g.ihx2);
-    s += d2_framed<T, ORDER>(X, p, sy, gj, g.ny, uc, (g.wall >> 2) & 3) * axis_coef<T, ORDER>(g.ihy2);
-    if (DIM == 3) s += d2_framed<T, ORDER>(X, p, sz, gk, g.nz, uc, (g.wall >> 4) & 3) * axis_coef<T, ORDER>(g.ihz2);
+    T s = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3) * k.x;
+    s += d2_framed<T, ORDER>(X, p, sy, gj, g.ny, uc, (g.wall >> 2) & 3) * k.y;
+    if (DIM == 3) s += d2_framed<T, ORDER>(X, p, sz, gk, g.nz, uc, (g.wall >> 4) & 3) * k.z;
     return s;
 }
 
@@ -132,6 +144,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
     __shared__ T X[LX * LY * LZ];
     __shared__ T B[BX * BY * BZ];
     const int tid = threadIdx.x;
+    const AxisCoefs<T> kc = axis_coefs<T, ORDER>(g);
     int bx, by, bz;
     xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
     const int x0 = bx * TX, y0 = by * TY, z0 = (DIM == 3) ? bz * TZ : 0;
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
         if (((gi + gj + gk) & 1) != 0) continue;
         const int p = (bx + H - 1) + LX * ((by + H - 1) + LY * ((DIM == 3) ? (bz + H - 1) : 0));
         const T uc = X[p];
-        const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw);
+        const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, kc, nw);
         const T r = B[q] - (uc - a * lap);
         rv[t] = uc + (w * r) / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
         rp[t] = p;
@@ -222,7 +235,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile(const T* __restrict
         const T uc = X[p];
         T out = uc;
         if (((gi + gj + gk) & 1) == 1) {
-            const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw);
+            const T lap = lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, kc, nw);
             const int qb = (tx + 1) + BX * ((ty + 1) + BY * ((DIM == 3) ? (tz + 1) : 0));
             const T r = B[qb] - (uc - a * lap);
             out = uc + (w * r) / mdiag_w<T, ORDER, DIM>(gi, gj, gk, g, a, nw ? g.wall : 0);
@@ -505,22 +518,18 @@ int64_t residual_tiles(const Geo& g) {
            ((g.nz + ResTile<3>::TZ - 1) / ResTile<3>::TZ);
 }
 
-template <typename T, typename TR, int ORDER, int DIM, bool WALLS>
-__global__ __launch_bounds__(kTileThreads) void k_residual_tile(const T* __restrict__ x, const T* __restrict__ b,
-                                                                T bscale, Geo g, T a, double* __restrict__ tile_partial,
-                                                                TR* __restrict__ r_out) {
+// One tile of k_residual_tile; IN: a 2D tile whose staged halo lies inside
+// the grid (tile_inside2d), so no load, point or ghost needs a test.
+template <typename T, typename TR, int ORDER, int DIM, bool WALLS, bool IN>
+__device__ __forceinline__ double residual_tile_body(const T* __restrict__ x, const T* __restrict__ b, T bscale,
+                                                     const Geo& g, T a, TR* __restrict__ r_out, T* X, int tid,
+                                                     int x0, int y0, int z0, bool nw) {
     constexpr int TX = ResTile<DIM>::TX, TY = ResTile<DIM>::TY, TZ = ResTile<DIM>::TZ;
     constexpr int R = ORDER / 2;
     constexpr int LX = TX + 2 * R, LY = TY + 2 * R, LZ = (DIM == 3) ? TZ + 2 * R : 1;
     constexpr int NX = LX * LY * LZ, NP = TX * TY * TZ;
     constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IP = NP / kTileThreads;
-    static_assert(NP % kTileThreads == 0, "whole points per thread");
-    __shared__ T X[NX];
-    const int tid = threadIdx.x;
-    int bx, by, bz;
-    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
-    const int x0 = bx * TX, y0 = by * TY, z0 = (DIM == 3) ? bz * TZ : 0;
-    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, z0, z0 + TZ, R);  // uniform per tile
+    const AxisCoefs<T> kc = axis_coefs<T, ORDER>(g);
     // every global load of a thread is issued before the first LDS store
     T xv[IX], bv[IP];
 #pragma unroll
@@ -530,7 +539,8 @@ __global__ __launch_bounds__(kTileThreads) void k_residual_tile(const T* __restr
         if (q < NX) {
             const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
             const int gi = x0 - R + lx, gj = y0 - R + ly, gk = (DIM == 3) ? z0 - R + lz : 0;
-            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz) v = x[lin(g, gi, gj, gk)];
+            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny && gk >= 0 && gk < g.nz))
+                v = x[lin(g, gi, gj, gk)];
         }
         xv[t] = v;
     }
@@ -538,7 +548,7 @@ __global__ __launch_bounds__(kTileThreads) void k_residual_tile(const T* __restr
     for (int t = 0; t < IP; ++t) {
         const int q = tid + t * kTileThreads;
         const int gi = x0 + q % TX, gj = y0 + (q / TX) % TY, gk = z0 + q / (TX * TY);
-        bv[t] = (gi < g.nx && gj < g.ny && gk < g.nz) ? b[lin(g, gi, gj, gk)] : T(0);
+        bv[t] = (IN || (gi < g.nx && gj < g.ny && gk < g.nz)) ? b[lin(g, gi, gj, gk)] : T(0);
     }
 #pragma unroll
     for (int t = 0; t < IX; ++t) {
@@ -552,12 +562,39 @@ __global__ __launch_bounds__(kTileThreads) void k_residual_tile(const T* __restr
         const int q = tid + t * kTileThreads;
         const int tx = q % TX, ty = (q / TX) % TY, tz = q / (TX * TY);
         const int gi = x0 + tx, gj = y0 + ty, gk = z0 + tz;
-        if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
+        if (!IN && (gi >= g.nx || gj >= g.ny || gk >= g.nz)) continue;
         const int p = (tx + R) + LX * ((ty + R) + LY * ((DIM == 3) ? (tz + R) : 0));
         const T uc = X[p];
-        const T r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, g, uc, nw));
+        const T r = bscale * bv[t] -
+                    (uc - a * lap_lds<T, ORDER, DIM, WALLS, IN>(X, p, LX, LX * LY, gi, gj, gk, g, uc, kc, nw));
         if (r_out) r_out[lin(g, gi, gj, gk)] = (TR)r;
         acc += (double)r * (double)r;
+    }
+    return acc;
+}
+
+template <typename T, typename TR, int ORDER, int DIM, bool WALLS>
+__global__ __launch_bounds__(kTileThreads) void k_residual_tile(const T* __restrict__ x, const T* __restrict__ b,
+                                                                T bscale, Geo g, T a, double* __restrict__ tile_partial,
+                                                                TR* __restrict__ r_out) {
+    constexpr int TX = ResTile<DIM>::TX, TY = ResTile<DIM>::TY, TZ = ResTile<DIM>::TZ;
+    constexpr int R = ORDER / 2;
+    constexpr int LX = TX + 2 * R, LY = TY + 2 * R, LZ = (DIM == 3) ? TZ + 2 * R : 1;
+    static_assert((TX * TY * TZ) % kTileThreads == 0, "whole points per thread");
+    __shared__ T X[LX * LY * LZ];
+    const int tid = threadIdx.x;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY, z0 = (DIM == 3) ? bz * TZ : 0;
+    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, z0, z0 + TZ, R);  // uniform per tile
+    double acc;
+    if constexpr (DIM == 2) {
+        if (!nw && tile_inside2d(g, x0, x0 + TX, y0, y0 + TY, R))
+            acc = residual_tile_body<T, TR, ORDER, DIM, WALLS, true>(x, b, bscale, g, a, r_out, X, tid, x0, y0, z0, nw);
+        else
+            acc = residual_tile_body<T, TR, ORDER, DIM, WALLS, false>(x, b, bscale, g, a, r_out, X, tid, x0, y0, z0, nw);
+    } else {
+        acc = residual_tile_body<T, TR, ORDER, DIM, WALLS, false>(x, b, bscale, g, a, r_out, X, tid, x0, y0, z0, nw);
     }
     const double s = block_sum_256(acc, tid);
     if (tid == 0) tile_partial[bx + gridDim.x * (by + gridDim.y * bz)] = s;
@@ -601,26 +638,19 @@ template hipError_t launch_residual_tile<double, float>(const double*, const dou
 // ---------------------------------------------------------------------------
 // Residual + full-weighting restriction per coarse tile.
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int DIM, int CY, bool WALLS>
-__global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restrict__ x, const T* __restrict__ b,
-                                                                T bscale, Geo gf, T a, T* __restrict__ bc, Geo gc) {
+// One coarse tile of k_restrict_tile; IN: a 2D tile whose fine region and
+// stencil reach lie inside the grid (tile_inside2d), so no load, point or
+// ghost needs a test.
+template <typename T, int ORDER, int DIM, int CY, bool WALLS, bool IN>
+__device__ __forceinline__ void restrict_tile_body(const T* __restrict__ x, const T* __restrict__ b, T bscale,
+                                                   const Geo& gf, T a, T* __restrict__ bc, const Geo& gc, T* X, T* Rf,
+                                                   int tid, int cx0, int cy0, int cz0, int fx0, int fy0, int fz0,
+                                                   bool nw) {
     constexpr int CX = RestrictTile<DIM>::CX, CZ = RestrictTile<DIM>::CZ;
     constexpr int R = ORDER / 2;
     constexpr int FX = 2 * CX + 1, FY = 2 * CY + 1, FZ = (DIM == 3) ? 2 * CZ + 1 : 1;
     constexpr int LX = FX + 2 * R, LY = FY + 2 * R, LZ = (DIM == 3) ? FZ + 2 * R : 1;
-    __shared__ T X[LX * LY * LZ];
-    __shared__ T Rf[FX * FY * FZ];
-    const int tid = threadIdx.x;
-    int bx, by, bz;
-    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
-    const int cx0 = bx * CX, cy0 = by * CY, cz0 = (DIM == 3) ? bz * CZ : 0;
-    // first fine point of the region: fine centre of coarse I is 2I + 1 behind
-    // a Dirichlet low wall, 2I behind a Neumann one (WALLS, 2D)
-    const int sx = (WALLS && (gf.wall & 1)) ? -1 : 0, sy = (WALLS && (gf.wall & 4)) ? -1 : 0;
-    const int sz = (WALLS && DIM == 3 && (gf.wall & 16)) ? -1 : 0;
-    const int fx0 = 2 * cx0 + sx, fy0 = 2 * cy0 + sy, fz0 = (DIM == 3) ? 2 * cz0 + sz : 0;
-    // the region and its stencil reach: fine points [f0 - R, f0 + F + R) per direction
-    const bool nw = WALLS && near_neumann(gf, fx0, fx0 + FX, fy0, fy0 + FY, fz0, fz0 + FZ, R);  // uniform per tile
+    const AxisCoefs<T> kc = axis_coefs<T, ORDER>(gf);
     // Staging as in the sweep: x (region + R) and b (region) go to registers
     // with every load issued before the first use.
     constexpr int NX = LX * LY * LZ, NF = FX * FY * FZ;
@@ -633,7 +663,8 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         if (q < NX) {
             const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
             const int gi = fx0 - R + lx, gj = fy0 - R + ly, gk = (DIM == 3) ? fz0 - R + lz : 0;
-            if (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz) v = x[lin(gf, gi, gj, gk)];
+            if (IN || (gi >= 0 && gi < gf.nx && gj >= 0 && gj < gf.ny && gk >= 0 && gk < gf.nz))
+                v = x[lin(gf, gi, gj, gk)];
         }
         xv[t] = v;
     }
@@ -645,7 +676,7 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
             const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
             const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
             // (a region starts below index 0 only when shifted)
-            if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz)
+            if (IN || ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz))
                 v = b[lin(gf, gi, gj, gk)];
         }
         bv[t] = v;
@@ -663,15 +694,16 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         const int fx = q % FX, fy = (q / FX) % FY, fz = q / (FX * FY);
         const int gi = fx0 + fx, gj = fy0 + fy, gk = fz0 + fz;
         T r = T(0);
-        if ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz) {
+        if (IN || ((!WALLS || (gi >= 0 && gj >= 0 && gk >= 0)) && gi < gf.nx && gj < gf.ny && gk < gf.nz)) {
             const int p = (fx + R) + LX * ((fy + R) + LY * ((DIM == 3) ? (fz + R) : 0));
             const T uc = X[p];
-            r = bscale * bv[t] - (uc - a * lap_lds<T, ORDER, DIM, WALLS>(X, p, LX, LX * LY, gi, gj, gk, gf, uc, nw));
+            r = bscale * bv[t] -
+                (uc - a * lap_lds<T, ORDER, DIM, WALLS, IN>(X, p, LX, LX * LY, gi, gj, gk, gf, uc, kc, nw));
         }
         Rf[q] = r;
     }
     __syncthreads();
-    if (nw) {
+    if (!IN && nw) {
         // region cells beyond a Neumann wall take the residual of their even
         // mirror inside the box (only in-range cells are read here)
         for (int q = tid; q < NF; q += kTileThreads) {
@@ -723,6 +755,37 @@ __global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restr
         }
         bc[lin(gc, ic, jc, kc)] = sum;
     }
+}
+
+template <typename T, int ORDER, int DIM, int CY, bool WALLS>
+__global__ __launch_bounds__(kTileThreads) void k_restrict_tile(const T* __restrict__ x, const T* __restrict__ b,
+                                                                T bscale, Geo gf, T a, T* __restrict__ bc, Geo gc) {
+    constexpr int CX = RestrictTile<DIM>::CX, CZ = RestrictTile<DIM>::CZ;
+    constexpr int R = ORDER / 2;
+    constexpr int FX = 2 * CX + 1, FY = 2 * CY + 1, FZ = (DIM == 3) ? 2 * CZ + 1 : 1;
+    constexpr int LX = FX + 2 * R, LY = FY + 2 * R, LZ = (DIM == 3) ? FZ + 2 * R : 1;
+    __shared__ T X[LX * LY * LZ];
+    __shared__ T Rf[FX * FY * FZ];
+    const int tid = threadIdx.x;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);  // XCD-contiguous bands of tiles
+    const int cx0 = bx * CX, cy0 = by * CY, cz0 = (DIM == 3) ? bz * CZ : 0;
+    // first fine point of the region: fine centre of coarse I is 2I + 1 behind
+    // a Dirichlet low wall, 2I behind a Neumann one (WALLS, 2D)
+    const int sx = (WALLS && (gf.wall & 1)) ? -1 : 0, sy = (WALLS && (gf.wall & 4)) ? -1 : 0;
+    const int sz = (WALLS && DIM == 3 && (gf.wall & 16)) ? -1 : 0;
+    const int fx0 = 2 * cx0 + sx, fy0 = 2 * cy0 + sy, fz0 = (DIM == 3) ? 2 * cz0 + sz : 0;
+    // the region and its stencil reach: fine points [f0 - R, f0 + F + R) per direction
+    const bool nw = WALLS && near_neumann(gf, fx0, fx0 + FX, fy0, fy0 + FY, fz0, fz0 + FZ, R);  // uniform per tile
+    if constexpr (DIM == 2) {
+        if (!nw && tile_inside2d(gf, fx0, fx0 + FX, fy0, fy0 + FY, R)) {
+            restrict_tile_body<T, ORDER, DIM, CY, WALLS, true>(x, b, bscale, gf, a, bc, gc, X, Rf, tid, cx0, cy0, cz0,
+                                                               fx0, fy0, fz0, nw);
+            return;
+        }
+    }
+    restrict_tile_body<T, ORDER, DIM, CY, WALLS, false>(x, b, bscale, gf, a, bc, gc, X, Rf, tid, cx0, cy0, cz0, fx0,
+                                                        fy0, fz0, nw);
 }
 
 // ---------------------------------------------------------------------------

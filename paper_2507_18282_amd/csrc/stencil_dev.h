@@ -134,6 +134,16 @@ __device__ __forceinline__ bool near_neumann(const Geo& g, int x0, int x1, int y
            ((g.wall & 16) && z0 - h <= 1) || ((g.wall & 32) && z1 + h >= g.nz - 2);
 }
 
+// True when the 2D box [x0 - h, x1 + h) x [y0 - h, y1 + h) lies inside the
+// grid.  A tile staged with that halo then loads no point beyond a wall, and
+// every point it relaxes (at most h - R layers beyond the tile) lies at least
+// R points inside: no wall, ghost or boundary diagonal enters, so its kernel
+// may drop those tests (a uniform branch per tile) and still compute every
+// value by the same expression.
+__device__ __forceinline__ bool tile_inside2d(const Geo& g, int x0, int x1, int y0, int y1, int h) {
+    return x0 - h >= 0 && x1 + h <= g.nx && y0 - h >= 0 && y1 + h <= g.ny;
+}
+
 // Diagonal of M = I - a L_h at (i, j, k) for the wall bits `wall` (Geo::wall
 // layout); kernels compiled for Dirichlet-only boxes pass a literal 0 so that
 // the Neumann cases fold away.

@@ -26,7 +26,7 @@ constexpr int kTileThreads = 256;
 // of H, b in B with a halo of 1): red on the tile plus one layer, then black
 // on the tile written out with the red points beside it.  NW selects the
 // Neumann-wall closures.
-template <typename T, int ORDER, int TY, bool NW>
+template <typename T, int ORDER, int TY, bool NW, bool IN>
 __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
                                                     T inv_diag, T w, T* __restrict__ xout) {
     constexpr int TX = 64;
@@ -47,17 +47,17 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
             dx = X[p - 1] + X[p + 1] - T(2) * uc;
             dy = X[p - LX] + X[p + LX] - T(2) * uc;
         } else {
-            const T l2 = (gi == 0) ? -uc : X[p - 2];
-            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
-            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
-            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            const T l2 = (!IN && gi == 0) ? -uc : X[p - 2];
+            const T r2 = (!IN && gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (!IN && gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (!IN && gj == g.ny - 1) ? -uc : X[p + 2 * LX];
             dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
             dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
         }
         const T r = bval - (uc - a * (dx * cxc + dy * cyc));
         // the diagonal differs from the interior one where a ghost refers back to
         // the point: at a Dirichlet wall point, one point inside a Neumann wall
-        const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
+        const bool edge = !IN && ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
                                             : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
         return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
     };
@@ -76,7 +76,7 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
         const int gj = y0 - 1 + by;
         const int c = 2 * m + (gj & 1);  // tile column of the red point (x0 is even)
         const int gi = x0 + c;
-        if (gj < 0 || gj >= g.ny || gi >= g.nx) continue;
+        if (!IN && (gj < 0 || gj >= g.ny || gi >= g.nx)) continue;
         rv[t] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
         rp[t] = (by + H - 1) * LX + c + H;
     }
@@ -86,7 +86,7 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
         const int by = tid, gj = y0 - 1 + by;
         const int c = (gj & 1) ? -1 : 64;
         const int gi = x0 + c;
-        if (gj >= 0 && gj < g.ny && gi >= 0 && gi < g.nx) {
+        if (IN || (gj >= 0 && gj < g.ny && gi >= 0 && gi < g.nx)) {
             rv[NRP] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
             rp[NRP] = (by + H - 1) * LX + c + H;
         }
@@ -105,33 +105,29 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
     for (int t = 0; t < TY / 8; ++t) {
         const int ty = rowsel + 8 * t;
         const int gj = y0 + ty;
-        if (gj >= g.ny) continue;
+        if (!IN && gj >= g.ny) continue;
         const int cb = 2 * m + 1 - (gj & 1), cr = 2 * m + (gj & 1);
         const int gib = x0 + cb, gir = x0 + cr;
         T* row = xout + (int64_t)gj * g.nx;
-        if (gib < g.nx) row[gib] = relax(cb + H, ty + H, gib, gj, B[(ty + 1) * BX + cb + 1]);
-        if (gir < g.nx) row[gir] = X[(ty + H) * LX + cr + H];
+        if (IN || gib < g.nx) row[gib] = relax(cb + H, ty + H, gib, gj, B[(ty + 1) * BX + cb + 1]);
+        if (IN || gir < g.nx) row[gir] = X[(ty + H) * LX + cr + H];
     }
 }
 
-template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS>
-__global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restrict__ xin, const T* __restrict__ xc,
-                                                               const T* __restrict__ b, T bscale, T* __restrict__ xout,
-                                                               Geo g, Geo gc, T a, T inv_diag, T w) {
+// Staging and phases of k_sweep_tile2d for one tile; IN: the tile lies
+// inside the grid with its halo (tile_inside2d), so no load or relaxed point
+// needs a bounds, ghost or wall test.
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS, bool IN>
+__device__ __forceinline__ void sweep_tile2d_body(const T* __restrict__ xin, const T* __restrict__ xc,
+                                                  const T* __restrict__ b, T bscale, T* __restrict__ xout,
+                                                  const Geo& g, const Geo& gc, T a, T inv_diag, T w, T* X, T* B,
+                                                  T* XC, int tid, int x0, int y0, bool nw) {
     constexpr int TX = 64;
     constexpr int R = ORDER / 2, H = R + 1;
     constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
     constexpr int BX = TX + 2, BY = TY + 2;
     constexpr int CXW = (LX + 5) / 2 + 1, CYW = (LY + 5) / 2 + 1;  // coarse cells under the x tile
-    __shared__ T X[LY * LX];
-    __shared__ T B[BY * BX];
-    __shared__ T XC[PROLONG ? CYW * CXW : 1];
-    const int tid = threadIdx.x;
-    int bx, by;
-    xcd_block(bx, by);  // XCD-contiguous bands of tiles
-    const int x0 = bx * TX, y0 = by * TY;
     const int cx0 = PROLONG ? (x0 - H - 1) >> 1 : 0, cy0 = PROLONG ? (y0 - H - 1) >> 1 : 0;
-    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, 0, 1, H);  // uniform per tile
 
     // Staging: every global load of a thread is issued (into registers) before
     // its first LDS store, so a block waits for memory once, not once per row.
@@ -158,7 +154,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
         if (!ZERO_IN && q < NX) {
             const int ly = q / LX, lx = q - ly * LX;
             const int gi = x0 - H + lx, gj = y0 - H + ly;
-            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = xin[(int64_t)gj * g.nx + gi];
+            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = xin[(int64_t)gj * g.nx + gi];
         }
         xv[t] = v;
     }
@@ -169,7 +165,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
         if (q < NB) {
             const int by = q / BX, bx = q - by * BX;
             const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
-            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = b[(int64_t)gj * g.nx + gi];
+            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = b[(int64_t)gj * g.nx + gi];
         }
         bv[t] = v;  // scaled at the LDS store: no arithmetic on a load in flight
     }
@@ -189,7 +185,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
             if (PROLONG) {
                 const int ly = q / LX, lx = q - ly * LX;
                 const int gi = x0 - H + lx, gj = y0 - H + ly;
-                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
+                if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) {
                     // q = f - off (off = 1 behind a Dirichlet low wall, 0 behind a
                     // Neumann one): q even -> coarse q/2; odd -> mean of (q-1)/2 and (q+1)/2
                     const int qi = WALLS ? gi - ((g.wall & 1) ? 0 : 1) : gi - 1;
@@ -215,12 +211,39 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
 
     // tiles near a Neumann wall run the wall closures; all others the
     // Dirichlet-only code (a uniform branch, taken once per tile)
-    if constexpr (WALLS) {
-        if (nw) sweep_tile2d_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-        else sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+    if constexpr (IN) {
+        sweep_tile2d_phases<T, ORDER, TY, false, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+    } else if constexpr (WALLS) {
+        if (nw) sweep_tile2d_phases<T, ORDER, TY, true, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        else sweep_tile2d_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     } else {
-        sweep_tile2d_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        sweep_tile2d_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     }
+}
+
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS>
+__global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restrict__ xin, const T* __restrict__ xc,
+                                                               const T* __restrict__ b, T bscale, T* __restrict__ xout,
+                                                               Geo g, Geo gc, T a, T inv_diag, T w) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 1;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BX = TX + 2, BY = TY + 2;
+    constexpr int CXW = (LX + 5) / 2 + 1, CYW = (LY + 5) / 2 + 1;
+    __shared__ T X[LY * LX];
+    __shared__ T B[BY * BX];
+    __shared__ T XC[PROLONG ? CYW * CXW : 1];
+    const int tid = threadIdx.x;
+    int bx, by;
+    xcd_block(bx, by);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY;
+    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, 0, 1, H);  // uniform per tile
+    if (!nw && tile_inside2d(g, x0, x0 + TX, y0, y0 + TY, H))
+        sweep_tile2d_body<T, ORDER, TY, ZERO_IN, PROLONG, WALLS, true>(xin, xc, b, bscale, xout, g, gc, a, inv_diag,
+                                                                       w, X, B, XC, tid, x0, y0, nw);
+    else
+        sweep_tile2d_body<T, ORDER, TY, ZERO_IN, PROLONG, WALLS, false>(xin, xc, b, bscale, xout, g, gc, a, inv_diag,
+                                                                        w, X, B, XC, tid, x0, y0, nw);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,7 +261,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restri
 // The relaxation phases of k_sweep2x_tile2d after staging (x in X with a
 // halo of R + 3, b in B with a halo of 3).  NW selects the Neumann-wall
 // closures.
-template <typename T, int ORDER, int TY, bool NW>
+template <typename T, int ORDER, int TY, bool NW, bool IN>
 __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
                                                T inv_diag, T w, T* __restrict__ xout) {
     constexpr int TX = 64;
@@ -259,15 +282,15 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
             dx = X[p - 1] + X[p + 1] - T(2) * uc;
             dy = X[p - LX] + X[p + LX] - T(2) * uc;
         } else {
-            const T l2 = (gi == 0) ? -uc : X[p - 2];
-            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
-            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
-            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            const T l2 = (!IN && gi == 0) ? -uc : X[p - 2];
+            const T r2 = (!IN && gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (!IN && gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (!IN && gj == g.ny - 1) ? -uc : X[p + 2 * LX];
             dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
             dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
         }
         const T r = bval - (uc - a * (dx * cxc + dy * cyc));
-        const bool edge = ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
+        const bool edge = !IN && ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
                                             : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
         return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
     };
@@ -287,7 +310,7 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
             const int r = idx / W2, k2 = idx - r * W2;
             const int gj = y0 - K + r;
             const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
-            if (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx) continue;
+            if (!IN && (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx)) continue;
             rv[t] = relax(gi, gj);
             rp[t] = (gj - y0 + H) * LX + (gi - x0 + H);
         }
@@ -310,10 +333,69 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
         const int r = idx / (TX / 2), k2 = idx - r * (TX / 2);
         const int gj = y0 + r;
         const int gib = x0 + ((1 + gj) & 1) + 2 * k2, gir = gib ^ 1;
-        if (gj >= g.ny) continue;
+        if (!IN && gj >= g.ny) continue;
         T* row = xout + (int64_t)gj * g.nx;
-        if (gib < g.nx) row[gib] = relax(gib, gj);
-        if (gir < g.nx) row[gir] = X[(gj - y0 + H) * LX + (gir - x0 + H)];
+        if (IN || gib < g.nx) row[gib] = relax(gib, gj);
+        if (IN || gir < g.nx) row[gir] = X[(gj - y0 + H) * LX + (gir - x0 + H)];
+    }
+}
+
+// Staging and phases of k_sweep2x_tile2d for one tile; IN as in
+// sweep_tile2d_body.
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool WALLS, bool IN>
+__device__ __forceinline__ void sweep2x_body(const T* __restrict__ xin, const T* __restrict__ b, T bscale,
+                                             T* __restrict__ xout, const Geo& g, T a, T inv_diag, T w, T* X, T* B,
+                                             int tid, int x0, int y0, bool nw) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 3;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BH = 3, BX = TX + 2 * BH, BY = TY + 2 * BH;
+
+    // staging, every global load issued before the first LDS store
+    constexpr int NX = LY * LX, NB = BY * BX;
+    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IB = (NB + kTileThreads - 1) / kTileThreads;
+    T xv[IX], bv[IB];
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (!ZERO_IN && q < NX) {
+            const int ly = q / LX, lx = q - ly * LX;
+            const int gi = x0 - H + lx, gj = y0 - H + ly;
+            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = xin[(int64_t)gj * g.nx + gi];
+        }
+        xv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
+        T v = T(0);
+        if (q < NB) {
+            const int by = q / BX, bx = q - by * BX;
+            const int gi = x0 - BH + bx, gj = y0 - BH + by;
+            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = b[(int64_t)gj * g.nx + gi];
+        }
+        bv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NX) X[q] = xv[t];
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * kTileThreads;
+        if (q < NB) B[q] = bscale * bv[t];
+    }
+    __syncthreads();
+
+    if constexpr (IN) {
+        sweep2x_phases<T, ORDER, TY, false, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+    } else if constexpr (WALLS) {
+        if (nw) sweep2x_phases<T, ORDER, TY, true, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        else sweep2x_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+    } else {
+        sweep2x_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     }
 }
 
@@ -332,51 +414,12 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_tile2d(const T* __rest
     xcd_block(bx, by);  // XCD-contiguous bands of tiles
     const int x0 = bx * TX, y0 = by * TY;
     const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, 0, 1, H);  // uniform per tile
-
-    // staging, every global load issued before the first LDS store
-    constexpr int NX = LY * LX, NB = BY * BX;
-    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IB = (NB + kTileThreads - 1) / kTileThreads;
-    T xv[IX], bv[IB];
-#pragma unroll
-    for (int t = 0; t < IX; ++t) {
-        const int q = tid + t * kTileThreads;
-        T v = T(0);
-        if (!ZERO_IN && q < NX) {
-            const int ly = q / LX, lx = q - ly * LX;
-            const int gi = x0 - H + lx, gj = y0 - H + ly;
-            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = xin[(int64_t)gj * g.nx + gi];
-        }
-        xv[t] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < IB; ++t) {
-        const int q = tid + t * kTileThreads;
-        T v = T(0);
-        if (q < NB) {
-            const int by = q / BX, bx = q - by * BX;
-            const int gi = x0 - BH + bx, gj = y0 - BH + by;
-            if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = b[(int64_t)gj * g.nx + gi];
-        }
-        bv[t] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < IX; ++t) {
-        const int q = tid + t * kTileThreads;
-        if (q < NX) X[q] = xv[t];
-    }
-#pragma unroll
-    for (int t = 0; t < IB; ++t) {
-        const int q = tid + t * kTileThreads;
-        if (q < NB) B[q] = bscale * bv[t];
-    }
-    __syncthreads();
-
-    if constexpr (WALLS) {
-        if (nw) sweep2x_phases<T, ORDER, TY, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-        else sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-    } else {
-        sweep2x_phases<T, ORDER, TY, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-    }
+    if (!nw && tile_inside2d(g, x0, x0 + TX, y0, y0 + TY, H))
+        sweep2x_body<T, ORDER, TY, ZERO_IN, WALLS, true>(xin, b, bscale, xout, g, a, inv_diag, w, X, B, tid, x0, y0,
+                                                         nw);
+    else
+        sweep2x_body<T, ORDER, TY, ZERO_IN, WALLS, false>(xin, b, bscale, xout, g, a, inv_diag, w, X, B, tid, x0, y0,
+                                                          nw);
 }
 
 // hipExtLaunchKernelGGL records ev0/ev1 (when given) at the dispatch's own
@@ -478,12 +521,14 @@ template hipError_t launch_sweep2x2d<float>(const float*, const float*, double, 
 // the (64 + 1) x (TY + 1) fine points from the tile's corner, into the LDS of
 // b (no longer needed), and restricted from there.
 // ---------------------------------------------------------------------------
-template <typename T, int ORDER, int TY, bool ZERO_IN>
-__global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const T* __restrict__ xin,
-                                                                          const T* __restrict__ b, T bscale,
-                                                                          T* __restrict__ xout, Geo g, T a,
-                                                                          T inv_diag, T w, T* __restrict__ bc,
-                                                                          Geo gc) {
+// One tile of k_sweep2x_restrict_tile2d; IN: the tile lies inside the grid
+// with its staged halo (tile_inside2d), so no load, relaxed point or residual
+// point needs a bounds, ghost or wall-diagonal test.
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool IN>
+__device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin, const T* __restrict__ b, T bscale,
+                                                      T* __restrict__ xout, const Geo& g, T a, T inv_diag, T w,
+                                                      T* __restrict__ bc, const Geo& gc, T* X, T* B, int tid, int x0,
+                                                      int y0) {
     constexpr int TX = 64;
     constexpr int R = ORDER / 2, M = R + 1, H = R + M + 3;
     constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
@@ -491,12 +536,6 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
     constexpr int RX = TX + 1, RY = TY + 1, NR = RX * RY;
     static_assert(NR <= BX * BY, "the residual reuses the LDS of b");
     static_assert(TY % 2 == 0, "coarse rows pair fine rows");
-    __shared__ T X[LY * LX];
-    __shared__ T B[BY * BX];
-    const int tid = threadIdx.x;
-    int bx, by;
-    xcd_block(bx, by);  // XCD-contiguous bands of tiles
-    const int x0 = bx * TX, y0 = by * TY;
 
     // staging, every global load issued before the first LDS store
     constexpr int NX = LY * LX, NB = BY * BX;
@@ -510,7 +549,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
             if (!ZERO_IN && q < NX) {
                 const int ly = q / LX, lx = q - ly * LX;
                 const int gi = x0 - H + lx, gj = y0 - H + ly;
-                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = xin[(int64_t)gj * g.nx + gi];
+                if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = xin[(int64_t)gj * g.nx + gi];
             }
             xv[t] = v;
         }
@@ -521,7 +560,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
             if (q < NB) {
                 const int ly = q / BX, lx = q - ly * BX;
                 const int gi = x0 - BH + lx, gj = y0 - BH + ly;
-                if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) v = b[(int64_t)gj * g.nx + gi];
+                if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = b[(int64_t)gj * g.nx + gi];
             }
             bv[t] = v;
         }
@@ -546,10 +585,10 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
             dx = X[p - 1] + X[p + 1] - T(2) * uc;
             dy = X[p - LX] + X[p + LX] - T(2) * uc;
         } else {
-            const T l2 = (gi == 0) ? -uc : X[p - 2];
-            const T r2 = (gi == g.nx - 1) ? -uc : X[p + 2];
-            const T d2 = (gj == 0) ? -uc : X[p - 2 * LX];
-            const T u2 = (gj == g.ny - 1) ? -uc : X[p + 2 * LX];
+            const T l2 = (!IN && gi == 0) ? -uc : X[p - 2];
+            const T r2 = (!IN && gi == g.nx - 1) ? -uc : X[p + 2];
+            const T d2 = (!IN && gj == 0) ? -uc : X[p - 2 * LX];
+            const T u2 = (!IN && gj == g.ny - 1) ? -uc : X[p + 2 * LX];
             dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
             dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
         }
@@ -560,7 +599,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
         const T bval = B[(gj - y0 + BH) * BX + (gi - x0 + BH)];
         const T uc = X[p];
         const T r = bval - (uc - a * lap(p, gi, gj, uc));
-        const bool edge = ORDER == 4 && (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1);
+        const bool edge = !IN && ORDER == 4 && (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1);
         return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, 0) : uc + r * inv_diag;
     };
     // one half-sweep of colour `colour` on the tile plus K layers, into LDS
@@ -578,7 +617,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
             const int r = idx / W2, k2 = idx - r * W2;
             const int gj = y0 - K + r;
             const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
-            if (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx) continue;
+            if (!IN && (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx)) continue;
             rv[t] = relax(gi, gj);
             rp[t] = (gj - y0 + H) * LX + (gi - x0 + H);
         }
@@ -597,7 +636,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
     for (int q = tid; q < TX * TY; q += kTileThreads) {
         const int r = q / TX, c = q - r * TX;
         const int gi = x0 + c, gj = y0 + r;
-        if (gi < g.nx && gj < g.ny) xout[(int64_t)gj * g.nx + gi] = X[(r + H) * LX + c + H];
+        if (IN || (gi < g.nx && gj < g.ny)) xout[(int64_t)gj * g.nx + gi] = X[(r + H) * LX + c + H];
     }
     // residual over fine points [x0, x0 + 64] x [y0, y0 + TY] (0 outside the grid)
     constexpr int IR = (NR + kTileThreads - 1) / kTileThreads;
@@ -609,7 +648,7 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
         if (q < NR) {
             const int ry = q / RX, rx = q - ry * RX;
             const int gi = x0 + rx, gj = y0 + ry;
-            if (gi < g.nx && gj < g.ny) {
+            if (IN || (gi < g.nx && gj < g.ny)) {
                 const int p = (ry + H) * LX + rx + H;
                 const T uc = X[p];
                 r = B[(ry + BH) * BX + rx + BH] - (uc - a * lap(p, gi, gj, uc));
@@ -640,6 +679,30 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const 
         }
         bc[(int64_t)jc * gc.nx + ic] = sum;
     }
+}
+
+template <typename T, int ORDER, int TY, bool ZERO_IN>
+__global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const T* __restrict__ xin,
+                                                                          const T* __restrict__ b, T bscale,
+                                                                          T* __restrict__ xout, Geo g, T a,
+                                                                          T inv_diag, T w, T* __restrict__ bc,
+                                                                          Geo gc) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, M = R + 1, H = R + M + 3;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BH = M + 3, BX = TX + 2 * BH, BY = TY + 2 * BH;
+    __shared__ T X[LY * LX];
+    __shared__ T B[BY * BX];
+    const int tid = threadIdx.x;
+    int bx, by;
+    xcd_block(bx, by);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY;
+    if (tile_inside2d(g, x0, x0 + TX, y0, y0 + TY, H))
+        sweep2x_restrict_body<T, ORDER, TY, ZERO_IN, true>(xin, b, bscale, xout, g, a, inv_diag, w, bc, gc, X, B, tid,
+                                                           x0, y0);
+    else
+        sweep2x_restrict_body<T, ORDER, TY, ZERO_IN, false>(xin, b, bscale, xout, g, a, inv_diag, w, bc, gc, X, B,
+                                                            tid, x0, y0);
 }
 
 template <typename T, int ORDER, int TY>

@@ -328,3 +328,63 @@ def test_zmarch_sweep_mixed_filter_matches_oracle():
     say("z-march mixed S v", P.n)
     got = to_host(op.apply_filter(to_dev(v)))
     assert rel_err(got, oracle_S(P, v)) < 4 * n_t * 2.0 ** -24
+
+
+# 2D levels of at least 1024 tiles of 64 x 16 run the two pre-smoothing sweeps
+# as one fused pass, the restriction on its own tiles and the prolongation
+# sweep on 64 x 16 tiles; smaller levels run the pre-smoothing fused with the
+# restriction.  Tiles whose staged halo lies inside the grid take the code
+# path without bounds, ghost or wall-diagonal tests.  2047 x 513 has 32 x 33
+# such tiles (ragged: 513 = 32 x 16 + 1), most of them inside; its second and
+# last level, 1023 x 256, takes eight sweeps as four fused passes on 64 x 8
+# tiles.  2047 x 511 (32 x 32 tiles, ragged in y) coarsens to nine levels, the
+# second of which (1023 x 255) takes the fused pre-smoothing and restriction.
+WIDE_CASES = [
+    synthetic.Problem(n=(2047, 513), length=(1.0, 0.25), order=4, omega=60.0, ts="implicit", adjust_omega=True),
+    synthetic.Problem(n=(2047, 513), length=(1.0, 0.25), order=2, omega=60.0, ts="implicit", adjust_omega=True),
+    synthetic.Problem(n=(2047, 511), length=(1.0, 0.25), order=4, omega=60.0, ts="implicit", adjust_omega=True),
+]
+
+
+@pytest.mark.parametrize("P", WIDE_CASES, ids=lambda P: f"{P.n}-o{P.order}")
+def test_wide_tiles_vcycle_matches_oracle(P):
+    op = make_op(P)
+    h, plan = oracle_plan(P)
+    hier = _mg_hierarchy(P, 0.5 * plan.dt ** 2, op)
+    assert op.mg_levels == len(hier.sizes) == (2 if P.n[1] == 513 else 9)
+    shape = P.n[::-1]
+    b = synthetic.uniform_pm1(51, P.n_active)
+    x = synthetic.uniform_pm1(52, P.n_active)
+    say("wide vcycle", P.n, P.order)
+    got = to_host(op.mg_vcycle(to_dev(b), to_dev(x)))
+    want = OMG.vcycle(x.reshape(shape), b.reshape(shape), hier).ravel()
+    assert rel_err(got, want) < 1e-12
+
+
+def test_wide_tiles_solve_reaches_exact_solution():
+    """The residual-norm pass of the convergence tests on wide tiles: the solve
+    stops at ||r|| <= tau ||b|| and reaches the exact solve within that bound."""
+    P = WIDE_CASES[2]
+    op = make_op(P)
+    h, plan = oracle_plan(P)
+    b = synthetic.uniform_pm1(54, P.n_active)
+    say("wide solve", P.n, P.order)
+    xd, cycles, rel = op.mg_solve(to_dev(b), to_dev(np.zeros(P.n_active)))
+    xe = W.solve_implicit_exact(b.reshape(P.n[::-1]), h, P.order, plan.dt).ravel()
+    assert rel <= P.mg_tol
+    assert np.linalg.norm(to_host(xd) - xe) <= P.mg_tol * np.linalg.norm(b) * 1.0001
+
+
+def test_wide_tiles_mixed_filter_matches_oracle():
+    """The FP32 instances of the same kernels inside mixed-precision implicit
+    S v, within the FP32 bound 4 N_t 2^-24 plus the multigrid tolerance, on
+    2047 x 511 (the two-level hierarchy of 2047 x 513 would not converge: its
+    1023 x 256 coarsest level gets only eight sweeps)."""
+    import dataclasses
+    P = dataclasses.replace(WIDE_CASES[2], precision="mixed")
+    op = make_op(P)
+    v = synthetic.uniform_pm1(53, P.n_active)
+    n_t = oracle_plan(P)[1].n_t
+    say("wide mixed S v", P.n)
+    got = to_host(op.apply_filter(to_dev(v)))
+    assert rel_err(got, oracle_S(P, v)) < 4 * n_t * 2.0 ** -24 + 100 * P.mg_tol

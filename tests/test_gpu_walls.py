@@ -137,6 +137,9 @@ IMPLICIT_CASES = [
     ((64, 64), (1.0, 1.0), (("D", "N"), ("N", "D")), 4, 30.0),
     ((17, 16, 15), (1.0, 0.9, 1.0), (("N", "N"), ("N", "D"), ("D", "D")), 2, 10.0),
     ((16, 17, 16), (1.0, 1.0, 1.0), (("D", "N"), ("N", "N"), ("N", "D")), 4, 12.0),
+    # wide enough for the 64 x 16 tiles of the finest level: tiles near the
+    # Neumann wall run its closures, tiles inside the grid the test-free path
+    ((2047, 512), (1.0, 0.25), (("D", "D"), ("N", "D")), 4, 60.0),
 ]
 
 
