@@ -33,6 +33,7 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
     constexpr int R = ORDER / 2, H = R + 1;
     constexpr int LX = TX + 2 * H;
     constexpr int BX = TX + 2, BY = TY + 2;
+    static_assert(LX % 2 == 0 && BX % 2 == 0, "paired rows must start on opposite column parities");
     const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
     // relaxed value at LDS cell (lx, ly) = global (gi, gj)
     auto relax = [&](int lx, int ly, int gi, int gj, T bval) -> T {
@@ -62,8 +63,12 @@ __device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, i
         return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
     };
 
-    const int rowsel = tid >> 5;  // 8 rows per pass, 32 lanes per row
-    const int m = tid & 31;
+    // 8 rows per pass, 32 lanes per row; the lanes of a wavefront alternate
+    // between its two rows, whose points of one colour sit in columns of
+    // opposite parity (LX and BX are even), so every 16 consecutive lanes
+    // read 16 distinct LDS bank pairs instead of 8 pairs twice
+    const int rowsel = ((tid >> 6) << 1) | (tid & 1);
+    const int m = (tid >> 1) & 31;
     // red half-sweep on tile rows -1..TY, tile columns 0..63 (one red point per lane) ...
     constexpr int NRP = (BY + 7) / 8;
     T rv[NRP + 1];
@@ -268,6 +273,7 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
     constexpr int R = ORDER / 2, H = R + 3;
     constexpr int LX = TX + 2 * H;
     constexpr int BH = 3, BX = TX + 2 * BH;
+    static_assert(LX % 2 == 0 && BX % 2 == 0 && TY % 2 == 0, "row pairs of opposite column parities");
     const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
     // relaxed value of global point (gi, gj) from the values now in LDS
     auto relax = [&](int gi, int gj) -> T {
@@ -307,7 +313,10 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
             rp[t] = -1;
             const int idx = tid + t * kTileThreads;
             if (idx >= NP) continue;
-            const int r = idx / W2, k2 = idx - r * W2;
+            // lanes alternate between the two rows of a pair (bank-conflict
+            // free reads, as in sweep_tile2d_phases; the row count is even)
+            const int pr = idx / (2 * W2), q2 = idx - pr * (2 * W2);
+            const int r = 2 * pr + (q2 & 1), k2 = q2 >> 1;
             const int gj = y0 - K + r;
             const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
             if (!IN && (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx)) continue;
@@ -330,7 +339,8 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
     for (int t = 0; t < IT; ++t) {
         const int idx = tid + t * kTileThreads;
         if (idx >= NP) continue;
-        const int r = idx / (TX / 2), k2 = idx - r * (TX / 2);
+        const int pr = idx / TX, q2 = idx - pr * TX;  // row pairs, as in `half`
+        const int r = 2 * pr + (q2 & 1), k2 = q2 >> 1;
         const int gj = y0 + r;
         const int gib = x0 + ((1 + gj) & 1) + 2 * k2, gir = gib ^ 1;
         if (!IN && gj >= g.ny) continue;
@@ -536,6 +546,7 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
     constexpr int RX = TX + 1, RY = TY + 1, NR = RX * RY;
     static_assert(NR <= BX * BY, "the residual reuses the LDS of b");
     static_assert(TY % 2 == 0, "coarse rows pair fine rows");
+    static_assert(LX % 2 == 0 && BX % 2 == 0, "row pairs of opposite column parities");
 
     // staging, every global load issued before the first LDS store
     constexpr int NX = LY * LX, NB = BY * BX;
@@ -614,7 +625,10 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
             rp[t] = -1;
             const int idx = tid + t * kTileThreads;
             if (idx >= NP) continue;
-            const int r = idx / W2, k2 = idx - r * W2;
+            // lanes alternate between the two rows of a pair (bank-conflict
+            // free reads, as in sweep_tile2d_phases; the row count is even)
+            const int pr = idx / (2 * W2), q2 = idx - pr * (2 * W2);
+            const int r = 2 * pr + (q2 & 1), k2 = q2 >> 1;
             const int gj = y0 - K + r;
             const int gi = x0 - K + ((colour + gj + x0 - K) & 1) + 2 * k2;
             if (!IN && (gj < 0 || gj >= g.ny || gi < 0 || gi >= g.nx)) continue;
