@@ -432,7 +432,12 @@ __global__ __launch_bounds__(kTileThreads) void k_sweep_z3d(const T* __restrict_
     load_x(RA.x, z0);
     load_b(RA.b, z0 - 1);
 
-    const int rowsel = tid >> 5, m = tid & 31;
+    // 8 rows per pass, 32 lanes per row; the lanes of a wavefront alternate
+    // between its two rows, whose points of one colour sit in columns of
+    // opposite parity (LX and BX are even), so consecutive lanes read
+    // distinct LDS banks
+    static_assert(LX % 2 == 0 && BX % 2 == 0, "paired rows must start on opposite column parities");
+    const int rowsel = ((tid >> 6) << 1) | (tid & 1), m = (tid >> 1) & 31;
     auto step = [&](int k, Regs& R) {
         // planes k+1 (x) and k (b) arrive; issue the loads of the next step
         store_x(R.x, k + 1);
