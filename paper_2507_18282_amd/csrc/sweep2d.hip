@@ -10,274 +10,45 @@
 
 namespace ew {
 
-constexpr int kTileThreads = 256;
-// Threads per workgroup of the fused two-sweep pass: 512 give 32 wavefronts
-// per CU instead of 20 (four workgroups fit the LDS either way); measured 1 %
-// faster on 2047^2 and 4 % on 1023^2.  (The single sweep measured 2 % slower
-// with 512 on 2047^2 and keeps 256.)
+// Threads per workgroup (same-box A/B measurements, rocprofv3 averages):
+//  * the fused two-sweep pass: 512, i.e. 32 wavefronts per CU instead of 20
+//    (four workgroups fit the LDS either way): 1 % faster on 2047^2, 4 % on
+//    1023^2 than 256;
+//  * the single sweep: 256 on 64 x 16 tiles (512 measured 2 % slower on
+//    2047^2), 512 on the 64 x 8 tiles of small levels (255^2: 5.6 -> 4.4 us);
+//  * the fused two-sweep + restriction pass of small levels, where the time
+//    per tile, not the bytes, sets the pace: 1024 (255^2: 8.3 us with 256,
+//    6.2 with 512, 5.6 with 1024).
 constexpr int kSweep2xThreads = 512;
+template <int TY>
+constexpr int single_sweep_threads() {
+    return TY >= 16 ? 256 : 512;
+}
+constexpr int kSweep2xRestrictThreads = 1024;
 
 // ---------------------------------------------------------------------------
-// 2D sweep, one tile of 64 x TY outputs per block of 256 threads.  x is staged
-// in LDS with a halo of H = R + 1, b with a halo of 1; with PROLONG the coarse
+// 2D sweep, one tile of 64 x TY outputs per workgroup.  x is staged in LDS
+// with a halo of H = R + 1, b with a halo of 1; with PROLONG the coarse
 // values under the tile are staged as well and interpolated from LDS.  During
-// each half-sweep every lane owns one point of the colour being relaxed
-// (a wavefront covers two rows of 32 same-colour points), so no lane idles on a
-// point of the other colour.  Interior points multiply by the reciprocal of
-// the constant interior diagonal; points whose diagonal carries an order-4
-// ghost divide.
+// each half-sweep every lane owns one point of the colour being relaxed, so
+// no lane idles on a point of the other colour.  Interior points multiply by
+// the reciprocal of the constant interior diagonal; points whose diagonal
+// carries an order-4 ghost divide.
 // ---------------------------------------------------------------------------
-// The relaxation phases of k_sweep_tile2d after staging (x in X with a halo
-// of H, b in B with a halo of 1): red on the tile plus one layer, then black
-// on the tile written out with the red points beside it.  NW selects the
-// Neumann-wall closures.
-template <typename T, int ORDER, int TY, bool NW, bool IN>
-__device__ __forceinline__ void sweep_tile2d_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
-                                                    T inv_diag, T w, T* __restrict__ xout) {
+// The relaxation phases of NS = 1 or 2 red-black sweeps of one 64 x TY tile
+// by NT threads, after staging: x in X with a halo of R + 2 NS - 1, b in B
+// with a halo of 2 NS - 1.  Each half-sweep but the last relaxes the tile
+// plus one layer more than the next one needs; the last (black) half-sweep
+// is written out with the red points beside it.  NW selects the Neumann-wall
+// closures; IN drops the tests a tile inside the grid does not need.
+template <typename T, int ORDER, int TY, bool NW, bool IN, int NS, int NT>
+__device__ __forceinline__ void sweep_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
+                                             T inv_diag, T w, T* __restrict__ xout) {
+    static_assert(NS == 1 || NS == 2, "one or two sweeps per pass");
     constexpr int TX = 64;
-    constexpr int R = ORDER / 2, H = R + 1;
+    constexpr int R = ORDER / 2, H = R + 2 * NS - 1;
     constexpr int LX = TX + 2 * H;
-    constexpr int BX = TX + 2, BY = TY + 2;
-    static_assert(LX % 2 == 0 && BX % 2 == 0, "paired rows must start on opposite column parities");
-    const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
-    // relaxed value at LDS cell (lx, ly) = global (gi, gj)
-    auto relax = [&](int lx, int ly, int gi, int gj, T bval) -> T {
-        const int p = ly * LX + lx;
-        const T uc = X[p];
-        T dx, dy;
-        if (NW) {
-            // Neumann walls: the even-reflection closure replaces the zero halo
-            dx = d2_framed<T, ORDER>(X, p, 1, gi, g.nx, uc, g.wall & 3);
-            dy = d2_framed<T, ORDER>(X, p, LX, gj, g.ny, uc, (g.wall >> 2) & 3);
-        } else if (ORDER == 2) {
-            dx = X[p - 1] + X[p + 1] - T(2) * uc;
-            dy = X[p - LX] + X[p + LX] - T(2) * uc;
-        } else {
-            const T l2 = (!IN && gi == 0) ? -uc : X[p - 2];
-            const T r2 = (!IN && gi == g.nx - 1) ? -uc : X[p + 2];
-            const T d2 = (!IN && gj == 0) ? -uc : X[p - 2 * LX];
-            const T u2 = (!IN && gj == g.ny - 1) ? -uc : X[p + 2 * LX];
-            dx = T(16) * (X[p - 1] + X[p + 1]) - (l2 + r2) - T(30) * uc;
-            dy = T(16) * (X[p - LX] + X[p + LX]) - (d2 + u2) - T(30) * uc;
-        }
-        const T r = bval - (uc - a * (dx * cxc + dy * cyc));
-        // the diagonal differs from the interior one where a ghost refers back to
-        // the point: at a Dirichlet wall point, one point inside a Neumann wall
-        const bool edge = !IN && ORDER == 4 && (NW ? (gi <= 1 || gi >= g.nx - 2 || gj <= 1 || gj >= g.ny - 2)
-                                            : (gi == 0 || gi == g.nx - 1 || gj == 0 || gj == g.ny - 1));
-        return edge ? uc + (w * r) / mdiag_w<T, ORDER, 2>(gi, gj, 0, g, a, NW ? g.wall : 0) : uc + r * inv_diag;
-    };
-
-    // 8 rows per pass, 32 lanes per row; the lanes of a wavefront alternate
-    // between its two rows, whose points of one colour sit in columns of
-    // opposite parity (LX and BX are even), so every 16 consecutive lanes
-    // read 16 distinct LDS bank pairs instead of 8 pairs twice
-    const int rowsel = ((tid >> 6) << 1) | (tid & 1);
-    const int m = (tid >> 1) & 31;
-    // red half-sweep on tile rows -1..TY, tile columns 0..63 (one red point per lane) ...
-    constexpr int NRP = (BY + 7) / 8;
-    T rv[NRP + 1];
-    int rp[NRP + 1];
-#pragma unroll
-    for (int t = 0; t < NRP; ++t) {
-        rp[t] = -1;
-        const int by = rowsel + 8 * t;
-        if (by >= BY) continue;
-        const int gj = y0 - 1 + by;
-        const int c = 2 * m + (gj & 1);  // tile column of the red point (x0 is even)
-        const int gi = x0 + c;
-        if (!IN && (gj < 0 || gj >= g.ny || gi >= g.nx)) continue;
-        rv[t] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
-        rp[t] = (by + H - 1) * LX + c + H;
-    }
-    // ... plus the red point of each row in tile column -1 or 64
-    rp[NRP] = -1;
-    if (tid < BY) {
-        const int by = tid, gj = y0 - 1 + by;
-        const int c = (gj & 1) ? -1 : 64;
-        const int gi = x0 + c;
-        if (IN || (gj >= 0 && gj < g.ny && gi >= 0 && gi < g.nx)) {
-            rv[NRP] = relax(c + H, by + H - 1, gi, gj, B[by * BX + c + 1]);
-            rp[NRP] = (by + H - 1) * LX + c + H;
-        }
-    }
-    // order 4 reads red neighbours (old values) that other lanes overwrite;
-    // order 2 reads each red point only in the lane that updates it
-    if (ORDER == 4) __syncthreads();
-#pragma unroll
-    for (int t = 0; t <= NRP; ++t)
-        if (rp[t] >= 0) X[rp[t]] = rv[t];
-    __syncthreads();
-
-    // black half-sweep on the tile; each lane writes its black point and the
-    // red point beside it
-#pragma unroll
-    for (int t = 0; t < TY / 8; ++t) {
-        const int ty = rowsel + 8 * t;
-        const int gj = y0 + ty;
-        if (!IN && gj >= g.ny) continue;
-        const int cb = 2 * m + 1 - (gj & 1), cr = 2 * m + (gj & 1);
-        const int gib = x0 + cb, gir = x0 + cr;
-        T* row = xout + (int64_t)gj * g.nx;
-        if (IN || gib < g.nx) row[gib] = relax(cb + H, ty + H, gib, gj, B[(ty + 1) * BX + cb + 1]);
-        if (IN || gir < g.nx) row[gir] = X[(ty + H) * LX + cr + H];
-    }
-}
-
-// Staging and phases of k_sweep_tile2d for one tile; IN: the tile lies
-// inside the grid with its halo (tile_inside2d), so no load or relaxed point
-// needs a bounds, ghost or wall test.
-template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS, bool IN>
-__device__ __forceinline__ void sweep_tile2d_body(const T* __restrict__ xin, const T* __restrict__ xc,
-                                                  const T* __restrict__ b, T bscale, T* __restrict__ xout,
-                                                  const Geo& g, const Geo& gc, T a, T inv_diag, T w, T* X, T* B,
-                                                  T* XC, int tid, int x0, int y0, bool nw) {
-    constexpr int TX = 64;
-    constexpr int R = ORDER / 2, H = R + 1;
-    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
-    constexpr int BX = TX + 2, BY = TY + 2;
-    constexpr int CXW = (LX + 5) / 2 + 1, CYW = (LY + 5) / 2 + 1;  // coarse cells under the x tile
-    const int cx0 = PROLONG ? (x0 - H - 1) >> 1 : 0, cy0 = PROLONG ? (y0 - H - 1) >> 1 : 0;
-
-    // Staging: every global load of a thread is issued (into registers) before
-    // its first LDS store, so a block waits for memory once, not once per row.
-    constexpr int NX = LY * LX, NB = BY * BX, NC = PROLONG ? CYW * CXW : 0;
-    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads;
-    constexpr int IB = (NB + kTileThreads - 1) / kTileThreads;
-    constexpr int IC = PROLONG ? (NC + kTileThreads - 1) / kTileThreads : 1;
-    T cv[IC], xv[IX], bv[IB];
-#pragma unroll
-    for (int t = 0; t < IC; ++t) {
-        const int q = tid + t * kTileThreads;
-        T v = T(0);
-        if (PROLONG && q < NC) {
-            const int cy = q / CXW, cxx = q - cy * CXW;
-            const int ic = cx0 + cxx, jc = cy0 + cy;
-            if (ic >= 0 && ic < gc.nx && jc >= 0 && jc < gc.ny) v = xc[(int64_t)jc * gc.nx + ic];
-        }
-        cv[t] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < IX; ++t) {
-        const int q = tid + t * kTileThreads;
-        T v = T(0);
-        if (!ZERO_IN && q < NX) {
-            const int ly = q / LX, lx = q - ly * LX;
-            const int gi = x0 - H + lx, gj = y0 - H + ly;
-            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = xin[(int64_t)gj * g.nx + gi];
-        }
-        xv[t] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < IB; ++t) {
-        const int q = tid + t * kTileThreads;
-        T v = T(0);
-        if (q < NB) {
-            const int by = q / BX, bx = q - by * BX;
-            const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
-            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = b[(int64_t)gj * g.nx + gi];
-        }
-        bv[t] = v;  // scaled at the LDS store: no arithmetic on a load in flight
-    }
-    if (PROLONG) {
-#pragma unroll
-        for (int t = 0; t < IC; ++t) {
-            const int q = tid + t * kTileThreads;
-            if (q < NC) XC[q] = cv[t];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < IX; ++t) {
-        const int q = tid + t * kTileThreads;
-        if (q < NX) {
-            T v = xv[t];
-            if (PROLONG) {
-                const int ly = q / LX, lx = q - ly * LX;
-                const int gi = x0 - H + lx, gj = y0 - H + ly;
-                if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) {
-                    // q = f - off (off = 1 behind a Dirichlet low wall, 0 behind a
-                    // Neumann one): q even -> coarse q/2; odd -> mean of (q-1)/2 and (q+1)/2
-                    const int qi = WALLS ? gi - ((g.wall & 1) ? 0 : 1) : gi - 1;
-                    const int qj = WALLS ? gj - ((g.wall & 4) ? 0 : 1) : gj - 1;
-                    const int ia = (qi >> 1) - cx0, ib = ((qi + 1) >> 1) - cx0;
-                    const int ja = (qj >> 1) - cy0, jb = ((qj + 1) >> 1) - cy0;
-                    const T wia = (qi & 1) ? T(0.5) : T(1), wib = (qi & 1) ? T(0.5) : T(0);
-                    const T wja = (qj & 1) ? T(0.5) : T(1), wjb = (qj & 1) ? T(0.5) : T(0);
-                    const T rowa = wia * XC[ja * CXW + ia] + wib * XC[ja * CXW + ib];
-                    const T rowb = wia * XC[jb * CXW + ia] + wib * XC[jb * CXW + ib];
-                    v += wja * rowa + wjb * rowb;
-                }
-            }
-            X[q] = v;
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < IB; ++t) {
-        const int q = tid + t * kTileThreads;
-        if (q < NB) B[q] = bscale * bv[t];
-    }
-    __syncthreads();
-
-    // tiles near a Neumann wall run the wall closures; all others the
-    // Dirichlet-only code (a uniform branch, taken once per tile)
-    if constexpr (IN) {
-        sweep_tile2d_phases<T, ORDER, TY, false, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-    } else if constexpr (WALLS) {
-        if (nw) sweep_tile2d_phases<T, ORDER, TY, true, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-        else sweep_tile2d_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-    } else {
-        sweep_tile2d_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-    }
-}
-
-template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS>
-__global__ __launch_bounds__(kTileThreads) void k_sweep_tile2d(const T* __restrict__ xin, const T* __restrict__ xc,
-                                                               const T* __restrict__ b, T bscale, T* __restrict__ xout,
-                                                               Geo g, Geo gc, T a, T inv_diag, T w) {
-    constexpr int TX = 64;
-    constexpr int R = ORDER / 2, H = R + 1;
-    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
-    constexpr int BX = TX + 2, BY = TY + 2;
-    constexpr int CXW = (LX + 5) / 2 + 1, CYW = (LY + 5) / 2 + 1;
-    __shared__ T X[LY * LX];
-    __shared__ T B[BY * BX];
-    __shared__ T XC[PROLONG ? CYW * CXW : 1];
-    const int tid = threadIdx.x;
-    int bx, by;
-    xcd_block(bx, by);  // XCD-contiguous bands of tiles
-    const int x0 = bx * TX, y0 = by * TY;
-    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, 0, 1, H);  // uniform per tile
-    if (!nw && tile_inside2d(g, x0, x0 + TX, y0, y0 + TY, H))
-        sweep_tile2d_body<T, ORDER, TY, ZERO_IN, PROLONG, WALLS, true>(xin, xc, b, bscale, xout, g, gc, a, inv_diag,
-                                                                       w, X, B, XC, tid, x0, y0, nw);
-    else
-        sweep_tile2d_body<T, ORDER, TY, ZERO_IN, PROLONG, WALLS, false>(xin, xc, b, bscale, xout, g, gc, a, inv_diag,
-                                                                        w, X, B, XC, tid, x0, y0, nw);
-}
-
-// ---------------------------------------------------------------------------
-// Two consecutive red-black sweeps of one 64 x TY tile from one staging of x
-// and b: red on the tile plus 3 layers, black on plus 2, red on plus 1, black
-// on the tile (each half-sweep relaxes one colour from the values before it,
-// so every phase needs the previous one on a region one layer wider, and the
-// order-4 same-colour neighbours two layers wider).  x is staged with a halo
-// of R + 3, b with a halo of 3.  The result equals two calls of the single
-// sweep bit for bit: every relaxed value is computed by the same expression
-// from the same inputs.  Halves the HBM traffic of the two pre-smoothing
-// sweeps and saves one launch per level.  (A layout with one LDS array per
-// colour, which makes the lanes' LDS reads contiguous, measured slower.)
-// ---------------------------------------------------------------------------
-// The relaxation phases of k_sweep2x_tile2d after staging (x in X with a
-// halo of R + 3, b in B with a halo of 3).  NW selects the Neumann-wall
-// closures.
-template <typename T, int ORDER, int TY, bool NW, bool IN>
-__device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0, int y0, const Geo& g, T a,
-                                               T inv_diag, T w, T* __restrict__ xout) {
-    constexpr int TX = 64;
-    constexpr int R = ORDER / 2, H = R + 3;
-    constexpr int LX = TX + 2 * H;
-    constexpr int BH = 3, BX = TX + 2 * BH;
+    constexpr int BH = 2 * NS - 1, BX = TX + 2 * BH;
     static_assert(LX % 2 == 0 && BX % 2 == 0 && TY % 2 == 0, "row pairs of opposite column parities");
     const T cxc = axis_coef<T, ORDER>(g.ihx2), cyc = axis_coef<T, ORDER>(g.ihy2);
     // relaxed value of global point (gi, gj) from the values now in LDS
@@ -310,16 +81,18 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
     auto half = [&](auto kc, int colour) {
         constexpr int K = decltype(kc)::value;
         constexpr int W2 = (TX + 2 * K) / 2, NR = TY + 2 * K, NP = NR * W2;
-        constexpr int IT = (NP + kSweep2xThreads - 1) / kSweep2xThreads;
+        constexpr int IT = (NP + NT - 1) / NT;
         T rv[IT];
         int rp[IT];
 #pragma unroll
         for (int t = 0; t < IT; ++t) {
             rp[t] = -1;
-            const int idx = tid + t * kSweep2xThreads;
+            const int idx = tid + t * NT;
             if (idx >= NP) continue;
-            // lanes alternate between the two rows of a pair (bank-conflict
-            // free reads, as in sweep_tile2d_phases; the row count is even)
+            // lanes alternate between the two rows of a pair, whose points of
+            // one colour sit in columns of opposite parity (LX and BX are
+            // even), so consecutive lanes read distinct LDS banks (the row
+            // count is even)
             const int pr = idx / (2 * W2), q2 = idx - pr * (2 * W2);
             const int r = 2 * pr + (q2 & 1), k2 = q2 >> 1;
             const int gj = y0 - K + r;
@@ -334,15 +107,17 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
             if (rp[t] >= 0) X[rp[t]] = rv[t];
         __syncthreads();
     };
-    half(std::integral_constant<int, 3>{}, 0);  // red, first sweep
-    half(std::integral_constant<int, 2>{}, 1);  // black, first sweep
-    half(std::integral_constant<int, 1>{}, 0);  // red, second sweep
-    // black of the second sweep on the tile, written out with the red point of
+    if constexpr (NS == 2) {
+        half(std::integral_constant<int, 3>{}, 0);  // red, first sweep
+        half(std::integral_constant<int, 2>{}, 1);  // black, first sweep
+    }
+    half(std::integral_constant<int, 1>{}, 0);  // red, last sweep
+    // black of the last sweep on the tile, written out with the red point of
     // the same pair of columns
-    constexpr int NP = TY * (TX / 2), IT = (NP + kSweep2xThreads - 1) / kSweep2xThreads;
+    constexpr int NP = TY * (TX / 2), IT = (NP + NT - 1) / NT;
 #pragma unroll
     for (int t = 0; t < IT; ++t) {
-        const int idx = tid + t * kSweep2xThreads;
+        const int idx = tid + t * NT;
         if (idx >= NP) continue;
         const int pr = idx / TX, q2 = idx - pr * TX;  // row pairs, as in `half`
         const int r = 2 * pr + (q2 & 1), k2 = q2 >> 1;
@@ -355,6 +130,150 @@ __device__ __forceinline__ void sweep2x_phases(T* X, const T* B, int tid, int x0
     }
 }
 
+// Staging and phases of k_sweep_tile2d for one tile; IN: the tile lies
+// inside the grid with its halo (tile_inside2d), so no load or relaxed point
+// needs a bounds, ghost or wall test.
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS, bool IN, int NT>
+__device__ __forceinline__ void sweep_tile2d_body(const T* __restrict__ xin, const T* __restrict__ xc,
+                                                  const T* __restrict__ b, T bscale, T* __restrict__ xout,
+                                                  const Geo& g, const Geo& gc, T a, T inv_diag, T w, T* X, T* B,
+                                                  T* XC, int tid, int x0, int y0, bool nw) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 1;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BX = TX + 2, BY = TY + 2;
+    constexpr int CXW = (LX + 5) / 2 + 1, CYW = (LY + 5) / 2 + 1;  // coarse cells under the x tile
+    const int cx0 = PROLONG ? (x0 - H - 1) >> 1 : 0, cy0 = PROLONG ? (y0 - H - 1) >> 1 : 0;
+
+    // Staging: every global load of a thread is issued (into registers) before
+    // its first LDS store, so a block waits for memory once, not once per row.
+    constexpr int NX = LY * LX, NB = BY * BX, NC = PROLONG ? CYW * CXW : 0;
+    constexpr int IX = (NX + NT - 1) / NT;
+    constexpr int IB = (NB + NT - 1) / NT;
+    constexpr int IC = PROLONG ? (NC + NT - 1) / NT : 1;
+    T cv[IC], xv[IX], bv[IB];
+#pragma unroll
+    for (int t = 0; t < IC; ++t) {
+        const int q = tid + t * NT;
+        T v = T(0);
+        if (PROLONG && q < NC) {
+            const int cy = q / CXW, cxx = q - cy * CXW;
+            const int ic = cx0 + cxx, jc = cy0 + cy;
+            if (ic >= 0 && ic < gc.nx && jc >= 0 && jc < gc.ny) v = xc[(int64_t)jc * gc.nx + ic];
+        }
+        cv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * NT;
+        T v = T(0);
+        if (!ZERO_IN && q < NX) {
+            const int ly = q / LX, lx = q - ly * LX;
+            const int gi = x0 - H + lx, gj = y0 - H + ly;
+            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = xin[(int64_t)gj * g.nx + gi];
+        }
+        xv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * NT;
+        T v = T(0);
+        if (q < NB) {
+            const int by = q / BX, bx = q - by * BX;
+            const int gi = x0 - 1 + bx, gj = y0 - 1 + by;
+            if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) v = b[(int64_t)gj * g.nx + gi];
+        }
+        bv[t] = v;  // scaled at the LDS store: no arithmetic on a load in flight
+    }
+    if (PROLONG) {
+#pragma unroll
+        for (int t = 0; t < IC; ++t) {
+            const int q = tid + t * NT;
+            if (q < NC) XC[q] = cv[t];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < IX; ++t) {
+        const int q = tid + t * NT;
+        if (q < NX) {
+            T v = xv[t];
+            if (PROLONG) {
+                const int ly = q / LX, lx = q - ly * LX;
+                const int gi = x0 - H + lx, gj = y0 - H + ly;
+                if (IN || (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)) {
+                    // q = f - off (off = 1 behind a Dirichlet low wall, 0 behind a
+                    // Neumann one): q even -> coarse q/2; odd -> mean of (q-1)/2 and (q+1)/2
+                    const int qi = WALLS ? gi - ((g.wall & 1) ? 0 : 1) : gi - 1;
+                    const int qj = WALLS ? gj - ((g.wall & 4) ? 0 : 1) : gj - 1;
+                    const int ia = (qi >> 1) - cx0, ib = ((qi + 1) >> 1) - cx0;
+                    const int ja = (qj >> 1) - cy0, jb = ((qj + 1) >> 1) - cy0;
+                    const T wia = (qi & 1) ? T(0.5) : T(1), wib = (qi & 1) ? T(0.5) : T(0);
+                    const T wja = (qj & 1) ? T(0.5) : T(1), wjb = (qj & 1) ? T(0.5) : T(0);
+                    const T rowa = wia * XC[ja * CXW + ia] + wib * XC[ja * CXW + ib];
+                    const T rowb = wia * XC[jb * CXW + ia] + wib * XC[jb * CXW + ib];
+                    v += wja * rowa + wjb * rowb;
+                }
+            }
+            X[q] = v;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < IB; ++t) {
+        const int q = tid + t * NT;
+        if (q < NB) B[q] = bscale * bv[t];
+    }
+    __syncthreads();
+
+    // tiles near a Neumann wall run the wall closures; all others the
+    // Dirichlet-only code (a uniform branch, taken once per tile)
+    if constexpr (IN) {
+        sweep_phases<T, ORDER, TY, false, true, 1, NT>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+    } else if constexpr (WALLS) {
+        if (nw) sweep_phases<T, ORDER, TY, true, false, 1, NT>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        else sweep_phases<T, ORDER, TY, false, false, 1, NT>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+    } else {
+        sweep_phases<T, ORDER, TY, false, false, 1, NT>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+    }
+}
+
+template <typename T, int ORDER, int TY, bool ZERO_IN, bool PROLONG, bool WALLS>
+__global__ __launch_bounds__(single_sweep_threads<TY>()) void k_sweep_tile2d(
+    const T* __restrict__ xin, const T* __restrict__ xc, const T* __restrict__ b, T bscale, T* __restrict__ xout,
+    Geo g, Geo gc, T a, T inv_diag, T w) {
+    constexpr int TX = 64;
+    constexpr int R = ORDER / 2, H = R + 1;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int BX = TX + 2, BY = TY + 2;
+    constexpr int CXW = (LX + 5) / 2 + 1, CYW = (LY + 5) / 2 + 1;
+    __shared__ T X[LY * LX];
+    __shared__ T B[BY * BX];
+    __shared__ T XC[PROLONG ? CYW * CXW : 1];
+    const int tid = threadIdx.x;
+    int bx, by;
+    xcd_block(bx, by);  // XCD-contiguous bands of tiles
+    const int x0 = bx * TX, y0 = by * TY;
+    const bool nw = WALLS && near_neumann(g, x0, x0 + TX, y0, y0 + TY, 0, 1, H);  // uniform per tile
+    if (!nw && tile_inside2d(g, x0, x0 + TX, y0, y0 + TY, H))
+        sweep_tile2d_body<T, ORDER, TY, ZERO_IN, PROLONG, WALLS, true, single_sweep_threads<TY>()>(
+            xin, xc, b, bscale, xout, g, gc, a, inv_diag, w, X, B, XC, tid, x0, y0, nw);
+    else
+        sweep_tile2d_body<T, ORDER, TY, ZERO_IN, PROLONG, WALLS, false, single_sweep_threads<TY>()>(
+            xin, xc, b, bscale, xout, g, gc, a, inv_diag, w, X, B, XC, tid, x0, y0, nw);
+}
+
+// ---------------------------------------------------------------------------
+// Two consecutive red-black sweeps of one 64 x TY tile from one staging of x
+// and b: red on the tile plus 3 layers, black on plus 2, red on plus 1, black
+// on the tile (each half-sweep relaxes one colour from the values before it,
+// so every phase needs the previous one on a region one layer wider, and the
+// order-4 same-colour neighbours two layers wider).  x is staged with a halo
+// of R + 3, b with a halo of 3.  The result equals two calls of the single
+// sweep bit for bit: every relaxed value is computed by the same expression
+// from the same inputs.  Halves the HBM traffic of the two pre-smoothing
+// sweeps and saves one launch per level.  (A layout with one LDS array per
+// colour, which makes the lanes' LDS reads contiguous, measured slower.)
+// ---------------------------------------------------------------------------
 // Staging and phases of k_sweep2x_tile2d for one tile; IN as in
 // sweep_tile2d_body.
 template <typename T, int ORDER, int TY, bool ZERO_IN, bool WALLS, bool IN>
@@ -406,12 +325,14 @@ __device__ __forceinline__ void sweep2x_body(const T* __restrict__ xin, const T*
     __syncthreads();
 
     if constexpr (IN) {
-        sweep2x_phases<T, ORDER, TY, false, true>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        sweep_phases<T, ORDER, TY, false, true, 2, kSweep2xThreads>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     } else if constexpr (WALLS) {
-        if (nw) sweep2x_phases<T, ORDER, TY, true, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
-        else sweep2x_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        if (nw)
+            sweep_phases<T, ORDER, TY, true, false, 2, kSweep2xThreads>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        else
+            sweep_phases<T, ORDER, TY, false, false, 2, kSweep2xThreads>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     } else {
-        sweep2x_phases<T, ORDER, TY, false, false>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
+        sweep_phases<T, ORDER, TY, false, false, 2, kSweep2xThreads>(X, B, tid, x0, y0, g, a, inv_diag, w, xout);
     }
 }
 
@@ -445,7 +366,7 @@ static hipError_t sweep2d_launch(const T* xin, const T* xc, const T* b, T bs, T*
                                  T aa, T inv, T w, bool zero_in, bool prolong, hipStream_t s, hipEvent_t ev0,
                                  hipEvent_t ev1) {
     dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
-    dim3 block(kTileThreads);
+    dim3 block(single_sweep_threads<TY>());
     if (zero_in && prolong)
         hipExtLaunchKernelGGL((k_sweep_tile2d<T, ORDER, TY, true, true, WALLS>), grid, block, 0, s, ev0, ev1, 0, xin, xc, b, bs, xout, g, gc, aa, inv, w);
     else if (zero_in)
@@ -556,12 +477,13 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
 
     // staging, every global load issued before the first LDS store
     constexpr int NX = LY * LX, NB = BY * BX;
-    constexpr int IX = (NX + kTileThreads - 1) / kTileThreads, IB = (NB + kTileThreads - 1) / kTileThreads;
+    constexpr int IX = (NX + kSweep2xRestrictThreads - 1) / kSweep2xRestrictThreads;
+    constexpr int IB = (NB + kSweep2xRestrictThreads - 1) / kSweep2xRestrictThreads;
     {
         T xv[IX], bv[IB];
 #pragma unroll
         for (int t = 0; t < IX; ++t) {
-            const int q = tid + t * kTileThreads;
+            const int q = tid + t * kSweep2xRestrictThreads;
             T v = T(0);
             if (!ZERO_IN && q < NX) {
                 const int ly = q / LX, lx = q - ly * LX;
@@ -572,7 +494,7 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
         }
 #pragma unroll
         for (int t = 0; t < IB; ++t) {
-            const int q = tid + t * kTileThreads;
+            const int q = tid + t * kSweep2xRestrictThreads;
             T v = T(0);
             if (q < NB) {
                 const int ly = q / BX, lx = q - ly * BX;
@@ -583,12 +505,12 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
         }
 #pragma unroll
         for (int t = 0; t < IX; ++t) {
-            const int q = tid + t * kTileThreads;
+            const int q = tid + t * kSweep2xRestrictThreads;
             if (q < NX) X[q] = xv[t];
         }
 #pragma unroll
         for (int t = 0; t < IB; ++t) {
-            const int q = tid + t * kTileThreads;
+            const int q = tid + t * kSweep2xRestrictThreads;
             if (q < NB) B[q] = bscale * bv[t];
         }
     }
@@ -623,16 +545,16 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
     auto half = [&](auto kc, int colour) {
         constexpr int K = decltype(kc)::value;
         constexpr int W2 = (TX + 2 * K) / 2, NRW = TY + 2 * K, NP = NRW * W2;
-        constexpr int IT = (NP + kTileThreads - 1) / kTileThreads;
+        constexpr int IT = (NP + kSweep2xRestrictThreads - 1) / kSweep2xRestrictThreads;
         T rv[IT];
         int rp[IT];
 #pragma unroll
         for (int t = 0; t < IT; ++t) {
             rp[t] = -1;
-            const int idx = tid + t * kTileThreads;
+            const int idx = tid + t * kSweep2xRestrictThreads;
             if (idx >= NP) continue;
             // lanes alternate between the two rows of a pair (bank-conflict
-            // free reads, as in sweep_tile2d_phases; the row count is even)
+            // free reads, as in sweep_phases; the row count is even)
             const int pr = idx / (2 * W2), q2 = idx - pr * (2 * W2);
             const int r = 2 * pr + (q2 & 1), k2 = q2 >> 1;
             const int gj = y0 - K + r;
@@ -653,17 +575,17 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
     half(std::integral_constant<int, M>{}, 1);      // black, second sweep
 
     // the tile's new iterate
-    for (int q = tid; q < TX * TY; q += kTileThreads) {
+    for (int q = tid; q < TX * TY; q += kSweep2xRestrictThreads) {
         const int r = q / TX, c = q - r * TX;
         const int gi = x0 + c, gj = y0 + r;
         if (IN || (gi < g.nx && gj < g.ny)) xout[(int64_t)gj * g.nx + gi] = X[(r + H) * LX + c + H];
     }
     // residual over fine points [x0, x0 + 64] x [y0, y0 + TY] (0 outside the grid)
-    constexpr int IR = (NR + kTileThreads - 1) / kTileThreads;
+    constexpr int IR = (NR + kSweep2xRestrictThreads - 1) / kSweep2xRestrictThreads;
     T rv[IR];
 #pragma unroll
     for (int t = 0; t < IR; ++t) {
-        const int q = tid + t * kTileThreads;
+        const int q = tid + t * kSweep2xRestrictThreads;
         T r = T(0);
         if (q < NR) {
             const int ry = q / RX, rx = q - ry * RX;
@@ -679,12 +601,12 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
     __syncthreads();  // every read of b is done: its LDS takes r
 #pragma unroll
     for (int t = 0; t < IR; ++t) {
-        const int q = tid + t * kTileThreads;
+        const int q = tid + t * kSweep2xRestrictThreads;
         if (q < NR) B[q] = rv[t];
     }
     __syncthreads();
     // full weighting onto the coarse points of the tile
-    for (int q = tid; q < (TX / 2) * (TY / 2); q += kTileThreads) {
+    for (int q = tid; q < (TX / 2) * (TY / 2); q += kSweep2xRestrictThreads) {
         const int cy = q / (TX / 2), cx = q - cy * (TX / 2);
         const int ic = (x0 >> 1) + cx, jc = (y0 >> 1) + cy;
         if (ic >= gc.nx || jc >= gc.ny) continue;
@@ -702,7 +624,7 @@ __device__ __forceinline__ void sweep2x_restrict_body(const T* __restrict__ xin,
 }
 
 template <typename T, int ORDER, int TY, bool ZERO_IN>
-__global__ __launch_bounds__(kTileThreads) void k_sweep2x_restrict_tile2d(const T* __restrict__ xin,
+__global__ __launch_bounds__(kSweep2xRestrictThreads) void k_sweep2x_restrict_tile2d(const T* __restrict__ xin,
                                                                           const T* __restrict__ b, T bscale,
                                                                           T* __restrict__ xout, Geo g, T a,
                                                                           T inv_diag, T w, T* __restrict__ bc,
@@ -730,7 +652,7 @@ static hipError_t sweep2x_restrict_launch(const T* xin, const T* b, T bs, T* xou
                                           bool zero_in, T* bc, const Geo& gc, hipStream_t s, hipEvent_t ev0,
                                           hipEvent_t ev1) {
     dim3 grid((g.nx + 63) / 64, (g.ny + TY - 1) / TY, 1);
-    dim3 block(kTileThreads);
+    dim3 block(kSweep2xRestrictThreads);
     if (zero_in)
         hipExtLaunchKernelGGL((k_sweep2x_restrict_tile2d<T, ORDER, TY, true>), grid, block, 0, s, ev0, ev1, 0, xin, b, bs, xout, g, aa, inv, w, bc, gc);
     else
