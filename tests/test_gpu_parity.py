@@ -388,3 +388,34 @@ def test_wide_tiles_mixed_filter_matches_oracle():
     say("wide mixed S v", P.n)
     got = to_host(op.apply_filter(to_dev(v)))
     assert rel_err(got, oracle_S(P, v)) < 4 * n_t * 2.0 ** -24 + 100 * P.mg_tol
+
+
+# Grids on which the inside-tile test holds with equality: a tile's staged
+# halo ends on the last grid point.  131 x 75: the prolongation sweep of the
+# finest level (halo R + 1 = 3 for order 4 on 64 x 8 tiles: 131 = 64 + 64 +
+# 3, 75 = 64 + 8 + 3).  133 x 77 with one level: eight sweeps as fused
+# two-sweep passes, whose halo R + 3 ends on the last point (133 = 64 + 64 +
+# 5, 77 = 64 + 8 + 5).
+EDGE_CASES = [
+    (synthetic.Problem(n=(131, 75), length=(1.0, 0.6), order=4, omega=40.0, ts="implicit", adjust_omega=True), 0),
+    (synthetic.Problem(n=(133, 77), length=(1.0, 0.6), order=4, omega=40.0, ts="implicit", adjust_omega=True), 1),
+]
+
+
+@pytest.mark.parametrize("case", EDGE_CASES, ids=lambda c: f"{c[0].n}-levels{c[1]}")
+def test_inside_tile_edges_vcycle_matches_oracle(case):
+    P, max_levels = case
+    op = make_op(P, mg_max_levels=max_levels, mg_coarse_points=40)
+    h, plan = oracle_plan(P)
+    a = 0.5 * plan.dt ** 2
+    hier = OMG.Hierarchy(P.n, D.spacing(P.n, P.length), P.order, a, nu1=2, nu2=1, coarse_sweeps=8,
+                         max_levels=max_levels if max_levels > 0 else 64, relax=op.mg_relax,
+                         relax_coarse=op.mg_relax_coarse)
+    assert op.mg_levels == len(hier.sizes)
+    shape = P.n[::-1]
+    b = synthetic.uniform_pm1(61, P.n_active)
+    x = synthetic.uniform_pm1(62, P.n_active)
+    say("inside-tile edge vcycle", P.n, max_levels)
+    got = to_host(op.mg_vcycle(to_dev(b), to_dev(x)))
+    want = OMG.vcycle(x.reshape(shape), b.reshape(shape), hier).ravel()
+    assert rel_err(got, want) < 1e-12
