@@ -44,12 +44,21 @@ struct MgsLink {
     const double* u;
 };
 
+// One workgroup of a batched step launch: the problem it advances and the
+// tile of that problem, so that a workgroup finds both with one load.
+struct BatchBlk {
+    int prob;
+    int tile;
+};
+
 hipError_t launch_batch_small(BatchProbDev* probs, const int* small_ids, int nsmall, const float* coef, int order,
                               size_t lds_bytes, hipStream_t s);
 hipError_t prepare_batch_small(int order, size_t lds_bytes);
 // coef: float (FP32 state) or double (fp64 != 0) filter weights.
-hipError_t launch_batch_step(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
-                             const void* coef, int step, int order, int tyr, int fp64, hipStream_t s);
+// blk: nblocks entries (problems ordered so that the ones still stepping at
+// `step` are covered by the first nblocks workgroups).
+hipError_t launch_batch_step(BatchProbDev* probs, const BatchBlk* blk, int nblocks, const void* coef, int step,
+                             int order, int tyr, int fp64, hipStream_t s);
 hipError_t launch_batch_convert(BatchProbDev* probs, const int* ids, const int* blk_start, int nseg, int nblocks,
                                 int to_fp32, hipStream_t s);
 hipError_t launch_batch_mgs(const BatchMgsDev* info, const MgsLink* links, int nprob, const int* blk_start,

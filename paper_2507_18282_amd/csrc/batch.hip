@@ -54,7 +54,7 @@ struct ew_batch_s {
     std::vector<int> small_ids, large_ids;
     int* small_ids_dev = nullptr;
     int* large_ids_dev = nullptr;
-    int* step_blk_dev = nullptr;
+    ew::BatchBlk* step_tab_dev = nullptr;  // (problem, tile) per step workgroup, sized for the shortest tiles
     int* conv_blk_dev = nullptr;
     int nblocks_step = 0, nblocks_conv = 0, max_nt_large = 0, tyr = 4;
     // Large problems are ordered by N_t, longest first, so the problems that
@@ -85,13 +85,17 @@ static ew_status build_step_table(ew_batch b, int tyr) {
     for (size_t s = 0; s < b->large_ids.size(); ++s)
         starts[s + 1] = starts[s] + step_tiles(b->P[b->large_ids[s]].g, tyr);
     b->nblocks_step = starts.back();
+    std::vector<BatchBlk> tab(b->nblocks_step);
+    for (size_t s = 0; s < b->large_ids.size(); ++s)
+        for (int t = starts[s]; t < starts[s + 1]; ++t) tab[t] = {b->large_ids[s], t - starts[s]};
     b->step_nblk.assign(b->max_nt_large, 0);
     size_t cnt = b->large_ids.size();
     for (int st = 0; st < b->max_nt_large; ++st) {  // cnt: problems with N_t > st
         while (cnt > 0 && b->P[b->large_ids[cnt - 1]].tp.n_t <= st) --cnt;
         b->step_nblk[st] = starts[cnt];
     }
-    EW_HIP_TRY(hipMemcpy(b->step_blk_dev, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!tab.empty())
+        EW_HIP_TRY(hipMemcpy(b->step_tab_dev, tab.data(), tab.size() * sizeof(BatchBlk), hipMemcpyHostToDevice));
     b->tyr = tyr;
     return EW_OK;
 }
@@ -113,8 +117,8 @@ static ew_status capture_graph(ew_batch b) {
         if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
     }
     for (int step = 0; e == hipSuccess && step < b->max_nt_large; ++step)
-        e = launch_batch_step(b->probs_dev, b->large_ids_dev, b->step_blk_dev, nl, b->step_nblk[step], b->coef_dev,
-                              step, b->order, b->tyr, b->fp64, s);
+        e = launch_batch_step(b->probs_dev, b->step_tab_dev, b->step_nblk[step], b->coef_dev, step, b->order, b->tyr,
+                              b->fp64, s);
     if (e == hipSuccess && nl > 0 && !b->fp64)
         e = launch_batch_convert(b->probs_dev, b->large_ids_dev, b->conv_blk_dev, nl, b->nblocks_conv, 0, s);
     if (e == hipSuccess && ns > 0) e = hipStreamWaitEvent(s, b->ev_join, 0);
@@ -164,13 +168,12 @@ static ew_status autotune(ew_batch b) {
     int best_tyr = 4;
     for (int c = 0; c < 4; ++c) {
         EW_TRY(build_step_table(b, cand[c]));
-        const int nl = (int)b->large_ids.size();
-        EW_HIP_TRY(launch_batch_step(b->probs_dev, b->large_ids_dev, b->step_blk_dev, nl, b->nblocks_step, b->coef_dev,
-                                     1, b->order, cand[c], b->fp64, b->stream));
+        EW_HIP_TRY(launch_batch_step(b->probs_dev, b->step_tab_dev, b->nblocks_step, b->coef_dev, 1, b->order, cand[c],
+                                     b->fp64, b->stream));
         EW_HIP_TRY(hipEventRecord(e0, b->stream));
         for (int r = 0; r < 8; ++r)
-            EW_HIP_TRY(launch_batch_step(b->probs_dev, b->large_ids_dev, b->step_blk_dev, nl, b->nblocks_step,
-                                         b->coef_dev, 1, b->order, cand[c], b->fp64, b->stream));
+            EW_HIP_TRY(launch_batch_step(b->probs_dev, b->step_tab_dev, b->nblocks_step, b->coef_dev, 1, b->order,
+                                         cand[c], b->fp64, b->stream));
         EW_HIP_TRY(hipEventRecord(e1, b->stream));
         EW_HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -323,7 +326,9 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
     b->nblocks_conv = conv_starts.back();
     EW_TRY(balloc(b.get(), (void**)&b->small_ids_dev, (b->small_ids.size() + 1) * sizeof(int)));
     EW_TRY(balloc(b.get(), (void**)&b->large_ids_dev, (b->large_ids.size() + 1) * sizeof(int)));
-    EW_TRY(balloc(b.get(), (void**)&b->step_blk_dev, (b->large_ids.size() + 1) * sizeof(int)));
+    size_t max_step_blocks = 1;  // the table for the shortest tiles (one row per thread) is the largest
+    for (int i : b->large_ids) max_step_blocks += step_tiles(b->P[i].g, 1);
+    EW_TRY(balloc(b.get(), (void**)&b->step_tab_dev, max_step_blocks * sizeof(BatchBlk)));
     EW_TRY(balloc(b.get(), (void**)&b->conv_blk_dev, conv_starts.size() * sizeof(int)));
     if (!b->small_ids.empty())
         EW_HIP_TRY(hipMemcpy(b->small_ids_dev, b->small_ids.data(), b->small_ids.size() * sizeof(int), hipMemcpyHostToDevice));

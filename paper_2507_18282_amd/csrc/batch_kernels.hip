@@ -9,8 +9,8 @@
 //                    S v.
 //  * k_batch_step    one leapfrog step (fused with the filter accumulation)
 //                    for every large problem that still has steps left, in
-//                    one launch; blocks map to (problem, tile) through a
-//                    prefix-sum table.
+//                    one launch; each workgroup reads its (problem, tile)
+//                    from a table built on the host.
 //  * k_batch_convert FP64 <-> FP32 copies of the boundary vectors.
 //  * k_batch_mgs     one modified Gram-Schmidt link for every problem of a
 //                    batched Arnoldi step (FP64), partial sums per problem.
@@ -110,17 +110,17 @@ __global__ __launch_bounds__(kBatchSmallThreads) void k_batch_small(BatchProbDev
 // Large problems: one step for every problem, tiles of 64 x (4 TYR) points.
 // --------------------------------------------------------------------------
 template <int ORDER, int TYR, typename T>
-__global__ __launch_bounds__(256) void k_batch_step(BatchProbDev* __restrict__ probs, const int* __restrict__ large_ids,
-                                                    const int* __restrict__ blk_start, int nlarge,
-                                                    const T* __restrict__ coef, int step) {
+__global__ __launch_bounds__(256) void k_batch_step(BatchProbDev* __restrict__ probs,
+                                                    const BatchBlk* __restrict__ blk, const T* __restrict__ coef,
+                                                    int step) {
     int wb, wy, wz;
     xcd_block(wb, wy, wz);  // each XCD takes a contiguous run of tiles (rows of a problem share halos)
-    const int s = find_segment(blk_start, nlarge, wb);
-    const BatchProbDev& P = probs[large_ids[s]];
+    const BatchBlk bt = blk[wb];  // one load (a binary search over the problems' first tiles took seven)
+    const BatchProbDev& P = probs[bt.prob];
     if (!P.active || step >= P.n_t) return;
     const Geo g = P.g;
     const int tiles_x = (g.nx + 63) >> 6;
-    const int tile = wb - blk_start[s];
+    const int tile = bt.tile;
     const int i = (tile % tiles_x) * 64 + (threadIdx.x & 63);
     const int j0 = (tile / tiles_x) * (4 * TYR) + (threadIdx.x >> 6);
     if (i >= g.nx) return;
@@ -239,9 +239,9 @@ hipError_t prepare_batch_small(int order, size_t lds_bytes) {
 }
 
 template <typename T>
-static void batch_step_typed(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
-                             const T* coef, int step, int order, int tyr, hipStream_t s) {
-#define EW_BSTEP(O, R) k_batch_step<O, R, T><<<nblocks, 256, 0, s>>>(probs, large_ids, blk_start, nlarge, coef, step)
+static void batch_step_typed(BatchProbDev* probs, const BatchBlk* blk, int nblocks, const T* coef, int step,
+                             int order, int tyr, hipStream_t s) {
+#define EW_BSTEP(O, R) k_batch_step<O, R, T><<<nblocks, 256, 0, s>>>(probs, blk, coef, step)
     if (order == 2) {
         switch (tyr) { case 1: EW_BSTEP(2, 1); break; case 2: EW_BSTEP(2, 2); break; case 4: EW_BSTEP(2, 4); break; default: EW_BSTEP(2, 8); }
     } else {
@@ -250,15 +250,13 @@ static void batch_step_typed(BatchProbDev* probs, const int* large_ids, const in
 #undef EW_BSTEP
 }
 
-hipError_t launch_batch_step(BatchProbDev* probs, const int* large_ids, const int* blk_start, int nlarge, int nblocks,
-                             const void* coef, int step, int order, int tyr, int fp64, hipStream_t s) {
-    if (nlarge == 0 || nblocks == 0) return hipSuccess;
+hipError_t launch_batch_step(BatchProbDev* probs, const BatchBlk* blk, int nblocks, const void* coef, int step,
+                             int order, int tyr, int fp64, hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
     if (fp64)
-        batch_step_typed<double>(probs, large_ids, blk_start, nlarge, nblocks, static_cast<const double*>(coef), step,
-                                 order, tyr, s);
+        batch_step_typed<double>(probs, blk, nblocks, static_cast<const double*>(coef), step, order, tyr, s);
     else
-        batch_step_typed<float>(probs, large_ids, blk_start, nlarge, nblocks, static_cast<const float*>(coef), step,
-                                order, tyr, s);
+        batch_step_typed<float>(probs, blk, nblocks, static_cast<const float*>(coef), step, order, tyr, s);
     return hipGetLastError();
 }
 
