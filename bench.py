@@ -604,7 +604,7 @@ def many_pairs(ks=None):
     return out
 
 
-def mixed_cube(n_cube: int = CUBE_N):
+def mixed_cube(n_cube: int = CUBE_N, precs=("mixed", "fp64")):
     """Unit cube, order 2, implicit 10 steps/period, omega 40 (adjusted), k = 8,
     m = 17, N_p from the lobe rule: complete eigensolves in mixed precision
     (FP32 inner multigrid + FP64 defect correction, FP32 filter accumulation)
@@ -612,7 +612,8 @@ def mixed_cube(n_cube: int = CUBE_N):
     deflation probes for the repeated eigenvalues, CUBE_BUDGET wave-solves),
     each eigenvalue compared with the closed form and with the FP64 solve's,
     eig-res stated; and the cost of one period on the 255^3 grid in both
-    precisions (S^2 v compared)."""
+    precisions (S^2 v compared).  `precs` selects the complete solves that run
+    (a 255^3 solve takes minutes in each precision)."""
     import numpy as np
     import torch
     import synthetic
@@ -626,7 +627,7 @@ def mixed_cube(n_cube: int = CUBE_N):
                        f"omega 40 (adjusted), N_p {n_p} (lobe rule), k=8, m=17, multigrid to 1e-10",
            "n_p": n_p, "eigenvalues_in_lobe": n_lobe}
     res = {}
-    for prec in ("mixed", "fp64"):
+    for prec in precs:
         op = Operator(n=P.n, length=P.length, order=P.order, omega=P.omega, ts=P.ts, n_its=P.n_its, n_p=n_p,
                       adjust_omega=True, precision=prec, mg_tol=P.mg_tol, mg_max_levels=MG_LEVELS,
                       mg_coarse_sweeps=MG_COARSE_SWEEPS)
@@ -654,7 +655,7 @@ def mixed_cube(n_cube: int = CUBE_N):
             f"max err vs closed form {max(errs) if errs else float('nan'):.2e}, "
             f"max eig-res {max(r.res) if r.res else float('nan'):.2e}")
         op.close()
-    a, b = sorted(res["mixed"].mu), sorted(res["fp64"].mu)
+    a, b = (sorted(res[p].mu) if p in res else [] for p in ("mixed", "fp64"))
     if a and b and len(a) == len(b):
         out["mixed_vs_fp64_mu_rel_diff"] = [abs(x - y) / y for x, y in zip(a, b)]
     # one period on 255^3: cost of each precision, S^2 v compared
@@ -707,6 +708,8 @@ def main(argv=None) -> int:
     ap.add_argument("--only-batch", action="store_true", help="run only the batched form and print its JSON")
     ap.add_argument("--cube-n", type=int, default=CUBE_N,
                     help="cube side of the mixed-vs-FP64 eigensolves (63 by default; 127 and 255 are longer runs)")
+    ap.add_argument("--cube-prec", choices=("mixed", "fp64", "both"), default="both",
+                    help="which complete cube eigensolves run (one precision per call keeps a 255^3 run shorter)")
     ap.add_argument("--no-headline-eigs", action="store_true",
                     help="skip the complete headline eigensolve (the eigenpairs/s of the headline workload)")
     a = ap.parse_args(argv)
@@ -735,7 +738,8 @@ def main(argv=None) -> int:
         print(json.dumps({"form": "learned_vs_plain", "result": learned_vs_plain()}), flush=True)
         return 0
     if a.only_cube:
-        print(json.dumps({"form": "mixed_cube", "result": mixed_cube(a.cube_n)}), flush=True)
+        precs = ("mixed", "fp64") if a.cube_prec == "both" else (a.cube_prec,)
+        print(json.dumps({"form": "mixed_cube", "result": mixed_cube(a.cube_n, precs)}), flush=True)
         return 0
     if a.only_batch:
         print(json.dumps({"form": "batched_vs_plain", "result": batched_vs_plain(a.batch_budget)}), flush=True)

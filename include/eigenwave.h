@@ -365,7 +365,10 @@ typedef struct {
  * (or on a mapped grid) the Krylov vectors, v0_dev and the residuals are in
  * the coordinates y = W^{1/2} u (W = 1/2 per Neumann wall a point lies on;
  * W = J on a mapped grid), where S and L_h are symmetric.
- * Host-blocking.  EW_ERR_NOT_CONVERGED if max_wave_solves is reached first. */
+ * Host-blocking.  EW_ERR_NOT_CONVERGED if max_wave_solves is reached first.
+ * With the environment variable EW_EIGS_PROGRESS set (to anything but "0"),
+ * each convergence test prints one line to stderr (run, basis size,
+ * wave-solves, restarts, leading converged Ritz pairs). */
 ew_status ew_eigs(ew_op op, const ew_eigs_desc* desc, int k_cap, double* mu_host, double* beta_host,
                   double* res_host, double* Y_dev, ew_eigs_stats* stats);
 

@@ -9,6 +9,8 @@
 // not fit a small buffer, each step crosses the host/device boundary once.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "eigs_core.h"
@@ -157,6 +159,14 @@ ew_status apply_L_sym(Workspace& ws, const double* in, double* out) {
     return EW_OK;
 }
 
+// With the environment variable EW_EIGS_PROGRESS set (to anything but "0"),
+// every convergence test of a run prints one line to stderr, so that a long
+// solve on a large grid shows how far it has come.
+static bool progress_enabled() {
+    const char* e = std::getenv("EW_EIGS_PROGRESS");
+    return e != nullptr && e[0] != '\0' && std::strcmp(e, "0") != 0;
+}
+
 // Probe runs test for convergence before the basis is full, at basis sizes
 // from kProbeFirstCheck on that are a power of two or three times one (16,
 // 24, 32, 48, 64, ...; the last test is always at the full basis).
@@ -263,6 +273,14 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
         T(j + 1, j) = nrm;
         return EW_OK;
     };
+    const bool progress = progress_enabled();
+    auto report = [&](int s) {
+        if (!progress) return;
+        std::fprintf(stderr,
+                     "ew_eigs: run %d, basis %d, %lld wave-solves, %lld restarts, %d leading Ritz pairs converged\n",
+                     probe, s, (long long)wave_solves, (long long)restarts, leading_converged(out.conv));
+        std::fflush(stderr);
+    };
     int p = 0;
     for (;;) {
         int j = p;
@@ -330,12 +348,15 @@ ew_status ks_run(Workspace& ws, int nl, int n_keep, double tol_ritz, int probe, 
             const int s = j;
             if (probe_check_at(s)) {
                 ritz(s);
-                if (stop_rule(s)) return EW_OK;
+                const bool stop = stop_rule(s);
+                report(s);
+                if (stop) return EW_OK;
             }
         }
         ritz(m);
         const double beta_m = T(m, m - 1);
         const bool stop = stop_rule(m);
+        report(m);
         if (stop || wave_solves >= ws_budget) return EW_OK;
         // Thick restart: keep the leading n_keep Ritz vectors and the residual vector.
         EW_TRY(rotate(ws, ws.V, m, out.Q, n_keep, ws.Vt));
