@@ -143,7 +143,7 @@ typedef struct {
  *                      2 a S / (1 + 2 a S) for order 2, (34/12) a S /
  *                      (1 + (30/12) a S) for order 4, S = sum_d 1/h_d^2 on
  *                      that level), raised to mg_coarse_sweeps, is <= 0.1.
- *   mg_relax           implicit boxes only: relaxation weight w of the
+ *   mg_relax           implicit solves: relaxation weight w of the
  *                      finest level's red-black half-sweeps,
  *                      x_i += w (b - M x)_i / M_ii (w > 1: over-relaxed
  *                      red-black Gauss-Seidel); 0 = the default 1.2; else in
@@ -152,7 +152,10 @@ typedef struct {
  *                      point always uses 1, an exact solve); 0 = the default
  *                      1.05; else in (0, 2).  The defaults took the fewest
  *                      V-cycles per solve on the 2D and 3D workloads tried.
- *                      Mapped grids ignore both. */
+ *                      On a mapped grid both weigh the zebra-line (or, on
+ *                      lines too long for LDS, point) relaxation,
+ *                      x <- x + w (relaxed value - x), and default to 1: the
+ *                      best weights depend on the map. */
 enum { EW_MG_LEVELS_AUTO = -1 };
 typedef struct {
     double omega;

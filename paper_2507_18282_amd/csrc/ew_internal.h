@@ -182,14 +182,15 @@ hipError_t launch_pointwise_mul(const double* in, const double* f, double* out, 
 // others copied); residual r = bscale b - M x, stored when r_out != nullptr
 // and with per-block partial sums of r^2 (kRedBlocks) when partial !=
 // nullptr; full-weighting restriction of r to the level with n_c = (n - 1)/2.
+// The half-sweep's correction is scaled by the weight w.
 hipError_t launch_rb_half_mapped(const double* xin, double* xout, const double* b, double bscale, const Geo& g,
-                                 const MapCoef& m, double a, int colour, hipStream_t s);
+                                 const MapCoef& m, double a, double w, int colour, hipStream_t s);
 // Zebra line relaxation, in place: every line j of parity `parity` solved
-// exactly for its own points with the values on lines j +- 1 held (needs
-// m.tw and line_relax_fits(g.nx)).
+// exactly for its own points with the values on lines j +- 1 held, and the
+// line set to x + w (solution - x) (needs m.tw and line_relax_fits(g.nx)).
 bool line_relax_fits(int nx);
 hipError_t launch_line_half_mapped(double* x, const double* b, double bscale, const Geo& g, const MapCoef& m,
-                                   double a, int parity, hipStream_t s);
+                                   double a, double w, int parity, hipStream_t s);
 hipError_t launch_residual_mapped(const double* x, const double* b, double bscale, const Geo& g, const MapCoef& m,
                                   double a, double* partial, double* r_out, hipStream_t s);
 hipError_t launch_restrict_fw(const double* r, const Geo& gf, double* bc, const Geo& gc, hipStream_t s);

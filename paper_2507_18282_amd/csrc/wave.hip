@@ -471,11 +471,13 @@ extern "C" ew_status ew_op_mg_half_sweep(ew_op op, const double* b_dev, double* 
     if (b_dev == x_dev) return fail(EW_ERR_INVALID_ARG, "b and x may not alias");
     double* tmp = (double*)op->levels[0].x[1];
     if (op->mapped && op->mcoef[0].tw) {
-        EW_HIP_TRY(launch_line_half_mapped(x_dev, b_dev, 1.0, op->g, op->mcoef[0], op->a, colour, op->stream));
+        EW_HIP_TRY(launch_line_half_mapped(x_dev, b_dev, 1.0, op->g, op->mcoef[0], op->a, op->level_relax(0), colour,
+                                           op->stream));
         return EW_OK;
     }
     if (op->mapped)
-        EW_HIP_TRY(launch_rb_half_mapped(x_dev, tmp, b_dev, 1.0, op->g, op->mcoef[0], op->a, colour, op->stream));
+        EW_HIP_TRY(launch_rb_half_mapped(x_dev, tmp, b_dev, 1.0, op->g, op->mcoef[0], op->a, op->level_relax(0), colour,
+                                         op->stream));
     else
         EW_HIP_TRY(launch_rb_half<double>(x_dev, tmp, b_dev, 1.0, op->g, op->order, op->a, op->relax, colour, op->stream));
     EW_HIP_TRY(hipMemcpyAsync(x_dev, tmp, op->N * sizeof(double), hipMemcpyDeviceToDevice, op->stream));

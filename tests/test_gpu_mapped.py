@@ -250,3 +250,43 @@ def test_implicit_eigs_match_dense_spectrum():
         u = Y[:, c].reshape(n[::-1])
         res = Mp.apply_laplacian(u, xy) + mu[c] * u
         assert np.linalg.norm(res) / mu[c] < 1e-7
+
+
+@pytest.mark.parametrize("case", [HALF_SWEEP_CASES[0], HALF_SWEEP_CASES[4]], ids=lambda c: f"{c[0]}-{c[1]}")
+def test_mapped_over_relaxed_half_sweep_and_solve(case):
+    """With mg_relax = w the half-sweep moves the relaxed lines (or points)
+    from x to x + w (relaxed value - x) (successive line over-relaxation);
+    mapped grids default to w = 1 on every level.  A solve with the weights
+    still reaches the exact solution within the stopping bound."""
+    from scipy import sparse
+    from scipy.sparse import linalg as spl
+    kind, n, params, omega = case
+    xy, op0 = _iop(*case)
+    assert (op0.mg_relax, op0.mg_relax_coarse) == (1.0, 1.0)
+    xy, op = _iop(*case, mg_relax=1.3, mg_relax_coarse=1.2)
+    assert (op.mg_relax, op.mg_relax_coarse) == (1.3, 1.2)
+    plan = Mp.implicit_plan(xy, omega)
+    N = n[0] * n[1]
+    M = (sparse.identity(N) - 0.5 * plan.dt ** 2 * Mp.laplacian_sparse(xy)).tocsr()
+    b = synthetic.uniform_pm1(75, N)
+    x0 = synthetic.uniform_pm1(76, N)
+    ii = np.tile(np.arange(n[0]), n[1])
+    jj = np.repeat(np.arange(n[1]), n[0])
+    for colour in (0, 1):
+        say("mapped over-relaxed half sweep", kind, n, colour)
+        got = to_host(op.mg_half_sweep(to_dev(b), to_dev(x0), colour))
+        if n[0] <= 2816:
+            sel = np.flatnonzero((jj & 1) == colour)
+            want = x0.copy()
+            want[sel] += 1.3 * spl.spsolve(M[sel][:, sel].tocsc(), (b - M @ x0)[sel])
+        else:
+            want = x0 + 1.3 * (b - M @ x0) / M.diagonal()
+            want = np.where(((ii + jj) & 1) == colour, want, x0)
+        assert rel_err(got, want) < 1e-12
+    if n[1] > 3:
+        say("mapped over-relaxed solve", kind, n)
+        x, cycles, rel = op.mg_solve(to_dev(b), to_dev(np.zeros(N)))
+        xe = Mp.solve_implicit_exact(b.reshape(n[::-1]), xy, plan.dt).ravel()
+        Jw = Mp.weights(xy)
+        assert rel <= 1e-10
+        assert np.linalg.norm(to_host(x) - xe) <= np.sqrt(Jw.max() / Jw.min()) * 1e-10 * np.linalg.norm(b) * 1.0001
