@@ -447,8 +447,9 @@ ew_status Op::mapped_vcycle(int l, double* cur, double* other, const double* b, 
         for (int s = 0; s < count; ++s) {
             if (m.tw) {
                 // per relaxed point: x on the two neighbouring lines, b, 1/J, two
-                // A22 and three B values, three factors; write x
-                ProfScope ps(this, EW_K_SMOOTH, l, 104.0 * (double)n);
+                // A22 and three B values, three factors; write x (and read the
+                // line's old x when over-relaxed)
+                ProfScope ps(this, EW_K_SMOOTH, l, (w == 1.0 ? 104.0 : 112.0) * (double)n);
                 EW_HIP_TRY(launch_line_half_mapped(cur, b, bscale, L.g, m, a, w, 0, stream));
                 EW_HIP_TRY(launch_line_half_mapped(cur, b, bscale, L.g, m, a, w, 1, stream));
             } else {
