@@ -353,7 +353,25 @@ ew_status Op::guess_rel_res(const double* b, double bscale, const double* x, dou
 
 ew_status Op::apply_filter(const double* v, double* out) {
     const double dt2 = dt * dt;
-    if (mapped && !implicit) {
+    if (mapped && !implicit && mapped_steps_blocked(g)) {
+        // several steps per launch; launches alternate between two state pairs
+        if (!wC) {
+            EW_TRY(alloc((void**)&wC, N * sizeof(double)));
+            EW_TRY(alloc((void**)&wD, N * sizeof(double)));
+        }
+        double* pair[2][2] = {{wA, wB}, {wC, wD}};
+        const double* rc = v;
+        const double* rp = nullptr;
+        const int per = mapped_steps_per_launch();
+        for (int k0 = 0, j = 0; k0 < n_t; k0 += per, j ^= 1) {
+            const int ns = std::min(per, n_t - k0);
+            ProfScope ps(this, EW_K_LEAPFROG, 0, ((k0 == 0 ? 56.0 : 72.0) + 72.0 * (ns - 1)) * (double)N);
+            EW_HIP_TRY(launch_leapfrog_mapped_blocked(rc, rp, pair[j][0], pair[j][1], out, g, mc, dt2, c_dev, k0, ns,
+                                                      stream));
+            rc = pair[j][0];
+            rp = pair[j][1];
+        }
+    } else if (mapped && !implicit) {
         {
             ProfScope ps(this, EW_K_LEAPFROG, 0, 56.0 * (double)N);
             EW_HIP_TRY(launch_leapfrog_mapped(v, nullptr, wA, out, g, mc, dt2, c[0], c[1], 1, stream));
