@@ -4,14 +4,15 @@
 //
 // On a grid of some 65k points one step moves under 5 MB, less than a launch
 // costs, so the per-step kernel runs at the launch rate.  Here a workgroup
-// stages a region of kRX x kRY points (its kTX x kTY output tile and a halo of
-// kSteps points on each side) of both states and of the four coefficient
-// arrays in LDS, then advances up to kSteps steps there: after step s only the
-// points at least s + 1 from the region's edge are current, and after the
-// last step the output tile still is.  The filter sum of the tile's points is
-// kept in registers.  Every point update is the per-step kernel's expression
-// on the same values, so the result is the same.  Tiles overlap in their
-// halos, so a launch reads one pair of state arrays and writes the other.
+// loads a region of kRX x kRY points (its kTX x kTY output tile and a halo of
+// kSteps points on each side), then advances up to kSteps steps on it: after
+// step s only the points at least s + 1 from the region's edge are current,
+// and after the last step the output tile still is.  The current state is
+// shared through LDS; each point's previous state, coefficients and (in the
+// output tile) filter sum stay in its thread's registers.  Every point update
+// is the per-step kernel's expression on the same values, so the result is
+// the same.  Tiles overlap in their halos, so a launch reads one pair of
+// state arrays and writes the other.
 #include <algorithm>
 
 #include "op.h"
@@ -26,105 +27,146 @@ constexpr int kTY = 16;
 constexpr int kSteps = 8;   // steps per launch and halo width
 constexpr int kRX = kTX + 2 * kSteps;
 constexpr int kRY = kTY + 2 * kSteps;
-constexpr int kThreads = 256;
-constexpr int kPts = kRX * kRY / kThreads;  // region points per thread
-static_assert(kRX * kRY % kThreads == 0, "region points split evenly over the threads");
+// Consecutive rows of one column per thread.  A step is bound by latency
+// (LDS reads, a chain of FP64 operations and the barrier), not by LDS or
+// arithmetic throughput, so more wavefronts per CU hide more of it: on a
+// 255^2 annulus (191 steps) a wave-solve took 0.246, 0.204 and 0.187 ms
+// with strips of 4, 2 and 1 rows (256, 512 and 1024 threads), and 0.202 ms
+// with 16 steps per launch and strips of 3.
+constexpr int kStrip = 1;
+constexpr int kThreads = kRX * kRY / kStrip;
+static_assert(kRY % kStrip == 0, "threads cover the region in strips");
 
-// Grids up to this many points take the blocked kernel; above it the
-// per-step kernel streams at most of the HBM rate.
+// Grids up to this many points take the blocked kernel; larger ones keep the
+// per-step kernel, whose launches are long enough to stream near the HBM rate.
 constexpr int64_t kMaxBlockedPoints = int64_t(1) << 18;
 
 // Steps k0 .. k0 + ns - 1 (1 <= ns <= kSteps), step k making W^{k+1} from
 // W^k = wcur and W^{k-1} = wprev and adding cfil[k + 1] W^{k+1} to acc (with
 // FIRST, k0 = 0: W^1 from W^0 alone, acc = cfil[0] W^0 + cfil[1] W^1).
 // Writes W^{k0+ns} to dcur and W^{k0+ns-1} to dprev.
+//
+// Each thread owns a strip of kStrip rows of one region column and keeps
+// their previous states and their nine coefficients in registers; a step
+// reads from LDS only the two side columns beside the strip and the points
+// just below and above it, and writes the strip's new values for the
+// neighbours.
 template <bool FIRST>
 __global__ __launch_bounds__(kThreads) void k_leapfrog_mapped_blocked(
     const double* __restrict__ wcur, const double* __restrict__ wprev, double* __restrict__ dcur,
     double* __restrict__ dprev, double* __restrict__ acc, Geo g, MapCoef m, double dt2,
     const double* __restrict__ cfil, int k0, int ns) {
-    __shared__ double sU[2][kRX * kRY];        // the two states, swapped each step
-    __shared__ double sW[(kRX + 1) * kRY];     // A11 / dr^2 at half points x - 1/2 .. x + kRX - 1/2
-    __shared__ double sS[kRX * (kRY + 1)];     // A22 / ds^2 at half points y - 1/2 .. y + kRY - 1/2
-    __shared__ double sB[kRX * kRY];           // J a^12 / (4 dr ds), 0 beyond the walls
-    __shared__ double sJ[kRX * kRY];           // 1 / J
+    __shared__ double sU[2][kRX * kRY];  // the current state, double-buffered across a step
+    __shared__ double sC[kSteps + 1];    // the launch's filter weights cfil[k0 .. k0 + ns]
     const int nx = g.nx, ny = g.ny;
     const int ox = (int)blockIdx.x * kTX - kSteps;  // grid coordinates of region point (0, 0)
     const int oy = (int)blockIdx.y * kTY - kSteps;
     const int t = threadIdx.x;
+    const int x = t % kRX;
+    const int y0 = (t / kRX) * kStrip;  // first row of the strip
+    const int gx = ox + x;
 
-    int depth[kPts];     // distance to the region's edge, -1 beyond the walls
-    double fsum[kPts];   // filter sum of an output point
+    if (t <= ns) sC[t] = cfil[k0 + t];  // read once, ahead of the step chain
+    int depth[kStrip];   // distance to the region's edge, -1 beyond the walls
+    double cur[kStrip], prv[kStrip], fsum[kStrip];
+    // the strip's coefficients, as the per-step kernel reads them (used only
+    // at points that are ever updated, which lie inside the grid)
+    double kw[kStrip], ke[kStrip], ks[kStrip], kn[kStrip];
+    double bw[kStrip], be[kStrip], bs[kStrip], bn[kStrip], kj[kStrip];
 #pragma unroll
-    for (int q = 0; q < kPts; ++q) {
-        const int p = t + q * kThreads;
-        const int x = p % kRX, y = p / kRX;
-        const int gx = ox + x, gy = oy + y;
+    for (int q = 0; q < kStrip; ++q) {
+        const int y = y0 + q, p = y * kRX + x;
+        const int gy = oy + y;
         const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
         const int d = std::min(std::min(x, kRX - 1 - x), std::min(y, kRY - 1 - y));
         const int64_t c = (int64_t)gy * nx + gx;
-        sU[0][p] = in ? wcur[c] : 0.0;
-        sU[1][p] = (!FIRST && in) ? wprev[c] : 0.0;
-        sB[p] = in ? m.cb[c] : 0.0;
-        sJ[p] = in ? m.ij[c] : 0.0;
+        const int64_t hw = (int64_t)gy * (nx + 1) + gx;  // half point gx - 1/2
+        cur[q] = in ? wcur[c] : 0.0;
+        prv[q] = (!FIRST && in) ? wprev[c] : 0.0;
+        sU[0][p] = cur[q];
+        sU[1][p] = 0.0;  // beyond the walls both buffers must read 0
         depth[q] = in ? d : -1;
         fsum[q] = (!FIRST && in && d >= kSteps) ? acc[c] : 0.0;
-    }
-    for (int p = t; p < (kRX + 1) * kRY; p += kThreads) {
-        const int x = p % (kRX + 1), y = p / (kRX + 1);
-        const int gx = ox + x, gy = oy + y;
-        sW[p] = (gx >= 0 && gx <= nx && gy >= 0 && gy < ny) ? m.cw[(int64_t)gy * (nx + 1) + gx] : 0.0;
-    }
-    for (int p = t; p < kRX * (kRY + 1); p += kThreads) {
-        const int x = p % kRX, y = p / kRX;
-        const int gx = ox + x, gy = oy + y;
-        sS[p] = (gx >= 0 && gx < nx && gy >= 0 && gy <= ny) ? m.cs[(int64_t)gy * nx + gx] : 0.0;
+        kw[q] = in ? m.cw[hw] : 0.0;
+        ke[q] = in ? m.cw[hw + 1] : 0.0;
+        ks[q] = in ? m.cs[c] : 0.0;
+        kn[q] = in ? m.cs[c + nx] : 0.0;
+        bw[q] = in && gx > 0 ? m.cb[c - 1] : 0.0;
+        be[q] = in && gx < nx - 1 ? m.cb[c + 1] : 0.0;
+        bs[q] = in && gy > 0 ? m.cb[c - nx] : 0.0;
+        bn[q] = in && gy < ny - 1 ? m.cb[c + nx] : 0.0;
+        kj[q] = in ? m.ij[c] : 0.0;
     }
     __syncthreads();
 
-    int a = 0;  // sU[a] holds W^k, sU[a ^ 1] W^{k-1}
-    for (int s = 0; s < ns; ++s) {
-        const double* u = sU[a];
-        double* un = sU[a ^ 1];
-        const double cnext = cfil[k0 + s + 1];
 #pragma unroll
-        for (int q = 0; q < kPts; ++q) {
-            if (depth[q] <= s) continue;  // not current after this step (or beyond a wall)
-            const int p = t + q * kThreads;
-            const int x = p % kRX, y = p / kRX;
-            // L_h u as the per-step kernel forms it; values beyond the walls are 0
-            const double uc = u[p];
-            const double uW = u[p - 1], uE = u[p + 1], uS = u[p - kRX], uN = u[p + kRX];
-            const double uSW = u[p - kRX - 1], uSE = u[p - kRX + 1];
-            const double uNW = u[p + kRX - 1], uNE = u[p + kRX + 1];
-            const int hw = y * (kRX + 1) + x;
-            double tt = sW[hw + 1] * (uE - uc) - sW[hw] * (uc - uW);
-            tt += sS[p + kRX] * (uN - uc) - sS[p] * (uc - uS);
-            const double bE = sB[p + 1], bW = sB[p - 1], bN = sB[p + kRX], bS = sB[p - kRX];
-            tt += bE * (uNE - uSE) - bW * (uNW - uSW);
-            tt += bN * (uNE - uNW) - bS * (uSE - uSW);
-            const double lap = sJ[p] * tt;
-            double wn;
-            if (FIRST && s == 0) {
-                wn = uc + (0.5 * dt2) * lap;
-                fsum[q] = cfil[0] * uc + cnext * wn;
-            } else {
-                wn = 2.0 * uc - un[p] + dt2 * lap;
-                fsum[q] = fsum[q] + cnext * wn;
-            }
-            un[p] = wn;  // only this thread reads un[p] in this step
+    for (int s = 0; s < kSteps; ++s) {
+        if (s >= ns) break;
+        const double* u = sU[s & 1];  // W^{k0+s}
+        double* un = sU[(s & 1) ^ 1];
+        const double cnext = sC[s + 1];
+        bool act[kStrip];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q) {
+            act[q] = depth[q] > s;  // current after this step (never beyond a wall)
+            any = any || act[q];
         }
-        a ^= 1;
+        if (any) {
+            // an updated point has 1 <= x <= kRX - 2; rows y0 - 1 .. y0 + kStrip
+            // outside the region are never a neighbour of one
+            double lc[kStrip + 2], rc[kStrip + 2];
+#pragma unroll
+            for (int r = 0; r < kStrip + 2; ++r) {
+                const int y = y0 - 1 + r;
+                const bool ok = y >= 0 && y < kRY;
+                lc[r] = ok ? u[y * kRX + x - 1] : 0.0;
+                rc[r] = ok ? u[y * kRX + x + 1] : 0.0;
+            }
+            const double below = y0 >= 1 ? u[(y0 - 1) * kRX + x] : 0.0;
+            const double above = y0 + kStrip < kRY ? u[(y0 + kStrip) * kRX + x] : 0.0;
+            double nxt[kStrip], nfs[kStrip];
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) {
+                // L_h u as the per-step kernel forms it; values beyond the walls are 0
+                const double uc = cur[q];
+                const double uS = q > 0 ? cur[q - 1] : below;
+                const double uN = q < kStrip - 1 ? cur[q + 1] : above;
+                const double uW = lc[q + 1], uE = rc[q + 1];
+                const double uSW = lc[q], uSE = rc[q], uNW = lc[q + 2], uNE = rc[q + 2];
+                double tt = ke[q] * (uE - uc) - kw[q] * (uc - uW);
+                tt += kn[q] * (uN - uc) - ks[q] * (uc - uS);
+                tt += be[q] * (uNE - uSE) - bw[q] * (uNW - uSW);
+                tt += bn[q] * (uNE - uNW) - bs[q] * (uSE - uSW);
+                const double lap = kj[q] * tt;
+                double wn;
+                if (FIRST && s == 0) {
+                    wn = uc + (0.5 * dt2) * lap;
+                    nfs[q] = sC[0] * uc + cnext * wn;
+                } else {
+                    wn = 2.0 * uc - prv[q] + dt2 * lap;
+                    nfs[q] = fsum[q] + cnext * wn;
+                }
+                nxt[q] = wn;
+            }
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) {
+                if (!act[q]) continue;
+                fsum[q] = nfs[q];
+                prv[q] = cur[q];
+                cur[q] = nxt[q];
+                un[(y0 + q) * kRX + x] = nxt[q];
+            }
+        }
         __syncthreads();
     }
 
 #pragma unroll
-    for (int q = 0; q < kPts; ++q) {
+    for (int q = 0; q < kStrip; ++q) {
         if (depth[q] < kSteps) continue;
-        const int p = t + q * kThreads;
-        const int64_t c = (int64_t)(oy + p / kRX) * nx + (ox + p % kRX);
-        dcur[c] = sU[a][p];
-        dprev[c] = sU[a ^ 1][p];
+        const int64_t c = (int64_t)(oy + y0 + q) * nx + gx;
+        dcur[c] = cur[q];
+        dprev[c] = prv[q];
         acc[c] = fsum[q];
     }
 }
