@@ -172,16 +172,13 @@ struct MapCoef {
     const double* gw;
 };
 hipError_t launch_laplacian_mapped(const double* u, double* out, const Geo& g, const MapCoef& m, hipStream_t s);
-// The explicit leapfrog step of launch_leapfrog with the mapped operator.
-hipError_t launch_leapfrog_mapped(const double* wcur, const double* wprev, double* wnext, double* acc, const Geo& g,
-                                  const MapCoef& m, double dt2, double ccur, double cnext, int first, hipStream_t s);
-// Small mapped grids (mapped_steps_blocked(g)): steps k0 .. k0 + ns - 1 of
-// that wave-solve in one launch, 1 <= ns <= mapped_steps_per_launch(); reads
+// Explicit leapfrog steps with the mapped operator fused with the filter
+// accumulation, as launch_leapfrog: steps k0 .. k0 + ns - 1 of a wave-solve
+// in one launch, 1 <= ns <= mapped_steps_per_launch(); reads
 // W^{k0} (wcur) and W^{k0-1} (wprev, null for k0 = 0, when the first step's
 // rule applies), writes W^{k0+ns} to dcur and W^{k0+ns-1} to dprev (neither
 // may alias wcur or wprev) and accumulates cfil_dev[k + 1] W^{k+1} into acc
 // (set to cfil_dev[0] W^0 + cfil_dev[1] W^1 when k0 = 0).
-bool mapped_steps_blocked(const Geo& g);
 int mapped_steps_per_launch();
 hipError_t launch_leapfrog_mapped_blocked(const double* wcur, const double* wprev, double* dcur, double* dprev,
                                           double* acc, const Geo& g, const MapCoef& m, double dt2,

@@ -12,8 +12,8 @@
 //
 // The coefficients are built once on the host from the caller's coordinates
 // and kept on the device as four arrays (A11 / dr^2 at x half points, A22 /
-// ds^2 at y half points, B / (4 dr ds) and 1/J at the nodes): the leapfrog
-// step streams them with the three state arrays, 72 B per point-step.  The
+// ds^2 at y half points, B / (4 dr ds) and 1/J at the nodes).  The explicit
+// steps run several per launch in LDS-staged tiles (mapped_steps.hip).  The
 // implicit scheme solves M = I - (dt^2/2) L_h by multigrid whose coarse
 // levels carry the Galerkin product R M P of the level above as nine
 // weights per point (on a non-orthogonal grid it contracts the error about
@@ -61,28 +61,6 @@ __global__ __launch_bounds__(256) void k_laplacian_mapped(const double* __restri
     out[c] = lap_mapped(u, c, i, j, g, m);
 }
 
-// Leapfrog step fused with the filter accumulation (eqs. explicitStep1,
-// explicitScheme, filterQuadrature), as k_leapfrog.
-template <bool FIRST>
-__global__ __launch_bounds__(256) void k_leapfrog_mapped(const double* __restrict__ wcur, const double* wprev,
-                                                         double* wnext, double* __restrict__ acc, Geo g, MapCoef m,
-                                                         double dt2, double ccur, double cnext) {
-    int i, j, k;
-    if (!tile_coords(g, i, j, k)) return;
-    const int64_t c = lin(g, i, j, 0);
-    const double uc = wcur[c];
-    const double lap = lap_mapped(wcur, c, i, j, g, m);
-    double wn;
-    if (FIRST) {
-        wn = uc + (0.5 * dt2) * lap;
-        acc[c] = ccur * uc + cnext * wn;
-    } else {
-        wn = 2.0 * uc - wprev[c] + dt2 * lap;
-        acc[c] = acc[c] + cnext * wn;
-    }
-    wnext[c] = wn;
-}
-
 __global__ __launch_bounds__(256) void k_pointwise_mul(const double* in, const double* __restrict__ f, double* out,
                                                        int64_t n) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
@@ -91,14 +69,6 @@ __global__ __launch_bounds__(256) void k_pointwise_mul(const double* in, const d
 
 hipError_t launch_laplacian_mapped(const double* u, double* out, const Geo& g, const MapCoef& m, hipStream_t s) {
     k_laplacian_mapped<<<tile_grid(g), dim3(kTileX, kTileY, 1), 0, s>>>(u, out, g, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_leapfrog_mapped(const double* wcur, const double* wprev, double* wnext, double* acc, const Geo& g,
-                                  const MapCoef& m, double dt2, double ccur, double cnext, int first, hipStream_t s) {
-    const dim3 grid = tile_grid(g), block(kTileX, kTileY, 1);
-    if (first) k_leapfrog_mapped<true><<<grid, block, 0, s>>>(wcur, wprev, wnext, acc, g, m, dt2, ccur, cnext);
-    else k_leapfrog_mapped<false><<<grid, block, 0, s>>>(wcur, wprev, wnext, acc, g, m, dt2, ccur, cnext);
     return hipGetLastError();
 }
 

@@ -1,18 +1,21 @@
-// Explicit wave-solve on a small single curvilinear grid, several leapfrog
-// steps per launch (Sec. "Discrete approximations": eqs. explicitStep1,
+// Explicit wave-solve on a single curvilinear grid, several leapfrog steps
+// per launch (Sec. "Discrete approximations": eqs. explicitStep1,
 // explicitScheme and filterQuadrature with the order-2 mapped operator).
 //
-// On a grid of some 65k points one step moves under 5 MB, less than a launch
-// costs, so the per-step kernel runs at the launch rate.  Here a workgroup
-// loads a region of kRX x kRY points (its kTX x kTY output tile and a halo of
-// kSteps points on each side), then advances up to kSteps steps on it: after
-// step s only the points at least s + 1 from the region's edge are current,
-// and after the last step the output tile still is.  The current state is
-// shared through LDS; each point's previous state, coefficients and (in the
-// output tile) filter sum stay in its thread's registers.  Every point update
-// is the per-step kernel's expression on the same values, so the result is
-// the same.  Tiles overlap in their halos, so a launch reads one pair of
-// state arrays and writes the other.
+// One launch per step streams 72 B per point-step (two states, the filter
+// sum and four coefficient arrays) and, on small grids, costs more than the
+// data it moves.  Here a workgroup loads a region of kRX x kRY points (its
+// kTX x kTY output tile and a halo of kSteps points on each side), then
+// advances up to kSteps steps on it: after step s only the points at least
+// s + 1 from the region's edge are current, and after the last step the
+// output tile still is.  The current state is shared through LDS; each
+// point's previous state, coefficients and (in the output tile) filter sum
+// stay in its thread's registers.  Every point update is the per-step
+// expression on the same values, so the result does not depend on kSteps.
+// Tiles overlap in their halos, so a launch reads one pair of state arrays
+// and writes the other.  Against one launch per step (which streamed at 0.84
+// of the HBM peak on 2047^2) a wave-solve took 0.187 against 0.725 ms on
+// 255^2, 1.93 against 3.33 ms on 1023^2 and 14.2 against 22.3 ms on 2047^2.
 #include <algorithm>
 
 #include "op.h"
@@ -36,10 +39,6 @@ constexpr int kRY = kTY + 2 * kSteps;
 constexpr int kStrip = 1;
 constexpr int kThreads = kRX * kRY / kStrip;
 static_assert(kRY % kStrip == 0, "threads cover the region in strips");
-
-// Grids up to this many points take the blocked kernel; larger ones keep the
-// per-step kernel, whose launches are long enough to stream near the HBM rate.
-constexpr int64_t kMaxBlockedPoints = int64_t(1) << 18;
 
 // Steps k0 .. k0 + ns - 1 (1 <= ns <= kSteps), step k making W^{k+1} from
 // W^k = wcur and W^{k-1} = wprev and adding cfil[k + 1] W^{k+1} to acc (with
@@ -173,14 +172,12 @@ __global__ __launch_bounds__(kThreads) void k_leapfrog_mapped_blocked(
 
 }  // namespace
 
-bool mapped_steps_blocked(const Geo& g) { return g.dim == 2 && g.size() <= kMaxBlockedPoints; }
-
 int mapped_steps_per_launch() { return kSteps; }
 
 hipError_t launch_leapfrog_mapped_blocked(const double* wcur, const double* wprev, double* dcur, double* dprev,
                                           double* acc, const Geo& g, const MapCoef& m, double dt2,
                                           const double* cfil_dev, int k0, int ns, hipStream_t s) {
-    if (ns < 1 || ns > kSteps || k0 < 0 || (k0 == 0) != (wprev == nullptr) || !mapped_steps_blocked(g))
+    if (ns < 1 || ns > kSteps || k0 < 0 || (k0 == 0) != (wprev == nullptr) || g.dim != 2)
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)((g.nx + kTX - 1) / kTX), (unsigned)((g.ny + kTY - 1) / kTY), 1);
     if (k0 == 0)

@@ -353,7 +353,7 @@ ew_status Op::guess_rel_res(const double* b, double bscale, const double* x, dou
 
 ew_status Op::apply_filter(const double* v, double* out) {
     const double dt2 = dt * dt;
-    if (mapped && !implicit && mapped_steps_blocked(g)) {
+    if (mapped && !implicit) {
         // several steps per launch; launches alternate between two state pairs
         if (!wC) {
             EW_TRY(alloc((void**)&wC, N * sizeof(double)));
@@ -370,20 +370,6 @@ ew_status Op::apply_filter(const double* v, double* out) {
                                                       stream));
             rc = pair[j][0];
             rp = pair[j][1];
-        }
-    } else if (mapped && !implicit) {
-        {
-            ProfScope ps(this, EW_K_LEAPFROG, 0, 56.0 * (double)N);
-            EW_HIP_TRY(launch_leapfrog_mapped(v, nullptr, wA, out, g, mc, dt2, c[0], c[1], 1, stream));
-        }
-        const double* prev = v;
-        double* cur = wA;
-        for (int k = 1; k < n_t; ++k) {
-            double* next = (prev == v) ? wB : const_cast<double*>(prev);
-            ProfScope ps(this, EW_K_LEAPFROG, 0, 72.0 * (double)N);
-            EW_HIP_TRY(launch_leapfrog_mapped(cur, prev, next, out, g, mc, dt2, 0.0, c[k + 1], 0, stream));
-            prev = cur;
-            cur = next;
         }
     } else if (!implicit && (mixed ? wave_small_fits<float>(g) : wave_small_fits<double>(g))) {
         ProfScope ps(this, EW_K_LEAPFROG, 0, 16.0 * (double)N);
