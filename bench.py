@@ -453,10 +453,10 @@ def mapped_form():
     """A single curvilinear grid beside the box: one explicit wave-solve on a
     2047^2 grid mapped by the smooth non-orthogonal skew map (order 2,
     omega 60, CFL 0.9) against the 2047^2 unit square with the same settings,
-    the leapfrog kernels timed with hipEvents (the box one step per launch,
-    the mapped one 8 steps per launch; one step of the mapped operator, as
-    one launch would stream it, moves 72 B per point: the state as in the
-    box kernel plus four coefficient arrays); and an eigensolve on a 255^2
+    the leapfrog kernels timed with hipEvents (8 steps per launch on both;
+    one step as one launch would stream it moves 40 B per point on the box
+    and 72 B on the mapped grid, the state plus four coefficient arrays);
+    and an eigensolve on a 255^2
     quarter annulus (radii 0.5 to 1, omega 40, k = 8, m = 20)."""
     import torch
     import synthetic
@@ -485,20 +485,15 @@ def mapped_form():
         prof = op.profile_end()
         avg = prof["total_ms"] / max(1, prof["launches"])
         gbs = prof["bytes_alg"] / max(1, prof["launches"]) / (avg * 1e-3) / 1e9
-        res = {"n_t": op.n_t, "pt_updates_per_s": st["pt_updates"] / dt, "ms_per_wave_solve": dt / 2 * 1e3}
-        if label == "box":
-            # one launch per step: bytes moved per launch over its duration
-            res.update({"leapfrog_avg_us": round(avg * 1e3, 3), "leapfrog_GBs": round(gbs, 1),
-                        "leapfrog_frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
-        else:
-            # several steps per launch: the per-step form's 72 B per point-step
-            # over the time per step exceeds what HBM could stream, since the
-            # blocked kernel reads each point once per launch
-            res.update({"steps_per_launch": round(op.n_t / max(1, prof["launches"]), 2),
-                        "launch_avg_us": round(avg * 1e3, 3),
-                        "us_per_step": round(prof["total_ms"] * 1e3 / op.n_t, 3),
-                        "per_step_form_GBs": round(gbs, 1)})
-        out[label] = res
+        # several steps per launch: the bytes one launch per step would move
+        # (40 B per point-step on the box, 72 B on the mapped grid) over the
+        # time per step can exceed what HBM streams, since the blocked kernels
+        # read each point once per launch
+        out[label] = {"n_t": op.n_t, "pt_updates_per_s": st["pt_updates"] / dt, "ms_per_wave_solve": dt / 2 * 1e3,
+                      "steps_per_launch": round(op.n_t / max(1, prof["launches"]), 2),
+                      "launch_avg_us": round(avg * 1e3, 3),
+                      "us_per_step": round(prof["total_ms"] * 1e3 / op.n_t, 3),
+                      "per_step_form_GBs": round(gbs, 1)}
         log(f"mapped form: {label}: n_t {op.n_t}, {dt / 2 * 1e3:.1f} ms per wave-solve, {prof['launches']} launches "
             f"of {avg * 1e3:.1f} us")
         op.close()

@@ -183,6 +183,12 @@ int mapped_steps_per_launch();
 hipError_t launch_leapfrog_mapped_blocked(const double* wcur, const double* wprev, double* dcur, double* dprev,
                                           double* acc, const Geo& g, const MapCoef& m, double dt2,
                                           const double* cfil_dev, int k0, int ns, hipStream_t s);
+// The same for a 2D box in FP64 (orders 2 and 4, any walls): steps k0 ..
+// k0 + ns - 1 in one launch, 1 <= ns <= box_steps_per_launch(order).
+int box_steps_per_launch(int order);
+hipError_t launch_leapfrog_box_blocked(const double* wcur, const double* wprev, double* dcur, double* dprev,
+                                       double* acc, const Geo& g, int order, double dt2, const double* cfil_dev,
+                                       int k0, int ns, hipStream_t s);
 // out = in * f elementwise (in and out may alias).
 hipError_t launch_pointwise_mul(const double* in, const double* f, double* out, int64_t n, hipStream_t s);
 // Multigrid for M = I - a L_h on a mapped level: out-of-place red-black

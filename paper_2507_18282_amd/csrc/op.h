@@ -100,7 +100,7 @@ struct Op {
     // workspace
     double* wA = nullptr;
     double* wB = nullptr;
-    double* wC = nullptr;  // second state pair of the mapped explicit steps (allocated at first use)
+    double* wC = nullptr;  // second state pair of the blocked explicit steps (allocated at first use)
     double* wD = nullptr;
     double* sbuf = nullptr;
     float* f0 = nullptr;

@@ -375,6 +375,24 @@ ew_status Op::apply_filter(const double* v, double* out) {
         ProfScope ps(this, EW_K_LEAPFROG, 0, 16.0 * (double)N);
         EW_HIP_TRY(mixed ? launch_wave_small<float>(v, out, g, order, dt2, c_dev, n_t, stream)
                          : launch_wave_small<double>(v, out, g, order, dt2, c_dev, n_t, stream));
+    } else if (!implicit && !mixed && g.dim == 2) {
+        // several steps per launch, as on mapped grids
+        if (!wC) {
+            EW_TRY(alloc((void**)&wC, N * sizeof(double)));
+            EW_TRY(alloc((void**)&wD, N * sizeof(double)));
+        }
+        double* pair[2][2] = {{wA, wB}, {wC, wD}};
+        const double* rc = v;
+        const double* rp = nullptr;
+        const int per = box_steps_per_launch(order);
+        for (int k0 = 0, j = 0; k0 < n_t; k0 += per, j ^= 1) {
+            const int ns = std::min(per, n_t - k0);
+            ProfScope ps(this, EW_K_LEAPFROG, 0, ((k0 == 0 ? 24.0 : 40.0) + 40.0 * (ns - 1)) * (double)N);
+            EW_HIP_TRY(launch_leapfrog_box_blocked(rc, rp, pair[j][0], pair[j][1], out, g, order, dt2, c_dev, k0, ns,
+                                                   stream));
+            rc = pair[j][0];
+            rp = pair[j][1];
+        }
     } else if (!implicit && !mixed) {
         {
             ProfScope ps(this, EW_K_LEAPFROG, 0, 24.0 * (double)N);

@@ -78,6 +78,32 @@ def test_explicit_filter_matches_oracle(P):
     assert rel_err(got, want) < 1e-11
 
 
+BLOCKED_CASES = [
+    # 2D FP64 boxes above the single-workgroup wave-solve advance 8 / R steps
+    # per launch (R the stencil radius) in 16 x 16 tiles with 8-point halos;
+    # ragged tiles both ways and step counts that leave a shorter last launch
+    synthetic.Problem(n=(211, 150), length=(1.0, 0.8), order=2, omega=12.0, ts="explicit", cfl=0.5),
+    synthetic.Problem(n=(150, 97), length=(1.1, 0.7), order=4, omega=11.0, ts="explicit", cfl=0.9,
+                      filter_const="quarter"),
+]
+
+
+@pytest.mark.parametrize("P", BLOCKED_CASES, ids=lambda P: f"{P.n}-o{P.order}")
+def test_explicit_blocked_steps_match_oracle(P):
+    op = make_op(P)
+    h, plan = oracle_plan(P)
+    v = synthetic.uniform_pm1(12, P.n_active)
+    say("explicit blocked filter", P.n, P.order, plan.n_t)
+    op.profile_begin("leapfrog")
+    got = to_host(op.apply_filter(to_dev(v)))
+    prof = op.profile_end()
+    per = 8 // (P.order // 2)
+    assert prof["launches"] == -(-plan.n_t // per)
+    assert rel_err(got, oracle_S(P, v)) < 1e-11
+    # a second wave-solve reuses the operator's state buffers
+    assert np.array_equal(got, to_host(op.apply_filter(to_dev(v))))
+
+
 def test_explicit_filter_on_sine_mode_is_beta_d():
     """S phi = beta~_d phi on the GPU (closed form of the discrete filter)."""
     P = synthetic.config_small_explicit()

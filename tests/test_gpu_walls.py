@@ -24,8 +24,9 @@ CASES = [
     ((40, 30), (1.0, 0.8), (("N", "D"), ("D", "N")), 2, 12.0, 0.5),      # one workgroup (k_wave_small)
     ((40, 30), (1.0, 0.8), (("N", "N"), ("D", "D")), 4, 12.0, 0.5),
     ((64, 48), (1.0, 0.7), (("D", "D"), ("N", "D")), 4, 15.0, 0.7),      # symmetry plane at y = 0
-    ((100, 90), (1.0, 0.9), (("N", "N"), ("N", "D")), 2, 10.0, 0.5),    # tiled leapfrog
+    ((100, 90), (1.0, 0.9), (("N", "N"), ("N", "D")), 2, 10.0, 0.5),    # several steps per launch
     ((100, 90), (1.0, 0.9), (("D", "N"), ("N", "N")), 4, 10.0, 0.5),
+    ((150, 70), (1.2, 0.6), (("N", "N"), ("N", "N")), 4, 11.0, 0.9),    # ragged tiles, Neumann all round
     ((13, 11, 9), (1.0, 0.9, 1.1), (("N", "D"), ("D", "D"), ("D", "N")), 2, 8.0, 0.5),
     ((13, 11, 9), (1.0, 0.9, 1.1), (("N", "N"), ("N", "D"), ("N", "N")), 4, 8.0, 0.5),
 ]
