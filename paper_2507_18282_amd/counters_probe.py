@@ -2,7 +2,8 @@
 (the calibration for FETCH_SIZE / WRITE_SIZE) followed by wave-solves of the
 headline implicit workload (2047^2 interior, order 4, FP64 multigrid), or
 with ``--workload mapped`` explicit wave-solves on the 2047^2 skew-mapped
-grid (order 2, omega 60, CFL 0.9), or with ``--workload mapped-implicit``
+grid (order 2, omega 60, CFL 0.9), or with ``--workload box-explicit`` the
+same on the 2047^2 unit square, or with ``--workload mapped-implicit``
 one implicit wave-solve there (omega 60 adjusted, 10 steps, multigrid to
 1e-10).  Further workloads for kernel traces:
 
@@ -32,7 +33,8 @@ COPY_BYTES = 256 * 1024 * 1024
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--wave-solves", type=int, default=1)
-    ap.add_argument("--workload", choices=("headline", "mapped", "mapped-implicit", "cube", "batch", "cnn"),
+    ap.add_argument("--workload", choices=("headline", "mapped", "box-explicit", "mapped-implicit", "cube", "batch",
+                                                "cnn"),
                     default="headline")
     a = ap.parse_args(argv)
     import torch
@@ -48,10 +50,12 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         print("counters probe done", flush=True)
         return 0
-    if a.workload in ("mapped", "mapped-implicit"):
+    if a.workload in ("mapped", "box-explicit", "mapped-implicit"):
         n = (2047, 2047)
         xy = synthetic.mapped_coords("skew", *n, eps=0.15)
-        if a.workload == "mapped":
+        if a.workload == "box-explicit":
+            op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="explicit", cfl=0.9)
+        elif a.workload == "mapped":
             op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="explicit", cfl=0.9, coords=xy)
         else:
             op = Operator(n=n, length=(1.0, 1.0), order=2, omega=60.0, ts="implicit", n_its=10, adjust_omega=True,
