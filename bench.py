@@ -223,7 +223,8 @@ def _batch_run(Ps, precision: str, tol_ritz: float, tol_res: float, budget: int)
     return {"state": "FP64" if precision == "fp64" else "FP32", "tol_ritz": tol_ritz, "eig_res_tol": tol_res,
             "batched": {"eigenpairs_per_s": nb / tb, "pairs": nb, "seconds": tb, "wave_solves": st["wave_solves"],
                         "pt_updates_per_s": st["pt_updates"] / tb, "small_problems": info["n_small"],
-                        "step_rows_per_thread": info["step_rows_per_thread"], "tune_us": info["tune_us"]},
+                        "step_rows_per_thread": info["step_rows_per_thread"], "tune_us": info["tune_us"],
+                        "steps_per_launch": info["steps_per_launch"]},
             "plain": {"eigenpairs_per_s": npl / tp, "pairs": npl, "seconds": tp, "wave_solves": wsp,
                       "pt_updates_per_s": ptp / tp},
             "speedup_eigenpairs_per_s": (nb / tb) / (npl / tp) if npl > 0 else None}

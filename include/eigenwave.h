@@ -437,12 +437,13 @@ ew_status ew_choose_periods(const ew_grid_desc* grid, const ew_op_desc* desc, in
  * FP32 (precision EW_PREC_MIXED) or FP64 (EW_PREC_FP64), one precision and
  * one stencil order for all problems.  With FP32 state, problems with
  * nx, ny <= 128 run their whole wave-solve inside one workgroup and larger
- * ones advance one time step per batched launch; with FP64 state every problem
- * takes the batched step launches.  One batched wave-solve is a captured
- * hipGraph (a graph of ordinary launches, not a persistent kernel) replayed
- * on a private stream and joined to the caller's stream with events.  At
- * creation the tile height of the batched step kernel is chosen by timing the
- * candidates on the batch (ew_batch_info.tune_us).
+ * ones advance one time step per batched launch, whose tile height is chosen
+ * at creation by timing the candidates on the batch (ew_batch_info.tune_us);
+ * with FP64 state every problem advances 8 steps (order 2) or 4 (order 4)
+ * per batched launch, in tiles that overlap by the steps' reach.  One batched
+ * wave-solve is a captured hipGraph (a graph of ordinary launches, not a
+ * persistent kernel) replayed on a private stream and joined to the caller's
+ * stream with events.
  * ------------------------------------------------------------------------ */
 typedef struct ew_batch_s* ew_batch;
 
@@ -450,12 +451,13 @@ typedef struct {
     int nprob;
     int n_small;                 /* problems solved inside one workgroup */
     int n_large;                 /* problems advanced by the batched step kernel */
-    int max_steps_large;         /* step launches per batched wave-solve */
-    int step_rows_per_thread;    /* tile height chosen by the autotuner (rows = 4 x this) */
-    double tune_us[4];           /* measured time per step launch for 1, 2, 4, 8 rows per thread */
+    int max_steps_large;         /* longest N_t among the batched-launch problems */
+    int step_rows_per_thread;    /* FP32 state: tile height chosen by the autotuner (rows = 4 x this); FP64: 0 */
+    double tune_us[4];           /* FP32 state: time per step launch for 1, 2, 4, 8 rows per thread; FP64: 0 */
     int64_t total_steps;         /* sum of N_t over the problems */
     int64_t pt_updates_per_wave_solve;
     int state_fp64;              /* 1: FP64 time levels and accumulation; 0: FP32 */
+    int steps_per_launch;        /* time steps per batched launch: 1 with FP32 state, 8 / (order / 2) with FP64 */
 } ew_batch_info;
 
 /* grids[i], descs[i] describe problem i (same rules as ew_op_create, plus:

@@ -315,7 +315,7 @@ class Batch:
                      "step_rows_per_thread": info.step_rows_per_thread, "tune_us": list(info.tune_us),
                      "total_steps": int(info.total_steps),
                      "pt_updates_per_wave_solve": int(info.pt_updates_per_wave_solve),
-                     "state_fp64": bool(info.state_fp64)}
+                     "state_fp64": bool(info.state_fp64), "steps_per_launch": info.steps_per_launch}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

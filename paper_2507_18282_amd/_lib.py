@@ -72,7 +72,7 @@ KCLASS = {"leapfrog": 0, "smooth": 1, "restrict": 2, "prolong": 3, "resnorm": 4,
 class BatchInfo(ctypes.Structure):
     _fields_ = [("nprob", c_int), ("n_small", c_int), ("n_large", c_int), ("max_steps_large", c_int),
                 ("step_rows_per_thread", c_int), ("tune_us", c_double * 4), ("total_steps", c_int64),
-                ("pt_updates_per_wave_solve", c_int64), ("state_fp64", c_int)]
+                ("pt_updates_per_wave_solve", c_int64), ("state_fp64", c_int), ("steps_per_launch", c_int)]
 
 
 class CnnTrainDesc(ctypes.Structure):

@@ -25,8 +25,10 @@ struct BatchProbDev {
     const double* v;   // W^0 (FP64, caller's vector)
     double* out;       // S v (FP64)
     void* f0;          // W^0 in the state type
-    void* fA;          // odd time levels
-    void* fB;          // even time levels >= 2
+    void* fA;          // odd time levels (FP64 state: the latest level after an even launch)
+    void* fB;          // even time levels >= 2 (FP64 state: the level before it)
+    void* fC;          // FP64 state: the latest level after an odd launch
+    void* fD;          // FP64 state: the level before it
     void* acc;         // filter accumulator
 };
 
@@ -59,6 +61,17 @@ hipError_t prepare_batch_small(int order, size_t lds_bytes);
 // `step` are covered by the first nblocks workgroups).
 hipError_t launch_batch_step(BatchProbDev* probs, const BatchBlk* blk, int nblocks, const void* coef, int step,
                              int order, int tyr, int fp64, hipStream_t s);
+// FP64 state: steps L S .. L S + S - 1 of every problem in launch L (S =
+// batch_steps_per_launch(order); a problem with fewer steps left does those),
+// in 16 x 16 tiles with 8-point halos (batch_blocked_tiles per problem; blk
+// as for launch_batch_step, the first nblocks workgroups covering the
+// problems still stepping at step L S).  Launch 0 reads W^0 from f0; launch
+// L > 0 reads the two levels launch L - 1 wrote, and launch L writes its last
+// two levels to (fA, fB) for even L and to (fC, fD) for odd L.
+int batch_steps_per_launch(int order);
+int batch_blocked_tiles(const Geo& g);
+hipError_t launch_batch_blocked(BatchProbDev* probs, const BatchBlk* blk, int nblocks, const double* coef, int launch,
+                                int order, hipStream_t s);
 hipError_t launch_batch_convert(BatchProbDev* probs, const int* ids, const int* blk_start, int nseg, int nblocks,
                                 int to_fp32, hipStream_t s);
 hipError_t launch_batch_mgs(const BatchMgsDev* info, const MgsLink* links, int nprob, const int* blk_start,

@@ -6,10 +6,11 @@
 // problems run their whole wave-solve in one LDS-resident workgroup each
 // (k_batch_small, on a forked branch), while every large problem advances one
 // time step per k_batch_step launch (one launch per step index, blocks of
-// problems that are already done exit at once).  With FP64 state every
-// problem takes the step launches, reading the caller's v as W^0 and
-// accumulating straight into the caller's out.  The tile height of k_batch_step is chosen at
-// creation by timing the candidates on the batch itself.  The Arnoldi process
+// problems that are already done exit at once); the tile height of
+// k_batch_step is chosen at creation by timing the candidates on the batch
+// itself.  With FP64 state every problem advances 8 / R steps per
+// k_batch_blocked launch (R the stencil's radius), reading the caller's v as
+// W^0 and accumulating straight into the caller's out.  The Arnoldi process
 // of every problem advances in lock-step: one batched wave-solve, then one
 // batched chain of modified Gram-Schmidt links, then the small host-side
 // Krylov-Schur bookkeeping of each problem.
@@ -34,6 +35,8 @@ struct BProb {
     void* f0 = nullptr;  // FP32 state only (FP64 state reads v and writes out)
     void* fA = nullptr;
     void* fB = nullptr;
+    void* fC = nullptr;  // FP64 state only: the second pair of time levels
+    void* fD = nullptr;
     void* acc = nullptr;
 };
 
@@ -60,6 +63,11 @@ struct ew_batch_s {
     // Large problems are ordered by N_t, longest first, so the problems that
     // still step at step index s are a prefix: step_nblk[s] blocks cover them.
     std::vector<int> step_nblk;
+    // FP64 state: several steps per launch in 16 x 16 tiles, problems in the
+    // same order; blk_nblk[L] blocks cover the problems stepping in launch L
+    ew::BatchBlk* blk_tab_dev = nullptr;
+    std::vector<int> blk_nblk;
+    int steps_per_launch = 1;
     size_t small_lds = 0;
     double tune_us[4] = {0, 0, 0, 0};
     hipGraph_t graph = nullptr;
@@ -100,6 +108,31 @@ static ew_status build_step_table(ew_batch b, int tyr) {
     return EW_OK;
 }
 
+// FP64 state: (problem, tile) of every k_batch_blocked workgroup, the
+// problems in the order of large_ids (longest N_t first), and the blocks that
+// cover the problems still stepping in each launch.
+static ew_status build_blocked_table(ew_batch b) {
+    b->steps_per_launch = batch_steps_per_launch(b->order);
+    const int spl = b->steps_per_launch;
+    std::vector<int> starts(b->large_ids.size() + 1, 0);
+    for (size_t s = 0; s < b->large_ids.size(); ++s)
+        starts[s + 1] = starts[s] + batch_blocked_tiles(b->P[b->large_ids[s]].g);
+    std::vector<BatchBlk> tab(starts.back());
+    for (size_t s = 0; s < b->large_ids.size(); ++s)
+        for (int t = starts[s]; t < starts[s + 1]; ++t) tab[t] = {b->large_ids[s], t - starts[s]};
+    const int nlaunch = (b->max_nt_large + spl - 1) / spl;
+    b->blk_nblk.assign(nlaunch, 0);
+    size_t cnt = b->large_ids.size();
+    for (int l = 0; l < nlaunch; ++l) {  // cnt: problems with N_t > l spl
+        while (cnt > 0 && b->P[b->large_ids[cnt - 1]].tp.n_t <= l * spl) --cnt;
+        b->blk_nblk[l] = starts[cnt];
+    }
+    EW_TRY(balloc(b, (void**)&b->blk_tab_dev, (tab.size() + 1) * sizeof(BatchBlk)));
+    if (!tab.empty())
+        EW_HIP_TRY(hipMemcpy(b->blk_tab_dev, tab.data(), tab.size() * sizeof(BatchBlk), hipMemcpyHostToDevice));
+    return EW_OK;
+}
+
 // One batched wave-solve as a graph on b->stream.
 static ew_status capture_graph(ew_batch b) {
     hipStream_t s = b->stream;
@@ -116,9 +149,15 @@ static ew_status capture_graph(ew_batch b) {
                                    b->small_lds, b->side);
         if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
     }
-    for (int step = 0; e == hipSuccess && step < b->max_nt_large; ++step)
-        e = launch_batch_step(b->probs_dev, b->step_tab_dev, b->step_nblk[step], b->coef_dev, step, b->order, b->tyr,
-                              b->fp64, s);
+    if (b->fp64) {
+        for (int l = 0; e == hipSuccess && l < (int)b->blk_nblk.size(); ++l)
+            e = launch_batch_blocked(b->probs_dev, b->blk_tab_dev, b->blk_nblk[l],
+                                     static_cast<const double*>(b->coef_dev), l, b->order, s);
+    } else {
+        for (int step = 0; e == hipSuccess && step < b->max_nt_large; ++step)
+            e = launch_batch_step(b->probs_dev, b->step_tab_dev, b->step_nblk[step], b->coef_dev, step, b->order,
+                                  b->tyr, b->fp64, s);
+    }
     if (e == hipSuccess && nl > 0 && !b->fp64)
         e = launch_batch_convert(b->probs_dev, b->large_ids_dev, b->conv_blk_dev, nl, b->nblocks_conv, 0, s);
     if (e == hipSuccess && ns > 0) e = hipStreamWaitEvent(s, b->ev_join, 0);
@@ -132,32 +171,14 @@ static ew_status capture_graph(ew_batch b) {
 }
 
 // Time k_batch_step for every tile height on the batch itself (step index 1
-// on the zero-initialised buffers) and keep the fastest.  With FP64 state, W^0
-// and the accumulator (the caller's v and out in a solve) are zeroed buffers
-// of the problem's size that live only for the tuning.
+// on the zero-initialised FP32 buffers) and keep the fastest.  FP64 state
+// runs k_batch_blocked, which has no such choice.
 static ew_status autotune(ew_batch b) {
-    if (b->large_ids.empty()) return EW_OK;
-    std::vector<void*> tmp;
-    struct FreeTmp {
-        std::vector<void*>& t;
-        ~FreeTmp() {
-            for (void* p : t) dev_free(p);
-        }
-    } free_tmp{tmp};
+    if (b->large_ids.empty() || b->fp64) return EW_OK;
     for (int i = 0; i < b->nprob; ++i) {
         b->probs_host[i].active = b->P[i].small ? 0 : 1;
         b->probs_host[i].v = nullptr;
         b->probs_host[i].out = nullptr;
-        if (b->fp64) {
-            for (void** q : {&b->probs_host[i].f0, &b->probs_host[i].acc}) {
-                void* p = nullptr;
-                const hipError_t e = dev_alloc(&p, b->P[i].N * sizeof(double), b->stream);
-                if (e != hipSuccess) return fail(EW_ERR_OOM, std::string("batch tuning buffer: ") + hipGetErrorString(e));
-                tmp.push_back(p);
-                EW_HIP_TRY(launch_fill<double>(static_cast<double*>(p), b->P[i].N, 0.0, b->stream));
-                *q = p;
-            }
-        }
     }
     EW_HIP_TRY(hipMemcpy(b->probs_dev, b->probs_host, b->nprob * sizeof(BatchProbDev), hipMemcpyHostToDevice));
     const int cand[4] = {1, 2, 4, 8};
@@ -186,8 +207,7 @@ static ew_status autotune(ew_batch b) {
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    EW_HIP_TRY(hipStreamSynchronize(b->stream));  // before the tuning buffers are freed
-    for (int i = 0; i < b->nprob && b->fp64; ++i) b->probs_host[i].f0 = b->probs_host[i].acc = nullptr;
+    EW_HIP_TRY(hipStreamSynchronize(b->stream));
     return build_step_table(b, best_tyr);
 }
 
@@ -303,9 +323,7 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
             b->large_ids.push_back(i);
             b->max_nt_large = std::max(b->max_nt_large, p.tp.n_t);
             if (b->fp64) {
-                EW_TRY(balloc(b.get(), &p.fA, p.N * sizeof(double)));
-                EW_TRY(balloc(b.get(), &p.fB, p.N * sizeof(double)));
-                for (void* z : {p.fA, p.fB}) EW_HIP_TRY(launch_fill<double>(static_cast<double*>(z), p.N, 0.0, b->stream));
+                for (void** z : {&p.fA, &p.fB, &p.fC, &p.fD}) EW_TRY(balloc(b.get(), z, p.N * sizeof(double)));
             } else {
                 for (void** z : {&p.f0, &p.fA, &p.fB, &p.acc}) {
                     EW_TRY(balloc(b.get(), z, p.N * sizeof(float)));
@@ -315,6 +333,8 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
             d.f0 = p.f0;
             d.fA = p.fA;
             d.fB = p.fB;
+            d.fC = p.fC;
+            d.fD = p.fD;
             d.acc = p.acc;
         }
     }
@@ -336,6 +356,7 @@ extern "C" ew_status ew_batch_create(int nprob, const ew_grid_desc* grids, const
         EW_HIP_TRY(hipMemcpy(b->large_ids_dev, b->large_ids.data(), b->large_ids.size() * sizeof(int), hipMemcpyHostToDevice));
     EW_HIP_TRY(hipMemcpy(b->conv_blk_dev, conv_starts.data(), conv_starts.size() * sizeof(int), hipMemcpyHostToDevice));
     if (!b->small_ids.empty()) EW_HIP_TRY(prepare_batch_small(b->order, b->small_lds));
+    if (b->fp64) EW_TRY(build_blocked_table(b.get()));
     EW_HIP_TRY(hipStreamSynchronize(b->stream));
     EW_TRY(autotune(b.get()));
     EW_TRY(capture_graph(b.get()));
@@ -351,7 +372,7 @@ extern "C" ew_status ew_batch_get_info(ew_batch b, ew_batch_info* out) {
     out->n_small = (int)b->small_ids.size();
     out->n_large = (int)b->large_ids.size();
     out->max_steps_large = b->max_nt_large;
-    out->step_rows_per_thread = b->tyr;
+    out->step_rows_per_thread = b->fp64 ? 0 : b->tyr;
     for (int c = 0; c < 4; ++c) out->tune_us[c] = b->tune_us[c];
     int64_t steps = 0, pts = 0;
     for (const BProb& p : b->P) {
@@ -361,6 +382,7 @@ extern "C" ew_status ew_batch_get_info(ew_batch b, ew_batch_info* out) {
     out->total_steps = steps;
     out->pt_updates_per_wave_solve = pts;
     out->state_fp64 = b->fp64;
+    out->steps_per_launch = b->fp64 ? b->steps_per_launch : 1;
     return EW_OK;
 }
 

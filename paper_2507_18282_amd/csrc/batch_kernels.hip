@@ -154,6 +154,92 @@ __global__ __launch_bounds__(256) void k_batch_step(BatchProbDev* __restrict__ p
 }
 
 // --------------------------------------------------------------------------
+// FP64 state: several steps per launch.  A workgroup loads a 32 x 32 region
+// of one problem (its 16 x 16 output tile and an 8-point halo) and advances
+// up to 8 / R steps on it (R the stencil's radius): after step s only the
+// points at least R (s + 1) from the region's edge are current, and after the
+// last step the output tile still is.  The current level is shared through
+// LDS (two buffers; beyond the walls both read 0), each point's previous
+// level and filter sum stay in registers; every update is k_batch_step's
+// expression on the same values.
+// --------------------------------------------------------------------------
+constexpr int kBlkTile = 16;
+constexpr int kBlkHalo = 8;
+constexpr int kBlkSide = kBlkTile + 2 * kBlkHalo;
+constexpr int kBlkThreads = kBlkSide * kBlkSide;  // one region point per thread
+
+template <int ORDER>
+__global__ __launch_bounds__(kBlkThreads) void k_batch_blocked(BatchProbDev* __restrict__ probs,
+                                                               const BatchBlk* __restrict__ blk,
+                                                               const double* __restrict__ coef, int launch) {
+    constexpr int kR = ORDER / 2;
+    constexpr int kSteps = kBlkHalo / kR;
+    __shared__ double sU[2][kBlkThreads];
+    __shared__ double sC[kSteps + 1];  // the launch's filter weights
+    const BatchBlk bt = blk[blockIdx.x];
+    const BatchProbDev& P = probs[bt.prob];
+    const int k0 = launch * kSteps;
+    if (!P.active || k0 >= P.n_t) return;  // the whole workgroup, before any barrier
+    const int ns = min(kSteps, P.n_t - k0);
+    const Geo g = P.g;
+    const int nx = g.nx, ny = g.ny;
+    const int tiles_x = (nx + kBlkTile - 1) / kBlkTile;
+    const int t = threadIdx.x;
+    const int x = t % kBlkSide, y = t / kBlkSide;
+    const int gx = (bt.tile % tiles_x) * kBlkTile - kBlkHalo + x;
+    const int gy = (bt.tile / tiles_x) * kBlkTile - kBlkHalo + y;
+    const bool first = k0 == 0;
+    const bool odd = (launch & 1) != 0;
+    const double* wcur = static_cast<const double*>(first ? P.f0 : (odd ? P.fA : P.fC));
+    const double* wprev = static_cast<const double*>(odd ? P.fB : P.fD);
+    double* dcur = static_cast<double*>(odd ? P.fC : P.fA);
+    double* dprev = static_cast<double*>(odd ? P.fD : P.fB);
+    double* acc = static_cast<double*>(P.acc);
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const int depth = min(min(x, kBlkSide - 1 - x), min(y, kBlkSide - 1 - y));
+    const int64_t c = (int64_t)gy * nx + gx;
+    const int last = in ? depth / kR : 0;  // current after steps 0 .. last - 1
+    double cur = in ? wcur[c] : 0.0;
+    double prv = (!first && in) ? wprev[c] : 0.0;
+    double fsum = (!first && in && depth >= kBlkHalo) ? acc[c] : 0.0;
+    sU[0][t] = cur;
+    sU[1][t] = 0.0;
+    if (t <= ns) sC[t] = coef[P.coef_off + k0 + t];
+    const double cx = axis_coef<double, ORDER>(g.ihx2), cy = axis_coef<double, ORDER>(g.ihy2);
+    const double dt2 = P.dt2;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+        if (s >= ns) break;
+        const double* u = sU[s & 1];
+        double* un = sU[(s & 1) ^ 1];
+        if (last > s) {
+            const double uc = cur;
+            double lap = d2_framed<double, ORDER>(u, t, 1, gx, nx, uc, 0) * cx;
+            lap += d2_framed<double, ORDER>(u, t, kBlkSide, gy, ny, uc, 0) * cy;
+            const double cn = sC[s + 1];
+            double wn;
+            if (first && s == 0) {
+                wn = uc + (0.5 * dt2) * lap;
+                fsum = sC[0] * uc + cn * wn;
+            } else {
+                wn = 2.0 * uc - prv + dt2 * lap;
+                fsum = fsum + cn * wn;
+            }
+            prv = cur;
+            cur = wn;
+            un[t] = wn;
+        }
+        __syncthreads();
+    }
+    if (in && depth >= kBlkHalo) {
+        dcur[c] = cur;
+        dprev[c] = prv;
+        acc[c] = fsum;
+    }
+}
+
+// --------------------------------------------------------------------------
 // FP64 <-> FP32 for the large problems (v -> f0 before the steps, acc -> out after).
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_batch_convert(BatchProbDev* __restrict__ probs, const int* __restrict__ ids,
@@ -257,6 +343,20 @@ hipError_t launch_batch_step(BatchProbDev* probs, const BatchBlk* blk, int nbloc
         batch_step_typed<double>(probs, blk, nblocks, static_cast<const double*>(coef), step, order, tyr, s);
     else
         batch_step_typed<float>(probs, blk, nblocks, static_cast<const float*>(coef), step, order, tyr, s);
+    return hipGetLastError();
+}
+
+int batch_steps_per_launch(int order) { return kBlkHalo / (order / 2); }
+
+int batch_blocked_tiles(const Geo& g) {
+    return ((g.nx + kBlkTile - 1) / kBlkTile) * ((g.ny + kBlkTile - 1) / kBlkTile);
+}
+
+hipError_t launch_batch_blocked(BatchProbDev* probs, const BatchBlk* blk, int nblocks, const double* coef, int launch,
+                                int order, hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
+    if (order == 2) k_batch_blocked<2><<<nblocks, kBlkThreads, 0, s>>>(probs, blk, coef, launch);
+    else k_batch_blocked<4><<<nblocks, kBlkThreads, 0, s>>>(probs, blk, coef, launch);
     return hipGetLastError();
 }
 

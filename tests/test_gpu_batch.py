@@ -77,7 +77,7 @@ def test_batch_autotuner_reports_candidates():
     bt = _batch(Ps)
     tu = bt.info["tune_us"]
     assert all(t > 0 for t in tu)
-    assert bt.info["step_rows_per_thread"] in (1, 2, 4, 8)
+    assert bt.info["step_rows_per_thread"] in (1, 2, 4, 8) and bt.info["steps_per_launch"] == 1
     assert tu[[1, 2, 4, 8].index(bt.info["step_rows_per_thread"])] == min(tu)
 
 
@@ -107,12 +107,16 @@ def test_batch_eigs_match_closed_form_and_standalone():
 
 @pytest.mark.parametrize("order", [2, 4])
 def test_batch_fp64_apply_matches_standalone_and_oracle(order):
-    """FP64 state: every problem takes the batched step launches (none runs in
-    one workgroup); repeated calls with other vectors leave v untouched."""
+    """FP64 state: every problem takes the batched launches of several steps
+    each (none runs in one workgroup; sizes from below one tile to ragged
+    multi-tile grids, step counts that end inside a launch); repeated calls
+    with other vectors leave v untouched."""
     Ps = _problems(order, [13, 40, 128, 129, 333], precision="fp64")
     say("batch fp64 apply", order)
     bt = _batch(Ps)
     assert bt.info["state_fp64"] and bt.info["n_small"] == 0 and bt.info["n_large"] == len(Ps)
+    # 8 / R steps per launch (R the stencil's radius), no tile-height tuning
+    assert bt.info["steps_per_launch"] == 8 // (order // 2) and bt.info["step_rows_per_thread"] == 0
     for rep in range(2):
         hv = [synthetic.uniform_pm1(700 + 10 * rep + i, P.n_active) for i, P in enumerate(Ps)]
         vs = [to_dev(x) for x in hv]
