@@ -271,7 +271,11 @@ ew_status ew_op_probe_guesses(ew_op op, int on);
  * initial condition W^0 with zero velocity, W is advanced N_t steps, and
  * out = sum_n c_n W^n with trapezoidal c_n (eq. filterQuadrature).
  * Stream-ordered for explicit; implicit blocks the host once per multigrid
- * cycle to test convergence.  EW_ERR_MG_NOT_CONVERGED if a solve fails. */
+ * cycle to test convergence.  Explicit 2D FP64 operators too large for the
+ * single-workgroup wave-solve (about 8192 points) and mapped operators
+ * advance several steps per launch and allocate two more time levels (16 B
+ * per point, held until ew_op_destroy) at their first call.  EW_ERR_MG_NOT_CONVERGED if a solve fails, EW_ERR_OOM if that
+ * allocation does. */
 ew_status ew_op_apply_filter(ew_op op, const double* v_dev, double* out_dev);
 
 /* For callers that cannot allocate device memory (code under HIP graph
