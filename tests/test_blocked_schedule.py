@@ -4,13 +4,17 @@ the box, mapped-grid and FP64-batch kernels).
 
 A launch advances up to 8 / R steps (R the stencil's radius): every 16 x 16
 output tile loads a region with an 8-point halo, and after step s only the
-points at least R (s + 1) from the region's edge are current.  Points beyond
-a wall read 0 in the region and the wall closures replace them as in one
-step per launch.  Each update then uses exactly the values one launch per
-step would use, so the two schedules agree bit for bit (numpy evaluates the
-same expression elementwise in both); both agree with the oracle's wall
-operator to rounding.  Sizes cover a grid smaller than one tile, ragged
-tiles, Neumann and mixed walls, and step counts that end inside a launch.
+points at least R (s + 1) from the region's edge are current.  Values a
+region cannot know spread inward by R per step, so the halo bounds the
+steps per launch (one step more fails these tests); updating only the
+current points keeps every read inside the region, which the kernels' LDS
+holds, and saves the rest.  Points beyond a wall read 0 in the region and
+the wall closures replace them as in one step per launch.  Each update then
+uses exactly the values one launch per step would use, so the two schedules
+agree bit for bit (numpy evaluates the same expression elementwise in
+both); both agree with the oracle's wall operator to rounding.  Sizes cover
+a grid smaller than one tile, ragged tiles, Neumann and mixed walls, and
+step counts that end inside a launch.
 """
 import numpy as np
 import pytest
@@ -48,9 +52,36 @@ def lap_frame(U, gx, gy, nx, ny, order, cx, cy, wall):
     return s
 
 
-def per_step(v, nx, ny, order, cx, cy, wall, dt2, cf, n_t):
+def lap_mapped(U, gx, gy, nx, ny, cw, cs, cb, ij):
+    """The mapped-grid operator as the kernels form it: conservative A11 and
+    A22 differences at half points plus the two cross terms, scaled by 1/J;
+    coefficients beyond the walls read 0."""
+    F = np.pad(U, 1)
+    sh = lambda ox, oy: F[1 + oy:F.shape[0] - 1 + oy, 1 + ox:F.shape[1] - 1 + ox]
+    uc, uW, uE, uS, uN = U, sh(-1, 0), sh(1, 0), sh(0, -1), sh(0, 1)
+    uSW, uSE, uNW, uNE = sh(-1, -1), sh(1, -1), sh(-1, 1), sh(1, 1)
+
+    def at(A, x, y, xmax, ymax):
+        ok = (x >= 0) & (x < xmax) & (y >= 0) & (y < ymax)
+        return np.where(ok, A[np.clip(y, 0, ymax - 1), np.clip(x, 0, xmax - 1)], 0.0)
+    inside = (gx >= 0) & (gx < nx) & (gy >= 0) & (gy < ny)
+    wl = np.where(inside, at(cw, gx, gy, nx + 1, ny), 0.0)
+    wr = np.where(inside, at(cw, gx + 1, gy, nx + 1, ny), 0.0)
+    ss = np.where(inside, at(cs, gx, gy, nx, ny + 1), 0.0)
+    sn = np.where(inside, at(cs, gx, gy + 1, nx, ny + 1), 0.0)
+    bE, bW = at(cb, gx + 1, gy, nx, ny), at(cb, gx - 1, gy, nx, ny)
+    bN, bS = at(cb, gx, gy + 1, nx, ny), at(cb, gx, gy - 1, nx, ny)
+    t = wr * (uE - uc) - wl * (uc - uW)
+    t = t + (sn * (uN - uc) - ss * (uc - uS))
+    t = t + (bE * (uNE - uSE) - bW * (uNW - uSW))
+    t = t + (bN * (uNE - uNW) - bS * (uSE - uSW))
+    return at(ij, gx, gy, nx, ny) * t
+
+
+def per_step(v, lap_at, dt2, cf, n_t):
+    ny, nx = v.shape
     gy, gx = np.mgrid[0:ny, 0:nx]
-    lap = lambda U: lap_frame(U, gx, gy, nx, ny, order, cx, cy, wall)
+    lap = lambda U: lap_at(U, gx, gy)
     cur = v + (0.5 * dt2) * lap(v)
     acc = cf[0] * v + cf[1] * cur
     prev = v
@@ -61,8 +92,10 @@ def per_step(v, nx, ny, order, cx, cy, wall, dt2, cf, n_t):
     return acc
 
 
-def blocked(v, nx, ny, order, cx, cy, wall, dt2, cf, n_t):
-    R = order // 2
+def blocked(v, R, lap_at, dt2, cf, n_t):
+    """The launches of 8 / R steps: R is the stencil's reach (1 for order 2
+    and the nine-point mapped operator, 2 for order 4)."""
+    ny, nx = v.shape
     per = HALO // R
     yy, xx = np.mgrid[0:SIDE, 0:SIDE]
     depth = np.minimum(np.minimum(xx, SIDE - 1 - xx), np.minimum(yy, SIDE - 1 - yy))
@@ -85,7 +118,8 @@ def blocked(v, nx, ny, order, cx, cy, wall, dt2, cf, n_t):
                 fsum = np.zeros_like(cur) if first else np.where(out, acc[cy_, cx_], 0.0)
                 for s in range(ns):
                     active = inside & (depth >= R * (s + 1))
-                    lap = lap_frame(cur, gx, gy, nx, ny, order, cx, cy, wall)
+                    assert not np.any(active & (depth < R))  # reads stay in the region
+                    lap = lap_at(cur, gx, gy)
                     if first and s == 0:
                         wn = cur + (0.5 * dt2) * lap
                         fn = cf[0] * cur + cf[1] * wn
@@ -118,10 +152,26 @@ def test_blocked_schedule_equals_one_step_per_launch(nx, ny, order, wall, n_t):
     rng = np.random.default_rng(1000 + nx * ny + order)
     v = rng.uniform(-1.0, 1.0, (ny, nx))
     cf = rng.uniform(0.0, 1.0, n_t + 1)
-    cx, cy = 1.3, 0.7
-    dt2 = 0.01
-    a = per_step(v, nx, ny, order, cx, cy, wall, dt2, cf, n_t)
-    b = blocked(v, nx, ny, order, cx, cy, wall, dt2, cf, n_t)
+    lap_at = lambda U, gx, gy: lap_frame(U, gx, gy, nx, ny, order, 1.3, 0.7, wall)
+    a = per_step(v, lap_at, 0.01, cf, n_t)
+    b = blocked(v, order // 2, lap_at, 0.01, cf, n_t)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nx,ny,n_t", [(5, 3, 3), (1, 4, 9), (37, 21, 17), (16, 16, 8), (33, 17, 11)])
+def test_blocked_schedule_on_the_mapped_operator(nx, ny, n_t):
+    """The same for the nine-point operator of a mapped grid (random
+    positive conservative coefficients, random cross terms)."""
+    rng = np.random.default_rng(2000 + nx * ny)
+    cw = rng.uniform(0.5, 1.5, (ny, nx + 1))
+    cs = rng.uniform(0.5, 1.5, (ny + 1, nx))
+    cb = rng.uniform(-0.2, 0.2, (ny, nx))
+    ij = rng.uniform(0.5, 1.5, (ny, nx))
+    v = rng.uniform(-1.0, 1.0, (ny, nx))
+    cf = rng.uniform(0.0, 1.0, n_t + 1)
+    lap_at = lambda U, gx, gy: lap_mapped(U, gx, gy, nx, ny, cw, cs, cb, ij)
+    a = per_step(v, lap_at, 0.05, cf, n_t)
+    b = blocked(v, 1, lap_at, 0.05, cf, n_t)
     assert np.array_equal(a, b)
 
 
